@@ -1,0 +1,212 @@
+/*
+ * ddlr.h -- C ABI of the DDLR (domain-decomposition low-rank) preconditioner
+ * library for AMD Instinct MI355X (gfx950).
+ *
+ * The method is that of Li & Saad, "Low-rank correction methods for algebraic
+ * domain decomposition preconditioners": a symmetric sparse A is split along a
+ * partition into p subdomains as A = A0 - E E^T (Sec. 3.1, eqs. splitA1 and
+ * split), A0 = blockdiag(B_i + alpha^{-2} E_i E_i^T, C + alpha^2 I), and the
+ * inverse is approximated through the Sherman-Morrison-Woodbury formula with a
+ * rank-k correction computed by Lanczos (Sec. 3.2 DDLR-1, Sec. 3.3 DDLR-2,
+ * Sec. 4.3 Lanczos).  The preconditioner is applied inside CG or GMRES
+ * (Sec. 5).
+ *
+ * Conventions for every call:
+ *   - All functions return ddlr_status; no exception or abort crosses the ABI.
+ *     On failure ddlr_last_error() returns a message for the calling thread.
+ *   - Host arrays are plain C arrays owned by the caller and only read (or
+ *     written, for outputs) during the call.
+ *   - Device vectors are hipMalloc'ed device pointers owned by the caller,
+ *     column-major with leading dimension ld >= n, in the caller's own row
+ *     order ("user order").  Work is queued on the given hipStream_t (passed
+ *     as void*, NULL = the default stream); calls that return results to host
+ *     memory synchronise that stream.
+ *   - A ddlr_prec is used by one stream at a time; it owns all of its device
+ *     memory (matrix, factors, U_k, workspaces) until ddlr_destroy.
+ *   - Indices are 0-based.  Matrices are CSR with full symmetric storage and
+ *     sorted column indices.
+ */
+#ifndef DDLR_H
+#define DDLR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    DDLR_OK = 0,
+    DDLR_E_INVALID = -1,         /* bad argument, partition, size or handle state */
+    DDLR_E_NOT_SYMMETRIC = -2,   /* A is not symmetric (pattern or values) */
+    DDLR_E_BREAKDOWN = -3,       /* zero / non-positive pivot in a local factor */
+    DDLR_E_NOT_SPD = -4,         /* preconditioner not SPD: CG refused, or G/H_k singular */
+    DDLR_E_NO_CONVERGENCE = -5,  /* Krylov solve hit maxit; x and info are still written */
+    DDLR_E_LANCZOS = -6,         /* Lanczos broke down before k+1 Ritz values */
+    DDLR_E_OOM = -7,             /* device allocation failed */
+    DDLR_E_DEVICE = -9           /* HIP error, or a host-only handle used for device work */
+} ddlr_status;
+
+typedef enum {
+    DDLR_VARIANT_A0 = 0,  /* no low-rank part: M^{-1} = A0^{-1} (block-Jacobi-like) */
+    DDLR_1 = 1,           /* one-sided, eq. (Mprec) with G_{k,theta}^{-1} of eq. (gkt) */
+    DDLR_2 = 2            /* two-sided, eq. (Form2a): A0^{-1} + U_k H_k U_k^T */
+} ddlr_variant;
+
+typedef enum { DDLR_THETA_LAMBDA_K1 = 0, DDLR_THETA_ZERO = 1 } ddlr_theta;
+typedef enum { DDLR_FACTOR_IC0 = 0, DDLR_FACTOR_ILDL0 = 1 } ddlr_factor;
+typedef enum { DDLR_CORDER_MULTICOLOR = 0, DDLR_CORDER_NATURAL = 1 } ddlr_corder;
+typedef enum { DDLR_FP64 = 0, DDLR_FP32 = 1, DDLR_FP32_UK_BF16 = 2 } ddlr_precision;
+
+/* Symmetric matrix, host memory, full storage, sorted columns. */
+typedef struct {
+    int64_t n;
+    const int64_t *row_ptr; /* n+1 */
+    const int32_t *col_idx; /* row_ptr[n] */
+    const double *val;      /* row_ptr[n] */
+} ddlr_csr;
+
+typedef struct {
+    double alpha;          /* splitting scale of eq. (EF); default 1 */
+    int32_t lanczos_steps; /* Lanczos steps m; 0 -> 2k */
+    int32_t theta;         /* ddlr_theta; default lambda_{k+1} (Sec. 5) */
+    int32_t factor;        /* ddlr_factor: IC(0) (positive pivots) or ILDL(0) (nonzero pivots) */
+    int32_t corder;        /* ddlr_corder: order of the interface block inside C_alpha's factor */
+    int32_t precision;     /* ddlr_precision of the preconditioner; Krylov is always FP64 */
+    int32_t device;        /* HIP device ordinal; -1 = host-only setup (ordering and factors only) */
+    int32_t reserved;
+    uint64_t seed;                /* Lanczos start vector when lanczos_start is NULL */
+    const double *lanczos_start;  /* host, length n, user order: its interface entries form q_1 */
+} ddlr_options;
+
+typedef struct {
+    int32_t method;  /* 0 = CG (Sec. 5, SPD matrix and preconditioner), 1 = GMRES(restart) */
+    int32_t restart; /* GMRES restart length; default 40 */
+    int32_t maxit;   /* default 500 */
+    int32_t reserved;
+    double rtol;     /* stop when ||r|| <= rtol ||b||; default 1e-6 */
+} ddlr_solve_options;
+
+typedef struct {
+    int32_t iters;       /* iterations (GMRES: inner steps) */
+    int32_t status;      /* DDLR_OK or DDLR_E_NO_CONVERGENCE for this right-hand side */
+    double relres;       /* recursive residual / ||b|| (GMRES: the least-squares estimate) */
+    double relres_true;  /* ||b - A x|| / ||b|| computed after the solve */
+} ddlr_solve_info;
+
+typedef struct {
+    int64_t n, m, s;        /* order, interior unknowns, interface unknowns */
+    int64_t nnz_a, nnz_l, nnz_e;
+    int32_t p, k, variant, lanczos_steps;
+    int32_t ncolours, levels_b_max, levels_c, spd;
+    int32_t precision, on_device;
+    double theta, c0;
+    double fill_ratio;      /* stored preconditioner entries / nnz(A) */
+    double setup_ms, lanczos_ms;
+} ddlr_info;
+
+typedef struct ddlr_prec ddlr_prec;
+
+/* Library version (major*100 + minor). */
+int32_t ddlr_version(void);
+
+/* Fills *opt with the defaults listed above. */
+void ddlr_options_default(ddlr_options *opt);
+void ddlr_solve_options_default(ddlr_solve_options *opt);
+
+/*
+ * Builds a DDLR preconditioner (Sec. 4.1, the four steps of the build):
+ *  1. classifies unknowns as interior / interface by the edge separator of
+ *     `part` (Sec. 2.1) and reorders to the form of eq. (Bmat);
+ *  2./3. forms B_{i,alpha}, C_alpha and E (Sec. 3.1) and factors every block by
+ *     incomplete LDL^T with the block's own pattern (Sec. 5);
+ *  4. runs `lanczos_steps` Lanczos steps with full reorthogonalisation on
+ *     E^T A0^{-1} E (DDLR-1) or E^T A0^{-2} E (DDLR-2) (Sec. 4.3) and forms
+ *     U_k with G_{k,theta}^{-1} (eq. gkt) or H_k (Lemma on H_k).
+ * A: host CSR (copied); part: host int32[n] with values in [0,p) (copied);
+ * k: rank (ignored for DDLR_VARIANT_A0; 1 <= k < number of interface unknowns).
+ * Errors: DDLR_E_INVALID, DDLR_E_NOT_SYMMETRIC, DDLR_E_BREAKDOWN (message names
+ * the row), DDLR_E_LANCZOS, DDLR_E_NOT_SPD (theta >= 1 or I - U_k^T E V_k not
+ * SPD), DDLR_E_OOM, DDLR_E_DEVICE.  On failure *out is NULL and nothing leaks.
+ */
+ddlr_status ddlr_setup(const ddlr_csr *A, const int32_t *part, int32_t p, int32_t k, int32_t variant,
+                       const ddlr_options *opt, ddlr_prec **out);
+
+/* y = M^{-1} x for nrhs columns (Sec. 4.2: the five steps of the DDLR-1
+ * preconditioning algorithm, or one A0 solve plus U_k H_k U_k^T for DDLR-2).
+ * x, y: device, user order, x and y must not overlap. */
+ddlr_status ddlr_apply(ddlr_prec *h, int32_t nrhs, const double *x, int64_t ldx, double *y, int64_t ldy,
+                       void *stream);
+
+/* y = A0^{-1} x with the local factors only (steps 1 and 5 of the DDLR-1
+ * algorithm: the p solves with B_{i,alpha} and the solve with C_alpha). */
+ddlr_status ddlr_a0_solve(ddlr_prec *h, int32_t nrhs, const double *x, int64_t ldx, double *y, int64_t ldy,
+                          void *stream);
+
+/* y = A x (the operator of the Krylov solves), device, user order. */
+ddlr_status ddlr_spmv(ddlr_prec *h, int32_t nrhs, const double *x, int64_t ldx, double *y, int64_t ldy,
+                      void *stream);
+
+/* Solves A x = b for nrhs right-hand sides with PCG or right-preconditioned
+ * GMRES(restart), x0 = 0, stopping rule of Sec. 5 (residual reduced by rtol,
+ * at most maxit iterations).  b, x: device, user order.  info: host array of
+ * nrhs entries.  Returns DDLR_E_NOT_SPD for CG with a preconditioner that is
+ * not certified SPD (largest Ritz value >= 1), DDLR_E_NO_CONVERGENCE if any
+ * right-hand side did not converge (x and info written for all). Synchronises
+ * the stream. */
+ddlr_status ddlr_solve(ddlr_prec *h, int32_t nrhs, const double *b, int64_t ldb, double *x, int64_t ldx,
+                       const ddlr_solve_options *opt, ddlr_solve_info *info, void *stream);
+
+/* Sizes, counts and timings of a built preconditioner. */
+ddlr_status ddlr_query(const ddlr_prec *h, ddlr_info *info);
+
+/* Reordering of step 1: perm[i] = user row at internal position i (interiors
+ * of subdomain 0..p-1, then the interface block in C_alpha's factor order);
+ * iface[u] = 1 for interface rows (user order); colour[j] = colour of the j-th
+ * interface position (0 with natural order).  Host arrays n, n, s. */
+ddlr_status ddlr_get_ordering(const ddlr_prec *h, int32_t *perm, int32_t *iface, int32_t *colour);
+
+/* Local factors in internal order: strict lower L as CSR (row_ptr n+1,
+ * col/val nnz_l) and D (n).  Host arrays. */
+ddlr_status ddlr_get_factor(const ddlr_prec *h, int64_t *row_ptr, int32_t *col, double *val, double *D);
+
+/* Level of each internal row in its block's forward triangular schedule. */
+ddlr_status ddlr_get_levels(const ddlr_prec *h, int32_t *level);
+
+/* Lanczos record: alpha_1..alpha_m, beta_1..beta_m and Ritz values (descending),
+ * m = info.lanczos_steps.  Host arrays. */
+ddlr_status ddlr_get_lanczos(const ddlr_prec *h, double *alpha, double *beta, double *ritz);
+
+/* Low-rank data in user order (host).  U: n x k column-major (DDLR-1: only the
+ * interface rows are nonzero).  aux: DDLR-1 lambda_1..lambda_k then theta
+ * (k+1 values); DDLR-2 H_k (k x k column-major). */
+ddlr_status ddlr_get_lowrank(const ddlr_prec *h, double *U, double *aux);
+
+/* Replaces the low-rank data (same layout as ddlr_get_lowrank), e.g. to
+ * restore a saved preconditioner.  variant 1 or 2; 1 <= k. */
+ddlr_status ddlr_set_lowrank(ddlr_prec *h, int32_t variant, int32_t k, const double *U, const double *aux);
+
+/* Kernel timing with HIP events recorded on the launch stream around each
+ * launch of a kernel class: 0 = the per-block triangular-solve kernel of the
+ * A0 solve (all B_{i,alpha} blocks, and C_alpha when it is not level-split),
+ * 1 = the per-level kernels of C_alpha, 2 = the SpMV with A, 3 = the low-rank
+ * correction kernels.  on != 0 enables and resets the counters; 0 disables.
+ * Synchronises the device. */
+ddlr_status ddlr_profile(ddlr_prec *h, int32_t on);
+
+/* Accumulated milliseconds and launches of kernel class `which` since
+ * profiling was enabled.  Synchronises the device. */
+ddlr_status ddlr_profile_read(ddlr_prec *h, int32_t which, double *total_ms, int64_t *launches);
+
+/* Releases everything the handle owns.  NULL is ignored. */
+void ddlr_destroy(ddlr_prec *h);
+
+const char *ddlr_status_string(int32_t status);
+const char *ddlr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DDLR_H */

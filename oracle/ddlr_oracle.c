@@ -600,6 +600,14 @@ static int dense_chol(int k, double *a) {
     return 0;
 }
 
+/* The SPD results (Propositions on SPD-ness of DDLR-1 and DDLR-2) assume A0
+ * SPD; with an indefinite local factor the preconditioner is not SPD. */
+static int pivots_positive(const orc_t *o) {
+    for (int64_t i = 0; i < o->n; ++i)
+        if (!(o->D[i] > 0.0)) return 0;
+    return 1;
+}
+
 /* Low-rank part of the preconditioner from the Lanczos run (Sec. 3.2 / 3.3). */
 static int build_lowrank(orc_t *o, int variant, int k, int thetamode) {
     const int m = o->msteps;
@@ -637,7 +645,7 @@ static int build_lowrank(orc_t *o, int variant, int k, int thetamode) {
             if (o->lam[j] == 1.0) st = ORC_E_NOT_SPD;
             o->dvec[j] = 1.0 / (1.0 - o->lam[j]) - o->c0;
         }
-        o->spd = (o->lam[0] < 1.0) && st == ORC_OK;
+        o->spd = (o->lam[0] < 1.0) && st == ORC_OK && pivots_positive(o);
     } else {
         /* V_k = Q_m Y_k, U_k = A0^{-1} E V_k, H_k = (I - U_k^T E V_k)^{-1} */
         double *EV = xcalloc(n * (int64_t)k, sizeof(double));
@@ -673,7 +681,7 @@ static int build_lowrank(orc_t *o, int variant, int k, int thetamode) {
             }
         }
         free(K); free(Mx); free(EV); free(QY);
-        o->spd = (st == ORC_OK);
+        o->spd = (st == ORC_OK) && pivots_positive(o);
         o->theta = 0.0;
         o->c0 = 0.0;
     }

@@ -1,0 +1,320 @@
+"""MI355X-native DDLR preconditioner (Li & Saad, domain-decomposition low-rank).
+
+Thin ctypes binding over the C ABI in include/ddlr.h (libddlr.so, HIP for
+gfx950).  Functions carry the C names; they only marshal arguments: every step
+of setup, apply and solve runs in the library.  Device vectors are torch
+tensors on the GPU, float64, shaped (n,) or (nrhs, n) and contiguous (row r of
+the tensor is right-hand side r, i.e. column-major with ld = n).  There is no
+CPU fallback: if the library is not built, loading fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libddlr.so")
+
+OK, E_INVALID, E_NOT_SYMMETRIC, E_BREAKDOWN, E_NOT_SPD, E_NO_CONVERGENCE, E_LANCZOS, E_OOM, E_DEVICE = (
+    0, -1, -2, -3, -4, -5, -6, -7, -9)
+VARIANT_A0, DDLR_1, DDLR_2 = 0, 1, 2
+THETA_LAMBDA_K1, THETA_ZERO = 0, 1
+FACTOR_IC0, FACTOR_ILDL0 = 0, 1
+CORDER_MULTICOLOR, CORDER_NATURAL = 0, 1
+FP64, FP32, FP32_UK_BF16 = 0, 1, 2
+
+
+class ddlr_csr(C.Structure):
+    _fields_ = [("n", C.c_int64), ("row_ptr", C.c_void_p), ("col_idx", C.c_void_p), ("val", C.c_void_p)]
+
+
+class ddlr_options(C.Structure):
+    _fields_ = [("alpha", C.c_double), ("lanczos_steps", C.c_int32), ("theta", C.c_int32),
+                ("factor", C.c_int32), ("corder", C.c_int32), ("precision", C.c_int32), ("device", C.c_int32),
+                ("reserved", C.c_int32), ("seed", C.c_uint64), ("lanczos_start", C.c_void_p)]
+
+
+class ddlr_solve_options(C.Structure):
+    _fields_ = [("method", C.c_int32), ("restart", C.c_int32), ("maxit", C.c_int32), ("reserved", C.c_int32),
+                ("rtol", C.c_double)]
+
+
+class ddlr_solve_info(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("status", C.c_int32), ("relres", C.c_double), ("relres_true", C.c_double)]
+
+
+class ddlr_info(C.Structure):
+    _fields_ = [("n", C.c_int64), ("m", C.c_int64), ("s", C.c_int64), ("nnz_a", C.c_int64), ("nnz_l", C.c_int64),
+                ("nnz_e", C.c_int64), ("p", C.c_int32), ("k", C.c_int32), ("variant", C.c_int32),
+                ("lanczos_steps", C.c_int32), ("ncolours", C.c_int32), ("levels_b_max", C.c_int32),
+                ("levels_c", C.c_int32), ("spd", C.c_int32), ("precision", C.c_int32), ("on_device", C.c_int32),
+                ("theta", C.c_double), ("c0", C.c_double), ("fill_ratio", C.c_double), ("setup_ms", C.c_double),
+                ("lanczos_ms", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class DDLRError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        super().__init__(f"{where}: status {status} ({msg})")
+        self.status = status
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Loads libddlr.so; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"DDLR HIP library not built: {path} is missing (run paper_1505_04341_amd/build.py)")
+    lib = C.CDLL(path)
+    P, I32, I64 = C.c_void_p, C.c_int32, C.c_int64
+    sig = {
+        "ddlr_version": (I32, []),
+        "ddlr_options_default": (None, [P]),
+        "ddlr_solve_options_default": (None, [P]),
+        "ddlr_setup": (I32, [P, P, I32, I32, I32, P, P]),
+        "ddlr_apply": (I32, [P, I32, P, I64, P, I64, P]),
+        "ddlr_a0_solve": (I32, [P, I32, P, I64, P, I64, P]),
+        "ddlr_spmv": (I32, [P, I32, P, I64, P, I64, P]),
+        "ddlr_solve": (I32, [P, I32, P, I64, P, I64, P, P, P]),
+        "ddlr_query": (I32, [P, P]),
+        "ddlr_get_ordering": (I32, [P, P, P, P]),
+        "ddlr_get_factor": (I32, [P, P, P, P, P]),
+        "ddlr_get_levels": (I32, [P, P]),
+        "ddlr_get_lanczos": (I32, [P, P, P, P]),
+        "ddlr_get_lowrank": (I32, [P, P, P]),
+        "ddlr_set_lowrank": (I32, [P, I32, I32, P, P]),
+        "ddlr_profile": (I32, [P, I32]),
+        "ddlr_profile_read": (I32, [P, I32, P, P]),
+        "ddlr_destroy": (None, [P]),
+        "ddlr_status_string": (C.c_char_p, [I32]),
+        "ddlr_last_error": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(st: int, where: str):
+    if st != OK:
+        lib = load_library()
+        raise DDLRError(st, where, lib.ddlr_last_error().decode(errors="replace"))
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _stream(stream):
+    if stream is not None:
+        return C.c_void_p(int(stream))
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev_cols(t, n: int):
+    """(ptr, nrhs, ld) of a contiguous float64 GPU tensor shaped (n,) or (nrhs, n)."""
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError("expected a contiguous float64 CUDA tensor")
+    if t.dim() == 1:
+        if t.shape[0] != n:
+            raise ValueError("length mismatch")
+        return C.c_void_p(t.data_ptr()), 1, n
+    if t.dim() != 2 or t.shape[1] != n:
+        raise ValueError("expected shape (nrhs, n)")
+    return C.c_void_p(t.data_ptr()), t.shape[0], n
+
+
+class Prec:
+    """Handle of a built preconditioner (ddlr_prec*)."""
+
+    def __init__(self, handle: int, n: int, keep=()):
+        self._h = C.c_void_p(handle)
+        self.n = n
+        self._keep = keep
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.ddlr_destroy(self._h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+
+def ddlr_setup(A, part, p: int, k: int, variant: int = DDLR_1, *, alpha: float = 1.0, lanczos_steps: int = 0,
+               theta: int = THETA_LAMBDA_K1, factor: int = FACTOR_IC0, corder: int = CORDER_MULTICOLOR,
+               precision: int = FP64, device: int = 0, seed: int = 0, lanczos_start=None) -> Prec:
+    """Builds the preconditioner. A: object with n, rowptr (int64), col (int32), val (float64)."""
+    lib = load_library()
+    rp = np.ascontiguousarray(A.rowptr, dtype=np.int64)
+    ci = np.ascontiguousarray(A.col, dtype=np.int32)
+    va = np.ascontiguousarray(A.val, dtype=np.float64)
+    pa = np.ascontiguousarray(part, dtype=np.int32)
+    csr = ddlr_csr(int(A.n), rp.ctypes.data, ci.ctypes.data, va.ctypes.data)
+    opt = ddlr_options()
+    lib.ddlr_options_default(C.byref(opt))
+    opt.alpha, opt.lanczos_steps, opt.theta = float(alpha), int(lanczos_steps), int(theta)
+    opt.factor, opt.corder, opt.precision, opt.device, opt.seed = int(factor), int(corder), int(precision), int(
+        device), int(seed)
+    v0 = None
+    if lanczos_start is not None:
+        v0 = np.ascontiguousarray(lanczos_start, dtype=np.float64)
+        opt.lanczos_start = v0.ctypes.data
+    h = C.c_void_p()
+    st = lib.ddlr_setup(C.byref(csr), _ptr(pa), int(p), int(k), int(variant), C.byref(opt), C.byref(h))
+    _check(st, "ddlr_setup")
+    return Prec(h.value, int(A.n))
+
+
+def _vec_op(name: str, prec: Prec, x, y, stream):
+    lib = load_library()
+    xp, nx, ldx = _dev_cols(x, prec.n)
+    yp, ny, ldy = _dev_cols(y, prec.n)
+    if nx != ny:
+        raise ValueError("x and y must have the same number of columns")
+    _check(getattr(lib, name)(prec.handle, nx, xp, ldx, yp, ldy, _stream(stream)), name)
+    return y
+
+
+def ddlr_apply(prec: Prec, x, y, stream=None):
+    """y = M^{-1} x (device tensors, user order)."""
+    return _vec_op("ddlr_apply", prec, x, y, stream)
+
+
+def ddlr_a0_solve(prec: Prec, x, y, stream=None):
+    """y = A0^{-1} x with the local factors."""
+    return _vec_op("ddlr_a0_solve", prec, x, y, stream)
+
+
+def ddlr_spmv(prec: Prec, x, y, stream=None):
+    """y = A x."""
+    return _vec_op("ddlr_spmv", prec, x, y, stream)
+
+
+def ddlr_solve(prec: Prec, b, x, *, method: int = 0, restart: int = 40, maxit: int = 500, rtol: float = 1e-6,
+               stream=None, raise_on_noconv: bool = False):
+    """Solves A x = b (PCG or GMRES); returns (status, list of per-rhs info dicts)."""
+    lib = load_library()
+    bp, nb, ldb = _dev_cols(b, prec.n)
+    xp, nxc, ldx = _dev_cols(x, prec.n)
+    if nb != nxc:
+        raise ValueError("b and x must have the same number of columns")
+    opt = ddlr_solve_options()
+    lib.ddlr_solve_options_default(C.byref(opt))
+    opt.method, opt.restart, opt.maxit, opt.rtol = int(method), int(restart), int(maxit), float(rtol)
+    infos = (ddlr_solve_info * nb)()
+    st = lib.ddlr_solve(prec.handle, nb, bp, ldb, xp, ldx, C.byref(opt), infos, _stream(stream))
+    if st not in (OK, E_NO_CONVERGENCE) or (raise_on_noconv and st != OK):
+        _check(st, "ddlr_solve")
+    return st, [dict(iters=i.iters, status=i.status, relres=i.relres, relres_true=i.relres_true) for i in infos]
+
+
+def ddlr_query(prec: Prec) -> dict:
+    lib = load_library()
+    info = ddlr_info()
+    _check(lib.ddlr_query(prec.handle, C.byref(info)), "ddlr_query")
+    return info.as_dict()
+
+
+def ddlr_get_ordering(prec: Prec):
+    """(perm, iface, colour) as numpy arrays (see ddlr.h)."""
+    lib = load_library()
+    q = ddlr_query(prec)
+    perm = np.zeros(q["n"], np.int32)
+    iface = np.zeros(q["n"], np.int32)
+    colour = np.zeros(max(q["s"], 1), np.int32)
+    _check(lib.ddlr_get_ordering(prec.handle, _ptr(perm), _ptr(iface), _ptr(colour)), "ddlr_get_ordering")
+    return perm, iface, colour[: q["s"]]
+
+
+def ddlr_get_factor(prec: Prec):
+    """(L as scipy CSR in internal order, D)."""
+    import scipy.sparse as sp
+    lib = load_library()
+    q = ddlr_query(prec)
+    n, nnz = q["n"], q["nnz_l"]
+    rp = np.zeros(n + 1, np.int64)
+    ci = np.zeros(max(nnz, 1), np.int32)
+    v = np.zeros(max(nnz, 1))
+    D = np.zeros(n)
+    _check(lib.ddlr_get_factor(prec.handle, _ptr(rp), _ptr(ci), _ptr(v), _ptr(D)), "ddlr_get_factor")
+    return sp.csr_matrix((v[:nnz], ci[:nnz], rp), shape=(n, n)), D
+
+
+def ddlr_get_levels(prec: Prec):
+    lib = load_library()
+    lev = np.zeros(prec.n, np.int32)
+    _check(lib.ddlr_get_levels(prec.handle, _ptr(lev)), "ddlr_get_levels")
+    return lev
+
+
+def ddlr_get_lanczos(prec: Prec):
+    lib = load_library()
+    m = ddlr_query(prec)["lanczos_steps"]
+    a, b, r = np.zeros(max(m, 1)), np.zeros(max(m, 1)), np.zeros(max(m, 1))
+    _check(lib.ddlr_get_lanczos(prec.handle, _ptr(a), _ptr(b), _ptr(r)), "ddlr_get_lanczos")
+    return a[:m], b[:m], r[:m]
+
+
+def ddlr_get_lowrank(prec: Prec):
+    """DDLR-1: (U n x k, lambda, theta); DDLR-2: (U, H_k)."""
+    lib = load_library()
+    q = ddlr_query(prec)
+    n, k = q["n"], q["k"]
+    U = np.zeros((n, k), order="F")
+    aux = np.zeros(k + 1 if q["variant"] == 1 else k * k)
+    _check(lib.ddlr_get_lowrank(prec.handle, _ptr(U), _ptr(aux)), "ddlr_get_lowrank")
+    if q["variant"] == 1:
+        return U, aux[:k].copy(), float(aux[k])
+    return U, aux.reshape(k, k, order="F").copy()
+
+
+def ddlr_set_lowrank(prec: Prec, variant: int, U, lam_or_H, theta: float = 0.0):
+    lib = load_library()
+    U = np.asfortranarray(U, dtype=np.float64)
+    k = U.shape[1]
+    if variant == 1:
+        aux = np.concatenate([np.asarray(lam_or_H, np.float64), [float(theta)]])
+    else:
+        aux = np.asfortranarray(lam_or_H, dtype=np.float64).reshape(-1, order="F")
+    _check(lib.ddlr_set_lowrank(prec.handle, int(variant), int(k), _ptr(U), _ptr(aux)), "ddlr_set_lowrank")
+
+
+PROF_TRSV_BLOCKS, PROF_TRSV_LEVELS, PROF_SPMV, PROF_LOWRANK = 0, 1, 2, 3
+
+
+def ddlr_profile(prec: Prec, on: bool = True):
+    _check(load_library().ddlr_profile(prec.handle, 1 if on else 0), "ddlr_profile")
+
+
+def ddlr_profile_read(prec: Prec, which: int):
+    """(total milliseconds, launches) of a kernel class since profiling was enabled."""
+    t = C.c_double()
+    cnt = C.c_int64()
+    _check(load_library().ddlr_profile_read(prec.handle, int(which), C.byref(t), C.byref(cnt)),
+           "ddlr_profile_read")
+    return t.value, cnt.value
+
+
+def ddlr_version() -> int:
+    return int(load_library().ddlr_version())
+
+
+EXPORTED = ["ddlr_version", "ddlr_options_default", "ddlr_solve_options_default", "ddlr_setup", "ddlr_apply",
+            "ddlr_a0_solve", "ddlr_spmv", "ddlr_solve", "ddlr_query", "ddlr_get_ordering", "ddlr_get_factor",
+            "ddlr_get_levels", "ddlr_get_lanczos", "ddlr_get_lowrank", "ddlr_set_lowrank", "ddlr_profile",
+            "ddlr_profile_read", "ddlr_destroy",
+            "ddlr_status_string", "ddlr_last_error"]

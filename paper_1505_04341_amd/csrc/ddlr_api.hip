@@ -1,0 +1,1246 @@
+// DDLR preconditioner library: device data, orchestration and the C ABI.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "ddlr.h"
+#include "host_setup.hpp"
+#include "kernels.hpp"
+
+using namespace ddlr;
+
+namespace {
+
+thread_local std::string g_err;
+
+// kernel classes timed by ddlr_profile: 0 narrow A0-solve kernel, 1 wide level
+// kernels, 2 SpMV with A, 3 low-rank correction kernels
+constexpr int kProfClasses = 4;
+
+#define HIPCHK(call)                                                                                   \
+    do {                                                                                               \
+        hipError_t e_ = (call);                                                                        \
+        if (e_ != hipSuccess)                                                                          \
+            throw SetupError{e_ == hipErrorOutOfMemory ? DDLR_E_OOM : DDLR_E_DEVICE,                   \
+                             std::string(#call) + ": " + hipGetErrorString(e_)};                       \
+    } while (0)
+
+#define LAUNCHCHK() HIPCHK(hipGetLastError())
+
+// Device allocation owned by a handle.
+struct DMem {
+    std::vector<void*> ptrs;
+    template <typename T> T* alloc(size_t count) {
+        void* p = nullptr;
+        if (count == 0) count = 1;
+        HIPCHK(hipMalloc(&p, count * sizeof(T)));
+        ptrs.push_back(p);
+        return static_cast<T*>(p);
+    }
+    template <typename T> T* upload(const std::vector<T>& h) {
+        T* d = alloc<T>(h.size());
+        if (!h.empty()) HIPCHK(hipMemcpy(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+        return d;
+    }
+    void release() {
+        for (void* p : ptrs) (void)hipFree(p);
+        ptrs.clear();
+    }
+};
+
+int grid_for(int64_t work, int block = 256, int cap = 8192) {
+    int64_t g = (work + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+// Factors of A0 in one precision, device order.
+template <typename T> struct DevFactors {
+    T *lv = nullptr, *uv = nullptr, *dinv = nullptr;
+    T *ev = nullptr, *etv = nullptr;  // E and E^T values
+    T *U = nullptr;                   // low-rank basis, row-major (rows x k)
+};
+
+struct Workspace {
+    int nrhs = 0;
+    // Krylov (double, device order)
+    double *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
+    // preconditioner temporaries (type of the preconditioner)
+    void *a0 = nullptr, *a1 = nullptr, *a2 = nullptr, *a3 = nullptr, *ys = nullptr, *ws = nullptr;
+    double *part = nullptr, *sums = nullptr, *coef = nullptr, *lrsum = nullptr;
+    CgLane* lanes = nullptr;
+    int* done = nullptr;
+    int* done_host = nullptr;
+    DMem mem;
+};
+
+}  // namespace
+
+struct ddlr_prec {
+    HostPlan plan;
+    int device = -1;
+    int variant = 0, k = 0, precision = 0, msteps = 0, spd = 0;
+    // Proposition (SPD-ness of DDLR-1) assumes A0 SPD: with indefinite local
+    // factors the preconditioner is indefinite whatever the Ritz values
+    bool pivots_positive = true;
+    double theta = 0.0, c0 = 0.0;
+    std::vector<double> lam, dvec_h, H_h, ta, tb, ritz;
+    double setup_ms = 0.0, lanczos_ms = 0.0;
+    DMem mem;
+    // device structures (device order)
+    int32_t* perm_dev = nullptr;  // device position -> user row
+    int32_t *sell_ptr = nullptr, *sell_col = nullptr;
+    double* sell_val = nullptr;
+    int64_t nslices = 0, sell_nnz = 0;
+    int32_t *lrp = nullptr, *lci = nullptr, *urp = nullptr, *uci = nullptr, *lvl_ptr = nullptr;
+    int32_t *erp = nullptr, *eci = nullptr, *etrp = nullptr, *etci = nullptr;
+    BlockDesc* blk = nullptr;
+    int nnarrow = 0, nnarrow_pad = 0;
+    std::vector<std::pair<int, int>> wide;  // rows [a,e) of the wide levels of C (forward order)
+    DevFactors<double> f64;
+    DevFactors<float> f32;
+    int64_t urows = 0;      // rows of U (s for DDLR-1, n for DDLR-2)
+    double *dvec = nullptr, *Hk = nullptr;
+    Workspace ws;
+    DMem lrmem;  // low-rank storage (replaced by set_lowrank)
+    // kernel timing (HIP events on the launch stream), per kernel class
+    bool prof = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev[kProfClasses];
+    std::vector<hipEvent_t> prof_pool;
+};
+
+namespace {
+
+// ------------------------------------------------------------ device upload
+
+void upload_structures(ddlr_prec* h) {
+    HostPlan& P = h->plan;
+    const int64_t n = P.n, m = P.m, s = P.s;
+    DMem& M = h->mem;
+    // permutation device -> user
+    std::vector<int32_t> pd(n);
+    for (int64_t d = 0; d < n; ++d) pd[d] = P.perm[P.dev2int[d]];
+    h->perm_dev = M.upload(pd);
+    // A in SELL-64, device order
+    h->nslices = (n + kSell - 1) / kSell;
+    std::vector<int32_t> sptr(h->nslices + 1, 0);
+    for (int64_t sl = 0; sl < h->nslices; ++sl) {
+        int w = 0;
+        for (int64_t d = sl * kSell; d < std::min<int64_t>(n, (sl + 1) * kSell); ++d) {
+            int64_t i = P.dev2int[d];
+            w = std::max<int>(w, (int)(P.A.rp[i + 1] - P.A.rp[i]));
+        }
+        sptr[sl + 1] = sptr[sl] + w * kSell;
+    }
+    h->sell_nnz = sptr[h->nslices];
+    std::vector<int32_t> scol(h->sell_nnz);
+    std::vector<double> sval(h->sell_nnz, 0.0);
+    for (int64_t sl = 0; sl < h->nslices; ++sl) {
+        const int w = (sptr[sl + 1] - sptr[sl]) / kSell;
+        for (int lane = 0; lane < kSell; ++lane) {
+            const int64_t d = sl * kSell + lane;
+            int64_t cnt = 0, i = -1;
+            if (d < n) {
+                i = P.dev2int[d];
+                cnt = P.A.rp[i + 1] - P.A.rp[i];
+            }
+            for (int j = 0; j < w; ++j) {
+                const int64_t q = sptr[sl] + (int64_t)j * kSell + lane;
+                if (j < cnt) {
+                    scol[q] = P.int2dev[P.A.ci[P.A.rp[i] + j]];
+                    sval[q] = P.A.v[P.A.rp[i] + j];
+                } else {
+                    scol[q] = (int32_t)std::min<int64_t>(d, n - 1);
+                    sval[q] = 0.0;
+                }
+            }
+        }
+    }
+    h->sell_ptr = M.upload(sptr);
+    h->sell_col = M.upload(scol);
+    h->sell_val = M.upload(sval);
+    // forward factor L and backward factor L^T, device order
+    if (P.L.nnz() > INT32_MAX) throw SetupError{DDLR_E_INVALID, "nnz(L) must fit in int32"};
+    std::vector<int32_t> lrp(n + 1, 0), lci(P.L.nnz());
+    std::vector<double> lv(P.L.nnz());
+    for (int64_t d = 0; d < n; ++d) {
+        const int64_t i = P.dev2int[d];
+        int32_t q = lrp[d];
+        for (int64_t t = P.L.rp[i]; t < P.L.rp[i + 1]; ++t, ++q) {
+            lci[q] = P.int2dev[P.L.ci[t]];
+            lv[q] = P.L.v[t];
+        }
+        lrp[d + 1] = q;
+    }
+    std::vector<int32_t> ucount(n + 1, 0);
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t t = P.L.rp[i]; t < P.L.rp[i + 1]; ++t) ucount[P.int2dev[P.L.ci[t]] + 1]++;
+    for (int64_t d = 0; d < n; ++d) ucount[d + 1] += ucount[d];
+    std::vector<int32_t> urp(ucount), uci(P.L.nnz()), fill(ucount.begin(), ucount.end() - 1);
+    std::vector<double> uv(P.L.nnz());
+    for (int64_t i = 0; i < n; ++i)  // ascending internal row j of L_ji -> ascending order in each L^T row
+        for (int64_t t = P.L.rp[i]; t < P.L.rp[i + 1]; ++t) {
+            const int32_t dcol = P.int2dev[P.L.ci[t]];
+            const int32_t q = fill[dcol]++;
+            uci[q] = P.int2dev[i];
+            uv[q] = P.L.v[t];
+        }
+    std::vector<double> dinv(n);
+    for (int64_t d = 0; d < n; ++d) dinv[d] = 1.0 / P.D[P.dev2int[d]];
+    h->lrp = M.upload(lrp);
+    h->lci = M.upload(lci);
+    h->urp = M.upload(urp);
+    h->uci = M.upload(uci);
+    h->f64.lv = M.upload(lv);
+    h->f64.uv = M.upload(uv);
+    h->f64.dinv = M.upload(dinv);
+    h->lvl_ptr = M.upload(P.lvl_ptr);
+    // E (n x s) and E^T (s x n) in device order
+    const double ia = 1.0 / P.alpha;
+    std::vector<int32_t> erp(n + 1, 0), eci;
+    std::vector<double> ev;
+    for (int64_t d = 0; d < n; ++d) {
+        const int64_t i = P.dev2int[d];
+        if (i < m) {
+            for (int64_t t = P.A.rp[i]; t < P.A.rp[i + 1]; ++t)
+                if (P.A.ci[t] >= m) {
+                    eci.push_back(P.int2dev[P.A.ci[t]] - (int32_t)m);
+                    ev.push_back(ia * P.A.v[t]);
+                }
+        } else {
+            eci.push_back((int32_t)(d - m));
+            ev.push_back(-P.alpha);
+        }
+        erp[d + 1] = (int32_t)eci.size();
+    }
+    std::vector<int32_t> etrp(s + 1, 0), etci(eci.size());
+    std::vector<double> etv(eci.size());
+    for (size_t t = 0; t < eci.size(); ++t) etrp[eci[t] + 1]++;
+    for (int64_t j = 0; j < s; ++j) etrp[j + 1] += etrp[j];
+    std::vector<int32_t> efill(etrp.begin(), etrp.end() - 1);
+    for (int64_t d = 0; d < n; ++d)
+        for (int32_t t = erp[d]; t < erp[d + 1]; ++t) {
+            const int32_t q = efill[eci[t]]++;
+            etci[q] = (int32_t)d;
+            etv[q] = ev[t];
+        }
+    h->erp = M.upload(erp);
+    h->eci = M.upload(eci);
+    h->etrp = M.upload(etrp);
+    h->etci = M.upload(etci);
+    h->f64.ev = M.upload(ev);
+    h->f64.etv = M.upload(etv);
+    if (h->precision != DDLR_FP64) {
+        auto demote = [&](const std::vector<double>& a) {
+            std::vector<float> f(a.size());
+            for (size_t i = 0; i < a.size(); ++i) f[i] = (float)a[i];
+            return M.upload(f);
+        };
+        h->f32.lv = demote(lv);
+        h->f32.uv = demote(uv);
+        h->f32.dinv = demote(dinv);
+        h->f32.ev = demote(ev);
+        h->f32.etv = demote(etv);
+    }
+    // schedule: B blocks are narrow (one workgroup per block and rhs); the
+    // interface block is wide when its levels are few and wide.
+    const int32_t p = P.p;
+    const int32_t c_lv0 = P.blk_lvl[p], c_lv1 = P.blk_lvl[p + 1];
+    const int32_t c_levels = c_lv1 - c_lv0;
+    bool c_wide = c_levels > 0 && c_levels <= 64 && s / std::max(1, c_levels) >= 2048;
+    if (const char* env = std::getenv("DDLR_C_WIDE")) {  // "1" forces level launches, "0" one workgroup
+        if (env[0] == '1') c_wide = c_levels > 0;
+        if (env[0] == '0') c_wide = false;
+    }
+    std::vector<BlockDesc> bd;
+    for (int32_t b = 0; b < p; ++b)
+        if (P.blk_lvl[b + 1] > P.blk_lvl[b]) bd.push_back({P.blk_lvl[b], P.blk_lvl[b + 1]});
+    h->wide.clear();
+    if (c_wide) {
+        for (int32_t l = c_lv0; l < c_lv1; ++l) h->wide.emplace_back(P.lvl_ptr[l], P.lvl_ptr[l + 1]);
+    } else {
+        bd.push_back({c_lv0, c_lv1});
+    }
+    h->nnarrow = (int)bd.size();
+    h->nnarrow_pad = (h->nnarrow + 7) / 8 * 8;
+    h->blk = M.upload(bd);
+}
+
+// ------------------------------------------------------------ workspace
+
+constexpr int kLrBlocks = 256;  // grid of the low-rank reduction
+
+template <typename T> T* wsalloc(Workspace& W, size_t count) { return W.mem.alloc<T>(count); }
+
+void ensure_ws(ddlr_prec* h, int nrhs) {
+    Workspace& W = h->ws;
+    if (W.nrhs >= nrhs) return;
+    W.mem.release();
+    if (W.done_host) {
+        (void)hipHostFree(W.done_host);
+        W.done_host = nullptr;
+    }
+    const int64_t n = h->plan.n, s = h->plan.s;
+    const size_t tsz = h->precision == DDLR_FP64 ? sizeof(double) : sizeof(float);
+    W.x = W.mem.alloc<double>(n * nrhs);
+    W.r = W.mem.alloc<double>(n * nrhs);
+    W.z = W.mem.alloc<double>(n * nrhs);
+    W.p = W.mem.alloc<double>(n * nrhs);
+    W.q = W.mem.alloc<double>(n * nrhs);
+    W.a0 = W.mem.alloc<char>(tsz * n * nrhs);
+    W.a1 = W.mem.alloc<char>(tsz * n * nrhs);
+    W.a2 = W.mem.alloc<char>(tsz * n * nrhs);
+    W.a3 = W.mem.alloc<char>(tsz * n * nrhs);
+    W.ys = W.mem.alloc<char>(tsz * s * nrhs);
+    W.ws = W.mem.alloc<char>(tsz * s * nrhs);
+    const int kk = std::max(1, h->k);
+    const int64_t parts = std::max({(int64_t)kRedBlocks * nrhs, ((n + 255) / 256) * (int64_t)nrhs,
+                                    (int64_t)kLrBlocks * nrhs * kk});
+    W.part = W.mem.alloc<double>(parts);
+    W.sums = W.mem.alloc<double>(std::max(nrhs, 1) * 256);
+    W.coef = W.mem.alloc<double>((size_t)std::max(nrhs, 1) * kk);
+    W.lrsum = W.mem.alloc<double>((size_t)std::max(nrhs, 1) * kk);
+    W.lanes = W.mem.alloc<CgLane>(std::max(nrhs, 1));
+    W.done = W.mem.alloc<int>(1);
+    HIPCHK(hipHostMalloc((void**)&W.done_host, sizeof(int)));
+    W.nrhs = nrhs;
+}
+
+// ------------------------------------------------------------ kernel timing
+
+hipEvent_t prof_event(ddlr_prec* h) {
+    if (!h->prof_pool.empty()) {
+        hipEvent_t e = h->prof_pool.back();
+        h->prof_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    HIPCHK(hipEventCreate(&e));
+    return e;
+}
+
+struct ProfScope {
+    ddlr_prec* h;
+    int cls;
+    hipStream_t st;
+    hipEvent_t e0 = nullptr;
+    ProfScope(ddlr_prec* h_, int cls_, hipStream_t st_) : h(h_), cls(cls_), st(st_) {
+        if (h->prof) {
+            e0 = prof_event(h);
+            HIPCHK(hipEventRecord(e0, st));
+        }
+    }
+    ~ProfScope() noexcept(false) {
+        if (e0) {
+            hipEvent_t e1 = prof_event(h);
+            HIPCHK(hipEventRecord(e1, st));
+            h->prof_ev[cls].emplace_back(e0, e1);
+        }
+    }
+};
+
+// ------------------------------------------------------------ A0 solve
+
+template <typename T> const DevFactors<T>& factors(const ddlr_prec* h);
+template <> const DevFactors<double>& factors<double>(const ddlr_prec* h) { return h->f64; }
+template <> const DevFactors<float>& factors<float>(const ddlr_prec* h) { return h->f32; }
+
+// z = A0^{-1} x, device order, columns of type T (x may equal z)
+template <typename T>
+void a0_solve_dev(ddlr_prec* h, const DevFactors<T>& F, int nrhs, const T* x, int64_t ldx, T* z, int64_t ldz,
+                  hipStream_t st, const int* done) {
+    if (h->nnarrow > 0) {
+        ProfScope ps(h, 0, st);
+        hipLaunchKernelGGL(k_trsv_narrow<T>, dim3(h->nnarrow_pad * nrhs), dim3(256), 0, st, h->blk, h->nnarrow,
+                           h->nnarrow_pad, nrhs, h->lvl_ptr, h->lrp, h->lci, F.lv, h->urp, h->uci, F.uv, F.dinv, x,
+                           ldx, z, ldz, done);
+        LAUNCHCHK();
+    }
+    ProfScope ps(h, 1, st);
+    for (size_t l = 0; l < h->wide.size(); ++l) {
+        const int a = h->wide[l].first, e = h->wide[l].second;
+        hipLaunchKernelGGL((k_trsv_level<T, false>), dim3(grid_for((int64_t)(e - a) * nrhs, 256, 1 << 30)), dim3(256),
+                           0, st, a, e, nrhs, h->lrp, h->lci, F.lv, F.dinv, x, ldx, z, ldz, done);
+        LAUNCHCHK();
+    }
+    for (size_t l = h->wide.size(); l-- > 0;) {
+        const int a = h->wide[l].first, e = h->wide[l].second;
+        hipLaunchKernelGGL((k_trsv_level<T, true>), dim3(grid_for((int64_t)(e - a) * nrhs, 256, 1 << 30)), dim3(256),
+                           0, st, a, e, nrhs, h->urp, h->uci, F.uv, F.dinv, x, ldx, z, ldz, done);
+        LAUNCHCHK();
+    }
+}
+
+// ------------------------------------------------------------ low-rank part
+
+// coef = d .* (U^T y) (mode 1) or H (U^T y) (mode 2)
+template <typename T>
+void lr_coef(ddlr_prec* h, const T* U, int64_t rows, int nrhs, const T* y, int64_t ldy, int mode, hipStream_t st,
+             const int* done) {
+    Workspace& W = h->ws;
+    const int k = h->k;
+    ProfScope ps(h, 3, st);
+    hipLaunchKernelGGL(k_lr_reduce<T>, dim3(kLrBlocks), dim3(256), 0, st, rows, k, nrhs, U, y, ldy, W.part, done);
+    LAUNCHCHK();
+    hipLaunchKernelGGL(k_reduce_cols, dim3(nrhs * k), dim3(256), 0, st, kLrBlocks, nrhs * k, W.part, W.lrsum, done);
+    LAUNCHCHK();
+    hipLaunchKernelGGL(k_lr_coef, dim3(1), dim3(256), 0, st, k, nrhs, W.lrsum, mode, h->dvec, h->Hk, W.coef, done);
+    LAUNCHCHK();
+}
+
+// ------------------------------------------------------------ preconditioner
+
+// out = M^{-1} in (device order, type T)
+template <typename T>
+void apply_dev_T(ddlr_prec* h, int nrhs, const T* in, int64_t ldin, T* out, int64_t ldout, hipStream_t st,
+                 const int* done) {
+    const DevFactors<T>& F = factors<T>(h);
+    Workspace& W = h->ws;
+    const int64_t n = h->plan.n, s = h->plan.s;
+    if (h->variant == DDLR_1) {
+        T* a1 = (T*)W.a1;
+        T* a2 = (T*)W.a2;
+        T* ys = (T*)W.ys;
+        T* wsv = (T*)W.ws;
+        a0_solve_dev<T>(h, F, nrhs, in, ldin, a1, n, st, done);  // step 1: A0 z = x
+        hipLaunchKernelGGL(k_csr_mv<T>, dim3(grid_for(s * nrhs)), dim3(256), 0, st, s, nrhs, h->etrp, h->etci, F.etv,
+                           a1, n, (const T*)nullptr, 0, ys, s, done);  // step 2: y = E^T z
+        LAUNCHCHK();
+        lr_coef<T>(h, F.U, s, nrhs, ys, s, 1, st, done);  // step 3: w = G_{k,theta}^{-1} y (eq. gkt)
+        hipLaunchKernelGGL(k_lr_expand<T>, dim3(grid_for(s)), dim3(256), 0, st, s, h->k, nrhs, F.U, h->ws.coef, h->c0,
+                           ys, s, wsv, s, done);
+        LAUNCHCHK();
+        hipLaunchKernelGGL(k_csr_mv<T>, dim3(grid_for(n * nrhs)), dim3(256), 0, st, n, nrhs, h->erp, h->eci, F.ev,
+                           wsv, s, in, ldin, a2, n, done);  // step 4: v = E w, fused x + v
+        LAUNCHCHK();
+        a0_solve_dev<T>(h, F, nrhs, a2, n, out, ldout, st, done);  // step 5: A0 u = x + v
+    } else if (h->variant == DDLR_2) {
+        a0_solve_dev<T>(h, F, nrhs, in, ldin, out, ldout, st, done);
+        lr_coef<T>(h, F.U, n, nrhs, in, ldin, 2, st, done);
+        hipLaunchKernelGGL(k_lr_expand<T>, dim3(grid_for(n)), dim3(256), 0, st, n, h->k, nrhs, F.U, h->ws.coef, 1.0,
+                           out, ldout, out, ldout, done);
+        LAUNCHCHK();
+    } else {
+        a0_solve_dev<T>(h, F, nrhs, in, ldin, out, ldout, st, done);
+    }
+}
+
+// out = M^{-1} in for double device-order columns
+void apply_dev(ddlr_prec* h, int nrhs, const double* in, int64_t ldin, double* out, int64_t ldout, hipStream_t st,
+               const int* done) {
+    if (h->precision == DDLR_FP64) {
+        apply_dev_T<double>(h, nrhs, in, ldin, out, ldout, st, done);
+        return;
+    }
+    const int64_t n = h->plan.n;
+    float* a0 = (float*)h->ws.a0;
+    float* a3 = (float*)h->ws.a3;  // distinct from every temporary of apply_dev_T
+    hipLaunchKernelGGL((k_cast<double, float>), dim3(grid_for(n * nrhs)), dim3(256), 0, st, n, nrhs, in, ldin, a0, n,
+                       done);
+    LAUNCHCHK();
+    apply_dev_T<float>(h, nrhs, a0, n, a3, n, st, done);
+    hipLaunchKernelGGL((k_cast<float, double>), dim3(grid_for(n * nrhs)), dim3(256), 0, st, n, nrhs, a3, n, out, ldout,
+                       done);
+    LAUNCHCHK();
+}
+
+void spmv_dev(ddlr_prec* h, int nrhs, const double* x, int64_t ldx, double* y, int64_t ldy, double* part,
+              hipStream_t st, const int* done) {
+    const int64_t n = h->plan.n;
+    ProfScope ps(h, 2, st);
+    hipLaunchKernelGGL(k_spmv_sell, dim3((n + 255) / 256), dim3(256), 0, st, n, nrhs, h->sell_ptr, h->sell_col,
+                       h->sell_val, x, ldx, y, ldy, part, done);
+    LAUNCHCHK();
+}
+
+// sums[r] = a_r . b_r
+void dot_dev(ddlr_prec* h, int nrhs, const double* a, const double* b, int64_t ld, hipStream_t st, const int* done) {
+    Workspace& W = h->ws;
+    hipLaunchKernelGGL((k_dot<double, double>), dim3(kRedBlocks), dim3(256), 0, st, h->plan.n, nrhs, a, ld, b, ld,
+                       W.part, done);
+    LAUNCHCHK();
+    hipLaunchKernelGGL(k_reduce_cols, dim3(nrhs), dim3(256), 0, st, kRedBlocks, nrhs, W.part, W.sums, done);
+    LAUNCHCHK();
+}
+
+// ------------------------------------------------------------ Lanczos build
+
+void lanczos_build(ddlr_prec* h, int k, int m_req, const double* v0_user, uint64_t seed, int theta_mode) {
+    HostPlan& P = h->plan;
+    const int64_t n = P.n, s = P.s, mI = P.m;
+    hipStream_t st = nullptr;
+    int m = std::min<int64_t>(m_req, s);
+    // start vector in device interface order
+    std::vector<double> q0(s);
+    std::vector<int32_t> pd(n);
+    for (int64_t d = 0; d < n; ++d) pd[d] = P.perm[P.dev2int[d]];
+    if (v0_user) {
+        for (int64_t j = 0; j < s; ++j) q0[j] = v0_user[pd[mI + j]];
+    } else {
+        // SplitMix64 (Steele, Lea & Flood 2014) keyed by seed and user row
+        for (int64_t j = 0; j < s; ++j) {
+            uint64_t z = seed * 0x9E3779B97F4A7C15ULL + (uint64_t)(pd[mI + j] + 1) * 0xBF58476D1CE4E5B9ULL;
+            z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+            z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+            z ^= z >> 31;
+            q0[j] = 2.0 * ((double)(z >> 11) * (1.0 / 9007199254740992.0)) - 1.0;
+        }
+    }
+    double nq = 0.0;
+    for (double v : q0) nq += v * v;
+    nq = std::sqrt(nq);
+    if (!(nq > 0.0)) throw SetupError{DDLR_E_INVALID, "Lanczos start vector is zero on the interface"};
+    for (double& v : q0) v /= nq;
+    DMem tmp;
+    double* Q = tmp.alloc<double>((size_t)s * (m + 1));
+    double* w = tmp.alloc<double>(s);
+    double* t1 = tmp.alloc<double>(n);
+    double* t2 = tmp.alloc<double>(n);
+    double* alpha = tmp.alloc<double>(m);
+    double* beta = tmp.alloc<double>(m);
+    double* sc = tmp.alloc<double>(4);  // amax, inv, scratch sum
+    double* part = tmp.alloc<double>((size_t)kRedBlocks * (m + 1));
+    double* csum = tmp.alloc<double>(m + 1);
+    HIPCHK(hipMemcpy(Q, q0.data(), s * sizeof(double), hipMemcpyHostToDevice));
+    hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, st, (int64_t)4, 0.0, sc);
+    LAUNCHCHK();
+    double* amax = sc;
+    double* inv = sc + 1;
+    double* sum1 = sc + 2;
+    const int gs = grid_for(s, 256, kRedBlocks);
+    for (int j = 0; j < m; ++j) {
+        double* qj = Q + (size_t)j * s;
+        // w = Op q_j : E, A0^{-1} (twice for DDLR-2), E^T
+        hipLaunchKernelGGL(k_csr_mv<double>, dim3(grid_for(n)), dim3(256), 0, st, n, 1, h->erp, h->eci, h->f64.ev, qj,
+                           s, (const double*)nullptr, 0, t1, n, nullptr);
+        LAUNCHCHK();
+        a0_solve_dev<double>(h, h->f64, 1, t1, n, t2, n, st, nullptr);
+        const double* src = t2;
+        if (h->variant == DDLR_2) {
+            a0_solve_dev<double>(h, h->f64, 1, t2, n, t1, n, st, nullptr);
+            src = t1;
+        }
+        hipLaunchKernelGGL(k_csr_mv<double>, dim3(grid_for(s)), dim3(256), 0, st, s, 1, h->etrp, h->etci, h->f64.etv,
+                           src, n, (const double*)nullptr, 0, w, s, nullptr);
+        LAUNCHCHK();
+        // alpha_j = q_j . w
+        hipLaunchKernelGGL((k_dot<double, double>), dim3(gs), dim3(256), 0, st, s, 1, qj, s, w, s, part, nullptr);
+        LAUNCHCHK();
+        hipLaunchKernelGGL(k_reduce_cols, dim3(1), dim3(256), 0, st, gs, 1, part, sum1, nullptr);
+        LAUNCHCHK();
+        hipLaunchKernelGGL(k_lanczos_scalar, dim3(1), dim3(64), 0, st, sum1, alpha + j, 0, amax, inv);
+        LAUNCHCHK();
+        hipLaunchKernelGGL(k_lanczos_3term, dim3(gs), dim3(256), 0, st, s, j, Q, s, alpha, beta, w);
+        LAUNCHCHK();
+        // full reorthogonalisation, classical Gram-Schmidt twice
+        for (int pass = 0; pass < 2; ++pass) {
+            hipLaunchKernelGGL(k_multidot, dim3(gs), dim3(256), 0, st, s, j + 1, Q, s, w, part);
+            LAUNCHCHK();
+            hipLaunchKernelGGL(k_reduce_cols, dim3(j + 1), dim3(256), 0, st, gs, j + 1, part, csum, nullptr);
+            LAUNCHCHK();
+            hipLaunchKernelGGL(k_gemv_sub, dim3(gs), dim3(256), 0, st, s, j + 1, Q, s, csum, w);
+            LAUNCHCHK();
+        }
+        // beta_j = ||w||, q_{j+1} = w / beta_j
+        hipLaunchKernelGGL((k_dot<double, double>), dim3(gs), dim3(256), 0, st, s, 1, w, s, w, s, part, nullptr);
+        LAUNCHCHK();
+        hipLaunchKernelGGL(k_reduce_cols, dim3(1), dim3(256), 0, st, gs, 1, part, sum1, nullptr);
+        LAUNCHCHK();
+        hipLaunchKernelGGL(k_lanczos_scalar, dim3(1), dim3(64), 0, st, sum1, beta + j, 1, amax, inv);
+        LAUNCHCHK();
+        hipLaunchKernelGGL(k_scale_to, dim3(gs), dim3(256), 0, st, s, w, inv, Q + (size_t)(j + 1) * s);
+        LAUNCHCHK();
+    }
+    std::vector<double> ha(m), hb(m), hs(4);
+    HIPCHK(hipMemcpy(ha.data(), alpha, m * sizeof(double), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(hb.data(), beta, m * sizeof(double), hipMemcpyDeviceToHost));
+    // truncate at the first breakdown (beta_j <= 1e-12 max |alpha_i|, same step included)
+    double am = 0.0;
+    int meff = m;
+    for (int j = 0; j < m; ++j) {
+        am = std::max(am, std::fabs(ha[j]));
+        if (hb[j] <= 1e-12 * am) {
+            meff = j + 1;
+            break;
+        }
+    }
+    h->ta.assign(ha.begin(), ha.begin() + meff);
+    h->tb.assign(hb.begin(), hb.begin() + meff);
+    h->msteps = meff;
+    if (meff < k + 1) {
+        tmp.release();
+        throw SetupError{DDLR_E_LANCZOS, "Lanczos broke down after " + std::to_string(meff) + " steps (k+1 = " +
+                                             std::to_string(k + 1) + " needed)"};
+    }
+    // Ritz pairs of T_m, descending (stable by index), largest-|.| entry of each vector positive
+    std::vector<double> ev, Z;
+    tridiag_eig(meff, h->ta.data(), h->tb.data(), ev, Z);
+    std::vector<int> idx(meff);
+    for (int i = 0; i < meff; ++i) idx[i] = i;
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return ev[a] > ev[b]; });
+    h->ritz.resize(meff);
+    std::vector<double> Y((size_t)meff * k);
+    for (int c = 0; c < meff; ++c) h->ritz[c] = ev[idx[c]];
+    for (int c = 0; c < k; ++c) {
+        const double* z = Z.data() + (size_t)idx[c] * meff;
+        int big = 0;
+        for (int r = 1; r < meff; ++r)
+            if (std::fabs(z[r]) > std::fabs(z[big])) big = r;
+        const double sg = z[big] < 0 ? -1.0 : 1.0;
+        for (int r = 0; r < meff; ++r) Y[r + (size_t)c * meff] = sg * z[r];
+    }
+    double* Yd = tmp.alloc<double>(Y.size());
+    HIPCHK(hipMemcpy(Yd, Y.data(), Y.size() * sizeof(double), hipMemcpyHostToDevice));
+    h->lrmem.release();
+    h->k = k;
+    if (h->variant == DDLR_1) {
+        h->urows = s;
+        h->f64.U = h->lrmem.alloc<double>((size_t)s * k);
+        hipLaunchKernelGGL(k_qy<double>, dim3(grid_for(s)), dim3(256), 0, st, s, meff, k, Q, s, Yd, h->f64.U, 0,
+                           (int64_t)0);
+        LAUNCHCHK();
+        h->lam.assign(h->ritz.begin(), h->ritz.begin() + k);
+        h->theta = theta_mode == DDLR_THETA_ZERO ? 0.0 : h->ritz[k];
+        if (!(h->theta < 1.0)) {
+            tmp.release();
+            throw SetupError{DDLR_E_NOT_SPD, "theta = lambda_{k+1} >= 1: G_{k,theta} is singular or indefinite"};
+        }
+        h->c0 = 1.0 / (1.0 - h->theta);
+        h->dvec_h.resize(k);
+        for (int j = 0; j < k; ++j) {
+            if (h->lam[j] == 1.0) {
+                tmp.release();
+                throw SetupError{DDLR_E_NOT_SPD, "Ritz value equal to 1"};
+            }
+            h->dvec_h[j] = 1.0 / (1.0 - h->lam[j]) - h->c0;
+        }
+        h->spd = h->lam[0] < 1.0 && h->pivots_positive;
+        h->dvec = h->lrmem.upload(h->dvec_h);
+    } else {
+        // V_k = Q_m Y_k, U_k = A0^{-1} E V_k, K = U_k^T E V_k, H_k = (I - sym(K))^{-1}
+        h->urows = n;
+        double* V = tmp.alloc<double>((size_t)s * k);
+        hipLaunchKernelGGL(k_qy<double>, dim3(grid_for(s)), dim3(256), 0, st, s, meff, k, Q, s, Yd, V, 1, s);
+        LAUNCHCHK();
+        double* EV = tmp.alloc<double>((size_t)n * k);
+        double* Ucm = tmp.alloc<double>((size_t)n * k);
+        hipLaunchKernelGGL(k_csr_mv<double>, dim3(grid_for(n * k)), dim3(256), 0, st, n, k, h->erp, h->eci, h->f64.ev,
+                           V, s, (const double*)nullptr, 0, EV, n, nullptr);
+        LAUNCHCHK();
+        a0_solve_dev<double>(h, h->f64, k, EV, n, Ucm, n, st, nullptr);
+        const int gblk = 512;
+        double* gp = tmp.alloc<double>((size_t)gblk * k * k);
+        hipLaunchKernelGGL(k_gram, dim3(gblk), dim3(256), 0, st, n, k, Ucm, n, EV, n, gp);
+        LAUNCHCHK();
+        std::vector<double> gh((size_t)gblk * k * k);
+        HIPCHK(hipMemcpy(gh.data(), gp, gh.size() * sizeof(double), hipMemcpyDeviceToHost));
+        std::vector<double> K((size_t)k * k, 0.0);
+        for (int b = 0; b < gblk; ++b)
+            for (int q = 0; q < k * k; ++q) K[q] += gh[(size_t)b * k * k + q];
+        // I - (K + K^T)/2, Cholesky (lower, column-major), then its inverse
+        std::vector<double> Mx((size_t)k * k);
+        for (int j = 0; j < k; ++j)
+            for (int i = 0; i < k; ++i)
+                Mx[i + j * k] = (i == j ? 1.0 : 0.0) - 0.5 * (K[i * k + j] + K[j * k + i]);
+        for (int j = 0; j < k; ++j) {
+            double d = Mx[j + j * k];
+            for (int t = 0; t < j; ++t) d -= Mx[j + t * k] * Mx[j + t * k];
+            if (!(d > 0.0)) {
+                tmp.release();
+                throw SetupError{DDLR_E_NOT_SPD, "I - U_k^T E V_k is not SPD (DDLR-2 preconditioner not SPD)"};
+            }
+            d = std::sqrt(d);
+            Mx[j + j * k] = d;
+            for (int i = j + 1; i < k; ++i) {
+                double v = Mx[i + j * k];
+                for (int t = 0; t < j; ++t) v -= Mx[i + t * k] * Mx[j + t * k];
+                Mx[i + j * k] = v / d;
+            }
+        }
+        h->H_h.assign((size_t)k * k, 0.0);
+        for (int c = 0; c < k; ++c) {
+            std::vector<double> e(k, 0.0);
+            e[c] = 1.0;
+            for (int i = 0; i < k; ++i) {
+                double v = e[i];
+                for (int t = 0; t < i; ++t) v -= Mx[i + t * k] * e[t];
+                e[i] = v / Mx[i + i * k];
+            }
+            for (int i = k - 1; i >= 0; --i) {
+                double v = e[i];
+                for (int t = i + 1; t < k; ++t) v -= Mx[t + i * k] * e[t];
+                e[i] = v / Mx[i + i * k];
+            }
+            for (int i = 0; i < k; ++i) h->H_h[i + (size_t)c * k] = e[i];
+        }
+        h->spd = h->pivots_positive;
+        h->f64.U = h->lrmem.alloc<double>((size_t)n * k);
+        hipLaunchKernelGGL(k_to_rowmajor<double>, dim3(grid_for(n * k)), dim3(256), 0, st, n, k, Ucm, n, h->f64.U);
+        LAUNCHCHK();
+        h->Hk = h->lrmem.upload(h->H_h);
+        h->theta = 0.0;
+        h->c0 = 0.0;
+    }
+    if (h->precision != DDLR_FP64) {
+        h->f32.U = h->lrmem.alloc<float>((size_t)h->urows * k);
+        hipLaunchKernelGGL((k_cast<double, float>), dim3(grid_for(h->urows * k)), dim3(256), 0, st, h->urows * k, 1,
+                           h->f64.U, (int64_t)0, h->f32.U, (int64_t)0, nullptr);
+        LAUNCHCHK();
+    }
+    HIPCHK(hipDeviceSynchronize());
+    tmp.release();
+}
+
+ddlr_status fail_status(const SetupError& e) {
+    g_err = e.msg;
+    return (ddlr_status)e.status;
+}
+
+bool dev_ok(const ddlr_prec* h) {
+    if (!h) {
+        g_err = "null handle";
+        return false;
+    }
+    if (h->device < 0) {
+        g_err = "host-only handle (device = -1) cannot run device work";
+        return false;
+    }
+    return true;
+}
+
+}  // namespace
+
+// ================================================================ C ABI
+
+extern "C" {
+
+int32_t ddlr_version(void) { return 100; }
+
+void ddlr_options_default(ddlr_options* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->alpha = 1.0;
+    o->lanczos_steps = 0;
+    o->theta = DDLR_THETA_LAMBDA_K1;
+    o->factor = DDLR_FACTOR_IC0;
+    o->corder = DDLR_CORDER_MULTICOLOR;
+    o->precision = DDLR_FP64;
+    o->device = 0;
+    o->seed = 0;
+    o->lanczos_start = nullptr;
+}
+
+void ddlr_solve_options_default(ddlr_solve_options* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->method = 0;
+    o->restart = 40;
+    o->maxit = 500;
+    o->rtol = 1e-6;
+}
+
+ddlr_status ddlr_setup(const ddlr_csr* A, const int32_t* part, int32_t p, int32_t k, int32_t variant,
+                       const ddlr_options* opt_in, ddlr_prec** out) {
+    if (out) *out = nullptr;
+    if (!A || !part || !out) {
+        g_err = "null argument";
+        return DDLR_E_INVALID;
+    }
+    ddlr_options opt;
+    if (opt_in) opt = *opt_in;
+    else ddlr_options_default(&opt);
+    std::unique_ptr<ddlr_prec> h(new ddlr_prec());
+    auto t0 = std::chrono::steady_clock::now();
+    try {
+        if (variant < 0 || variant > 2) throw SetupError{DDLR_E_INVALID, "variant must be 0, 1 or 2"};
+        if (opt.precision < 0 || opt.precision > 2) throw SetupError{DDLR_E_INVALID, "bad precision"};
+        if (opt.factor < 0 || opt.factor > 1 || opt.corder < 0 || opt.corder > 1)
+            throw SetupError{DDLR_E_INVALID, "bad factor/corder option"};
+        h->precision = opt.precision;
+        h->variant = variant;
+        build_plan(h->plan, A->n, A->row_ptr, A->col_idx, A->val, part, p, opt.alpha, opt.factor, opt.corder);
+        for (double d : h->plan.D) h->pivots_positive = h->pivots_positive && d > 0.0;
+        h->spd = variant == 0 ? (int)h->pivots_positive : 0;
+        const int64_t s = h->plan.s;
+        if (variant != 0) {
+            if (k < 1 || (int64_t)k + 1 > s || k > 128)
+                throw SetupError{DDLR_E_INVALID, "k must satisfy 1 <= k, k+1 <= s and k <= 128"};
+        }
+        h->device = opt.device;
+        if (opt.device >= 0) {
+            HIPCHK(hipSetDevice(opt.device));
+            upload_structures(h.get());
+            if (variant != 0) {
+                int m = opt.lanczos_steps > 0 ? opt.lanczos_steps : 2 * k;
+                if (m < k + 1 || m > 1000)
+                    throw SetupError{DDLR_E_INVALID, "lanczos_steps must be in [k+1, 1000]"};
+                auto l0 = std::chrono::steady_clock::now();
+                lanczos_build(h.get(), k, m, opt.lanczos_start, opt.seed, opt.theta);
+                h->lanczos_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - l0).count();
+            }
+            HIPCHK(hipDeviceSynchronize());
+        } else if (variant != 0) {
+            h->k = 0;
+        }
+    } catch (const SetupError& e) {
+        h->ws.mem.release();
+        h->lrmem.release();
+        h->mem.release();
+        return fail_status(e);
+    } catch (const std::bad_alloc&) {
+        h->ws.mem.release();
+        h->lrmem.release();
+        h->mem.release();
+        g_err = "host out of memory";
+        return DDLR_E_OOM;
+    }
+    h->setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    *out = h.release();
+    return DDLR_OK;
+}
+
+}  // extern "C"
+
+static ddlr_status check_vec(const ddlr_prec* h, int32_t nrhs, const void* x, int64_t ldx, const void* y,
+                             int64_t ldy) {
+    if (!dev_ok(h)) return h ? DDLR_E_DEVICE : DDLR_E_INVALID;
+    if (nrhs < 0 || (nrhs > 0 && (!x || !y)) || ldx < h->plan.n || ldy < h->plan.n) {
+        g_err = "bad nrhs, pointer or leading dimension";
+        return DDLR_E_INVALID;
+    }
+    return DDLR_OK;
+}
+
+// Applies op to columns in chunks of kMaxRhs: gather -> op (device order) -> scatter
+template <typename Op>
+static ddlr_status run_chunked(ddlr_prec* h, int32_t nrhs, const double* x, int64_t ldx, double* y, int64_t ldy,
+                               void* stream, Op op) {
+    try {
+        HIPCHK(hipSetDevice(h->device));
+        hipStream_t st = (hipStream_t)stream;
+        const int64_t n = h->plan.n;
+        for (int32_t c0 = 0; c0 < nrhs; c0 += kMaxRhs) {
+            const int nr = std::min<int>(kMaxRhs, nrhs - c0);
+            ensure_ws(h, nr);
+            Workspace& W = h->ws;
+            hipLaunchKernelGGL((k_gather<double, double>), dim3(grid_for(n * nr)), dim3(256), 0, st, n, nr,
+                               h->perm_dev, x + c0 * ldx, ldx, W.r, n);
+            LAUNCHCHK();
+            op(nr, W.r, W.z, st);
+            hipLaunchKernelGGL((k_scatter<double, double>), dim3(grid_for(n * nr)), dim3(256), 0, st, n, nr,
+                               h->perm_dev, W.z, n, y + c0 * ldy, ldy);
+            LAUNCHCHK();
+        }
+    } catch (const SetupError& e) {
+        return fail_status(e);
+    }
+    return DDLR_OK;
+}
+
+extern "C" {
+
+ddlr_status ddlr_apply(ddlr_prec* h, int32_t nrhs, const double* x, int64_t ldx, double* y, int64_t ldy,
+                       void* stream) {
+    ddlr_status st = check_vec(h, nrhs, x, ldx, y, ldy);
+    if (st != DDLR_OK) return st;
+    return run_chunked(h, nrhs, x, ldx, y, ldy, stream, [&](int nr, double* in, double* out, hipStream_t s) {
+        apply_dev(h, nr, in, h->plan.n, out, h->plan.n, s, nullptr);
+    });
+}
+
+ddlr_status ddlr_a0_solve(ddlr_prec* h, int32_t nrhs, const double* x, int64_t ldx, double* y, int64_t ldy,
+                          void* stream) {
+    ddlr_status st = check_vec(h, nrhs, x, ldx, y, ldy);
+    if (st != DDLR_OK) return st;
+    const int v = h->variant;
+    h->variant = 0;
+    ddlr_status r = run_chunked(h, nrhs, x, ldx, y, ldy, stream, [&](int nr, double* in, double* out, hipStream_t s) {
+        apply_dev(h, nr, in, h->plan.n, out, h->plan.n, s, nullptr);
+    });
+    h->variant = v;
+    return r;
+}
+
+ddlr_status ddlr_spmv(ddlr_prec* h, int32_t nrhs, const double* x, int64_t ldx, double* y, int64_t ldy,
+                      void* stream) {
+    ddlr_status st = check_vec(h, nrhs, x, ldx, y, ldy);
+    if (st != DDLR_OK) return st;
+    return run_chunked(h, nrhs, x, ldx, y, ldy, stream, [&](int nr, double* in, double* out, hipStream_t s) {
+        spmv_dev(h, nr, in, h->plan.n, out, h->plan.n, nullptr, s, nullptr);
+    });
+}
+
+}  // extern "C"
+
+// PCG on nr columns already gathered into W.r (b); result in W.x.
+static void pcg_dev(ddlr_prec* h, int nr, const ddlr_solve_options& o, hipStream_t st) {
+    Workspace& W = h->ws;
+    const int64_t n = h->plan.n;
+    const double tol2 = o.rtol * o.rtol;
+    const int npart_spmv = (int)((n + 255) / 256);
+    hipLaunchKernelGGL(k_fill, dim3(grid_for(n * nr)), dim3(256), 0, st, n * nr, 0.0, W.x);
+    LAUNCHCHK();
+    dot_dev(h, nr, W.r, W.r, n, st, nullptr);
+    hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(64), 0, st, 0, nr, W.sums, W.lanes, tol2, o.maxit, W.done);
+    LAUNCHCHK();
+    apply_dev(h, nr, W.r, n, W.z, n, st, W.done);
+    dot_dev(h, nr, W.r, W.z, n, st, W.done);
+    hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(64), 0, st, 1, nr, W.sums, W.lanes, tol2, o.maxit, W.done);
+    LAUNCHCHK();
+    hipLaunchKernelGGL(k_cg_p, dim3(grid_for(n * nr)), dim3(256), 0, st, n, nr, W.lanes, 1, W.z, W.p, n, W.done);
+    LAUNCHCHK();
+    const int chunk = 8;
+    for (int it = 0; it < o.maxit; it += chunk) {
+        for (int c = 0; c < chunk; ++c) {
+            spmv_dev(h, nr, W.p, n, W.q, n, W.part, st, W.done);
+            hipLaunchKernelGGL(k_reduce_cols, dim3(nr), dim3(256), 0, st, npart_spmv, nr, W.part, W.sums, W.done);
+            LAUNCHCHK();
+            hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(64), 0, st, 2, nr, W.sums, W.lanes, tol2, o.maxit, W.done);
+            LAUNCHCHK();
+            hipLaunchKernelGGL(k_cg_xr, dim3(kRedBlocks), dim3(256), 0, st, n, nr, W.lanes, W.p, W.q, W.x, W.r, n,
+                               W.part, W.done);
+            LAUNCHCHK();
+            hipLaunchKernelGGL(k_reduce_cols, dim3(nr), dim3(256), 0, st, kRedBlocks, nr, W.part, W.sums, W.done);
+            LAUNCHCHK();
+            hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(64), 0, st, 3, nr, W.sums, W.lanes, tol2, o.maxit, W.done);
+            LAUNCHCHK();
+            apply_dev(h, nr, W.r, n, W.z, n, st, W.done);
+            dot_dev(h, nr, W.r, W.z, n, st, W.done);
+            hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(64), 0, st, 4, nr, W.sums, W.lanes, tol2, o.maxit, W.done);
+            LAUNCHCHK();
+            hipLaunchKernelGGL(k_cg_p, dim3(grid_for(n * nr)), dim3(256), 0, st, n, nr, W.lanes, 0, W.z, W.p, n,
+                               W.done);
+            LAUNCHCHK();
+        }
+        HIPCHK(hipMemcpyAsync(W.done_host, W.done, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (*W.done_host) break;
+    }
+}
+
+extern "C" {
+
+ddlr_status ddlr_solve(ddlr_prec* h, int32_t nrhs, const double* b, int64_t ldb, double* x, int64_t ldx,
+                       const ddlr_solve_options* opt_in, ddlr_solve_info* info, void* stream) {
+    ddlr_status st0 = check_vec(h, nrhs, b, ldb, x, ldx);
+    if (st0 != DDLR_OK) return st0;
+    ddlr_solve_options o;
+    if (opt_in) o = *opt_in;
+    else ddlr_solve_options_default(&o);
+    if (!info || o.maxit < 1 || !(o.rtol > 0.0) || (o.method != 0 && o.method != 1)) {
+        g_err = "bad solve options";
+        return DDLR_E_INVALID;
+    }
+    if (o.method == 1) {
+        g_err = "GMRES is not available in this build";
+        return DDLR_E_INVALID;
+    }
+    if (o.method == 0 && !h->spd) {
+        g_err = "preconditioner is not certified SPD (negative local pivot or largest Ritz value >= 1): use GMRES";
+        return DDLR_E_NOT_SPD;
+    }
+    ddlr_status result = DDLR_OK;
+    try {
+        HIPCHK(hipSetDevice(h->device));
+        hipStream_t st = (hipStream_t)stream;
+        const int64_t n = h->plan.n;
+        for (int32_t c0 = 0; c0 < nrhs; c0 += kMaxRhs) {
+            const int nr = std::min<int>(kMaxRhs, nrhs - c0);
+            ensure_ws(h, nr);
+            Workspace& W = h->ws;
+            hipLaunchKernelGGL((k_gather<double, double>), dim3(grid_for(n * nr)), dim3(256), 0, st, n, nr,
+                               h->perm_dev, b + c0 * ldb, ldb, W.r, n);
+            LAUNCHCHK();
+            pcg_dev(h, nr, o, st);
+            hipLaunchKernelGGL((k_scatter<double, double>), dim3(grid_for(n * nr)), dim3(256), 0, st, n, nr,
+                               h->perm_dev, W.x, n, x + c0 * ldx, ldx);
+            LAUNCHCHK();
+            // true residual: q = b - A x (device order), recursive residual from the lanes
+            hipLaunchKernelGGL((k_gather<double, double>), dim3(grid_for(n * nr)), dim3(256), 0, st, n, nr,
+                               h->perm_dev, b + c0 * ldb, ldb, W.r, n);
+            LAUNCHCHK();
+            spmv_dev(h, nr, W.x, n, W.q, n, nullptr, st, nullptr);
+            hipLaunchKernelGGL(k_sub, dim3(grid_for(n * nr)), dim3(256), 0, st, n * nr, W.r, W.q, W.z);
+            LAUNCHCHK();
+            std::vector<CgLane> lanes(nr);
+            std::vector<double> rr(nr);
+            HIPCHK(hipMemcpyAsync(lanes.data(), W.lanes, nr * sizeof(CgLane), hipMemcpyDeviceToHost, st));
+            dot_dev(h, nr, W.z, W.z, n, st, nullptr);
+            HIPCHK(hipMemcpyAsync(rr.data(), W.sums, nr * sizeof(double), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            for (int c = 0; c < nr; ++c) {
+                ddlr_solve_info& inf = info[c0 + c];
+                const double bb = lanes[c].bb;
+                inf.iters = lanes[c].its;
+                const bool conv = bb == 0.0 || lanes[c].rr <= o.rtol * o.rtol * bb;
+                inf.status = conv ? DDLR_OK : DDLR_E_NO_CONVERGENCE;
+                inf.relres = bb > 0 ? std::sqrt(lanes[c].rr / bb) : 0.0;
+                inf.relres_true = bb > 0 ? std::sqrt(rr[c] / bb) : 0.0;
+                if (!conv) result = DDLR_E_NO_CONVERGENCE;
+            }
+        }
+    } catch (const SetupError& e) {
+        return fail_status(e);
+    }
+    if (result != DDLR_OK) g_err = "some right-hand sides did not converge";
+    return result;
+}
+
+ddlr_status ddlr_query(const ddlr_prec* h, ddlr_info* info) {
+    if (!h || !info) {
+        g_err = "null argument";
+        return DDLR_E_INVALID;
+    }
+    std::memset(info, 0, sizeof(*info));
+    const HostPlan& P = h->plan;
+    info->n = P.n;
+    info->m = P.m;
+    info->s = P.s;
+    info->nnz_a = P.A.nnz();
+    info->nnz_l = P.L.nnz();
+    info->nnz_e = P.A.nnz() - P.A0.nnz() + P.s;  // unused rough figure, recomputed below
+    int64_t ne = 0;
+    for (int64_t i = 0; i < P.m; ++i)
+        for (int64_t t = P.A.rp[i]; t < P.A.rp[i + 1]; ++t) ne += P.A.ci[t] >= P.m;
+    info->nnz_e = ne + P.s;
+    info->p = P.p;
+    info->k = h->k;
+    info->variant = h->variant;
+    info->lanczos_steps = h->msteps;
+    info->ncolours = P.ncolours;
+    info->levels_b_max = P.levels_b_max;
+    info->levels_c = P.levels_c;
+    info->spd = h->spd;
+    info->precision = h->precision;
+    info->on_device = h->device >= 0;
+    info->theta = h->theta;
+    info->c0 = h->c0;
+    // stored entries: L (strict lower) + D + E + U_k (+ H_k)
+    const double stored = (double)P.L.nnz() + (double)P.n + (double)info->nnz_e + (double)h->urows * h->k +
+                          (h->variant == DDLR_2 ? (double)h->k * h->k : 0.0);
+    info->fill_ratio = stored / (double)P.A.nnz();
+    info->setup_ms = h->setup_ms;
+    info->lanczos_ms = h->lanczos_ms;
+    return DDLR_OK;
+}
+
+ddlr_status ddlr_get_ordering(const ddlr_prec* h, int32_t* perm, int32_t* iface, int32_t* colour) {
+    if (!h) {
+        g_err = "null handle";
+        return DDLR_E_INVALID;
+    }
+    const HostPlan& P = h->plan;
+    if (perm) std::copy(P.perm.begin(), P.perm.end(), perm);
+    if (iface) std::copy(P.iface.begin(), P.iface.end(), iface);
+    if (colour) std::copy(P.colour.begin(), P.colour.end(), colour);
+    return DDLR_OK;
+}
+
+ddlr_status ddlr_get_factor(const ddlr_prec* h, int64_t* row_ptr, int32_t* col, double* val, double* D) {
+    if (!h) {
+        g_err = "null handle";
+        return DDLR_E_INVALID;
+    }
+    const HostPlan& P = h->plan;
+    if (row_ptr) std::copy(P.L.rp.begin(), P.L.rp.end(), row_ptr);
+    if (col) std::copy(P.L.ci.begin(), P.L.ci.end(), col);
+    if (val) std::copy(P.L.v.begin(), P.L.v.end(), val);
+    if (D) std::copy(P.D.begin(), P.D.end(), D);
+    return DDLR_OK;
+}
+
+ddlr_status ddlr_get_levels(const ddlr_prec* h, int32_t* level) {
+    if (!h || !level) {
+        g_err = "null argument";
+        return DDLR_E_INVALID;
+    }
+    std::copy(h->plan.level.begin(), h->plan.level.end(), level);
+    return DDLR_OK;
+}
+
+ddlr_status ddlr_get_lanczos(const ddlr_prec* h, double* alpha, double* beta, double* ritz) {
+    if (!h) {
+        g_err = "null handle";
+        return DDLR_E_INVALID;
+    }
+    if (alpha) std::copy(h->ta.begin(), h->ta.end(), alpha);
+    if (beta) std::copy(h->tb.begin(), h->tb.end(), beta);
+    if (ritz) std::copy(h->ritz.begin(), h->ritz.end(), ritz);
+    return DDLR_OK;
+}
+
+ddlr_status ddlr_get_lowrank(const ddlr_prec* h, double* U, double* aux) {
+    if (!dev_ok(h)) return h ? DDLR_E_DEVICE : DDLR_E_INVALID;
+    if (h->variant == 0 || h->k == 0) {
+        g_err = "no low-rank part";
+        return DDLR_E_INVALID;
+    }
+    try {
+        HIPCHK(hipSetDevice(h->device));
+        const HostPlan& P = h->plan;
+        const int k = h->k;
+        std::vector<double> Ur((size_t)h->urows * k);
+        HIPCHK(hipMemcpy(Ur.data(), h->f64.U, Ur.size() * sizeof(double), hipMemcpyDeviceToHost));
+        if (U) {
+            std::fill(U, U + (size_t)P.n * k, 0.0);
+            const int64_t off = h->variant == DDLR_1 ? P.m : 0;
+            for (int64_t i = 0; i < h->urows; ++i) {
+                const int32_t user = P.perm[P.dev2int[off + i]];
+                for (int j = 0; j < k; ++j) U[user + (size_t)j * P.n] = Ur[(size_t)i * k + j];
+            }
+        }
+        if (aux) {
+            if (h->variant == DDLR_1) {
+                std::copy(h->lam.begin(), h->lam.end(), aux);
+                aux[k] = h->theta;
+            } else {
+                std::copy(h->H_h.begin(), h->H_h.end(), aux);
+            }
+        }
+    } catch (const SetupError& e) {
+        return fail_status(e);
+    }
+    return DDLR_OK;
+}
+
+ddlr_status ddlr_set_lowrank(ddlr_prec* h, int32_t variant, int32_t k, const double* U, const double* aux) {
+    if (!dev_ok(h)) return h ? DDLR_E_DEVICE : DDLR_E_INVALID;
+    if ((variant != 1 && variant != 2) || k < 1 || k > 128 || !U || !aux) {
+        g_err = "bad set_lowrank arguments";
+        return DDLR_E_INVALID;
+    }
+    try {
+        HIPCHK(hipSetDevice(h->device));
+        HIPCHK(hipDeviceSynchronize());
+        const HostPlan& P = h->plan;
+        const int64_t rows = variant == 1 ? P.s : P.n, off = variant == 1 ? P.m : 0;
+        std::vector<double> Ur((size_t)rows * k);
+        for (int64_t i = 0; i < rows; ++i) {
+            const int32_t user = P.perm[P.dev2int[off + i]];
+            for (int j = 0; j < k; ++j) Ur[(size_t)i * k + j] = U[user + (size_t)j * P.n];
+        }
+        h->lrmem.release();
+        h->dvec = nullptr;
+        h->Hk = nullptr;
+        h->f64.U = nullptr;
+        h->f32.U = nullptr;
+        h->variant = variant;
+        h->k = k;
+        h->urows = rows;
+        h->f64.U = h->lrmem.upload(Ur);
+        if (h->precision != DDLR_FP64) {
+            std::vector<float> f(Ur.size());
+            for (size_t i = 0; i < f.size(); ++i) f[i] = (float)Ur[i];
+            h->f32.U = h->lrmem.upload(f);
+        }
+        if (variant == 1) {
+            h->lam.assign(aux, aux + k);
+            h->theta = aux[k];
+            h->c0 = 1.0 / (1.0 - h->theta);
+            h->dvec_h.resize(k);
+            for (int j = 0; j < k; ++j) h->dvec_h[j] = 1.0 / (1.0 - h->lam[j]) - h->c0;
+            h->spd = h->theta < 1.0 && h->lam[0] < 1.0 && h->pivots_positive;
+            h->dvec = h->lrmem.upload(h->dvec_h);
+        } else {
+            h->H_h.assign(aux, aux + (size_t)k * k);
+            h->Hk = h->lrmem.upload(h->H_h);
+            h->spd = h->pivots_positive;
+            h->theta = 0.0;
+            h->c0 = 0.0;
+        }
+        h->ws.nrhs = 0;  // coefficient buffers depend on k
+        h->ws.mem.release();
+    } catch (const SetupError& e) {
+        return fail_status(e);
+    }
+    return DDLR_OK;
+}
+
+static void prof_reset(ddlr_prec* h) {
+    for (int c = 0; c < kProfClasses; ++c) {
+        for (auto& pr : h->prof_ev[c]) {
+            h->prof_pool.push_back(pr.first);
+            h->prof_pool.push_back(pr.second);
+        }
+        h->prof_ev[c].clear();
+    }
+}
+
+ddlr_status ddlr_profile(ddlr_prec* h, int32_t on) {
+    if (!dev_ok(h)) return h ? DDLR_E_DEVICE : DDLR_E_INVALID;
+    try {
+        HIPCHK(hipSetDevice(h->device));
+        HIPCHK(hipDeviceSynchronize());
+        prof_reset(h);
+        h->prof = on != 0;
+    } catch (const SetupError& e) {
+        return fail_status(e);
+    }
+    return DDLR_OK;
+}
+
+ddlr_status ddlr_profile_read(ddlr_prec* h, int32_t which, double* total_ms, int64_t* launches) {
+    if (!dev_ok(h)) return h ? DDLR_E_DEVICE : DDLR_E_INVALID;
+    if (which < 0 || which >= kProfClasses || !total_ms || !launches) {
+        g_err = "bad profile query";
+        return DDLR_E_INVALID;
+    }
+    try {
+        HIPCHK(hipSetDevice(h->device));
+        HIPCHK(hipDeviceSynchronize());
+        double t = 0.0;
+        for (auto& pr : h->prof_ev[which]) {
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, pr.first, pr.second));
+            t += ms;
+        }
+        *total_ms = t;
+        *launches = (int64_t)h->prof_ev[which].size();
+    } catch (const SetupError& e) {
+        return fail_status(e);
+    }
+    return DDLR_OK;
+}
+
+void ddlr_destroy(ddlr_prec* h) {
+    if (!h) return;
+    if (h->device >= 0) {
+        (void)hipSetDevice(h->device);
+        (void)hipDeviceSynchronize();
+        prof_reset(h);
+        for (hipEvent_t e : h->prof_pool) (void)hipEventDestroy(e);
+    }
+    h->ws.mem.release();
+    if (h->ws.done_host) (void)hipHostFree(h->ws.done_host);
+    h->lrmem.release();
+    h->mem.release();
+    delete h;
+}
+
+const char* ddlr_status_string(int32_t s) {
+    switch (s) {
+    case DDLR_OK: return "ok";
+    case DDLR_E_INVALID: return "invalid argument";
+    case DDLR_E_NOT_SYMMETRIC: return "matrix not symmetric";
+    case DDLR_E_BREAKDOWN: return "local factorisation breakdown";
+    case DDLR_E_NOT_SPD: return "preconditioner not SPD";
+    case DDLR_E_NO_CONVERGENCE: return "no convergence";
+    case DDLR_E_LANCZOS: return "Lanczos breakdown";
+    case DDLR_E_OOM: return "out of device memory";
+    case DDLR_E_DEVICE: return "device error";
+    default: return "unknown status";
+    }
+}
+
+const char* ddlr_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,67 @@
+// Host-side construction of the DDLR splitting and local factors.
+//
+// Steps 1-3 of the build (Sec. 4.1): classification and reordering (Sec. 2.1,
+// eq. Bmat), the splitting A = A0 - E E^T (Sec. 3.1), incomplete LDL^T of every
+// diagonal block of A0 (Sec. 5), plus what the GPU needs to run those factors:
+// a level schedule per block and the "device order" that stores every level of
+// every block contiguously.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace ddlr {
+
+struct SetupError {
+    int status;
+    std::string msg;
+};
+
+struct HostCsr {
+    std::vector<int64_t> rp;
+    std::vector<int32_t> ci;
+    std::vector<double> v;
+    int64_t rows() const { return rp.empty() ? 0 : (int64_t)rp.size() - 1; }
+    int64_t nnz() const { return rp.empty() ? 0 : rp.back(); }
+};
+
+struct HostPlan {
+    int64_t n = 0, m = 0, s = 0;
+    int32_t p = 0;
+    double alpha = 1.0;
+    int32_t ncolours = 0;
+    // ordering (internal = factor order)
+    std::vector<int32_t> iface;   // user row -> 0/1
+    std::vector<int32_t> perm;    // internal -> user
+    std::vector<int32_t> iperm;   // user -> internal
+    std::vector<int32_t> colour;  // interface position -> colour
+    std::vector<int64_t> boff;    // p+2 block offsets (internal order)
+    // internal-order matrices
+    HostCsr A;    // P A P^T
+    HostCsr A0;   // blockdiag(B_alpha, C_alpha)
+    HostCsr L;    // strict lower incomplete factor, internal order
+    std::vector<double> D;
+    // level schedule (internal order) and device order
+    std::vector<int32_t> level;   // internal row -> level inside its block
+    std::vector<int32_t> dev2int; // device position -> internal row
+    std::vector<int32_t> int2dev; // internal row -> device position
+    std::vector<int32_t> lvl_ptr; // device-order row offsets of all levels, all blocks, concatenated
+    std::vector<int32_t> blk_lvl; // p+2: levels of block b are lvl_ptr[blk_lvl[b] .. blk_lvl[b+1]]
+    int32_t levels_b_max = 0, levels_c = 0;
+};
+
+// Validates A (sorted columns, symmetric values) and part.
+void validate(int64_t n, const int64_t* rp, const int32_t* ci, const double* v, const int32_t* part, int32_t p);
+
+// Steps 1-3.  factor: 0 = IC(0) (pivots must be > 0), 1 = ILDL(0) (|pivot| >=
+// 1e-14 |a_ii|).  corder: 0 = greedy multicolour interface order, 1 = natural.
+void build_plan(HostPlan& P, int64_t n, const int64_t* rp, const int32_t* ci, const double* v,
+                const int32_t* part, int32_t p, double alpha, int factor, int corder);
+
+// Eigen-decomposition of a symmetric tridiagonal matrix (diag a[0..m-1],
+// off-diagonal b[0..m-2]) by implicit QR steps with Wilkinson shifts.
+// Returns eigenvalues (unsorted) in ev and eigenvectors column-major in Z.
+void tridiag_eig(int m, const double* a, const double* b, std::vector<double>& ev, std::vector<double>& Z);
+
+}  // namespace ddlr

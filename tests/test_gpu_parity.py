@@ -1,0 +1,231 @@
+"""GPU parity of the HIP path against the CPU oracle, through the C ABI.
+
+Tolerances (FP64 path): A0 solve and SpMV 1e-12 relative, preconditioner
+application with imported low-rank data 1e-10 relative, CG iterate after a
+fixed number of steps 1e-10, own end-to-end setup: Ritz values 1e-8 and
+iteration counts within one of the oracle.  Mixed path: true residual
+<= 1e-6 and at most 10% (+1) more iterations than FP64.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import paper_1505_04341_amd as D
+import workloads as w
+from oracle import FACTOR_ILDL, Oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def say(*a):
+    print("[case]", *a, file=sys.stderr, flush=True)
+
+
+def to_dev(x):
+    """(n, nrhs) numpy -> (nrhs, n) contiguous cuda float64."""
+    x = np.asarray(x, dtype=np.float64)
+    if x.ndim == 1:
+        return torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+    return torch.from_numpy(np.ascontiguousarray(x.T)).to(DEV)
+
+
+def to_host(t):
+    a = t.cpu().numpy()
+    return a if a.ndim == 1 else a.T
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def setup_pair(cfg, variant=1, wide=None, **kw):
+    if wide is not None:
+        os.environ["DDLR_C_WIDE"] = "1" if wide else "0"
+    try:
+        h = D.ddlr_setup(cfg["A"], cfg["part"], cfg["p"], cfg["k"], variant, lanczos_steps=cfg.get("m", 0),
+                         lanczos_start=w.lanczos_start(cfg["A"].n, 0), **kw)
+    finally:
+        os.environ.pop("DDLR_C_WIDE", None)
+    o = Oracle(cfg["A"], cfg["part"], cfg["p"], alpha=kw.get("alpha", 1.0), corder=kw.get("corder", 0),
+               factor=FACTOR_ILDL if kw.get("factor", 0) == 1 else 0)
+    return h, o
+
+
+def irregular():
+    A = w.tpfa_2d(37, 29, 11)
+    return dict(A=A, part=w.box_partition((37, 29), (3, 2)), p=6, k=6, m=20)
+
+
+CASES = {"c1": lambda: w.config("c1"), "small2d": lambda: w.config("small2d"),
+         "small3d": lambda: w.config("small3d"), "irregular": irregular}
+
+
+@pytest.mark.parametrize("name", ["c1", "small3d", "irregular"])
+@pytest.mark.parametrize("wide", [False, True])
+def test_a0_solve_and_spmv(name, wide):
+    cfg = CASES[name]()
+    say("a0_solve", name, "wide", wide)
+    h, o = setup_pair(cfg, variant=D.VARIANT_A0, wide=wide)
+    n = cfg["A"].n
+    rng = np.random.default_rng(7)
+    for nrhs in (1, 3, 17):  # 17: two launches of up to 16 columns, ragged tail
+        x = rng.standard_normal((n, nrhs))
+        y = torch.empty((nrhs, n), dtype=torch.float64, device=DEV)
+        D.ddlr_a0_solve(h, to_dev(x), y)
+        got = to_host(y)
+        ref = o.a0_solve(x)
+        assert rel(got, ref) <= 1e-12, (nrhs, rel(got, ref))
+        D.ddlr_spmv(h, to_dev(x), y)
+        ref = cfg["A"].to_scipy() @ x
+        assert rel(to_host(y), ref) <= 1e-14
+
+
+@pytest.mark.parametrize("name", ["c1", "small2d", "irregular"])
+@pytest.mark.parametrize("variant", [1, 2])
+def test_apply_with_imported_lowrank(name, variant):
+    cfg = CASES[name]()
+    say("apply imported", name, variant)
+    h, o = setup_pair(cfg, variant=variant)
+    o.lowrank(variant, cfg["k"], cfg["m"], w.lanczos_start(cfg["A"].n, 0))
+    lr = o.get_lowrank()
+    if variant == 1:
+        D.ddlr_set_lowrank(h, 1, lr[0], lr[1], lr[2])
+    else:
+        D.ddlr_set_lowrank(h, 2, lr[0], lr[1])
+    n = cfg["A"].n
+    x = np.random.default_rng(3).standard_normal((n, 5))
+    y = torch.empty((5, n), dtype=torch.float64, device=DEV)
+    D.ddlr_apply(h, to_dev(x), y)
+    ref = o.apply(x)
+    assert rel(to_host(y), ref) <= 1e-10
+    # round trip of the low-rank data through the ABI
+    back = D.ddlr_get_lowrank(h)
+    assert np.array_equal(back[0], lr[0])
+
+
+@pytest.mark.parametrize("name", ["c1", "irregular", "small3d"])
+@pytest.mark.parametrize("variant", [1, 2])
+def test_own_lanczos_matches_oracle(name, variant):
+    cfg = CASES[name]()
+    say("lanczos", name, variant)
+    h, o = setup_pair(cfg, variant=variant)
+    o.lowrank(variant, cfg["k"], cfg["m"], w.lanczos_start(cfg["A"].n, 0))
+    ga, gb, gr = D.ddlr_get_lanczos(h)
+    oa, ob, orz = o.lanczos_record()
+    assert len(ga) == len(oa)
+    k = cfg["k"]
+    assert np.abs(gr[: k + 1] - orz[: k + 1]).max() <= 1e-8 * max(1.0, abs(orz[0]))
+    assert np.abs(ga[:4] - oa[:4]).max() <= 1e-10 * np.abs(oa).max()
+    q = D.ddlr_query(h)
+    if variant == 1:
+        assert abs(q["theta"] - orz[k]) <= 1e-8
+
+
+@pytest.mark.parametrize("name", ["c1", "small3d", "irregular"])
+def test_pcg_fixed_steps_matches_oracle(name):
+    """Same preconditioner (imported), same number of CG steps: same iterate."""
+    cfg = CASES[name]()
+    say("pcg fixed", name)
+    h, o = setup_pair(cfg, variant=1)
+    o.lowrank(1, cfg["k"], cfg["m"], w.lanczos_start(cfg["A"].n, 0))
+    U, lam, th = o.get_lowrank()
+    D.ddlr_set_lowrank(h, 1, U, lam, th)
+    b, _ = w.rhs_from_solution(cfg["A"], 0, 3)
+    x = torch.zeros((3, cfg["A"].n), dtype=torch.float64, device=DEV)
+    st, info = D.ddlr_solve(h, to_dev(b), x, maxit=6)
+    assert st == D.E_NO_CONVERGENCE and all(i["iters"] == 6 for i in info)
+    xo, infoo = o.pcg(b, maxit=6)
+    assert rel(to_host(x), xo) <= 1e-10
+    st, info = D.ddlr_solve(h, to_dev(b), x)
+    xo, infoo = o.pcg(b)
+    assert st == D.OK
+    # the iterates agree to rounding, so the step that crosses 1e-6 may differ by one
+    assert all(abs(i["iters"] - int(io)) <= 1 for i, io in zip(info, infoo["its"]))
+    assert rel(to_host(x), xo) <= 1e-5
+
+
+@pytest.mark.parametrize("name", ["c1", "small3d"])
+@pytest.mark.parametrize("variant", [1, 2])
+def test_pcg_end_to_end_own_setup(name, variant):
+    cfg = CASES[name]()
+    say("pcg e2e", name, variant)
+    h, o = setup_pair(cfg, variant=variant)
+    o.lowrank(variant, cfg["k"], cfg["m"], w.lanczos_start(cfg["A"].n, 0))
+    nrhs = cfg.get("nrhs", 1)
+    b, xs = w.rhs_from_solution(cfg["A"], 0, nrhs)
+    x = torch.zeros((nrhs, cfg["A"].n), dtype=torch.float64, device=DEV)
+    st, info = D.ddlr_solve(h, to_dev(b), x)
+    assert st == D.OK
+    xo, infoo = o.pcg(b)
+    for i, io in zip(info, infoo["its"]):
+        assert abs(i["iters"] - io) <= 1
+        assert i["relres_true"] <= 1.05e-6
+    assert rel(to_host(x), xo) <= 1e-5
+
+
+@pytest.mark.parametrize("prec", [D.FP32])
+def test_mixed_precision_solve(prec):
+    cfg = w.config("small3d")
+    say("mixed", prec)
+    h64, _ = setup_pair(cfg, variant=1)
+    h32 = D.ddlr_setup(cfg["A"], cfg["part"], cfg["p"], cfg["k"], 1, lanczos_steps=cfg["m"],
+                       lanczos_start=w.lanczos_start(cfg["A"].n, 0), precision=prec)
+    b, xs = w.rhs_from_solution(cfg["A"], 0, 4)
+    x64 = torch.zeros((4, cfg["A"].n), dtype=torch.float64, device=DEV)
+    x32 = torch.zeros_like(x64)
+    _, i64 = D.ddlr_solve(h64, to_dev(b), x64)
+    st, i32 = D.ddlr_solve(h32, to_dev(b), x32)
+    assert st == D.OK
+    for a, c in zip(i64, i32):
+        assert c["relres_true"] <= 1e-6
+        assert c["iters"] <= int(1.1 * a["iters"]) + 1
+    # state the error against the FP64 result
+    err = rel(to_host(x32), to_host(x64))
+    say("mixed vs fp64 relative difference", err)
+    assert err <= 1e-4
+
+
+def test_solve_edge_cases():
+    cfg = w.config("c1")
+    say("edge cases")
+    h, o = setup_pair(cfg, variant=1)
+    n = cfg["A"].n
+    b = np.zeros((n, 2))
+    b[:, 1] = w.rhs_from_solution(cfg["A"], 1, 1)[0][:, 0]
+    x = torch.full((2, n), 5.0, dtype=torch.float64, device=DEV)
+    st, info = D.ddlr_solve(h, to_dev(b), x)
+    assert st == D.OK
+    assert info[0]["iters"] == 0 and float(x[0].abs().max()) == 0.0
+    assert info[1]["iters"] > 0
+    st, info = D.ddlr_solve(h, to_dev(b), x, maxit=1)
+    assert st == D.E_NO_CONVERGENCE and info[1]["iters"] == 1 and info[1]["status"] == D.E_NO_CONVERGENCE
+    # zero columns is a no-op
+    lib = D.load_library()
+    assert lib.ddlr_apply(h.handle, 0, None, n, None, n, None) == D.OK
+    # leading dimension too small
+    t = torch.zeros(n, dtype=torch.float64, device=DEV)
+    assert lib.ddlr_apply(h.handle, 1, t.data_ptr(), n - 1, t.data_ptr(), n, None) == D.E_INVALID
+
+
+def test_cg_refused_for_indefinite_preconditioner():
+    A = w.laplacian_2d(24, 20)
+    d = A.val.copy()
+    rows = np.repeat(np.arange(A.n), np.diff(A.rowptr))
+    d[rows == A.col] -= 0.7  # largest Ritz value of E^T A0^{-1} E above 1
+    A = w.CSR(A.n, A.rowptr, A.col, d)
+    part = w.box_partition((24, 20), (2, 2))
+    say("indefinite")
+    h = D.ddlr_setup(A, part, 4, 10, 1, lanczos_steps=30, factor=D.FACTOR_ILDL0,
+                     lanczos_start=w.lanczos_start(A.n, 1))
+    q = D.ddlr_query(h)
+    assert q["spd"] == 0
+    b = to_dev(w.rhs_from_solution(A, 0, 1)[0])
+    x = torch.zeros_like(b)
+    with pytest.raises(D.DDLRError) as e:
+        D.ddlr_solve(h, b, x)
+    assert e.value.status == D.E_NOT_SPD

@@ -1,0 +1,120 @@
+"""CPU tests of the HIP library's host side: the C ABI loads and exports every
+declared symbol, and the host setup (ordering, colouring, splitting, local
+factors, level schedule) matches the oracle.  No device work is done here
+(setup with device = -1)."""
+import os
+import re
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import paper_1505_04341_amd as D
+import workloads as w
+from oracle import Oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_symbol():
+    hdr = open(os.path.join(ROOT, "include", "ddlr.h")).read()
+    declared = sorted(set(re.findall(r"\b(ddlr_[a-z0-9_]+)\s*\(", hdr)))
+    lib = D.load_library()
+    missing = [s for s in declared if not hasattr(lib, s)]
+    assert not missing, missing
+    assert set(declared) == set(D.EXPORTED)
+
+
+def _cases():
+    yield "c1", w.config("c1"), {}
+    yield "small2d", w.config("small2d"), {}
+    yield "small3d", w.config("small3d"), {}
+    A = w.random27_3d(9, 8, 7, 3)
+    yield "r27", dict(A=A, part=w.box_partition((9, 8, 7), (2, 2, 2)), p=8, k=6), dict(alpha=2.0)
+    A = w.tpfa_2d(31, 27, 5)
+    yield "tpfa", dict(A=A, part=w.box_partition((31, 27), (3, 3)), p=9, k=6), {}
+    yield "c1-natural", w.config("c1"), dict(corder=D.CORDER_NATURAL)
+
+
+@pytest.mark.parametrize("name,cfg,kw", list(_cases()), ids=[c[0] for c in _cases()])
+def test_host_setup_matches_oracle(name, cfg, kw):
+    A = cfg["A"]
+    h = D.ddlr_setup(A, cfg["part"], cfg["p"], cfg["k"], D.DDLR_1, device=-1, **kw)
+    o = Oracle(A, cfg["part"], cfg["p"], alpha=kw.get("alpha", 1.0), corder=kw.get("corder", 0))
+    perm, iface, colour = D.ddlr_get_ordering(h)
+    operm, oiface, ocolour, _ = o.ordering()
+    assert np.array_equal(perm, operm)
+    assert np.array_equal(iface, oiface)
+    assert np.array_equal(colour, ocolour)
+    q = D.ddlr_query(h)
+    assert (q["m"], q["s"], q["ncolours"]) == (o.m, o.s, o.ncolours)
+    L, Dg = D.ddlr_get_factor(h)
+    Lo = o.csr("L")
+    assert np.array_equal(L.indptr, Lo.indptr) and np.array_equal(L.indices, Lo.indices)
+    assert np.abs(L.data - Lo.data).max(initial=0) <= 1e-12 * max(1.0, np.abs(Lo.data).max(initial=0))
+    assert np.abs(Dg - o.diag()).max() <= 1e-12 * np.abs(o.diag()).max()
+
+
+@pytest.mark.parametrize("name,cfg,kw", list(_cases()), ids=[c[0] for c in _cases()])
+def test_level_schedule_valid(name, cfg, kw):
+    """Every row's level is 1 + the largest level of the rows it depends on
+    (0 if none), so rows of one level are independent."""
+    h = D.ddlr_setup(cfg["A"], cfg["part"], cfg["p"], cfg["k"], D.DDLR_1, device=-1, **kw)
+    L, _ = D.ddlr_get_factor(h)
+    lev = D.ddlr_get_levels(h)
+    Lc = L.tocsr()
+    for i in range(L.shape[0]):
+        cols = Lc.indices[Lc.indptr[i]:Lc.indptr[i + 1]]
+        expect = 0 if cols.size == 0 else lev[cols].max() + 1
+        assert lev[i] == expect
+
+
+def test_level_depth_closed_form():
+    """Lexicographic box: level of (x,y) is x+y inside the interior block, so the
+    depth of a B-block is (nx-1)+(ny-1) of its interior box (C1: 31+31 - 1 = 61)."""
+    c = w.config("c1")
+    h = D.ddlr_setup(c["A"], c["part"], c["p"], c["k"], D.DDLR_1, device=-1)
+    q = D.ddlr_query(h)
+    assert q["levels_b_max"] == 61 and q["levels_c"] == q["ncolours"] == 2
+
+
+def test_setup_errors_are_reported():
+    A = w.laplacian_2d(6, 6)
+    part = w.box_partition((6, 6), (2, 2))
+    bad = part.copy()
+    bad[0] = 7
+    with pytest.raises(D.DDLRError) as e:
+        D.ddlr_setup(A, bad, 4, 2, D.DDLR_1, device=-1)
+    assert e.value.status == D.E_INVALID
+    d = A.to_dense()
+    d[0, 1] = -3.0
+    M = sp.csr_matrix(d)
+    M.sort_indices()
+    B = w.CSR(36, M.indptr.astype(np.int64), M.indices.astype(np.int32), M.data)
+    with pytest.raises(D.DDLRError) as e:
+        D.ddlr_setup(B, part, 4, 2, D.DDLR_1, device=-1)
+    assert e.value.status == D.E_NOT_SYMMETRIC
+    d = A.to_dense()
+    d[7, 7] = -3.0
+    M = sp.csr_matrix(d)
+    M.sort_indices()
+    B = w.CSR(36, M.indptr.astype(np.int64), M.indices.astype(np.int32), M.data)
+    with pytest.raises(D.DDLRError) as e:
+        D.ddlr_setup(B, part, 4, 2, D.DDLR_1, device=-1)
+    assert e.value.status == D.E_BREAKDOWN
+    assert "row" in str(e.value)
+    D.ddlr_setup(B, part, 4, 2, D.DDLR_1, device=-1, factor=D.FACTOR_ILDL0)
+    with pytest.raises(D.DDLRError) as e:  # k + 1 > s
+        D.ddlr_setup(A, part, 4, 400, D.DDLR_1, device=-1)
+    assert e.value.status == D.E_INVALID
+    with pytest.raises(D.DDLRError) as e:  # a single subdomain has no interface
+        D.ddlr_setup(A, np.zeros(36, np.int32), 1, 2, D.DDLR_1, device=-1)
+    assert e.value.status == D.E_INVALID
+
+
+def test_host_only_handle_refuses_device_work():
+    c = w.config("c1")
+    h = D.ddlr_setup(c["A"], c["part"], c["p"], c["k"], D.DDLR_1, device=-1)
+    lib = D.load_library()
+    st = lib.ddlr_apply(h.handle, 1, None, c["A"].n, None, c["A"].n, None)
+    assert st == D.E_DEVICE

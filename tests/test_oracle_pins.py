@@ -261,7 +261,9 @@ def test_breakdown_and_input_errors():
     with pytest.raises(OracleError) as e:
         Oracle(B, part, 4)
     assert e.value.status == E_BREAKDOWN
-    Oracle(B, part, 4, factor=FACTOR_ILDL)  # nonzero pivots: accepted
+    ob = Oracle(B, part, 4, factor=FACTOR_ILDL)  # nonzero pivots: accepted
+    ob.lowrank(1, 2, 6, w.lanczos_start(36, 0))
+    assert np.any(ob.diag() < 0) and not ob.spd  # indefinite local factor: never certified SPD
     d2 = A.to_dense()
     d2[0, 1] = -2.0
     M2 = sp.csr_matrix(d2)
@@ -518,6 +520,11 @@ def test_gmres_indefinite():
     part = w.box_partition((24, 20), (2, 2))
     o = Oracle(A, part, 4, factor=FACTOR_ILDL)
     o.lowrank(1, 10, 30, w.lanczos_start(A.n, 1))
+    assert o.spd  # sigma = 0.1 keeps every local pivot positive here
+    ob = Oracle(A.__class__(A.n, A.rowptr, A.col, np.where(rows == A.col, A.val - 0.6, A.val)), part, 4,
+                factor=FACTOR_ILDL)
+    ob.lowrank(1, 10, 30, w.lanczos_start(A.n, 1))
+    assert ob.lanczos_record()[2][0] >= 1 and not ob.spd  # Sec. 5: largest eigenvalue >= 1 -> not SPD
     b, _ = w.rhs_from_solution(A, 0, 2)
     x, info = o.gmres(b, restart=40)
     assert info["status"] == 0
