@@ -105,6 +105,14 @@ struct ddlr_prec {
     int32_t *erp = nullptr, *eci = nullptr, *etrp = nullptr, *etci = nullptr;
     BlockDesc* blk = nullptr;
     int nnarrow = 0, nnarrow_pad = 0;
+    // ring variant of the narrow A0-solve kernel (per-level ELL, LDS window)
+    RingBlock* rblk = nullptr;
+    int32_t *foff = nullptr, *fwid = nullptr, *fcol = nullptr, *boff_ = nullptr, *bwid = nullptr, *bcol = nullptr;
+    double *fval64 = nullptr, *bval64 = nullptr;
+    float *fval32 = nullptr, *bval32 = nullptr;
+    int ring_kw = 0;                          // 4, 8, 16 or 0 (ring kernel unusable)
+    bool ring_ok64 = false, ring_ok32 = false;  // dependency window fits the LDS ring
+    bool lr_plain = false;                      // low-rank kernels without MFMA (comparison only)
     std::vector<std::pair<int, int>> wide;  // rows [a,e) of the wide levels of C (forward order)
     DevFactors<double> f64;
     DevFactors<float> f32;
@@ -121,6 +129,89 @@ struct ddlr_prec {
 namespace {
 
 // ------------------------------------------------------------ device upload
+
+constexpr int kRing64 = 8192, kRing32 = 16384;  // LDS ring rows: 64 KB either way
+
+// Per-level ELL copies of L (forward) and L^T (backward) for the ring kernel,
+// with block-local column indices, and the check that every dependency falls
+// inside the LDS window of the most recent kRing rows.
+void build_ring(ddlr_prec* h, const std::vector<BlockDesc>& bd, const std::vector<int32_t>& lrp,
+                const std::vector<int32_t>& lci, const std::vector<double>& lv, const std::vector<int32_t>& urp,
+                const std::vector<int32_t>& uci, const std::vector<double>& uv) {
+    const HostPlan& P = h->plan;
+    const int nlev = (int)P.lvl_ptr.size() - 1;
+    // block start (device row) of every level
+    std::vector<int32_t> lvl_row0(nlev, 0);
+    for (int32_t b = 0; b <= P.p; ++b)
+        for (int32_t l = P.blk_lvl[b]; l < P.blk_lvl[b + 1]; ++l) lvl_row0[l] = (int32_t)P.boff[b];
+    std::vector<int32_t> foff(nlev), fwid(nlev), boff(nlev), bwid(nlev);
+    std::vector<int32_t> fcol, bcol;
+    std::vector<double> fval, bval;
+    int kw = 0;
+    auto build = [&](const std::vector<int32_t>& rp, const std::vector<int32_t>& ci, const std::vector<double>& v,
+                     std::vector<int32_t>& off, std::vector<int32_t>& wid, std::vector<int32_t>& col,
+                     std::vector<double>& val) {
+        for (int l = 0; l < nlev; ++l) {
+            const int a = P.lvl_ptr[l], e = P.lvl_ptr[l + 1], nr = e - a;
+            int wmax = 0;
+            for (int i = a; i < e; ++i) wmax = std::max(wmax, rp[i + 1] - rp[i]);
+            off[l] = (int32_t)col.size();
+            wid[l] = wmax;
+            col.resize(col.size() + (size_t)wmax * nr, -1);
+            val.resize(val.size() + (size_t)wmax * nr, 0.0);
+            for (int i = a; i < e; ++i)
+                for (int t = rp[i], j = 0; t < rp[i + 1]; ++t, ++j) {
+                    col[off[l] + (size_t)j * nr + (i - a)] = ci[t] - lvl_row0[l];
+                    val[off[l] + (size_t)j * nr + (i - a)] = v[t];
+                }
+        }
+    };
+    build(lrp, lci, lv, foff, fwid, fcol, fval);
+    build(urp, uci, uv, boff, bwid, bcol, bval);
+    bool ok64 = true, ok32 = true;
+    for (const BlockDesc& b : bd) {
+        for (int l = b.lvl0; l < b.lvl1; ++l) {
+            kw = std::max({kw, fwid[l], bwid[l]});
+            const int row0 = lvl_row0[l];
+            const int a = P.lvl_ptr[l] - row0, e = P.lvl_ptr[l + 1] - row0;
+            for (int i = a; i < e; ++i) {
+                for (int t = lrp[row0 + i]; t < lrp[row0 + i + 1]; ++t) {
+                    const int c = lci[t] - row0;
+                    ok64 = ok64 && c >= e - kRing64;
+                    ok32 = ok32 && c >= e - kRing32;
+                }
+                for (int t = urp[row0 + i]; t < urp[row0 + i + 1]; ++t) {
+                    const int c = uci[t] - row0;
+                    ok64 = ok64 && c < a + kRing64;
+                    ok32 = ok32 && c < a + kRing32;
+                }
+            }
+        }
+    }
+    h->ring_kw = kw <= 4 ? 4 : kw <= 8 ? 8 : kw <= 16 ? 16 : 0;
+    if (const char* env = std::getenv("DDLR_TRSV_PLAIN"))  // "1": always the plain per-level kernel
+        if (env[0] == '1') h->ring_kw = 0;
+    h->ring_ok64 = ok64 && h->ring_kw > 0;
+    h->ring_ok32 = ok32 && h->ring_kw > 0;
+    if (!h->ring_ok64 && !h->ring_ok32) return;
+    std::vector<RingBlock> rb;
+    for (const BlockDesc& b : bd) rb.push_back({b.lvl0, b.lvl1, lvl_row0[b.lvl0], 0});
+    DMem& M = h->mem;
+    h->rblk = M.upload(rb);
+    h->foff = M.upload(foff);
+    h->fwid = M.upload(fwid);
+    h->fcol = M.upload(fcol);
+    h->boff_ = M.upload(boff);
+    h->bwid = M.upload(bwid);
+    h->bcol = M.upload(bcol);
+    h->fval64 = M.upload(fval);
+    h->bval64 = M.upload(bval);
+    if (h->precision != DDLR_FP64) {
+        std::vector<float> f(fval.begin(), fval.end()), g(bval.begin(), bval.end());
+        h->fval32 = M.upload(f);
+        h->bval32 = M.upload(g);
+    }
+}
 
 void upload_structures(ddlr_prec* h) {
     HostPlan& P = h->plan;
@@ -273,11 +364,12 @@ void upload_structures(ddlr_prec* h) {
     h->nnarrow = (int)bd.size();
     h->nnarrow_pad = (h->nnarrow + 7) / 8 * 8;
     h->blk = M.upload(bd);
+    build_ring(h, bd, lrp, lci, lv, urp, uci, uv);
 }
 
 // ------------------------------------------------------------ workspace
 
-constexpr int kLrBlocks = 256;  // grid of the low-rank reduction
+constexpr int kLrBlocks = 1024;  // grid of the low-rank reduction
 
 template <typename T> T* wsalloc(Workspace& W, size_t count) { return W.mem.alloc<T>(count); }
 
@@ -354,11 +446,49 @@ template <typename T> const DevFactors<T>& factors(const ddlr_prec* h);
 template <> const DevFactors<double>& factors<double>(const ddlr_prec* h) { return h->f64; }
 template <> const DevFactors<float>& factors<float>(const ddlr_prec* h) { return h->f32; }
 
+template <typename T> bool ring_ready(const ddlr_prec* h);
+template <> bool ring_ready<double>(const ddlr_prec* h) { return h->ring_ok64; }
+template <> bool ring_ready<float>(const ddlr_prec* h) { return h->ring_ok32 && h->fval32; }
+
+template <typename T, int KW, int RING>
+void launch_ring_kw(ddlr_prec* h, const T* fval, const T* bval, const T* dinv, int nrhs, const T* x, int64_t ldx,
+                    T* z, int64_t ldz, hipStream_t st, const int* done) {
+    hipLaunchKernelGGL((k_trsv_ring<T, KW, RING>), dim3(h->nnarrow_pad * nrhs), dim3(kRingThreads), 0, st, h->rblk,
+                       h->nnarrow, h->nnarrow_pad, nrhs, h->lvl_ptr, h->foff, h->fwid, h->fcol, fval, h->boff_,
+                       h->bwid, h->bcol, bval, dinv, x, ldx, z, ldz, done);
+    LAUNCHCHK();
+}
+
+template <typename T>
+void launch_ring(ddlr_prec* h, const DevFactors<T>& F, int nrhs, const T* x, int64_t ldx, T* z, int64_t ldz,
+                 hipStream_t st, const int* done);
+template <>
+void launch_ring<double>(ddlr_prec* h, const DevFactors<double>& F, int nrhs, const double* x, int64_t ldx, double* z,
+                         int64_t ldz, hipStream_t st, const int* done) {
+    switch (h->ring_kw) {
+    case 4: launch_ring_kw<double, 4, kRing64>(h, h->fval64, h->bval64, F.dinv, nrhs, x, ldx, z, ldz, st, done); break;
+    case 8: launch_ring_kw<double, 8, kRing64>(h, h->fval64, h->bval64, F.dinv, nrhs, x, ldx, z, ldz, st, done); break;
+    default: launch_ring_kw<double, 16, kRing64>(h, h->fval64, h->bval64, F.dinv, nrhs, x, ldx, z, ldz, st, done);
+    }
+}
+template <>
+void launch_ring<float>(ddlr_prec* h, const DevFactors<float>& F, int nrhs, const float* x, int64_t ldx, float* z,
+                        int64_t ldz, hipStream_t st, const int* done) {
+    switch (h->ring_kw) {
+    case 4: launch_ring_kw<float, 4, kRing32>(h, h->fval32, h->bval32, F.dinv, nrhs, x, ldx, z, ldz, st, done); break;
+    case 8: launch_ring_kw<float, 8, kRing32>(h, h->fval32, h->bval32, F.dinv, nrhs, x, ldx, z, ldz, st, done); break;
+    default: launch_ring_kw<float, 16, kRing32>(h, h->fval32, h->bval32, F.dinv, nrhs, x, ldx, z, ldz, st, done);
+    }
+}
+
 // z = A0^{-1} x, device order, columns of type T (x may equal z)
 template <typename T>
 void a0_solve_dev(ddlr_prec* h, const DevFactors<T>& F, int nrhs, const T* x, int64_t ldx, T* z, int64_t ldz,
                   hipStream_t st, const int* done) {
-    if (h->nnarrow > 0) {
+    if (h->nnarrow > 0 && ring_ready<T>(h)) {
+        ProfScope ps(h, 0, st);
+        launch_ring<T>(h, F, nrhs, x, ldx, z, ldz, st, done);
+    } else if (h->nnarrow > 0) {
         ProfScope ps(h, 0, st);
         hipLaunchKernelGGL(k_trsv_narrow<T>, dim3(h->nnarrow_pad * nrhs), dim3(256), 0, st, h->blk, h->nnarrow,
                            h->nnarrow_pad, nrhs, h->lvl_ptr, h->lrp, h->lci, F.lv, h->urp, h->uci, F.uv, F.dinv, x,
@@ -389,11 +519,31 @@ void lr_coef(ddlr_prec* h, const T* U, int64_t rows, int nrhs, const T* y, int64
     Workspace& W = h->ws;
     const int k = h->k;
     ProfScope ps(h, 3, st);
-    hipLaunchKernelGGL(k_lr_reduce<T>, dim3(kLrBlocks), dim3(256), 0, st, rows, k, nrhs, U, y, ldy, W.part, done);
+    if (h->lr_plain)
+        hipLaunchKernelGGL(k_lr_reduce<T>, dim3(kLrBlocks), dim3(256), 0, st, rows, k, nrhs, U, y, ldy, W.part, done);
+    else
+        hipLaunchKernelGGL(k_lr_reduce_mfma<T>, dim3(kLrBlocks), dim3(256), 0, st, rows, k, nrhs, U, y, ldy, W.part,
+                           done);
     LAUNCHCHK();
     hipLaunchKernelGGL(k_reduce_cols, dim3(nrhs * k), dim3(256), 0, st, kLrBlocks, nrhs * k, W.part, W.lrsum, done);
     LAUNCHCHK();
     hipLaunchKernelGGL(k_lr_coef, dim3(1), dim3(256), 0, st, k, nrhs, W.lrsum, mode, h->dvec, h->Hk, W.coef, done);
+    LAUNCHCHK();
+}
+
+// out = beta in + U coef
+template <typename T>
+void lr_expand(ddlr_prec* h, const T* U, int64_t rows, int nrhs, double beta, const T* in, int64_t ldin, T* out,
+               int64_t ldout, hipStream_t st, const int* done) {
+    ProfScope ps(h, 3, st);
+    if (h->lr_plain) {
+        hipLaunchKernelGGL(k_lr_expand<T>, dim3(grid_for(rows)), dim3(256), 0, st, rows, h->k, nrhs, U, h->ws.coef,
+                           beta, in, ldin, out, ldout, done);
+    } else {
+        const int64_t tiles = (rows + 15) / 16;
+        hipLaunchKernelGGL(k_lr_expand_mfma<T>, dim3(grid_for(tiles, 4)), dim3(256), 0, st, rows, h->k, nrhs, U,
+                           h->ws.coef, beta, in, ldin, out, ldout, done);
+    }
     LAUNCHCHK();
 }
 
@@ -416,9 +566,7 @@ void apply_dev_T(ddlr_prec* h, int nrhs, const T* in, int64_t ldin, T* out, int6
                            a1, n, (const T*)nullptr, 0, ys, s, done);  // step 2: y = E^T z
         LAUNCHCHK();
         lr_coef<T>(h, F.U, s, nrhs, ys, s, 1, st, done);  // step 3: w = G_{k,theta}^{-1} y (eq. gkt)
-        hipLaunchKernelGGL(k_lr_expand<T>, dim3(grid_for(s)), dim3(256), 0, st, s, h->k, nrhs, F.U, h->ws.coef, h->c0,
-                           ys, s, wsv, s, done);
-        LAUNCHCHK();
+        lr_expand<T>(h, F.U, s, nrhs, h->c0, ys, s, wsv, s, st, done);
         hipLaunchKernelGGL(k_csr_mv<T>, dim3(grid_for(n * nrhs)), dim3(256), 0, st, n, nrhs, h->erp, h->eci, F.ev,
                            wsv, s, in, ldin, a2, n, done);  // step 4: v = E w, fused x + v
         LAUNCHCHK();
@@ -426,9 +574,7 @@ void apply_dev_T(ddlr_prec* h, int nrhs, const T* in, int64_t ldin, T* out, int6
     } else if (h->variant == DDLR_2) {
         a0_solve_dev<T>(h, F, nrhs, in, ldin, out, ldout, st, done);
         lr_coef<T>(h, F.U, n, nrhs, in, ldin, 2, st, done);
-        hipLaunchKernelGGL(k_lr_expand<T>, dim3(grid_for(n)), dim3(256), 0, st, n, h->k, nrhs, F.U, h->ws.coef, 1.0,
-                           out, ldout, out, ldout, done);
-        LAUNCHCHK();
+        lr_expand<T>(h, F.U, n, nrhs, 1.0, out, ldout, out, ldout, st, done);
     } else {
         a0_solve_dev<T>(h, F, nrhs, in, ldin, out, ldout, st, done);
     }
@@ -767,6 +913,7 @@ ddlr_status ddlr_setup(const ddlr_csr* A, const int32_t* part, int32_t p, int32_
             throw SetupError{DDLR_E_INVALID, "bad factor/corder option"};
         h->precision = opt.precision;
         h->variant = variant;
+        if (const char* env = std::getenv("DDLR_LR_PLAIN")) h->lr_plain = env[0] == '1';
         build_plan(h->plan, A->n, A->row_ptr, A->col_idx, A->val, part, p, opt.alpha, opt.factor, opt.corder);
         for (double d : h->plan.D) h->pivots_positive = h->pivots_positive && d > 0.0;
         h->spd = variant == 0 ? (int)h->pivots_positive : 0;

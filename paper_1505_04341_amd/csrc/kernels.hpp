@@ -121,6 +121,135 @@ __global__ __launch_bounds__(256) void k_trsv_narrow(
     }
 }
 
+// ------------------------------------- A0 solve: narrow blocks, LDS ring
+//
+// Same schedule as k_trsv_narrow, restructured for latency:
+//  * each row's dependencies are stored per level in ELL form (width = the
+//    level's longest row, entries column-major, column = row index local to
+//    the block, -1 = padding), so one level's data is one coalesced segment;
+//  * the next level's entries, right-hand side values and D^{-1} are loaded
+//    into registers before the current level is computed, so their HBM
+//    latency overlaps the computation and the barrier;
+//  * results go to global memory and to a ring of the most recent kRing rows
+//    in LDS; the host has checked that every dependency of every level lies
+//    inside that window (forward: c >= e - kRing; backward: c < a + kRing),
+//    so all gathers hit LDS and levels are separated by LDS-only barriers.
+// 512 threads, up to 2 rows per thread per level in registers; longer levels
+// finish their tail rows without prefetch.
+struct RingBlock {
+    int32_t lvl0, lvl1, row0, pad;
+};
+
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+constexpr int kRingThreads = 512;
+
+template <typename T, int KW> struct LevelRegs {
+    int a, e, w, off;
+    int c[2][KW];
+    T v[2][KW];
+    T xv[2];
+    T dv[2];
+};
+
+template <typename T, int KW, bool kBwd>
+__device__ __forceinline__ void ring_load(LevelRegs<T, KW>& R, int l, int row0, const int32_t* __restrict__ lvl_ptr,
+                                          const int32_t* __restrict__ eoff, const int32_t* __restrict__ ewid,
+                                          const int32_t* __restrict__ ecol, const T* __restrict__ eval,
+                                          const T* __restrict__ dinv, const T* src) {
+    R.a = lvl_ptr[l] - row0;
+    R.e = lvl_ptr[l + 1] - row0;
+    R.w = ewid[l];
+    R.off = eoff[l];
+    const int nr = R.e - R.a;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int i = R.a + (int)threadIdx.x + q * kRingThreads;
+        if (i < R.e) {
+            const int base = R.off + (i - R.a);
+#pragma unroll
+            for (int j = 0; j < KW; ++j)
+                if (j < R.w) {
+                    R.c[q][j] = ecol[base + j * nr];
+                    R.v[q][j] = eval[base + j * nr];
+                }
+            R.xv[q] = src[i];
+            if (kBwd) R.dv[q] = dinv[row0 + i];
+        }
+    }
+}
+
+template <typename T, int KW, int kRing, bool kBwd>
+__device__ __forceinline__ void ring_compute(const LevelRegs<T, KW>& R, int row0, T* ring,
+                                             const int32_t* __restrict__ ecol, const T* __restrict__ eval,
+                                             const T* __restrict__ dinv, const T* src, T* dst) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int i = R.a + (int)threadIdx.x + q * kRingThreads;
+        if (i < R.e) {
+            T s = kBwd ? R.xv[q] * R.dv[q] : R.xv[q];
+#pragma unroll
+            for (int j = 0; j < KW; ++j)
+                if (j < R.w) {
+                    const int c = R.c[q][j];
+                    if (c >= 0) s -= R.v[q][j] * ring[c & (kRing - 1)];
+                }
+            ring[i & (kRing - 1)] = s;
+            dst[i] = s;
+        }
+    }
+    // rows beyond 2 * kRingThreads: no prefetch
+    const int nr = R.e - R.a;
+    for (int i = R.a + 2 * kRingThreads + (int)threadIdx.x; i < R.e; i += kRingThreads) {
+        const int base = R.off + (i - R.a);
+        T s = kBwd ? src[i] * dinv[row0 + i] : src[i];
+        for (int j = 0; j < R.w; ++j) {
+            const int c = ecol[base + j * nr];
+            if (c >= 0) s -= eval[base + j * nr] * ring[c & (kRing - 1)];
+        }
+        ring[i & (kRing - 1)] = s;
+        dst[i] = s;
+    }
+}
+
+template <typename T, int KW, int kRing>
+__global__ __launch_bounds__(kRingThreads) void k_trsv_ring(
+    const RingBlock* __restrict__ blk, int nblk, int nblk_pad, int nrhs, const int32_t* __restrict__ lvl_ptr,
+    const int32_t* __restrict__ foff, const int32_t* __restrict__ fwid, const int32_t* __restrict__ fcol,
+    const T* __restrict__ fval, const int32_t* __restrict__ boff, const int32_t* __restrict__ bwid,
+    const int32_t* __restrict__ bcol, const T* __restrict__ bval, const T* __restrict__ dinv, const T* x, int64_t ldx,
+    T* z, int64_t ldz, const int* __restrict__ done) {
+    __shared__ T ring[kRing];
+    if (done && *done) return;
+    const int b = blockIdx.x % nblk_pad, r = blockIdx.x / nblk_pad;
+    if (b >= nblk || r >= nrhs) return;
+    const RingBlock d = blk[b];
+    const T* xr = x + r * ldx + d.row0;
+    T* zr = z + r * ldz + d.row0;
+    LevelRegs<T, KW> cur, nxt;
+    // forward sweep: y = x - L y
+    ring_load<T, KW, false>(cur, d.lvl0, d.row0, lvl_ptr, foff, fwid, fcol, fval, dinv, xr);
+    for (int l = d.lvl0; l < d.lvl1; ++l) {
+        if (l + 1 < d.lvl1) ring_load<T, KW, false>(nxt, l + 1, d.row0, lvl_ptr, foff, fwid, fcol, fval, dinv, xr);
+        ring_compute<T, KW, kRing, false>(cur, d.row0, ring, fcol, fval, dinv, xr, zr);
+        lds_barrier();
+        cur = nxt;
+    }
+    __syncthreads();  // global fence: the backward sweep reads y_i from memory
+    // backward sweep: z = D^{-1} y - L^T z
+    ring_load<T, KW, true>(cur, d.lvl1 - 1, d.row0, lvl_ptr, boff, bwid, bcol, bval, dinv, zr);
+    for (int l = d.lvl1 - 1; l >= d.lvl0; --l) {
+        if (l - 1 >= d.lvl0) ring_load<T, KW, true>(nxt, l - 1, d.row0, lvl_ptr, boff, bwid, bcol, bval, dinv, zr);
+        ring_compute<T, KW, kRing, true>(cur, d.row0, ring, bcol, bval, dinv, zr, zr);
+        lds_barrier();
+        cur = nxt;
+    }
+}
+
 // ------------------------------------------------ A0 solve: one wide level
 //
 // For the interface block C_alpha in multicolour order the schedule has a few
@@ -303,6 +432,117 @@ __global__ __launch_bounds__(256) void k_lr_expand(int64_t rows, int k, int nrhs
 #pragma unroll
         for (int r = 0; r < kMaxRhs; ++r)
             if (r < nrhs) out[i + r * ldout] = (T)acc[r];
+    }
+}
+
+// ------------------------------------------- low-rank correction on MFMA
+//
+// Tall-skinny products with the matrix cores, 16x16x4 MFMA (FP64 for the FP64
+// path, FP32 for the mixed path).  Operand layout of the 16x16x4 MFMA
+// (wave64): A (16x4) lane l holds A[l%16][l/16]; B (4x16) lane l holds
+// B[l/16][l%16]; C (16x16) lane l, register v holds C[row(l,v)][l%16] with
+// row = 4*(l/16)+v for FP32 and row = l/16 + 4*v for FP64 (measured on gfx950).
+typedef float mfma_f32x4 __attribute__((ext_vector_type(4)));
+typedef double mfma_f64x4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct MfmaAcc;
+template <> struct MfmaAcc<float> {
+    typedef mfma_f32x4 type;
+    static __device__ __forceinline__ type step(float a, float b, type c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+template <> struct MfmaAcc<double> {
+    typedef mfma_f64x4 type;
+    static __device__ __forceinline__ type step(double a, double b, type c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lane, int v) { return (lane >> 4) + 4 * v; }
+};
+
+// Reduce: part[block][r][j] = sum over the block's rows of U[row][j] y_r[row].
+// C = U^T Y: M = k (tiles of 16), N = nrhs (<= 16), K = rows (steps of 4).
+// Each wave owns a contiguous run of rows; k <= 128 -> up to 8 accumulator tiles.
+template <typename T>
+__global__ __launch_bounds__(256) void k_lr_reduce_mfma(int64_t rows, int k, int nrhs, const T* __restrict__ U,
+                                                        const T* __restrict__ y, int64_t ldy,
+                                                        double* __restrict__ part, const int* __restrict__ done) {
+    typedef typename MfmaAcc<T>::type acc_t;
+    __shared__ double stage[4][64];
+    if (done && *done) return;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int nwaves = gridDim.x * 4;
+    const int64_t gw = (int64_t)blockIdx.x * 4 + wv;
+    const int64_t per = ((rows + nwaves - 1) / nwaves + 3) & ~(int64_t)3;
+    const int64_t r0 = gw * per, r1 = r0 + per < rows ? r0 + per : rows;
+    const int ntile = (k + 15) >> 4;
+    acc_t acc[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) acc[t] = acc_t{0, 0, 0, 0};
+    const int col = lane & 15, kk = lane >> 4;
+    for (int64_t i0 = r0; i0 < r1; i0 += 4) {
+        const int64_t i = i0 + kk;
+        const bool ok = i < r1;
+        const T bval = (ok && col < nrhs) ? y[i + col * ldy] : T(0);
+#pragma unroll
+        for (int t = 0; t < 8; ++t)
+            if (t < ntile) {
+                const int j = t * 16 + col;
+                const T aval = (ok && j < k) ? U[i * k + j] : T(0);
+                acc[t] = MfmaAcc<T>::step(aval, bval, acc[t]);
+            }
+    }
+    // acc[t] holds C[j = 16t + row(lane, v)][rhs = lane%16]; fold the 4 waves through LDS
+    for (int t = 0; t < ntile; ++t) {
+        for (int v = 0; v < 4; ++v) {
+            stage[wv][lane] = (double)acc[t][v];
+            __syncthreads();
+            const int j = t * 16 + MfmaAcc<T>::row(lane, v), rr = lane & 15;
+            if (wv == 0 && j < k && rr < nrhs)
+                part[((int64_t)blockIdx.x * nrhs + rr) * k + j] =
+                    (stage[0][lane] + stage[1][lane]) + (stage[2][lane] + stage[3][lane]);
+            __syncthreads();
+        }
+    }
+}
+
+// Expand: out[row][r] = beta in[row][r] + sum_j U[row][j] coef[r][j].
+// M = 16 rows, N = nrhs (<= 16), K = k (steps of 4); one 16-row tile per wave-step.
+template <typename T>
+__global__ __launch_bounds__(256) void k_lr_expand_mfma(int64_t rows, int k, int nrhs, const T* __restrict__ U,
+                                                        const double* __restrict__ coef, double beta, const T* in,
+                                                        int64_t ldin, T* out, int64_t ldout,
+                                                        const int* __restrict__ done) {
+    typedef typename MfmaAcc<T>::type acc_t;
+    __shared__ T cf[128 * 16];  // cf[j*16 + r]
+    if (done && *done) return;
+    for (int q = threadIdx.x; q < 128 * 16; q += blockDim.x) {
+        const int j = q >> 4, rr = q & 15;
+        cf[q] = (j < k && rr < nrhs) ? (T)coef[rr * k + j] : T(0);
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int row_in = lane & 15, kk = lane >> 4;
+    const int64_t ntiles = (rows + 15) >> 4;
+    for (int64_t tile = (int64_t)blockIdx.x * 4 + wv; tile < ntiles; tile += (int64_t)gridDim.x * 4) {
+        const int64_t i = tile * 16 + row_in;
+        acc_t acc = acc_t{0, 0, 0, 0};
+        for (int j0 = 0; j0 < k; j0 += 4) {
+            const int j = j0 + kk;
+            const T aval = (i < rows && j < k) ? U[i * k + j] : T(0);
+            const T bval = cf[j * 16 + (lane & 15)];
+            acc = MfmaAcc<T>::step(aval, bval, acc);
+        }
+        const int rr = lane & 15;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int64_t row = tile * 16 + MfmaAcc<T>::row(lane, v);
+            if (row < rows && rr < nrhs) {
+                const double o = beta * (double)in[row + rr * ldin] + (double)acc[v];
+                out[row + rr * ldout] = (T)o;
+            }
+        }
     }
 }
 

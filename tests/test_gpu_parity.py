@@ -43,14 +43,18 @@ def rel(a, b):
     return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
 
 
-def setup_pair(cfg, variant=1, wide=None, **kw):
+def setup_pair(cfg, variant=1, wide=None, env=None, **kw):
+    """Builds the GPU preconditioner (kernel choices forced through env) and the oracle."""
+    env = dict(env or {})
     if wide is not None:
-        os.environ["DDLR_C_WIDE"] = "1" if wide else "0"
+        env["DDLR_C_WIDE"] = "1" if wide else "0"
+    os.environ.update(env)
     try:
         h = D.ddlr_setup(cfg["A"], cfg["part"], cfg["p"], cfg["k"], variant, lanczos_steps=cfg.get("m", 0),
                          lanczos_start=w.lanczos_start(cfg["A"].n, 0), **kw)
     finally:
-        os.environ.pop("DDLR_C_WIDE", None)
+        for key in env:
+            os.environ.pop(key, None)
     o = Oracle(cfg["A"], cfg["part"], cfg["p"], alpha=kw.get("alpha", 1.0), corder=kw.get("corder", 0),
                factor=FACTOR_ILDL if kw.get("factor", 0) == 1 else 0)
     return h, o
@@ -61,16 +65,24 @@ def irregular():
     return dict(A=A, part=w.box_partition((37, 29), (3, 2)), p=6, k=6, m=20)
 
 
+def big3d():
+    """Blocks of about 10,000 rows: larger than the FP64 LDS ring (8,192 rows),
+    so the ring wraps within a block."""
+    A = w.laplacian_3d(48, 48, 40)
+    return dict(A=A, part=w.box_partition((48, 48, 40), (2, 2, 2)), p=8, k=8, m=20)
+
+
 CASES = {"c1": lambda: w.config("c1"), "small2d": lambda: w.config("small2d"),
-         "small3d": lambda: w.config("small3d"), "irregular": irregular}
+         "small3d": lambda: w.config("small3d"), "irregular": irregular, "big3d": big3d}
 
 
-@pytest.mark.parametrize("name", ["c1", "small3d", "irregular"])
+@pytest.mark.parametrize("name", ["c1", "small3d", "irregular", "big3d"])
 @pytest.mark.parametrize("wide", [False, True])
-def test_a0_solve_and_spmv(name, wide):
+@pytest.mark.parametrize("kernel", ["ring", "plain"])
+def test_a0_solve_and_spmv(name, wide, kernel):
     cfg = CASES[name]()
-    say("a0_solve", name, "wide", wide)
-    h, o = setup_pair(cfg, variant=D.VARIANT_A0, wide=wide)
+    say("a0_solve", name, "wide", wide, kernel)
+    h, o = setup_pair(cfg, variant=D.VARIANT_A0, wide=wide, env={"DDLR_TRSV_PLAIN": "1" if kernel == "plain" else "0"})
     n = cfg["A"].n
     rng = np.random.default_rng(7)
     for nrhs in (1, 3, 17):  # 17: two launches of up to 16 columns, ragged tail
@@ -87,10 +99,11 @@ def test_a0_solve_and_spmv(name, wide):
 
 @pytest.mark.parametrize("name", ["c1", "small2d", "irregular"])
 @pytest.mark.parametrize("variant", [1, 2])
-def test_apply_with_imported_lowrank(name, variant):
+@pytest.mark.parametrize("lr", ["mfma", "plain"])
+def test_apply_with_imported_lowrank(name, variant, lr):
     cfg = CASES[name]()
-    say("apply imported", name, variant)
-    h, o = setup_pair(cfg, variant=variant)
+    say("apply imported", name, variant, lr)
+    h, o = setup_pair(cfg, variant=variant, env={"DDLR_LR_PLAIN": "1" if lr == "plain" else "0"})
     o.lowrank(variant, cfg["k"], cfg["m"], w.lanczos_start(cfg["A"].n, 0))
     lr = o.get_lowrank()
     if variant == 1:
@@ -166,6 +179,25 @@ def test_pcg_end_to_end_own_setup(name, variant):
         assert abs(i["iters"] - io) <= 1
         assert i["relres_true"] <= 1.05e-6
     assert rel(to_host(x), xo) <= 1e-5
+
+
+@pytest.mark.parametrize("variant", [1, 2])
+@pytest.mark.parametrize("lr", ["mfma", "plain"])
+def test_fp32_apply_matches_oracle(variant, lr):
+    """FP32 preconditioner (factors, E, U_k in single precision): same operator
+    as the FP64 oracle up to single-precision rounding."""
+    cfg = irregular()
+    say("fp32 apply", variant, lr)
+    h, o = setup_pair(cfg, variant=variant, precision=D.FP32, env={"DDLR_LR_PLAIN": "1" if lr == "plain" else "0"})
+    o.lowrank(variant, cfg["k"], cfg["m"], w.lanczos_start(cfg["A"].n, 0))
+    lr_ = o.get_lowrank()
+    D.ddlr_set_lowrank(h, variant, *lr_)
+    n = cfg["A"].n
+    for nrhs in (1, 5, 16):
+        x = np.random.default_rng(nrhs).standard_normal((n, nrhs))
+        y = torch.empty((nrhs, n), dtype=torch.float64, device=DEV)
+        D.ddlr_apply(h, to_dev(x), y)
+        assert rel(to_host(y), o.apply(x)) <= 1e-4
 
 
 @pytest.mark.parametrize("prec", [D.FP32])
