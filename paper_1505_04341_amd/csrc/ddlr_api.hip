@@ -107,12 +107,17 @@ struct ddlr_prec {
     int nnarrow = 0, nnarrow_pad = 0;
     // ring variant of the narrow A0-solve kernel (per-level ELL, LDS window)
     RingBlock* rblk = nullptr;
-    int32_t *foff = nullptr, *fwid = nullptr, *fcol = nullptr, *boff_ = nullptr, *bwid = nullptr, *bcol = nullptr;
+    int32_t *foff = nullptr, *fcol = nullptr, *boff_ = nullptr, *bcol = nullptr;
     double *fval64 = nullptr, *bval64 = nullptr;
     float *fval32 = nullptr, *bval32 = nullptr;
-    int ring_kw = 0;                          // 4, 8, 16 or 0 (ring kernel unusable)
+    int ring_kw = 0;                          // 2, 3, 4, 8, 16 or 0 (ring kernel unusable)
     bool ring_ok64 = false, ring_ok32 = false;  // dependency window fits the LDS ring
     bool lr_plain = false;                      // low-rank kernels without MFMA (comparison only)
+    // the interface block's level kernels run on a side stream, overlapping the
+    // B-block kernel (fork/join by events on the caller's stream)
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    bool overlap = true;
     std::vector<std::pair<int, int>> wide;  // rows [a,e) of the wide levels of C (forward order)
     DevFactors<double> f64;
     DevFactors<float> f32;
@@ -133,48 +138,27 @@ namespace {
 constexpr int kRing64 = 8192, kRing32 = 16384;  // LDS ring rows: 64 KB either way
 
 // Per-level ELL copies of L (forward) and L^T (backward) for the ring kernel,
-// with block-local column indices, and the check that every dependency falls
-// inside the LDS window of the most recent kRing rows.
+// fixed width KW for every level, block-local column indices, and the check
+// that every dependency falls inside the LDS window of the most recent kRing
+// rows.
 void build_ring(ddlr_prec* h, const std::vector<BlockDesc>& bd, const std::vector<int32_t>& lrp,
                 const std::vector<int32_t>& lci, const std::vector<double>& lv, const std::vector<int32_t>& urp,
                 const std::vector<int32_t>& uci, const std::vector<double>& uv) {
     const HostPlan& P = h->plan;
     const int nlev = (int)P.lvl_ptr.size() - 1;
-    // block start (device row) of every level
     std::vector<int32_t> lvl_row0(nlev, 0);
     for (int32_t b = 0; b <= P.p; ++b)
         for (int32_t l = P.blk_lvl[b]; l < P.blk_lvl[b + 1]; ++l) lvl_row0[l] = (int32_t)P.boff[b];
-    std::vector<int32_t> foff(nlev), fwid(nlev), boff(nlev), bwid(nlev);
-    std::vector<int32_t> fcol, bcol;
-    std::vector<double> fval, bval;
+    // width and window checks over the narrow blocks
     int kw = 0;
-    auto build = [&](const std::vector<int32_t>& rp, const std::vector<int32_t>& ci, const std::vector<double>& v,
-                     std::vector<int32_t>& off, std::vector<int32_t>& wid, std::vector<int32_t>& col,
-                     std::vector<double>& val) {
-        for (int l = 0; l < nlev; ++l) {
-            const int a = P.lvl_ptr[l], e = P.lvl_ptr[l + 1], nr = e - a;
-            int wmax = 0;
-            for (int i = a; i < e; ++i) wmax = std::max(wmax, rp[i + 1] - rp[i]);
-            off[l] = (int32_t)col.size();
-            wid[l] = wmax;
-            col.resize(col.size() + (size_t)wmax * nr, -1);
-            val.resize(val.size() + (size_t)wmax * nr, 0.0);
-            for (int i = a; i < e; ++i)
-                for (int t = rp[i], j = 0; t < rp[i + 1]; ++t, ++j) {
-                    col[off[l] + (size_t)j * nr + (i - a)] = ci[t] - lvl_row0[l];
-                    val[off[l] + (size_t)j * nr + (i - a)] = v[t];
-                }
-        }
-    };
-    build(lrp, lci, lv, foff, fwid, fcol, fval);
-    build(urp, uci, uv, boff, bwid, bcol, bval);
     bool ok64 = true, ok32 = true;
     for (const BlockDesc& b : bd) {
+        if (b.lvl1 - b.lvl0 > kRingMaxLevels) ok64 = ok32 = false;
         for (int l = b.lvl0; l < b.lvl1; ++l) {
-            kw = std::max({kw, fwid[l], bwid[l]});
             const int row0 = lvl_row0[l];
             const int a = P.lvl_ptr[l] - row0, e = P.lvl_ptr[l + 1] - row0;
             for (int i = a; i < e; ++i) {
+                kw = std::max({kw, lrp[row0 + i + 1] - lrp[row0 + i], urp[row0 + i + 1] - urp[row0 + i]});
                 for (int t = lrp[row0 + i]; t < lrp[row0 + i + 1]; ++t) {
                     const int c = lci[t] - row0;
                     ok64 = ok64 && c >= e - kRing64;
@@ -188,21 +172,40 @@ void build_ring(ddlr_prec* h, const std::vector<BlockDesc>& bd, const std::vecto
             }
         }
     }
-    h->ring_kw = kw <= 4 ? 4 : kw <= 8 ? 8 : kw <= 16 ? 16 : 0;
+    h->ring_kw = kw <= 2 ? 2 : kw <= 3 ? 3 : kw <= 4 ? 4 : kw <= 8 ? 8 : kw <= 16 ? 16 : 0;
     if (const char* env = std::getenv("DDLR_TRSV_PLAIN"))  // "1": always the plain per-level kernel
         if (env[0] == '1') h->ring_kw = 0;
     h->ring_ok64 = ok64 && h->ring_kw > 0;
     h->ring_ok32 = ok32 && h->ring_kw > 0;
     if (!h->ring_ok64 && !h->ring_ok32) return;
+    const int KW = h->ring_kw;
+    std::vector<int32_t> foff(nlev), boff(nlev), fcol, bcol;
+    std::vector<double> fval, bval;
+    auto build = [&](const std::vector<int32_t>& rp, const std::vector<int32_t>& ci, const std::vector<double>& v,
+                     std::vector<int32_t>& off, std::vector<int32_t>& col, std::vector<double>& val) {
+        for (int l = 0; l < nlev; ++l) {
+            const int a = P.lvl_ptr[l], e = P.lvl_ptr[l + 1], nr = e - a;
+            off[l] = (int32_t)col.size();
+            col.resize(col.size() + (size_t)KW * nr, 0);  // padding: column 0, value 0
+            val.resize(val.size() + (size_t)KW * nr, 0.0);
+            for (int i = a; i < e; ++i) {
+                const int t0 = rp[i], t1 = std::min(rp[i + 1], rp[i] + KW);
+                for (int t = t0, j = 0; t < t1; ++t, ++j) {
+                    col[off[l] + (size_t)j * nr + (i - a)] = ci[t] - lvl_row0[l];
+                    val[off[l] + (size_t)j * nr + (i - a)] = v[t];
+                }
+            }
+        }
+    };
+    build(lrp, lci, lv, foff, fcol, fval);
+    build(urp, uci, uv, boff, bcol, bval);
     std::vector<RingBlock> rb;
     for (const BlockDesc& b : bd) rb.push_back({b.lvl0, b.lvl1, lvl_row0[b.lvl0], 0});
     DMem& M = h->mem;
     h->rblk = M.upload(rb);
     h->foff = M.upload(foff);
-    h->fwid = M.upload(fwid);
     h->fcol = M.upload(fcol);
     h->boff_ = M.upload(boff);
-    h->bwid = M.upload(bwid);
     h->bcol = M.upload(bcol);
     h->fval64 = M.upload(fval);
     h->bval64 = M.upload(bval);
@@ -449,81 +452,107 @@ template <> const DevFactors<float>& factors<float>(const ddlr_prec* h) { return
 template <typename T> bool ring_ready(const ddlr_prec* h);
 template <> bool ring_ready<double>(const ddlr_prec* h) { return h->ring_ok64; }
 template <> bool ring_ready<float>(const ddlr_prec* h) { return h->ring_ok32 && h->fval32; }
+template <typename T> const T* ring_fval(const ddlr_prec* h);
+template <> const double* ring_fval<double>(const ddlr_prec* h) { return h->fval64; }
+template <> const float* ring_fval<float>(const ddlr_prec* h) { return h->fval32; }
+template <typename T> const T* ring_bval(const ddlr_prec* h);
+template <> const double* ring_bval<double>(const ddlr_prec* h) { return h->bval64; }
+template <> const float* ring_bval<float>(const ddlr_prec* h) { return h->bval32; }
+template <typename T> constexpr int ring_rows();
+template <> constexpr int ring_rows<double>() { return kRing64; }
+template <> constexpr int ring_rows<float>() { return kRing32; }
 
-template <typename T, int KW, int RING>
-void launch_ring_kw(ddlr_prec* h, const T* fval, const T* bval, const T* dinv, int nrhs, const T* x, int64_t ldx,
-                    T* z, int64_t ldz, hipStream_t st, const int* done) {
-    hipLaunchKernelGGL((k_trsv_ring<T, KW, RING>), dim3(h->nnarrow_pad * nrhs), dim3(kRingThreads), 0, st, h->rblk,
-                       h->nnarrow, h->nnarrow_pad, nrhs, h->lvl_ptr, h->foff, h->fwid, h->fcol, fval, h->boff_,
-                       h->bwid, h->bcol, bval, dinv, x, ldx, z, ldz, done);
+template <typename T, int KW, typename TIn, typename TOut>
+void launch_ring_kw(ddlr_prec* h, const T* dinv, int nrhs, const TIn* x, int64_t ldx, TOut* z, int64_t ldz,
+                    hipStream_t st, const int* done) {
+    hipLaunchKernelGGL((k_trsv_ring<T, KW, ring_rows<T>(), TIn, TOut>), dim3(h->nnarrow_pad * nrhs),
+                       dim3(kRingThreads), 0, st, h->rblk, h->nnarrow, h->nnarrow_pad, nrhs, h->lvl_ptr, h->foff,
+                       h->fcol, ring_fval<T>(h), h->boff_, h->bcol, ring_bval<T>(h), dinv, x, ldx, z, ldz, done);
     LAUNCHCHK();
 }
 
-template <typename T>
-void launch_ring(ddlr_prec* h, const DevFactors<T>& F, int nrhs, const T* x, int64_t ldx, T* z, int64_t ldz,
-                 hipStream_t st, const int* done);
-template <>
-void launch_ring<double>(ddlr_prec* h, const DevFactors<double>& F, int nrhs, const double* x, int64_t ldx, double* z,
-                         int64_t ldz, hipStream_t st, const int* done) {
+template <typename T, typename TIn, typename TOut>
+void launch_ring(ddlr_prec* h, const T* dinv, int nrhs, const TIn* x, int64_t ldx, TOut* z, int64_t ldz,
+                 hipStream_t st, const int* done) {
     switch (h->ring_kw) {
-    case 4: launch_ring_kw<double, 4, kRing64>(h, h->fval64, h->bval64, F.dinv, nrhs, x, ldx, z, ldz, st, done); break;
-    case 8: launch_ring_kw<double, 8, kRing64>(h, h->fval64, h->bval64, F.dinv, nrhs, x, ldx, z, ldz, st, done); break;
-    default: launch_ring_kw<double, 16, kRing64>(h, h->fval64, h->bval64, F.dinv, nrhs, x, ldx, z, ldz, st, done);
-    }
-}
-template <>
-void launch_ring<float>(ddlr_prec* h, const DevFactors<float>& F, int nrhs, const float* x, int64_t ldx, float* z,
-                        int64_t ldz, hipStream_t st, const int* done) {
-    switch (h->ring_kw) {
-    case 4: launch_ring_kw<float, 4, kRing32>(h, h->fval32, h->bval32, F.dinv, nrhs, x, ldx, z, ldz, st, done); break;
-    case 8: launch_ring_kw<float, 8, kRing32>(h, h->fval32, h->bval32, F.dinv, nrhs, x, ldx, z, ldz, st, done); break;
-    default: launch_ring_kw<float, 16, kRing32>(h, h->fval32, h->bval32, F.dinv, nrhs, x, ldx, z, ldz, st, done);
+    case 2: launch_ring_kw<T, 2, TIn, TOut>(h, dinv, nrhs, x, ldx, z, ldz, st, done); break;
+    case 3: launch_ring_kw<T, 3, TIn, TOut>(h, dinv, nrhs, x, ldx, z, ldz, st, done); break;
+    case 4: launch_ring_kw<T, 4, TIn, TOut>(h, dinv, nrhs, x, ldx, z, ldz, st, done); break;
+    case 8: launch_ring_kw<T, 8, TIn, TOut>(h, dinv, nrhs, x, ldx, z, ldz, st, done); break;
+    default: launch_ring_kw<T, 16, TIn, TOut>(h, dinv, nrhs, x, ldx, z, ldz, st, done);
     }
 }
 
-// z = A0^{-1} x, device order, columns of type T (x may equal z)
-template <typename T>
-void a0_solve_dev(ddlr_prec* h, const DevFactors<T>& F, int nrhs, const T* x, int64_t ldx, T* z, int64_t ldz,
-                  hipStream_t st, const int* done) {
-    if (h->nnarrow > 0 && ring_ready<T>(h)) {
-        ProfScope ps(h, 0, st);
-        launch_ring<T>(h, F, nrhs, x, ldx, z, ldz, st, done);
-    } else if (h->nnarrow > 0) {
-        ProfScope ps(h, 0, st);
-        hipLaunchKernelGGL(k_trsv_narrow<T>, dim3(h->nnarrow_pad * nrhs), dim3(256), 0, st, h->blk, h->nnarrow,
-                           h->nnarrow_pad, nrhs, h->lvl_ptr, h->lrp, h->lci, F.lv, h->urp, h->uci, F.uv, F.dinv, x,
-                           ldx, z, ldz, done);
-        LAUNCHCHK();
-    }
+// Interface-block levels (multicolour order): forward levels, the last one
+// fused with the diagonal scaling, then backward levels.
+template <typename T, typename TIn, typename TOut>
+void wide_levels(ddlr_prec* h, const DevFactors<T>& F, int nrhs, const TIn* x, int64_t ldx, TOut* z, int64_t ldz,
+                 hipStream_t st, const int* done) {
     ProfScope ps(h, 1, st);
-    for (size_t l = 0; l < h->wide.size(); ++l) {
+    const int nl = (int)h->wide.size();
+    for (int l = 0; l < nl; ++l) {
         const int a = h->wide[l].first, e = h->wide[l].second;
-        hipLaunchKernelGGL((k_trsv_level<T, false>), dim3(grid_for((int64_t)(e - a) * nrhs, 256, 1 << 30)), dim3(256),
-                           0, st, a, e, nrhs, h->lrp, h->lci, F.lv, F.dinv, x, ldx, z, ldz, done);
+        const dim3 g(grid_for((int64_t)(e - a) * nrhs, 256, 1 << 30));
+        if (l + 1 < nl)
+            hipLaunchKernelGGL((k_trsv_level<T, 0, TIn, TOut>), g, dim3(256), 0, st, a, e, nrhs, h->lrp, h->lci, F.lv,
+                               F.dinv, x, ldx, z, ldz, done);
+        else
+            hipLaunchKernelGGL((k_trsv_level<T, 2, TIn, TOut>), g, dim3(256), 0, st, a, e, nrhs, h->lrp, h->lci, F.lv,
+                               F.dinv, x, ldx, z, ldz, done);
         LAUNCHCHK();
     }
-    for (size_t l = h->wide.size(); l-- > 0;) {
+    for (int l = nl - 2; l >= 0; --l) {
         const int a = h->wide[l].first, e = h->wide[l].second;
-        hipLaunchKernelGGL((k_trsv_level<T, true>), dim3(grid_for((int64_t)(e - a) * nrhs, 256, 1 << 30)), dim3(256),
-                           0, st, a, e, nrhs, h->urp, h->uci, F.uv, F.dinv, x, ldx, z, ldz, done);
+        hipLaunchKernelGGL((k_trsv_level<T, 1, TIn, TOut>), dim3(grid_for((int64_t)(e - a) * nrhs, 256, 1 << 30)),
+                           dim3(256), 0, st, a, e, nrhs, h->urp, h->uci, F.uv, F.dinv, x, ldx, z, ldz, done);
         LAUNCHCHK();
+    }
+}
+
+// z = A0^{-1} x, device order (x may equal z when TIn == TOut)
+template <typename T, typename TIn, typename TOut>
+void a0_solve_dev(ddlr_prec* h, const DevFactors<T>& F, int nrhs, const TIn* x, int64_t ldx, TOut* z, int64_t ldz,
+                  hipStream_t st, const int* done) {
+    const bool fork = !h->wide.empty() && h->nnarrow > 0 && h->overlap && h->side;
+    hipStream_t cst = st;
+    if (fork) {
+        HIPCHK(hipEventRecord(h->ev_fork, st));
+        HIPCHK(hipStreamWaitEvent(h->side, h->ev_fork, 0));
+        cst = h->side;
+    }
+    if (!h->wide.empty()) wide_levels<T, TIn, TOut>(h, F, nrhs, x, ldx, z, ldz, cst, done);
+    if (h->nnarrow > 0) {
+        ProfScope ps(h, 0, st);
+        if (ring_ready<T>(h)) {
+            launch_ring<T, TIn, TOut>(h, F.dinv, nrhs, x, ldx, z, ldz, st, done);
+        } else {
+            hipLaunchKernelGGL((k_trsv_narrow<T, TIn, TOut>), dim3(h->nnarrow_pad * nrhs), dim3(256), 0, st, h->blk,
+                               h->nnarrow, h->nnarrow_pad, nrhs, h->lvl_ptr, h->lrp, h->lci, F.lv, h->urp, h->uci,
+                               F.uv, F.dinv, x, ldx, z, ldz, done);
+            LAUNCHCHK();
+        }
+    }
+    if (fork) {
+        HIPCHK(hipEventRecord(h->ev_join, h->side));
+        HIPCHK(hipStreamWaitEvent(st, h->ev_join, 0));
     }
 }
 
 // ------------------------------------------------------------ low-rank part
 
 // coef = d .* (U^T y) (mode 1) or H (U^T y) (mode 2)
-template <typename T>
-void lr_coef(ddlr_prec* h, const T* U, int64_t rows, int nrhs, const T* y, int64_t ldy, int mode, hipStream_t st,
+template <typename T, typename TY>
+void lr_coef(ddlr_prec* h, const T* U, int64_t rows, int nrhs, const TY* y, int64_t ldy, int mode, hipStream_t st,
              const int* done) {
     Workspace& W = h->ws;
     const int k = h->k;
     ProfScope ps(h, 3, st);
     if (h->lr_plain)
-        hipLaunchKernelGGL(k_lr_reduce<T>, dim3(kLrBlocks), dim3(256), 0, st, rows, k, nrhs, U, y, ldy, W.part, done);
-    else
-        hipLaunchKernelGGL(k_lr_reduce_mfma<T>, dim3(kLrBlocks), dim3(256), 0, st, rows, k, nrhs, U, y, ldy, W.part,
+        hipLaunchKernelGGL((k_lr_reduce<T, TY>), dim3(kLrBlocks), dim3(256), 0, st, rows, k, nrhs, U, y, ldy, W.part,
                            done);
+    else
+        hipLaunchKernelGGL((k_lr_reduce_mfma<T, TY>), dim3(kLrBlocks), dim3(256), 0, st, rows, k, nrhs, U, y, ldy,
+                           W.part, done);
     LAUNCHCHK();
     hipLaunchKernelGGL(k_reduce_cols, dim3(nrhs * k), dim3(256), 0, st, kLrBlocks, nrhs * k, W.part, W.lrsum, done);
     LAUNCHCHK();
@@ -532,26 +561,28 @@ void lr_coef(ddlr_prec* h, const T* U, int64_t rows, int nrhs, const T* y, int64
 }
 
 // out = beta in + U coef
-template <typename T>
-void lr_expand(ddlr_prec* h, const T* U, int64_t rows, int nrhs, double beta, const T* in, int64_t ldin, T* out,
+template <typename T, typename TIO>
+void lr_expand(ddlr_prec* h, const T* U, int64_t rows, int nrhs, double beta, const TIO* in, int64_t ldin, TIO* out,
                int64_t ldout, hipStream_t st, const int* done) {
     ProfScope ps(h, 3, st);
     if (h->lr_plain) {
-        hipLaunchKernelGGL(k_lr_expand<T>, dim3(grid_for(rows)), dim3(256), 0, st, rows, h->k, nrhs, U, h->ws.coef,
-                           beta, in, ldin, out, ldout, done);
+        hipLaunchKernelGGL((k_lr_expand<T, TIO>), dim3(grid_for(rows)), dim3(256), 0, st, rows, h->k, nrhs, U,
+                           h->ws.coef, beta, in, ldin, out, ldout, done);
     } else {
         const int64_t tiles = (rows + 15) / 16;
-        hipLaunchKernelGGL(k_lr_expand_mfma<T>, dim3(grid_for(tiles, 4)), dim3(256), 0, st, rows, h->k, nrhs, U,
-                           h->ws.coef, beta, in, ldin, out, ldout, done);
+        hipLaunchKernelGGL((k_lr_expand_mfma<T, TIO>), dim3(grid_for(tiles, 4)), dim3(256), 0, st, rows, h->k, nrhs,
+                           U, h->ws.coef, beta, in, ldin, out, ldout, done);
     }
     LAUNCHCHK();
 }
 
 // ------------------------------------------------------------ preconditioner
 
-// out = M^{-1} in (device order, type T)
+// out = M^{-1} in (device order); I/O in double, preconditioner arithmetic in T.
+// Precision changes happen inside the kernels that read the input and write
+// the output (no separate cast passes).
 template <typename T>
-void apply_dev_T(ddlr_prec* h, int nrhs, const T* in, int64_t ldin, T* out, int64_t ldout, hipStream_t st,
+void apply_dev_T(ddlr_prec* h, int nrhs, const double* in, int64_t ldin, double* out, int64_t ldout, hipStream_t st,
                  const int* done) {
     const DevFactors<T>& F = factors<T>(h);
     Workspace& W = h->ws;
@@ -561,42 +592,30 @@ void apply_dev_T(ddlr_prec* h, int nrhs, const T* in, int64_t ldin, T* out, int6
         T* a2 = (T*)W.a2;
         T* ys = (T*)W.ys;
         T* wsv = (T*)W.ws;
-        a0_solve_dev<T>(h, F, nrhs, in, ldin, a1, n, st, done);  // step 1: A0 z = x
-        hipLaunchKernelGGL(k_csr_mv<T>, dim3(grid_for(s * nrhs)), dim3(256), 0, st, s, nrhs, h->etrp, h->etci, F.etv,
-                           a1, n, (const T*)nullptr, 0, ys, s, done);  // step 2: y = E^T z
+        a0_solve_dev<T, double, T>(h, F, nrhs, in, ldin, a1, n, st, done);  // step 1: A0 z = x
+        hipLaunchKernelGGL((k_csr_mv<T, T>), dim3(grid_for(s * nrhs)), dim3(256), 0, st, s, nrhs, h->etrp, h->etci,
+                           F.etv, a1, n, (const T*)nullptr, 0, ys, s, done);  // step 2: y = E^T z
         LAUNCHCHK();
-        lr_coef<T>(h, F.U, s, nrhs, ys, s, 1, st, done);  // step 3: w = G_{k,theta}^{-1} y (eq. gkt)
-        lr_expand<T>(h, F.U, s, nrhs, h->c0, ys, s, wsv, s, st, done);
-        hipLaunchKernelGGL(k_csr_mv<T>, dim3(grid_for(n * nrhs)), dim3(256), 0, st, n, nrhs, h->erp, h->eci, F.ev,
-                           wsv, s, in, ldin, a2, n, done);  // step 4: v = E w, fused x + v
+        lr_coef<T, T>(h, F.U, s, nrhs, ys, s, 1, st, done);  // step 3: w = G_{k,theta}^{-1} y (eq. gkt)
+        lr_expand<T, T>(h, F.U, s, nrhs, h->c0, ys, s, wsv, s, st, done);
+        hipLaunchKernelGGL((k_csr_mv<T, double>), dim3(grid_for(n * nrhs)), dim3(256), 0, st, n, nrhs, h->erp, h->eci,
+                           F.ev, wsv, s, in, ldin, a2, n, done);  // step 4: v = E w, fused x + v
         LAUNCHCHK();
-        a0_solve_dev<T>(h, F, nrhs, a2, n, out, ldout, st, done);  // step 5: A0 u = x + v
+        a0_solve_dev<T, T, double>(h, F, nrhs, a2, n, out, ldout, st, done);  // step 5: A0 u = x + v
     } else if (h->variant == DDLR_2) {
-        a0_solve_dev<T>(h, F, nrhs, in, ldin, out, ldout, st, done);
-        lr_coef<T>(h, F.U, n, nrhs, in, ldin, 2, st, done);
-        lr_expand<T>(h, F.U, n, nrhs, 1.0, out, ldout, out, ldout, st, done);
+        a0_solve_dev<T, double, double>(h, F, nrhs, in, ldin, out, ldout, st, done);
+        lr_coef<T, double>(h, F.U, n, nrhs, in, ldin, 2, st, done);
+        lr_expand<T, double>(h, F.U, n, nrhs, 1.0, out, ldout, out, ldout, st, done);
     } else {
-        a0_solve_dev<T>(h, F, nrhs, in, ldin, out, ldout, st, done);
+        a0_solve_dev<T, double, double>(h, F, nrhs, in, ldin, out, ldout, st, done);
     }
 }
 
 // out = M^{-1} in for double device-order columns
 void apply_dev(ddlr_prec* h, int nrhs, const double* in, int64_t ldin, double* out, int64_t ldout, hipStream_t st,
                const int* done) {
-    if (h->precision == DDLR_FP64) {
-        apply_dev_T<double>(h, nrhs, in, ldin, out, ldout, st, done);
-        return;
-    }
-    const int64_t n = h->plan.n;
-    float* a0 = (float*)h->ws.a0;
-    float* a3 = (float*)h->ws.a3;  // distinct from every temporary of apply_dev_T
-    hipLaunchKernelGGL((k_cast<double, float>), dim3(grid_for(n * nrhs)), dim3(256), 0, st, n, nrhs, in, ldin, a0, n,
-                       done);
-    LAUNCHCHK();
-    apply_dev_T<float>(h, nrhs, a0, n, a3, n, st, done);
-    hipLaunchKernelGGL((k_cast<float, double>), dim3(grid_for(n * nrhs)), dim3(256), 0, st, n, nrhs, a3, n, out, ldout,
-                       done);
-    LAUNCHCHK();
+    if (h->precision == DDLR_FP64) apply_dev_T<double>(h, nrhs, in, ldin, out, ldout, st, done);
+    else apply_dev_T<float>(h, nrhs, in, ldin, out, ldout, st, done);
 }
 
 void spmv_dev(ddlr_prec* h, int nrhs, const double* x, int64_t ldx, double* y, int64_t ldy, double* part,
@@ -669,10 +688,10 @@ void lanczos_build(ddlr_prec* h, int k, int m_req, const double* v0_user, uint64
         hipLaunchKernelGGL(k_csr_mv<double>, dim3(grid_for(n)), dim3(256), 0, st, n, 1, h->erp, h->eci, h->f64.ev, qj,
                            s, (const double*)nullptr, 0, t1, n, nullptr);
         LAUNCHCHK();
-        a0_solve_dev<double>(h, h->f64, 1, t1, n, t2, n, st, nullptr);
+        a0_solve_dev<double, double, double>(h, h->f64, 1, t1, n, t2, n, st, nullptr);
         const double* src = t2;
         if (h->variant == DDLR_2) {
-            a0_solve_dev<double>(h, h->f64, 1, t2, n, t1, n, st, nullptr);
+            a0_solve_dev<double, double, double>(h, h->f64, 1, t2, n, t1, n, st, nullptr);
             src = t1;
         }
         hipLaunchKernelGGL(k_csr_mv<double>, dim3(grid_for(s)), dim3(256), 0, st, s, 1, h->etrp, h->etci, h->f64.etv,
@@ -782,7 +801,7 @@ void lanczos_build(ddlr_prec* h, int k, int m_req, const double* v0_user, uint64
         hipLaunchKernelGGL(k_csr_mv<double>, dim3(grid_for(n * k)), dim3(256), 0, st, n, k, h->erp, h->eci, h->f64.ev,
                            V, s, (const double*)nullptr, 0, EV, n, nullptr);
         LAUNCHCHK();
-        a0_solve_dev<double>(h, h->f64, k, EV, n, Ucm, n, st, nullptr);
+        a0_solve_dev<double, double, double>(h, h->f64, k, EV, n, Ucm, n, st, nullptr);
         const int gblk = 512;
         double* gp = tmp.alloc<double>((size_t)gblk * k * k);
         hipLaunchKernelGGL(k_gram, dim3(gblk), dim3(256), 0, st, n, k, Ucm, n, EV, n, gp);
@@ -844,6 +863,14 @@ void lanczos_build(ddlr_prec* h, int k, int m_req, const double* v0_user, uint64
     }
     HIPCHK(hipDeviceSynchronize());
     tmp.release();
+}
+
+void release_streams(ddlr_prec* h) {
+    if (h->side) (void)hipStreamDestroy(h->side);
+    if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+    if (h->ev_join) (void)hipEventDestroy(h->ev_join);
+    h->side = nullptr;
+    h->ev_fork = h->ev_join = nullptr;
 }
 
 ddlr_status fail_status(const SetupError& e) {
@@ -926,6 +953,12 @@ ddlr_status ddlr_setup(const ddlr_csr* A, const int32_t* part, int32_t p, int32_
         if (opt.device >= 0) {
             HIPCHK(hipSetDevice(opt.device));
             upload_structures(h.get());
+            if (const char* env = std::getenv("DDLR_NO_OVERLAP")) h->overlap = env[0] != '1';
+            if (!h->wide.empty()) {
+                HIPCHK(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));  // default priority
+                HIPCHK(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
+                HIPCHK(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
+            }
             if (variant != 0) {
                 int m = opt.lanczos_steps > 0 ? opt.lanczos_steps : 2 * k;
                 if (m < k + 1 || m > 1000)
@@ -939,11 +972,13 @@ ddlr_status ddlr_setup(const ddlr_csr* A, const int32_t* part, int32_t p, int32_
             h->k = 0;
         }
     } catch (const SetupError& e) {
+        release_streams(h.get());
         h->ws.mem.release();
         h->lrmem.release();
         h->mem.release();
         return fail_status(e);
     } catch (const std::bad_alloc&) {
+        release_streams(h.get());
         h->ws.mem.release();
         h->lrmem.release();
         h->mem.release();
@@ -1365,6 +1400,7 @@ void ddlr_destroy(ddlr_prec* h) {
         (void)hipDeviceSynchronize();
         prof_reset(h);
         for (hipEvent_t e : h->prof_pool) (void)hipEventDestroy(e);
+        release_streams(h);
     }
     h->ws.mem.release();
     if (h->ws.done_host) (void)hipHostFree(h->ws.done_host);

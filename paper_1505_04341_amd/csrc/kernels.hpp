@@ -87,35 +87,35 @@ struct BlockDesc {
     int32_t lvl0, lvl1;  // levels [lvl0, lvl1) in lvl_ptr
 };
 
-template <typename T>
+template <typename T, typename TIn, typename TOut>
 __global__ __launch_bounds__(256) void k_trsv_narrow(
     const BlockDesc* __restrict__ blk, int nblk, int nblk_pad, int nrhs, const int32_t* __restrict__ lvl_ptr,
     const int32_t* __restrict__ lrp, const int32_t* __restrict__ lci, const T* __restrict__ lv,
     const int32_t* __restrict__ urp, const int32_t* __restrict__ uci, const T* __restrict__ uv,
-    const T* __restrict__ dinv, const T* x, int64_t ldx, T* z, int64_t ldz, const int* __restrict__ done) {
+    const T* __restrict__ dinv, const TIn* x, int64_t ldx, TOut* z, int64_t ldz, const int* __restrict__ done) {
     if (done && *done) return;
     const int b = blockIdx.x % nblk_pad, r = blockIdx.x / nblk_pad;
     if (b >= nblk || r >= nrhs) return;
     const BlockDesc d = blk[b];
-    const T* xr = x + r * ldx;
-    T* zr = z + r * ldz;
+    const TIn* xr = x + r * ldx;
+    TOut* zr = z + r * ldz;
     for (int l = d.lvl0; l < d.lvl1; ++l) {
         const int a = lvl_ptr[l], e = lvl_ptr[l + 1];
         for (int i = a + threadIdx.x; i < e; i += blockDim.x) {
-            T s = xr[i];
+            T s = (T)xr[i];
             const int t1 = lrp[i + 1];
-            for (int t = lrp[i]; t < t1; ++t) s -= lv[t] * zr[lci[t]];
-            zr[i] = s;
+            for (int t = lrp[i]; t < t1; ++t) s -= lv[t] * (T)zr[lci[t]];
+            zr[i] = (TOut)s;
         }
         __syncthreads();
     }
     for (int l = d.lvl1 - 1; l >= d.lvl0; --l) {
         const int a = lvl_ptr[l], e = lvl_ptr[l + 1];
         for (int i = a + threadIdx.x; i < e; i += blockDim.x) {
-            T s = zr[i] * dinv[i];
+            T s = (T)zr[i] * dinv[i];
             const int t1 = urp[i + 1];
-            for (int t = urp[i]; t < t1; ++t) s -= uv[t] * zr[uci[t]];
-            zr[i] = s;
+            for (int t = urp[i]; t < t1; ++t) s -= uv[t] * (T)zr[uci[t]];
+            zr[i] = (TOut)s;
         }
         __syncthreads();
     }
@@ -124,18 +124,22 @@ __global__ __launch_bounds__(256) void k_trsv_narrow(
 // ------------------------------------- A0 solve: narrow blocks, LDS ring
 //
 // Same schedule as k_trsv_narrow, restructured for latency:
-//  * each row's dependencies are stored per level in ELL form (width = the
-//    level's longest row, entries column-major, column = row index local to
-//    the block, -1 = padding), so one level's data is one coalesced segment;
-//  * the next level's entries, right-hand side values and D^{-1} are loaded
-//    into registers before the current level is computed, so their HBM
-//    latency overlaps the computation and the barrier;
+//  * each row's dependencies are stored per level in ELL form with a fixed
+//    width KW (entries column-major, column = row index local to the block;
+//    padding has column 0 and value 0), so one level's data is one coalesced
+//    segment and every level issues the same loads;
+//  * the next kD-1 levels' entries, right-hand side values and D^{-1} are
+//    loaded into registers ahead of use, so HBM latency overlaps computation
+//    and barriers; the steady-state loop has no divergent branches, which
+//    lets the compiler wait only for the level being computed;
+//  * lanes beyond a level's last row load and recompute that last row (all
+//    loads are unconditional) but only the owning lane stores it;
 //  * results go to global memory and to a ring of the most recent kRing rows
 //    in LDS; the host has checked that every dependency of every level lies
 //    inside that window (forward: c >= e - kRing; backward: c < a + kRing),
 //    so all gathers hit LDS and levels are separated by LDS-only barriers.
-// 512 threads, up to 2 rows per thread per level in registers; longer levels
-// finish their tail rows without prefetch.
+// 512 threads, two rows per thread per level in registers; levels longer than
+// 1024 rows finish their tail without prefetch.
 struct RingBlock {
     int32_t lvl0, lvl1, row0, pad;
 };
@@ -147,129 +151,173 @@ __device__ __forceinline__ void lds_barrier() {
 }
 
 constexpr int kRingThreads = 512;
+constexpr int kRingMaxLevels = 511;
 
-template <typename T, int KW> struct LevelRegs {
-    int a, e, w, off;
+// Registers of one prefetched level.  The right-hand-side value is kept in its
+// storage type TS and converted when used, so no load is waited for early.
+template <typename T, int KW, typename TS> struct LevelRegs {
+    int a, e, off;
     int c[2][KW];
     T v[2][KW];
-    T xv[2];
+    TS xv[2];
     T dv[2];
 };
 
-template <typename T, int KW, bool kBwd>
-__device__ __forceinline__ void ring_load(LevelRegs<T, KW>& R, int l, int row0, const int32_t* __restrict__ lvl_ptr,
-                                          const int32_t* __restrict__ eoff, const int32_t* __restrict__ ewid,
+// Per-level metadata of one block, staged in LDS at kernel start: local first
+// row and the ELL offsets of L and L^T.
+template <typename T, int KW, bool kBwd, typename TS>
+__device__ __forceinline__ void ring_load(LevelRegs<T, KW, TS>& R, int q, int row0, const int4* meta,
                                           const int32_t* __restrict__ ecol, const T* __restrict__ eval,
-                                          const T* __restrict__ dinv, const T* src) {
-    R.a = lvl_ptr[l] - row0;
-    R.e = lvl_ptr[l + 1] - row0;
-    R.w = ewid[l];
-    R.off = eoff[l];
+                                          const T* __restrict__ dinv, const TS* src) {
+    const int4 mq = meta[q];  // uniform across the workgroup: keep it in scalar registers
+    R.a = __builtin_amdgcn_readfirstlane(mq.x);
+    R.e = __builtin_amdgcn_readfirstlane(meta[q + 1].x);
+    R.off = __builtin_amdgcn_readfirstlane(kBwd ? mq.z : mq.y);
     const int nr = R.e - R.a;
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-        const int i = R.a + (int)threadIdx.x + q * kRingThreads;
-        if (i < R.e) {
-            const int base = R.off + (i - R.a);
+    for (int qq = 0; qq < 2; ++qq) {
+        if (qq == 1 && nr <= kRingThreads) break;  // uniform: one row set covers the level
+        const int i = min(R.a + (int)threadIdx.x + qq * kRingThreads, R.e - 1);
+        const int base = R.off + (i - R.a);
 #pragma unroll
-            for (int j = 0; j < KW; ++j)
-                if (j < R.w) {
-                    R.c[q][j] = ecol[base + j * nr];
-                    R.v[q][j] = eval[base + j * nr];
-                }
-            R.xv[q] = src[i];
-            if (kBwd) R.dv[q] = dinv[row0 + i];
+        for (int j = 0; j < KW; ++j) {
+            R.c[qq][j] = ecol[base + j * nr];
+            R.v[qq][j] = eval[base + j * nr];
         }
+        R.xv[qq] = src[i];
+        if (kBwd) R.dv[qq] = dinv[row0 + i];
     }
 }
 
-template <typename T, int KW, int kRing, bool kBwd>
-__device__ __forceinline__ void ring_compute(const LevelRegs<T, KW>& R, int row0, T* ring,
+template <typename T, int KW, int kRing, bool kBwd, typename TS, typename TD>
+__device__ __forceinline__ void ring_compute(const LevelRegs<T, KW, TS>& R, int row0, T* ring,
                                              const int32_t* __restrict__ ecol, const T* __restrict__ eval,
-                                             const T* __restrict__ dinv, const T* src, T* dst) {
+                                             const T* __restrict__ dinv, const TS* src, TD* dst) {
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
-        const int i = R.a + (int)threadIdx.x + q * kRingThreads;
-        if (i < R.e) {
-            T s = kBwd ? R.xv[q] * R.dv[q] : R.xv[q];
+        if (q == 1 && R.e - R.a <= kRingThreads) break;
+        const int i0 = R.a + (int)threadIdx.x + q * kRingThreads;
+        const int i = min(i0, R.e - 1);
+        T s = kBwd ? (T)R.xv[q] * R.dv[q] : (T)R.xv[q];
 #pragma unroll
-            for (int j = 0; j < KW; ++j)
-                if (j < R.w) {
-                    const int c = R.c[q][j];
-                    if (c >= 0) s -= R.v[q][j] * ring[c & (kRing - 1)];
-                }
+        for (int j = 0; j < KW; ++j) s -= R.v[q][j] * ring[R.c[q][j] & (kRing - 1)];
+        // only the owning lane stores: duplicate global stores of a forward value
+        // from other waves are not ordered against the owner's backward store
+        if (i0 < R.e) {
             ring[i & (kRing - 1)] = s;
-            dst[i] = s;
+            dst[i] = (TD)s;
         }
     }
     // rows beyond 2 * kRingThreads: no prefetch
     const int nr = R.e - R.a;
     for (int i = R.a + 2 * kRingThreads + (int)threadIdx.x; i < R.e; i += kRingThreads) {
         const int base = R.off + (i - R.a);
-        T s = kBwd ? src[i] * dinv[row0 + i] : src[i];
-        for (int j = 0; j < R.w; ++j) {
-            const int c = ecol[base + j * nr];
-            if (c >= 0) s -= eval[base + j * nr] * ring[c & (kRing - 1)];
-        }
+        T s = kBwd ? (T)src[i] * dinv[row0 + i] : (T)src[i];
+        for (int j = 0; j < KW; ++j) s -= eval[base + j * nr] * ring[ecol[base + j * nr] & (kRing - 1)];
         ring[i & (kRing - 1)] = s;
-        dst[i] = s;
+        dst[i] = (TD)s;
     }
 }
 
-template <typename T, int KW, int kRing>
+// Prefetch depth (levels in flight) that keeps the register budget under 128
+// VGPRs, so two 512-thread workgroups fit on a CU.
+template <typename T, int KW> struct RingDepth { static constexpr int value = 2; };
+template <> struct RingDepth<float, 2> { static constexpr int value = 4; };
+template <> struct RingDepth<float, 3> { static constexpr int value = 4; };
+template <> struct RingDepth<float, 4> { static constexpr int value = 3; };
+template <> struct RingDepth<double, 2> { static constexpr int value = 3; };
+template <> struct RingDepth<double, 3> { static constexpr int value = 3; };
+
+// One sweep over local levels; kBwd walks them from the last to the first.
+template <typename T, int KW, int kRing, bool kBwd, typename TS, typename TD>
+__device__ __forceinline__ void ring_sweep(int nlev, int row0, const int4* meta, T* ring,
+                                           const int32_t* __restrict__ ecol, const T* __restrict__ eval,
+                                           const T* __restrict__ dinv, const TS* src, TD* dst) {
+    constexpr int kD = RingDepth<T, KW>::value;
+    LevelRegs<T, KW, TS> buf[kD];
+    auto lev = [&](int q) { return kBwd ? nlev - 1 - q : q; };
+#pragma unroll
+    for (int u = 0; u < kD - 1; ++u)
+        if (u < nlev) ring_load<T, KW, kBwd, TS>(buf[u], lev(u), row0, meta, ecol, eval, dinv, src);
+    int q0 = 0;
+    // steady state: every prefetch in the group is a real level
+    for (; q0 + 2 * kD - 1 <= nlev; q0 += kD) {
+#pragma unroll
+        for (int u = 0; u < kD; ++u) {
+            ring_load<T, KW, kBwd, TS>(buf[(u + kD - 1) % kD], lev(q0 + u + kD - 1), row0, meta, ecol, eval, dinv,
+                                       src);
+            ring_compute<T, KW, kRing, kBwd, TS, TD>(buf[u], row0, ring, ecol, eval, dinv, src, dst);
+            lds_barrier();
+        }
+    }
+    // tail
+    for (; q0 < nlev; q0 += kD) {
+#pragma unroll
+        for (int u = 0; u < kD; ++u) {
+            const int q = q0 + u;
+            if (q < nlev) {
+                if (q + kD - 1 < nlev)
+                    ring_load<T, KW, kBwd, TS>(buf[(u + kD - 1) % kD], lev(q + kD - 1), row0, meta, ecol, eval, dinv,
+                                               src);
+                ring_compute<T, KW, kRing, kBwd, TS, TD>(buf[u], row0, ring, ecol, eval, dinv, src, dst);
+                lds_barrier();
+            }
+        }
+    }
+}
+
+template <typename T, int KW, int kRing, typename TIn, typename TOut>
 __global__ __launch_bounds__(kRingThreads) void k_trsv_ring(
     const RingBlock* __restrict__ blk, int nblk, int nblk_pad, int nrhs, const int32_t* __restrict__ lvl_ptr,
-    const int32_t* __restrict__ foff, const int32_t* __restrict__ fwid, const int32_t* __restrict__ fcol,
-    const T* __restrict__ fval, const int32_t* __restrict__ boff, const int32_t* __restrict__ bwid,
-    const int32_t* __restrict__ bcol, const T* __restrict__ bval, const T* __restrict__ dinv, const T* x, int64_t ldx,
-    T* z, int64_t ldz, const int* __restrict__ done) {
+    const int32_t* __restrict__ foff, const int32_t* __restrict__ fcol, const T* __restrict__ fval,
+    const int32_t* __restrict__ boff, const int32_t* __restrict__ bcol, const T* __restrict__ bval,
+    const T* __restrict__ dinv, const TIn* x, int64_t ldx, TOut* z, int64_t ldz, const int* __restrict__ done) {
     __shared__ T ring[kRing];
+    __shared__ int4 meta[kRingMaxLevels + 1];
     if (done && *done) return;
     const int b = blockIdx.x % nblk_pad, r = blockIdx.x / nblk_pad;
     if (b >= nblk || r >= nrhs) return;
     const RingBlock d = blk[b];
-    const T* xr = x + r * ldx + d.row0;
-    T* zr = z + r * ldz + d.row0;
-    LevelRegs<T, KW> cur, nxt;
-    // forward sweep: y = x - L y
-    ring_load<T, KW, false>(cur, d.lvl0, d.row0, lvl_ptr, foff, fwid, fcol, fval, dinv, xr);
-    for (int l = d.lvl0; l < d.lvl1; ++l) {
-        if (l + 1 < d.lvl1) ring_load<T, KW, false>(nxt, l + 1, d.row0, lvl_ptr, foff, fwid, fcol, fval, dinv, xr);
-        ring_compute<T, KW, kRing, false>(cur, d.row0, ring, fcol, fval, dinv, xr, zr);
-        lds_barrier();
-        cur = nxt;
+    const int nlev = d.lvl1 - d.lvl0;  // 1 .. kRingMaxLevels (checked on the host)
+    for (int q = threadIdx.x; q <= nlev; q += kRingThreads) {
+        const int l = d.lvl0 + q;
+        meta[q] = q < nlev ? int4{lvl_ptr[l] - d.row0, foff[l], boff[l], 0} : int4{lvl_ptr[l] - d.row0, 0, 0, 0};
     }
+    for (int q = threadIdx.x; q < kRing; q += kRingThreads) ring[q] = T(0);
+    __syncthreads();
+    const TIn* xr = x + r * ldx + d.row0;
+    TOut* zr = z + r * ldz + d.row0;
+    // forward sweep: y = x - L y
+    ring_sweep<T, KW, kRing, false, TIn, TOut>(nlev, d.row0, meta, ring, fcol, fval, dinv, xr, zr);
     __syncthreads();  // global fence: the backward sweep reads y_i from memory
     // backward sweep: z = D^{-1} y - L^T z
-    ring_load<T, KW, true>(cur, d.lvl1 - 1, d.row0, lvl_ptr, boff, bwid, bcol, bval, dinv, zr);
-    for (int l = d.lvl1 - 1; l >= d.lvl0; --l) {
-        if (l - 1 >= d.lvl0) ring_load<T, KW, true>(nxt, l - 1, d.row0, lvl_ptr, boff, bwid, bcol, bval, dinv, zr);
-        ring_compute<T, KW, kRing, true>(cur, d.row0, ring, bcol, bval, dinv, zr, zr);
-        lds_barrier();
-        cur = nxt;
-    }
+    ring_sweep<T, KW, kRing, true, TOut, TOut>(nlev, d.row0, meta, ring, bcol, bval, dinv, zr, zr);
 }
 
 // ------------------------------------------------ A0 solve: one wide level
 //
 // For the interface block C_alpha in multicolour order the schedule has a few
 // very wide levels; each level is one grid-wide launch over rows x rhs.
-// forward:  z_i = x_i - sum L_ij z_j ;  backward: z_i = D_i^{-1} z_i - sum L_ji z_j
-template <typename T, bool kBackward>
+// kind 0 forward:   z_i = x_i - sum_j L_ij z_j
+// kind 1 backward:  z_i = D_i^{-1} z_i - sum_j L_ji z_j
+// kind 2 the last forward level, which has no backward dependencies:
+//                   z_i = D_i^{-1} (x_i - sum_j L_ij z_j)
+template <typename T, int kKind, typename TIn, typename TOut>
 __global__ __launch_bounds__(256) void k_trsv_level(int a, int e, int nrhs, const int32_t* __restrict__ rp,
                                                     const int32_t* __restrict__ ci, const T* __restrict__ v,
-                                                    const T* __restrict__ dinv, const T* x, int64_t ldx, T* z,
+                                                    const T* __restrict__ dinv, const TIn* x, int64_t ldx, TOut* z,
                                                     int64_t ldz, const int* __restrict__ done) {
     if (done && *done) return;
     const int rows = e - a;
     const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (g >= (int64_t)rows * nrhs) return;
     const int r = (int)(g / rows), i = a + (int)(g - (int64_t)r * rows);
-    T* zr = z + r * ldz;
-    T s = kBackward ? zr[i] * dinv[i] : x[i + r * ldx];
+    TOut* zr = z + r * ldz;
+    T s = kKind == 1 ? (T)zr[i] * dinv[i] : (T)x[i + r * ldx];
     const int t1 = rp[i + 1];
-    for (int t = rp[i]; t < t1; ++t) s -= v[t] * zr[ci[t]];
-    zr[i] = s;
+    for (int t = rp[i]; t < t1; ++t) s -= v[t] * (T)zr[ci[t]];
+    if (kKind == 2) s *= dinv[i];
+    zr[i] = (TOut)s;
 }
 
 // ------------------------------------------------------------ SpMV (SELL-64)
@@ -327,17 +375,17 @@ __global__ __launch_bounds__(256) void k_spmv_sell(int64_t n, int nrhs, const in
 // interior rows and -alpha on the interface diagonal, eq. EF).
 //   k_csr_mv:  y = M w            (E^T z, or E q for Lanczos)
 //   k_csr_add: t = x + M w        (step 4 of the DDLR-1 algorithm fused with x + v)
-template <typename T>
+template <typename T, typename TX = T>
 __global__ __launch_bounds__(256) void k_csr_mv(int64_t rows, int nrhs, const int32_t* __restrict__ rp,
                                                 const int32_t* __restrict__ ci, const T* __restrict__ v,
-                                                const T* __restrict__ w, int64_t ldw, const T* __restrict__ x,
+                                                const T* __restrict__ w, int64_t ldw, const TX* __restrict__ x,
                                                 int64_t ldx, T* __restrict__ y, int64_t ldy,
                                                 const int* __restrict__ done) {
     if (done && *done) return;
     const int64_t total = rows * nrhs;
     for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
         const int64_t r = g / rows, i = g - r * rows;
-        T s = x ? x[i + r * ldx] : T(0);
+        T s = x ? (T)x[i + r * ldx] : T(0);
         const T* wr = w + r * ldw;
         for (int t = rp[i]; t < rp[i + 1]; ++t) s += v[t] * wr[ci[t]];
         y[i + r * ldy] = s;
@@ -351,9 +399,9 @@ __global__ __launch_bounds__(256) void k_csr_mv(int64_t rows, int nrhs, const in
 // U_k is row-major (k contiguous per row).  Stage 1 accumulates per-block
 // partials of U_k^T y (k x nrhs); stage 2 sums them in fixed order and applies
 // d (DDLR-1) or H_k (DDLR-2); stage 3 expands.
-template <typename T>
+template <typename T, typename TY = T>
 __global__ __launch_bounds__(256) void k_lr_reduce(int64_t rows, int k, int nrhs, const T* __restrict__ U,
-                                                   const T* __restrict__ y, int64_t ldy, double* __restrict__ part,
+                                                   const TY* __restrict__ y, int64_t ldy, double* __restrict__ part,
                                                    const int* __restrict__ done) {
     // part layout: [block][r][j]; lane <-> column j, waves and blocks stride the rows
     __shared__ double sh[4][64];
@@ -410,10 +458,10 @@ __global__ __launch_bounds__(256) void k_reduce_cols(int nparts, int ncols, cons
 }
 
 // out[i] = beta * in[i] + sum_j U[i][j] coef[r][j]
-template <typename T>
+template <typename T, typename TIO = T>
 __global__ __launch_bounds__(256) void k_lr_expand(int64_t rows, int k, int nrhs, const T* __restrict__ U,
-                                                   const double* __restrict__ coef, double beta, const T* in,
-                                                   int64_t ldin, T* out, int64_t ldout, const int* __restrict__ done) {
+                                                   const double* __restrict__ coef, double beta, const TIO* in,
+                                                   int64_t ldin, TIO* out, int64_t ldout, const int* __restrict__ done) {
     __shared__ double cf[kMaxRhs * 128];
     if (done && *done) return;
     for (int q = threadIdx.x; q < nrhs * k; q += blockDim.x) cf[q] = coef[q];
@@ -431,7 +479,7 @@ __global__ __launch_bounds__(256) void k_lr_expand(int64_t rows, int k, int nrhs
         }
 #pragma unroll
         for (int r = 0; r < kMaxRhs; ++r)
-            if (r < nrhs) out[i + r * ldout] = (T)acc[r];
+            if (r < nrhs) out[i + r * ldout] = (TIO)acc[r];
     }
 }
 
@@ -464,9 +512,9 @@ template <> struct MfmaAcc<double> {
 // Reduce: part[block][r][j] = sum over the block's rows of U[row][j] y_r[row].
 // C = U^T Y: M = k (tiles of 16), N = nrhs (<= 16), K = rows (steps of 4).
 // Each wave owns a contiguous run of rows; k <= 128 -> up to 8 accumulator tiles.
-template <typename T>
+template <typename T, typename TY = T>
 __global__ __launch_bounds__(256) void k_lr_reduce_mfma(int64_t rows, int k, int nrhs, const T* __restrict__ U,
-                                                        const T* __restrict__ y, int64_t ldy,
+                                                        const TY* __restrict__ y, int64_t ldy,
                                                         double* __restrict__ part, const int* __restrict__ done) {
     typedef typename MfmaAcc<T>::type acc_t;
     __shared__ double stage[4][64];
@@ -484,7 +532,7 @@ __global__ __launch_bounds__(256) void k_lr_reduce_mfma(int64_t rows, int k, int
     for (int64_t i0 = r0; i0 < r1; i0 += 4) {
         const int64_t i = i0 + kk;
         const bool ok = i < r1;
-        const T bval = (ok && col < nrhs) ? y[i + col * ldy] : T(0);
+        const T bval = (ok && col < nrhs) ? (T)y[i + col * ldy] : T(0);
 #pragma unroll
         for (int t = 0; t < 8; ++t)
             if (t < ntile) {
@@ -509,10 +557,10 @@ __global__ __launch_bounds__(256) void k_lr_reduce_mfma(int64_t rows, int k, int
 
 // Expand: out[row][r] = beta in[row][r] + sum_j U[row][j] coef[r][j].
 // M = 16 rows, N = nrhs (<= 16), K = k (steps of 4); one 16-row tile per wave-step.
-template <typename T>
+template <typename T, typename TIO = T>
 __global__ __launch_bounds__(256) void k_lr_expand_mfma(int64_t rows, int k, int nrhs, const T* __restrict__ U,
-                                                        const double* __restrict__ coef, double beta, const T* in,
-                                                        int64_t ldin, T* out, int64_t ldout,
+                                                        const double* __restrict__ coef, double beta, const TIO* in,
+                                                        int64_t ldin, TIO* out, int64_t ldout,
                                                         const int* __restrict__ done) {
     typedef typename MfmaAcc<T>::type acc_t;
     __shared__ T cf[128 * 16];  // cf[j*16 + r]
@@ -540,7 +588,7 @@ __global__ __launch_bounds__(256) void k_lr_expand_mfma(int64_t rows, int k, int
             const int64_t row = tile * 16 + MfmaAcc<T>::row(lane, v);
             if (row < rows && rr < nrhs) {
                 const double o = beta * (double)in[row + rr * ldin] + (double)acc[v];
-                out[row + rr * ldout] = (T)o;
+                out[row + rr * ldout] = (TIO)o;
             }
         }
     }

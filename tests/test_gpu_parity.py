@@ -261,3 +261,19 @@ def test_cg_refused_for_indefinite_preconditioner():
     with pytest.raises(D.DDLRError) as e:
         D.ddlr_solve(h, b, x)
     assert e.value.status == D.E_NOT_SPD
+
+
+@pytest.mark.parametrize("overlap", ["0", "1"])
+def test_interface_levels_on_side_stream(overlap):
+    """The interface block's level kernels on a side stream (fork/join by
+    events) or on the caller's stream give the same result."""
+    cfg = big3d()
+    say("side stream", overlap)
+    h, o = setup_pair(cfg, variant=1, wide=True, env={"DDLR_NO_OVERLAP": "1" if overlap == "0" else "0"},
+                      precision=D.FP32)
+    n = cfg["A"].n
+    x = np.random.default_rng(11).standard_normal((n, 8))
+    y = torch.empty((8, n), dtype=torch.float64, device=DEV)
+    for _ in range(3):
+        D.ddlr_a0_solve(h, to_dev(x), y)
+    assert rel(to_host(y), o.a0_solve(x)) <= 1e-5
