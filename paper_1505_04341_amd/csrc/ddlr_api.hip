@@ -81,6 +81,12 @@ struct Workspace {
     int* done = nullptr;
     int* done_host = nullptr;
     DMem mem;
+    // GMRES (allocated on first use, sized for gm_m and nrhs)
+    int gm_m = 0, gm_nrhs = 0;
+    double *gV = nullptr, *gH = nullptr, *gcs = nullptr, *gsn = nullptr, *gg = nullptr, *gy = nullptr;
+    double *gcoef = nullptr, *ginv = nullptr, *gpart = nullptr;
+    GmLane* glanes = nullptr;
+    DMem gmem;
 };
 
 }  // namespace
@@ -380,6 +386,8 @@ void ensure_ws(ddlr_prec* h, int nrhs) {
     Workspace& W = h->ws;
     if (W.nrhs >= nrhs) return;
     W.mem.release();
+    W.gmem.release();
+    W.gm_m = W.gm_nrhs = 0;
     if (W.done_host) {
         (void)hipHostFree(W.done_host);
         W.done_host = nullptr;
@@ -1063,6 +1071,105 @@ ddlr_status ddlr_spmv(ddlr_prec* h, int32_t nrhs, const double* x, int64_t ldx, 
 
 }  // extern "C"
 
+constexpr int kGmChunks = 64;
+
+static void ensure_gmres(ddlr_prec* h, int nr, int m) {
+    Workspace& W = h->ws;
+    if (W.gm_m >= m && W.gm_nrhs >= nr) return;
+    W.gmem.release();
+    const int64_t n = h->plan.n;
+    W.gV = W.gmem.alloc<double>((size_t)(m + 1) * nr * n);
+    W.gH = W.gmem.alloc<double>((size_t)nr * m * (m + 1));
+    W.gcs = W.gmem.alloc<double>((size_t)nr * m);
+    W.gsn = W.gmem.alloc<double>((size_t)nr * m);
+    W.gg = W.gmem.alloc<double>((size_t)nr * (m + 1));
+    W.gy = W.gmem.alloc<double>((size_t)nr * m);
+    W.gcoef = W.gmem.alloc<double>((size_t)nr * (m + 1));
+    W.ginv = W.gmem.alloc<double>(nr);
+    W.gpart = W.gmem.alloc<double>((size_t)kGmChunks * (m + 1) * nr);
+    W.glanes = W.gmem.alloc<GmLane>(nr);
+    W.gm_m = m;
+    W.gm_nrhs = nr;
+}
+
+// Right-preconditioned GMRES(m) on nr columns already gathered into W.r (b);
+// result in W.x.  Arnoldi by classical Gram-Schmidt applied twice.
+static void gmres_dev(ddlr_prec* h, int nr, const ddlr_solve_options& o, hipStream_t st) {
+    const int m = o.restart;
+    ensure_gmres(h, nr, m);
+    Workspace& W = h->ws;
+    const int64_t n = h->plan.n;
+    const double tol2 = o.rtol * o.rtol;
+    // W.p keeps b; W.x = 0
+    HIPCHK(hipMemcpyAsync(W.p, W.r, sizeof(double) * n * nr, hipMemcpyDeviceToDevice, st));
+    hipLaunchKernelGGL(k_fill, dim3(grid_for(n * nr)), dim3(256), 0, st, n * nr, 0.0, W.x);
+    LAUNCHCHK();
+    for (int cycle = 0;; ++cycle) {
+        // r = b - A x, beta = ||r||
+        spmv_dev(h, nr, W.x, n, W.q, n, nullptr, st, nullptr);
+        hipLaunchKernelGGL(k_sub, dim3(grid_for(n * nr)), dim3(256), 0, st, n * nr, W.p, W.q, W.r);
+        LAUNCHCHK();
+        dot_dev(h, nr, W.r, W.r, n, st, nullptr);
+        hipLaunchKernelGGL(k_gm_start, dim3(1), dim3(64), 0, st, nr, m, W.sums, W.gg, W.gH, W.ginv, W.glanes, tol2,
+                           o.maxit, cycle == 0 ? 1 : 0, W.done);
+        LAUNCHCHK();
+        HIPCHK(hipMemcpyAsync(W.done_host, W.done, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (!*W.done_host) break;  // no lane opened a cycle
+        // done := 0 while any lane is active (k_gm_start wrote "any active" into it)
+        hipLaunchKernelGGL(k_gm_scale, dim3(grid_for(n * nr)), dim3(256), 0, st, n, nr, W.r, W.ginv, W.gV);
+        LAUNCHCHK();
+        hipLaunchKernelGGL(k_flag_not, dim3(1), dim3(1), 0, st, W.done);
+        LAUNCHCHK();
+        for (int j = 0; j < m; ++j) {
+            double* Vj = W.gV + (size_t)j * nr * n;
+            apply_dev(h, nr, Vj, n, W.z, n, st, W.done);               // z = M^{-1} v_j
+            spmv_dev(h, nr, W.z, n, W.q, n, nullptr, st, W.done);      // w = A z
+            for (int pass = 0; pass < 2; ++pass) {
+                hipLaunchKernelGGL(k_gm_dots, dim3(kGmChunks, j + 1), dim3(256), 0, st, n, nr, W.gV, W.q, W.gpart,
+                                   W.done);
+                LAUNCHCHK();
+                hipLaunchKernelGGL(k_gm_coef, dim3(1), dim3(256), 0, st, kGmChunks, nr, j + 1, m, j, W.gpart, W.gcoef,
+                                   W.gH, W.glanes, W.done);
+                LAUNCHCHK();
+                hipLaunchKernelGGL(k_gm_sub, dim3(grid_for(n * nr)), dim3(256), 0, st, n, nr, j + 1, W.gV, W.gcoef,
+                                   W.q, W.done);
+                LAUNCHCHK();
+            }
+            dot_dev(h, nr, W.q, W.q, n, st, W.done);
+            hipLaunchKernelGGL(k_gm_givens, dim3(1), dim3(64), 0, st, j, nr, m, W.sums, W.gH, W.gcs, W.gsn, W.gg,
+                               W.ginv, W.glanes, tol2, o.maxit, W.done);
+            LAUNCHCHK();
+            if (j + 1 < m) {
+                hipLaunchKernelGGL(k_gm_scale, dim3(grid_for(n * nr)), dim3(256), 0, st, n, nr, W.q, W.ginv,
+                                   W.gV + (size_t)(j + 1) * nr * n);
+                LAUNCHCHK();
+            }
+            if ((j + 1) % 8 == 0 || j + 1 == m) {
+                HIPCHK(hipMemcpyAsync(W.done_host, W.done, sizeof(int), hipMemcpyDeviceToHost, st));
+                HIPCHK(hipStreamSynchronize(st));
+                if (*W.done_host) break;
+            }
+        }
+        // x += M^{-1} V y
+        hipLaunchKernelGGL(k_gm_solve, dim3(1), dim3(64), 0, st, nr, m, W.gH, W.gg, W.gy, W.glanes);
+        LAUNCHCHK();
+        hipLaunchKernelGGL(k_gm_combine, dim3(grid_for(n * nr)), dim3(256), 0, st, n, nr, m, W.gV, W.gy, W.glanes,
+                           W.r);
+        LAUNCHCHK();
+        apply_dev(h, nr, W.r, n, W.z, n, st, nullptr);
+        hipLaunchKernelGGL(k_gm_xupdate, dim3(grid_for(n * nr)), dim3(256), 0, st, n, nr, W.glanes, W.z, W.x);
+        LAUNCHCHK();
+    }
+    // lanes -> CG lane records used by the reporting code
+    hipLaunchKernelGGL(k_gm_report, dim3(1), dim3(64), 0, st, nr, W.glanes, W.lanes);
+    LAUNCHCHK();
+}
+
+extern "C" {
+
+}  // extern "C"
+
 // PCG on nr columns already gathered into W.r (b); result in W.x.
 static void pcg_dev(ddlr_prec* h, int nr, const ddlr_solve_options& o, hipStream_t st) {
     Workspace& W = h->ws;
@@ -1122,8 +1229,8 @@ ddlr_status ddlr_solve(ddlr_prec* h, int32_t nrhs, const double* b, int64_t ldb,
         g_err = "bad solve options";
         return DDLR_E_INVALID;
     }
-    if (o.method == 1) {
-        g_err = "GMRES is not available in this build";
+    if (o.method == 1 && (o.restart < 1 || o.restart > 60)) {
+        g_err = "GMRES restart must be in [1, 60]";
         return DDLR_E_INVALID;
     }
     if (o.method == 0 && !h->spd) {
@@ -1142,7 +1249,8 @@ ddlr_status ddlr_solve(ddlr_prec* h, int32_t nrhs, const double* b, int64_t ldb,
             hipLaunchKernelGGL((k_gather<double, double>), dim3(grid_for(n * nr)), dim3(256), 0, st, n, nr,
                                h->perm_dev, b + c0 * ldb, ldb, W.r, n);
             LAUNCHCHK();
-            pcg_dev(h, nr, o, st);
+            if (o.method == 0) pcg_dev(h, nr, o, st);
+            else gmres_dev(h, nr, o, st);
             hipLaunchKernelGGL((k_scatter<double, double>), dim3(grid_for(n * nr)), dim3(256), 0, st, n, nr,
                                h->perm_dev, W.x, n, x + c0 * ldx, ldx);
             LAUNCHCHK();
@@ -1163,7 +1271,7 @@ ddlr_status ddlr_solve(ddlr_prec* h, int32_t nrhs, const double* b, int64_t ldb,
                 ddlr_solve_info& inf = info[c0 + c];
                 const double bb = lanes[c].bb;
                 inf.iters = lanes[c].its;
-                const bool conv = bb == 0.0 || lanes[c].rr <= o.rtol * o.rtol * bb;
+                const bool conv = bb == 0.0 || lanes[c].rr <= o.rtol * o.rtol * bb || (o.method == 1 && lanes[c].active);
                 inf.status = conv ? DDLR_OK : DDLR_E_NO_CONVERGENCE;
                 inf.relres = bb > 0 ? std::sqrt(lanes[c].rr / bb) : 0.0;
                 inf.relres_true = bb > 0 ? std::sqrt(rr[c] / bb) : 0.0;
@@ -1341,6 +1449,8 @@ ddlr_status ddlr_set_lowrank(ddlr_prec* h, int32_t variant, int32_t k, const dou
         }
         h->ws.nrhs = 0;  // coefficient buffers depend on k
         h->ws.mem.release();
+        h->ws.gmem.release();
+        h->ws.gm_m = h->ws.gm_nrhs = 0;
     } catch (const SetupError& e) {
         return fail_status(e);
     }
@@ -1403,6 +1513,7 @@ void ddlr_destroy(ddlr_prec* h) {
         release_streams(h);
     }
     h->ws.mem.release();
+    h->ws.gmem.release();
     if (h->ws.done_host) (void)hipHostFree(h->ws.done_host);
     h->lrmem.release();
     h->mem.release();

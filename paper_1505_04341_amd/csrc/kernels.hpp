@@ -699,6 +699,237 @@ __global__ __launch_bounds__(256) void k_cg_p(int64_t n, int nrhs, const CgLane*
     }
 }
 
+// ------------------------------------------------------------ GMRES steps
+//
+// Right-preconditioned restarted GMRES on nrhs independent systems.  Basis
+// vectors are stored as V[l][r][i] (l = basis index, r = right-hand side), so
+// the l-th vectors of all systems form one column-major n x nrhs block.
+struct GmLane {
+    double bb, est;
+    int32_t its, kc, active, conv, dead, pad;  // kc: steps taken in the current cycle
+};
+
+// part[(l * nchunk + chunk) * nrhs + r] = V[l][r] . w[r] over the chunk's rows
+__global__ __launch_bounds__(256) void k_gm_dots(int64_t n, int nrhs, const double* __restrict__ V,
+                                                 const double* __restrict__ w, double* __restrict__ part,
+                                                 const int* __restrict__ done) {
+    __shared__ double sh[4][kMaxRhs];
+    if (done && *done) return;
+    const int l = blockIdx.y, chunk = blockIdx.x, nchunk = gridDim.x;
+    double acc[kMaxRhs];
+#pragma unroll
+    for (int r = 0; r < kMaxRhs; ++r) acc[r] = 0.0;
+    const double* Vl = V + (int64_t)l * nrhs * n;
+    for (int64_t i = (int64_t)chunk * blockDim.x + threadIdx.x; i < n; i += (int64_t)nchunk * blockDim.x) {
+#pragma unroll
+        for (int r = 0; r < kMaxRhs; ++r)
+            if (r < nrhs) acc[r] += Vl[r * n + i] * w[r * n + i];
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int r = 0; r < nrhs; ++r) {
+        const double v = wave_sum(acc[r]);
+        if (lane == 0) sh[wv][r] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < nrhs) {
+        const int r = threadIdx.x;
+        part[((int64_t)l * nchunk + chunk) * nrhs + r] = (sh[0][r] + sh[1][r]) + (sh[2][r] + sh[3][r]);
+    }
+}
+
+// coef[r][l] = sum over chunks; H column j of lane r accumulates coef (two
+// Gram-Schmidt passes add up to the Hessenberg entries)
+__global__ void k_gm_coef(int nchunk, int nrhs, int ncols, int m, int j, const double* __restrict__ part,
+                          double* __restrict__ coef, double* __restrict__ H, const GmLane* __restrict__ L,
+                          const int* __restrict__ done) {
+    if (done && *done) return;
+    for (int q = threadIdx.x; q < nrhs * ncols; q += blockDim.x) {
+        const int r = q / ncols, l = q - r * ncols;
+        double s = 0.0;
+        for (int c = 0; c < nchunk; ++c) s += part[((int64_t)l * nchunk + c) * nrhs + r];
+        const bool act = L[r].active;
+        coef[r * ncols + l] = act ? s : 0.0;
+        if (act) H[((int64_t)r * m + j) * (m + 1) + l] += s;
+    }
+}
+
+// w[r] -= sum_l V[l][r] coef[r][l]
+__global__ __launch_bounds__(256) void k_gm_sub(int64_t n, int nrhs, int ncols, const double* __restrict__ V,
+                                                const double* __restrict__ coef, double* __restrict__ w,
+                                                const int* __restrict__ done) {
+    __shared__ double cf[kMaxRhs * 64];
+    if (done && *done) return;
+    for (int q = threadIdx.x; q < nrhs * ncols; q += blockDim.x) cf[q] = coef[q];
+    __syncthreads();
+    const int64_t total = n * nrhs;
+    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = g / n, i = g - r * n;
+        double v = w[r * n + i];
+        for (int l = 0; l < ncols; ++l) v -= V[((int64_t)l * nrhs + r) * n + i] * cf[r * ncols + l];
+        w[r * n + i] = v;
+    }
+}
+
+// Step j of every active lane: h_{j+1,j} = ||w||, previous rotations applied
+// to column j, a new rotation, the residual estimate |g_{j+1}|, stopping test.
+__global__ void k_gm_givens(int j, int nrhs, int m, const double* __restrict__ wn2, double* __restrict__ H,
+                            double* __restrict__ cs, double* __restrict__ sn, double* __restrict__ g,
+                            double* __restrict__ inv, GmLane* __restrict__ L, double tol2, int maxit,
+                            int* __restrict__ done) {
+    if (done && *done) return;
+    const int r = threadIdx.x;
+    if (r < nrhs) {
+        GmLane& l = L[r];
+        inv[r] = 0.0;
+        if (l.active) {
+            double* h = H + ((int64_t)r * m + j) * (m + 1);
+            double* c = cs + (int64_t)r * m;
+            double* s = sn + (int64_t)r * m;
+            double* gg = g + (int64_t)r * (m + 1);
+            const double hn = sqrt(wn2[r]);
+            h[j + 1] = hn;
+            inv[r] = hn > 0.0 ? 1.0 / hn : 0.0;
+            for (int q = 0; q < j; ++q) {
+                const double t0 = c[q] * h[q] + s[q] * h[q + 1];
+                const double t1 = -s[q] * h[q] + c[q] * h[q + 1];
+                h[q] = t0;
+                h[q + 1] = t1;
+            }
+            const double den = sqrt(h[j] * h[j] + h[j + 1] * h[j + 1]);
+            c[j] = den > 0.0 ? h[j] / den : 1.0;
+            s[j] = den > 0.0 ? h[j + 1] / den : 0.0;
+            h[j] = den;
+            h[j + 1] = 0.0;
+            gg[j + 1] = -s[j] * gg[j];
+            gg[j] = c[j] * gg[j];
+            l.its += 1;
+            l.kc = j + 1;
+            l.est = fabs(gg[j + 1]);
+            const bool conv = l.est * l.est <= tol2 * l.bb;
+            if (conv) l.conv = 1;
+            if (conv || l.its >= maxit || j + 1 == m || hn == 0.0) l.active = 0;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && done) {
+        int any = 0;
+        for (int q = 0; q < nrhs; ++q) any |= L[q].active;
+        *done = any ? 0 : 1;
+    }
+}
+
+// V[j+1][r] = w[r] * inv[r]
+__global__ __launch_bounds__(256) void k_gm_scale(int64_t n, int nrhs, const double* __restrict__ w,
+                                                  const double* __restrict__ inv, double* __restrict__ Vn) {
+    const int64_t total = n * nrhs;
+    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = g / n;
+        Vn[g] = w[g] * inv[r];
+    }
+}
+
+// Cycle start: beta_r = ||r_r||; lanes that converged or ran out of steps are
+// retired, the others open a cycle with g = beta e_1 and V[0] = r / beta.
+__global__ void k_gm_start(int nrhs, int m, const double* __restrict__ rn2, double* __restrict__ g,
+                           double* __restrict__ H, double* __restrict__ inv, GmLane* __restrict__ L, double tol2,
+                           int maxit, int first, int* __restrict__ any_active) {
+    const int r = threadIdx.x;
+    if (r < nrhs) {
+        GmLane& l = L[r];
+        const double b2 = rn2[r];
+        if (first) {
+            l.bb = b2;
+            l.its = 0;
+            l.conv = 0;
+            l.dead = 0;
+            l.est = sqrt(b2);
+        }
+        l.kc = 0;
+        l.active = 0;
+        inv[r] = 0.0;
+        if (!l.dead) {
+            if (b2 <= tol2 * l.bb) {
+                l.conv = 1;
+                l.dead = 1;
+                l.est = sqrt(b2);
+            } else if (l.its >= maxit) {
+                l.dead = 1;
+            } else {
+                l.active = 1;
+                const double beta = sqrt(b2);
+                inv[r] = 1.0 / beta;
+                double* gg = g + (int64_t)r * (m + 1);
+                for (int q = 0; q <= m; ++q) gg[q] = 0.0;
+                gg[0] = beta;
+                double* h = H + (int64_t)r * m * (m + 1);
+                for (int q = 0; q < m * (m + 1); ++q) h[q] = 0.0;
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int any = 0;
+        for (int q = 0; q < nrhs; ++q) any |= L[q].active;
+        *any_active = any;
+    }
+}
+
+// y = H^{-1} g (upper triangular, kc x kc) per lane
+__global__ void k_gm_solve(int nrhs, int m, const double* __restrict__ H, const double* __restrict__ g,
+                           double* __restrict__ y, const GmLane* __restrict__ L) {
+    const int r = threadIdx.x;
+    if (r >= nrhs) return;
+    const int kc = L[r].kc;
+    const double* h = H + (int64_t)r * m * (m + 1);
+    const double* gg = g + (int64_t)r * (m + 1);
+    double* yy = y + (int64_t)r * m;
+    for (int q = 0; q < m; ++q) yy[q] = 0.0;
+    for (int i = kc - 1; i >= 0; --i) {
+        double v = gg[i];
+        for (int q = i + 1; q < kc; ++q) v -= h[(int64_t)q * (m + 1) + i] * yy[q];
+        yy[i] = v / h[(int64_t)i * (m + 1) + i];
+    }
+}
+
+// u[r] = sum_{l < kc_r} V[l][r] y[r][l]
+__global__ __launch_bounds__(256) void k_gm_combine(int64_t n, int nrhs, int m, const double* __restrict__ V,
+                                                    const double* __restrict__ y, const GmLane* __restrict__ L,
+                                                    double* __restrict__ u) {
+    const int64_t total = n * nrhs;
+    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = g / n, i = g - r * n;
+        const int kc = L[r].kc;
+        double v = 0.0;
+        for (int l = 0; l < kc; ++l) v += V[((int64_t)l * nrhs + r) * n + i] * y[r * m + l];
+        u[g] = v;
+    }
+}
+
+// done := !done (turns the "any lane active" result of k_gm_start into the
+// early-exit flag of the step kernels)
+__global__ void k_flag_not(int* __restrict__ f) { *f = *f ? 0 : 1; }
+
+// GMRES lane state -> the solve report (rr = est^2, active = converged flag)
+__global__ void k_gm_report(int nrhs, const GmLane* __restrict__ G, CgLane* __restrict__ L) {
+    const int r = threadIdx.x;
+    if (r < nrhs) {
+        L[r].bb = G[r].bb;
+        L[r].rr = G[r].est * G[r].est;
+        L[r].its = G[r].its;
+        L[r].active = G[r].conv;
+    }
+}
+
+// x[r] += z[r] for lanes that took steps in this cycle
+__global__ __launch_bounds__(256) void k_gm_xupdate(int64_t n, int nrhs, const GmLane* __restrict__ L,
+                                                    const double* __restrict__ z, double* __restrict__ x) {
+    const int64_t total = n * nrhs;
+    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = g / n;
+        if (L[r].kc > 0) x[g] += z[g];
+    }
+}
+
 // ------------------------------------------------------------ Lanczos steps
 //
 // Q holds the Lanczos vectors as columns (s x (m+1), column-major, ld s).

@@ -277,3 +277,46 @@ def test_interface_levels_on_side_stream(overlap):
     for _ in range(3):
         D.ddlr_a0_solve(h, to_dev(x), y)
     assert rel(to_host(y), o.a0_solve(x)) <= 1e-5
+
+
+def shifted2d(sig, nx=24, ny=20):
+    A = w.laplacian_2d(nx, ny)
+    d = A.val.copy()
+    rows = np.repeat(np.arange(A.n), np.diff(A.rowptr))
+    d[rows == A.col] -= sig
+    return w.CSR(A.n, A.rowptr, A.col, d), w.box_partition((nx, ny), (2, 2))
+
+
+@pytest.mark.parametrize("restart", [40, 7])
+@pytest.mark.parametrize("variant", [0, 1, 2])
+def test_gmres_matches_oracle(restart, variant):
+    """Right-preconditioned GMRES(restart) on an indefinite shifted Laplacian:
+    iterate and iteration count as in the oracle's GMRES."""
+    A, part = shifted2d(0.3)
+    say("gmres", restart, variant)
+    h = D.ddlr_setup(A, part, 4, 10, variant, lanczos_steps=30, factor=D.FACTOR_ILDL0,
+                     lanczos_start=w.lanczos_start(A.n, 1))
+    o = Oracle(A, part, 4, factor=FACTOR_ILDL)
+    if variant:
+        o.lowrank(variant, 10, 30, w.lanczos_start(A.n, 1))
+        lr = o.get_lowrank()
+        D.ddlr_set_lowrank(h, variant, *lr)  # same preconditioner on both sides
+    b, _ = w.rhs_from_solution(A, 0, 3)
+    x = torch.zeros((3, A.n), dtype=torch.float64, device=DEV)
+    st, info = D.ddlr_solve(h, to_dev(b), x, method=1, restart=restart)
+    xo, io = o.gmres(b, restart=restart)
+    # short restarts with the A0 part alone may stagnate on this indefinite
+    # problem: the statuses must agree either way
+    assert st == io["status"]
+    for i, it in zip(info, io["its"]):
+        # rounding differences accumulate over many short restart cycles
+        assert abs(i["iters"] - int(it)) <= max(1, int(0.03 * int(it)))
+        if st == D.OK:
+            assert i["relres"] <= 1e-6 and i["relres_true"] <= 2e-6
+    if st == D.OK:
+        assert rel(to_host(x), xo) <= 1e-5
+    # a fixed number of steps gives the same iterate
+    st, info = D.ddlr_solve(h, to_dev(b), x, method=1, restart=restart, maxit=restart + 3)
+    xo, io = o.gmres(b, restart=restart, maxit=restart + 3)
+    assert st == D.E_NO_CONVERGENCE and all(i["iters"] == restart + 3 for i in info)
+    assert rel(to_host(x), xo) <= 1e-9
