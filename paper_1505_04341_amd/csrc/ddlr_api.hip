@@ -9,6 +9,7 @@
 #include <cstring>
 #include <memory>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "ddlr.h"
@@ -128,6 +129,8 @@ struct ddlr_prec {
     DevFactors<double> f64;
     DevFactors<float> f32;
     int64_t urows = 0;      // rows of U (s for DDLR-1, n for DDLR-2)
+    __bf16 *ubr = nullptr, *ubt = nullptr;  // BF16 U_k: row-major (k padded to 32) and reduction tiles
+    int ukp = 0, uktiles = 0;
     double *dvec = nullptr, *Hk = nullptr;
     Workspace ws;
     DMem lrmem;  // low-rank storage (replaced by set_lowrank)
@@ -555,7 +558,10 @@ void lr_coef(ddlr_prec* h, const T* U, int64_t rows, int nrhs, const TY* y, int6
     Workspace& W = h->ws;
     const int k = h->k;
     ProfScope ps(h, 3, st);
-    if (h->lr_plain)
+    if (h->ubt && std::is_same<T, float>::value)
+        hipLaunchKernelGGL((k_lr_reduce_bf16<TY>), dim3(kLrBlocks), dim3(256), 0, st, rows, k, nrhs, h->ubt, y, ldy,
+                           W.part, done);
+    else if (h->lr_plain)
         hipLaunchKernelGGL((k_lr_reduce<T, TY>), dim3(kLrBlocks), dim3(256), 0, st, rows, k, nrhs, U, y, ldy, W.part,
                            done);
     else
@@ -573,7 +579,11 @@ template <typename T, typename TIO>
 void lr_expand(ddlr_prec* h, const T* U, int64_t rows, int nrhs, double beta, const TIO* in, int64_t ldin, TIO* out,
                int64_t ldout, hipStream_t st, const int* done) {
     ProfScope ps(h, 3, st);
-    if (h->lr_plain) {
+    if (h->ubr && std::is_same<T, float>::value) {
+        const int64_t tiles = (rows + 15) / 16;
+        hipLaunchKernelGGL((k_lr_expand_bf16<TIO>), dim3(grid_for(tiles, 4)), dim3(256), 0, st, rows, h->k, h->ukp,
+                           nrhs, h->ubr, h->ws.coef, beta, in, ldin, out, ldout, done);
+    } else if (h->lr_plain) {
         hipLaunchKernelGGL((k_lr_expand<T, TIO>), dim3(grid_for(rows)), dim3(256), 0, st, rows, h->k, nrhs, U,
                            h->ws.coef, beta, in, ldin, out, ldout, done);
     } else {
@@ -642,6 +652,21 @@ void dot_dev(ddlr_prec* h, int nrhs, const double* a, const double* b, int64_t l
                        W.part, done);
     LAUNCHCHK();
     hipLaunchKernelGGL(k_reduce_cols, dim3(nrhs), dim3(256), 0, st, kRedBlocks, nrhs, W.part, W.sums, done);
+    LAUNCHCHK();
+}
+
+// BF16 copies of U_k for the DDLR_FP32_UK_BF16 configuration
+void make_bf16_basis(ddlr_prec* h) {
+    if (h->precision != DDLR_FP32_UK_BF16 || !h->f64.U || h->k < 1) return;
+    const int64_t rows = h->urows;
+    const int k = h->k;
+    h->ukp = (k + 31) / 32 * 32;
+    h->uktiles = (k + 15) / 16;
+    const int64_t nb = (rows + 31) / 32;
+    h->ubt = h->lrmem.alloc<__bf16>((size_t)nb * h->uktiles * 512);
+    h->ubr = h->lrmem.alloc<__bf16>((size_t)rows * h->ukp);
+    hipLaunchKernelGGL(k_make_bf16, dim3(grid_for(nb * h->uktiles * 512 + rows * h->ukp)), dim3(256), 0, nullptr, rows,
+                       k, h->f64.U, h->ukp, h->uktiles, h->ubr, h->ubt);
     LAUNCHCHK();
 }
 
@@ -869,6 +894,7 @@ void lanczos_build(ddlr_prec* h, int k, int m_req, const double* v0_user, uint64
                            h->f64.U, (int64_t)0, h->f32.U, (int64_t)0, nullptr);
         LAUNCHCHK();
     }
+    make_bf16_basis(h);
     HIPCHK(hipDeviceSynchronize());
     tmp.release();
 }
@@ -1432,6 +1458,8 @@ ddlr_status ddlr_set_lowrank(ddlr_prec* h, int32_t variant, int32_t k, const dou
             for (size_t i = 0; i < f.size(); ++i) f[i] = (float)Ur[i];
             h->f32.U = h->lrmem.upload(f);
         }
+        h->ubr = h->ubt = nullptr;
+        make_bf16_basis(h);
         if (variant == 1) {
             h->lam.assign(aux, aux + k);
             h->theta = aux[k];

@@ -594,6 +594,144 @@ __global__ __launch_bounds__(256) void k_lr_expand_mfma(int64_t rows, int k, int
     }
 }
 
+// ------------------------------------- low-rank correction, BF16 U_k (gfx950)
+//
+// U_k stored in bfloat16 (rounded from the FP64 basis), products on the
+// 16x16x32 bf16 MFMA with FP32 accumulation.  Operand layout (measured on
+// gfx950): lane l, element e holds A[l%16][8(l/16)+e] and B[8(l/16)+e][l%16];
+// the FP32 result is laid out as for the 16x16x4 FP32 MFMA.  The vector
+// operand (y in the reduction, the coefficients in the expansion) is split
+// into a high and a low bf16 part and both are multiplied, so only U_k
+// carries bf16 rounding.
+typedef __bf16 mfma_bf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ mfma_f32x4 mfma_bf16(mfma_bf16x8 a, mfma_bf16x8 b, mfma_f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// Tiled copy for the reduction: Ut[(rb * ktiles + jt) * 512 + l * 8 + e] =
+// U[32 rb + 8 (l/16) + e][16 jt + l%16] (zero outside rows x k).  Row-major
+// copy for the expansion: Ur[i * kp + j] (kp = k rounded up to 32).
+__global__ void k_make_bf16(int64_t rows, int k, const double* __restrict__ U, int kp, int ktiles,
+                            __bf16* __restrict__ Ur, __bf16* __restrict__ Ut) {
+    const int64_t nb = (rows + 31) / 32;
+    const int64_t tot_t = nb * ktiles * 512, tot_r = rows * kp;
+    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < tot_t + tot_r;
+         g += (int64_t)gridDim.x * blockDim.x) {
+        if (g < tot_t) {
+            const int64_t blk = g / 512;
+            const int idx = (int)(g - blk * 512), l = idx / 8, e = idx % 8;
+            const int64_t rb = blk / ktiles;
+            const int jt = (int)(blk - rb * ktiles);
+            const int64_t i = rb * 32 + 8 * (l / 16) + e;
+            const int j = jt * 16 + l % 16;
+            Ut[g] = (__bf16)((i < rows && j < k) ? U[i * k + j] : 0.0);
+        } else {
+            const int64_t q = g - tot_t, i = q / kp;
+            const int j = (int)(q - i * kp);
+            Ur[q] = (__bf16)(j < k ? U[i * k + j] : 0.0);
+        }
+    }
+}
+
+template <typename TY>
+__global__ __launch_bounds__(256) void k_lr_reduce_bf16(int64_t rows, int k, int nrhs, const __bf16* __restrict__ Ut,
+                                                        const TY* __restrict__ y, int64_t ldy,
+                                                        double* __restrict__ part, const int* __restrict__ done) {
+    __shared__ double stage[4][64];
+    if (done && *done) return;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int ktiles = (k + 15) >> 4;
+    const int64_t nb = (rows + 31) / 32;
+    const int nwaves = gridDim.x * 4;
+    const int64_t gw = (int64_t)blockIdx.x * 4 + wv;
+    const int64_t per = (nb + nwaves - 1) / nwaves;
+    const int64_t b0 = gw * per, b1 = b0 + per < nb ? b0 + per : nb;
+    mfma_f32x4 acc[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) acc[t] = mfma_f32x4{0, 0, 0, 0};
+    const int n = lane & 15, kg = lane >> 4;
+    for (int64_t rb = b0; rb < b1; ++rb) {
+        mfma_bf16x8 yh, yl;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int64_t i = rb * 32 + 8 * kg + e;
+            const float v = (i < rows && n < nrhs) ? (float)y[i + n * ldy] : 0.f;
+            const __bf16 hi = (__bf16)v;
+            yh[e] = hi;
+            yl[e] = (__bf16)(v - (float)hi);
+        }
+        const __bf16* ub = Ut + (rb * ktiles) * 512 + lane * 8;
+#pragma unroll
+        for (int t = 0; t < 8; ++t)
+            if (t < ktiles) {
+                const mfma_bf16x8 a = *reinterpret_cast<const mfma_bf16x8*>(ub + t * 512);
+                acc[t] = mfma_bf16(a, yh, acc[t]);
+                acc[t] = mfma_bf16(a, yl, acc[t]);
+            }
+    }
+    for (int t = 0; t < ktiles; ++t) {
+        for (int v = 0; v < 4; ++v) {
+            stage[wv][lane] = (double)acc[t][v];
+            __syncthreads();
+            const int j = t * 16 + 4 * (lane >> 4) + v, rr = lane & 15;
+            if (wv == 0 && j < k && rr < nrhs)
+                part[((int64_t)blockIdx.x * nrhs + rr) * k + j] =
+                    (stage[0][lane] + stage[1][lane]) + (stage[2][lane] + stage[3][lane]);
+            __syncthreads();
+        }
+    }
+}
+
+template <typename TIO>
+__global__ __launch_bounds__(256) void k_lr_expand_bf16(int64_t rows, int k, int kp, int nrhs,
+                                                        const __bf16* __restrict__ Ur,
+                                                        const double* __restrict__ coef, double beta, const TIO* in,
+                                                        int64_t ldin, TIO* out, int64_t ldout,
+                                                        const int* __restrict__ done) {
+    __shared__ __bf16 ch[128 * 16], cl[128 * 16];  // coefficient hi / lo parts, [j][r]
+    if (done && *done) return;
+    for (int q = threadIdx.x; q < kp * 16; q += blockDim.x) {
+        const int j = q >> 4, rr = q & 15;
+        const float v = (j < k && rr < nrhs) ? (float)coef[rr * k + j] : 0.f;
+        const __bf16 hi = (__bf16)v;
+        ch[q] = hi;
+        cl[q] = (__bf16)(v - (float)hi);
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int m = lane & 15, kg = lane >> 4;
+    const int64_t ntiles = (rows + 15) >> 4;
+    for (int64_t tile = (int64_t)blockIdx.x * 4 + wv; tile < ntiles; tile += (int64_t)gridDim.x * 4) {
+        const int64_t i = tile * 16 + m;
+        mfma_f32x4 acc = mfma_f32x4{0, 0, 0, 0};
+        for (int k0 = 0; k0 < kp; k0 += 32) {
+            mfma_bf16x8 a;
+            if (i < rows) a = *reinterpret_cast<const mfma_bf16x8*>(Ur + i * kp + k0 + 8 * kg);
+            else
+#pragma unroll
+                for (int e = 0; e < 8; ++e) a[e] = (__bf16)0.f;
+            mfma_bf16x8 bh, bl;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                bh[e] = ch[(k0 + 8 * kg + e) * 16 + m];
+                bl[e] = cl[(k0 + 8 * kg + e) * 16 + m];
+            }
+            acc = mfma_bf16(a, bh, acc);
+            acc = mfma_bf16(a, bl, acc);
+        }
+        const int rr = lane & 15;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int64_t row = tile * 16 + 4 * kg + v;
+            if (row < rows && rr < nrhs) {
+                const double o = beta * (double)in[row + rr * ldin] + (double)acc[v];
+                out[row + rr * ldout] = (TIO)o;
+            }
+        }
+    }
+}
+
 // --------------------------------------------------------- dots and CG steps
 
 // part[block*nrhs + r] = sum over the block's rows of a_r . b_r

@@ -200,7 +200,24 @@ def test_fp32_apply_matches_oracle(variant, lr):
         assert rel(to_host(y), o.apply(x)) <= 1e-4
 
 
-@pytest.mark.parametrize("prec", [D.FP32])
+@pytest.mark.parametrize("variant", [1, 2])
+def test_bf16_basis_apply_matches_oracle(variant):
+    """FP32 preconditioner with U_k in bfloat16 on the bf16 MFMA: the operator
+    matches the FP64 oracle up to bf16 rounding of U_k (2^-9 relative)."""
+    cfg = irregular()
+    say("bf16 apply", variant)
+    h, o = setup_pair(cfg, variant=variant, precision=D.FP32_UK_BF16)
+    o.lowrank(variant, cfg["k"], cfg["m"], w.lanczos_start(cfg["A"].n, 0))
+    D.ddlr_set_lowrank(h, variant, *o.get_lowrank())
+    n = cfg["A"].n
+    for nrhs in (1, 7, 16):
+        x = np.random.default_rng(nrhs).standard_normal((n, nrhs))
+        y = torch.empty((nrhs, n), dtype=torch.float64, device=DEV)
+        D.ddlr_apply(h, to_dev(x), y)
+        assert rel(to_host(y), o.apply(x)) <= 5e-3
+
+
+@pytest.mark.parametrize("prec", [D.FP32, D.FP32_UK_BF16])
 def test_mixed_precision_solve(prec):
     cfg = w.config("small3d")
     say("mixed", prec)
