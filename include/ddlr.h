@@ -202,6 +202,33 @@ ddlr_status ddlr_profile_read(ddlr_prec *h, int32_t which, double *total_ms, int
 /* Releases everything the handle owns.  NULL is ignored. */
 void ddlr_destroy(ddlr_prec *h);
 
+/*
+ * Batches of independent systems.  The paper motivates reuse of a built
+ * preconditioner for many solves (Sec. 6); a batch solves many different
+ * systems at once: their device structures are concatenated so that every
+ * kernel (SpMV, the A0 solve, E / E^T) covers all systems in one launch,
+ * while dot products, CG scalars and the rank-k correction are per system.
+ * The iteration loop is captured once into a HIP graph and replayed.
+ *
+ * ddlr_batch_create: members are built device handles (same device and
+ * precision, variant DDLR_1 or DDLR_VARIANT_A0, FP64 or FP32); the batch copies
+ * what it needs, so members may be destroyed afterwards.  nsys <= 1024.
+ * Vectors of a batch are device arrays holding the systems' vectors one after
+ * the other, each in its own user order; ddlr_batch_offsets gives the nsys+1
+ * start offsets (host array).
+ */
+typedef struct ddlr_batch ddlr_batch;
+ddlr_status ddlr_batch_create(int32_t nsys, ddlr_prec *const *members, ddlr_batch **out);
+ddlr_status ddlr_batch_offsets(const ddlr_batch *b, int64_t *offsets);
+/* y = M_q^{-1} x_q for every system q. */
+ddlr_status ddlr_batch_apply(ddlr_batch *b, const double *x, double *y, void *stream);
+/* PCG on every system (x0 = 0, stopping rule of Sec. 5); info: host array of
+ * nsys entries.  Synchronises the stream.  DDLR_E_NO_CONVERGENCE if any system
+ * hit maxit (x and info written for all). */
+ddlr_status ddlr_batch_solve(ddlr_batch *b, const double *bvec, double *x, const ddlr_solve_options *opt,
+                             ddlr_solve_info *info, void *stream);
+void ddlr_batch_destroy(ddlr_batch *b);
+
 const char *ddlr_status_string(int32_t status);
 const char *ddlr_last_error(void);
 

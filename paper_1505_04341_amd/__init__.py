@@ -93,6 +93,11 @@ def load_library(path: str = LIB_PATH):
         "ddlr_set_lowrank": (I32, [P, I32, I32, P, P]),
         "ddlr_profile": (I32, [P, I32]),
         "ddlr_profile_read": (I32, [P, I32, P, P]),
+        "ddlr_batch_create": (I32, [I32, P, P]),
+        "ddlr_batch_offsets": (I32, [P, P]),
+        "ddlr_batch_apply": (I32, [P, P, P, P]),
+        "ddlr_batch_solve": (I32, [P, P, P, P, P, P]),
+        "ddlr_batch_destroy": (None, [P]),
         "ddlr_destroy": (None, [P]),
         "ddlr_status_string": (C.c_char_p, [I32]),
         "ddlr_last_error": (C.c_char_p, []),
@@ -293,6 +298,58 @@ def ddlr_set_lowrank(prec: Prec, variant: int, U, lam_or_H, theta: float = 0.0):
     _check(lib.ddlr_set_lowrank(prec.handle, int(variant), int(k), _ptr(U), _ptr(aux)), "ddlr_set_lowrank")
 
 
+class Batch:
+    """Handle of a batch of independent systems (ddlr_batch*)."""
+
+    def __init__(self, handle: int, offsets: np.ndarray):
+        self._h = C.c_void_p(handle)
+        self.offsets = offsets
+        self.n = int(offsets[-1])
+        self.nsys = len(offsets) - 1
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.ddlr_batch_destroy(self._h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+
+def ddlr_batch_create(members) -> Batch:
+    """Merges built preconditioners of independent systems into one batch."""
+    lib = load_library()
+    arr = (C.c_void_p * len(members))(*[m.handle.value for m in members])
+    h = C.c_void_p()
+    _check(lib.ddlr_batch_create(len(members), arr, C.byref(h)), "ddlr_batch_create")
+    off = np.zeros(len(members) + 1, np.int64)
+    _check(lib.ddlr_batch_offsets(h, _ptr(off)), "ddlr_batch_offsets")
+    return Batch(h.value, off)
+
+
+def ddlr_batch_apply(batch: Batch, x, y, stream=None):
+    xp, _, _ = _dev_cols(x, batch.n)
+    yp, _, _ = _dev_cols(y, batch.n)
+    _check(load_library().ddlr_batch_apply(batch.handle, xp, yp, _stream(stream)), "ddlr_batch_apply")
+    return y
+
+
+def ddlr_batch_solve(batch: Batch, b, x, *, maxit: int = 500, rtol: float = 1e-6, stream=None):
+    """PCG on every system; returns (status, list of per-system info dicts)."""
+    lib = load_library()
+    bp, _, _ = _dev_cols(b, batch.n)
+    xp, _, _ = _dev_cols(x, batch.n)
+    opt = ddlr_solve_options()
+    lib.ddlr_solve_options_default(C.byref(opt))
+    opt.maxit, opt.rtol = int(maxit), float(rtol)
+    infos = (ddlr_solve_info * batch.nsys)()
+    st = lib.ddlr_batch_solve(batch.handle, bp, xp, C.byref(opt), infos, _stream(stream))
+    if st not in (OK, E_NO_CONVERGENCE):
+        _check(st, "ddlr_batch_solve")
+    return st, [dict(iters=i.iters, status=i.status, relres=i.relres, relres_true=i.relres_true) for i in infos]
+
+
 PROF_TRSV_BLOCKS, PROF_TRSV_LEVELS, PROF_SPMV, PROF_LOWRANK = 0, 1, 2, 3
 
 
@@ -316,5 +373,6 @@ def ddlr_version() -> int:
 EXPORTED = ["ddlr_version", "ddlr_options_default", "ddlr_solve_options_default", "ddlr_setup", "ddlr_apply",
             "ddlr_a0_solve", "ddlr_spmv", "ddlr_solve", "ddlr_query", "ddlr_get_ordering", "ddlr_get_factor",
             "ddlr_get_levels", "ddlr_get_lanczos", "ddlr_get_lowrank", "ddlr_set_lowrank", "ddlr_profile",
-            "ddlr_profile_read", "ddlr_destroy",
+            "ddlr_profile_read", "ddlr_batch_create", "ddlr_batch_offsets", "ddlr_batch_apply",
+            "ddlr_batch_solve", "ddlr_batch_destroy", "ddlr_destroy",
             "ddlr_status_string", "ddlr_last_error"]

@@ -129,6 +129,13 @@ struct ddlr_prec {
     DevFactors<double> f64;
     DevFactors<float> f32;
     int64_t urows = 0;      // rows of U (s for DDLR-1, n for DDLR-2)
+    int64_t ndev = 0, sdev = 0;  // device-order rows and interface positions (all systems of a batch)
+    // batch of independent systems (nsys > 1): per-system row / interface offsets,
+    // low-rank scalars; the CG lanes are the systems
+    int nsys = 1;
+    int64_t *seg_roff = nullptr, *seg_soff = nullptr;
+    double *c0s = nullptr, *dvecs = nullptr;
+    bool capturing = false;
     __bf16 *ubr = nullptr, *ubt = nullptr;  // BF16 U_k: row-major (k padded to 32) and reduction tiles
     int ukp = 0, uktiles = 0;
     double *dvec = nullptr, *Hk = nullptr;
@@ -146,26 +153,201 @@ namespace {
 
 constexpr int kRing64 = 8192, kRing32 = 16384;  // LDS ring rows: 64 KB either way
 
+// Device-order arrays of one preconditioner (or of several merged), built on
+// the host before upload.
+struct DevHost {
+    int64_t n = 0, s = 0;
+    std::vector<int32_t> perm_dev;  // device position -> user row
+    std::vector<int64_t> arp;       // A in device order (CSR)
+    std::vector<int32_t> aci;
+    std::vector<double> av;
+    std::vector<int32_t> lrp, lci, urp, uci;  // L (forward) and L^T (backward)
+    std::vector<double> lv, uv, dinv;
+    std::vector<int32_t> lvl_ptr, lvl_row0;  // level row starts; first row of each level's block
+    std::vector<BlockDesc> narrow;           // level ranges of the blocks solved one workgroup each
+    std::vector<std::pair<int, int>> wide;   // rows of the interface levels launched one by one
+    std::vector<int32_t> erp, eci, etrp, etci;
+    std::vector<double> ev, etv;
+};
+
+// c_mode: -1 choose (few, wide interface levels -> level launches), 0 interface
+// block as one narrow block, 1 interface levels launched one by one
+DevHost build_devhost(const HostPlan& P, int c_mode) {
+    DevHost D;
+    const int64_t n = P.n, m = P.m, s = P.s;
+    D.n = n;
+    D.s = s;
+    D.perm_dev.resize(n);
+    for (int64_t d = 0; d < n; ++d) D.perm_dev[d] = P.perm[P.dev2int[d]];
+    D.arp.assign(n + 1, 0);
+    D.aci.reserve(P.A.nnz());
+    D.av.reserve(P.A.nnz());
+    for (int64_t d = 0; d < n; ++d) {
+        const int64_t i = P.dev2int[d];
+        for (int64_t t = P.A.rp[i]; t < P.A.rp[i + 1]; ++t) {
+            D.aci.push_back(P.int2dev[P.A.ci[t]]);
+            D.av.push_back(P.A.v[t]);
+        }
+        D.arp[d + 1] = (int64_t)D.aci.size();
+    }
+    if (P.L.nnz() > INT32_MAX) throw SetupError{DDLR_E_INVALID, "nnz(L) must fit in int32"};
+    D.lrp.assign(n + 1, 0);
+    D.lci.resize(P.L.nnz());
+    D.lv.resize(P.L.nnz());
+    for (int64_t d = 0; d < n; ++d) {
+        const int64_t i = P.dev2int[d];
+        int32_t q = D.lrp[d];
+        for (int64_t t = P.L.rp[i]; t < P.L.rp[i + 1]; ++t, ++q) {
+            D.lci[q] = P.int2dev[P.L.ci[t]];
+            D.lv[q] = P.L.v[t];
+        }
+        D.lrp[d + 1] = q;
+    }
+    D.urp.assign(n + 1, 0);
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t t = P.L.rp[i]; t < P.L.rp[i + 1]; ++t) D.urp[P.int2dev[P.L.ci[t]] + 1]++;
+    for (int64_t d = 0; d < n; ++d) D.urp[d + 1] += D.urp[d];
+    D.uci.resize(P.L.nnz());
+    D.uv.resize(P.L.nnz());
+    std::vector<int32_t> fill(D.urp.begin(), D.urp.end() - 1);
+    for (int64_t i = 0; i < n; ++i)  // ascending internal row j of L_ji -> ascending order in each L^T row
+        for (int64_t t = P.L.rp[i]; t < P.L.rp[i + 1]; ++t) {
+            const int32_t q = fill[P.int2dev[P.L.ci[t]]]++;
+            D.uci[q] = P.int2dev[i];
+            D.uv[q] = P.L.v[t];
+        }
+    D.dinv.resize(n);
+    for (int64_t d = 0; d < n; ++d) D.dinv[d] = 1.0 / P.D[P.dev2int[d]];
+    D.lvl_ptr = P.lvl_ptr;
+    const int nlev = (int)P.lvl_ptr.size() - 1;
+    D.lvl_row0.assign(nlev, 0);
+    for (int32_t b = 0; b <= P.p; ++b)
+        for (int32_t l = P.blk_lvl[b]; l < P.blk_lvl[b + 1]; ++l) D.lvl_row0[l] = (int32_t)P.boff[b];
+    // E (n x s) and E^T (s x n)
+    const double ia = 1.0 / P.alpha;
+    D.erp.assign(n + 1, 0);
+    for (int64_t d = 0; d < n; ++d) {
+        const int64_t i = P.dev2int[d];
+        if (i < m) {
+            for (int64_t t = P.A.rp[i]; t < P.A.rp[i + 1]; ++t)
+                if (P.A.ci[t] >= m) {
+                    D.eci.push_back(P.int2dev[P.A.ci[t]] - (int32_t)m);
+                    D.ev.push_back(ia * P.A.v[t]);
+                }
+        } else {
+            D.eci.push_back((int32_t)(d - m));
+            D.ev.push_back(-P.alpha);
+        }
+        D.erp[d + 1] = (int32_t)D.eci.size();
+    }
+    D.etrp.assign(s + 1, 0);
+    D.etci.resize(D.eci.size());
+    D.etv.resize(D.eci.size());
+    for (size_t t = 0; t < D.eci.size(); ++t) D.etrp[D.eci[t] + 1]++;
+    for (int64_t j = 0; j < s; ++j) D.etrp[j + 1] += D.etrp[j];
+    std::vector<int32_t> efill(D.etrp.begin(), D.etrp.end() - 1);
+    for (int64_t d = 0; d < n; ++d)
+        for (int32_t t = D.erp[d]; t < D.erp[d + 1]; ++t) {
+            const int32_t q = efill[D.eci[t]]++;
+            D.etci[q] = (int32_t)d;
+            D.etv[q] = D.ev[t];
+        }
+    // schedule: B blocks are narrow; the interface block is wide when its
+    // levels are few and wide
+    const int32_t p = P.p;
+    const int32_t c_lv0 = P.blk_lvl[p], c_lv1 = P.blk_lvl[p + 1];
+    const int32_t c_levels = c_lv1 - c_lv0;
+    bool c_wide = c_levels > 0 && c_levels <= 64 && s / std::max(1, c_levels) >= 2048;
+    if (const char* env = std::getenv("DDLR_C_WIDE")) {  // "1" forces level launches, "0" one workgroup
+        if (env[0] == '1') c_wide = c_levels > 0;
+        if (env[0] == '0') c_wide = false;
+    }
+    if (c_mode == 0) c_wide = false;
+    if (c_mode == 1) c_wide = c_levels > 0;
+    for (int32_t b = 0; b < p; ++b)
+        if (P.blk_lvl[b + 1] > P.blk_lvl[b]) D.narrow.push_back({P.blk_lvl[b], P.blk_lvl[b + 1]});
+    if (c_wide) {
+        for (int32_t l = c_lv0; l < c_lv1; ++l) D.wide.emplace_back(P.lvl_ptr[l], P.lvl_ptr[l + 1]);
+    } else if (c_levels > 0) {
+        D.narrow.push_back({c_lv0, c_lv1});
+    }
+    return D;
+}
+
+// Concatenates several systems: rows, interface positions and levels are
+// offset by the sizes of the systems before.
+void merge_devhost(const std::vector<const DevHost*>& parts, DevHost& out) {
+    out = DevHost();
+    int64_t R = 0, S = 0;
+    int32_t Lv = 0;
+    out.arp.push_back(0);
+    out.lrp.push_back(0);
+    out.urp.push_back(0);
+    out.erp.push_back(0);
+    out.etrp.push_back(0);
+    for (const DevHost* P : parts) {
+        for (int32_t v : P->perm_dev) out.perm_dev.push_back((int32_t)(v + R));
+        for (int64_t d = 0; d < P->n; ++d) {
+            for (int64_t t = P->arp[d]; t < P->arp[d + 1]; ++t) {
+                out.aci.push_back((int32_t)(P->aci[t] + R));
+                out.av.push_back(P->av[t]);
+            }
+            out.arp.push_back((int64_t)out.aci.size());
+            for (int32_t t = P->lrp[d]; t < P->lrp[d + 1]; ++t) {
+                out.lci.push_back((int32_t)(P->lci[t] + R));
+                out.lv.push_back(P->lv[t]);
+            }
+            out.lrp.push_back((int32_t)out.lci.size());
+            for (int32_t t = P->urp[d]; t < P->urp[d + 1]; ++t) {
+                out.uci.push_back((int32_t)(P->uci[t] + R));
+                out.uv.push_back(P->uv[t]);
+            }
+            out.urp.push_back((int32_t)out.uci.size());
+            for (int32_t t = P->erp[d]; t < P->erp[d + 1]; ++t) {
+                out.eci.push_back((int32_t)(P->eci[t] + S));
+                out.ev.push_back(P->ev[t]);
+            }
+            out.erp.push_back((int32_t)out.eci.size());
+            out.dinv.push_back(P->dinv[d]);
+        }
+        for (int64_t j = 0; j < P->s; ++j) {
+            for (int32_t t = P->etrp[j]; t < P->etrp[j + 1]; ++t) {
+                out.etci.push_back((int32_t)(P->etci[t] + R));
+                out.etv.push_back(P->etv[t]);
+            }
+            out.etrp.push_back((int32_t)out.etci.size());
+        }
+        const int nl = (int)P->lvl_ptr.size() - 1;
+        for (int l = 0; l < nl; ++l) {
+            out.lvl_ptr.push_back((int32_t)(P->lvl_ptr[l] + R));
+            out.lvl_row0.push_back((int32_t)(P->lvl_row0[l] + R));
+        }
+        for (const BlockDesc& b : P->narrow) out.narrow.push_back({b.lvl0 + Lv, b.lvl1 + Lv});
+        for (const auto& wv : P->wide) out.wide.emplace_back((int)(wv.first + R), (int)(wv.second + R));
+        R += P->n;
+        S += P->s;
+        Lv += nl;
+    }
+    out.lvl_ptr.push_back((int32_t)R);
+    out.n = R;
+    out.s = S;
+}
+
 // Per-level ELL copies of L (forward) and L^T (backward) for the ring kernel,
 // fixed width KW for every level, block-local column indices, and the check
 // that every dependency falls inside the LDS window of the most recent kRing
 // rows.
-void build_ring(ddlr_prec* h, const std::vector<BlockDesc>& bd, const std::vector<int32_t>& lrp,
-                const std::vector<int32_t>& lci, const std::vector<double>& lv, const std::vector<int32_t>& urp,
-                const std::vector<int32_t>& uci, const std::vector<double>& uv) {
-    const HostPlan& P = h->plan;
-    const int nlev = (int)P.lvl_ptr.size() - 1;
-    std::vector<int32_t> lvl_row0(nlev, 0);
-    for (int32_t b = 0; b <= P.p; ++b)
-        for (int32_t l = P.blk_lvl[b]; l < P.blk_lvl[b + 1]; ++l) lvl_row0[l] = (int32_t)P.boff[b];
-    // width and window checks over the narrow blocks
+void build_ring(ddlr_prec* h, const DevHost& D) {
+    const std::vector<BlockDesc>& bd = D.narrow;
+    const std::vector<int32_t>&lrp = D.lrp, &lci = D.lci, &urp = D.urp, &uci = D.uci;
+    const int nlev = (int)D.lvl_ptr.size() - 1;
     int kw = 0;
     bool ok64 = true, ok32 = true;
     for (const BlockDesc& b : bd) {
         if (b.lvl1 - b.lvl0 > kRingMaxLevels) ok64 = ok32 = false;
         for (int l = b.lvl0; l < b.lvl1; ++l) {
-            const int row0 = lvl_row0[l];
-            const int a = P.lvl_ptr[l] - row0, e = P.lvl_ptr[l + 1] - row0;
+            const int row0 = D.lvl_row0[l];
+            const int a = D.lvl_ptr[l] - row0, e = D.lvl_ptr[l + 1] - row0;
             for (int i = a; i < e; ++i) {
                 kw = std::max({kw, lrp[row0 + i + 1] - lrp[row0 + i], urp[row0 + i + 1] - urp[row0 + i]});
                 for (int t = lrp[row0 + i]; t < lrp[row0 + i + 1]; ++t) {
@@ -193,23 +375,23 @@ void build_ring(ddlr_prec* h, const std::vector<BlockDesc>& bd, const std::vecto
     auto build = [&](const std::vector<int32_t>& rp, const std::vector<int32_t>& ci, const std::vector<double>& v,
                      std::vector<int32_t>& off, std::vector<int32_t>& col, std::vector<double>& val) {
         for (int l = 0; l < nlev; ++l) {
-            const int a = P.lvl_ptr[l], e = P.lvl_ptr[l + 1], nr = e - a;
+            const int a = D.lvl_ptr[l], e = D.lvl_ptr[l + 1], nr = e - a;
             off[l] = (int32_t)col.size();
             col.resize(col.size() + (size_t)KW * nr, 0);  // padding: column 0, value 0
             val.resize(val.size() + (size_t)KW * nr, 0.0);
             for (int i = a; i < e; ++i) {
                 const int t0 = rp[i], t1 = std::min(rp[i + 1], rp[i] + KW);
                 for (int t = t0, j = 0; t < t1; ++t, ++j) {
-                    col[off[l] + (size_t)j * nr + (i - a)] = ci[t] - lvl_row0[l];
+                    col[off[l] + (size_t)j * nr + (i - a)] = ci[t] - D.lvl_row0[l];
                     val[off[l] + (size_t)j * nr + (i - a)] = v[t];
                 }
             }
         }
     };
-    build(lrp, lci, lv, foff, fcol, fval);
-    build(urp, uci, uv, boff, bcol, bval);
+    build(lrp, lci, D.lv, foff, fcol, fval);
+    build(urp, uci, D.uv, boff, bcol, bval);
     std::vector<RingBlock> rb;
-    for (const BlockDesc& b : bd) rb.push_back({b.lvl0, b.lvl1, lvl_row0[b.lvl0], 0});
+    for (const BlockDesc& b : bd) rb.push_back({b.lvl0, b.lvl1, D.lvl_row0[b.lvl0], 0});
     DMem& M = h->mem;
     h->rblk = M.upload(rb);
     h->foff = M.upload(foff);
@@ -225,24 +407,21 @@ void build_ring(ddlr_prec* h, const std::vector<BlockDesc>& bd, const std::vecto
     }
 }
 
-void upload_structures(ddlr_prec* h) {
-    HostPlan& P = h->plan;
-    const int64_t n = P.n, m = P.m, s = P.s;
+// Uploads the device-order arrays and builds SELL-64 for A.
+void upload_devhost(ddlr_prec* h, const DevHost& D) {
     DMem& M = h->mem;
-    // permutation device -> user
-    std::vector<int32_t> pd(n);
-    for (int64_t d = 0; d < n; ++d) pd[d] = P.perm[P.dev2int[d]];
-    h->perm_dev = M.upload(pd);
-    // A in SELL-64, device order
+    const int64_t n = D.n;
+    h->ndev = n;
+    h->sdev = D.s;
+    h->perm_dev = M.upload(D.perm_dev);
     h->nslices = (n + kSell - 1) / kSell;
     std::vector<int32_t> sptr(h->nslices + 1, 0);
     for (int64_t sl = 0; sl < h->nslices; ++sl) {
-        int w = 0;
-        for (int64_t d = sl * kSell; d < std::min<int64_t>(n, (sl + 1) * kSell); ++d) {
-            int64_t i = P.dev2int[d];
-            w = std::max<int>(w, (int)(P.A.rp[i + 1] - P.A.rp[i]));
-        }
-        sptr[sl + 1] = sptr[sl] + w * kSell;
+        int64_t w = 0;
+        for (int64_t d = sl * kSell; d < std::min<int64_t>(n, (sl + 1) * kSell); ++d)
+            w = std::max<int64_t>(w, D.arp[d + 1] - D.arp[d]);
+        if ((int64_t)sptr[sl] + w * kSell > INT32_MAX) throw SetupError{DDLR_E_INVALID, "A too large for SELL-64"};
+        sptr[sl + 1] = sptr[sl] + (int32_t)(w * kSell);
     }
     h->sell_nnz = sptr[h->nslices];
     std::vector<int32_t> scol(h->sell_nnz);
@@ -251,16 +430,12 @@ void upload_structures(ddlr_prec* h) {
         const int w = (sptr[sl + 1] - sptr[sl]) / kSell;
         for (int lane = 0; lane < kSell; ++lane) {
             const int64_t d = sl * kSell + lane;
-            int64_t cnt = 0, i = -1;
-            if (d < n) {
-                i = P.dev2int[d];
-                cnt = P.A.rp[i + 1] - P.A.rp[i];
-            }
+            const int64_t cnt = d < n ? D.arp[d + 1] - D.arp[d] : 0;
             for (int j = 0; j < w; ++j) {
                 const int64_t q = sptr[sl] + (int64_t)j * kSell + lane;
                 if (j < cnt) {
-                    scol[q] = P.int2dev[P.A.ci[P.A.rp[i] + j]];
-                    sval[q] = P.A.v[P.A.rp[i] + j];
+                    scol[q] = D.aci[D.arp[d] + j];
+                    sval[q] = D.av[D.arp[d] + j];
                 } else {
                     scol[q] = (int32_t)std::min<int64_t>(d, n - 1);
                     sval[q] = 0.0;
@@ -271,117 +446,45 @@ void upload_structures(ddlr_prec* h) {
     h->sell_ptr = M.upload(sptr);
     h->sell_col = M.upload(scol);
     h->sell_val = M.upload(sval);
-    // forward factor L and backward factor L^T, device order
-    if (P.L.nnz() > INT32_MAX) throw SetupError{DDLR_E_INVALID, "nnz(L) must fit in int32"};
-    std::vector<int32_t> lrp(n + 1, 0), lci(P.L.nnz());
-    std::vector<double> lv(P.L.nnz());
-    for (int64_t d = 0; d < n; ++d) {
-        const int64_t i = P.dev2int[d];
-        int32_t q = lrp[d];
-        for (int64_t t = P.L.rp[i]; t < P.L.rp[i + 1]; ++t, ++q) {
-            lci[q] = P.int2dev[P.L.ci[t]];
-            lv[q] = P.L.v[t];
-        }
-        lrp[d + 1] = q;
-    }
-    std::vector<int32_t> ucount(n + 1, 0);
-    for (int64_t i = 0; i < n; ++i)
-        for (int64_t t = P.L.rp[i]; t < P.L.rp[i + 1]; ++t) ucount[P.int2dev[P.L.ci[t]] + 1]++;
-    for (int64_t d = 0; d < n; ++d) ucount[d + 1] += ucount[d];
-    std::vector<int32_t> urp(ucount), uci(P.L.nnz()), fill(ucount.begin(), ucount.end() - 1);
-    std::vector<double> uv(P.L.nnz());
-    for (int64_t i = 0; i < n; ++i)  // ascending internal row j of L_ji -> ascending order in each L^T row
-        for (int64_t t = P.L.rp[i]; t < P.L.rp[i + 1]; ++t) {
-            const int32_t dcol = P.int2dev[P.L.ci[t]];
-            const int32_t q = fill[dcol]++;
-            uci[q] = P.int2dev[i];
-            uv[q] = P.L.v[t];
-        }
-    std::vector<double> dinv(n);
-    for (int64_t d = 0; d < n; ++d) dinv[d] = 1.0 / P.D[P.dev2int[d]];
-    h->lrp = M.upload(lrp);
-    h->lci = M.upload(lci);
-    h->urp = M.upload(urp);
-    h->uci = M.upload(uci);
-    h->f64.lv = M.upload(lv);
-    h->f64.uv = M.upload(uv);
-    h->f64.dinv = M.upload(dinv);
-    h->lvl_ptr = M.upload(P.lvl_ptr);
-    // E (n x s) and E^T (s x n) in device order
-    const double ia = 1.0 / P.alpha;
-    std::vector<int32_t> erp(n + 1, 0), eci;
-    std::vector<double> ev;
-    for (int64_t d = 0; d < n; ++d) {
-        const int64_t i = P.dev2int[d];
-        if (i < m) {
-            for (int64_t t = P.A.rp[i]; t < P.A.rp[i + 1]; ++t)
-                if (P.A.ci[t] >= m) {
-                    eci.push_back(P.int2dev[P.A.ci[t]] - (int32_t)m);
-                    ev.push_back(ia * P.A.v[t]);
-                }
-        } else {
-            eci.push_back((int32_t)(d - m));
-            ev.push_back(-P.alpha);
-        }
-        erp[d + 1] = (int32_t)eci.size();
-    }
-    std::vector<int32_t> etrp(s + 1, 0), etci(eci.size());
-    std::vector<double> etv(eci.size());
-    for (size_t t = 0; t < eci.size(); ++t) etrp[eci[t] + 1]++;
-    for (int64_t j = 0; j < s; ++j) etrp[j + 1] += etrp[j];
-    std::vector<int32_t> efill(etrp.begin(), etrp.end() - 1);
-    for (int64_t d = 0; d < n; ++d)
-        for (int32_t t = erp[d]; t < erp[d + 1]; ++t) {
-            const int32_t q = efill[eci[t]]++;
-            etci[q] = (int32_t)d;
-            etv[q] = ev[t];
-        }
-    h->erp = M.upload(erp);
-    h->eci = M.upload(eci);
-    h->etrp = M.upload(etrp);
-    h->etci = M.upload(etci);
-    h->f64.ev = M.upload(ev);
-    h->f64.etv = M.upload(etv);
+    h->lrp = M.upload(D.lrp);
+    h->lci = M.upload(D.lci);
+    h->urp = M.upload(D.urp);
+    h->uci = M.upload(D.uci);
+    h->f64.lv = M.upload(D.lv);
+    h->f64.uv = M.upload(D.uv);
+    h->f64.dinv = M.upload(D.dinv);
+    h->lvl_ptr = M.upload(D.lvl_ptr);
+    h->erp = M.upload(D.erp);
+    h->eci = M.upload(D.eci);
+    h->etrp = M.upload(D.etrp);
+    h->etci = M.upload(D.etci);
+    h->f64.ev = M.upload(D.ev);
+    h->f64.etv = M.upload(D.etv);
     if (h->precision != DDLR_FP64) {
         auto demote = [&](const std::vector<double>& a) {
             std::vector<float> f(a.size());
             for (size_t i = 0; i < a.size(); ++i) f[i] = (float)a[i];
             return M.upload(f);
         };
-        h->f32.lv = demote(lv);
-        h->f32.uv = demote(uv);
-        h->f32.dinv = demote(dinv);
-        h->f32.ev = demote(ev);
-        h->f32.etv = demote(etv);
+        h->f32.lv = demote(D.lv);
+        h->f32.uv = demote(D.uv);
+        h->f32.dinv = demote(D.dinv);
+        h->f32.ev = demote(D.ev);
+        h->f32.etv = demote(D.etv);
     }
-    // schedule: B blocks are narrow (one workgroup per block and rhs); the
-    // interface block is wide when its levels are few and wide.
-    const int32_t p = P.p;
-    const int32_t c_lv0 = P.blk_lvl[p], c_lv1 = P.blk_lvl[p + 1];
-    const int32_t c_levels = c_lv1 - c_lv0;
-    bool c_wide = c_levels > 0 && c_levels <= 64 && s / std::max(1, c_levels) >= 2048;
-    if (const char* env = std::getenv("DDLR_C_WIDE")) {  // "1" forces level launches, "0" one workgroup
-        if (env[0] == '1') c_wide = c_levels > 0;
-        if (env[0] == '0') c_wide = false;
-    }
-    std::vector<BlockDesc> bd;
-    for (int32_t b = 0; b < p; ++b)
-        if (P.blk_lvl[b + 1] > P.blk_lvl[b]) bd.push_back({P.blk_lvl[b], P.blk_lvl[b + 1]});
-    h->wide.clear();
-    if (c_wide) {
-        for (int32_t l = c_lv0; l < c_lv1; ++l) h->wide.emplace_back(P.lvl_ptr[l], P.lvl_ptr[l + 1]);
-    } else {
-        bd.push_back({c_lv0, c_lv1});
-    }
-    h->nnarrow = (int)bd.size();
+    h->wide = D.wide;
+    h->nnarrow = (int)D.narrow.size();
     h->nnarrow_pad = (h->nnarrow + 7) / 8 * 8;
-    h->blk = M.upload(bd);
-    build_ring(h, bd, lrp, lci, lv, urp, uci, uv);
+    h->blk = M.upload(D.narrow);
+    build_ring(h, D);
 }
+
+void upload_structures(ddlr_prec* h, int c_mode = -1) { upload_devhost(h, build_devhost(h->plan, c_mode)); }
 
 // ------------------------------------------------------------ workspace
 
 constexpr int kLrBlocks = 1024;  // grid of the low-rank reduction
+constexpr int kSegChunks = 16;   // blocks per system in the per-system kernels of a batch
 
 template <typename T> T* wsalloc(Workspace& W, size_t count) { return W.mem.alloc<T>(count); }
 
@@ -395,7 +498,7 @@ void ensure_ws(ddlr_prec* h, int nrhs) {
         (void)hipHostFree(W.done_host);
         W.done_host = nullptr;
     }
-    const int64_t n = h->plan.n, s = h->plan.s;
+    const int64_t n = h->ndev, s = h->sdev;
     const size_t tsz = h->precision == DDLR_FP64 ? sizeof(double) : sizeof(float);
     W.x = W.mem.alloc<double>(n * nrhs);
     W.r = W.mem.alloc<double>(n * nrhs);
@@ -410,12 +513,12 @@ void ensure_ws(ddlr_prec* h, int nrhs) {
     W.ws = W.mem.alloc<char>(tsz * s * nrhs);
     const int kk = std::max(1, h->k);
     const int64_t parts = std::max({(int64_t)kRedBlocks * nrhs, ((n + 255) / 256) * (int64_t)nrhs,
-                                    (int64_t)kLrBlocks * nrhs * kk});
+                                    (int64_t)kLrBlocks * nrhs * kk, (int64_t)kSegChunks * h->nsys});
     W.part = W.mem.alloc<double>(parts);
-    W.sums = W.mem.alloc<double>(std::max(nrhs, 1) * 256);
-    W.coef = W.mem.alloc<double>((size_t)std::max(nrhs, 1) * kk);
+    W.sums = W.mem.alloc<double>((size_t)std::max(nrhs, h->nsys) * 256);
+    W.coef = W.mem.alloc<double>((size_t)std::max(nrhs, h->nsys) * kk);
     W.lrsum = W.mem.alloc<double>((size_t)std::max(nrhs, 1) * kk);
-    W.lanes = W.mem.alloc<CgLane>(std::max(nrhs, 1));
+    W.lanes = W.mem.alloc<CgLane>(std::max(nrhs, h->nsys));
     W.done = W.mem.alloc<int>(1);
     HIPCHK(hipHostMalloc((void**)&W.done_host, sizeof(int)));
     W.nrhs = nrhs;
@@ -440,7 +543,7 @@ struct ProfScope {
     hipStream_t st;
     hipEvent_t e0 = nullptr;
     ProfScope(ddlr_prec* h_, int cls_, hipStream_t st_) : h(h_), cls(cls_), st(st_) {
-        if (h->prof) {
+        if (h->prof && !h->capturing) {
             e0 = prof_event(h);
             HIPCHK(hipEventRecord(e0, st));
         }
@@ -604,7 +707,7 @@ void apply_dev_T(ddlr_prec* h, int nrhs, const double* in, int64_t ldin, double*
                  const int* done) {
     const DevFactors<T>& F = factors<T>(h);
     Workspace& W = h->ws;
-    const int64_t n = h->plan.n, s = h->plan.s;
+    const int64_t n = h->ndev, s = h->sdev;
     if (h->variant == DDLR_1) {
         T* a1 = (T*)W.a1;
         T* a2 = (T*)W.a2;
@@ -614,8 +717,18 @@ void apply_dev_T(ddlr_prec* h, int nrhs, const double* in, int64_t ldin, double*
         hipLaunchKernelGGL((k_csr_mv<T, T>), dim3(grid_for(s * nrhs)), dim3(256), 0, st, s, nrhs, h->etrp, h->etci,
                            F.etv, a1, n, (const T*)nullptr, 0, ys, s, done);  // step 2: y = E^T z
         LAUNCHCHK();
-        lr_coef<T, T>(h, F.U, s, nrhs, ys, s, 1, st, done);  // step 3: w = G_{k,theta}^{-1} y (eq. gkt)
-        lr_expand<T, T>(h, F.U, s, nrhs, h->c0, ys, s, wsv, s, st, done);
+        if (h->nsys > 1) {  // per system of a batch (one column)
+            ProfScope ps(h, 3, st);
+            hipLaunchKernelGGL(k_seg_lr_coef<T>, dim3(h->nsys), dim3(256), 0, st, h->seg_soff, h->k, F.U, ys, h->dvecs,
+                               W.coef, done);
+            LAUNCHCHK();
+            hipLaunchKernelGGL(k_seg_lr_expand<T>, dim3(kSegChunks, h->nsys), dim3(256), 0, st, h->seg_soff, h->k, F.U,
+                               W.coef, h->c0s, ys, wsv, done);
+            LAUNCHCHK();
+        } else {
+            lr_coef<T, T>(h, F.U, s, nrhs, ys, s, 1, st, done);  // step 3: w = G_{k,theta}^{-1} y (eq. gkt)
+            lr_expand<T, T>(h, F.U, s, nrhs, h->c0, ys, s, wsv, s, st, done);
+        }
         hipLaunchKernelGGL((k_csr_mv<T, double>), dim3(grid_for(n * nrhs)), dim3(256), 0, st, n, nrhs, h->erp, h->eci,
                            F.ev, wsv, s, in, ldin, a2, n, done);  // step 4: v = E w, fused x + v
         LAUNCHCHK();
@@ -638,7 +751,7 @@ void apply_dev(ddlr_prec* h, int nrhs, const double* in, int64_t ldin, double* o
 
 void spmv_dev(ddlr_prec* h, int nrhs, const double* x, int64_t ldx, double* y, int64_t ldy, double* part,
               hipStream_t st, const int* done) {
-    const int64_t n = h->plan.n;
+    const int64_t n = h->ndev;
     ProfScope ps(h, 2, st);
     hipLaunchKernelGGL(k_spmv_sell, dim3((n + 255) / 256), dim3(256), 0, st, n, nrhs, h->sell_ptr, h->sell_col,
                        h->sell_val, x, ldx, y, ldy, part, done);
@@ -648,7 +761,7 @@ void spmv_dev(ddlr_prec* h, int nrhs, const double* x, int64_t ldx, double* y, i
 // sums[r] = a_r . b_r
 void dot_dev(ddlr_prec* h, int nrhs, const double* a, const double* b, int64_t ld, hipStream_t st, const int* done) {
     Workspace& W = h->ws;
-    hipLaunchKernelGGL((k_dot<double, double>), dim3(kRedBlocks), dim3(256), 0, st, h->plan.n, nrhs, a, ld, b, ld,
+    hipLaunchKernelGGL((k_dot<double, double>), dim3(kRedBlocks), dim3(256), 0, st, h->ndev, nrhs, a, ld, b, ld,
                        W.part, done);
     LAUNCHCHK();
     hipLaunchKernelGGL(k_reduce_cols, dim3(nrhs), dim3(256), 0, st, kRedBlocks, nrhs, W.part, W.sums, done);
@@ -1029,7 +1142,7 @@ ddlr_status ddlr_setup(const ddlr_csr* A, const int32_t* part, int32_t p, int32_
 static ddlr_status check_vec(const ddlr_prec* h, int32_t nrhs, const void* x, int64_t ldx, const void* y,
                              int64_t ldy) {
     if (!dev_ok(h)) return h ? DDLR_E_DEVICE : DDLR_E_INVALID;
-    if (nrhs < 0 || (nrhs > 0 && (!x || !y)) || ldx < h->plan.n || ldy < h->plan.n) {
+    if (nrhs < 0 || (nrhs > 0 && (!x || !y)) || ldx < h->ndev || ldy < h->ndev) {
         g_err = "bad nrhs, pointer or leading dimension";
         return DDLR_E_INVALID;
     }
@@ -1043,7 +1156,7 @@ static ddlr_status run_chunked(ddlr_prec* h, int32_t nrhs, const double* x, int6
     try {
         HIPCHK(hipSetDevice(h->device));
         hipStream_t st = (hipStream_t)stream;
-        const int64_t n = h->plan.n;
+        const int64_t n = h->ndev;
         for (int32_t c0 = 0; c0 < nrhs; c0 += kMaxRhs) {
             const int nr = std::min<int>(kMaxRhs, nrhs - c0);
             ensure_ws(h, nr);
@@ -1069,7 +1182,7 @@ ddlr_status ddlr_apply(ddlr_prec* h, int32_t nrhs, const double* x, int64_t ldx,
     ddlr_status st = check_vec(h, nrhs, x, ldx, y, ldy);
     if (st != DDLR_OK) return st;
     return run_chunked(h, nrhs, x, ldx, y, ldy, stream, [&](int nr, double* in, double* out, hipStream_t s) {
-        apply_dev(h, nr, in, h->plan.n, out, h->plan.n, s, nullptr);
+        apply_dev(h, nr, in, h->ndev, out, h->ndev, s, nullptr);
     });
 }
 
@@ -1080,7 +1193,7 @@ ddlr_status ddlr_a0_solve(ddlr_prec* h, int32_t nrhs, const double* x, int64_t l
     const int v = h->variant;
     h->variant = 0;
     ddlr_status r = run_chunked(h, nrhs, x, ldx, y, ldy, stream, [&](int nr, double* in, double* out, hipStream_t s) {
-        apply_dev(h, nr, in, h->plan.n, out, h->plan.n, s, nullptr);
+        apply_dev(h, nr, in, h->ndev, out, h->ndev, s, nullptr);
     });
     h->variant = v;
     return r;
@@ -1091,7 +1204,7 @@ ddlr_status ddlr_spmv(ddlr_prec* h, int32_t nrhs, const double* x, int64_t ldx, 
     ddlr_status st = check_vec(h, nrhs, x, ldx, y, ldy);
     if (st != DDLR_OK) return st;
     return run_chunked(h, nrhs, x, ldx, y, ldy, stream, [&](int nr, double* in, double* out, hipStream_t s) {
-        spmv_dev(h, nr, in, h->plan.n, out, h->plan.n, nullptr, s, nullptr);
+        spmv_dev(h, nr, in, h->ndev, out, h->ndev, nullptr, s, nullptr);
     });
 }
 
@@ -1103,7 +1216,7 @@ static void ensure_gmres(ddlr_prec* h, int nr, int m) {
     Workspace& W = h->ws;
     if (W.gm_m >= m && W.gm_nrhs >= nr) return;
     W.gmem.release();
-    const int64_t n = h->plan.n;
+    const int64_t n = h->ndev;
     W.gV = W.gmem.alloc<double>((size_t)(m + 1) * nr * n);
     W.gH = W.gmem.alloc<double>((size_t)nr * m * (m + 1));
     W.gcs = W.gmem.alloc<double>((size_t)nr * m);
@@ -1124,7 +1237,7 @@ static void gmres_dev(ddlr_prec* h, int nr, const ddlr_solve_options& o, hipStre
     const int m = o.restart;
     ensure_gmres(h, nr, m);
     Workspace& W = h->ws;
-    const int64_t n = h->plan.n;
+    const int64_t n = h->ndev;
     const double tol2 = o.rtol * o.rtol;
     // W.p keeps b; W.x = 0
     HIPCHK(hipMemcpyAsync(W.p, W.r, sizeof(double) * n * nr, hipMemcpyDeviceToDevice, st));
@@ -1199,7 +1312,7 @@ extern "C" {
 // PCG on nr columns already gathered into W.r (b); result in W.x.
 static void pcg_dev(ddlr_prec* h, int nr, const ddlr_solve_options& o, hipStream_t st) {
     Workspace& W = h->ws;
-    const int64_t n = h->plan.n;
+    const int64_t n = h->ndev;
     const double tol2 = o.rtol * o.rtol;
     const int npart_spmv = (int)((n + 255) / 256);
     hipLaunchKernelGGL(k_fill, dim3(grid_for(n * nr)), dim3(256), 0, st, n * nr, 0.0, W.x);
@@ -1267,7 +1380,7 @@ ddlr_status ddlr_solve(ddlr_prec* h, int32_t nrhs, const double* b, int64_t ldb,
     try {
         HIPCHK(hipSetDevice(h->device));
         hipStream_t st = (hipStream_t)stream;
-        const int64_t n = h->plan.n;
+        const int64_t n = h->ndev;
         for (int32_t c0 = 0; c0 < nrhs; c0 += kMaxRhs) {
             const int nr = std::min<int>(kMaxRhs, nrhs - c0);
             ensure_ws(h, nr);
@@ -1564,5 +1677,296 @@ const char* ddlr_status_string(int32_t s) {
 }
 
 const char* ddlr_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"
+
+// ================================================================ batches
+
+struct ddlr_batch {
+    ddlr_prec* h = nullptr;  // merged preconditioner, one CG lane per system
+    int nsys = 0;
+    std::vector<int64_t> roff, soff;
+    std::vector<int32_t> spd;
+    hipStream_t own = nullptr;  // internal stream (captured into the iteration graph)
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    int graph_chunk = 0, graph_maxit = -1;
+    double graph_tol2 = -1.0;
+};
+
+namespace {
+
+constexpr int kBatchChunk = 8;  // CG iterations per graph launch
+
+void batch_release(ddlr_batch* B) {
+    if (B->gexec) (void)hipGraphExecDestroy(B->gexec);
+    if (B->graph) (void)hipGraphDestroy(B->graph);
+    if (B->own) (void)hipStreamDestroy(B->own);
+    if (B->ev_in) (void)hipEventDestroy(B->ev_in);
+    if (B->ev_out) (void)hipEventDestroy(B->ev_out);
+    if (B->h) ddlr_destroy(B->h);
+    B->h = nullptr;
+}
+
+void seg_dot(ddlr_prec* h, const double* a, const double* b, hipStream_t st, const int* done) {
+    Workspace& W = h->ws;
+    hipLaunchKernelGGL(k_seg_dot, dim3(kSegChunks, h->nsys), dim3(256), 0, st, h->seg_roff, a, b, W.part, done);
+    LAUNCHCHK();
+    hipLaunchKernelGGL(k_reduce_cols, dim3(h->nsys), dim3(256), 0, st, kSegChunks, h->nsys, W.part, W.sums, done);
+    LAUNCHCHK();
+}
+
+void seg_scalar(ddlr_prec* h, int what, double tol2, int maxit, hipStream_t st) {
+    Workspace& W = h->ws;
+    hipLaunchKernelGGL(k_cg_scalar_many, dim3(1), dim3(256), 0, st, what, h->nsys, W.sums, W.lanes, tol2, maxit,
+                       W.done);
+    LAUNCHCHK();
+}
+
+// one CG iteration of every system (device-side early exit through W.done)
+void batch_iteration(ddlr_prec* h, double tol2, int maxit, hipStream_t st) {
+    Workspace& W = h->ws;
+    const int64_t n = h->ndev;
+    spmv_dev(h, 1, W.p, n, W.q, n, nullptr, st, W.done);
+    seg_dot(h, W.p, W.q, st, W.done);
+    seg_scalar(h, 2, tol2, maxit, st);
+    hipLaunchKernelGGL(k_seg_cg_xr, dim3(kSegChunks, h->nsys), dim3(256), 0, st, h->seg_roff, W.lanes, W.p, W.q, W.x,
+                       W.r, W.part, W.done);
+    LAUNCHCHK();
+    hipLaunchKernelGGL(k_reduce_cols, dim3(h->nsys), dim3(256), 0, st, kSegChunks, h->nsys, W.part, W.sums, W.done);
+    LAUNCHCHK();
+    seg_scalar(h, 3, tol2, maxit, st);
+    apply_dev(h, 1, W.r, n, W.z, n, st, W.done);
+    seg_dot(h, W.r, W.z, st, W.done);
+    seg_scalar(h, 4, tol2, maxit, st);
+    hipLaunchKernelGGL(k_seg_cg_p, dim3(kSegChunks, h->nsys), dim3(256), 0, st, h->seg_roff, W.lanes, 0, W.z, W.p,
+                       W.done);
+    LAUNCHCHK();
+}
+
+}  // namespace
+
+extern "C" {
+
+ddlr_status ddlr_batch_create(int32_t nsys, ddlr_prec* const* members, ddlr_batch** out) {
+    if (out) *out = nullptr;
+    if (!out || !members || nsys < 1 || nsys > 1024) {
+        g_err = "bad batch arguments (1 <= nsys <= 1024)";
+        return DDLR_E_INVALID;
+    }
+    const ddlr_prec* m0 = members[0];
+    for (int q = 0; q < nsys; ++q) {
+        const ddlr_prec* m = members[q];
+        if (!m || m->device < 0 || m->nsys != 1 || m->device != m0->device || m->precision != m0->precision ||
+            m->variant != m0->variant || m->variant == DDLR_2 || m->precision == DDLR_FP32_UK_BF16) {
+            g_err = "batch members must be single-system device handles with the same device, precision and "
+                    "variant (DDLR-1 or A0 only; FP64 or FP32)";
+            return DDLR_E_INVALID;
+        }
+    }
+    std::unique_ptr<ddlr_batch> B(new ddlr_batch());
+    B->nsys = nsys;
+    try {
+        HIPCHK(hipSetDevice(m0->device));
+        ddlr_prec* h = new ddlr_prec();
+        B->h = h;
+        h->device = m0->device;
+        h->precision = m0->precision;
+        h->variant = m0->variant;
+        h->nsys = nsys;
+        h->overlap = false;
+        // device structures of every member, interface blocks as single blocks
+        std::vector<DevHost> parts(nsys);
+        std::vector<const DevHost*> pp(nsys);
+        B->roff.assign(nsys + 1, 0);
+        B->soff.assign(nsys + 1, 0);
+        for (int q = 0; q < nsys; ++q) {
+            parts[q] = build_devhost(members[q]->plan, 0);
+            pp[q] = &parts[q];
+            B->roff[q + 1] = B->roff[q] + parts[q].n;
+            B->soff[q + 1] = B->soff[q] + parts[q].s;
+            B->spd.push_back(members[q]->spd);
+        }
+        DevHost D;
+        merge_devhost(pp, D);
+        parts.clear();
+        upload_devhost(h, D);
+        h->seg_roff = h->mem.upload(B->roff);
+        h->seg_soff = h->mem.upload(B->soff);
+        int kmax = 0;
+        for (int q = 0; q < nsys; ++q) kmax = std::max(kmax, members[q]->k);
+        h->k = h->variant == DDLR_1 ? kmax : 0;
+        h->spd = 1;
+        for (int q = 0; q < nsys; ++q) h->spd = h->spd && members[q]->spd;
+        if (h->variant == DDLR_1) {
+            // U of every system (interface rows in device order), padded to kmax columns
+            const int64_t s = B->soff[nsys];
+            std::vector<double> U((size_t)s * kmax, 0.0), dv((size_t)nsys * kmax, 0.0), c0(nsys);
+            for (int q = 0; q < nsys; ++q) {
+                const ddlr_prec* m = members[q];
+                std::vector<double> Uq((size_t)m->urows * m->k);
+                HIPCHK(hipMemcpy(Uq.data(), m->f64.U, Uq.size() * sizeof(double), hipMemcpyDeviceToHost));
+                for (int64_t i = 0; i < m->urows; ++i)
+                    for (int j = 0; j < m->k; ++j) U[(size_t)(B->soff[q] + i) * kmax + j] = Uq[(size_t)i * m->k + j];
+                for (int j = 0; j < m->k; ++j) dv[(size_t)q * kmax + j] = m->dvec_h[j];
+                c0[q] = m->c0;
+            }
+            h->urows = s;
+            h->f64.U = h->lrmem.upload(U);
+            if (h->precision != DDLR_FP64) {
+                std::vector<float> f(U.begin(), U.end());
+                h->f32.U = h->lrmem.upload(f);
+            }
+            h->dvecs = h->lrmem.upload(dv);
+            h->c0s = h->lrmem.upload(c0);
+        }
+        HIPCHK(hipStreamCreateWithFlags(&B->own, hipStreamNonBlocking));  // default priority
+        HIPCHK(hipEventCreateWithFlags(&B->ev_in, hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&B->ev_out, hipEventDisableTiming));
+        ensure_ws(h, 1);
+        HIPCHK(hipDeviceSynchronize());
+    } catch (const SetupError& e) {
+        batch_release(B.get());
+        return fail_status(e);
+    } catch (const std::bad_alloc&) {
+        batch_release(B.get());
+        g_err = "host out of memory";
+        return DDLR_E_OOM;
+    }
+    *out = B.release();
+    return DDLR_OK;
+}
+
+ddlr_status ddlr_batch_offsets(const ddlr_batch* B, int64_t* offsets) {
+    if (!B || !offsets) {
+        g_err = "null argument";
+        return DDLR_E_INVALID;
+    }
+    std::copy(B->roff.begin(), B->roff.end(), offsets);
+    return DDLR_OK;
+}
+
+ddlr_status ddlr_batch_apply(ddlr_batch* B, const double* x, double* y, void* stream) {
+    if (!B || !x || !y) {
+        g_err = "null argument";
+        return DDLR_E_INVALID;
+    }
+    ddlr_prec* h = B->h;
+    return run_chunked(h, 1, x, h->ndev, y, h->ndev, stream, [&](int nr, double* in, double* out, hipStream_t s) {
+        apply_dev(h, nr, in, h->ndev, out, h->ndev, s, nullptr);
+    });
+}
+
+ddlr_status ddlr_batch_solve(ddlr_batch* B, const double* b, double* x, const ddlr_solve_options* opt_in,
+                             ddlr_solve_info* info, void* stream) {
+    if (!B || !b || !x || !info) {
+        g_err = "null argument";
+        return DDLR_E_INVALID;
+    }
+    ddlr_solve_options o;
+    if (opt_in) o = *opt_in;
+    else ddlr_solve_options_default(&o);
+    if (o.method != 0 || o.maxit < 1 || !(o.rtol > 0.0)) {
+        g_err = "batch solves use CG (method 0) with maxit >= 1 and rtol > 0";
+        return DDLR_E_INVALID;
+    }
+    ddlr_prec* h = B->h;
+    if (!h->spd) {
+        g_err = "a member preconditioner is not certified SPD";
+        return DDLR_E_NOT_SPD;
+    }
+    const double tol2 = o.rtol * o.rtol;
+    ddlr_status result = DDLR_OK;
+    try {
+        HIPCHK(hipSetDevice(h->device));
+        hipStream_t ust = (hipStream_t)stream, st = B->own;
+        HIPCHK(hipEventRecord(B->ev_in, ust));
+        HIPCHK(hipStreamWaitEvent(st, B->ev_in, 0));
+        Workspace& W = h->ws;
+        const int64_t n = h->ndev;
+        hipLaunchKernelGGL((k_gather<double, double>), dim3(grid_for(n)), dim3(256), 0, st, n, 1, h->perm_dev, b, n,
+                           W.r, n);
+        LAUNCHCHK();
+        hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(256), 0, st, n, 0.0, W.x);
+        LAUNCHCHK();
+        seg_dot(h, W.r, W.r, st, nullptr);
+        seg_scalar(h, 0, tol2, o.maxit, st);
+        apply_dev(h, 1, W.r, n, W.z, n, st, W.done);
+        seg_dot(h, W.r, W.z, st, W.done);
+        seg_scalar(h, 1, tol2, o.maxit, st);
+        hipLaunchKernelGGL(k_seg_cg_p, dim3(kSegChunks, h->nsys), dim3(256), 0, st, h->seg_roff, W.lanes, 1, W.z, W.p,
+                           W.done);
+        LAUNCHCHK();
+        // kBatchChunk iterations captured once into a graph, replayed until every system is done
+        if (!B->gexec || B->graph_tol2 != tol2 || B->graph_maxit != o.maxit) {
+            if (B->gexec) (void)hipGraphExecDestroy(B->gexec);
+            if (B->graph) (void)hipGraphDestroy(B->graph);
+            B->gexec = nullptr;
+            B->graph = nullptr;
+            h->capturing = true;
+            HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+            for (int c = 0; c < kBatchChunk; ++c) batch_iteration(h, tol2, o.maxit, st);
+            hipGraph_t g = nullptr;
+            const hipError_t ec = hipStreamEndCapture(st, &g);
+            h->capturing = false;
+            HIPCHK(ec);
+            B->graph = g;
+            HIPCHK(hipGraphInstantiate(&B->gexec, B->graph, nullptr, nullptr, 0));
+            B->graph_tol2 = tol2;
+            B->graph_maxit = o.maxit;
+        }
+        for (int it = 0; it < o.maxit; it += kBatchChunk) {
+            HIPCHK(hipGraphLaunch(B->gexec, st));
+            HIPCHK(hipMemcpyAsync(W.done_host, W.done, sizeof(int), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            if (*W.done_host) break;
+        }
+        hipLaunchKernelGGL((k_scatter<double, double>), dim3(grid_for(n)), dim3(256), 0, st, n, 1, h->perm_dev, W.x, n,
+                           x, n);
+        LAUNCHCHK();
+        // true residual per system
+        hipLaunchKernelGGL((k_gather<double, double>), dim3(grid_for(n)), dim3(256), 0, st, n, 1, h->perm_dev, b, n,
+                           W.r, n);
+        LAUNCHCHK();
+        spmv_dev(h, 1, W.x, n, W.q, n, nullptr, st, nullptr);
+        hipLaunchKernelGGL(k_sub, dim3(grid_for(n)), dim3(256), 0, st, n, W.r, W.q, W.z);
+        LAUNCHCHK();
+        seg_dot(h, W.z, W.z, st, nullptr);
+        const int ns = h->nsys;
+        std::vector<CgLane> lanes(ns);
+        std::vector<double> rr(ns);
+        HIPCHK(hipMemcpyAsync(lanes.data(), W.lanes, ns * sizeof(CgLane), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(rr.data(), W.sums, ns * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        HIPCHK(hipEventRecord(B->ev_out, st));
+        HIPCHK(hipStreamWaitEvent(ust, B->ev_out, 0));
+        for (int q = 0; q < ns; ++q) {
+            ddlr_solve_info& inf = info[q];
+            const double bb = lanes[q].bb;
+            inf.iters = lanes[q].its;
+            const bool conv = bb == 0.0 || lanes[q].rr <= tol2 * bb;
+            inf.status = conv ? DDLR_OK : DDLR_E_NO_CONVERGENCE;
+            inf.relres = bb > 0 ? std::sqrt(lanes[q].rr / bb) : 0.0;
+            inf.relres_true = bb > 0 ? std::sqrt(rr[q] / bb) : 0.0;
+            if (!conv) result = DDLR_E_NO_CONVERGENCE;
+        }
+    } catch (const SetupError& e) {
+        h->capturing = false;
+        return fail_status(e);
+    }
+    if (result != DDLR_OK) g_err = "some systems did not converge";
+    return result;
+}
+
+void ddlr_batch_destroy(ddlr_batch* B) {
+    if (!B) return;
+    if (B->h && B->h->device >= 0) {
+        (void)hipSetDevice(B->h->device);
+        (void)hipDeviceSynchronize();
+    }
+    batch_release(B);
+    delete B;
+}
 
 }  // extern "C"

@@ -837,6 +837,149 @@ __global__ __launch_bounds__(256) void k_cg_p(int64_t n, int nrhs, const CgLane*
     }
 }
 
+// ------------------------------------------------------------ batches
+//
+// A batch concatenates independent systems: system q owns device rows
+// [roff[q], roff[q+1]) and interface positions [soff[q], soff[q+1]).  SpMV,
+// the A0 solve and the E / E^T products run over the union unchanged; the
+// reductions, the CG scalars and the low-rank correction are per system.
+// Grids are (chunks, systems): blockIdx.y selects the system, so every block
+// knows its system without a per-row lookup.
+
+// part[chunk * nsys + q] = partial a . b over system q's rows
+__global__ __launch_bounds__(256) void k_seg_dot(const int64_t* __restrict__ roff, const double* __restrict__ a,
+                                                 const double* __restrict__ b, double* __restrict__ part,
+                                                 const int* __restrict__ done) {
+    __shared__ double sh[4];
+    if (done && *done) return;
+    const int q = blockIdx.y, nsys = gridDim.y;
+    const int64_t r0 = roff[q], r1 = roff[q + 1];
+    double acc = 0.0;
+    for (int64_t i = r0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < r1; i += (int64_t)gridDim.x * blockDim.x)
+        acc += a[i] * b[i];
+    const double t = block_sum256(acc, sh);
+    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * nsys + q] = t;
+}
+
+// x += alpha_q p ; r -= alpha_q q ; part = r.r   per system
+__global__ __launch_bounds__(256) void k_seg_cg_xr(const int64_t* __restrict__ roff, const CgLane* __restrict__ L,
+                                                   const double* __restrict__ p, const double* __restrict__ qv,
+                                                   double* __restrict__ x, double* __restrict__ r,
+                                                   double* __restrict__ part, const int* __restrict__ done) {
+    __shared__ double sh[4];
+    if (done && *done) return;
+    const int q = blockIdx.y, nsys = gridDim.y;
+    const int64_t r0 = roff[q], r1 = roff[q + 1];
+    const bool act = L[q].active;
+    const double a = L[q].alpha;
+    double acc = 0.0;
+    for (int64_t i = r0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < r1; i += (int64_t)gridDim.x * blockDim.x) {
+        double ri = r[i];
+        if (act) {
+            x[i] += a * p[i];
+            ri -= a * qv[i];
+            r[i] = ri;
+        }
+        acc += ri * ri;
+    }
+    const double t = block_sum256(acc, sh);
+    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * nsys + q] = t;
+}
+
+// p = z + beta_q p (active systems); init: p = z
+__global__ __launch_bounds__(256) void k_seg_cg_p(const int64_t* __restrict__ roff, const CgLane* __restrict__ L,
+                                                  int init, const double* __restrict__ z, double* __restrict__ p,
+                                                  const int* __restrict__ done) {
+    if (done && *done) return;
+    const int q = blockIdx.y;
+    const int64_t r0 = roff[q], r1 = roff[q + 1];
+    const bool act = L[q].active;
+    const double be = L[q].beta;
+    for (int64_t i = r0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < r1; i += (int64_t)gridDim.x * blockDim.x) {
+        if (init) p[i] = z[i];
+        else if (act) p[i] = z[i] + be * p[i];
+    }
+}
+
+// DDLR-1 coefficients of each system: coef[q][j] = d_q[j] * sum over system
+// q's interface positions of U[i][j] y[i].  One workgroup per system; lanes
+// own columns, the four waves stride the rows, fixed-order fold.
+template <typename T>
+__global__ __launch_bounds__(256) void k_seg_lr_coef(const int64_t* __restrict__ soff, int k, const T* __restrict__ U,
+                                                     const T* __restrict__ y, const double* __restrict__ dvec,
+                                                     double* __restrict__ coef, const int* __restrict__ done) {
+    __shared__ double sh[4][64];
+    if (done && *done) return;
+    const int q = blockIdx.x;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t r0 = soff[q], r1 = soff[q + 1];
+    for (int j0 = 0; j0 < k; j0 += 64) {
+        const int j = j0 + lane;
+        double acc = 0.0;
+        if (j < k)
+            for (int64_t i = r0 + wv; i < r1; i += 4) acc += (double)U[i * k + j] * (double)y[i];
+        sh[wv][lane] = acc;
+        __syncthreads();
+        if (wv == 0 && j < k)
+            coef[(int64_t)q * k + j] = dvec[(int64_t)q * k + j] * ((sh[0][lane] + sh[1][lane]) + (sh[2][lane] + sh[3][lane]));
+        __syncthreads();
+    }
+}
+
+// w = c0_q y + U coef_q over each system's interface positions
+template <typename T>
+__global__ __launch_bounds__(256) void k_seg_lr_expand(const int64_t* __restrict__ soff, int k, const T* __restrict__ U,
+                                                       const double* __restrict__ coef, const double* __restrict__ c0,
+                                                       const T* __restrict__ y, T* __restrict__ w,
+                                                       const int* __restrict__ done) {
+    __shared__ double cf[128];
+    if (done && *done) return;
+    const int q = blockIdx.y;
+    for (int j = threadIdx.x; j < k; j += blockDim.x) cf[j] = coef[(int64_t)q * k + j];
+    __syncthreads();
+    const int64_t r0 = soff[q], r1 = soff[q + 1];
+    const double cq = c0[q];
+    for (int64_t i = r0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < r1; i += (int64_t)gridDim.x * blockDim.x) {
+        double v = cq * (double)y[i];
+        for (int j = 0; j < k; ++j) v += (double)U[i * k + j] * cf[j];
+        w[i] = (T)v;
+    }
+}
+
+// CG scalars of many lanes: one thread per lane (blockDim >= nlanes)
+__global__ void k_cg_scalar_many(int what, int nlanes, const double* __restrict__ sums, CgLane* __restrict__ L,
+                                 double tol2, int maxit, int* __restrict__ done) {
+    if (what != 0 && done && *done) return;
+    __shared__ int any;
+    if (threadIdx.x == 0) any = 0;
+    __syncthreads();
+    for (int r = threadIdx.x; r < nlanes; r += blockDim.x) {
+        const double s = sums[r];
+        CgLane& l = L[r];
+        switch (what) {
+        case 0: l.bb = s; l.rr = s; l.its = 0; l.active = s > 0.0; l.rz = 0; l.alpha = 0; l.beta = 0; break;
+        case 1: l.rz = s; break;
+        case 2: l.alpha = l.active ? l.rz / s : 0.0; break;
+        case 3:
+            if (l.active) {
+                l.rr = s;
+                l.its += 1;
+                if (s <= tol2 * l.bb || l.its >= maxit) l.active = 0;
+            }
+            break;
+        case 4:
+            if (l.active) {
+                l.beta = s / l.rz;
+                l.rz = s;
+            }
+            break;
+        }
+        if (l.active) any = 1;  // benign race: every writer stores 1
+    }
+    __syncthreads();
+    if ((what == 0 || what == 3) && threadIdx.x == 0 && done) *done = any ? 0 : 1;
+}
+
 // ------------------------------------------------------------ GMRES steps
 //
 // Right-preconditioned restarted GMRES on nrhs independent systems.  Basis

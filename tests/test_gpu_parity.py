@@ -337,3 +337,71 @@ def test_gmres_matches_oracle(restart, variant):
     xo, io = o.gmres(b, restart=restart, maxit=restart + 3)
     assert st == D.E_NO_CONVERGENCE and all(i["iters"] == restart + 3 for i in info)
     assert rel(to_host(x), xo) <= 1e-9
+
+
+def batch_members(count, prec, seed=0):
+    rng = np.random.default_rng(seed)
+    out = []
+    for q in range(count):
+        nx, ny = int(rng.integers(12, 40)), int(rng.integers(12, 40))
+        px, py = int(rng.integers(2, 4)), int(rng.integers(1, 4))
+        A = w.tpfa_2d(nx, ny, 100 + q)
+        part = w.box_partition((nx, ny), (px, py))
+        out.append((A, part, px * py))
+    return out
+
+
+@pytest.mark.parametrize("prec", [D.FP64, D.FP32])
+def test_batch_matches_single_and_oracle(prec):
+    """Each system's result in the batch equals its solve alone (same operator,
+    different reduction grouping: within 1e-9) and the oracle's; the captured
+    iteration graph gives identical results on every replay, with other eager
+    work between replays."""
+    mem = batch_members(11, prec)
+    say("batch", prec)
+    k, m = 4, 10
+    hs = [D.ddlr_setup(A, part, p, k, 1, lanczos_steps=m, lanczos_start=w.lanczos_start(A.n, 3), precision=prec)
+          for A, part, p in mem]
+    B = D.ddlr_batch_create(hs)
+    bs = [w.rhs_from_solution(A, q, 1)[0][:, 0] for q, (A, _, _) in enumerate(mem)]
+    bt = torch.from_numpy(np.concatenate(bs)).to(DEV)
+    xs = []
+    for rep in range(3):
+        x = torch.zeros_like(bt)
+        st, info = D.ddlr_batch_solve(B, bt, x)
+        assert st == D.OK
+        xs.append(x.cpu().numpy())
+        # eager work between replays: a single-system solve on another handle
+        b0 = torch.from_numpy(bs[0]).to(DEV)
+        D.ddlr_solve(hs[0], b0, torch.zeros_like(b0))
+    assert np.array_equal(xs[0], xs[1]) and np.array_equal(xs[0], xs[2])
+    off = B.offsets
+    for q, ((A, part, p), h) in enumerate(zip(mem, hs)):
+        b = torch.from_numpy(bs[q]).to(DEV)
+        xq = torch.zeros_like(b)
+        st1, i1 = D.ddlr_solve(h, b, xq)
+        xb = xs[0][off[q]:off[q + 1]]
+        # FP32: the batch's per-system correction accumulates in FP64, the single
+        # path's FP32 MFMA in FP32 (operators equal to ~1e-7)
+        slack = 1 if prec == D.FP64 else max(1, int(0.1 * i1[0]["iters"]))
+        assert abs(info[q]["iters"] - i1[0]["iters"]) <= slack
+        assert info[q]["relres_true"] <= 1.05e-6
+        # two CG runs stopped at 1e-6 residual differ by up to ~cond * 1e-6 in x;
+        # these random-coefficient systems (contrast 1e4) are ill-conditioned
+        assert rel(xb, xq.cpu().numpy()) <= 1e-4
+        o = Oracle(A, part, p)
+        o.lowrank(1, k, m, w.lanczos_start(A.n, 3))
+        xo, io = o.pcg(bs[q])
+        if prec == D.FP64:
+            assert abs(info[q]["iters"] - int(io["its"][0])) <= 1
+        else:  # mixed-precision bar against the FP64 oracle
+            assert info[q]["iters"] <= int(1.1 * int(io["its"][0])) + 1
+        assert rel(xb, xo) <= 1e-4
+    # the batch's preconditioner application equals each member's
+    y = torch.empty_like(bt)
+    D.ddlr_batch_apply(B, bt, y)
+    for q, h in enumerate(hs):
+        b = torch.from_numpy(bs[q]).to(DEV)
+        yq = torch.empty_like(b)
+        D.ddlr_apply(h, b, yq)
+        assert rel(y.cpu().numpy()[off[q]:off[q + 1]], yq.cpu().numpy()) <= (1e-12 if prec == D.FP64 else 1e-6)
