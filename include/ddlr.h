@@ -45,6 +45,7 @@ typedef enum {
     DDLR_E_NO_CONVERGENCE = -5,  /* Krylov solve hit maxit; x and info are still written */
     DDLR_E_LANCZOS = -6,         /* Lanczos broke down before k+1 Ritz values */
     DDLR_E_OOM = -7,             /* device allocation failed */
+    DDLR_E_BUDGET = -8,          /* serving: the HBM budget cannot hold the matrix */
     DDLR_E_DEVICE = -9           /* HIP error, or a host-only handle used for device work */
 } ddlr_status;
 
@@ -228,6 +229,45 @@ ddlr_status ddlr_batch_apply(ddlr_batch *b, const double *x, double *y, void *st
 ddlr_status ddlr_batch_solve(ddlr_batch *b, const double *bvec, double *x, const ddlr_solve_options *opt,
                              ddlr_solve_info *info, void *stream);
 void ddlr_batch_destroy(ddlr_batch *b);
+
+/*
+ * Serving: resident preconditioners, requests of 1..nrhs right-hand sides
+ * arriving at any time, continuous batching.  Every added matrix keeps its
+ * factors and U_k on the device and owns `slots_per_matrix` CG lanes (columns).
+ * A worker thread admits queued right-hand sides into free lanes of their
+ * matrix, runs a few CG iterations on every matrix with lanes (one stream per
+ * matrix, so matrices overlap on the device), and retires finished lanes,
+ * copying x back.  Each lane's arithmetic is independent of the other lanes and
+ * of its admission time, so a result is the same alone and in a mix.
+ *
+ * ddlr_server_create: device, HBM budget in bytes (0 = unlimited), lanes per
+ *   matrix (1..16).
+ * ddlr_server_add: the server uses `h` exclusively from now on (do not use it
+ *   for other calls until the server is destroyed); DDLR_E_BUDGET if the
+ *   resident bytes of all added matrices would exceed the budget.
+ * ddlr_server_submit: b_host / x_host are host arrays of nrhs columns (user
+ *   order, ld = n) that must stay valid until the request is done; x_host is
+ *   written when the request completes.  CG only (method 0).
+ * ddlr_server_poll / ddlr_server_wait: info is a host array of nrhs entries;
+ *   relres_true is not computed by the server (-1).
+ * ddlr_server_stats: counters, solves/s over the span from the first submit
+ *   to the last completion, p50 / p99 request latency (submit to completion).
+ */
+typedef struct ddlr_server ddlr_server;
+typedef struct {
+    int64_t requests_submitted, requests_done, solves_done, queued;
+    double solves_per_s, p50_ms, p99_ms;
+    size_t hbm_used, hbm_budget;
+    int32_t matrices, reserved;
+} ddlr_server_counters;
+ddlr_status ddlr_server_create(int32_t device, size_t hbm_budget_bytes, int32_t slots_per_matrix, ddlr_server **out);
+ddlr_status ddlr_server_add(ddlr_server *s, ddlr_prec *h, int32_t *matrix_id);
+ddlr_status ddlr_server_submit(ddlr_server *s, int32_t matrix_id, int32_t nrhs, const double *b_host, double *x_host,
+                               const ddlr_solve_options *opt, uint64_t *ticket);
+ddlr_status ddlr_server_poll(ddlr_server *s, uint64_t ticket, int32_t *done, ddlr_solve_info *info);
+ddlr_status ddlr_server_wait(ddlr_server *s, uint64_t ticket, ddlr_solve_info *info);
+ddlr_status ddlr_server_stats(ddlr_server *s, ddlr_server_counters *stats);
+void ddlr_server_destroy(ddlr_server *s);
 
 const char *ddlr_status_string(int32_t status);
 const char *ddlr_last_error(void);

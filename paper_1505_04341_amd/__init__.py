@@ -17,8 +17,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libddlr.so")
 
-OK, E_INVALID, E_NOT_SYMMETRIC, E_BREAKDOWN, E_NOT_SPD, E_NO_CONVERGENCE, E_LANCZOS, E_OOM, E_DEVICE = (
-    0, -1, -2, -3, -4, -5, -6, -7, -9)
+OK, E_INVALID, E_NOT_SYMMETRIC, E_BREAKDOWN, E_NOT_SPD, E_NO_CONVERGENCE, E_LANCZOS, E_OOM, E_BUDGET, E_DEVICE = (
+    0, -1, -2, -3, -4, -5, -6, -7, -8, -9)
 VARIANT_A0, DDLR_1, DDLR_2 = 0, 1, 2
 THETA_LAMBDA_K1, THETA_ZERO = 0, 1
 FACTOR_IC0, FACTOR_ILDL0 = 0, 1
@@ -55,6 +55,16 @@ class ddlr_info(C.Structure):
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class ddlr_server_counters(C.Structure):
+    _fields_ = [("requests_submitted", C.c_int64), ("requests_done", C.c_int64), ("solves_done", C.c_int64),
+                ("queued", C.c_int64), ("solves_per_s", C.c_double), ("p50_ms", C.c_double), ("p99_ms", C.c_double),
+                ("hbm_used", C.c_size_t), ("hbm_budget", C.c_size_t), ("matrices", C.c_int32),
+                ("reserved", C.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
 
 
 class DDLRError(RuntimeError):
@@ -98,6 +108,13 @@ def load_library(path: str = LIB_PATH):
         "ddlr_batch_apply": (I32, [P, P, P, P]),
         "ddlr_batch_solve": (I32, [P, P, P, P, P, P]),
         "ddlr_batch_destroy": (None, [P]),
+        "ddlr_server_create": (I32, [I32, C.c_size_t, I32, P]),
+        "ddlr_server_add": (I32, [P, P, P]),
+        "ddlr_server_submit": (I32, [P, I32, I32, P, P, P, P]),
+        "ddlr_server_poll": (I32, [P, C.c_uint64, P, P]),
+        "ddlr_server_wait": (I32, [P, C.c_uint64, P]),
+        "ddlr_server_stats": (I32, [P, P]),
+        "ddlr_server_destroy": (None, [P]),
         "ddlr_destroy": (None, [P]),
         "ddlr_status_string": (C.c_char_p, [I32]),
         "ddlr_last_error": (C.c_char_p, []),
@@ -350,6 +367,79 @@ def ddlr_batch_solve(batch: Batch, b, x, *, maxit: int = 500, rtol: float = 1e-6
     return st, [dict(iters=i.iters, status=i.status, relres=i.relres, relres_true=i.relres_true) for i in infos]
 
 
+class Server:
+    """Handle of a serving engine (ddlr_server*).  Keeps the host arrays of
+    pending requests alive until they complete."""
+
+    def __init__(self, handle: int):
+        self._h = C.c_void_p(handle)
+        self._pending = {}
+        self._members = []
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.ddlr_server_destroy(self._h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+
+def ddlr_server_create(device: int = 0, hbm_budget_bytes: int = 0, slots_per_matrix: int = 16) -> Server:
+    h = C.c_void_p()
+    _check(load_library().ddlr_server_create(int(device), int(hbm_budget_bytes), int(slots_per_matrix), C.byref(h)),
+           "ddlr_server_create")
+    return Server(h.value)
+
+
+def ddlr_server_add(server: Server, prec: Prec) -> int:
+    mid = C.c_int32()
+    _check(load_library().ddlr_server_add(server.handle, prec.handle, C.byref(mid)), "ddlr_server_add")
+    server._members.append(prec)  # the server uses the handle from now on
+    return mid.value
+
+
+def ddlr_server_submit(server: Server, matrix_id: int, b: np.ndarray, *, rtol: float = 1e-6, maxit: int = 500):
+    """b: host (n,) or (n, nrhs); returns (ticket, x) where x is filled when the request is done."""
+    lib = load_library()
+    b2 = np.asfortranarray(np.asarray(b, dtype=np.float64).reshape(b.shape[0], -1))
+    x = np.zeros_like(b2, order="F")
+    opt = ddlr_solve_options()
+    lib.ddlr_solve_options_default(C.byref(opt))
+    opt.rtol, opt.maxit = float(rtol), int(maxit)
+    t = C.c_uint64()
+    _check(lib.ddlr_server_submit(server.handle, int(matrix_id), b2.shape[1], _ptr(b2), _ptr(x), C.byref(opt),
+                                  C.byref(t)), "ddlr_server_submit")
+    server._pending[t.value] = (b2, x)
+    return t.value, x
+
+
+def ddlr_server_poll(server: Server, ticket: int):
+    b2, x = server._pending[ticket]
+    infos = (ddlr_solve_info * b2.shape[1])()
+    done = C.c_int32()
+    _check(load_library().ddlr_server_poll(server.handle, C.c_uint64(ticket), C.byref(done), infos), "ddlr_server_poll")
+    if not done.value:
+        return False, None
+    return True, [dict(iters=i.iters, status=i.status, relres=i.relres) for i in infos]
+
+
+def ddlr_server_wait(server: Server, ticket: int):
+    b2, x = server._pending[ticket]
+    infos = (ddlr_solve_info * b2.shape[1])()
+    st = load_library().ddlr_server_wait(server.handle, C.c_uint64(ticket), infos)
+    if st not in (OK, E_NO_CONVERGENCE):
+        _check(st, "ddlr_server_wait")
+    return st, [dict(iters=i.iters, status=i.status, relres=i.relres) for i in infos]
+
+
+def ddlr_server_stats(server: Server) -> dict:
+    c = ddlr_server_counters()
+    _check(load_library().ddlr_server_stats(server.handle, C.byref(c)), "ddlr_server_stats")
+    return c.as_dict()
+
+
 PROF_TRSV_BLOCKS, PROF_TRSV_LEVELS, PROF_SPMV, PROF_LOWRANK = 0, 1, 2, 3
 
 
@@ -374,5 +464,6 @@ EXPORTED = ["ddlr_version", "ddlr_options_default", "ddlr_solve_options_default"
             "ddlr_a0_solve", "ddlr_spmv", "ddlr_solve", "ddlr_query", "ddlr_get_ordering", "ddlr_get_factor",
             "ddlr_get_levels", "ddlr_get_lanczos", "ddlr_get_lowrank", "ddlr_set_lowrank", "ddlr_profile",
             "ddlr_profile_read", "ddlr_batch_create", "ddlr_batch_offsets", "ddlr_batch_apply",
-            "ddlr_batch_solve", "ddlr_batch_destroy", "ddlr_destroy",
+            "ddlr_batch_solve", "ddlr_batch_destroy", "ddlr_server_create", "ddlr_server_add", "ddlr_server_submit",
+            "ddlr_server_poll", "ddlr_server_wait", "ddlr_server_stats", "ddlr_server_destroy", "ddlr_destroy",
             "ddlr_status_string", "ddlr_last_error"]

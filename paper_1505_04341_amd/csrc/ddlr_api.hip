@@ -3,6 +3,11 @@
 
 #include <algorithm>
 #include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -39,11 +44,13 @@ constexpr int kProfClasses = 4;
 // Device allocation owned by a handle.
 struct DMem {
     std::vector<void*> ptrs;
+    size_t bytes = 0;
     template <typename T> T* alloc(size_t count) {
         void* p = nullptr;
         if (count == 0) count = 1;
         HIPCHK(hipMalloc(&p, count * sizeof(T)));
         ptrs.push_back(p);
+        bytes += count * sizeof(T);
         return static_cast<T*>(p);
     }
     template <typename T> T* upload(const std::vector<T>& h) {
@@ -54,6 +61,7 @@ struct DMem {
     void release() {
         for (void* p : ptrs) (void)hipFree(p);
         ptrs.clear();
+        bytes = 0;
     }
 };
 
@@ -88,6 +96,9 @@ struct Workspace {
     double *gcoef = nullptr, *ginv = nullptr, *gpart = nullptr;
     GmLane* glanes = nullptr;
     DMem gmem;
+    // lane admission (device copies of the host request)
+    int32_t *adm_start = nullptr, *adm_maxit = nullptr;
+    double* adm_tol2 = nullptr;
 };
 
 }  // namespace
@@ -519,6 +530,9 @@ void ensure_ws(ddlr_prec* h, int nrhs) {
     W.coef = W.mem.alloc<double>((size_t)std::max(nrhs, h->nsys) * kk);
     W.lrsum = W.mem.alloc<double>((size_t)std::max(nrhs, 1) * kk);
     W.lanes = W.mem.alloc<CgLane>(std::max(nrhs, h->nsys));
+    W.adm_start = W.mem.alloc<int32_t>(std::max(nrhs, 1));
+    W.adm_maxit = W.mem.alloc<int32_t>(std::max(nrhs, 1));
+    W.adm_tol2 = W.mem.alloc<double>(std::max(nrhs, 1));
     W.done = W.mem.alloc<int>(1);
     HIPCHK(hipHostMalloc((void**)&W.done_host, sizeof(int)));
     W.nrhs = nrhs;
@@ -1309,49 +1323,59 @@ extern "C" {
 
 }  // extern "C"
 
-// PCG on nr columns already gathered into W.r (b); result in W.x.
-static void pcg_dev(ddlr_prec* h, int nr, const ddlr_solve_options& o, hipStream_t st) {
+// One CG iteration of every lane (lane phases, see CgLane), nr columns of the
+// handle's workspace.  Kernels exit early once W.done is set.
+static void lane_iteration(ddlr_prec* h, int nr, hipStream_t st) {
     Workspace& W = h->ws;
     const int64_t n = h->ndev;
-    const double tol2 = o.rtol * o.rtol;
     const int npart_spmv = (int)((n + 255) / 256);
-    hipLaunchKernelGGL(k_fill, dim3(grid_for(n * nr)), dim3(256), 0, st, n * nr, 0.0, W.x);
+    spmv_dev(h, nr, W.p, n, W.q, n, W.part, st, W.done);
+    hipLaunchKernelGGL(k_reduce_cols, dim3(nr), dim3(256), 0, st, npart_spmv, nr, W.part, W.sums, W.done);
     LAUNCHCHK();
-    dot_dev(h, nr, W.r, W.r, n, st, nullptr);
-    hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(64), 0, st, 0, nr, W.sums, W.lanes, tol2, o.maxit, W.done);
+    hipLaunchKernelGGL(k_lane_scalar, dim3(1), dim3(64), 0, st, 2, nr, W.sums, W.lanes, W.done);
+    LAUNCHCHK();
+    hipLaunchKernelGGL(k_cg_xr, dim3(kRedBlocks), dim3(256), 0, st, n, nr, W.lanes, W.p, W.q, W.x, W.r, n, W.part,
+                       W.done);
+    LAUNCHCHK();
+    hipLaunchKernelGGL(k_reduce_cols, dim3(nr), dim3(256), 0, st, kRedBlocks, nr, W.part, W.sums, W.done);
+    LAUNCHCHK();
+    hipLaunchKernelGGL(k_lane_scalar, dim3(1), dim3(64), 0, st, 3, nr, W.sums, W.lanes, W.done);
     LAUNCHCHK();
     apply_dev(h, nr, W.r, n, W.z, n, st, W.done);
     dot_dev(h, nr, W.r, W.z, n, st, W.done);
-    hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(64), 0, st, 1, nr, W.sums, W.lanes, tol2, o.maxit, W.done);
+    hipLaunchKernelGGL(k_lane_scalar, dim3(1), dim3(64), 0, st, 4, nr, W.sums, W.lanes, W.done);
     LAUNCHCHK();
-    hipLaunchKernelGGL(k_cg_p, dim3(grid_for(n * nr)), dim3(256), 0, st, n, nr, W.lanes, 1, W.z, W.p, n, W.done);
+    hipLaunchKernelGGL(k_cg_p, dim3(grid_for(n * nr)), dim3(256), 0, st, n, nr, W.lanes, 0, W.z, W.p, n, W.done);
     LAUNCHCHK();
+}
+
+// Admits lanes flagged in the host array start[0..nr) (tolerance rtol^2,
+// limit maxit); their b must already be in W.r.
+static void lane_admit(ddlr_prec* h, int nr, const std::vector<int32_t>& start, const std::vector<double>& tol2,
+                       const std::vector<int32_t>& maxit, hipStream_t st) {
+    Workspace& W = h->ws;
+    HIPCHK(hipMemcpyAsync(W.adm_start, start.data(), nr * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(W.adm_tol2, tol2.data(), nr * sizeof(double), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(W.adm_maxit, maxit.data(), nr * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_lane_zero, dim3(grid_for(h->ndev * nr)), dim3(256), 0, st, h->ndev, nr, W.adm_start, W.x, W.p,
+                       h->ndev);
+    LAUNCHCHK();
+    hipLaunchKernelGGL(k_lane_admit, dim3(1), dim3(64), 0, st, nr, W.adm_start, W.adm_tol2, W.adm_maxit, W.lanes,
+                       W.done);
+    LAUNCHCHK();
+}
+
+// PCG on nr columns already gathered into W.r (b); result in W.x.
+static void pcg_dev(ddlr_prec* h, int nr, const ddlr_solve_options& o, hipStream_t st) {
+    std::vector<int32_t> start(nr, 1), maxit(nr, o.maxit);
+    std::vector<double> tol2(nr, o.rtol * o.rtol);
+    lane_admit(h, nr, start, tol2, maxit, st);
     const int chunk = 8;
-    for (int it = 0; it < o.maxit; it += chunk) {
-        for (int c = 0; c < chunk; ++c) {
-            spmv_dev(h, nr, W.p, n, W.q, n, W.part, st, W.done);
-            hipLaunchKernelGGL(k_reduce_cols, dim3(nr), dim3(256), 0, st, npart_spmv, nr, W.part, W.sums, W.done);
-            LAUNCHCHK();
-            hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(64), 0, st, 2, nr, W.sums, W.lanes, tol2, o.maxit, W.done);
-            LAUNCHCHK();
-            hipLaunchKernelGGL(k_cg_xr, dim3(kRedBlocks), dim3(256), 0, st, n, nr, W.lanes, W.p, W.q, W.x, W.r, n,
-                               W.part, W.done);
-            LAUNCHCHK();
-            hipLaunchKernelGGL(k_reduce_cols, dim3(nr), dim3(256), 0, st, kRedBlocks, nr, W.part, W.sums, W.done);
-            LAUNCHCHK();
-            hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(64), 0, st, 3, nr, W.sums, W.lanes, tol2, o.maxit, W.done);
-            LAUNCHCHK();
-            apply_dev(h, nr, W.r, n, W.z, n, st, W.done);
-            dot_dev(h, nr, W.r, W.z, n, st, W.done);
-            hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(64), 0, st, 4, nr, W.sums, W.lanes, tol2, o.maxit, W.done);
-            LAUNCHCHK();
-            hipLaunchKernelGGL(k_cg_p, dim3(grid_for(n * nr)), dim3(256), 0, st, n, nr, W.lanes, 0, W.z, W.p, n,
-                               W.done);
-            LAUNCHCHK();
-        }
-        HIPCHK(hipMemcpyAsync(W.done_host, W.done, sizeof(int), hipMemcpyDeviceToHost, st));
+    for (int it = 0; it <= o.maxit; it += chunk) {
+        for (int c = 0; c < chunk; ++c) lane_iteration(h, nr, st);
+        HIPCHK(hipMemcpyAsync(h->ws.done_host, h->ws.done, sizeof(int), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
-        if (*W.done_host) break;
+        if (*h->ws.done_host) break;
     }
 }
 
@@ -1671,6 +1695,7 @@ const char* ddlr_status_string(int32_t s) {
     case DDLR_E_NO_CONVERGENCE: return "no convergence";
     case DDLR_E_LANCZOS: return "Lanczos breakdown";
     case DDLR_E_OOM: return "out of device memory";
+    case DDLR_E_BUDGET: return "HBM budget exceeded";
     case DDLR_E_DEVICE: return "device error";
     default: return "unknown status";
     }
@@ -1967,6 +1992,386 @@ void ddlr_batch_destroy(ddlr_batch* B) {
     }
     batch_release(B);
     delete B;
+}
+
+}  // extern "C"
+
+// ================================================================ serving
+
+struct SrvRequest {
+    uint64_t ticket = 0;
+    int mid = 0, nrhs = 0;
+    const double* b = nullptr;
+    double* x = nullptr;
+    double tol2 = 0.0;
+    int maxit = 0;
+    int next_col = 0, done_cols = 0;
+    std::vector<ddlr_solve_info> info;
+    double t_submit = 0.0, t_done = 0.0;
+    bool done = false;
+};
+
+struct SrvMatrix {
+    ddlr_prec* h = nullptr;
+    hipStream_t st = nullptr;
+    double* stage = nullptr;  // user-order staging, n x slots
+    DMem mem;
+    size_t bytes = 0;
+    std::vector<SrvRequest*> slot_req;
+    std::vector<int> slot_col;
+    std::vector<CgLane> lanes_h;
+};
+
+struct ddlr_server {
+    int device = 0, slots = 16, tick = 4;
+    size_t budget = 0, used = 0;
+    std::vector<std::unique_ptr<SrvMatrix>> mats;
+    std::mutex mu;
+    std::condition_variable cv, cv_done;
+    std::thread worker;
+    bool stop = false;
+    std::deque<SrvRequest*> queue;
+    std::unordered_map<uint64_t, std::unique_ptr<SrvRequest>> reqs;
+    uint64_t next_ticket = 1;
+    std::vector<double> lat_ms;
+    int64_t solves_done = 0, submitted = 0, requests_done = 0;
+    double t_first = -1.0, t_last = 0.0;
+    int worker_status = DDLR_OK;
+    std::string worker_err;
+};
+
+namespace {
+
+double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// One pass of the engine: admit queued columns into free slots, run `tick`
+// iterations on every matrix that has lanes, retire finished lanes.
+bool server_step(ddlr_server* S) {
+    struct Adm {
+        int slot;
+        SrvRequest* r;
+        int col;
+    };
+    std::vector<std::vector<Adm>> adm(S->mats.size());
+    bool any = false;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        for (auto it = S->queue.begin(); it != S->queue.end();) {
+            SrvRequest* r = *it;
+            SrvMatrix& M = *S->mats[r->mid];
+            for (int sl = 0; sl < S->slots && r->next_col < r->nrhs; ++sl)
+                if (!M.slot_req[sl]) {
+                    M.slot_req[sl] = r;
+                    M.slot_col[sl] = r->next_col;
+                    adm[r->mid].push_back({sl, r, r->next_col});
+                    r->next_col++;
+                }
+            if (r->next_col == r->nrhs) it = S->queue.erase(it);
+            else ++it;
+        }
+        for (auto& M : S->mats)
+            for (SrvRequest* r : M->slot_req) any = any || r;
+    }
+    if (!any) return false;
+    const int ns = S->slots;
+    for (size_t mi = 0; mi < S->mats.size(); ++mi) {
+        SrvMatrix& M = *S->mats[mi];
+        ddlr_prec* h = M.h;
+        const int64_t n = h->ndev;
+        if (!adm[mi].empty()) {
+            std::vector<int32_t> start(ns, 0), maxit(ns, 0);
+            std::vector<double> tol2(ns, 0.0);
+            for (const Adm& a : adm[mi]) {
+                HIPCHK(hipMemcpyAsync(M.stage + (size_t)a.slot * n, a.r->b + (size_t)a.col * n, n * sizeof(double),
+                                      hipMemcpyHostToDevice, M.st));
+                hipLaunchKernelGGL((k_gather<double, double>), dim3(grid_for(n)), dim3(256), 0, M.st, n, 1, h->perm_dev,
+                                   M.stage + (size_t)a.slot * n, n, h->ws.r + (size_t)a.slot * n, n);
+                LAUNCHCHK();
+                start[a.slot] = 1;
+                tol2[a.slot] = a.r->tol2;
+                maxit[a.slot] = a.r->maxit;
+            }
+            lane_admit(h, ns, start, tol2, maxit, M.st);
+        }
+        bool occupied = false;
+        for (SrvRequest* r : M.slot_req) occupied = occupied || r;
+        if (!occupied) continue;
+        for (int c = 0; c < S->tick; ++c) lane_iteration(h, ns, M.st);
+        HIPCHK(hipMemcpyAsync(M.lanes_h.data(), h->ws.lanes, ns * sizeof(CgLane), hipMemcpyDeviceToHost, M.st));
+    }
+    for (auto& Mp : S->mats) HIPCHK(hipStreamSynchronize(Mp->st));
+    // retire finished lanes
+    for (size_t mi = 0; mi < S->mats.size(); ++mi) {
+        SrvMatrix& M = *S->mats[mi];
+        ddlr_prec* h = M.h;
+        const int64_t n = h->ndev;
+        std::vector<int> fin;
+        for (int sl = 0; sl < ns; ++sl)
+            if (M.slot_req[sl] && M.lanes_h[sl].phase == 3) fin.push_back(sl);
+        if (fin.empty()) continue;
+        for (int sl : fin) {
+            hipLaunchKernelGGL((k_scatter<double, double>), dim3(grid_for(n)), dim3(256), 0, M.st, n, 1, h->perm_dev,
+                               h->ws.x + (size_t)sl * n, n, M.stage + (size_t)sl * n, n);
+            LAUNCHCHK();
+            SrvRequest* r = M.slot_req[sl];
+            HIPCHK(hipMemcpyAsync(r->x + (size_t)M.slot_col[sl] * n, M.stage + (size_t)sl * n, n * sizeof(double),
+                                  hipMemcpyDeviceToHost, M.st));
+        }
+        HIPCHK(hipStreamSynchronize(M.st));
+        const double t = now_s();
+        std::lock_guard<std::mutex> lk(S->mu);
+        for (int sl : fin) {
+            SrvRequest* r = M.slot_req[sl];
+            const CgLane& l = M.lanes_h[sl];
+            ddlr_solve_info& inf = r->info[M.slot_col[sl]];
+            const bool conv = l.bb == 0.0 || l.rr <= l.tol2 * l.bb;
+            inf.iters = l.its;
+            inf.status = conv ? DDLR_OK : DDLR_E_NO_CONVERGENCE;
+            inf.relres = l.bb > 0 ? std::sqrt(l.rr / l.bb) : 0.0;
+            inf.relres_true = -1.0;  // not computed by the server
+            r->done_cols++;
+            S->solves_done++;
+            M.slot_req[sl] = nullptr;
+            if (r->done_cols == r->nrhs) {
+                r->done = true;
+                r->t_done = t;
+                S->lat_ms.push_back(1e3 * (t - r->t_submit));
+                S->requests_done++;
+                S->t_last = t;
+            }
+        }
+        S->cv_done.notify_all();
+    }
+    return true;
+}
+
+void server_loop(ddlr_server* S) {
+    try {
+        HIPCHK(hipSetDevice(S->device));
+        while (true) {
+            {
+                std::unique_lock<std::mutex> lk(S->mu);
+                if (S->stop) break;
+            }
+            if (!server_step(S)) {
+                std::unique_lock<std::mutex> lk(S->mu);
+                if (S->stop) break;
+                S->cv.wait_for(lk, std::chrono::milliseconds(2));
+            }
+        }
+    } catch (const SetupError& e) {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->worker_status = e.status;
+        S->worker_err = e.msg;
+        S->cv_done.notify_all();
+    }
+}
+
+size_t prec_bytes(const ddlr_prec* h) { return h->mem.bytes + h->lrmem.bytes + h->ws.mem.bytes + h->ws.gmem.bytes; }
+
+}  // namespace
+
+extern "C" {
+
+ddlr_status ddlr_server_create(int32_t device, size_t hbm_budget_bytes, int32_t slots_per_matrix, ddlr_server** out) {
+    if (out) *out = nullptr;
+    if (!out || device < 0 || slots_per_matrix < 1 || slots_per_matrix > kMaxRhs) {
+        g_err = "bad server arguments (1 <= slots_per_matrix <= 16)";
+        return DDLR_E_INVALID;
+    }
+    std::unique_ptr<ddlr_server> S(new ddlr_server());
+    S->device = device;
+    S->budget = hbm_budget_bytes;
+    S->slots = slots_per_matrix;
+    try {
+        HIPCHK(hipSetDevice(device));
+    } catch (const SetupError& e) {
+        return fail_status(e);
+    }
+    ddlr_server* raw = S.get();
+    S->worker = std::thread(server_loop, raw);
+    *out = S.release();
+    return DDLR_OK;
+}
+
+ddlr_status ddlr_server_add(ddlr_server* S, ddlr_prec* h, int32_t* matrix_id) {
+    if (!S || !h || !matrix_id || h->device != S->device || h->nsys != 1) {
+        g_err = "bad server_add arguments (single-system handle on the server's device)";
+        return DDLR_E_INVALID;
+    }
+    std::unique_ptr<SrvMatrix> M(new SrvMatrix());
+    M->h = h;
+    try {
+        HIPCHK(hipSetDevice(S->device));
+        std::lock_guard<std::mutex> lk(S->mu);
+        const size_t before = prec_bytes(h);
+        const size_t stage = (size_t)h->ndev * S->slots * sizeof(double);
+        // workspace for the slots, then the budget check on everything resident
+        ensure_ws(h, S->slots);
+        const size_t need = prec_bytes(h) + stage;
+        if (S->budget > 0 && S->used + need > S->budget) {
+            (void)before;
+            g_err = "HBM budget exceeded: " + std::to_string((S->used + need) >> 20) + " MiB > " +
+                    std::to_string(S->budget >> 20) + " MiB";
+            return DDLR_E_BUDGET;
+        }
+        M->stage = M->mem.alloc<double>((size_t)h->ndev * S->slots);
+        HIPCHK(hipStreamCreateWithFlags(&M->st, hipStreamNonBlocking));  // default priority
+        M->bytes = need;
+        M->slot_req.assign(S->slots, nullptr);
+        M->slot_col.assign(S->slots, 0);
+        M->lanes_h.resize(S->slots);
+        // no lane is active until admitted
+        std::vector<int32_t> none(S->slots, 0), mx(S->slots, 0);
+        std::vector<double> tz(S->slots, 0.0);
+        HIPCHK(hipMemset(h->ws.lanes, 0, S->slots * sizeof(CgLane)));
+        HIPCHK(hipDeviceSynchronize());
+        S->used += need;
+        *matrix_id = (int32_t)S->mats.size();
+        S->mats.push_back(std::move(M));
+    } catch (const SetupError& e) {
+        return fail_status(e);
+    }
+    return DDLR_OK;
+}
+
+ddlr_status ddlr_server_submit(ddlr_server* S, int32_t matrix_id, int32_t nrhs, const double* b_host, double* x_host,
+                               const ddlr_solve_options* opt_in, uint64_t* ticket) {
+    if (!S || !b_host || !x_host || !ticket || nrhs < 1) {
+        g_err = "bad submit arguments";
+        return DDLR_E_INVALID;
+    }
+    ddlr_solve_options o;
+    if (opt_in) o = *opt_in;
+    else ddlr_solve_options_default(&o);
+    if (o.method != 0 || o.maxit < 1 || !(o.rtol > 0.0)) {
+        g_err = "the server runs CG (method 0) with maxit >= 1 and rtol > 0";
+        return DDLR_E_INVALID;
+    }
+    std::unique_ptr<SrvRequest> r(new SrvRequest());
+    r->nrhs = nrhs;
+    r->b = b_host;
+    r->x = x_host;
+    r->tol2 = o.rtol * o.rtol;
+    r->maxit = o.maxit;
+    r->info.assign(nrhs, ddlr_solve_info{0, 0, 0.0, 0.0});
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        if (S->worker_status != DDLR_OK) {
+            g_err = S->worker_err;
+            return (ddlr_status)S->worker_status;
+        }
+        if (matrix_id < 0 || matrix_id >= (int32_t)S->mats.size()) {
+            g_err = "unknown matrix id";
+            return DDLR_E_INVALID;
+        }
+        if (!S->mats[matrix_id]->h->spd) {
+            g_err = "preconditioner is not certified SPD";
+            return DDLR_E_NOT_SPD;
+        }
+        r->mid = matrix_id;
+        r->ticket = S->next_ticket++;
+        r->t_submit = now_s();
+        if (S->t_first < 0) S->t_first = r->t_submit;
+        S->submitted++;
+        *ticket = r->ticket;
+        S->queue.push_back(r.get());
+        S->reqs[r->ticket] = std::move(r);
+    }
+    S->cv.notify_all();
+    return DDLR_OK;
+}
+
+ddlr_status ddlr_server_poll(ddlr_server* S, uint64_t ticket, int32_t* done, ddlr_solve_info* info) {
+    if (!S || !done) {
+        g_err = "null argument";
+        return DDLR_E_INVALID;
+    }
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (S->worker_status != DDLR_OK) {
+        g_err = S->worker_err;
+        return (ddlr_status)S->worker_status;
+    }
+    auto it = S->reqs.find(ticket);
+    if (it == S->reqs.end()) {
+        g_err = "unknown ticket";
+        return DDLR_E_INVALID;
+    }
+    *done = it->second->done ? 1 : 0;
+    if (it->second->done && info) std::copy(it->second->info.begin(), it->second->info.end(), info);
+    return DDLR_OK;
+}
+
+ddlr_status ddlr_server_wait(ddlr_server* S, uint64_t ticket, ddlr_solve_info* info) {
+    if (!S) {
+        g_err = "null argument";
+        return DDLR_E_INVALID;
+    }
+    std::unique_lock<std::mutex> lk(S->mu);
+    auto it = S->reqs.find(ticket);
+    if (it == S->reqs.end()) {
+        g_err = "unknown ticket";
+        return DDLR_E_INVALID;
+    }
+    SrvRequest* r = it->second.get();
+    S->cv_done.wait(lk, [&] { return r->done || S->worker_status != DDLR_OK; });
+    if (S->worker_status != DDLR_OK) {
+        g_err = S->worker_err;
+        return (ddlr_status)S->worker_status;
+    }
+    if (info) std::copy(r->info.begin(), r->info.end(), info);
+    for (const ddlr_solve_info& i : r->info)
+        if (i.status != DDLR_OK) return DDLR_E_NO_CONVERGENCE;
+    return DDLR_OK;
+}
+
+ddlr_status ddlr_server_stats(ddlr_server* S, ddlr_server_counters* st) {
+    if (!S || !st) {
+        g_err = "null argument";
+        return DDLR_E_INVALID;
+    }
+    std::lock_guard<std::mutex> lk(S->mu);
+    std::memset(st, 0, sizeof(*st));
+    std::vector<double> l = S->lat_ms;
+    std::sort(l.begin(), l.end());
+    auto pct = [&](double q) {
+        if (l.empty()) return 0.0;
+        const double pos = q * (l.size() - 1);
+        const size_t lo = (size_t)pos;
+        const size_t hi = std::min(lo + 1, l.size() - 1);
+        return l[lo] + (pos - lo) * (l[hi] - l[lo]);
+    };
+    st->requests_submitted = S->submitted;
+    st->requests_done = S->requests_done;
+    st->solves_done = S->solves_done;
+    st->queued = (int64_t)S->queue.size();
+    st->p50_ms = pct(0.50);
+    st->p99_ms = pct(0.99);
+    const double span = S->t_last - S->t_first;
+    st->solves_per_s = (span > 0 && S->solves_done > 0) ? S->solves_done / span : 0.0;
+    st->hbm_used = S->used;
+    st->hbm_budget = S->budget;
+    st->matrices = (int32_t)S->mats.size();
+    return DDLR_OK;
+}
+
+void ddlr_server_destroy(ddlr_server* S) {
+    if (!S) return;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->stop = true;
+    }
+    S->cv.notify_all();
+    if (S->worker.joinable()) S->worker.join();
+    (void)hipSetDevice(S->device);
+    (void)hipDeviceSynchronize();
+    for (auto& M : S->mats) {
+        if (M->st) (void)hipStreamDestroy(M->st);
+        M->mem.release();
+    }
+    delete S;
 }
 
 }  // extern "C"

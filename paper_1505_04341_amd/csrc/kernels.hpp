@@ -751,46 +751,89 @@ __global__ __launch_bounds__(256) void k_dot(int64_t n, int nrhs, const TA* __re
 }
 
 // Per right-hand-side state of the CG iteration (device resident).
+// phase: 0 idle, 1 initialising (r = b, x = 0, p = 0 on entry), 2 running,
+// 3 finished.  active == (phase == 2).  A lane in phase 1 runs one pass of the
+// iteration kernels with alpha = 0 (x and r unchanged) that computes
+// bb = ||b||^2, z = M^{-1} r, rz = r.z and p = z, exactly the CG start, so a
+// lane's arithmetic does not depend on when it entered or on other lanes.
 struct CgLane {
-    double bb, rz, rr, alpha, beta;
-    int32_t active, its;
+    double bb, rz, rr, alpha, beta, tol2;
+    int32_t active, its, phase, maxit;
 };
 
-// what: 0 = init (bb, rr from ||b||^2), 1 = first rz, 2 = alpha = rz / p^T q,
-//       3 = residual check after the x, r update, 4 = beta from the new rz
-// sums[r] holds the reduced dot product of right-hand side r.
-__global__ void k_cg_scalar(int what, int nrhs, const double* __restrict__ sums, CgLane* __restrict__ L, double tol2,
-                            int maxit, int* __restrict__ done) {
-    if (what != 0 && done && *done) return;
-    const int r = threadIdx.x;
-    if (r < nrhs) {
-        const double s = sums[r];
+// Lane-phase CG scalars (one thread per lane, blockDim >= nlanes); sums[r]
+// is the reduced dot product of lane r.  what: 2 alpha (p.Ap), 3 residual
+// check / initialisation of bb, 4 beta (r.z).  done := no lane initialising
+// or running.
+__global__ void k_lane_scalar(int what, int nlanes, const double* __restrict__ sums, CgLane* __restrict__ L,
+                              int* __restrict__ done) {
+    if (done && *done) return;
+    __shared__ int any;
+    if (threadIdx.x == 0) any = 0;
+    __syncthreads();
+    for (int r = threadIdx.x; r < nlanes; r += blockDim.x) {
         CgLane& l = L[r];
-        switch (what) {
-        case 0: l.bb = s; l.rr = s; l.its = 0; l.active = s > 0.0; l.rz = 0; l.alpha = 0; l.beta = 0; break;
-        case 1: l.rz = s; break;
-        case 2: l.alpha = l.active ? l.rz / s : 0.0; break;
-        case 3:
-            if (l.active) {
+        const double s = sums[r];
+        if (what == 2) {
+            l.alpha = l.phase == 2 ? l.rz / s : 0.0;
+        } else if (what == 3) {
+            if (l.phase == 1) {
+                l.bb = s;
+                l.rr = s;
+                if (!(s > 0.0)) { l.phase = 3; l.active = 0; }
+            } else if (l.phase == 2) {
                 l.rr = s;
                 l.its += 1;
-                if (s <= tol2 * l.bb || l.its >= maxit) l.active = 0;
+                if (s <= l.tol2 * l.bb || l.its >= l.maxit) { l.phase = 3; l.active = 0; }
             }
-            break;
-        case 4:
-            if (l.active) {
+        } else if (what == 4) {
+            if (l.phase == 1) {
+                l.rz = s;
+                l.beta = 0.0;
+                l.phase = 2;
+                l.active = 1;
+            } else if (l.phase == 2) {
                 l.beta = s / l.rz;
                 l.rz = s;
             }
-            break;
         }
+        if (l.phase == 1 || l.phase == 2) any = 1;  // benign race: every writer stores 1
     }
-    if (what == 0 || what == 3) {
-        __syncthreads();
-        if (threadIdx.x == 0 && done) {
-            int any = 0;
-            for (int q = 0; q < nrhs; ++q) any |= L[q].active;
-            *done = any ? 0 : 1;
+    __syncthreads();
+    if (what == 3 && threadIdx.x == 0 && done) *done = any ? 0 : 1;
+}
+
+// Admission of lanes: lane r in [0, nlanes) with start[r] != 0 enters phase 1
+// with its tolerance and iteration limit; its x and p columns are zeroed.
+__global__ void k_lane_admit(int nlanes, const int32_t* __restrict__ start, const double* __restrict__ tol2,
+                             const int32_t* __restrict__ maxit, CgLane* __restrict__ L, int* __restrict__ done) {
+    const int r = threadIdx.x;
+    if (r < nlanes && start[r]) {
+        CgLane& l = L[r];
+        l.bb = l.rz = l.rr = l.alpha = l.beta = 0.0;
+        l.tol2 = tol2[r];
+        l.maxit = maxit[r];
+        l.its = 0;
+        l.phase = 1;
+        l.active = 0;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && done) {
+        int any = 0;
+        for (int q = 0; q < nlanes; ++q) any |= (L[q].phase == 1 || L[q].phase == 2);
+        *done = any ? 0 : 1;
+    }
+}
+
+// x[:, r] = 0 and p[:, r] = 0 for admitted lanes
+__global__ void k_lane_zero(int64_t n, int nlanes, const int32_t* __restrict__ start, double* __restrict__ x,
+                            double* __restrict__ p, int64_t ld) {
+    const int64_t total = n * nlanes;
+    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = g / n, i = g - r * n;
+        if (start[r]) {
+            x[i + r * ld] = 0.0;
+            p[i + r * ld] = 0.0;
         }
     }
 }

@@ -405,3 +405,61 @@ def test_batch_matches_single_and_oracle(prec):
         yq = torch.empty_like(b)
         D.ddlr_apply(h, b, yq)
         assert rel(y.cpu().numpy()[off[q]:off[q + 1]], yq.cpu().numpy()) <= (1e-12 if prec == D.FP64 else 1e-6)
+
+
+def test_serving_same_alone_and_in_mix():
+    """Continuous batching: a right-hand side solved alone, by the server with
+    an otherwise empty queue, and by the server inside a stream of requests on
+    three matrices (requests arriving while others run, more columns than
+    lanes) gives bitwise the same x."""
+    import time
+    cfgs = [w.config("c1"), w.config("small3d"), irregular()]
+    hs, refs, bsets = [], [], []
+    for q, cfg in enumerate(cfgs):
+        say("serving setup", q)
+        h = D.ddlr_setup(cfg["A"], cfg["part"], cfg["p"], cfg["k"], 1, lanczos_steps=cfg["m"],
+                         lanczos_start=w.lanczos_start(cfg["A"].n, 0), precision=D.FP32)
+        b, _ = w.rhs_from_solution(cfg["A"], 10 * q, 6)
+        bt = torch.from_numpy(np.ascontiguousarray(b.T)).to(DEV)
+        xt = torch.zeros_like(bt)
+        st, info = D.ddlr_solve(h, bt, xt)
+        assert st == D.OK
+        hs.append(h)
+        refs.append(xt.cpu().numpy().T)
+        bsets.append(b)
+    srv = D.ddlr_server_create(0, 0, 4)
+    mids = [D.ddlr_server_add(srv, h) for h in hs]
+    # alone
+    t, x = D.ddlr_server_submit(srv, mids[1], bsets[1][:, 2])
+    st, info = D.ddlr_server_wait(srv, t)
+    assert st == D.OK and np.array_equal(x[:, 0], refs[1][:, 2])
+    # in a mix: random matrices, 1..6 columns, staggered arrivals
+    rng = np.random.default_rng(5)
+    jobs = []
+    for j in range(24):
+        q = int(rng.integers(0, 3))
+        cols = sorted(rng.choice(6, size=int(rng.integers(1, 7)), replace=False))
+        t, x = D.ddlr_server_submit(srv, mids[q], bsets[q][:, cols])
+        jobs.append((t, x, q, cols))
+        time.sleep(float(rng.exponential(0.002)))
+    for t, x, q, cols in jobs:
+        st, info = D.ddlr_server_wait(srv, t)
+        assert st == D.OK
+        assert all(i["relres"] <= 1e-6 for i in info)
+        assert np.array_equal(x, refs[q][:, cols]), (q, cols)
+    stats = D.ddlr_server_stats(srv)
+    assert stats["requests_done"] == 25 and stats["queued"] == 0
+    assert stats["p99_ms"] >= stats["p50_ms"] > 0 and stats["solves_per_s"] > 0
+    say("serving stats", stats)
+    del srv
+
+
+def test_serving_budget_admission():
+    cfg = w.config("small3d")
+    h = D.ddlr_setup(cfg["A"], cfg["part"], cfg["p"], cfg["k"], 1, lanczos_steps=cfg["m"],
+                     lanczos_start=w.lanczos_start(cfg["A"].n, 0))
+    srv = D.ddlr_server_create(0, 1 << 20, 4)  # 1 MiB cannot hold the matrix
+    with pytest.raises(D.DDLRError) as e:
+        D.ddlr_server_add(srv, h)
+    assert e.value.status == D.E_BUDGET
+    del srv
