@@ -76,7 +76,7 @@ typedef struct {
     int32_t corder;        /* ddlr_corder: order of the interface block inside C_alpha's factor */
     int32_t precision;     /* ddlr_precision of the preconditioner; Krylov is always FP64 */
     int32_t device;        /* HIP device ordinal; -1 = host-only setup (ordering and factors only) */
-    int32_t reserved;
+    int32_t no_autotune;   /* 0: tune launch shapes on the first solve with a column count (default) */
     uint64_t seed;                /* Lanczos start vector when lanczos_start is NULL */
     const double *lanczos_start;  /* host, length n, user order: its interface entries form q_1 */
 } ddlr_options;
@@ -200,6 +200,28 @@ ddlr_status ddlr_profile(ddlr_prec *h, int32_t on);
  * profiling was enabled.  Synchronises the device. */
 ddlr_status ddlr_profile_read(ddlr_prec *h, int32_t which, double *total_ms, int64_t *launches);
 
+/* Launch-shape autotuner.  The block triangular solve of the A0 solve (the
+ * local solves of Sec. 4.2, steps 1 and 5) can give a workgroup 1, 2, 4 or 8
+ * right-hand sides of one block, sharing the block's factor entries between
+ * them, and the interface block's level kernels can run beside it on a side
+ * stream or in line.  The first solve, apply or A0 solve with a given column
+ * count times the eligible shapes on the device (HIP events, a few
+ * milliseconds) and keeps the fastest; every shape does the same arithmetic
+ * in the same order, so results do not depend on the choice.  ddlr_tune runs
+ * (retune != 0: re-runs) the tuner for nrhs in 1..16 on `stream` and reports
+ * the choice and the measured times; it synchronises the stream.  Batches
+ * (ddlr_batch_*) use fixed shapes.  Setting options.no_autotune keeps the
+ * defaults (one column per workgroup, overlap on) unless ddlr_tune is called. */
+typedef struct {
+    int32_t nrhs;            /* column count the shape is for */
+    int32_t ring_cols;       /* right-hand sides per workgroup of the block triangular solve */
+    int32_t overlap;         /* 1: interface levels on the side stream, 0: in line */
+    int32_t reserved;
+    float a0_us[4];          /* A0 solve time with 1, 2, 4, 8 columns per workgroup (0: not eligible) */
+    float a0_no_overlap_us;  /* best shape with the interface levels in line (0: not measured) */
+} ddlr_tuning;
+ddlr_status ddlr_tune(ddlr_prec *h, int32_t nrhs, int32_t retune, ddlr_tuning *out, void *stream);
+
 /* Releases everything the handle owns.  NULL is ignored. */
 void ddlr_destroy(ddlr_prec *h);
 
@@ -252,6 +274,9 @@ void ddlr_batch_destroy(ddlr_batch *b);
  *   relres_true is not computed by the server (-1).
  * ddlr_server_stats: counters, solves/s over the span from the first submit
  *   to the last completion, p50 / p99 request latency (submit to completion).
+ * ddlr_server_reset_stats: starts a new measurement window: clears the
+ *   latency record and the submitted / done / solves counters; requests in
+ *   flight are counted in the new window when they complete.
  */
 typedef struct ddlr_server ddlr_server;
 typedef struct {
@@ -267,6 +292,7 @@ ddlr_status ddlr_server_submit(ddlr_server *s, int32_t matrix_id, int32_t nrhs, 
 ddlr_status ddlr_server_poll(ddlr_server *s, uint64_t ticket, int32_t *done, ddlr_solve_info *info);
 ddlr_status ddlr_server_wait(ddlr_server *s, uint64_t ticket, ddlr_solve_info *info);
 ddlr_status ddlr_server_stats(ddlr_server *s, ddlr_server_counters *stats);
+ddlr_status ddlr_server_reset_stats(ddlr_server *s);
 void ddlr_server_destroy(ddlr_server *s);
 
 const char *ddlr_status_string(int32_t status);

@@ -62,8 +62,15 @@ def _load():
         lib.orc_gmres.restype = C.c_int
         lib.orc_gmres.argtypes = [P, C.c_int, P, P, C.c_int, C.c_double, C.c_int, P, P]
         lib.orc_matvec.argtypes = [P, P, P]
+        lib.orc_threads.restype = C.c_int
+        lib.orc_threads.argtypes = []
         _lib = lib
     return _lib
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's parallel loops use."""
+    return int(_load().orc_threads())
 
 
 def _p(a: np.ndarray):

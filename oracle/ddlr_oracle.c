@@ -37,6 +37,9 @@
 #include <stdint.h>
 #include <stdio.h>
 #include <stdlib.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <string.h>
 
 #define ORC_OK 0
@@ -1050,3 +1053,12 @@ int orc_gmres(const orc_t *o, int nrhs, const double *b, double *x, int restart,
 
 /* y = A x in user order (used by tests for residuals) */
 void orc_matvec(const orc_t *o, const double *x, double *y) { csr_mv(&o->A, o->n, x, y); }
+
+/* number of OpenMP threads the parallel loops above run with */
+int orc_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

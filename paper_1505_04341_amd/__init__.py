@@ -33,7 +33,16 @@ class ddlr_csr(C.Structure):
 class ddlr_options(C.Structure):
     _fields_ = [("alpha", C.c_double), ("lanczos_steps", C.c_int32), ("theta", C.c_int32),
                 ("factor", C.c_int32), ("corder", C.c_int32), ("precision", C.c_int32), ("device", C.c_int32),
-                ("reserved", C.c_int32), ("seed", C.c_uint64), ("lanczos_start", C.c_void_p)]
+                ("no_autotune", C.c_int32), ("seed", C.c_uint64), ("lanczos_start", C.c_void_p)]
+
+
+class ddlr_tuning(C.Structure):
+    _fields_ = [("nrhs", C.c_int32), ("ring_cols", C.c_int32), ("overlap", C.c_int32), ("reserved", C.c_int32),
+                ("a0_us", C.c_float * 4), ("a0_no_overlap_us", C.c_float)]
+
+    def as_dict(self):
+        return dict(nrhs=self.nrhs, ring_cols=self.ring_cols, overlap=self.overlap, a0_us=list(self.a0_us),
+                    a0_no_overlap_us=self.a0_no_overlap_us)
 
 
 class ddlr_solve_options(C.Structure):
@@ -114,7 +123,9 @@ def load_library(path: str = LIB_PATH):
         "ddlr_server_poll": (I32, [P, C.c_uint64, P, P]),
         "ddlr_server_wait": (I32, [P, C.c_uint64, P]),
         "ddlr_server_stats": (I32, [P, P]),
+        "ddlr_server_reset_stats": (I32, [P]),
         "ddlr_server_destroy": (None, [P]),
+        "ddlr_tune": (I32, [P, I32, I32, P, P]),
         "ddlr_destroy": (None, [P]),
         "ddlr_status_string": (C.c_char_p, [I32]),
         "ddlr_last_error": (C.c_char_p, []),
@@ -178,7 +189,8 @@ class Prec:
 
 def ddlr_setup(A, part, p: int, k: int, variant: int = DDLR_1, *, alpha: float = 1.0, lanczos_steps: int = 0,
                theta: int = THETA_LAMBDA_K1, factor: int = FACTOR_IC0, corder: int = CORDER_MULTICOLOR,
-               precision: int = FP64, device: int = 0, seed: int = 0, lanczos_start=None) -> Prec:
+               precision: int = FP64, device: int = 0, seed: int = 0, lanczos_start=None,
+               autotune: bool = True) -> Prec:
     """Builds the preconditioner. A: object with n, rowptr (int64), col (int32), val (float64)."""
     lib = load_library()
     rp = np.ascontiguousarray(A.rowptr, dtype=np.int64)
@@ -191,6 +203,7 @@ def ddlr_setup(A, part, p: int, k: int, variant: int = DDLR_1, *, alpha: float =
     opt.alpha, opt.lanczos_steps, opt.theta = float(alpha), int(lanczos_steps), int(theta)
     opt.factor, opt.corder, opt.precision, opt.device, opt.seed = int(factor), int(corder), int(precision), int(
         device), int(seed)
+    opt.no_autotune = 0 if autotune else 1
     v0 = None
     if lanczos_start is not None:
         v0 = np.ascontiguousarray(lanczos_start, dtype=np.float64)
@@ -440,6 +453,18 @@ def ddlr_server_stats(server: Server) -> dict:
     return c.as_dict()
 
 
+def ddlr_tune(prec: Prec, nrhs: int, retune: bool = False, stream=None) -> dict:
+    """Runs (or reports) the launch-shape autotuner for nrhs columns."""
+    t = ddlr_tuning()
+    _check(load_library().ddlr_tune(prec.handle, int(nrhs), 1 if retune else 0, C.byref(t), _stream(stream)),
+           "ddlr_tune")
+    return t.as_dict()
+
+
+def ddlr_server_reset_stats(server: Server) -> None:
+    _check(load_library().ddlr_server_reset_stats(server.handle), "ddlr_server_reset_stats")
+
+
 PROF_TRSV_BLOCKS, PROF_TRSV_LEVELS, PROF_SPMV, PROF_LOWRANK = 0, 1, 2, 3
 
 
@@ -465,5 +490,5 @@ EXPORTED = ["ddlr_version", "ddlr_options_default", "ddlr_solve_options_default"
             "ddlr_get_levels", "ddlr_get_lanczos", "ddlr_get_lowrank", "ddlr_set_lowrank", "ddlr_profile",
             "ddlr_profile_read", "ddlr_batch_create", "ddlr_batch_offsets", "ddlr_batch_apply",
             "ddlr_batch_solve", "ddlr_batch_destroy", "ddlr_server_create", "ddlr_server_add", "ddlr_server_submit",
-            "ddlr_server_poll", "ddlr_server_wait", "ddlr_server_stats", "ddlr_server_destroy", "ddlr_destroy",
+            "ddlr_server_poll", "ddlr_server_wait", "ddlr_server_stats", "ddlr_server_reset_stats", "ddlr_server_destroy", "ddlr_tune", "ddlr_destroy",
             "ddlr_status_string", "ddlr_last_error"]

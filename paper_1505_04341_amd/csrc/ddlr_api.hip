@@ -5,6 +5,7 @@
 #include <chrono>
 #include <condition_variable>
 #include <deque>
+#include <map>
 #include <mutex>
 #include <thread>
 #include <unordered_map>
@@ -72,6 +73,9 @@ int grid_for(int64_t work, int block = 256, int cap = 8192) {
     return (int)g;
 }
 
+// 2-D grid (row chunks, right-hand sides) for the column kernels
+dim3 grid2(int64_t rows, int nrhs) { return dim3(grid_for(rows, 256, std::max(32, 8192 / std::max(nrhs, 1))), nrhs); }
+
 // Factors of A0 in one precision, device order.
 template <typename T> struct DevFactors {
     T *lv = nullptr, *uv = nullptr, *dinv = nullptr;
@@ -130,6 +134,17 @@ struct ddlr_prec {
     float *fval32 = nullptr, *bval32 = nullptr;
     int ring_kw = 0;                          // 2, 3, 4, 8, 16 or 0 (ring kernel unusable)
     bool ring_ok64 = false, ring_ok32 = false;  // dependency window fits the LDS ring
+    int ring_need = 0;                          // rows the ring must hold (dependency window)
+    // autotuned launch shape per number of columns: columns per workgroup of
+    // the ring kernel (1, 2, 4, 8) and the interface-level overlap; both leave
+    // the arithmetic unchanged
+    struct Tune {
+        int ring_r = 1, overlap = 1;
+        float a0_us[4] = {0, 0, 0, 0};
+        float a0_noov_us = 0;
+    };
+    std::map<int, Tune> tune;
+    int tune_mode = 1;  // 1: tune on first use of a column count, 0: defaults
     bool lr_plain = false;                      // low-rank kernels without MFMA (comparison only)
     // the interface block's level kernels run on a side stream, overlapping the
     // B-block kernel (fork/join by events on the caller's stream)
@@ -352,7 +367,7 @@ void build_ring(ddlr_prec* h, const DevHost& D) {
     const std::vector<BlockDesc>& bd = D.narrow;
     const std::vector<int32_t>&lrp = D.lrp, &lci = D.lci, &urp = D.urp, &uci = D.uci;
     const int nlev = (int)D.lvl_ptr.size() - 1;
-    int kw = 0;
+    int kw = 0, need = 0;
     bool ok64 = true, ok32 = true;
     for (const BlockDesc& b : bd) {
         if (b.lvl1 - b.lvl0 > kRingMaxLevels) ok64 = ok32 = false;
@@ -365,11 +380,13 @@ void build_ring(ddlr_prec* h, const DevHost& D) {
                     const int c = lci[t] - row0;
                     ok64 = ok64 && c >= e - kRing64;
                     ok32 = ok32 && c >= e - kRing32;
+                    need = std::max(need, e - c);
                 }
                 for (int t = urp[row0 + i]; t < urp[row0 + i + 1]; ++t) {
                     const int c = uci[t] - row0;
                     ok64 = ok64 && c < a + kRing64;
                     ok32 = ok32 && c < a + kRing32;
+                    need = std::max(need, c - a + 1);
                 }
             }
         }
@@ -379,6 +396,7 @@ void build_ring(ddlr_prec* h, const DevHost& D) {
         if (env[0] == '1') h->ring_kw = 0;
     h->ring_ok64 = ok64 && h->ring_kw > 0;
     h->ring_ok32 = ok32 && h->ring_kw > 0;
+    h->ring_need = need;
     if (!h->ring_ok64 && !h->ring_ok32) return;
     const int KW = h->ring_kw;
     std::vector<int32_t> foff(nlev), boff(nlev), fcol, bcol;
@@ -499,6 +517,19 @@ constexpr int kSegChunks = 16;   // blocks per system in the per-system kernels 
 
 template <typename T> T* wsalloc(Workspace& W, size_t count) { return W.mem.alloc<T>(count); }
 
+// stride of the interleaved CG direction p: the power of two >= lanes
+int lane_stride(int lanes) {
+    int S = 1;
+    while (S < lanes) S <<= 1;
+    return S;
+}
+
+int ilog2(int v) {
+    int l = 0;
+    while ((1 << l) < v) ++l;
+    return l;
+}
+
 void ensure_ws(ddlr_prec* h, int nrhs) {
     Workspace& W = h->ws;
     if (W.nrhs >= nrhs) return;
@@ -514,7 +545,10 @@ void ensure_ws(ddlr_prec* h, int nrhs) {
     W.x = W.mem.alloc<double>(n * nrhs);
     W.r = W.mem.alloc<double>(n * nrhs);
     W.z = W.mem.alloc<double>(n * nrhs);
-    W.p = W.mem.alloc<double>(n * nrhs);
+    // p is interleaved inside CG (stride lane_stride(nrhs)); zeroed so the
+    // padding lanes hold finite values
+    W.p = W.mem.alloc<double>(n * lane_stride(nrhs));
+    HIPCHK(hipMemset(W.p, 0, sizeof(double) * n * lane_stride(nrhs)));
     W.q = W.mem.alloc<double>(n * nrhs);
     W.a0 = W.mem.alloc<char>(tsz * n * nrhs);
     W.a1 = W.mem.alloc<char>(tsz * n * nrhs);
@@ -611,6 +645,49 @@ void launch_ring(ddlr_prec* h, const T* dinv, int nrhs, const TIn* x, int64_t ld
     }
 }
 
+// R columns per workgroup (the ring holds ring_rows_r<T, R>() rows of R values)
+template <typename T> bool ring_r_ok(const ddlr_prec* h, int R) {
+    if (R == 1) return true;  // the one-column kernel, or the plain fallback
+    if (!ring_ready<T>(h) || h->ring_kw > 4) return false;
+    switch (R) {
+    case 2: return h->ring_need <= ring_rows_r<T, 2>();
+    case 4: return h->ring_need <= ring_rows_r<T, 4>();
+    case 8: return h->ring_need <= ring_rows_r<T, 8>();
+    default: return false;
+    }
+}
+
+template <typename T, int KW, int R, typename TIn, typename TOut>
+void launch_ring_rk(ddlr_prec* h, const T* dinv, int nrhs, const TIn* x, int64_t ldx, TOut* z, int64_t ldz,
+                    hipStream_t st, const int* done) {
+    const int ng = nrhs / R;
+    hipLaunchKernelGGL((k_trsv_ring_r<T, KW, R, TIn, TOut>), dim3(h->nnarrow_pad * ng), dim3(kRingThreads), 0, st,
+                       h->rblk, h->nnarrow, h->nnarrow_pad, ng, h->lvl_ptr, h->foff, h->fcol, ring_fval<T>(h), h->boff_,
+                       h->bcol, ring_bval<T>(h), dinv, x, ldx, z, ldz, done);
+    LAUNCHCHK();
+}
+
+template <typename T, int R, typename TIn, typename TOut>
+void launch_ring_r(ddlr_prec* h, const T* dinv, int nrhs, const TIn* x, int64_t ldx, TOut* z, int64_t ldz,
+                   hipStream_t st, const int* done) {
+    switch (h->ring_kw) {
+    case 2: launch_ring_rk<T, 2, R, TIn, TOut>(h, dinv, nrhs, x, ldx, z, ldz, st, done); break;
+    case 3: launch_ring_rk<T, 3, R, TIn, TOut>(h, dinv, nrhs, x, ldx, z, ldz, st, done); break;
+    default: launch_ring_rk<T, 4, R, TIn, TOut>(h, dinv, nrhs, x, ldx, z, ldz, st, done);
+    }
+}
+
+// columns per workgroup for an nrhs-column solve: the tuned choice, reduced
+// to a power of two that divides nrhs and fits the ring
+template <typename T> int ring_r_for(const ddlr_prec* h, int nrhs) {
+    int R = 1;
+    auto it = h->tune.find(nrhs);
+    if (it != h->tune.end()) R = it->second.ring_r;
+    if (const char* env = std::getenv("DDLR_RING_R")) R = std::atoi(env);
+    while (R > 1 && (nrhs % R != 0 || !ring_r_ok<T>(h, R))) R >>= 1;
+    return std::max(R, 1);
+}
+
 // Interface-block levels (multicolour order): forward levels, the last one
 // fused with the diagonal scaling, then backward levels.
 template <typename T, typename TIn, typename TOut>
@@ -620,7 +697,7 @@ void wide_levels(ddlr_prec* h, const DevFactors<T>& F, int nrhs, const TIn* x, i
     const int nl = (int)h->wide.size();
     for (int l = 0; l < nl; ++l) {
         const int a = h->wide[l].first, e = h->wide[l].second;
-        const dim3 g(grid_for((int64_t)(e - a) * nrhs, 256, 1 << 30));
+        const dim3 g((e - a + 255) / 256, nrhs);
         if (l + 1 < nl)
             hipLaunchKernelGGL((k_trsv_level<T, 0, TIn, TOut>), g, dim3(256), 0, st, a, e, nrhs, h->lrp, h->lci, F.lv,
                                F.dinv, x, ldx, z, ldz, done);
@@ -631,7 +708,7 @@ void wide_levels(ddlr_prec* h, const DevFactors<T>& F, int nrhs, const TIn* x, i
     }
     for (int l = nl - 2; l >= 0; --l) {
         const int a = h->wide[l].first, e = h->wide[l].second;
-        hipLaunchKernelGGL((k_trsv_level<T, 1, TIn, TOut>), dim3(grid_for((int64_t)(e - a) * nrhs, 256, 1 << 30)),
+        hipLaunchKernelGGL((k_trsv_level<T, 1, TIn, TOut>), dim3((e - a + 255) / 256, nrhs),
                            dim3(256), 0, st, a, e, nrhs, h->urp, h->uci, F.uv, F.dinv, x, ldx, z, ldz, done);
         LAUNCHCHK();
     }
@@ -641,7 +718,9 @@ void wide_levels(ddlr_prec* h, const DevFactors<T>& F, int nrhs, const TIn* x, i
 template <typename T, typename TIn, typename TOut>
 void a0_solve_dev(ddlr_prec* h, const DevFactors<T>& F, int nrhs, const TIn* x, int64_t ldx, TOut* z, int64_t ldz,
                   hipStream_t st, const int* done) {
-    const bool fork = !h->wide.empty() && h->nnarrow > 0 && h->overlap && h->side;
+    bool ov = h->overlap;
+    if (auto it = h->tune.find(nrhs); it != h->tune.end()) ov = ov && it->second.overlap;
+    const bool fork = !h->wide.empty() && h->nnarrow > 0 && ov && h->side;
     hipStream_t cst = st;
     if (fork) {
         HIPCHK(hipEventRecord(h->ev_fork, st));
@@ -652,7 +731,12 @@ void a0_solve_dev(ddlr_prec* h, const DevFactors<T>& F, int nrhs, const TIn* x, 
     if (h->nnarrow > 0) {
         ProfScope ps(h, 0, st);
         if (ring_ready<T>(h)) {
-            launch_ring<T, TIn, TOut>(h, F.dinv, nrhs, x, ldx, z, ldz, st, done);
+            switch (ring_r_for<T>(h, nrhs)) {
+            case 2: launch_ring_r<T, 2, TIn, TOut>(h, F.dinv, nrhs, x, ldx, z, ldz, st, done); break;
+            case 4: launch_ring_r<T, 4, TIn, TOut>(h, F.dinv, nrhs, x, ldx, z, ldz, st, done); break;
+            case 8: launch_ring_r<T, 8, TIn, TOut>(h, F.dinv, nrhs, x, ldx, z, ldz, st, done); break;
+            default: launch_ring<T, TIn, TOut>(h, F.dinv, nrhs, x, ldx, z, ldz, st, done);
+            }
         } else {
             hipLaunchKernelGGL((k_trsv_narrow<T, TIn, TOut>), dim3(h->nnarrow_pad * nrhs), dim3(256), 0, st, h->blk,
                                h->nnarrow, h->nnarrow_pad, nrhs, h->lvl_ptr, h->lrp, h->lci, F.lv, h->urp, h->uci,
@@ -728,7 +812,7 @@ void apply_dev_T(ddlr_prec* h, int nrhs, const double* in, int64_t ldin, double*
         T* ys = (T*)W.ys;
         T* wsv = (T*)W.ws;
         a0_solve_dev<T, double, T>(h, F, nrhs, in, ldin, a1, n, st, done);  // step 1: A0 z = x
-        hipLaunchKernelGGL((k_csr_mv<T, T>), dim3(grid_for(s * nrhs)), dim3(256), 0, st, s, nrhs, h->etrp, h->etci,
+        hipLaunchKernelGGL((k_csr_mv<T, T>), grid2(s, nrhs), dim3(256), 0, st, s, nrhs, h->etrp, h->etci,
                            F.etv, a1, n, (const T*)nullptr, 0, ys, s, done);  // step 2: y = E^T z
         LAUNCHCHK();
         if (h->nsys > 1) {  // per system of a batch (one column)
@@ -743,7 +827,7 @@ void apply_dev_T(ddlr_prec* h, int nrhs, const double* in, int64_t ldin, double*
             lr_coef<T, T>(h, F.U, s, nrhs, ys, s, 1, st, done);  // step 3: w = G_{k,theta}^{-1} y (eq. gkt)
             lr_expand<T, T>(h, F.U, s, nrhs, h->c0, ys, s, wsv, s, st, done);
         }
-        hipLaunchKernelGGL((k_csr_mv<T, double>), dim3(grid_for(n * nrhs)), dim3(256), 0, st, n, nrhs, h->erp, h->eci,
+        hipLaunchKernelGGL((k_csr_mv<T, double>), grid2(n, nrhs), dim3(256), 0, st, n, nrhs, h->erp, h->eci,
                            F.ev, wsv, s, in, ldin, a2, n, done);  // step 4: v = E w, fused x + v
         LAUNCHCHK();
         a0_solve_dev<T, T, double>(h, F, nrhs, a2, n, out, ldout, st, done);  // step 5: A0 u = x + v
@@ -767,8 +851,66 @@ void spmv_dev(ddlr_prec* h, int nrhs, const double* x, int64_t ldx, double* y, i
               hipStream_t st, const int* done) {
     const int64_t n = h->ndev;
     ProfScope ps(h, 2, st);
-    hipLaunchKernelGGL(k_spmv_sell, dim3((n + 255) / 256), dim3(256), 0, st, n, nrhs, h->sell_ptr, h->sell_col,
+    const int64_t chunks = (n + 255) / 256;
+    hipLaunchKernelGGL(k_spmv_sell, dim3((chunks + 7) / 8 * 8), dim3(256), 0, st, n, nrhs, h->sell_ptr, h->sell_col,
                        h->sell_val, x, ldx, y, ldy, part, done);
+    LAUNCHCHK();
+}
+
+// y = A x with x interleaved (x[i * S + r], S = lane_stride(nrhs))
+void spmv_il_dev(ddlr_prec* h, int nrhs, const double* x, double* y, int64_t ldy, double* part, hipStream_t st,
+                 const int* done) {
+    const int64_t n = h->ndev;
+    ProfScope ps(h, 2, st);
+    const int64_t chunks = (n + 255) / 256;
+    const dim3 grid((chunks + 7) / 8 * 8), blk(256);
+    switch (lane_stride(nrhs)) {
+        case 1:
+            hipLaunchKernelGGL(k_spmv_sell_il<1>, grid, blk, 0, st, n, nrhs, h->sell_ptr, h->sell_col, h->sell_val, x,
+                               y, ldy, part, done);
+            break;
+        case 2:
+            hipLaunchKernelGGL(k_spmv_sell_il<2>, grid, blk, 0, st, n, nrhs, h->sell_ptr, h->sell_col, h->sell_val, x,
+                               y, ldy, part, done);
+            break;
+        case 4:
+            hipLaunchKernelGGL(k_spmv_sell_il<4>, grid, blk, 0, st, n, nrhs, h->sell_ptr, h->sell_col, h->sell_val, x,
+                               y, ldy, part, done);
+            break;
+        case 8:
+            hipLaunchKernelGGL(k_spmv_sell_il<8>, grid, blk, 0, st, n, nrhs, h->sell_ptr, h->sell_col, h->sell_val, x,
+                               y, ldy, part, done);
+            break;
+        default:
+            hipLaunchKernelGGL(k_spmv_sell_il<16>, grid, blk, 0, st, n, nrhs, h->sell_ptr, h->sell_col, h->sell_val,
+                               x, y, ldy, part, done);
+            break;
+    }
+    LAUNCHCHK();
+}
+
+// x += alpha p ; r -= alpha q per lane (p interleaved)
+void cg_xr_dev(ddlr_prec* h, int nr, hipStream_t st) {
+    Workspace& W = h->ws;
+    const int64_t n = h->ndev;
+    const dim3 grid(kRedBlocks), blk(256);
+    switch (lane_stride(nr)) {
+        case 1:
+            hipLaunchKernelGGL(k_cg_xr<1>, grid, blk, 0, st, n, nr, W.lanes, W.p, W.q, W.x, W.r, n, W.part, W.done);
+            break;
+        case 2:
+            hipLaunchKernelGGL(k_cg_xr<2>, grid, blk, 0, st, n, nr, W.lanes, W.p, W.q, W.x, W.r, n, W.part, W.done);
+            break;
+        case 4:
+            hipLaunchKernelGGL(k_cg_xr<4>, grid, blk, 0, st, n, nr, W.lanes, W.p, W.q, W.x, W.r, n, W.part, W.done);
+            break;
+        case 8:
+            hipLaunchKernelGGL(k_cg_xr<8>, grid, blk, 0, st, n, nr, W.lanes, W.p, W.q, W.x, W.r, n, W.part, W.done);
+            break;
+        default:
+            hipLaunchKernelGGL(k_cg_xr<16>, grid, blk, 0, st, n, nr, W.lanes, W.p, W.q, W.x, W.r, n, W.part, W.done);
+            break;
+    }
     LAUNCHCHK();
 }
 
@@ -958,7 +1100,7 @@ void lanczos_build(ddlr_prec* h, int k, int m_req, const double* v0_user, uint64
         LAUNCHCHK();
         double* EV = tmp.alloc<double>((size_t)n * k);
         double* Ucm = tmp.alloc<double>((size_t)n * k);
-        hipLaunchKernelGGL(k_csr_mv<double>, dim3(grid_for(n * k)), dim3(256), 0, st, n, k, h->erp, h->eci, h->f64.ev,
+        hipLaunchKernelGGL(k_csr_mv<double>, grid2(n, k), dim3(256), 0, st, n, k, h->erp, h->eci, h->f64.ev,
                            V, s, (const double*)nullptr, 0, EV, n, nullptr);
         LAUNCHCHK();
         a0_solve_dev<double, double, double>(h, h->f64, k, EV, n, Ucm, n, st, nullptr);
@@ -1115,6 +1257,7 @@ ddlr_status ddlr_setup(const ddlr_csr* A, const int32_t* part, int32_t p, int32_
             HIPCHK(hipSetDevice(opt.device));
             upload_structures(h.get());
             if (const char* env = std::getenv("DDLR_NO_OVERLAP")) h->overlap = env[0] != '1';
+            h->tune_mode = opt.no_autotune ? 0 : 1;
             if (!h->wide.empty()) {
                 HIPCHK(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));  // default priority
                 HIPCHK(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
@@ -1163,6 +1306,74 @@ static ddlr_status check_vec(const ddlr_prec* h, int32_t nrhs, const void* x, in
     return DDLR_OK;
 }
 
+// ------------------------------------------------------------ autotuner
+//
+// On the first A0 solve with a given number of columns, times the block
+// triangular solve with 1, 2, 4 and 8 columns per workgroup (those that divide
+// the column count and whose LDS ring holds the dependency window), then the
+// interface-level overlap on and off with the best shape, and keeps the
+// fastest.  The candidates differ in launch shape only, not in arithmetic, so
+// the choice never changes a result.  Scratch: workspace buffers q and a1.
+template <typename T>
+void autotune_T(ddlr_prec* h, const DevFactors<T>& F, int nrhs, hipStream_t st) {
+    Workspace& W = h->ws;
+    const int64_t n = h->ndev;
+    const bool prof = h->prof;
+    h->prof = false;
+    hipLaunchKernelGGL(k_fill, dim3(grid_for(n * nrhs)), dim3(256), 0, st, n * nrhs, 0.0, W.q);
+    LAUNCHCHK();
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    auto time_a0 = [&]() -> float {
+        a0_solve_dev<T, double, T>(h, F, nrhs, W.q, n, (T*)W.a1, n, st, nullptr);
+        float best = 1e30f;
+        for (int rep = 0; rep < 3; ++rep) {
+            HIPCHK(hipEventRecord(e0, st));
+            a0_solve_dev<T, double, T>(h, F, nrhs, W.q, n, (T*)W.a1, n, st, nullptr);
+            HIPCHK(hipEventRecord(e1, st));
+            HIPCHK(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            best = std::min(best, ms);
+        }
+        return 1e3f * best;
+    };
+    ddlr_prec::Tune& tn = h->tune[nrhs];
+    tn = ddlr_prec::Tune();
+    const int Rs[4] = {1, 2, 4, 8};
+    float best = 1e30f;
+    int bestR = 1;
+    for (int q = 0; q < 4; ++q) {
+        const int R = Rs[q];
+        if (nrhs % R != 0 || !ring_r_ok<T>(h, R) || (R > 1 && h->nnarrow == 0)) continue;
+        tn.ring_r = R;
+        tn.a0_us[q] = time_a0();
+        if (tn.a0_us[q] < best) {
+            best = tn.a0_us[q];
+            bestR = R;
+        }
+    }
+    tn.ring_r = bestR;
+    tn.overlap = 1;
+    if (h->overlap && h->side && !h->wide.empty() && h->nnarrow > 0) {
+        tn.overlap = 0;
+        tn.a0_noov_us = time_a0();
+        tn.overlap = tn.a0_noov_us < best ? 0 : 1;
+    }
+    HIPCHK(hipEventDestroy(e0));
+    HIPCHK(hipEventDestroy(e1));
+    h->prof = prof;
+}
+
+void autotune(ddlr_prec* h, int nrhs, hipStream_t st, bool force) {
+    if (h->capturing || h->nsys > 1) return;
+    if (!force && (h->tune_mode == 0 || h->tune.count(nrhs))) return;
+    ensure_ws(h, nrhs);
+    if (h->precision == DDLR_FP64) autotune_T<double>(h, h->f64, nrhs, st);
+    else autotune_T<float>(h, h->f32, nrhs, st);
+}
+
 // Applies op to columns in chunks of kMaxRhs: gather -> op (device order) -> scatter
 template <typename Op>
 static ddlr_status run_chunked(ddlr_prec* h, int32_t nrhs, const double* x, int64_t ldx, double* y, int64_t ldy,
@@ -1174,12 +1385,13 @@ static ddlr_status run_chunked(ddlr_prec* h, int32_t nrhs, const double* x, int6
         for (int32_t c0 = 0; c0 < nrhs; c0 += kMaxRhs) {
             const int nr = std::min<int>(kMaxRhs, nrhs - c0);
             ensure_ws(h, nr);
+            autotune(h, nr, st, false);
             Workspace& W = h->ws;
-            hipLaunchKernelGGL((k_gather<double, double>), dim3(grid_for(n * nr)), dim3(256), 0, st, n, nr,
+            hipLaunchKernelGGL((k_gather<double, double>), grid2(n, nr), dim3(256), 0, st, n, nr,
                                h->perm_dev, x + c0 * ldx, ldx, W.r, n);
             LAUNCHCHK();
             op(nr, W.r, W.z, st);
-            hipLaunchKernelGGL((k_scatter<double, double>), dim3(grid_for(n * nr)), dim3(256), 0, st, n, nr,
+            hipLaunchKernelGGL((k_scatter<double, double>), grid2(n, nr), dim3(256), 0, st, n, nr,
                                h->perm_dev, W.z, n, y + c0 * ldy, ldy);
             LAUNCHCHK();
         }
@@ -1270,7 +1482,7 @@ static void gmres_dev(ddlr_prec* h, int nr, const ddlr_solve_options& o, hipStre
         HIPCHK(hipStreamSynchronize(st));
         if (!*W.done_host) break;  // no lane opened a cycle
         // done := 0 while any lane is active (k_gm_start wrote "any active" into it)
-        hipLaunchKernelGGL(k_gm_scale, dim3(grid_for(n * nr)), dim3(256), 0, st, n, nr, W.r, W.ginv, W.gV);
+        hipLaunchKernelGGL(k_gm_scale, grid2(n, nr), dim3(256), 0, st, n, nr, W.r, W.ginv, W.gV);
         LAUNCHCHK();
         hipLaunchKernelGGL(k_flag_not, dim3(1), dim3(1), 0, st, W.done);
         LAUNCHCHK();
@@ -1285,7 +1497,7 @@ static void gmres_dev(ddlr_prec* h, int nr, const ddlr_solve_options& o, hipStre
                 hipLaunchKernelGGL(k_gm_coef, dim3(1), dim3(256), 0, st, kGmChunks, nr, j + 1, m, j, W.gpart, W.gcoef,
                                    W.gH, W.glanes, W.done);
                 LAUNCHCHK();
-                hipLaunchKernelGGL(k_gm_sub, dim3(grid_for(n * nr)), dim3(256), 0, st, n, nr, j + 1, W.gV, W.gcoef,
+                hipLaunchKernelGGL(k_gm_sub, grid2(n, nr), dim3(256), 0, st, n, nr, j + 1, W.gV, W.gcoef,
                                    W.q, W.done);
                 LAUNCHCHK();
             }
@@ -1294,7 +1506,7 @@ static void gmres_dev(ddlr_prec* h, int nr, const ddlr_solve_options& o, hipStre
                                W.ginv, W.glanes, tol2, o.maxit, W.done);
             LAUNCHCHK();
             if (j + 1 < m) {
-                hipLaunchKernelGGL(k_gm_scale, dim3(grid_for(n * nr)), dim3(256), 0, st, n, nr, W.q, W.ginv,
+                hipLaunchKernelGGL(k_gm_scale, grid2(n, nr), dim3(256), 0, st, n, nr, W.q, W.ginv,
                                    W.gV + (size_t)(j + 1) * nr * n);
                 LAUNCHCHK();
             }
@@ -1307,11 +1519,11 @@ static void gmres_dev(ddlr_prec* h, int nr, const ddlr_solve_options& o, hipStre
         // x += M^{-1} V y
         hipLaunchKernelGGL(k_gm_solve, dim3(1), dim3(64), 0, st, nr, m, W.gH, W.gg, W.gy, W.glanes);
         LAUNCHCHK();
-        hipLaunchKernelGGL(k_gm_combine, dim3(grid_for(n * nr)), dim3(256), 0, st, n, nr, m, W.gV, W.gy, W.glanes,
+        hipLaunchKernelGGL(k_gm_combine, grid2(n, nr), dim3(256), 0, st, n, nr, m, W.gV, W.gy, W.glanes,
                            W.r);
         LAUNCHCHK();
         apply_dev(h, nr, W.r, n, W.z, n, st, nullptr);
-        hipLaunchKernelGGL(k_gm_xupdate, dim3(grid_for(n * nr)), dim3(256), 0, st, n, nr, W.glanes, W.z, W.x);
+        hipLaunchKernelGGL(k_gm_xupdate, grid2(n, nr), dim3(256), 0, st, n, nr, W.glanes, W.z, W.x);
         LAUNCHCHK();
     }
     // lanes -> CG lane records used by the reporting code
@@ -1329,14 +1541,12 @@ static void lane_iteration(ddlr_prec* h, int nr, hipStream_t st) {
     Workspace& W = h->ws;
     const int64_t n = h->ndev;
     const int npart_spmv = (int)((n + 255) / 256);
-    spmv_dev(h, nr, W.p, n, W.q, n, W.part, st, W.done);
+    spmv_il_dev(h, nr, W.p, W.q, n, W.part, st, W.done);
     hipLaunchKernelGGL(k_reduce_cols, dim3(nr), dim3(256), 0, st, npart_spmv, nr, W.part, W.sums, W.done);
     LAUNCHCHK();
     hipLaunchKernelGGL(k_lane_scalar, dim3(1), dim3(64), 0, st, 2, nr, W.sums, W.lanes, W.done);
     LAUNCHCHK();
-    hipLaunchKernelGGL(k_cg_xr, dim3(kRedBlocks), dim3(256), 0, st, n, nr, W.lanes, W.p, W.q, W.x, W.r, n, W.part,
-                       W.done);
-    LAUNCHCHK();
+    cg_xr_dev(h, nr, st);
     hipLaunchKernelGGL(k_reduce_cols, dim3(nr), dim3(256), 0, st, kRedBlocks, nr, W.part, W.sums, W.done);
     LAUNCHCHK();
     hipLaunchKernelGGL(k_lane_scalar, dim3(1), dim3(64), 0, st, 3, nr, W.sums, W.lanes, W.done);
@@ -1345,7 +1555,8 @@ static void lane_iteration(ddlr_prec* h, int nr, hipStream_t st) {
     dot_dev(h, nr, W.r, W.z, n, st, W.done);
     hipLaunchKernelGGL(k_lane_scalar, dim3(1), dim3(64), 0, st, 4, nr, W.sums, W.lanes, W.done);
     LAUNCHCHK();
-    hipLaunchKernelGGL(k_cg_p, dim3(grid_for(n * nr)), dim3(256), 0, st, n, nr, W.lanes, 0, W.z, W.p, n, W.done);
+    const int S = lane_stride(nr);
+    hipLaunchKernelGGL(k_cg_p, dim3(grid_for(n * S)), dim3(256), 0, st, n, nr, ilog2(S), W.lanes, W.z, W.p, n, W.done);
     LAUNCHCHK();
 }
 
@@ -1357,8 +1568,8 @@ static void lane_admit(ddlr_prec* h, int nr, const std::vector<int32_t>& start, 
     HIPCHK(hipMemcpyAsync(W.adm_start, start.data(), nr * sizeof(int32_t), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(W.adm_tol2, tol2.data(), nr * sizeof(double), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(W.adm_maxit, maxit.data(), nr * sizeof(int32_t), hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(k_lane_zero, dim3(grid_for(h->ndev * nr)), dim3(256), 0, st, h->ndev, nr, W.adm_start, W.x, W.p,
-                       h->ndev);
+    hipLaunchKernelGGL(k_lane_zero, dim3(grid_for(h->ndev * lane_stride(nr))), dim3(256), 0, st, h->ndev, nr,
+                       ilog2(lane_stride(nr)), W.adm_start, W.x, W.p, h->ndev);
     LAUNCHCHK();
     hipLaunchKernelGGL(k_lane_admit, dim3(1), dim3(64), 0, st, nr, W.adm_start, W.adm_tol2, W.adm_maxit, W.lanes,
                        W.done);
@@ -1408,17 +1619,18 @@ ddlr_status ddlr_solve(ddlr_prec* h, int32_t nrhs, const double* b, int64_t ldb,
         for (int32_t c0 = 0; c0 < nrhs; c0 += kMaxRhs) {
             const int nr = std::min<int>(kMaxRhs, nrhs - c0);
             ensure_ws(h, nr);
+            autotune(h, nr, st, false);
             Workspace& W = h->ws;
-            hipLaunchKernelGGL((k_gather<double, double>), dim3(grid_for(n * nr)), dim3(256), 0, st, n, nr,
+            hipLaunchKernelGGL((k_gather<double, double>), grid2(n, nr), dim3(256), 0, st, n, nr,
                                h->perm_dev, b + c0 * ldb, ldb, W.r, n);
             LAUNCHCHK();
             if (o.method == 0) pcg_dev(h, nr, o, st);
             else gmres_dev(h, nr, o, st);
-            hipLaunchKernelGGL((k_scatter<double, double>), dim3(grid_for(n * nr)), dim3(256), 0, st, n, nr,
+            hipLaunchKernelGGL((k_scatter<double, double>), grid2(n, nr), dim3(256), 0, st, n, nr,
                                h->perm_dev, W.x, n, x + c0 * ldx, ldx);
             LAUNCHCHK();
             // true residual: q = b - A x (device order), recursive residual from the lanes
-            hipLaunchKernelGGL((k_gather<double, double>), dim3(grid_for(n * nr)), dim3(256), 0, st, n, nr,
+            hipLaunchKernelGGL((k_gather<double, double>), grid2(n, nr), dim3(256), 0, st, n, nr,
                                h->perm_dev, b + c0 * ldb, ldb, W.r, n);
             LAUNCHCHK();
             spmv_dev(h, nr, W.x, n, W.q, n, nullptr, st, nullptr);
@@ -1668,6 +1880,35 @@ ddlr_status ddlr_profile_read(ddlr_prec* h, int32_t which, double* total_ms, int
     return DDLR_OK;
 }
 
+ddlr_status ddlr_tune(ddlr_prec* h, int32_t nrhs, int32_t retune, ddlr_tuning* out, void* stream) {
+    if (!dev_ok(h)) return h ? DDLR_E_DEVICE : DDLR_E_INVALID;
+    if (nrhs < 1 || nrhs > kMaxRhs || !out) {
+        g_err = "nrhs must be in [1, 16] and out non-null";
+        return DDLR_E_INVALID;
+    }
+    try {
+        HIPCHK(hipSetDevice(h->device));
+        hipStream_t st = (hipStream_t)stream;
+        autotune(h, nrhs, st, retune != 0 || !h->tune.count(nrhs));
+        HIPCHK(hipStreamSynchronize(st));
+    } catch (const SetupError& e) {
+        return fail_status(e);
+    }
+    std::memset(out, 0, sizeof(*out));
+    out->nrhs = nrhs;
+    auto it = h->tune.find(nrhs);
+    if (it == h->tune.end()) {  // batches: fixed shape
+        out->ring_cols = 1;
+        out->overlap = h->overlap ? 1 : 0;
+        return DDLR_OK;
+    }
+    out->ring_cols = it->second.ring_r;
+    out->overlap = it->second.overlap;
+    for (int q = 0; q < 4; ++q) out->a0_us[q] = it->second.a0_us[q];
+    out->a0_no_overlap_us = it->second.a0_noov_us;
+    return DDLR_OK;
+}
+
 void ddlr_destroy(ddlr_prec* h) {
     if (!h) return;
     if (h->device >= 0) {
@@ -1801,6 +2042,7 @@ ddlr_status ddlr_batch_create(int32_t nsys, ddlr_prec* const* members, ddlr_batc
         h->variant = m0->variant;
         h->nsys = nsys;
         h->overlap = false;
+        h->tune_mode = 0;
         // device structures of every member, interface blocks as single blocks
         std::vector<DevHost> parts(nsys);
         std::vector<const DevHost*> pp(nsys);
@@ -2354,6 +2596,19 @@ ddlr_status ddlr_server_stats(ddlr_server* S, ddlr_server_counters* st) {
     st->hbm_used = S->used;
     st->hbm_budget = S->budget;
     st->matrices = (int32_t)S->mats.size();
+    return DDLR_OK;
+}
+
+ddlr_status ddlr_server_reset_stats(ddlr_server* S) {
+    if (!S) {
+        g_err = "null argument";
+        return DDLR_E_INVALID;
+    }
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->lat_ms.clear();
+    S->solves_done = S->submitted = S->requests_done = 0;
+    S->t_first = -1.0;
+    S->t_last = 0.0;
     return DDLR_OK;
 }
 

@@ -45,33 +45,27 @@ template <typename T> __device__ __forceinline__ T ld(const T* p) { return *p; }
 template <typename TI, typename TO>
 __global__ void k_gather(int64_t n, int nrhs, const int32_t* __restrict__ perm, const TI* __restrict__ x, int64_t ldx,
                          TO* __restrict__ y, int64_t ldy) {
-    const int64_t total = n * nrhs;
-    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t r = g / n, d = g - r * n;
+    const int64_t r = blockIdx.y;  // grid (chunks, nrhs)
+    for (int64_t d = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; d < n; d += (int64_t)gridDim.x * blockDim.x)
         y[d + r * ldy] = (TO)x[perm[d] + r * ldx];
-    }
 }
 
 // y[perm[d] + r*ldy] = x[d + r*ldx]   (device order -> user order)
 template <typename TI, typename TO>
 __global__ void k_scatter(int64_t n, int nrhs, const int32_t* __restrict__ perm, const TI* __restrict__ x, int64_t ldx,
                           TO* __restrict__ y, int64_t ldy) {
-    const int64_t total = n * nrhs;
-    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t r = g / n, d = g - r * n;
+    const int64_t r = blockIdx.y;  // grid (chunks, nrhs)
+    for (int64_t d = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; d < n; d += (int64_t)gridDim.x * blockDim.x)
         y[perm[d] + r * ldy] = (TO)x[d + r * ldx];
-    }
 }
 
 template <typename TI, typename TO>
 __global__ void k_cast(int64_t n, int nrhs, const TI* __restrict__ x, int64_t ldx, TO* __restrict__ y, int64_t ldy,
                        const int* __restrict__ done) {
     if (done && *done) return;
-    const int64_t total = n * nrhs;
-    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t r = g / n, d = g - r * n;
+    const int64_t r = blockIdx.y;  // grid (chunks, nrhs)
+    for (int64_t d = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; d < n; d += (int64_t)gridDim.x * blockDim.x)
         y[d + r * ldy] = (TO)x[d + r * ldx];
-    }
 }
 
 // ------------------------------------------------ A0 solve: narrow blocks
@@ -278,7 +272,8 @@ __global__ __launch_bounds__(kRingThreads) void k_trsv_ring(
     const int b = blockIdx.x % nblk_pad, r = blockIdx.x / nblk_pad;
     if (b >= nblk || r >= nrhs) return;
     const RingBlock d = blk[b];
-    const int nlev = d.lvl1 - d.lvl0;  // 1 .. kRingMaxLevels (checked on the host)
+    const int nlev = d.lvl1 - d.lvl0;  // <= kRingMaxLevels (checked on the host)
+    if (nlev <= 0) return;
     for (int q = threadIdx.x; q <= nlev; q += kRingThreads) {
         const int l = d.lvl0 + q;
         meta[q] = q < nlev ? int4{lvl_ptr[l] - d.row0, foff[l], boff[l], 0} : int4{lvl_ptr[l] - d.row0, 0, 0, 0};
@@ -292,6 +287,168 @@ __global__ __launch_bounds__(kRingThreads) void k_trsv_ring(
     __syncthreads();  // global fence: the backward sweep reads y_i from memory
     // backward sweep: z = D^{-1} y - L^T z
     ring_sweep<T, KW, kRing, true, TOut, TOut>(nlev, d.row0, meta, ring, bcol, bval, dinv, zr, zr);
+}
+
+// ----------------------------- A0 solve: narrow blocks, R columns per workgroup
+//
+// The ring kernel above runs one workgroup per (block, column), so every
+// column's workgroup loads the block's level entries of L and L^T again.
+// This variant gives a workgroup R columns of one block: the entries are
+// loaded once and used R times, and the LDS ring keeps the R values of a row
+// side by side, so one vector LDS read gathers a dependency for all R
+// columns.  Per column the arithmetic is that of the one-column kernel (same
+// operations in the same order), so the results are bitwise the same for any
+// R.  The ring holds kRing rows of R values (64 KB); the host checks the
+// dependency window against kRing as for the one-column kernel.
+template <typename T, int R> constexpr int ring_rows_r() { return 65536 / (int)(sizeof(T) * R); }
+
+template <typename T, int KW, int R, typename TS> struct LevelRegsR {
+    int a, e, off;
+    int c[2][KW];
+    T v[2][KW];
+    TS xv[2][R];
+    T dv[2];
+};
+
+template <typename T, int KW, int R, bool kBwd, typename TS>
+__device__ __forceinline__ void ringr_load(LevelRegsR<T, KW, R, TS>& L, int q, int row0, const int4* meta,
+                                           const int32_t* __restrict__ ecol, const T* __restrict__ eval,
+                                           const T* __restrict__ dinv, const TS* src, int64_t lds) {
+    const int4 mq = meta[q];
+    L.a = __builtin_amdgcn_readfirstlane(mq.x);
+    L.e = __builtin_amdgcn_readfirstlane(meta[q + 1].x);
+    L.off = __builtin_amdgcn_readfirstlane(kBwd ? mq.z : mq.y);
+    const int nr = L.e - L.a;
+#pragma unroll
+    for (int qq = 0; qq < 2; ++qq) {
+        if (qq == 1 && nr <= kRingThreads) break;  // uniform: one row set covers the level
+        const int i = min(L.a + (int)threadIdx.x + qq * kRingThreads, L.e - 1);
+        const int base = L.off + (i - L.a);
+#pragma unroll
+        for (int j = 0; j < KW; ++j) {
+            L.c[qq][j] = ecol[base + j * nr];
+            L.v[qq][j] = eval[base + j * nr];
+        }
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr) L.xv[qq][rr] = src[i + rr * lds];
+        if (kBwd) L.dv[qq] = dinv[row0 + i];
+    }
+}
+
+template <typename T, int KW, int kRing, int R, bool kBwd, typename TS, typename TD>
+__device__ __forceinline__ void ringr_compute(const LevelRegsR<T, KW, R, TS>& L, int row0, T* ring,
+                                              const int32_t* __restrict__ ecol, const T* __restrict__ eval,
+                                              const T* __restrict__ dinv, const TS* src, int64_t lds, TD* dst,
+                                              int64_t ldd) {
+    using V = T __attribute__((ext_vector_type(R)));
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        if (q == 1 && L.e - L.a <= kRingThreads) break;
+        const int i0 = L.a + (int)threadIdx.x + q * kRingThreads;
+        const int i = min(i0, L.e - 1);
+        V sv;
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr) sv[rr] = kBwd ? (T)L.xv[q][rr] * L.dv[q] : (T)L.xv[q][rr];
+#pragma unroll
+        for (int j = 0; j < KW; ++j) {
+            const V g = *reinterpret_cast<const V*>(ring + (size_t)(L.c[q][j] & (kRing - 1)) * R);
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr) sv[rr] -= L.v[q][j] * g[rr];
+        }
+        if (i0 < L.e) {
+            *reinterpret_cast<V*>(ring + (size_t)(i & (kRing - 1)) * R) = sv;
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr) dst[i + rr * ldd] = (TD)sv[rr];
+        }
+    }
+    // rows beyond 2 * kRingThreads: no prefetch
+    const int nr = L.e - L.a;
+    for (int i = L.a + 2 * kRingThreads + (int)threadIdx.x; i < L.e; i += kRingThreads) {
+        const int base = L.off + (i - L.a);
+        V sv;
+        const T dvi = kBwd ? dinv[row0 + i] : T(1);
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr) sv[rr] = kBwd ? (T)src[i + rr * lds] * dvi : (T)src[i + rr * lds];
+        for (int j = 0; j < KW; ++j) {
+            const T vj = eval[base + j * nr];
+            const V g = *reinterpret_cast<const V*>(ring + (size_t)(ecol[base + j * nr] & (kRing - 1)) * R);
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr) sv[rr] -= vj * g[rr];
+        }
+        *reinterpret_cast<V*>(ring + (size_t)(i & (kRing - 1)) * R) = sv;
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr) dst[i + rr * ldd] = (TD)sv[rr];
+    }
+}
+
+template <typename T> struct RingDepthR { static constexpr int value = 3; };
+template <> struct RingDepthR<double> { static constexpr int value = 2; };
+
+template <typename T, int KW, int kRing, int R, bool kBwd, typename TS, typename TD>
+__device__ __forceinline__ void ringr_sweep(int nlev, int row0, const int4* meta, T* ring,
+                                            const int32_t* __restrict__ ecol, const T* __restrict__ eval,
+                                            const T* __restrict__ dinv, const TS* src, int64_t lds, TD* dst,
+                                            int64_t ldd) {
+    constexpr int kD = RingDepthR<T>::value;
+    LevelRegsR<T, KW, R, TS> buf[kD];
+    auto lev = [&](int q) { return kBwd ? nlev - 1 - q : q; };
+#pragma unroll
+    for (int u = 0; u < kD - 1; ++u)
+        if (u < nlev) ringr_load<T, KW, R, kBwd, TS>(buf[u], lev(u), row0, meta, ecol, eval, dinv, src, lds);
+    int q0 = 0;
+    for (; q0 + 2 * kD - 1 <= nlev; q0 += kD) {
+#pragma unroll
+        for (int u = 0; u < kD; ++u) {
+            ringr_load<T, KW, R, kBwd, TS>(buf[(u + kD - 1) % kD], lev(q0 + u + kD - 1), row0, meta, ecol, eval,
+                                           dinv, src, lds);
+            ringr_compute<T, KW, kRing, R, kBwd, TS, TD>(buf[u], row0, ring, ecol, eval, dinv, src, lds, dst, ldd);
+            lds_barrier();
+        }
+    }
+    for (; q0 < nlev; q0 += kD) {
+#pragma unroll
+        for (int u = 0; u < kD; ++u) {
+            const int q = q0 + u;
+            if (q < nlev) {
+                if (q + kD - 1 < nlev)
+                    ringr_load<T, KW, R, kBwd, TS>(buf[(u + kD - 1) % kD], lev(q + kD - 1), row0, meta, ecol, eval,
+                                                   dinv, src, lds);
+                ringr_compute<T, KW, kRing, R, kBwd, TS, TD>(buf[u], row0, ring, ecol, eval, dinv, src, lds, dst,
+                                                             ldd);
+                lds_barrier();
+            }
+        }
+    }
+}
+
+// grid: nblk_pad * ngroups workgroups; workgroup (b, g) solves block b for
+// columns g*R .. g*R+R-1 (the host launches only ngroups = nrhs / R).
+template <typename T, int KW, int R, typename TIn, typename TOut>
+__global__ __launch_bounds__(kRingThreads) void k_trsv_ring_r(
+    const RingBlock* __restrict__ blk, int nblk, int nblk_pad, int ngroups, const int32_t* __restrict__ lvl_ptr,
+    const int32_t* __restrict__ foff, const int32_t* __restrict__ fcol, const T* __restrict__ fval,
+    const int32_t* __restrict__ boff, const int32_t* __restrict__ bcol, const T* __restrict__ bval,
+    const T* __restrict__ dinv, const TIn* x, int64_t ldx, TOut* z, int64_t ldz, const int* __restrict__ done) {
+    constexpr int kRing = ring_rows_r<T, R>();
+    __shared__ __attribute__((aligned(16))) T ring[kRing * R];
+    __shared__ int4 meta[kRingMaxLevels + 1];
+    if (done && *done) return;
+    const int b = blockIdx.x % nblk_pad, g = blockIdx.x / nblk_pad;
+    if (b >= nblk || g >= ngroups) return;
+    const RingBlock d = blk[b];
+    const int nlev = d.lvl1 - d.lvl0;  // <= kRingMaxLevels (checked on the host)
+    if (nlev <= 0) return;
+    for (int q = threadIdx.x; q <= nlev; q += kRingThreads) {
+        const int l = d.lvl0 + q;
+        meta[q] = q < nlev ? int4{lvl_ptr[l] - d.row0, foff[l], boff[l], 0} : int4{lvl_ptr[l] - d.row0, 0, 0, 0};
+    }
+    for (int q = threadIdx.x; q < kRing * R; q += kRingThreads) ring[q] = T(0);
+    __syncthreads();
+    const TIn* xr = x + (int64_t)g * R * ldx + d.row0;
+    TOut* zr = z + (int64_t)g * R * ldz + d.row0;
+    ringr_sweep<T, KW, kRing, R, false, TIn, TOut>(nlev, d.row0, meta, ring, fcol, fval, dinv, xr, ldx, zr, ldz);
+    __syncthreads();  // global fence: the backward sweep reads y_i from memory
+    ringr_sweep<T, KW, kRing, R, true, TOut, TOut>(nlev, d.row0, meta, ring, bcol, bval, dinv, zr, ldz, zr, ldz);
 }
 
 // ------------------------------------------------ A0 solve: one wide level
@@ -308,10 +465,9 @@ __global__ __launch_bounds__(256) void k_trsv_level(int a, int e, int nrhs, cons
                                                     const T* __restrict__ dinv, const TIn* x, int64_t ldx, TOut* z,
                                                     int64_t ldz, const int* __restrict__ done) {
     if (done && *done) return;
-    const int rows = e - a;
-    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (g >= (int64_t)rows * nrhs) return;
-    const int r = (int)(g / rows), i = a + (int)(g - (int64_t)r * rows);
+    const int r = blockIdx.y;  // grid (row chunks, nrhs)
+    const int i = a + (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i >= e) return;
     TOut* zr = z + r * ldz;
     T s = kKind == 1 ? (T)zr[i] * dinv[i] : (T)x[i + r * ldx];
     const int t1 = rp[i + 1];
@@ -324,8 +480,9 @@ __global__ __launch_bounds__(256) void k_trsv_level(int a, int e, int nrhs, cons
 //
 // y = A x for up to kMaxRhs columns; A is FP64 in SELL-64 (slices of 64 rows,
 // entries column-major inside a slice, padding points at the row itself with
-// value 0).  Optionally accumulates per-block partial dot products x.y per
-// right-hand side into part[block*nrhs + r] (used for p^T A p in CG).
+// value 0).  Optionally accumulates per-chunk partial dot products x.y per
+// right-hand side into part[chunk*nrhs + r], chunk = 256-row chunk index
+// (used for p^T A p in CG).
 __global__ __launch_bounds__(256) void k_spmv_sell(int64_t n, int nrhs, const int32_t* __restrict__ sptr,
                                                    const int32_t* __restrict__ col, const double* __restrict__ val,
                                                    const double* __restrict__ x, int64_t ldx, double* __restrict__ y,
@@ -333,7 +490,13 @@ __global__ __launch_bounds__(256) void k_spmv_sell(int64_t n, int nrhs, const in
                                                    const int* __restrict__ done) {
     __shared__ double sh[4 * kMaxRhs];
     if (done && *done) return;
-    const int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    // XCD-aware chunk order: workgroups are dealt round-robin to the 8 XCDs,
+    // so give each XCD one contiguous eighth of the rows (grid padded to a
+    // multiple of 8); x lines gathered by neighbouring chunks then meet in
+    // the same L2 instead of being fetched once per XCD.
+    const int64_t per = gridDim.x >> 3;
+    const int64_t wg = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    const int64_t row = wg * blockDim.x + threadIdx.x;
     double acc[kMaxRhs];
 #pragma unroll
     for (int r = 0; r < kMaxRhs; ++r) acc[r] = 0.0;
@@ -361,10 +524,76 @@ __global__ __launch_bounds__(256) void k_spmv_sell(int64_t n, int nrhs, const in
             if (lane == 0) sh[w * kMaxRhs + r] = v;
         }
         __syncthreads();
-        if (threadIdx.x < nrhs) {
+        if (threadIdx.x < nrhs && wg * blockDim.x < n) {
             const int r = threadIdx.x;
-            part[blockIdx.x * nrhs + r] =
+            part[wg * nrhs + r] =
                 (sh[0 * kMaxRhs + r] + sh[1 * kMaxRhs + r]) + (sh[2 * kMaxRhs + r] + sh[3 * kMaxRhs + r]);
+        }
+    }
+}
+
+// Same product with x interleaved: x[row * S + r], S a power of two >= nrhs
+// (the CG search direction is kept this way).  One gather then brings the
+// values of all right-hand sides of a column in one S*8-byte segment, where
+// column-major x needs one cache line per right-hand side; with 8 columns of
+// 2M rows the column-major lines in flight overflow the L2 and are fetched
+// several times.  Per-row sums run over the slice entries in the same order
+// as k_spmv_sell, so both give bitwise the same y.
+template <int S>
+__global__ __launch_bounds__(256) void k_spmv_sell_il(int64_t n, int nrhs, const int32_t* __restrict__ sptr,
+                                                      const int32_t* __restrict__ col,
+                                                      const double* __restrict__ val, const double* __restrict__ x,
+                                                      double* __restrict__ y, int64_t ldy, double* __restrict__ part,
+                                                      const int* __restrict__ done) {
+    __shared__ double sh[4 * S];
+    if (done && *done) return;
+    const int64_t per = gridDim.x >> 3;
+    const int64_t wg = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    const int64_t row = wg * blockDim.x + threadIdx.x;
+    double acc[S];
+#pragma unroll
+    for (int r = 0; r < S; ++r) acc[r] = 0.0;
+    if (row < n) {
+        const int64_t sl = row >> 6;
+        const int lane = (int)(row & 63);
+        const int base = sptr[sl], width = (sptr[sl + 1] - base) >> 6;
+        for (int j = 0; j < width; ++j) {
+            const int q = base + j * kSell + lane;
+            const int c = col[q];
+            const double a = val[q];
+            const double* xc = x + (int64_t)c * S;
+            double xv[S];
+            if constexpr (S == 1) {
+                xv[0] = xc[0];
+            } else {
+#pragma unroll
+                for (int r = 0; r < S; r += 2) {
+                    const double2 t = *reinterpret_cast<const double2*>(xc + r);
+                    xv[r] = t.x;
+                    xv[r + 1] = t.y;
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < S; ++r) acc[r] += a * xv[r];
+        }
+#pragma unroll
+        for (int r = 0; r < S; ++r)
+            if (r < nrhs) y[row + r * ldy] = acc[r];
+    }
+    if (part) {
+        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+        for (int r = 0; r < S; ++r) {
+            if (r < nrhs) {
+                double v = row < n ? acc[r] * x[row * S + r] : 0.0;
+                v = wave_sum(v);
+                if (lane == 0) sh[w * S + r] = v;
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x < nrhs && wg * blockDim.x < n) {
+            const int r = threadIdx.x;
+            part[wg * nrhs + r] = (sh[0 * S + r] + sh[1 * S + r]) + (sh[2 * S + r] + sh[3 * S + r]);
         }
     }
 }
@@ -382,12 +611,12 @@ __global__ __launch_bounds__(256) void k_csr_mv(int64_t rows, int nrhs, const in
                                                 int64_t ldx, T* __restrict__ y, int64_t ldy,
                                                 const int* __restrict__ done) {
     if (done && *done) return;
-    const int64_t total = rows * nrhs;
-    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t r = g / rows, i = g - r * rows;
+    const int64_t r = blockIdx.y;  // grid (row chunks, nrhs)
+    const T* wr = w + r * ldw;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < rows; i += (int64_t)gridDim.x * blockDim.x) {
         T s = x ? (T)x[i + r * ldx] : T(0);
-        const T* wr = w + r * ldw;
-        for (int t = rp[i]; t < rp[i + 1]; ++t) s += v[t] * wr[ci[t]];
+        const int t1 = rp[i + 1];
+        for (int t = rp[i]; t < t1; ++t) s += v[t] * wr[ci[t]];
         y[i + r * ldy] = s;
     }
 }
@@ -826,57 +1055,86 @@ __global__ void k_lane_admit(int nlanes, const int32_t* __restrict__ start, cons
 }
 
 // x[:, r] = 0 and p[:, r] = 0 for admitted lanes
-__global__ void k_lane_zero(int64_t n, int nlanes, const int32_t* __restrict__ start, double* __restrict__ x,
-                            double* __restrict__ p, int64_t ld) {
-    const int64_t total = n * nlanes;
+// x is column-major (ld); p is interleaved with stride S (p[i * S + r]).
+__global__ void k_lane_zero(int64_t n, int nlanes, int lgS, const int32_t* __restrict__ start,
+                            double* __restrict__ x, double* __restrict__ p, int64_t ld) {
+    const int64_t total = n << lgS;
     for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t r = g / n, i = g - r * n;
-        if (start[r]) {
+        const int64_t i = g >> lgS;
+        const int r = (int)(g & ((1 << lgS) - 1));
+        if (r < nlanes && start[r]) {
             x[i + r * ld] = 0.0;
-            p[i + r * ld] = 0.0;
+            p[g] = 0.0;
         }
     }
 }
 
-// x += alpha p ; r -= alpha q ; part = r.r   (active lanes only)
+// x += alpha p ; r -= alpha q ; part = r.r   (active lanes only).  x, r, q
+// column-major (ld); p interleaved with stride S.  Each thread walks its rows
+// once for all lanes; every lane's sum runs over the same rows in the same
+// order whatever the number of lanes, so a lane's result does not depend on
+// the other lanes.
+template <int S>
 __global__ __launch_bounds__(256) void k_cg_xr(int64_t n, int nrhs, const CgLane* __restrict__ L,
                                                const double* __restrict__ p, const double* __restrict__ q,
                                                double* __restrict__ x, double* __restrict__ r, int64_t ld,
                                                double* __restrict__ part, const int* __restrict__ done) {
     __shared__ double sh[4];
     if (done && *done) return;
-    for (int c = 0; c < nrhs; ++c) {
-        const bool act = L[c].active;
-        const double a = L[c].alpha;
-        double acc = 0.0;
-        for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-            const int64_t o = i + c * ld;
-            double ri = r[o];
-            if (act) {
-                x[o] += a * p[o];
-                ri -= a * q[o];
-                r[o] = ri;
+    bool act[S];
+    double a[S], acc[S];
+#pragma unroll
+    for (int c = 0; c < S; ++c) {
+        act[c] = c < nrhs && L[c].active;
+        a[c] = c < nrhs ? L[c].alpha : 0.0;
+        acc[c] = 0.0;
+    }
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double pv[S];
+        if constexpr (S == 1) {
+            pv[0] = p[i];
+        } else {
+#pragma unroll
+            for (int c = 0; c < S; c += 2) {
+                const double2 t = *reinterpret_cast<const double2*>(p + i * S + c);
+                pv[c] = t.x;
+                pv[c + 1] = t.y;
             }
-            acc += ri * ri;
         }
-        const double s = block_sum256(acc, sh);
-        if (threadIdx.x == 0) part[blockIdx.x * nrhs + c] = s;
+#pragma unroll
+        for (int c = 0; c < S; ++c) {
+            if (c < nrhs) {
+                const int64_t o = i + c * ld;
+                double ri = r[o];
+                if (act[c]) {
+                    x[o] += a[c] * pv[c];
+                    ri -= a[c] * q[o];
+                    r[o] = ri;
+                }
+                acc[c] += ri * ri;
+            }
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < S; ++c) {
+        if (c < nrhs) {
+            const double t = block_sum256(acc[c], sh);
+            if (threadIdx.x == 0) part[blockIdx.x * nrhs + c] = t;
+        }
     }
 }
 
-// p = z + beta p (active lanes); init: p = z
-__global__ __launch_bounds__(256) void k_cg_p(int64_t n, int nrhs, const CgLane* __restrict__ L, int init,
+// p = z + beta p (active lanes); z column-major (ld), p interleaved (stride
+// S = 2^lgS)
+__global__ __launch_bounds__(256) void k_cg_p(int64_t n, int nrhs, int lgS, const CgLane* __restrict__ L,
                                               const double* __restrict__ z, double* __restrict__ p, int64_t ld,
                                               const int* __restrict__ done) {
     if (done && *done) return;
-    const int64_t total = n * nrhs;
+    const int64_t total = n << lgS;
     for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t c = g / n, i = g - c * n;
-        if (init) {
-            p[i + c * ld] = z[i + c * ld];
-        } else if (L[c].active) {
-            p[i + c * ld] = z[i + c * ld] + L[c].beta * p[i + c * ld];
-        }
+        const int64_t i = g >> lgS;
+        const int c = (int)(g & ((1 << lgS) - 1));
+        if (c < nrhs && L[c].active) p[g] = z[i + c * ld] + L[c].beta * p[g];
     }
 }
 
@@ -1085,9 +1343,8 @@ __global__ __launch_bounds__(256) void k_gm_sub(int64_t n, int nrhs, int ncols, 
     if (done && *done) return;
     for (int q = threadIdx.x; q < nrhs * ncols; q += blockDim.x) cf[q] = coef[q];
     __syncthreads();
-    const int64_t total = n * nrhs;
-    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t r = g / n, i = g - r * n;
+    const int64_t r = blockIdx.y;  // grid (row chunks, nrhs)
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         double v = w[r * n + i];
         for (int l = 0; l < ncols; ++l) v -= V[((int64_t)l * nrhs + r) * n + i] * cf[r * ncols + l];
         w[r * n + i] = v;
@@ -1145,11 +1402,9 @@ __global__ void k_gm_givens(int j, int nrhs, int m, const double* __restrict__ w
 // V[j+1][r] = w[r] * inv[r]
 __global__ __launch_bounds__(256) void k_gm_scale(int64_t n, int nrhs, const double* __restrict__ w,
                                                   const double* __restrict__ inv, double* __restrict__ Vn) {
-    const int64_t total = n * nrhs;
-    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t r = g / n;
-        Vn[g] = w[g] * inv[r];
-    }
+    const int64_t r = blockIdx.y;  // grid (row chunks, nrhs)
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        Vn[r * n + i] = w[r * n + i] * inv[r];
 }
 
 // Cycle start: beta_r = ||r_r||; lanes that converged or ran out of steps are
@@ -1219,13 +1474,12 @@ __global__ void k_gm_solve(int nrhs, int m, const double* __restrict__ H, const 
 __global__ __launch_bounds__(256) void k_gm_combine(int64_t n, int nrhs, int m, const double* __restrict__ V,
                                                     const double* __restrict__ y, const GmLane* __restrict__ L,
                                                     double* __restrict__ u) {
-    const int64_t total = n * nrhs;
-    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t r = g / n, i = g - r * n;
-        const int kc = L[r].kc;
+    const int64_t r = blockIdx.y;  // grid (row chunks, nrhs)
+    const int kc = L[r].kc;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         double v = 0.0;
         for (int l = 0; l < kc; ++l) v += V[((int64_t)l * nrhs + r) * n + i] * y[r * m + l];
-        u[g] = v;
+        u[r * n + i] = v;
     }
 }
 
@@ -1247,11 +1501,10 @@ __global__ void k_gm_report(int nrhs, const GmLane* __restrict__ G, CgLane* __re
 // x[r] += z[r] for lanes that took steps in this cycle
 __global__ __launch_bounds__(256) void k_gm_xupdate(int64_t n, int nrhs, const GmLane* __restrict__ L,
                                                     const double* __restrict__ z, double* __restrict__ x) {
-    const int64_t total = n * nrhs;
-    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t r = g / n;
-        if (L[r].kc > 0) x[g] += z[g];
-    }
+    const int64_t r = blockIdx.y;  // grid (row chunks, nrhs)
+    if (L[r].kc <= 0) return;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        x[r * n + i] += z[r * n + i];
 }
 
 // ------------------------------------------------------------ Lanczos steps

@@ -463,3 +463,32 @@ def test_serving_budget_admission():
         D.ddlr_server_add(srv, h)
     assert e.value.status == D.E_BUDGET
     del srv
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_autotuner_shapes_bitwise(prec):
+    """Every launch shape the autotuner may pick (1, 2, 4, 8 columns per
+    workgroup of the block triangular solve; interface overlap on/off) gives
+    bitwise the same A0 solve, and ddlr_tune reports an eligible choice."""
+    import os
+    cfg = w.config("small3d")
+    A = cfg["A"]
+    h = D.ddlr_setup(A, cfg["part"], cfg["p"], cfg["k"], 0, precision=[D.FP64, D.FP32][prec], autotune=False)
+    x = torch.randn(8, A.n, dtype=torch.float64, device=DEV)
+    outs = []
+    for R in ("1", "2", "4", "8"):
+        os.environ["DDLR_RING_R"] = R
+        y = torch.empty_like(x)
+        D.ddlr_a0_solve(h, x, y)
+        torch.cuda.synchronize()
+        outs.append(y.cpu())
+    os.environ.pop("DDLR_RING_R")
+    for o in outs[1:]:
+        assert torch.equal(o, outs[0])
+    t = D.ddlr_tune(h, 8, retune=True)
+    say("tune", t)
+    assert t["ring_cols"] in (1, 2, 4, 8) and t["a0_us"][0] > 0
+    y = torch.empty_like(x)
+    D.ddlr_a0_solve(h, x, y)
+    torch.cuda.synchronize()
+    assert torch.equal(y.cpu(), outs[0])

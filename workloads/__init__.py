@@ -275,3 +275,41 @@ def config(name: str) -> dict:
         return dict(A=A, part=box_partition((18, 17, 16), (2, 3, 2)), p=12, k=10, m=24, nrhs=4,
                     dims=(18, 17, 16), variant=1, method="cg")
     raise KeyError(name)
+
+
+def _draw_int(seed: int, stream: str, idx: int, lo: int, hi: int) -> int:
+    """Integer uniform on {lo..hi} from the counter-based generator."""
+    u = float(uniform(seed, stream, np.array([idx], dtype=np.uint64))[0])
+    return lo + min(int(u * (hi - lo + 1)), hi - lo)
+
+
+def batch_systems(count: int = 256, seed: int = 0, side_lo: int = 32, side_hi: int = 256) -> list:
+    """Batch of independent SPD 2-D diffusion systems (cell-centred two-point
+    flux, per-cell log-uniform coefficients).  System i: grid sides Nx, Ny
+    uniform on {side_lo..side_hi}, box split px x py with px, py uniform on
+    {2,3,4}, coefficients from seed + i, rank 16 from 32 Lanczos steps."""
+    out = []
+    for i in range(count):
+        nx = _draw_int(seed, "batch_nx", i, side_lo, side_hi)
+        ny = _draw_int(seed, "batch_ny", i, side_lo, side_hi)
+        px = _draw_int(seed, "batch_px", i, 2, 4)
+        py = _draw_int(seed, "batch_py", i, 2, 4)
+        A = tpfa_2d(nx, ny, seed + i)
+        out.append(dict(A=A, part=box_partition((nx, ny), (px, py)), p=px * py, k=16, m=32, dims=(nx, ny),
+                        seed=seed + i))
+    return out
+
+
+# resident matrices of the serving stream: grid side, box split, rank
+SERVING_MATRICES = ((37, (2, 2, 4), 32), (46, (2, 2, 4), 32), (55, (2, 4, 4), 40), (64, (2, 4, 4), 40),
+                    (73, (4, 4, 4), 48), (82, (4, 4, 4), 48), (91, (4, 4, 8), 64), (100, (4, 4, 8), 64))
+
+
+def serving_matrix(j: int, seed: int = 0) -> dict:
+    """Matrix j of the serving stream: 27-point random-coefficient SPD
+    M-matrix on an N^3 grid, N^3 from 50,653 to 10^6, 16..128 box
+    subdomains, rank 32..64 from 2k Lanczos steps."""
+    N, parts, k = SERVING_MATRICES[j]
+    A = random27_3d(N, N, N, seed + j)
+    p = parts[0] * parts[1] * parts[2]
+    return dict(A=A, part=box_partition((N, N, N), parts), p=p, k=k, m=2 * k, dims=(N, N, N), seed=seed + j)
