@@ -145,6 +145,12 @@ struct ddlr_prec {
     };
     std::map<int, Tune> tune;
     int tune_mode = 1;  // 1: tune on first use of a column count, 0: defaults
+    // CG runs on a private stream (joined to the caller's by events) so a
+    // chunk of iterations can be captured once per column count into a graph
+    hipStream_t cg_st = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    std::map<int, std::pair<hipGraph_t, hipGraphExec_t>> cg_graphs;
+    bool use_graphs = true;
     bool lr_plain = false;                      // low-rank kernels without MFMA (comparison only)
     // the interface block's level kernels run on a side stream, overlapping the
     // B-block kernel (fork/join by events on the caller's stream)
@@ -530,9 +536,12 @@ int ilog2(int v) {
     return l;
 }
 
+void drop_graphs(ddlr_prec* h);
+
 void ensure_ws(ddlr_prec* h, int nrhs) {
     Workspace& W = h->ws;
     if (W.nrhs >= nrhs) return;
+    drop_graphs(h);  // captured kernels hold workspace pointers
     W.mem.release();
     W.gmem.release();
     W.gm_m = W.gm_nrhs = 0;
@@ -812,7 +821,7 @@ void apply_dev_T(ddlr_prec* h, int nrhs, const double* in, int64_t ldin, double*
         T* ys = (T*)W.ys;
         T* wsv = (T*)W.ws;
         a0_solve_dev<T, double, T>(h, F, nrhs, in, ldin, a1, n, st, done);  // step 1: A0 z = x
-        hipLaunchKernelGGL((k_csr_mv<T, T>), grid2(s, nrhs), dim3(256), 0, st, s, nrhs, h->etrp, h->etci,
+        hipLaunchKernelGGL((k_csr_mv<T, T>), dim3(grid_for(s)), dim3(256), 0, st, s, nrhs, h->etrp, h->etci,
                            F.etv, a1, n, (const T*)nullptr, 0, ys, s, done);  // step 2: y = E^T z
         LAUNCHCHK();
         if (h->nsys > 1) {  // per system of a batch (one column)
@@ -827,7 +836,7 @@ void apply_dev_T(ddlr_prec* h, int nrhs, const double* in, int64_t ldin, double*
             lr_coef<T, T>(h, F.U, s, nrhs, ys, s, 1, st, done);  // step 3: w = G_{k,theta}^{-1} y (eq. gkt)
             lr_expand<T, T>(h, F.U, s, nrhs, h->c0, ys, s, wsv, s, st, done);
         }
-        hipLaunchKernelGGL((k_csr_mv<T, double>), grid2(n, nrhs), dim3(256), 0, st, n, nrhs, h->erp, h->eci,
+        hipLaunchKernelGGL((k_csr_mv<T, double>), dim3(grid_for(n)), dim3(256), 0, st, n, nrhs, h->erp, h->eci,
                            F.ev, wsv, s, in, ldin, a2, n, done);  // step 4: v = E w, fused x + v
         LAUNCHCHK();
         a0_solve_dev<T, T, double>(h, F, nrhs, a2, n, out, ldout, st, done);  // step 5: A0 u = x + v
@@ -1100,7 +1109,7 @@ void lanczos_build(ddlr_prec* h, int k, int m_req, const double* v0_user, uint64
         LAUNCHCHK();
         double* EV = tmp.alloc<double>((size_t)n * k);
         double* Ucm = tmp.alloc<double>((size_t)n * k);
-        hipLaunchKernelGGL(k_csr_mv<double>, grid2(n, k), dim3(256), 0, st, n, k, h->erp, h->eci, h->f64.ev,
+        hipLaunchKernelGGL(k_csr_mv<double>, dim3(grid_for(n)), dim3(256), 0, st, n, k, h->erp, h->eci, h->f64.ev,
                            V, s, (const double*)nullptr, 0, EV, n, nullptr);
         LAUNCHCHK();
         a0_solve_dev<double, double, double>(h, h->f64, k, EV, n, Ucm, n, st, nullptr);
@@ -1168,7 +1177,21 @@ void lanczos_build(ddlr_prec* h, int k, int m_req, const double* v0_user, uint64
     tmp.release();
 }
 
+void drop_graphs(ddlr_prec* h) {
+    for (auto& g : h->cg_graphs) {
+        if (g.second.second) (void)hipGraphExecDestroy(g.second.second);
+        if (g.second.first) (void)hipGraphDestroy(g.second.first);
+    }
+    h->cg_graphs.clear();
+}
+
 void release_streams(ddlr_prec* h) {
+    drop_graphs(h);
+    if (h->cg_st) (void)hipStreamDestroy(h->cg_st);
+    if (h->ev_in) (void)hipEventDestroy(h->ev_in);
+    if (h->ev_out) (void)hipEventDestroy(h->ev_out);
+    h->cg_st = nullptr;
+    h->ev_in = h->ev_out = nullptr;
     if (h->side) (void)hipStreamDestroy(h->side);
     if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
     if (h->ev_join) (void)hipEventDestroy(h->ev_join);
@@ -1370,6 +1393,7 @@ void autotune(ddlr_prec* h, int nrhs, hipStream_t st, bool force) {
     if (h->capturing || h->nsys > 1) return;
     if (!force && (h->tune_mode == 0 || h->tune.count(nrhs))) return;
     ensure_ws(h, nrhs);
+    drop_graphs(h);  // captured launches embed the shape
     if (h->precision == DDLR_FP64) autotune_T<double>(h, h->f64, nrhs, st);
     else autotune_T<float>(h, h->f32, nrhs, st);
 }
@@ -1577,17 +1601,62 @@ static void lane_admit(ddlr_prec* h, int nr, const std::vector<int32_t>& start, 
 }
 
 // PCG on nr columns already gathered into W.r (b); result in W.x.
-static void pcg_dev(ddlr_prec* h, int nr, const ddlr_solve_options& o, hipStream_t st) {
+constexpr int kCgChunk = 8;
+
+// kCgChunk lane iterations on st: replayed from a graph captured on first use
+// for this column count (eager while profiling, or if capture fails)
+static void cg_chunk(ddlr_prec* h, int nr, hipStream_t st) {
+    if (h->prof || !h->use_graphs) {
+        for (int c = 0; c < kCgChunk; ++c) lane_iteration(h, nr, st);
+        return;
+    }
+    auto it = h->cg_graphs.find(nr);
+    if (it == h->cg_graphs.end()) {
+        h->capturing = true;
+        HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        bool ok = true;
+        try {
+            for (int c = 0; c < kCgChunk; ++c) lane_iteration(h, nr, st);
+        } catch (const SetupError&) {
+            ok = false;
+        }
+        hipGraph_t g = nullptr;
+        const hipError_t ec = hipStreamEndCapture(st, &g);
+        h->capturing = false;
+        hipGraphExec_t ge = nullptr;
+        if (ok && ec == hipSuccess && g && hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) == hipSuccess) {
+            it = h->cg_graphs.emplace(nr, std::make_pair(g, ge)).first;
+        } else {
+            (void)hipGetLastError();
+            if (g) (void)hipGraphDestroy(g);
+            h->use_graphs = false;  // fall back to eager launches for this handle
+            for (int c = 0; c < kCgChunk; ++c) lane_iteration(h, nr, st);
+            return;
+        }
+    }
+    HIPCHK(hipGraphLaunch(it->second.second, st));
+}
+
+static void pcg_dev(ddlr_prec* h, int nr, const ddlr_solve_options& o, hipStream_t ust) {
+    if (!h->cg_st) {
+        HIPCHK(hipStreamCreateWithFlags(&h->cg_st, hipStreamNonBlocking));  // default priority
+        HIPCHK(hipEventCreateWithFlags(&h->ev_in, hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&h->ev_out, hipEventDisableTiming));
+    }
+    hipStream_t st = h->cg_st;
+    HIPCHK(hipEventRecord(h->ev_in, ust));
+    HIPCHK(hipStreamWaitEvent(st, h->ev_in, 0));
     std::vector<int32_t> start(nr, 1), maxit(nr, o.maxit);
     std::vector<double> tol2(nr, o.rtol * o.rtol);
     lane_admit(h, nr, start, tol2, maxit, st);
-    const int chunk = 8;
-    for (int it = 0; it <= o.maxit; it += chunk) {
-        for (int c = 0; c < chunk; ++c) lane_iteration(h, nr, st);
+    for (int it = 0; it <= o.maxit; it += kCgChunk) {
+        cg_chunk(h, nr, st);
         HIPCHK(hipMemcpyAsync(h->ws.done_host, h->ws.done, sizeof(int), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         if (*h->ws.done_host) break;
     }
+    HIPCHK(hipEventRecord(h->ev_out, st));
+    HIPCHK(hipStreamWaitEvent(ust, h->ev_out, 0));
 }
 
 extern "C" {
@@ -1793,6 +1862,7 @@ ddlr_status ddlr_set_lowrank(ddlr_prec* h, int32_t variant, int32_t k, const dou
             const int32_t user = P.perm[P.dev2int[off + i]];
             for (int j = 0; j < k; ++j) Ur[(size_t)i * k + j] = U[user + (size_t)j * P.n];
         }
+        drop_graphs(h);  // captured kernels hold the low-rank pointers
         h->lrmem.release();
         h->dvec = nullptr;
         h->Hk = nullptr;

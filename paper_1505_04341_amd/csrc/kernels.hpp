@@ -611,13 +611,15 @@ __global__ __launch_bounds__(256) void k_csr_mv(int64_t rows, int nrhs, const in
                                                 int64_t ldx, T* __restrict__ y, int64_t ldy,
                                                 const int* __restrict__ done) {
     if (done && *done) return;
-    const int64_t r = blockIdx.y;  // grid (row chunks, nrhs)
-    const T* wr = w + r * ldw;
+    // one thread per row for all columns: the row's entries are read once
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < rows; i += (int64_t)gridDim.x * blockDim.x) {
-        T s = x ? (T)x[i + r * ldx] : T(0);
-        const int t1 = rp[i + 1];
-        for (int t = rp[i]; t < t1; ++t) s += v[t] * wr[ci[t]];
-        y[i + r * ldy] = s;
+        const int t0 = rp[i], t1 = rp[i + 1];
+        for (int r = 0; r < nrhs; ++r) {
+            T s = x ? (T)x[i + r * ldx] : T(0);
+            const T* wr = w + r * ldw;
+            for (int t = t0; t < t1; ++t) s += v[t] * wr[ci[t]];
+            y[i + r * ldy] = s;
+        }
     }
 }
 
