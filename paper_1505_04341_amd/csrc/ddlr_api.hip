@@ -81,6 +81,7 @@ template <typename T> struct DevFactors {
     T *lv = nullptr, *uv = nullptr, *dinv = nullptr;
     T *ev = nullptr, *etv = nullptr;  // E and E^T values
     T *U = nullptr;                   // low-rank basis, row-major (rows x k)
+    T *Ut = nullptr;                  // the same in MFMA tile order (k % 16 == 0), for U^T y
 };
 
 struct Workspace {
@@ -774,6 +775,9 @@ void lr_coef(ddlr_prec* h, const T* U, int64_t rows, int nrhs, const TY* y, int6
     else if (h->lr_plain)
         hipLaunchKernelGGL((k_lr_reduce<T, TY>), dim3(kLrBlocks), dim3(256), 0, st, rows, k, nrhs, U, y, ldy, W.part,
                            done);
+    else if (factors<T>(h).Ut && factors<T>(h).U == U)
+        hipLaunchKernelGGL((k_lr_reduce_t<T, TY>), dim3(kLrBlocks), dim3(256), 0, st, rows, k, nrhs,
+                           factors<T>(h).Ut, y, ldy, W.part, done);
     else
         hipLaunchKernelGGL((k_lr_reduce_mfma<T, TY>), dim3(kLrBlocks), dim3(256), 0, st, rows, k, nrhs, U, y, ldy,
                            W.part, done);
@@ -796,6 +800,10 @@ void lr_expand(ddlr_prec* h, const T* U, int64_t rows, int nrhs, double beta, co
     } else if (h->lr_plain) {
         hipLaunchKernelGGL((k_lr_expand<T, TIO>), dim3(grid_for(rows)), dim3(256), 0, st, rows, h->k, nrhs, U,
                            h->ws.coef, beta, in, ldin, out, ldout, done);
+    } else if (h->k % 16 == 0 && h->k <= 128) {
+        const int64_t tiles = (rows + 15) / 16;
+        hipLaunchKernelGGL((k_lr_expand_v<T, TIO>), dim3(grid_for(tiles, 4)), dim3(256), 0, st, rows, h->k, nrhs,
+                           U, h->ws.coef, beta, in, ldin, out, ldout, done);
     } else {
         const int64_t tiles = (rows + 15) / 16;
         hipLaunchKernelGGL((k_lr_expand_mfma<T, TIO>), dim3(grid_for(tiles, 4)), dim3(256), 0, st, rows, h->k, nrhs,
@@ -931,6 +939,27 @@ void dot_dev(ddlr_prec* h, int nrhs, const double* a, const double* b, int64_t l
     LAUNCHCHK();
     hipLaunchKernelGGL(k_reduce_cols, dim3(nrhs), dim3(256), 0, st, kRedBlocks, nrhs, W.part, W.sums, done);
     LAUNCHCHK();
+}
+
+// Tile-ordered copies of U_k for the wide-load reduction (k a multiple of 16)
+void make_tiled_basis(ddlr_prec* h) {
+    h->f64.Ut = nullptr;
+    h->f32.Ut = nullptr;
+    if (h->k < 16 || h->k % 16 != 0 || h->k > 128) return;
+    const int64_t rows = h->urows;
+    const int64_t total = (rows + 15) / 16 * 16 * h->k;
+    if (h->f64.U) {
+        h->f64.Ut = h->lrmem.alloc<double>((size_t)total);
+        hipLaunchKernelGGL(k_make_ut<double>, dim3(grid_for(total)), dim3(256), 0, nullptr, rows, h->k, h->f64.U,
+                           h->f64.Ut);
+        LAUNCHCHK();
+    }
+    if (h->f32.U) {
+        h->f32.Ut = h->lrmem.alloc<float>((size_t)total);
+        hipLaunchKernelGGL(k_make_ut<float>, dim3(grid_for(total)), dim3(256), 0, nullptr, rows, h->k, h->f32.U,
+                           h->f32.Ut);
+        LAUNCHCHK();
+    }
 }
 
 // BF16 copies of U_k for the DDLR_FP32_UK_BF16 configuration
@@ -1173,6 +1202,7 @@ void lanczos_build(ddlr_prec* h, int k, int m_req, const double* v0_user, uint64
         LAUNCHCHK();
     }
     make_bf16_basis(h);
+    make_tiled_basis(h);
     HIPCHK(hipDeviceSynchronize());
     tmp.release();
 }
@@ -1879,6 +1909,7 @@ ddlr_status ddlr_set_lowrank(ddlr_prec* h, int32_t variant, int32_t k, const dou
         }
         h->ubr = h->ubt = nullptr;
         make_bf16_basis(h);
+        make_tiled_basis(h);
         if (variant == 1) {
             h->lam.assign(aux, aux + k);
             h->theta = aux[k];

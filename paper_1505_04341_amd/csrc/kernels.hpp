@@ -825,6 +825,134 @@ __global__ __launch_bounds__(256) void k_lr_expand_mfma(int64_t rows, int k, int
     }
 }
 
+// ----------------------- low-rank correction, wide operand loads (k % 16 == 0)
+//
+// The kernels above load one U_k element per lane per MFMA step, so at k =
+// 32 a wave walks its rows in a chain of 4-byte loads feeding MFMAs and the
+// correction runs at a fraction of HBM bandwidth.  These variants load the
+// operands of four MFMA steps with one 16-byte (FP32) or two 16-byte (FP64)
+// loads per lane.
+//
+// Reduction: U_k is also kept in MFMA tile order, Ut: for row tile rt (16
+// rows) and column tile jt (16 columns), lane l = (m = l%16, q = l/16) holds
+// four consecutive values U[16 rt + 4q + s][16 jt + m], s = 0..3, which are
+// its A operands (row j = 16jt + m, K index q) for the four K steps of the
+// tile; the y operand of lane (n = l%16, q) at step s is y[16 rt + 4q + s][n].
+template <typename T>
+__global__ void k_make_ut(int64_t rows, int k, const T* __restrict__ U, T* __restrict__ Ut) {
+    const int njt = k >> 4;
+    const int64_t nrt = (rows + 15) >> 4;
+    const int64_t total = nrt * njt * 256;
+    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
+        const int s = (int)(g & 3), l = (int)((g >> 2) & 63);
+        const int64_t t = g >> 8;
+        const int jt = (int)(t % njt);
+        const int64_t rt = t / njt;
+        const int64_t row = 16 * rt + 4 * (l >> 4) + s;
+        const int j = 16 * jt + (l & 15);
+        Ut[g] = row < rows ? U[row * k + j] : T(0);
+    }
+}
+
+template <typename T> struct Vec4 { typedef T __attribute__((ext_vector_type(4))) type; };
+
+template <typename T, typename TY = T>
+__global__ __launch_bounds__(256) void k_lr_reduce_t(int64_t rows, int k, int nrhs, const T* __restrict__ Ut,
+                                                     const TY* __restrict__ y, int64_t ldy, double* __restrict__ part,
+                                                     const int* __restrict__ done) {
+    typedef typename MfmaAcc<T>::type acc_t;
+    typedef typename Vec4<T>::type v4;
+    __shared__ double stage[4][64];
+    if (done && *done) return;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int nwaves = gridDim.x * 4;
+    const int64_t gw = (int64_t)blockIdx.x * 4 + wv;
+    const int64_t nrt = (rows + 15) >> 4;
+    const int64_t per = (nrt + nwaves - 1) / nwaves;
+    const int64_t t0 = gw * per, t1 = t0 + per < nrt ? t0 + per : nrt;
+    const int njt = k >> 4;  // <= 8
+    acc_t acc[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) acc[t] = acc_t{0, 0, 0, 0};
+    const int n = lane & 15, q = lane >> 4;
+    const v4* Ut4 = reinterpret_cast<const v4*>(Ut);
+#pragma unroll 2
+    for (int64_t rt = t0; rt < t1; ++rt) {
+        T b[4];
+#pragma unroll
+        for (int st = 0; st < 4; ++st) {
+            const int64_t row = 16 * rt + 4 * q + st;
+            b[st] = (row < rows && n < nrhs) ? (T)y[row + n * ldy] : T(0);
+        }
+#pragma unroll
+        for (int jt = 0; jt < 8; ++jt)
+            if (jt < njt) {
+                const v4 a = Ut4[(rt * njt + jt) * 64 + lane];
+#pragma unroll
+                for (int st = 0; st < 4; ++st) acc[jt] = MfmaAcc<T>::step(a[st], b[st], acc[jt]);
+            }
+    }
+    // acc[t] holds C[j = 16t + row(lane, v)][rhs = lane%16]; fold the 4 waves through LDS
+    for (int t = 0; t < njt; ++t) {
+        for (int v = 0; v < 4; ++v) {
+            stage[wv][lane] = (double)acc[t][v];
+            __syncthreads();
+            const int j = t * 16 + MfmaAcc<T>::row(lane, v), rr = lane & 15;
+            if (wv == 0 && rr < nrhs)
+                part[((int64_t)blockIdx.x * nrhs + rr) * k + j] =
+                    (stage[0][lane] + stage[1][lane]) + (stage[2][lane] + stage[3][lane]);
+            __syncthreads();
+        }
+    }
+}
+
+// Expansion: out[row][r] = beta in[row][r] + sum_j U[row][j] coef[r][j] with
+// row-major U_k.  Lane (m = l%16 -> row, q = l/16) loads U[row][16c + 4q ..
+// 16c + 4q + 3] in one go and uses element s at K step s, whose K index q
+// stands for column j = 16c + 4q + s; the coefficient operand follows the
+// same j.  M = 16 rows, N = nrhs (<= 16).
+template <typename T, typename TIO = T>
+__global__ __launch_bounds__(256) void k_lr_expand_v(int64_t rows, int k, int nrhs, const T* __restrict__ U,
+                                                     const double* __restrict__ coef, double beta, const TIO* in,
+                                                     int64_t ldin, TIO* out, int64_t ldout,
+                                                     const int* __restrict__ done) {
+    typedef typename MfmaAcc<T>::type acc_t;
+    typedef typename Vec4<T>::type v4;
+    __shared__ T cf[128 * 16];  // cf[j*16 + r]
+    if (done && *done) return;
+    for (int qq = threadIdx.x; qq < 128 * 16; qq += blockDim.x) {
+        const int j = qq >> 4, rr = qq & 15;
+        cf[qq] = (j < k && rr < nrhs) ? (T)coef[rr * k + j] : T(0);
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int m = lane & 15, q = lane >> 4;
+    const int nc = k >> 4;
+    const int64_t ntiles = (rows + 15) >> 4;
+    for (int64_t tile = (int64_t)blockIdx.x * 4 + wv; tile < ntiles; tile += (int64_t)gridDim.x * 4) {
+        const int64_t i = tile * 16 + m;
+        const int64_t ic = i < rows ? i : rows - 1;  // clamped row: loaded, never stored
+        acc_t acc = acc_t{0, 0, 0, 0};
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+            if (c < nc) {
+                const v4 a = *reinterpret_cast<const v4*>(U + ic * k + 16 * c + 4 * q);
+#pragma unroll
+                for (int st = 0; st < 4; ++st)
+                    acc = MfmaAcc<T>::step(a[st], cf[(16 * c + 4 * q + st) * 16 + m], acc);
+            }
+        const int rr = lane & 15;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int64_t row = tile * 16 + MfmaAcc<T>::row(lane, v);
+            if (row < rows && rr < nrhs) {
+                const double o = beta * (double)in[row + rr * ldin] + (double)acc[v];
+                out[row + rr * ldout] = (TIO)o;
+            }
+        }
+    }
+}
+
 // ------------------------------------- low-rank correction, BF16 U_k (gfx950)
 //
 // U_k stored in bfloat16 (rounded from the FP64 basis), products on the

@@ -492,3 +492,35 @@ def test_autotuner_shapes_bitwise(prec):
     D.ddlr_a0_solve(h, x, y)
     torch.cuda.synchronize()
     assert torch.equal(y.cpu(), outs[0])
+
+
+def wide_k():
+    """A 3-D case with k a multiple of 16 (the wide-load low-rank kernels) and
+    interface rows not a multiple of 16 (ragged last tile)."""
+    A = w.laplacian_3d(22, 19, 17)
+    return dict(A=A, part=w.box_partition((22, 19, 17), (3, 2, 2)), p=12, k=32, m=48)
+
+
+@pytest.mark.parametrize("variant", [1, 2])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("k", [16, 32])
+def test_apply_wide_lowrank_kernels(variant, prec, k):
+    """k % 16 == 0 selects the low-rank kernels with 16-byte operand loads
+    (tile-ordered U_k for U_k^T y, permuted K for U_k c): the apply matches the
+    oracle (FP64 to 1e-10, FP32 to single-precision rounding) and the
+    one-element-per-lane MFMA kernels up to rounding order."""
+    cfg = wide_k()
+    cfg["k"], cfg["m"] = k, 2 * k + 8
+    say("wide lowrank", variant, prec, k)
+    p_ = D.FP64 if prec == "fp64" else D.FP32
+    h, o = setup_pair(cfg, variant=variant, precision=p_)
+    o.lowrank(variant, cfg["k"], cfg["m"], w.lanczos_start(cfg["A"].n, 0))
+    lr_ = o.get_lowrank()
+    D.ddlr_set_lowrank(h, variant, *lr_)
+    n = cfg["A"].n
+    tol = 1e-10 if prec == "fp64" else 1e-4
+    for nrhs in (1, 6, 16):
+        x = np.random.default_rng(nrhs).standard_normal((n, nrhs))
+        y = torch.empty((nrhs, n), dtype=torch.float64, device=DEV)
+        D.ddlr_apply(h, to_dev(x), y)
+        assert rel(to_host(y), o.apply(x)) <= tol, nrhs
