@@ -91,6 +91,7 @@ struct Workspace {
     // preconditioner temporaries (type of the preconditioner)
     void *a0 = nullptr, *a1 = nullptr, *a2 = nullptr, *a3 = nullptr, *ys = nullptr, *ws = nullptr;
     double *part = nullptr, *sums = nullptr, *coef = nullptr, *lrsum = nullptr;
+    double* xa = nullptr;  // per-lane step of the deferred x update
     CgLane* lanes = nullptr;
     int* done = nullptr;
     int* done_host = nullptr;
@@ -150,6 +151,9 @@ struct ddlr_prec {
     // chunk of iterations can be captured once per column count into a graph
     hipStream_t cg_st = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    // x += alpha p runs on its own stream beside the preconditioner
+    hipStream_t x_st = nullptr;
+    hipEvent_t ev_xf = nullptr, ev_xj = nullptr;
     std::map<int, std::pair<hipGraph_t, hipGraphExec_t>> cg_graphs;
     bool use_graphs = true;
     bool lr_plain = false;                      // low-rank kernels without MFMA (comparison only)
@@ -573,6 +577,7 @@ void ensure_ws(ddlr_prec* h, int nrhs) {
     W.sums = W.mem.alloc<double>((size_t)std::max(nrhs, h->nsys) * 256);
     W.coef = W.mem.alloc<double>((size_t)std::max(nrhs, h->nsys) * kk);
     W.lrsum = W.mem.alloc<double>((size_t)std::max(nrhs, 1) * kk);
+    W.xa = W.mem.alloc<double>(std::max(nrhs, 1));
     W.lanes = W.mem.alloc<CgLane>(std::max(nrhs, h->nsys));
     W.adm_start = W.mem.alloc<int32_t>(std::max(nrhs, 1));
     W.adm_maxit = W.mem.alloc<int32_t>(std::max(nrhs, 1));
@@ -931,6 +936,39 @@ void cg_xr_dev(ddlr_prec* h, int nr, hipStream_t st) {
     LAUNCHCHK();
 }
 
+// streams for the lane-phase CG (created outside any graph capture)
+void ensure_cg_streams(ddlr_prec* h) {
+    if (h->x_st) return;
+    HIPCHK(hipStreamCreateWithFlags(&h->x_st, hipStreamNonBlocking));  // default priority
+    HIPCHK(hipEventCreateWithFlags(&h->ev_xf, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&h->ev_xj, hipEventDisableTiming));
+}
+
+template <int S> void cg_split_launch(ddlr_prec* h, int nr, hipStream_t st) {
+    Workspace& W = h->ws;
+    const int64_t n = h->ndev;
+    hipLaunchKernelGGL(k_cg_r<S>, dim3(kRedBlocks), dim3(256), 0, st, n, nr, W.lanes, W.q, W.r, n, W.xa, W.part,
+                       W.done);
+    LAUNCHCHK();
+    HIPCHK(hipEventRecord(h->ev_xf, st));
+    HIPCHK(hipStreamWaitEvent(h->x_st, h->ev_xf, 0));
+    hipLaunchKernelGGL(k_cg_x<S>, dim3(grid_for(n)), dim3(256), 0, h->x_st, n, nr, W.xa, W.p, W.x, n);
+    LAUNCHCHK();
+    HIPCHK(hipEventRecord(h->ev_xj, h->x_st));
+}
+
+// r -= alpha q (with r.r partials) on st; x += alpha p forked to the x stream
+// (joined by cg_join before p changes)
+void cg_split_dev(ddlr_prec* h, int nr, hipStream_t st) {
+    switch (lane_stride(nr)) {
+    case 1: cg_split_launch<1>(h, nr, st); break;
+    case 2: cg_split_launch<2>(h, nr, st); break;
+    case 4: cg_split_launch<4>(h, nr, st); break;
+    case 8: cg_split_launch<8>(h, nr, st); break;
+    default: cg_split_launch<16>(h, nr, st); break;
+    }
+}
+
 // sums[r] = a_r . b_r
 void dot_dev(ddlr_prec* h, int nrhs, const double* a, const double* b, int64_t ld, hipStream_t st, const int* done) {
     Workspace& W = h->ws;
@@ -1222,6 +1260,11 @@ void release_streams(ddlr_prec* h) {
     if (h->ev_out) (void)hipEventDestroy(h->ev_out);
     h->cg_st = nullptr;
     h->ev_in = h->ev_out = nullptr;
+    if (h->x_st) (void)hipStreamDestroy(h->x_st);
+    if (h->ev_xf) (void)hipEventDestroy(h->ev_xf);
+    if (h->ev_xj) (void)hipEventDestroy(h->ev_xj);
+    h->x_st = nullptr;
+    h->ev_xf = h->ev_xj = nullptr;
     if (h->side) (void)hipStreamDestroy(h->side);
     if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
     if (h->ev_join) (void)hipEventDestroy(h->ev_join);
@@ -1600,7 +1643,9 @@ static void lane_iteration(ddlr_prec* h, int nr, hipStream_t st) {
     LAUNCHCHK();
     hipLaunchKernelGGL(k_lane_scalar, dim3(1), dim3(64), 0, st, 2, nr, W.sums, W.lanes, W.done);
     LAUNCHCHK();
-    cg_xr_dev(h, nr, st);
+    const bool split = h->x_st != nullptr;
+    if (split) cg_split_dev(h, nr, st);  // x += alpha p overlaps the preconditioner
+    else cg_xr_dev(h, nr, st);
     hipLaunchKernelGGL(k_reduce_cols, dim3(nr), dim3(256), 0, st, kRedBlocks, nr, W.part, W.sums, W.done);
     LAUNCHCHK();
     hipLaunchKernelGGL(k_lane_scalar, dim3(1), dim3(64), 0, st, 3, nr, W.sums, W.lanes, W.done);
@@ -1609,6 +1654,7 @@ static void lane_iteration(ddlr_prec* h, int nr, hipStream_t st) {
     dot_dev(h, nr, W.r, W.z, n, st, W.done);
     hipLaunchKernelGGL(k_lane_scalar, dim3(1), dim3(64), 0, st, 4, nr, W.sums, W.lanes, W.done);
     LAUNCHCHK();
+    if (split) HIPCHK(hipStreamWaitEvent(st, h->ev_xj, 0));  // x used the old p
     const int S = lane_stride(nr);
     hipLaunchKernelGGL(k_cg_p, dim3(grid_for(n * S)), dim3(256), 0, st, n, nr, ilog2(S), W.lanes, W.z, W.p, n, W.done);
     LAUNCHCHK();
@@ -1668,6 +1714,7 @@ static void cg_chunk(ddlr_prec* h, int nr, hipStream_t st) {
 }
 
 static void pcg_dev(ddlr_prec* h, int nr, const ddlr_solve_options& o, hipStream_t ust) {
+    ensure_cg_streams(h);
     if (!h->cg_st) {
         HIPCHK(hipStreamCreateWithFlags(&h->cg_st, hipStreamNonBlocking));  // default priority
         HIPCHK(hipEventCreateWithFlags(&h->ev_in, hipEventDisableTiming));
@@ -2553,6 +2600,7 @@ ddlr_status ddlr_server_add(ddlr_server* S, ddlr_prec* h, int32_t* matrix_id) {
         const size_t stage = (size_t)h->ndev * S->slots * sizeof(double);
         // workspace for the slots, then the budget check on everything resident
         ensure_ws(h, S->slots);
+        ensure_cg_streams(h);
         const size_t need = prec_bytes(h) + stage;
         if (S->budget > 0 && S->used + need > S->budget) {
             (void)before;

@@ -1254,6 +1254,85 @@ __global__ __launch_bounds__(256) void k_cg_xr(int64_t n, int nrhs, const CgLane
     }
 }
 
+// The two halves of k_cg_xr for overlapping x with the preconditioner: r -=
+// alpha q with the r.r partials on the critical path (it also records the
+// step xa[c] = alpha for active lanes, 0 otherwise), and x += xa p on a side
+// stream while the preconditioner runs.  Same per-element arithmetic as
+// k_cg_xr.
+template <int S>
+__global__ __launch_bounds__(256) void k_cg_r(int64_t n, int nrhs, const CgLane* __restrict__ L,
+                                              const double* __restrict__ q, double* __restrict__ r, int64_t ld,
+                                              double* __restrict__ xa, double* __restrict__ part,
+                                              const int* __restrict__ done) {
+    __shared__ double sh[4];
+    if (done && *done) {  // nothing running: the forked x update must do nothing
+        if (blockIdx.x == 0 && threadIdx.x < nrhs) xa[threadIdx.x] = 0.0;
+        return;
+    }
+    bool act[S];
+    double a[S], acc[S];
+#pragma unroll
+    for (int c = 0; c < S; ++c) {
+        act[c] = c < nrhs && L[c].active;
+        a[c] = c < nrhs ? L[c].alpha : 0.0;
+        acc[c] = 0.0;
+    }
+    if (blockIdx.x == 0 && threadIdx.x < nrhs) xa[threadIdx.x] = L[threadIdx.x].active ? L[threadIdx.x].alpha : 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+#pragma unroll
+        for (int c = 0; c < S; ++c) {
+            if (c < nrhs) {
+                const int64_t o = i + c * ld;
+                double ri = r[o];
+                if (act[c]) {
+                    ri -= a[c] * q[o];
+                    r[o] = ri;
+                }
+                acc[c] += ri * ri;
+            }
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < S; ++c) {
+        if (c < nrhs) {
+            const double t = block_sum256(acc[c], sh);
+            if (threadIdx.x == 0) part[blockIdx.x * nrhs + c] = t;
+        }
+    }
+}
+
+// k_cg_x does not read the done flag: it may start after the residual check
+// of the same iteration has set it, and must still apply that iteration's
+// step.  Its own work list is the xa snapshot (all zero: nothing to do).
+template <int S>
+__global__ __launch_bounds__(256) void k_cg_x(int64_t n, int nrhs, const double* __restrict__ xa,
+                                              const double* __restrict__ p, double* __restrict__ x, int64_t ld) {
+    double a[S];
+    bool any = false;
+#pragma unroll
+    for (int c = 0; c < S; ++c) {
+        a[c] = c < nrhs ? xa[c] : 0.0;
+        any = any || a[c] != 0.0;
+    }
+    if (!any) return;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double pv[S];
+        if constexpr (S == 1) {
+            pv[0] = p[i];
+        } else {
+#pragma unroll
+            for (int c = 0; c < S; c += 2) {
+                const double2 t = *reinterpret_cast<const double2*>(p + i * S + c);
+                pv[c] = t.x;
+                pv[c + 1] = t.y;
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < S; ++c)
+            if (c < nrhs && a[c] != 0.0) x[i + c * ld] += a[c] * pv[c];
+    }
+}
+
 // p = z + beta p (active lanes); z column-major (ld), p interleaved (stride
 // S = 2^lgS)
 __global__ __launch_bounds__(256) void k_cg_p(int64_t n, int nrhs, int lgS, const CgLane* __restrict__ L,
