@@ -155,7 +155,7 @@ struct ddlr_prec {
     hipStream_t x_st = nullptr;
     hipEvent_t ev_xf = nullptr, ev_xj = nullptr;
     std::map<int, std::pair<hipGraph_t, hipGraphExec_t>> cg_graphs;
-    bool use_graphs = true;
+    bool use_graphs = true;  // DDLR_CG_GRAPH=0: eager launches
     bool lr_plain = false;                      // low-rank kernels without MFMA (comparison only)
     // the interface block's level kernels run on a side stream, overlapping the
     // B-block kernel (fork/join by events on the caller's stream)
@@ -1354,6 +1354,7 @@ ddlr_status ddlr_setup(const ddlr_csr* A, const int32_t* part, int32_t p, int32_
             upload_structures(h.get());
             if (const char* env = std::getenv("DDLR_NO_OVERLAP")) h->overlap = env[0] != '1';
             h->tune_mode = opt.no_autotune ? 0 : 1;
+            if (const char* env = std::getenv("DDLR_CG_GRAPH")) h->use_graphs = env[0] != '0';
             if (!h->wide.empty()) {
                 HIPCHK(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));  // default priority
                 HIPCHK(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
