@@ -52,6 +52,10 @@ def _load():
         lib.orc_a0_solve.argtypes = [P, C.c_int, P, P]
         lib.orc_lowrank.restype = C.c_int
         lib.orc_lowrank.argtypes = [P, C.c_int, C.c_int, C.c_int, C.c_int, P]
+        lib.orc_lowrank_ctl.restype = C.c_int
+        lib.orc_lowrank_ctl.argtypes = [P, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, C.c_int, P]
+        lib.orc_extend.restype = C.c_int
+        lib.orc_extend.argtypes = [P, C.c_int, C.c_int, C.c_int, C.c_double, C.c_int]
         lib.orc_lanczos_record.argtypes = [P, P, P, P]
         lib.orc_lanczos_basis.argtypes = [P, P]
         lib.orc_get_lowrank.argtypes = [P, P, P]
@@ -162,14 +166,32 @@ class Oracle:
         _lib.orc_a0_solve(self._h, x2.shape[1], _p(x2), _p(z))
         return z[:, 0] if one else z
 
-    def lowrank(self, variant, k, m, v0, theta_zero=False):
+    def lowrank(self, variant, k, m, v0, theta_zero=False, check=0, eps=1e-4):
+        """Lanczos of m steps (check = 0) or of at most m steps stopped by the
+        convergence test every `check` steps with tolerance eps, then the
+        low-rank build with rank k."""
         v0 = np.ascontiguousarray(v0, dtype=np.float64)
-        st = _lib.orc_lowrank(self._h, int(variant), int(k), int(m), 1 if theta_zero else 0, _p(v0))
+        st = _lib.orc_lowrank_ctl(self._h, int(variant), int(k), int(m), int(check), float(eps),
+                                  1 if theta_zero else 0, _p(v0))
         if st != OK:
             raise OracleError(st, "lowrank")
         self.variant, self.k = int(variant), int(k)
         self.spd = bool(_lib.orc_size(self._h, 10))
         return self
+
+    def extend(self, k, more, check=0, eps=1e-4, theta_zero=False):
+        """Continue the stored Lanczos run by `more` steps (or until the
+        convergence test holds) and rebuild with rank k."""
+        st = _lib.orc_extend(self._h, int(k), int(more), int(check), float(eps), 1 if theta_zero else 0)
+        if st != OK:
+            raise OracleError(st, "extend")
+        self.k = int(k)
+        self.spd = bool(_lib.orc_size(self._h, 10))
+        return self
+
+    @property
+    def msteps(self):
+        return int(_lib.orc_size(self._h, 7))
 
     def lanczos_record(self):
         msteps = int(_lib.orc_size(self._h, 7))

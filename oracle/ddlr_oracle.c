@@ -96,7 +96,11 @@ typedef struct {
     int msteps;
     double *ta, *tb;  /* alpha_1..alpha_m, beta_1..beta_m */
     double *ritz;     /* descending, length msteps */
-    double *Q;        /* s x msteps */
+    double *Q;        /* s x (msteps + 1): q_1..q_m and q_{m+1} */
+    int qcap;         /* columns allocated in Q, ta, tb */
+    int lvariant;     /* operator of the stored run (1 or 2), 0 if none */
+    int broke;        /* the stored run ended in an invariant subspace */
+    double amax;      /* max |alpha_i| so far */
 } orc_t;
 
 static void *xcalloc(size_t n, size_t sz) {
@@ -511,25 +515,64 @@ static void jacobi_eig(int m, double *T, double *ev, double *V) {
  * applied twice) on the s x s operator; start vector v0 (length s, internal
  * interface order).  Stops early on breakdown (beta_j <= 1e-12 max|alpha|).
  * Returns the number of steps taken. */
-static int lanczos(orc_t *o, int variant, int m, const double *v0) {
-    const int64_t s = o->s, n = o->n;
+/* Sum of the k largest eigenvalues of the leading j x j block of T_m
+ * (the sigma of the convergence test, eq. converge); cyclic Jacobi. */
+static double ritz_top_sum(const orc_t *o, int j, int k) {
+    double *T = xcalloc((int64_t)j * j, sizeof(double));
+    double *V = xcalloc((int64_t)j * j, sizeof(double));
+    double *ev = xcalloc(j, sizeof(double));
+    for (int i = 0; i < j; ++i) {
+        T[i + i * j] = o->ta[i];
+        if (i + 1 < j) { T[i + 1 + i * j] = o->tb[i]; T[i + (i + 1) * j] = o->tb[i]; }
+    }
+    jacobi_eig(j, T, ev, V);
+    /* k largest by repeated selection */
+    double sum = 0.0;
+    for (int c = 0; c < k && c < j; ++c) {
+        int best = -1;
+        for (int i = 0; i < j; ++i)
+            if (ev[i] == ev[i] && (best < 0 || ev[i] > ev[best])) best = i;
+        sum += ev[best];
+        ev[best] = NAN;
+    }
+    free(T); free(V); free(ev);
+    return sum;
+}
+
+/* Make room for m_max Lanczos steps (q_1..q_{m_max+1}), keeping the run so far. */
+static void lanczos_reserve(orc_t *o, int m_max) {
+    if (m_max + 1 <= o->qcap) return;
+    const int64_t s = o->s;
+    double *Q = xcalloc(s * (int64_t)(m_max + 1), sizeof(double));
+    double *ta = xcalloc(m_max + 1, sizeof(double)), *tb = xcalloc(m_max + 1, sizeof(double));
+    if (o->Q) memcpy(Q, o->Q, s * (int64_t)(o->msteps + 1) * sizeof(double));
+    if (o->ta) memcpy(ta, o->ta, o->msteps * sizeof(double));
+    if (o->tb) memcpy(tb, o->tb, o->msteps * sizeof(double));
     free(o->Q); free(o->ta); free(o->tb);
-    o->Q = xcalloc(s * (int64_t)(m + 1), sizeof(double));
-    o->ta = xcalloc(m + 1, sizeof(double));
-    o->tb = xcalloc(m + 1, sizeof(double));
+    o->Q = Q; o->ta = ta; o->tb = tb;
+    o->qcap = m_max + 1;
+}
+
+/* Lanczos on E^T A0^{-1} E (DDLR-1) or E^T A0^{-2} E (DDLR-2), Sec. 4.3, with
+ * full reorthogonalisation (classical Gram-Schmidt applied twice).  Continues
+ * the stored run from step msteps up to m_max steps.  With check > 0 it stops
+ * early at the first step m that is a multiple of check, with m >= k + 1,
+ * where the sums of the k largest Ritz values of T_{m-1} and T_m satisfy
+ * |sigma_m - sigma_{m-1}| / |sigma_{m-1}| < eps (eq. converge). */
+static int lanczos_run(orc_t *o, int m_max, int check, double eps, int k) {
+    const int64_t s = o->s, n = o->n;
+    const int variant = o->lvariant;
+    lanczos_reserve(o, m_max);
     double *w = xcalloc(s, sizeof(double));
-    double *c = xcalloc(m + 1, sizeof(double));
+    double *c = xcalloc(m_max + 1, sizeof(double));
     double *t1 = xcalloc(n, sizeof(double)), *t2 = xcalloc(n, sizeof(double));
-    double nv = nrm2(v0, s);
-    for (int64_t i = 0; i < s; ++i) o->Q[i] = v0[i] / nv;
-    double amax = 0.0;
     int j;
-    for (j = 0; j < m; ++j) {
+    for (j = o->msteps; j < m_max && !o->broke; ++j) {
         double *qj = o->Q + s * (int64_t)j;
         lanczos_op(o, variant, qj, w, t1, t2);
         double aj = dot(qj, w, s);
         o->ta[j] = aj;
-        if (fabs(aj) > amax) amax = fabs(aj);
+        if (fabs(aj) > o->amax) o->amax = fabs(aj);
         for (int64_t i = 0; i < s; ++i) w[i] -= aj * qj[i];
         if (j > 0) {
             double *qp = o->Q + s * (int64_t)(j - 1);
@@ -544,14 +587,30 @@ static int lanczos(orc_t *o, int variant, int m, const double *v0) {
         }
         double bj = nrm2(w, s);
         o->tb[j] = bj;
-        if (bj <= 1e-12 * amax) { ++j; break; }  /* invariant subspace found */
+        o->msteps = j + 1;
+        if (bj <= 1e-12 * o->amax) { o->broke = 1; break; }  /* invariant subspace found */
         double *qn = o->Q + s * (int64_t)(j + 1);  /* q_{j+1}, kept also after the last step */
         for (int64_t i = 0; i < s; ++i) qn[i] = w[i] / bj;
-        if (j + 1 == m) { ++j; break; }
+        const int m = j + 1;
+        if (check > 0 && m % check == 0 && m >= k + 1) {
+            const double sp = ritz_top_sum(o, m - 1, k), sm = ritz_top_sum(o, m, k);
+            if (fabs((sm - sp) / sp) < eps) break;
+        }
     }
     free(w); free(c); free(t1); free(t2);
-    o->msteps = j;
-    return j;
+    return o->msteps;
+}
+
+/* Start a new run from v0 (interface order, not normalised). */
+static void lanczos_start(orc_t *o, int variant, const double *v0) {
+    const int64_t s = o->s;
+    o->msteps = 0;
+    o->broke = 0;
+    o->amax = 0.0;
+    o->lvariant = variant;
+    lanczos_reserve(o, 1);
+    double nv = nrm2(v0, s);
+    for (int64_t i = 0; i < s; ++i) o->Q[i] = v0[i] / nv;
 }
 
 /* Ritz pairs of T_m (descending, stable by index); each eigenvector's
@@ -831,16 +890,36 @@ void orc_a0_solve(const orc_t *o, int nrhs, const double *x, double *z) {
 }
 
 /* Lanczos + low-rank build. v0: length n, user order (interface entries used). */
-int orc_lowrank(orc_t *o, int variant, int k, int m, int thetamode, const double *v0) {
+/* Low-rank build from a Lanczos run of m steps (check = 0), or of up to m
+ * steps stopped by eq. (converge) tested every check steps with tolerance eps
+ * (Sec. 5: every 10 steps, eps = 1e-4, at most 5k steps). */
+int orc_lowrank_ctl(orc_t *o, int variant, int k, int m, int check, double eps, int thetamode, const double *v0) {
     if (variant != 1 && variant != 2) return ORC_E_INVALID;
-    if (k < 1 || k + 1 > o->s || m < k + 1) return ORC_E_INVALID;
+    if (k < 1 || k + 1 > o->s || m < k + 1 || check < 0) return ORC_E_INVALID;
     if (m > o->s) m = (int)o->s;
     double *q = xcalloc(o->s, sizeof(double));
     for (int64_t y = 0; y < o->s; ++y) q[y] = v0[o->perm[o->m + y]];
-    lanczos(o, variant, m, q);
+    lanczos_start(o, variant, q);
     free(q);
+    lanczos_run(o, m, check, eps, k);
     if (o->msteps < k + 1) return ORC_E_LANCZOS;
     return build_lowrank(o, variant, k, thetamode);
+}
+
+int orc_lowrank(orc_t *o, int variant, int k, int m, int thetamode, const double *v0) {
+    return orc_lowrank_ctl(o, variant, k, m, 0, 0.0, thetamode, v0);
+}
+
+/* Improving a given preconditioner (Sec. on improving): continue the stored
+ * Lanczos run by `more` steps (check = 0) or until eq. (converge) holds
+ * within `more` steps, then rebuild the low-rank part with rank k. */
+int orc_extend(orc_t *o, int k, int more, int check, double eps, int thetamode) {
+    if (o->lvariant == 0 || more < 0 || check < 0 || k < 1 || k + 1 > o->s) return ORC_E_INVALID;
+    int m = o->msteps + more;
+    if (m > o->s) m = (int)o->s;
+    if (!o->broke) lanczos_run(o, m, check, eps, k);
+    if (o->msteps < k + 1) return ORC_E_LANCZOS;
+    return build_lowrank(o, o->lvariant, k, thetamode);
 }
 
 void orc_lanczos_record(const orc_t *o, double *ta, double *tb, double *ritzv) {

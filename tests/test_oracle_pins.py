@@ -537,3 +537,53 @@ def test_gmres_indefinite():
     oe.set_lowrank(1, _user_rows(oe, U), lam, 0.0)
     _, info_e = oe.gmres(b[:, 0])
     assert info_e["its"][0] == 1
+
+
+# ------------------------------------------- Lanczos control and rank extension
+def _sigma(ta, tb, j, k):
+    """Sum of the k largest eigenvalues of the leading j x j block of T (LAPACK)."""
+    T = np.diag(ta[:j]) + np.diag(tb[: j - 1], 1) + np.diag(tb[: j - 1], -1)
+    return float(np.sort(np.linalg.eigvalsh(T))[::-1][:k].sum())
+
+
+@pytest.mark.parametrize("variant", [1, 2])
+def test_lanczos_convergence_rule(variant):
+    """Sec. 5 / eq. (converge): checked every 10 steps, the run stops at the
+    first multiple m of 10 (m >= k+1) with |sigma_m - sigma_{m-1}| <
+    eps |sigma_{m-1}|, sigma_j = sum of the k largest Ritz values of T_j.
+    The stopping step is re-derived from the recorded T with LAPACK."""
+    cfg = w.config("small3d")
+    k, eps, mmax = 10, 1e-4, 5 * 10
+    o = Oracle(cfg["A"], cfg["part"], cfg["p"])
+    o.lowrank(variant, k, mmax, w.lanczos_start(cfg["A"].n, 0), check=10, eps=eps)
+    ta, tb, _ = o.lanczos_record()
+    m = o.msteps
+    assert m % 10 == 0 or m == mmax
+    for j in range(10, m + 1, 10):
+        if j < k + 1:
+            continue
+        sp, sm = _sigma(ta, tb, j - 1, k), _sigma(ta, tb, j, k)
+        hit = abs((sm - sp) / sp) < eps
+        assert hit == (j == m) or (j == m == mmax), (j, m)
+    # eps extremes: a huge tolerance stops at the first check past k; zero runs to the cap
+    o.lowrank(variant, k, mmax, w.lanczos_start(cfg["A"].n, 0), check=10, eps=10.0)
+    assert o.msteps == 20
+    o.lowrank(variant, k, mmax, w.lanczos_start(cfg["A"].n, 0), check=10, eps=0.0)
+    assert o.msteps == mmax
+
+
+@pytest.mark.parametrize("variant", [1, 2])
+def test_extend_equals_direct_run(variant):
+    """Improving a given preconditioner: continuing the stored Lanczos run and
+    rebuilding with a larger k gives exactly the preconditioner built from a
+    single run of the combined length (the steps are the same operations)."""
+    cfg = w.config("small3d")
+    v0 = w.lanczos_start(cfg["A"].n, 0)
+    a = Oracle(cfg["A"], cfg["part"], cfg["p"]).lowrank(variant, 6, 16, v0)
+    a.extend(10, 12)
+    b = Oracle(cfg["A"], cfg["part"], cfg["p"]).lowrank(variant, 10, 28, v0)
+    assert a.msteps == b.msteps == 28
+    for x, y in zip(a.lanczos_record(), b.lanczos_record()):
+        assert np.array_equal(x, y)
+    for x, y in zip(a.get_lowrank(), b.get_lowrank()):
+        assert np.array_equal(np.asarray(x), np.asarray(y))
