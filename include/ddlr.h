@@ -77,6 +77,10 @@ typedef struct {
     int32_t precision;     /* ddlr_precision of the preconditioner; Krylov is always FP64 */
     int32_t device;        /* HIP device ordinal; -1 = host-only setup (ordering and factors only) */
     int32_t no_autotune;   /* 0: tune launch shapes on the first solve with a column count (default) */
+    int32_t lanczos_check; /* 0: lanczos_steps fixed steps; > 0: the control of Sec. 5 -- eq. (converge) on the
+                              sum of the k largest Ritz values, tested every lanczos_check steps (paper: 10) */
+    int32_t lanczos_max;   /* with lanczos_check > 0: step limit; 0 -> 5k (Sec. 5) */
+    double lanczos_tol;    /* with lanczos_check > 0: tolerance of eq. (converge); 0 -> 1e-4 (Sec. 5) */
     uint64_t seed;                /* Lanczos start vector when lanczos_start is NULL */
     const double *lanczos_start;  /* host, length n, user order: its interface entries form q_1 */
 } ddlr_options;
@@ -199,6 +203,21 @@ ddlr_status ddlr_profile(ddlr_prec *h, int32_t on);
 /* Accumulated milliseconds and launches of kernel class `which` since
  * profiling was enabled.  Synchronises the device. */
 ddlr_status ddlr_profile_read(ddlr_prec *h, int32_t which, double *total_ms, int64_t *launches);
+
+/* Improving a given preconditioner (Sec. on improving a given
+ * preconditioner): continues the Lanczos run of ddlr_setup (kept on the
+ * device: s x (m+1) doubles) by `more_steps` steps -- or, with check > 0, until
+ * eq. (converge) holds at a multiple of `check` (tolerance tol, 0 -> 1e-4)
+ * within `more_steps` -- and rebuilds U_k and G_k^{-1} / H_k with rank k (any
+ * k with k+1 <= total steps, larger or smaller than before).  The result is
+ * the same as a setup whose Lanczos ran the combined number of steps.  After
+ * a breakdown the run cannot grow and only the rank can change.  Errors:
+ * DDLR_E_INVALID (no Lanczos run: variant 0 or data from ddlr_set_lowrank;
+ * bad arguments), DDLR_E_LANCZOS (fewer than k+1 steps), DDLR_E_NOT_SPD as
+ * for ddlr_setup; on error the previous low-rank part is gone and the handle
+ * acts as the A0-only preconditioner until a successful call.  Synchronises
+ * the device. */
+ddlr_status ddlr_extend_lowrank(ddlr_prec *h, int32_t k, int32_t more_steps, int32_t check, double tol);
 
 /* Launch-shape autotuner.  The block triangular solve of the A0 solve (the
  * local solves of Sec. 4.2, steps 1 and 5) can give a workgroup 1, 2, 4 or 8

@@ -33,7 +33,8 @@ class ddlr_csr(C.Structure):
 class ddlr_options(C.Structure):
     _fields_ = [("alpha", C.c_double), ("lanczos_steps", C.c_int32), ("theta", C.c_int32),
                 ("factor", C.c_int32), ("corder", C.c_int32), ("precision", C.c_int32), ("device", C.c_int32),
-                ("no_autotune", C.c_int32), ("seed", C.c_uint64), ("lanczos_start", C.c_void_p)]
+                ("no_autotune", C.c_int32), ("lanczos_check", C.c_int32), ("lanczos_max", C.c_int32),
+                ("lanczos_tol", C.c_double), ("seed", C.c_uint64), ("lanczos_start", C.c_void_p)]
 
 
 class ddlr_tuning(C.Structure):
@@ -126,6 +127,7 @@ def load_library(path: str = LIB_PATH):
         "ddlr_server_reset_stats": (I32, [P]),
         "ddlr_server_destroy": (None, [P]),
         "ddlr_tune": (I32, [P, I32, I32, P, P]),
+        "ddlr_extend_lowrank": (I32, [P, I32, I32, I32, C.c_double]),
         "ddlr_destroy": (None, [P]),
         "ddlr_status_string": (C.c_char_p, [I32]),
         "ddlr_last_error": (C.c_char_p, []),
@@ -190,7 +192,7 @@ class Prec:
 def ddlr_setup(A, part, p: int, k: int, variant: int = DDLR_1, *, alpha: float = 1.0, lanczos_steps: int = 0,
                theta: int = THETA_LAMBDA_K1, factor: int = FACTOR_IC0, corder: int = CORDER_MULTICOLOR,
                precision: int = FP64, device: int = 0, seed: int = 0, lanczos_start=None,
-               autotune: bool = True) -> Prec:
+               autotune: bool = True, lanczos_check: int = 0, lanczos_max: int = 0, lanczos_tol: float = 0.0) -> Prec:
     """Builds the preconditioner. A: object with n, rowptr (int64), col (int32), val (float64)."""
     lib = load_library()
     rp = np.ascontiguousarray(A.rowptr, dtype=np.int64)
@@ -204,6 +206,7 @@ def ddlr_setup(A, part, p: int, k: int, variant: int = DDLR_1, *, alpha: float =
     opt.factor, opt.corder, opt.precision, opt.device, opt.seed = int(factor), int(corder), int(precision), int(
         device), int(seed)
     opt.no_autotune = 0 if autotune else 1
+    opt.lanczos_check, opt.lanczos_max, opt.lanczos_tol = int(lanczos_check), int(lanczos_max), float(lanczos_tol)
     v0 = None
     if lanczos_start is not None:
         v0 = np.ascontiguousarray(lanczos_start, dtype=np.float64)
@@ -453,6 +456,12 @@ def ddlr_server_stats(server: Server) -> dict:
     return c.as_dict()
 
 
+def ddlr_extend_lowrank(prec: Prec, k: int, more_steps: int, check: int = 0, tol: float = 0.0) -> None:
+    """Continues the setup's Lanczos run and rebuilds the low-rank part with rank k."""
+    _check(load_library().ddlr_extend_lowrank(prec.handle, int(k), int(more_steps), int(check), float(tol)),
+           "ddlr_extend_lowrank")
+
+
 def ddlr_tune(prec: Prec, nrhs: int, retune: bool = False, stream=None) -> dict:
     """Runs (or reports) the launch-shape autotuner for nrhs columns."""
     t = ddlr_tuning()
@@ -490,5 +499,5 @@ EXPORTED = ["ddlr_version", "ddlr_options_default", "ddlr_solve_options_default"
             "ddlr_get_levels", "ddlr_get_lanczos", "ddlr_get_lowrank", "ddlr_set_lowrank", "ddlr_profile",
             "ddlr_profile_read", "ddlr_batch_create", "ddlr_batch_offsets", "ddlr_batch_apply",
             "ddlr_batch_solve", "ddlr_batch_destroy", "ddlr_server_create", "ddlr_server_add", "ddlr_server_submit",
-            "ddlr_server_poll", "ddlr_server_wait", "ddlr_server_stats", "ddlr_server_reset_stats", "ddlr_server_destroy", "ddlr_tune", "ddlr_destroy",
+            "ddlr_server_poll", "ddlr_server_wait", "ddlr_server_stats", "ddlr_server_reset_stats", "ddlr_server_destroy", "ddlr_extend_lowrank", "ddlr_tune", "ddlr_destroy",
             "ddlr_status_string", "ddlr_last_error"]

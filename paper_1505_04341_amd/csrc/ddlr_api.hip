@@ -84,6 +84,18 @@ template <typename T> struct DevFactors {
     T *Ut = nullptr;                  // the same in MFMA tile order (k % 16 == 0), for U^T y
 };
 
+// A Lanczos run kept for continuation: basis Q (s x (cap+1), device
+// interface order), alpha / beta on device and host, step scratch.
+struct LanczosRun {
+    DMem mem;
+    double *Q = nullptr, *alpha = nullptr, *beta = nullptr, *sc = nullptr;
+    double *w = nullptr, *t1 = nullptr, *t2 = nullptr, *part = nullptr, *csum = nullptr;
+    int cap = 0, steps = 0;
+    int lvariant = 0;  // operator of the run: DDLR_1 or DDLR_2
+    bool broke = false;
+    std::vector<double> ha, hb;
+};
+
 struct Workspace {
     int nrhs = 0;
     // Krylov (double, device order)
@@ -119,6 +131,8 @@ struct ddlr_prec {
     double theta = 0.0, c0 = 0.0;
     std::vector<double> lam, dvec_h, H_h, ta, tb, ritz;
     double setup_ms = 0.0, lanczos_ms = 0.0;
+    LanczosRun lrun;     // the setup's Lanczos run (for ddlr_extend_lowrank)
+    int theta_mode = 0;  // ddlr_theta of the low-rank build
     DMem mem;
     // device structures (device order)
     int32_t* perm_dev = nullptr;  // device position -> user row
@@ -1017,11 +1031,46 @@ void make_bf16_basis(ddlr_prec* h) {
 
 // ------------------------------------------------------------ Lanczos build
 
-void lanczos_build(ddlr_prec* h, int k, int m_req, const double* v0_user, uint64_t seed, int theta_mode) {
+// Lanczos run on E^T A0^{-1} E (DDLR-1) or E^T A0^{-2} E (DDLR-2), Sec. 4.3,
+// kept on the device so it can be continued (improving a given
+// preconditioner by more steps and a larger k).
+void lanczos_reserve(ddlr_prec* h, int cap) {
+    LanczosRun& R = h->lrun;
+    if (cap <= R.cap) return;
+    const int64_t n = h->plan.n, s = h->plan.s;
+    DMem nm;
+    double* Q = nm.alloc<double>((size_t)s * (cap + 1));
+    double* al = nm.alloc<double>(cap);
+    double* be = nm.alloc<double>(cap);
+    double* sc = nm.alloc<double>(4);
+    if (R.Q) {
+        HIPCHK(hipMemcpy(Q, R.Q, sizeof(double) * (size_t)s * (R.steps + 1), hipMemcpyDeviceToDevice));
+        if (R.steps > 0) {
+            HIPCHK(hipMemcpy(al, R.alpha, sizeof(double) * R.steps, hipMemcpyDeviceToDevice));
+            HIPCHK(hipMemcpy(be, R.beta, sizeof(double) * R.steps, hipMemcpyDeviceToDevice));
+        }
+        HIPCHK(hipMemcpy(sc, R.sc, sizeof(double) * 4, hipMemcpyDeviceToDevice));
+    } else {
+        HIPCHK(hipMemset(sc, 0, sizeof(double) * 4));
+    }
+    R.w = nm.alloc<double>(s);
+    R.t1 = nm.alloc<double>(n);
+    R.t2 = nm.alloc<double>(n);
+    R.part = nm.alloc<double>((size_t)kRedBlocks * (cap + 1));
+    R.csum = nm.alloc<double>(cap + 1);
+    HIPCHK(hipDeviceSynchronize());
+    R.mem.release();
+    R.mem = std::move(nm);
+    R.Q = Q;
+    R.alpha = al;
+    R.beta = be;
+    R.sc = sc;
+    R.cap = cap;
+}
+
+void lanczos_start(ddlr_prec* h, const double* v0_user, uint64_t seed) {
     HostPlan& P = h->plan;
     const int64_t n = P.n, s = P.s, mI = P.m;
-    hipStream_t st = nullptr;
-    int m = std::min<int64_t>(m_req, s);
     // start vector in device interface order
     std::vector<double> q0(s);
     std::vector<int32_t> pd(n);
@@ -1043,24 +1092,73 @@ void lanczos_build(ddlr_prec* h, int k, int m_req, const double* v0_user, uint64
     nq = std::sqrt(nq);
     if (!(nq > 0.0)) throw SetupError{DDLR_E_INVALID, "Lanczos start vector is zero on the interface"};
     for (double& v : q0) v /= nq;
-    DMem tmp;
-    double* Q = tmp.alloc<double>((size_t)s * (m + 1));
-    double* w = tmp.alloc<double>(s);
-    double* t1 = tmp.alloc<double>(n);
-    double* t2 = tmp.alloc<double>(n);
-    double* alpha = tmp.alloc<double>(m);
-    double* beta = tmp.alloc<double>(m);
-    double* sc = tmp.alloc<double>(4);  // amax, inv, scratch sum
-    double* part = tmp.alloc<double>((size_t)kRedBlocks * (m + 1));
-    double* csum = tmp.alloc<double>(m + 1);
-    HIPCHK(hipMemcpy(Q, q0.data(), s * sizeof(double), hipMemcpyHostToDevice));
-    hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, st, (int64_t)4, 0.0, sc);
-    LAUNCHCHK();
-    double* amax = sc;
-    double* inv = sc + 1;
-    double* sum1 = sc + 2;
+    LanczosRun& R = h->lrun;
+    R.steps = 0;
+    R.broke = false;
+    R.lvariant = h->variant;
+    R.ha.clear();
+    R.hb.clear();
+    lanczos_reserve(h, 1);
+    HIPCHK(hipMemcpy(R.Q, q0.data(), s * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(hipMemset(R.sc, 0, sizeof(double) * 4));
+}
+
+// Sum of the k largest eigenvalues of the leading j x j block of T
+// (the sigma of eq. converge).
+double ritz_top_sum(const std::vector<double>& ta, const std::vector<double>& tb, int j, int k) {
+    std::vector<double> ev, Z;
+    tridiag_eig(j, ta.data(), tb.data(), ev, Z);
+    std::sort(ev.begin(), ev.end(), [](double a, double b) { return a > b; });
+    double sum = 0.0;
+    for (int c = 0; c < k && c < j; ++c) sum += ev[c];
+    return sum;
+}
+
+// Copies alpha / beta of the run to the host and cuts it at the first
+// breakdown (beta_j <= 1e-12 max_{i<=j} |alpha_i|, that step included).
+void lanczos_sync(ddlr_prec* h, int done_steps) {
+    LanczosRun& R = h->lrun;
+    R.ha.resize(done_steps);
+    R.hb.resize(done_steps);
+    HIPCHK(hipMemcpy(R.ha.data(), R.alpha, done_steps * sizeof(double), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(R.hb.data(), R.beta, done_steps * sizeof(double), hipMemcpyDeviceToHost));
+    double am = 0.0;
+    R.steps = done_steps;
+    for (int j = 0; j < done_steps; ++j) {
+        am = std::max(am, std::fabs(R.ha[j]));
+        if (R.hb[j] <= 1e-12 * am) {
+            R.steps = j + 1;
+            R.broke = true;
+            break;
+        }
+    }
+    R.ha.resize(R.steps);
+    R.hb.resize(R.steps);
+}
+
+// Continues the run up to m_max steps.  With check > 0 it stops at the first
+// step m that is a multiple of check (m >= k+1) where the sums of the k
+// largest Ritz values of T_{m-1} and T_m satisfy eq. (converge) with eps.
+void lanczos_advance(ddlr_prec* h, int m_max, int check, double eps, int k) {
+    LanczosRun& R = h->lrun;
+    const int64_t n = h->plan.n, s = h->plan.s;
+    m_max = (int)std::min<int64_t>(m_max, s);
+    if (R.broke || R.steps >= m_max) return;
+    lanczos_reserve(h, m_max);
+    hipStream_t st = nullptr;
+    double* Q = R.Q;
+    double* w = R.w;
+    double* t1 = R.t1;
+    double* t2 = R.t2;
+    double* alpha = R.alpha;
+    double* beta = R.beta;
+    double* part = R.part;
+    double* csum = R.csum;
+    double* amax = R.sc;
+    double* inv = R.sc + 1;
+    double* sum1 = R.sc + 2;
     const int gs = grid_for(s, 256, kRedBlocks);
-    for (int j = 0; j < m; ++j) {
+    for (int j = R.steps; j < m_max; ++j) {
         double* qj = Q + (size_t)j * s;
         // w = Op q_j : E, A0^{-1} (twice for DDLR-2), E^T
         hipLaunchKernelGGL(k_csr_mv<double>, dim3(grid_for(n)), dim3(256), 0, st, n, 1, h->erp, h->eci, h->f64.ev, qj,
@@ -1068,7 +1166,7 @@ void lanczos_build(ddlr_prec* h, int k, int m_req, const double* v0_user, uint64
         LAUNCHCHK();
         a0_solve_dev<double, double, double>(h, h->f64, 1, t1, n, t2, n, st, nullptr);
         const double* src = t2;
-        if (h->variant == DDLR_2) {
+        if (R.lvariant == DDLR_2) {
             a0_solve_dev<double, double, double>(h, h->f64, 1, t2, n, t1, n, st, nullptr);
             src = t1;
         }
@@ -1102,28 +1200,34 @@ void lanczos_build(ddlr_prec* h, int k, int m_req, const double* v0_user, uint64
         LAUNCHCHK();
         hipLaunchKernelGGL(k_scale_to, dim3(gs), dim3(256), 0, st, s, w, inv, Q + (size_t)(j + 1) * s);
         LAUNCHCHK();
-    }
-    std::vector<double> ha(m), hb(m), hs(4);
-    HIPCHK(hipMemcpy(ha.data(), alpha, m * sizeof(double), hipMemcpyDeviceToHost));
-    HIPCHK(hipMemcpy(hb.data(), beta, m * sizeof(double), hipMemcpyDeviceToHost));
-    // truncate at the first breakdown (beta_j <= 1e-12 max |alpha_i|, same step included)
-    double am = 0.0;
-    int meff = m;
-    for (int j = 0; j < m; ++j) {
-        am = std::max(am, std::fabs(ha[j]));
-        if (hb[j] <= 1e-12 * am) {
-            meff = j + 1;
-            break;
+        const int m = j + 1;
+        if (check > 0 && m % check == 0 && m >= k + 1) {
+            lanczos_sync(h, m);
+            if (R.broke) return;
+            const double sp = ritz_top_sum(R.ha, R.hb, m - 1, k), sm = ritz_top_sum(R.ha, R.hb, m, k);
+            if (std::fabs((sm - sp) / sp) < eps) return;
         }
     }
-    h->ta.assign(ha.begin(), ha.begin() + meff);
-    h->tb.assign(hb.begin(), hb.begin() + meff);
+    lanczos_sync(h, m_max);
+}
+
+// U_k and G_k^{-1} (DDLR-1) or H_k (DDLR-2) of rank k from the run's Ritz pairs.
+void lanczos_finish(ddlr_prec* h, int k, int theta_mode) {
+    HostPlan& P = h->plan;
+    const int64_t n = P.n, s = P.s;
+    LanczosRun& R = h->lrun;
+    hipStream_t st = nullptr;
+    const int meff = R.steps;
+    const double* Q = R.Q;
+    h->ta = R.ha;
+    h->tb = R.hb;
     h->msteps = meff;
-    if (meff < k + 1) {
-        tmp.release();
+    h->theta_mode = theta_mode;
+    drop_graphs(h);  // captured kernels hold the low-rank pointers
+    DMem tmp;
+    if (meff < k + 1)
         throw SetupError{DDLR_E_LANCZOS, "Lanczos broke down after " + std::to_string(meff) + " steps (k+1 = " +
                                              std::to_string(k + 1) + " needed)"};
-    }
     // Ritz pairs of T_m, descending (stable by index), largest-|.| entry of each vector positive
     std::vector<double> ev, Z;
     tridiag_eig(meff, h->ta.data(), h->tb.data(), ev, Z);
@@ -1245,6 +1349,13 @@ void lanczos_build(ddlr_prec* h, int k, int m_req, const double* v0_user, uint64
     tmp.release();
 }
 
+void lanczos_build(ddlr_prec* h, int k, int m_max, const double* v0_user, uint64_t seed, int theta_mode, int check,
+                   double eps) {
+    lanczos_start(h, v0_user, seed);
+    lanczos_advance(h, m_max, check, eps, k);
+    lanczos_finish(h, k, theta_mode);
+}
+
 void drop_graphs(ddlr_prec* h) {
     for (auto& g : h->cg_graphs) {
         if (g.second.second) (void)hipGraphExecDestroy(g.second.second);
@@ -1361,11 +1472,19 @@ ddlr_status ddlr_setup(const ddlr_csr* A, const int32_t* part, int32_t p, int32_
                 HIPCHK(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
             }
             if (variant != 0) {
-                int m = opt.lanczos_steps > 0 ? opt.lanczos_steps : 2 * k;
-                if (m < k + 1 || m > 1000)
-                    throw SetupError{DDLR_E_INVALID, "lanczos_steps must be in [k+1, 1000]"};
+                // fixed m steps (default 2k), or the paper's control: at most
+                // lanczos_max steps (default 5k), stopped by eq. (converge)
+                // tested every lanczos_check steps with lanczos_tol (default 1e-4)
+                const bool ctl = opt.lanczos_check > 0;
+                int m = ctl ? (opt.lanczos_max > 0 ? opt.lanczos_max : 5 * k)
+                            : (opt.lanczos_steps > 0 ? opt.lanczos_steps : 2 * k);
+                if (m < k + 1 || m > 2000)
+                    throw SetupError{DDLR_E_INVALID, "Lanczos step limit must be in [k+1, 2000]"};
+                if (ctl && !(opt.lanczos_tol >= 0.0))
+                    throw SetupError{DDLR_E_INVALID, "lanczos_tol must be >= 0"};
+                const double eps = ctl ? (opt.lanczos_tol > 0.0 ? opt.lanczos_tol : 1e-4) : 0.0;
                 auto l0 = std::chrono::steady_clock::now();
-                lanczos_build(h.get(), k, m, opt.lanczos_start, opt.seed, opt.theta);
+                lanczos_build(h.get(), k, m, opt.lanczos_start, opt.seed, opt.theta, ctl ? opt.lanczos_check : 0, eps);
                 h->lanczos_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - l0).count();
             }
             HIPCHK(hipDeviceSynchronize());
@@ -1941,6 +2060,8 @@ ddlr_status ddlr_set_lowrank(ddlr_prec* h, int32_t variant, int32_t k, const dou
             for (int j = 0; j < k; ++j) Ur[(size_t)i * k + j] = U[user + (size_t)j * P.n];
         }
         drop_graphs(h);  // captured kernels hold the low-rank pointers
+        h->lrun.mem.release();  // imported data: no Lanczos run to continue
+        h->lrun = LanczosRun();
         h->lrmem.release();
         h->dvec = nullptr;
         h->Hk = nullptr;
@@ -2029,6 +2150,40 @@ ddlr_status ddlr_profile_read(ddlr_prec* h, int32_t which, double* total_ms, int
     return DDLR_OK;
 }
 
+ddlr_status ddlr_extend_lowrank(ddlr_prec* h, int32_t k, int32_t more_steps, int32_t check, double tol) {
+    if (!dev_ok(h)) return h ? DDLR_E_DEVICE : DDLR_E_INVALID;
+    if (h->lrun.steps == 0 || h->lrun.lvariant == 0 || h->nsys > 1) {
+        g_err = "no Lanczos run to continue (variant 0, imported low-rank data, or a batch)";
+        return DDLR_E_INVALID;
+    }
+    if (k < 1 || k > 128 || more_steps < 0 || check < 0 || !(tol >= 0.0) ||
+        (int64_t)h->lrun.steps + more_steps > 2000) {
+        g_err = "bad extend arguments (1 <= k <= 128, more_steps >= 0, total steps <= 2000, check >= 0, tol >= 0)";
+        return DDLR_E_INVALID;
+    }
+    try {
+        HIPCHK(hipSetDevice(h->device));
+        HIPCHK(hipDeviceSynchronize());
+        h->variant = h->lrun.lvariant;
+        const int m = (int)std::min<int64_t>((int64_t)h->lrun.steps + more_steps, h->plan.s);
+        lanczos_advance(h, m, check, check > 0 ? (tol > 0.0 ? tol : 1e-4) : 0.0, k);
+        lanczos_finish(h, k, h->theta_mode);
+        HIPCHK(hipDeviceSynchronize());
+    } catch (const SetupError& e) {
+        // the previous low-rank part may be gone: fall back to the A0 part alone
+        h->variant = 0;
+        h->k = 0;
+        h->f64.U = nullptr;
+        h->f32.U = nullptr;
+        h->f64.Ut = nullptr;
+        h->f32.Ut = nullptr;
+        h->ubr = h->ubt = nullptr;
+        h->spd = (int)h->pivots_positive;
+        return fail_status(e);
+    }
+    return DDLR_OK;
+}
+
 ddlr_status ddlr_tune(ddlr_prec* h, int32_t nrhs, int32_t retune, ddlr_tuning* out, void* stream) {
     if (!dev_ok(h)) return h ? DDLR_E_DEVICE : DDLR_E_INVALID;
     if (nrhs < 1 || nrhs > kMaxRhs || !out) {
@@ -2071,6 +2226,7 @@ void ddlr_destroy(ddlr_prec* h) {
     h->ws.gmem.release();
     if (h->ws.done_host) (void)hipHostFree(h->ws.done_host);
     h->lrmem.release();
+    h->lrun.mem.release();
     h->mem.release();
     delete h;
 }
@@ -2560,7 +2716,9 @@ void server_loop(ddlr_server* S) {
     }
 }
 
-size_t prec_bytes(const ddlr_prec* h) { return h->mem.bytes + h->lrmem.bytes + h->ws.mem.bytes + h->ws.gmem.bytes; }
+size_t prec_bytes(const ddlr_prec* h) {
+    return h->mem.bytes + h->lrmem.bytes + h->ws.mem.bytes + h->ws.gmem.bytes + h->lrun.mem.bytes;
+}
 
 }  // namespace
 

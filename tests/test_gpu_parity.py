@@ -524,3 +524,56 @@ def test_apply_wide_lowrank_kernels(variant, prec, k):
         y = torch.empty((nrhs, n), dtype=torch.float64, device=DEV)
         D.ddlr_apply(h, to_dev(x), y)
         assert rel(to_host(y), o.apply(x)) <= tol, nrhs
+
+
+@pytest.mark.parametrize("variant", [1, 2])
+def test_lanczos_control_matches_oracle(variant):
+    """The paper's Lanczos control (eq. converge every 10 steps, eps 1e-4,
+    at most 5k steps): same stopping step and Ritz values as the oracle."""
+    cfg = w.config("small3d")
+    k = cfg["k"]
+    say("lanczos control", variant)
+    h, o = setup_pair(cfg, variant=variant, lanczos_check=10, lanczos_tol=1e-4)
+    o.lowrank(variant, k, 5 * k, w.lanczos_start(cfg["A"].n, 0), check=10, eps=1e-4)
+    q = D.ddlr_query(h)
+    assert q["lanczos_steps"] == o.msteps
+    ga, gb, gr = D.ddlr_get_lanczos(h)
+    oa, ob, orz = o.lanczos_record()
+    assert np.abs(gr[: k + 1] - orz[: k + 1]).max() <= 1e-8 * max(1.0, abs(orz[0]))
+    n = cfg["A"].n
+    x = np.random.default_rng(4).standard_normal((n, 3))
+    y = torch.empty((3, n), dtype=torch.float64, device=DEV)
+    D.ddlr_set_lowrank(h, variant, *o.get_lowrank())
+    D.ddlr_apply(h, to_dev(x), y)
+    assert rel(to_host(y), o.apply(x)) <= 1e-10
+
+
+@pytest.mark.parametrize("variant", [1, 2])
+def test_extend_lowrank(variant):
+    """Improving a given preconditioner: setup with (k=6, m=16), then
+    continuing by 12 steps to k=10 gives bitwise the preconditioner of a
+    single (k=10, m=28) setup, and matches the oracle's extended build."""
+    cfg = w.config("small3d")
+    v0 = w.lanczos_start(cfg["A"].n, 0)
+    say("extend", variant)
+    h1 = D.ddlr_setup(cfg["A"], cfg["part"], cfg["p"], 6, variant, lanczos_steps=16, lanczos_start=v0)
+    D.ddlr_extend_lowrank(h1, 10, 12)
+    h2 = D.ddlr_setup(cfg["A"], cfg["part"], cfg["p"], 10, variant, lanczos_steps=28, lanczos_start=v0)
+    assert D.ddlr_query(h1)["lanczos_steps"] == D.ddlr_query(h2)["lanczos_steps"] == 28
+    for a, b in zip(D.ddlr_get_lanczos(h1), D.ddlr_get_lanczos(h2)):
+        assert np.array_equal(a, b)
+    n = cfg["A"].n
+    x = np.random.default_rng(6).standard_normal((n, 4))
+    y1 = torch.empty((4, n), dtype=torch.float64, device=DEV)
+    y2 = torch.empty_like(y1)
+    D.ddlr_apply(h1, to_dev(x), y1)
+    D.ddlr_apply(h2, to_dev(x), y2)
+    assert torch.equal(y1, y2)
+    o = Oracle(cfg["A"], cfg["part"], cfg["p"]).lowrank(variant, 6, 16, v0)
+    o.extend(10, 12)
+    # same operator as the oracle up to the eigensolver's rounding of T_m
+    assert rel(to_host(y1), o.apply(x)) <= 1e-8
+    # errors: no run to continue after imported low-rank data
+    D.ddlr_set_lowrank(h2, variant, *o.get_lowrank())
+    with pytest.raises(D.DDLRError):
+        D.ddlr_extend_lowrank(h2, 12, 4)
