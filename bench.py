@@ -14,6 +14,8 @@ Other workloads (--config):
       from 128 Lanczos steps, GMRES(40); FP64 against FP32 with BF16 U_k.
   c4  256 independent 2-D diffusion systems (sides 32..256, 4..16 boxes,
       k = 16) solved together by the batch engine (FP32 preconditioner).
+  u1  unstructured: random geometric graph Laplacian (500,000 unknowns),
+      64 parts from the library's graph partitioner, k = 32, 8 rhs, CG.
   c5  serving: 8 resident 27-point random-coefficient matrices (n 50,653 ..
       10^6), requests of 1..16 right-hand sides arriving as a Poisson process;
       saturation throughput, then p50/p99 request latency at 0.5x and 0.9x of it.
@@ -144,8 +146,20 @@ def timed_solves(D, torch, h, bt, xt, steps, warmup, method, label, prof_steps=2
 
 
 # ---------------------------------------------------------------- c1, c2, c3
+def unstructured_config(D, w):
+    """u1: random geometric graph Laplacian (500,000 unknowns, about 12
+    neighbours per row, Morton-numbered), partitioned by the library's
+    recursive bisection into 64 parts; DDLR-1 k = 32 from 64 Lanczos steps,
+    8 right-hand sides, CG."""
+    A, _ = w.rgg_laplacian(500_000, 12, 7)
+    t0 = time.perf_counter()
+    part = D.ddlr_partition_graph(A, 64)
+    log("u1: partition", f"{time.perf_counter() - t0:.2f}s", "nnz/row", round(len(A.col) / A.n, 2))
+    return dict(A=A, part=part, p=64, k=32, m=64, nrhs=8, variant=1, method="cg")
+
+
 def run_single(args, D, w, torch):
-    cfg = w.config(args.config)
+    cfg = unstructured_config(D, w) if args.config == "u1" else w.config(args.config)
     A = cfg["A"]
     n, nrhs, k, m, p = A.n, cfg["nrhs"], cfg["k"], cfg["m"], cfg["p"]
     gm = cfg["method"] == "gmres"
@@ -183,6 +197,7 @@ def run_single(args, D, w, torch):
         "c1": "5-point Laplacian 64^2, 2x2 boxes",
         "c2": "7-point Laplacian 128^3, 4x4x4 boxes",
         "c3": "7-point Laplacian 100^3 shifted (20 negative eigenvalues), 4x4x8 boxes, ILDL(0)",
+        "u1": "random geometric graph Laplacian n=500,000 (~12 per row), 64 parts by recursive bisection",
     }[args.config]
     krylov = "GMRES(40)" if gm else "CG"
     out = {
@@ -393,7 +408,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "u1"])
     ap.add_argument("--variant", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-rhs", type=int, default=3, help="right-hand sides the oracle solves for the baseline")

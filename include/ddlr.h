@@ -176,6 +176,20 @@ ddlr_status ddlr_get_ordering(const ddlr_prec *h, int32_t *perm, int32_t *iface,
  * col/val nnz_l) and D (n).  Host arrays. */
 ddlr_status ddlr_get_factor(const ddlr_prec *h, int64_t *row_ptr, int32_t *col, double *val, double *D);
 
+/* A partition of the unknowns for matrices without a geometric split.  The
+ * method takes the partition into p subdomains as an input produced by a
+ * graph partitioner (Sec. 2.1); this helper is a deterministic recursive
+ * bisection of the adjacency graph of A (pattern only): a vertex set with q
+ * parts to form is cut after the first round(|set| floor(q/2) / q) vertices of
+ * a breadth-first order of its induced subgraph, started from a
+ * pseudo-peripheral vertex (George-Liu search from the lowest-numbered
+ * vertex, neighbours in ascending order, unreached components appended from
+ * their lowest vertex); the first piece gets the lower part ids.  part: host
+ * array of n entries (0..p-1), written on success.  Errors: DDLR_E_INVALID for
+ * bad arguments or if a part would be empty (fewer vertices than parts in a
+ * piece). */
+ddlr_status ddlr_partition_graph(const ddlr_csr *A, int32_t p, int32_t *part);
+
 /* Level of each internal row in its block's forward triangular schedule. */
 ddlr_status ddlr_get_levels(const ddlr_prec *h, int32_t *level);
 
@@ -222,22 +236,30 @@ ddlr_status ddlr_extend_lowrank(ddlr_prec *h, int32_t k, int32_t more_steps, int
 /* Launch-shape autotuner.  The block triangular solve of the A0 solve (the
  * local solves of Sec. 4.2, steps 1 and 5) can give a workgroup 1, 2, 4 or 8
  * right-hand sides of one block, sharing the block's factor entries between
- * them, and the interface block's level kernels can run beside it on a side
- * stream or in line.  The first solve, apply or A0 solve with a given column
+ * them; with one right-hand side per workgroup, blocks whose levels are
+ * narrow can use workgroups of 64 (one wave, no barriers) or 256 threads
+ * instead of 512; the plain per-level kernel (CSR rows, no ring) is also a
+ * candidate; and the interface block's level kernels can run beside it on a
+ * side stream or in line.  The first solve, apply or A0 solve with a given column
  * count times the eligible shapes on the device (HIP events, a few
  * milliseconds) and keeps the fastest; every shape does the same arithmetic
  * in the same order, so results do not depend on the choice.  ddlr_tune runs
  * (retune != 0: re-runs) the tuner for nrhs in 1..16 on `stream` and reports
  * the choice and the measured times; it synchronises the stream.  Batches
- * (ddlr_batch_*) use fixed shapes.  Setting options.no_autotune keeps the
- * defaults (one column per workgroup, overlap on) unless ddlr_tune is called. */
+ * (ddlr_batch_*) use fixed shapes (the smallest eligible workgroup, one
+ * column).  Setting options.no_autotune keeps the defaults (one column per
+ * workgroup of the smallest eligible size, overlap on) unless ddlr_tune is
+ * called. */
 typedef struct {
     int32_t nrhs;            /* column count the shape is for */
     int32_t ring_cols;       /* right-hand sides per workgroup of the block triangular solve */
     int32_t overlap;         /* 1: interface levels on the side stream, 0: in line */
-    int32_t reserved;
-    float a0_us[4];          /* A0 solve time with 1, 2, 4, 8 columns per workgroup (0: not eligible) */
+    int32_t ring_threads;    /* threads per workgroup of the block triangular solve (64, 256, 512), or -1:
+                                the plain per-level kernel (CSR rows, no LDS ring) */
+    float a0_us[4];          /* A0 solve time, 512 threads, 1, 2, 4, 8 columns per workgroup (0: not eligible) */
     float a0_no_overlap_us;  /* best shape with the interface levels in line (0: not measured) */
+    float a0_thin_us[2];     /* one column per workgroup of 64 / 256 threads (0: not eligible) */
+    float a0_plain_us;       /* the plain per-level kernel (0: not measured) */
 } ddlr_tuning;
 ddlr_status ddlr_tune(ddlr_prec *h, int32_t nrhs, int32_t retune, ddlr_tuning *out, void *stream);
 

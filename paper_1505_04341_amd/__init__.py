@@ -38,12 +38,14 @@ class ddlr_options(C.Structure):
 
 
 class ddlr_tuning(C.Structure):
-    _fields_ = [("nrhs", C.c_int32), ("ring_cols", C.c_int32), ("overlap", C.c_int32), ("reserved", C.c_int32),
-                ("a0_us", C.c_float * 4), ("a0_no_overlap_us", C.c_float)]
+    _fields_ = [("nrhs", C.c_int32), ("ring_cols", C.c_int32), ("overlap", C.c_int32), ("ring_threads", C.c_int32),
+                ("a0_us", C.c_float * 4), ("a0_no_overlap_us", C.c_float), ("a0_thin_us", C.c_float * 2),
+                ("a0_plain_us", C.c_float)]
 
     def as_dict(self):
-        return dict(nrhs=self.nrhs, ring_cols=self.ring_cols, overlap=self.overlap, a0_us=list(self.a0_us),
-                    a0_no_overlap_us=self.a0_no_overlap_us)
+        return dict(nrhs=self.nrhs, ring_cols=self.ring_cols, overlap=self.overlap, ring_threads=self.ring_threads,
+                    a0_us=list(self.a0_us), a0_no_overlap_us=self.a0_no_overlap_us, a0_thin_us=list(self.a0_thin_us),
+                    a0_plain_us=self.a0_plain_us)
 
 
 class ddlr_solve_options(C.Structure):
@@ -128,6 +130,7 @@ def load_library(path: str = LIB_PATH):
         "ddlr_server_destroy": (None, [P]),
         "ddlr_tune": (I32, [P, I32, I32, P, P]),
         "ddlr_extend_lowrank": (I32, [P, I32, I32, I32, C.c_double]),
+        "ddlr_partition_graph": (I32, [P, I32, P]),
         "ddlr_destroy": (None, [P]),
         "ddlr_status_string": (C.c_char_p, [I32]),
         "ddlr_last_error": (C.c_char_p, []),
@@ -456,6 +459,18 @@ def ddlr_server_stats(server: Server) -> dict:
     return c.as_dict()
 
 
+def ddlr_partition_graph(A, p: int) -> np.ndarray:
+    """Recursive-bisection partition of the adjacency graph of A into p parts (host)."""
+    lib = load_library()
+    rp = np.ascontiguousarray(A.rowptr, dtype=np.int64)
+    ci = np.ascontiguousarray(A.col, dtype=np.int32)
+    va = np.ascontiguousarray(A.val, dtype=np.float64)
+    csr = ddlr_csr(int(A.n), rp.ctypes.data, ci.ctypes.data, va.ctypes.data)
+    part = np.zeros(int(A.n), np.int32)
+    _check(lib.ddlr_partition_graph(C.byref(csr), int(p), _ptr(part)), "ddlr_partition_graph")
+    return part
+
+
 def ddlr_extend_lowrank(prec: Prec, k: int, more_steps: int, check: int = 0, tol: float = 0.0) -> None:
     """Continues the setup's Lanczos run and rebuilds the low-rank part with rank k."""
     _check(load_library().ddlr_extend_lowrank(prec.handle, int(k), int(more_steps), int(check), float(tol)),
@@ -499,5 +514,5 @@ EXPORTED = ["ddlr_version", "ddlr_options_default", "ddlr_solve_options_default"
             "ddlr_get_levels", "ddlr_get_lanczos", "ddlr_get_lowrank", "ddlr_set_lowrank", "ddlr_profile",
             "ddlr_profile_read", "ddlr_batch_create", "ddlr_batch_offsets", "ddlr_batch_apply",
             "ddlr_batch_solve", "ddlr_batch_destroy", "ddlr_server_create", "ddlr_server_add", "ddlr_server_submit",
-            "ddlr_server_poll", "ddlr_server_wait", "ddlr_server_stats", "ddlr_server_reset_stats", "ddlr_server_destroy", "ddlr_extend_lowrank", "ddlr_tune", "ddlr_destroy",
+            "ddlr_server_poll", "ddlr_server_wait", "ddlr_server_stats", "ddlr_server_reset_stats", "ddlr_server_destroy", "ddlr_extend_lowrank", "ddlr_partition_graph", "ddlr_tune", "ddlr_destroy",
             "ddlr_status_string", "ddlr_last_error"]

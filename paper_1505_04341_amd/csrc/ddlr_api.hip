@@ -151,12 +151,15 @@ struct ddlr_prec {
     int ring_kw = 0;                          // 2, 3, 4, 8, 16 or 0 (ring kernel unusable)
     bool ring_ok64 = false, ring_ok32 = false;  // dependency window fits the LDS ring
     int ring_need = 0;                          // rows the ring must hold (dependency window)
+    int ring_maxw = 0;                          // widest level of the narrow blocks
     // autotuned launch shape per number of columns: columns per workgroup of
     // the ring kernel (1, 2, 4, 8) and the interface-level overlap; both leave
     // the arithmetic unchanged
     struct Tune {
-        int ring_r = 1, overlap = 1;
+        int ring_r = 1, ring_nt = 0, overlap = 1;  // ring_nt 0: smallest eligible, -1: plain kernel
         float a0_us[4] = {0, 0, 0, 0};
+        float a0_thin_us[2] = {0, 0};  // one column per workgroup of 64 / 256 threads
+        float a0_plain_us = 0;         // the plain per-level kernel
         float a0_noov_us = 0;
     };
     std::map<int, Tune> tune;
@@ -203,6 +206,7 @@ namespace {
 // ------------------------------------------------------------ device upload
 
 constexpr int kRing64 = 8192, kRing32 = 16384;  // LDS ring rows: 64 KB either way
+constexpr int kRingThin = 2048;                  // ring rows of the 64- and 256-thread workgroups
 
 // Device-order arrays of one preconditioner (or of several merged), built on
 // the host before upload.
@@ -392,13 +396,14 @@ void build_ring(ddlr_prec* h, const DevHost& D) {
     const std::vector<BlockDesc>& bd = D.narrow;
     const std::vector<int32_t>&lrp = D.lrp, &lci = D.lci, &urp = D.urp, &uci = D.uci;
     const int nlev = (int)D.lvl_ptr.size() - 1;
-    int kw = 0, need = 0;
+    int kw = 0, need = 0, maxw = 0;
     bool ok64 = true, ok32 = true;
     for (const BlockDesc& b : bd) {
         if (b.lvl1 - b.lvl0 > kRingMaxLevels) ok64 = ok32 = false;
         for (int l = b.lvl0; l < b.lvl1; ++l) {
             const int row0 = D.lvl_row0[l];
             const int a = D.lvl_ptr[l] - row0, e = D.lvl_ptr[l + 1] - row0;
+            maxw = std::max(maxw, e - a);
             for (int i = a; i < e; ++i) {
                 kw = std::max({kw, lrp[row0 + i + 1] - lrp[row0 + i], urp[row0 + i + 1] - urp[row0 + i]});
                 for (int t = lrp[row0 + i]; t < lrp[row0 + i + 1]; ++t) {
@@ -416,12 +421,13 @@ void build_ring(ddlr_prec* h, const DevHost& D) {
             }
         }
     }
-    h->ring_kw = kw <= 2 ? 2 : kw <= 3 ? 3 : kw <= 4 ? 4 : kw <= 8 ? 8 : kw <= 16 ? 16 : 0;
+    h->ring_kw = kw <= 2 ? 2 : kw <= 3 ? 3 : kw <= 4 ? 4 : kw <= 8 ? 8 : kw <= 16 ? 16 : kw <= 32 ? 32 : 0;
     if (const char* env = std::getenv("DDLR_TRSV_PLAIN"))  // "1": always the plain per-level kernel
         if (env[0] == '1') h->ring_kw = 0;
     h->ring_ok64 = ok64 && h->ring_kw > 0;
     h->ring_ok32 = ok32 && h->ring_kw > 0;
     h->ring_need = need;
+    h->ring_maxw = maxw;
     if (!h->ring_ok64 && !h->ring_ok32) return;
     const int KW = h->ring_kw;
     std::vector<int32_t> foff(nlev), boff(nlev), fcol, bcol;
@@ -653,13 +659,41 @@ template <typename T> constexpr int ring_rows();
 template <> constexpr int ring_rows<double>() { return kRing64; }
 template <> constexpr int ring_rows<float>() { return kRing32; }
 
+// Workgroup sizes of the one-column ring kernel: 512 always (rows beyond its
+// row sets are done without prefetch); 64 and 256 when every level fits their
+// row sets and the dependency window fits the smaller ring.
+template <int KW> constexpr int ring_sets_host() { return KW <= 16 ? 2 : 1; }
+bool ring_nt_ok(const ddlr_prec* h, int nt) {
+    if (nt == 512) return true;
+    const int ns = h->ring_kw <= 16 ? 2 : 1;
+    return h->ring_maxw <= nt * ns && h->ring_need <= kRingThin;
+}
+int ring_nt_default(const ddlr_prec* h) {
+    for (int nt : {64, 256})
+        if (ring_nt_ok(h, nt)) return nt;
+    return 512;
+}
+
+template <typename T, int KW, typename TIn, typename TOut, int NT>
+void launch_ring_nt(ddlr_prec* h, const T* dinv, int nrhs, const TIn* x, int64_t ldx, TOut* z, int64_t ldz,
+                    hipStream_t st, const int* done) {
+    constexpr int kRing = NT == 512 ? ring_rows<T>() : kRingThin;
+    hipLaunchKernelGGL((k_trsv_ring<T, KW, kRing, TIn, TOut, NT>), dim3(h->nnarrow_pad * nrhs), dim3(NT), 0, st,
+                       h->rblk, h->nnarrow, h->nnarrow_pad, nrhs, h->lvl_ptr, h->foff, h->fcol, ring_fval<T>(h),
+                       h->boff_, h->bcol, ring_bval<T>(h), dinv, x, ldx, z, ldz, done);
+    LAUNCHCHK();
+}
+
+template <typename T> int ring_nt_for(const ddlr_prec* h, int nrhs);
+
 template <typename T, int KW, typename TIn, typename TOut>
 void launch_ring_kw(ddlr_prec* h, const T* dinv, int nrhs, const TIn* x, int64_t ldx, TOut* z, int64_t ldz,
                     hipStream_t st, const int* done) {
-    hipLaunchKernelGGL((k_trsv_ring<T, KW, ring_rows<T>(), TIn, TOut>), dim3(h->nnarrow_pad * nrhs),
-                       dim3(kRingThreads), 0, st, h->rblk, h->nnarrow, h->nnarrow_pad, nrhs, h->lvl_ptr, h->foff,
-                       h->fcol, ring_fval<T>(h), h->boff_, h->bcol, ring_bval<T>(h), dinv, x, ldx, z, ldz, done);
-    LAUNCHCHK();
+    switch (ring_nt_for<T>(h, nrhs)) {
+    case 64: launch_ring_nt<T, KW, TIn, TOut, 64>(h, dinv, nrhs, x, ldx, z, ldz, st, done); break;
+    case 256: launch_ring_nt<T, KW, TIn, TOut, 256>(h, dinv, nrhs, x, ldx, z, ldz, st, done); break;
+    default: launch_ring_nt<T, KW, TIn, TOut, 512>(h, dinv, nrhs, x, ldx, z, ldz, st, done);
+    }
 }
 
 template <typename T, typename TIn, typename TOut>
@@ -670,7 +704,8 @@ void launch_ring(ddlr_prec* h, const T* dinv, int nrhs, const TIn* x, int64_t ld
     case 3: launch_ring_kw<T, 3, TIn, TOut>(h, dinv, nrhs, x, ldx, z, ldz, st, done); break;
     case 4: launch_ring_kw<T, 4, TIn, TOut>(h, dinv, nrhs, x, ldx, z, ldz, st, done); break;
     case 8: launch_ring_kw<T, 8, TIn, TOut>(h, dinv, nrhs, x, ldx, z, ldz, st, done); break;
-    default: launch_ring_kw<T, 16, TIn, TOut>(h, dinv, nrhs, x, ldx, z, ldz, st, done);
+    case 16: launch_ring_kw<T, 16, TIn, TOut>(h, dinv, nrhs, x, ldx, z, ldz, st, done); break;
+    default: launch_ring_kw<T, 32, TIn, TOut>(h, dinv, nrhs, x, ldx, z, ldz, st, done);
     }
 }
 
@@ -717,6 +752,17 @@ template <typename T> int ring_r_for(const ddlr_prec* h, int nrhs) {
     return std::max(R, 1);
 }
 
+// workgroup size of the one-column ring kernel (tuned, else the smallest eligible)
+template <typename T> int ring_nt_for(const ddlr_prec* h, int nrhs) {
+    int nt = 0;
+    auto it = h->tune.find(nrhs);
+    if (it != h->tune.end()) nt = it->second.ring_nt;
+    if (const char* env = std::getenv("DDLR_RING_NT")) nt = std::atoi(env);
+    if (nt == -1) return -1;  // the plain per-level kernel
+    if (nt != 64 && nt != 256 && nt != 512) nt = ring_nt_default(h);
+    return ring_nt_ok(h, nt) ? nt : 512;
+}
+
 // Interface-block levels (multicolour order): forward levels, the last one
 // fused with the diagonal scaling, then backward levels.
 template <typename T, typename TIn, typename TOut>
@@ -759,7 +805,7 @@ void a0_solve_dev(ddlr_prec* h, const DevFactors<T>& F, int nrhs, const TIn* x, 
     if (!h->wide.empty()) wide_levels<T, TIn, TOut>(h, F, nrhs, x, ldx, z, ldz, cst, done);
     if (h->nnarrow > 0) {
         ProfScope ps(h, 0, st);
-        if (ring_ready<T>(h)) {
+        if (ring_ready<T>(h) && ring_nt_for<T>(h, nrhs) > 0) {
             switch (ring_r_for<T>(h, nrhs)) {
             case 2: launch_ring_r<T, 2, TIn, TOut>(h, F.dinv, nrhs, x, ldx, z, ldz, st, done); break;
             case 4: launch_ring_r<T, 4, TIn, TOut>(h, F.dinv, nrhs, x, ldx, z, ldz, st, done); break;
@@ -1559,7 +1605,8 @@ void autotune_T(ddlr_prec* h, const DevFactors<T>& F, int nrhs, hipStream_t st) 
     tn = ddlr_prec::Tune();
     const int Rs[4] = {1, 2, 4, 8};
     float best = 1e30f;
-    int bestR = 1;
+    int bestR = 1, bestNT = 512;
+    tn.ring_nt = 512;
     for (int q = 0; q < 4; ++q) {
         const int R = Rs[q];
         if (nrhs % R != 0 || !ring_r_ok<T>(h, R) || (R > 1 && h->nnarrow == 0)) continue;
@@ -1570,7 +1617,34 @@ void autotune_T(ddlr_prec* h, const DevFactors<T>& F, int nrhs, hipStream_t st) 
             bestR = R;
         }
     }
+    // thin workgroups (one column each) for narrow levels
+    if (ring_ready<T>(h) && h->nnarrow > 0) {
+        const int nts[2] = {64, 256};
+        for (int q = 0; q < 2; ++q) {
+            if (!ring_nt_ok(h, nts[q])) continue;
+            tn.ring_r = 1;
+            tn.ring_nt = nts[q];
+            tn.a0_thin_us[q] = time_a0();
+            if (tn.a0_thin_us[q] < best) {
+                best = tn.a0_thin_us[q];
+                bestR = 1;
+                bestNT = nts[q];
+            }
+        }
+    }
+    // the plain per-level kernel (padding to a wide ELL can cost more than it saves)
+    if (ring_ready<T>(h) && h->nnarrow > 0) {
+        tn.ring_r = 1;
+        tn.ring_nt = -1;
+        tn.a0_plain_us = time_a0();
+        if (tn.a0_plain_us < best) {
+            best = tn.a0_plain_us;
+            bestR = 1;
+            bestNT = -1;
+        }
+    }
     tn.ring_r = bestR;
+    tn.ring_nt = bestR > 1 ? 512 : bestNT;
     tn.overlap = 1;
     if (h->overlap && h->side && !h->wide.empty() && h->nnarrow > 0) {
         tn.overlap = 0;
@@ -1989,6 +2063,22 @@ ddlr_status ddlr_get_factor(const ddlr_prec* h, int64_t* row_ptr, int32_t* col, 
     return DDLR_OK;
 }
 
+ddlr_status ddlr_partition_graph(const ddlr_csr* A, int32_t p, int32_t* part) {
+    if (!A || !part || !A->row_ptr || !A->col_idx || A->n < 1 || p < 1) {
+        g_err = "null argument, n < 1 or p < 1";
+        return DDLR_E_INVALID;
+    }
+    try {
+        partition_graph(A->n, A->row_ptr, A->col_idx, p, part);
+    } catch (const SetupError& e) {
+        return fail_status(e);
+    } catch (const std::bad_alloc&) {
+        g_err = "host allocation failed";
+        return DDLR_E_OOM;
+    }
+    return DDLR_OK;
+}
+
 ddlr_status ddlr_get_levels(const ddlr_prec* h, int32_t* level) {
     if (!h || !level) {
         g_err = "null argument";
@@ -2203,12 +2293,18 @@ ddlr_status ddlr_tune(ddlr_prec* h, int32_t nrhs, int32_t retune, ddlr_tuning* o
     auto it = h->tune.find(nrhs);
     if (it == h->tune.end()) {  // batches: fixed shape
         out->ring_cols = 1;
+        out->ring_threads = ring_nt_default(h);
         out->overlap = h->overlap ? 1 : 0;
         return DDLR_OK;
     }
     out->ring_cols = it->second.ring_r;
+    out->ring_threads = it->second.ring_r > 1 ? 512 : (h->precision == DDLR_FP64 ? ring_nt_for<double>(h, nrhs)
+                                                                                   : ring_nt_for<float>(h, nrhs));
+    if (!(h->precision == DDLR_FP64 ? ring_ready<double>(h) : ring_ready<float>(h))) out->ring_threads = -1;
+    out->a0_plain_us = it->second.a0_plain_us;
     out->overlap = it->second.overlap;
     for (int q = 0; q < 4; ++q) out->a0_us[q] = it->second.a0_us[q];
+    for (int q = 0; q < 2; ++q) out->a0_thin_us[q] = it->second.a0_thin_us[q];
     out->a0_no_overlap_us = it->second.a0_noov_us;
     return DDLR_OK;
 }

@@ -64,4 +64,8 @@ void build_plan(HostPlan& P, int64_t n, const int64_t* rp, const int32_t* ci, co
 // Returns eigenvalues (unsorted) in ev and eigenvectors column-major in Z.
 void tridiag_eig(int m, const double* a, const double* b, std::vector<double>& ev, std::vector<double>& Z);
 
+// Recursive bisection of the adjacency graph of a symmetric pattern into p
+// parts (partition.cpp).
+void partition_graph(int64_t n, const int64_t* rp, const int32_t* ci, int32_t p, int32_t* part);
+
 }  // namespace ddlr

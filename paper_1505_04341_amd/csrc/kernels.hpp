@@ -39,6 +39,12 @@ __device__ __forceinline__ double block_sum256(double v, double* sh) {
 
 template <typename T> __device__ __forceinline__ T ld(const T* p) { return *p; }
 
+// s - a b with one rounding.  Every triangular-solve kernel forms its row sums
+// with this, so kernels of different shape give bitwise the same results
+// whatever the compiler would contract on its own.
+__device__ __forceinline__ float fnms(float s, float a, float b) { return __builtin_fmaf(-a, b, s); }
+__device__ __forceinline__ double fnms(double s, double a, double b) { return __builtin_fma(-a, b, s); }
+
 // --------------------------------------------------------- permutation / casts
 
 // y[d + r*ldy] = x[perm[d] + r*ldx]   (user order -> device order)
@@ -98,7 +104,7 @@ __global__ __launch_bounds__(256) void k_trsv_narrow(
         for (int i = a + threadIdx.x; i < e; i += blockDim.x) {
             T s = (T)xr[i];
             const int t1 = lrp[i + 1];
-            for (int t = lrp[i]; t < t1; ++t) s -= lv[t] * (T)zr[lci[t]];
+            for (int t = lrp[i]; t < t1; ++t) s = fnms(s, lv[t], (T)zr[lci[t]]);
             zr[i] = (TOut)s;
         }
         __syncthreads();
@@ -108,7 +114,7 @@ __global__ __launch_bounds__(256) void k_trsv_narrow(
         for (int i = a + threadIdx.x; i < e; i += blockDim.x) {
             T s = (T)zr[i] * dinv[i];
             const int t1 = urp[i + 1];
-            for (int t = urp[i]; t < t1; ++t) s -= uv[t] * (T)zr[uci[t]];
+            for (int t = urp[i]; t < t1; ++t) s = fnms(s, uv[t], (T)zr[uci[t]]);
             zr[i] = (TOut)s;
         }
         __syncthreads();
@@ -147,20 +153,29 @@ __device__ __forceinline__ void lds_barrier() {
 constexpr int kRingThreads = 512;
 constexpr int kRingMaxLevels = 511;
 
-// Registers of one prefetched level.  The right-hand-side value is kept in its
-// storage type TS and converted when used, so no load is waited for early.
-template <typename T, int KW, typename TS> struct LevelRegs {
+// Registers of one prefetched level: NS row sets of NT rows.  The right-hand-
+// side value is kept in its storage type TS and converted when used, so no
+// load is waited for early.
+template <typename T, int KW, typename TS, int NS> struct LevelRegs {
     int a, e, off;
-    int c[2][KW];
-    T v[2][KW];
-    TS xv[2];
-    T dv[2];
+    int c[NS][KW];
+    T v[NS][KW];
+    TS xv[NS];
+    T dv[NS];
 };
+
+// Separation of consecutive levels: an LDS-only barrier for several waves; a
+// single wave needs none (its LDS operations execute in order), only a
+// compiler fence so no access moves across the level boundary.
+template <int NT> __device__ __forceinline__ void level_sync() {
+    if constexpr (NT > 64) lds_barrier();
+    else __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
 
 // Per-level metadata of one block, staged in LDS at kernel start: local first
 // row and the ELL offsets of L and L^T.
-template <typename T, int KW, bool kBwd, typename TS>
-__device__ __forceinline__ void ring_load(LevelRegs<T, KW, TS>& R, int q, int row0, const int4* meta,
+template <typename T, int KW, bool kBwd, typename TS, int NT, int NS>
+__device__ __forceinline__ void ring_load(LevelRegs<T, KW, TS, NS>& R, int q, int row0, const int4* meta,
                                           const int32_t* __restrict__ ecol, const T* __restrict__ eval,
                                           const T* __restrict__ dinv, const TS* src) {
     const int4 mq = meta[q];  // uniform across the workgroup: keep it in scalar registers
@@ -169,9 +184,9 @@ __device__ __forceinline__ void ring_load(LevelRegs<T, KW, TS>& R, int q, int ro
     R.off = __builtin_amdgcn_readfirstlane(kBwd ? mq.z : mq.y);
     const int nr = R.e - R.a;
 #pragma unroll
-    for (int qq = 0; qq < 2; ++qq) {
-        if (qq == 1 && nr <= kRingThreads) break;  // uniform: one row set covers the level
-        const int i = min(R.a + (int)threadIdx.x + qq * kRingThreads, R.e - 1);
+    for (int qq = 0; qq < NS; ++qq) {
+        if (qq >= 1 && nr <= qq * NT) break;  // uniform: fewer row sets cover the level
+        const int i = min(R.a + (int)threadIdx.x + qq * NT, R.e - 1);
         const int base = R.off + (i - R.a);
 #pragma unroll
         for (int j = 0; j < KW; ++j) {
@@ -183,18 +198,18 @@ __device__ __forceinline__ void ring_load(LevelRegs<T, KW, TS>& R, int q, int ro
     }
 }
 
-template <typename T, int KW, int kRing, bool kBwd, typename TS, typename TD>
-__device__ __forceinline__ void ring_compute(const LevelRegs<T, KW, TS>& R, int row0, T* ring,
+template <typename T, int KW, int kRing, bool kBwd, typename TS, typename TD, int NT, int NS>
+__device__ __forceinline__ void ring_compute(const LevelRegs<T, KW, TS, NS>& R, int row0, T* ring,
                                              const int32_t* __restrict__ ecol, const T* __restrict__ eval,
                                              const T* __restrict__ dinv, const TS* src, TD* dst) {
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-        if (q == 1 && R.e - R.a <= kRingThreads) break;
-        const int i0 = R.a + (int)threadIdx.x + q * kRingThreads;
+    for (int q = 0; q < NS; ++q) {
+        if (q >= 1 && R.e - R.a <= q * NT) break;
+        const int i0 = R.a + (int)threadIdx.x + q * NT;
         const int i = min(i0, R.e - 1);
         T s = kBwd ? (T)R.xv[q] * R.dv[q] : (T)R.xv[q];
 #pragma unroll
-        for (int j = 0; j < KW; ++j) s -= R.v[q][j] * ring[R.c[q][j] & (kRing - 1)];
+        for (int j = 0; j < KW; ++j) s = fnms(s, R.v[q][j], ring[R.c[q][j] & (kRing - 1)]);
         // only the owning lane stores: duplicate global stores of a forward value
         // from other waves are not ordered against the owner's backward store
         if (i0 < R.e) {
@@ -202,12 +217,12 @@ __device__ __forceinline__ void ring_compute(const LevelRegs<T, KW, TS>& R, int 
             dst[i] = (TD)s;
         }
     }
-    // rows beyond 2 * kRingThreads: no prefetch
+    // rows beyond NS * NT: no prefetch
     const int nr = R.e - R.a;
-    for (int i = R.a + 2 * kRingThreads + (int)threadIdx.x; i < R.e; i += kRingThreads) {
+    for (int i = R.a + NS * NT + (int)threadIdx.x; i < R.e; i += NT) {
         const int base = R.off + (i - R.a);
         T s = kBwd ? (T)src[i] * dinv[row0 + i] : (T)src[i];
-        for (int j = 0; j < KW; ++j) s -= eval[base + j * nr] * ring[ecol[base + j * nr] & (kRing - 1)];
+        for (int j = 0; j < KW; ++j) s = fnms(s, eval[base + j * nr], ring[ecol[base + j * nr] & (kRing - 1)]);
         ring[i & (kRing - 1)] = s;
         dst[i] = (TD)s;
     }
@@ -222,26 +237,29 @@ template <> struct RingDepth<float, 4> { static constexpr int value = 3; };
 template <> struct RingDepth<double, 2> { static constexpr int value = 3; };
 template <> struct RingDepth<double, 3> { static constexpr int value = 3; };
 
+// Row sets per thread: two up to width 16, one at width 32 (registers).
+template <int KW> constexpr int ring_sets() { return KW <= 16 ? 2 : 1; }
+
 // One sweep over local levels; kBwd walks them from the last to the first.
-template <typename T, int KW, int kRing, bool kBwd, typename TS, typename TD>
+template <typename T, int KW, int kRing, bool kBwd, typename TS, typename TD, int NT, int NS>
 __device__ __forceinline__ void ring_sweep(int nlev, int row0, const int4* meta, T* ring,
                                            const int32_t* __restrict__ ecol, const T* __restrict__ eval,
                                            const T* __restrict__ dinv, const TS* src, TD* dst) {
     constexpr int kD = RingDepth<T, KW>::value;
-    LevelRegs<T, KW, TS> buf[kD];
+    LevelRegs<T, KW, TS, NS> buf[kD];
     auto lev = [&](int q) { return kBwd ? nlev - 1 - q : q; };
 #pragma unroll
     for (int u = 0; u < kD - 1; ++u)
-        if (u < nlev) ring_load<T, KW, kBwd, TS>(buf[u], lev(u), row0, meta, ecol, eval, dinv, src);
+        if (u < nlev) ring_load<T, KW, kBwd, TS, NT, NS>(buf[u], lev(u), row0, meta, ecol, eval, dinv, src);
     int q0 = 0;
     // steady state: every prefetch in the group is a real level
     for (; q0 + 2 * kD - 1 <= nlev; q0 += kD) {
 #pragma unroll
         for (int u = 0; u < kD; ++u) {
-            ring_load<T, KW, kBwd, TS>(buf[(u + kD - 1) % kD], lev(q0 + u + kD - 1), row0, meta, ecol, eval, dinv,
-                                       src);
-            ring_compute<T, KW, kRing, kBwd, TS, TD>(buf[u], row0, ring, ecol, eval, dinv, src, dst);
-            lds_barrier();
+            ring_load<T, KW, kBwd, TS, NT, NS>(buf[(u + kD - 1) % kD], lev(q0 + u + kD - 1), row0, meta, ecol, eval,
+                                               dinv, src);
+            ring_compute<T, KW, kRing, kBwd, TS, TD, NT, NS>(buf[u], row0, ring, ecol, eval, dinv, src, dst);
+            level_sync<NT>();
         }
     }
     // tail
@@ -251,21 +269,24 @@ __device__ __forceinline__ void ring_sweep(int nlev, int row0, const int4* meta,
             const int q = q0 + u;
             if (q < nlev) {
                 if (q + kD - 1 < nlev)
-                    ring_load<T, KW, kBwd, TS>(buf[(u + kD - 1) % kD], lev(q + kD - 1), row0, meta, ecol, eval, dinv,
-                                               src);
-                ring_compute<T, KW, kRing, kBwd, TS, TD>(buf[u], row0, ring, ecol, eval, dinv, src, dst);
-                lds_barrier();
+                    ring_load<T, KW, kBwd, TS, NT, NS>(buf[(u + kD - 1) % kD], lev(q + kD - 1), row0, meta, ecol,
+                                                       eval, dinv, src);
+                ring_compute<T, KW, kRing, kBwd, TS, TD, NT, NS>(buf[u], row0, ring, ecol, eval, dinv, src, dst);
+                level_sync<NT>();
             }
         }
     }
 }
 
-template <typename T, int KW, int kRing, typename TIn, typename TOut>
-__global__ __launch_bounds__(kRingThreads) void k_trsv_ring(
+// One workgroup of NT threads per (block, column); NT = 512 for wide levels,
+// 64 (one wave, no barriers) or 256 for thin ones, with a smaller ring.
+template <typename T, int KW, int kRing, typename TIn, typename TOut, int NT>
+__global__ __launch_bounds__(NT) void k_trsv_ring(
     const RingBlock* __restrict__ blk, int nblk, int nblk_pad, int nrhs, const int32_t* __restrict__ lvl_ptr,
     const int32_t* __restrict__ foff, const int32_t* __restrict__ fcol, const T* __restrict__ fval,
     const int32_t* __restrict__ boff, const int32_t* __restrict__ bcol, const T* __restrict__ bval,
     const T* __restrict__ dinv, const TIn* x, int64_t ldx, TOut* z, int64_t ldz, const int* __restrict__ done) {
+    constexpr int NS = ring_sets<KW>();
     __shared__ T ring[kRing];
     __shared__ int4 meta[kRingMaxLevels + 1];
     if (done && *done) return;
@@ -274,19 +295,19 @@ __global__ __launch_bounds__(kRingThreads) void k_trsv_ring(
     const RingBlock d = blk[b];
     const int nlev = d.lvl1 - d.lvl0;  // <= kRingMaxLevels (checked on the host)
     if (nlev <= 0) return;
-    for (int q = threadIdx.x; q <= nlev; q += kRingThreads) {
+    for (int q = threadIdx.x; q <= nlev; q += NT) {
         const int l = d.lvl0 + q;
         meta[q] = q < nlev ? int4{lvl_ptr[l] - d.row0, foff[l], boff[l], 0} : int4{lvl_ptr[l] - d.row0, 0, 0, 0};
     }
-    for (int q = threadIdx.x; q < kRing; q += kRingThreads) ring[q] = T(0);
+    for (int q = threadIdx.x; q < kRing; q += NT) ring[q] = T(0);
     __syncthreads();
     const TIn* xr = x + r * ldx + d.row0;
     TOut* zr = z + r * ldz + d.row0;
     // forward sweep: y = x - L y
-    ring_sweep<T, KW, kRing, false, TIn, TOut>(nlev, d.row0, meta, ring, fcol, fval, dinv, xr, zr);
+    ring_sweep<T, KW, kRing, false, TIn, TOut, NT, NS>(nlev, d.row0, meta, ring, fcol, fval, dinv, xr, zr);
     __syncthreads();  // global fence: the backward sweep reads y_i from memory
     // backward sweep: z = D^{-1} y - L^T z
-    ring_sweep<T, KW, kRing, true, TOut, TOut>(nlev, d.row0, meta, ring, bcol, bval, dinv, zr, zr);
+    ring_sweep<T, KW, kRing, true, TOut, TOut, NT, NS>(nlev, d.row0, meta, ring, bcol, bval, dinv, zr, zr);
 }
 
 // ----------------------------- A0 solve: narrow blocks, R columns per workgroup
@@ -353,7 +374,7 @@ __device__ __forceinline__ void ringr_compute(const LevelRegsR<T, KW, R, TS>& L,
         for (int j = 0; j < KW; ++j) {
             const V g = *reinterpret_cast<const V*>(ring + (size_t)(L.c[q][j] & (kRing - 1)) * R);
 #pragma unroll
-            for (int rr = 0; rr < R; ++rr) sv[rr] -= L.v[q][j] * g[rr];
+            for (int rr = 0; rr < R; ++rr) sv[rr] = fnms(sv[rr], L.v[q][j], g[rr]);
         }
         if (i0 < L.e) {
             *reinterpret_cast<V*>(ring + (size_t)(i & (kRing - 1)) * R) = sv;
@@ -373,7 +394,7 @@ __device__ __forceinline__ void ringr_compute(const LevelRegsR<T, KW, R, TS>& L,
             const T vj = eval[base + j * nr];
             const V g = *reinterpret_cast<const V*>(ring + (size_t)(ecol[base + j * nr] & (kRing - 1)) * R);
 #pragma unroll
-            for (int rr = 0; rr < R; ++rr) sv[rr] -= vj * g[rr];
+            for (int rr = 0; rr < R; ++rr) sv[rr] = fnms(sv[rr], vj, g[rr]);
         }
         *reinterpret_cast<V*>(ring + (size_t)(i & (kRing - 1)) * R) = sv;
 #pragma unroll
@@ -471,7 +492,7 @@ __global__ __launch_bounds__(256) void k_trsv_level(int a, int e, int nrhs, cons
     TOut* zr = z + r * ldz;
     T s = kKind == 1 ? (T)zr[i] * dinv[i] : (T)x[i + r * ldx];
     const int t1 = rp[i + 1];
-    for (int t = rp[i]; t < t1; ++t) s -= v[t] * (T)zr[ci[t]];
+    for (int t = rp[i]; t < t1; ++t) s = fnms(s, v[t], (T)zr[ci[t]]);
     if (kKind == 2) s *= dinv[i];
     zr[i] = (TOut)s;
 }

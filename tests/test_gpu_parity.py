@@ -577,3 +577,68 @@ def test_extend_lowrank(variant):
     D.ddlr_set_lowrank(h2, variant, *o.get_lowrank())
     with pytest.raises(D.DDLRError):
         D.ddlr_extend_lowrank(h2, 12, 4)
+
+
+def test_unstructured_rgg_end_to_end():
+    """General sparse SPD matrix (random geometric graph Laplacian) with the
+    library's graph partitioner: the partition equals the reference
+    definition, the A0 solve matches the oracle to 1e-12 and PCG takes the
+    oracle's iteration count (+-1) to the same solution."""
+    from oracle.partition import partition_graph
+    A, _ = w.rgg_laplacian(30000, 10, 5)
+    p = 16
+    part = D.ddlr_partition_graph(A, p)
+    assert np.array_equal(part, partition_graph(A, p))
+    cfg = dict(A=A, part=part, p=p, k=16, m=32)
+    say("rgg", A.n, len(A.col))
+    h, o = setup_pair(cfg, variant=1)
+    n = A.n
+    x = np.random.default_rng(9).standard_normal((n, 3))
+    y = torch.empty((3, n), dtype=torch.float64, device=DEV)
+    D.ddlr_a0_solve(h, to_dev(x), y)
+    assert rel(to_host(y), o.a0_solve(x)) <= 1e-12
+    o.lowrank(1, cfg["k"], cfg["m"], w.lanczos_start(n, 0))
+    b, xs = w.rhs_from_solution(A, 3, 2)
+    xt = torch.zeros((2, n), dtype=torch.float64, device=DEV)
+    st, info = D.ddlr_solve(h, to_dev(b), xt)
+    xo, io = o.pcg(b)
+    assert st == D.OK
+    for i, its in zip(info, io["its"]):
+        assert abs(i["iters"] - int(its)) <= 1 and i["relres_true"] <= 1.05e-6
+    assert rel(to_host(xt), xo) <= 1e-5
+
+
+@pytest.mark.parametrize("case", ["small3d", "rgg", "tpfa"])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_ring_workgroup_sizes_bitwise(case, prec):
+    """The one-column block triangular solve with 64 (single wave, no
+    barriers), 256 and 512 threads per workgroup, and the plain per-level
+    kernel, give bitwise the same A0 solve (where eligible) and match the
+    oracle; covers ELL width 32 (unstructured rows) and narrow 2-D levels."""
+    import os
+    if case == "small3d":
+        cfg = w.config("small3d")
+    elif case == "rgg":
+        A, _ = w.rgg_laplacian(12000, 12, 8)
+        cfg = dict(A=A, part=D.ddlr_partition_graph(A, 8), p=8, k=8, m=16)
+    else:
+        A = w.tpfa_2d(90, 70, 3)
+        cfg = dict(A=A, part=w.box_partition((90, 70), (3, 2)), p=6, k=8, m=16)
+    A = cfg["A"]
+    h, o = setup_pair(cfg, variant=0, precision=[D.FP64, D.FP32][prec], autotune=False)
+    x = np.random.default_rng(2).standard_normal((A.n, 3))
+    outs = {}
+    for nt in ("64", "256", "512", "-1"):
+        os.environ["DDLR_RING_NT"] = nt
+        y = torch.empty((3, A.n), dtype=torch.float64, device=DEV)
+        D.ddlr_a0_solve(h, to_dev(x), y)
+        torch.cuda.synchronize()
+        outs[nt] = y.cpu()
+    os.environ.pop("DDLR_RING_NT")
+    for nt in ("64", "256", "-1"):  # -1: the plain per-level kernel
+        assert torch.equal(outs[nt], outs["512"]), nt
+    ref = o.a0_solve(x)
+    assert rel(outs["512"].numpy().T, ref) <= (1e-12 if prec == 0 else 1e-5)
+    t = D.ddlr_tune(h, 1, retune=True)
+    say("tune", case, prec, t)
+    assert t["ring_threads"] in (-1, 64, 256, 512)

@@ -118,3 +118,20 @@ def test_host_only_handle_refuses_device_work():
     lib = D.load_library()
     st = lib.ddlr_apply(h.handle, 1, None, c["A"].n, None, c["A"].n, None)
     assert st == D.E_DEVICE
+
+
+@pytest.mark.parametrize("p", [2, 7, 16])
+def test_partitioner_matches_reference(p):
+    """Library recursive bisection == the reference definition, bit-exact."""
+    from oracle.partition import partition_graph
+    A, _ = w.rgg_laplacian(6000, 9, 3)
+    assert np.array_equal(D.ddlr_partition_graph(A, p), partition_graph(A, p))
+    G = w.laplacian_2d(23, 17)
+    assert np.array_equal(D.ddlr_partition_graph(G, p), partition_graph(G, p))
+
+
+def test_partitioner_errors():
+    G = w.laplacian_2d(3, 2)
+    with pytest.raises(D.DDLRError) as e:
+        D.ddlr_partition_graph(G, 7)  # more parts than vertices
+    assert e.value.status == D.E_INVALID

@@ -587,3 +587,51 @@ def test_extend_equals_direct_run(variant):
         assert np.array_equal(x, y)
     for x, y in zip(a.get_lowrank(), b.get_lowrank()):
         assert np.array_equal(np.asarray(x), np.asarray(y))
+
+
+# ------------------------------------------------------------ graph partitioner
+def _path(n):
+    rows = np.concatenate([np.arange(n - 1), np.arange(1, n), np.arange(n)])
+    cols = np.concatenate([np.arange(1, n), np.arange(n - 1), np.arange(n)])
+    return w._from_triplets(n, rows, cols, np.ones(len(rows)))
+
+
+def _expected_sizes(n, p):
+    """Part sizes of the recursive bisection depend only on (n, p)."""
+    if p == 1:
+        return [n]
+    q1 = p // 2
+    t = (n * q1 * 2 + p) // (2 * p)
+    return _expected_sizes(t, q1) + _expected_sizes(n - t, p - q1)
+
+
+def test_partition_path_graph_by_hand():
+    from oracle.partition import partition_graph
+    # path 0-1-...-8: BFS from the end vertex 0 visits 0..8 in order; 3 parts of 3
+    assert partition_graph(_path(9), 3).tolist() == [0, 0, 0, 1, 1, 1, 2, 2, 2]
+    # path numbered from the middle: the pseudo-peripheral search moves to an end
+    n = 7
+    perm = np.array([3, 2, 4, 1, 5, 0, 6])  # vertex i sits at position perm[i] on the line
+    pos = np.empty(n, int)
+    pos[perm] = np.arange(n)
+    rows, cols = [], []
+    for a in range(n - 1):
+        u, v = pos[a], pos[a + 1]
+        rows += [u, v]
+        cols += [v, u]
+    A = w._from_triplets(n, np.array(rows + list(range(n))), np.array(cols + list(range(n))), np.ones(len(rows) + n))
+    part = partition_graph(A, 2)
+    # halves are contiguous along the line: positions 0..3 in one part (t = 4), 4..6 in the other
+    assert len(set(part[pos[:4]])) == 1 and len(set(part[pos[4:]])) == 1 and part[pos[0]] != part[pos[6]]
+
+
+def test_partition_sizes_and_components():
+    from oracle.partition import partition_graph
+    A, _ = w.rgg_laplacian(3000, 8, 2)
+    for p in (2, 5, 8, 13):
+        part = partition_graph(A, p)
+        assert sorted(np.bincount(part, minlength=p).tolist()) == sorted(_expected_sizes(A.n, p))
+    # two disconnected paths: the component of vertex 0 comes first in the BFS order
+    B = w._from_triplets(8, np.array([0, 1, 1, 2, 4, 5, 5, 6, 6, 7] + list(range(8))),
+                         np.array([1, 0, 2, 1, 5, 4, 6, 5, 7, 6] + list(range(8))), np.ones(18))
+    assert partition_graph(B, 2).tolist() == [0, 0, 0, 0, 1, 1, 1, 1]

@@ -300,6 +300,33 @@ def batch_systems(count: int = 256, seed: int = 0, side_lo: int = 32, side_hi: i
     return out
 
 
+def rgg_laplacian(n: int, degree: float, seed: int) -> tuple:
+    """Random geometric graph Laplacian, an unstructured SPD M-matrix: n points
+    uniform in the unit cube (counter-based, stream "rgg"), numbered along a
+    Morton curve, joined when closer than r with n (4/3) pi r^3 = degree;
+    a_ij = -w_ij with w_ij uniform in [0.5, 1.5) per pair (stream "rggw"),
+    a_ii = sum_j w_ij + 0.01.  Returns (CSR, points)."""
+    from scipy.spatial import cKDTree
+    idx = np.arange(3 * n, dtype=np.uint64)
+    P = uniform(seed, "rgg", idx).reshape(n, 3)
+    # Morton order (10 bits per axis) for a locality-preserving numbering
+    q = np.minimum((P * 1024).astype(np.uint64), np.uint64(1023))
+    code = np.zeros(n, dtype=np.uint64)
+    for b in range(10):
+        for d in range(3):
+            code |= ((q[:, d] >> np.uint64(b)) & np.uint64(1)) << np.uint64(3 * b + d)
+    P = P[np.argsort(code, kind="stable")]
+    r = (3.0 * degree / (4.0 * np.pi * n)) ** (1.0 / 3.0)
+    pairs = cKDTree(P).query_pairs(r, output_type="ndarray").astype(np.int64)
+    lo, hi = np.minimum(pairs[:, 0], pairs[:, 1]), np.maximum(pairs[:, 0], pairs[:, 1])
+    wgt = 0.5 + uniform(seed, "rggw", (lo * n + hi).astype(np.uint64))
+    rows = np.concatenate([lo, hi, np.arange(n)])
+    cols = np.concatenate([hi, lo, np.arange(n)])
+    dsum = np.bincount(lo, wgt, n) + np.bincount(hi, wgt, n)
+    vals = np.concatenate([-wgt, -wgt, dsum + 0.01])
+    return _from_triplets(n, rows, cols, vals), P
+
+
 # resident matrices of the serving stream: grid side, box split, rank
 SERVING_MATRICES = ((37, (2, 2, 4), 32), (46, (2, 2, 4), 32), (55, (2, 4, 4), 40), (64, (2, 4, 4), 40),
                     (73, (4, 4, 4), 48), (82, (4, 4, 4), 48), (91, (4, 4, 8), 64), (100, (4, 4, 8), 64))
