@@ -93,9 +93,15 @@ def roofline_of(D, h, q, nrhs, tbytes, prof):
     avg_s = tot_ms / max(launches, 1) / 1e3
     by = trsv_bytes(nrhs, tbytes, nnz_b, rows_b)
     achieved = by / avg_s / 1e9 if avg_s > 0 else 0.0
-    R = D.ddlr_tune(h, nrhs)["ring_cols"]  # tuned shape (reported, not re-run)
+    tn = D.ddlr_tune(h, nrhs)  # tuned shape (reported, not re-run)
+    R, nt = tn["ring_cols"], tn["ring_threads"]
     t = "float" if tbytes == 4 else "double"
-    kname = f"k_trsv_ring_r<{t}, KW, {R}>" if R > 1 else f"k_trsv_ring<{t}, KW, ring>"
+    if R > 1:
+        kname = f"k_trsv_ring_r<{t}, KW, {R}>"
+    elif nt > 0:
+        kname = f"k_trsv_ring<{t}, KW, {nt} threads>"
+    else:
+        kname = f"k_trsv_narrow<{t}>"
     return {"bound": "hbm", "kernel": kname, "columns_per_workgroup": R, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "bytes_per_launch": by,
             "avg_launch_us": round(avg_s * 1e6, 2), "launches": launches}
@@ -115,7 +121,8 @@ def breakdown_of(D, prof, K, step_ms):
 
 def timed_solves(D, torch, h, bt, xt, steps, warmup, method, label, prof_steps=2):
     """Warm-up, then `steps` timed solves (the production path: CG iterations
-    replayed from captured graphs), then `prof_steps` solves with per-launch
+    replayed from captured graphs or launched eagerly, whichever the library
+    measured faster during the first solves), then `prof_steps` solves with per-launch
     HIP-event timing (same kernels and launch shapes, launched eagerly) for
     the kernel breakdown and the roofline's launch duration."""
     for _ in range(warmup):
@@ -182,6 +189,10 @@ def run_single(args, D, w, torch):
         log(name, "setup", f"{setup_s:.2f}s", "lanczos", f"{q['lanczos_ms']:.0f}ms", "theta", q["theta"])
         r = timed_solves(D, torch, h, bt, xt, args.steps, args.warmup, method, name)
         r.update(h=h, q=q, setup_s=setup_s, xerr=float(np.linalg.norm(r["x"] - xs) / np.linalg.norm(xs)))
+        tn = D.ddlr_tune(h, nrhs)  # the shapes the solves used (not re-run)
+        r["tuning"] = {key: tn[key] for key in ("ring_cols", "ring_threads", "overlap", "cg_overlap", "cg_graph",
+                                                "cg_eager_us", "cg_eager_in_line_us", "cg_graph_us")}
+        log(name, "tuning", r["tuning"])
         res[name] = r
     mixed, f64 = res["mixed"], res["fp64"]
     K = args.steps
@@ -226,6 +237,7 @@ def run_single(args, D, w, torch):
                   "x_rel_diff_vs_fp64": float(np.linalg.norm(mixed["x"] - f64["x"]) / np.linalg.norm(f64["x"]))},
         "mixed_over_fp64": round(value / (solves / f64["total"]), 3),
         "setup_s": {"fp64": round(f64["setup_s"], 3), "mixed": round(mixed["setup_s"], 3)},
+        "tuning": {"fp64": f64["tuning"], "mixed": mixed["tuning"]},
         "roofline": roof,
         "kernel_breakdown": breakdown_of(D, mixed["prof"], mixed["prof_steps"], mixed["prof_ms_per_step"]),
         "cpu_baseline": cpu,

@@ -249,7 +249,17 @@ ddlr_status ddlr_extend_lowrank(ddlr_prec *h, int32_t k, int32_t more_steps, int
  * (ddlr_batch_*) use fixed shapes (the smallest eligible workgroup, one
  * column).  Setting options.no_autotune keeps the defaults (one column per
  * workgroup of the smallest eligible size, overlap on) unless ddlr_tune is
- * called. */
+ * called.  PCG (ddlr_solve, method 0) runs its iterations in chunks of 8,
+ * replayed from a captured HIP graph or launched eagerly: graph replay saves
+ * launch overhead, but forked branches of a replayed graph (the interface
+ * levels beside the block solve) may run one after the other.  Unless the
+ * environment forces one form (DDLR_CG_GRAPH=1 graphs, 0 eager), the first
+ * solves with a column count time whole chunks on the host: eager chunks
+ * with the interface levels beside and in line with the block solve (that
+ * overlap competes with other forked work inside an iteration, so its A0-only
+ * timing above does not decide it for PCG), then replayed chunks with the
+ * better choice; the faster forms are kept.  cg_* below report that
+ * measurement. */
 typedef struct {
     int32_t nrhs;            /* column count the shape is for */
     int32_t ring_cols;       /* right-hand sides per workgroup of the block triangular solve */
@@ -260,6 +270,14 @@ typedef struct {
     float a0_no_overlap_us;  /* best shape with the interface levels in line (0: not measured) */
     float a0_thin_us[2];     /* one column per workgroup of 64 / 256 threads (0: not eligible) */
     float a0_plain_us;       /* the plain per-level kernel (0: not measured) */
+    int32_t cg_graph;        /* PCG chunks of this column count: 1 replayed graphs, 0 eager launches,
+                                -1 still being measured */
+    float cg_eager_us;       /* fastest timed eager chunk of 8 PCG iterations with the chosen overlap
+                                (0: none yet) */
+    float cg_graph_us;       /* fastest timed replayed chunk (0: none yet) */
+    int32_t cg_overlap;      /* PCG: interface levels beside (1) or in line with (0) the block solve; -1: still
+                                being measured, or no interface levels to overlap */
+    float cg_eager_in_line_us; /* fastest eager chunk with the interface levels in line (0: not timed) */
 } ddlr_tuning;
 ddlr_status ddlr_tune(ddlr_prec *h, int32_t nrhs, int32_t retune, ddlr_tuning *out, void *stream);
 

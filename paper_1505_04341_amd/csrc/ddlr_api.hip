@@ -66,6 +66,52 @@ struct DMem {
     }
 };
 
+// Streams shared by every handle on a device: the interface-level stream, the
+// CG stream and the x-update stream.  A process gets few hardware queues (4 by
+// default) and the runtime maps further streams onto queues already in use;
+// with three streams per handle a second handle's streams would share queues,
+// and forked work (the interface levels beside the block solve, the x update)
+// would run one after the other.  One set per device keeps them on distinct
+// queues.  Calls that put work on them (setup, solves, applies, tuning, the
+// server's steps) hold the device's lock, so one thread's graph capture on
+// these streams never picks up another thread's work; such calls on one
+// device are serialised.
+struct DevStreams {
+    std::recursive_mutex mu;
+    hipStream_t side = nullptr, cg = nullptr, x = nullptr;
+};
+
+// The set of device `dev`, created on first use in the order side, cg, x and
+// kept until the process ends.
+DevStreams& dev_streams(int dev) {
+    static std::mutex g;
+    static std::map<int, std::unique_ptr<DevStreams>> all;
+    DevStreams* D;
+    {
+        std::lock_guard<std::mutex> lk(g);
+        std::unique_ptr<DevStreams>& p = all[dev];
+        if (!p) p.reset(new DevStreams());
+        D = p.get();
+    }
+    std::lock_guard<std::recursive_mutex> lk(D->mu);
+    if (!D->x) {
+        int cur = 0;
+        HIPCHK(hipGetDevice(&cur));
+        HIPCHK(hipSetDevice(dev));
+        if (!D->side) HIPCHK(hipStreamCreateWithFlags(&D->side, hipStreamNonBlocking));  // default priority
+        if (!D->cg) HIPCHK(hipStreamCreateWithFlags(&D->cg, hipStreamNonBlocking));
+        HIPCHK(hipStreamCreateWithFlags(&D->x, hipStreamNonBlocking));
+        HIPCHK(hipSetDevice(cur));
+    }
+    return *D;
+}
+
+// Holds the stream lock of a device for its scope.
+struct DevLock {
+    std::lock_guard<std::recursive_mutex> lk;
+    explicit DevLock(int dev) : lk(dev_streams(dev).mu) {}
+};
+
 int grid_for(int64_t work, int block = 256, int cap = 8192) {
     int64_t g = (work + block - 1) / block;
     if (g < 1) g = 1;
@@ -145,7 +191,7 @@ struct ddlr_prec {
     int nnarrow = 0, nnarrow_pad = 0;
     // ring variant of the narrow A0-solve kernel (per-level ELL, LDS window)
     RingBlock* rblk = nullptr;
-    int32_t *foff = nullptr, *fcol = nullptr, *boff_ = nullptr, *bcol = nullptr;
+    int32_t *foff = nullptr, *fcol = nullptr, *boff_ = nullptr, *bcol = nullptr, *lwid = nullptr;
     double *fval64 = nullptr, *bval64 = nullptr;
     float *fval32 = nullptr, *bval32 = nullptr;
     int ring_kw = 0;                          // 2, 3, 4, 8, 16 or 0 (ring kernel unusable)
@@ -172,7 +218,18 @@ struct ddlr_prec {
     hipStream_t x_st = nullptr;
     hipEvent_t ev_xf = nullptr, ev_xj = nullptr;
     std::map<int, std::pair<hipGraph_t, hipGraphExec_t>> cg_graphs;
-    bool use_graphs = true;  // DDLR_CG_GRAPH=0: eager launches
+    // CG chunk launches: 2 = measured (eager and replayed chunks are timed on
+    // the first solves of each column count and the faster is kept), 1 = graphs,
+    // 0 = eager (DDLR_CG_GRAPH=1 / 0 force one)
+    int graph_mode = 2;
+    struct CgMode {
+        double eager_us[2] = {1e30, 1e30};  // fastest eager chunk, interface levels in line / beside
+        double graph_us = 1e30;
+        int ne[2] = {0, 0}, ng = 0;  // timed eager chunks; graph chunks (the capture included)
+        int ov = -1;                 // measured choice of overlap for CG (-1: not yet / not eligible)
+    };
+    std::map<int, CgMode> cg_mode;
+    int ov_override = -1;  // >= 0: overlap for the A0 solves being launched (set by the CG driver)
     bool lr_plain = false;                      // low-rank kernels without MFMA (comparison only)
     // the interface block's level kernels run on a side stream, overlapping the
     // B-block kernel (fork/join by events on the caller's stream)
@@ -206,7 +263,7 @@ namespace {
 // ------------------------------------------------------------ device upload
 
 constexpr int kRing64 = 8192, kRing32 = 16384;  // LDS ring rows: 64 KB either way
-constexpr int kRingThin = 2048;                  // ring rows of the 64- and 256-thread workgroups
+constexpr int kRingThin = 2048;                  // widest window the untuned 64/256-thread choice takes
 
 // Device-order arrays of one preconditioner (or of several merged), built on
 // the host before upload.
@@ -430,17 +487,27 @@ void build_ring(ddlr_prec* h, const DevHost& D) {
     h->ring_maxw = maxw;
     if (!h->ring_ok64 && !h->ring_ok32) return;
     const int KW = h->ring_kw;
-    std::vector<int32_t> foff(nlev), boff(nlev), fcol, bcol;
+    std::vector<int32_t> foff(nlev), boff(nlev), fcol, bcol, lwid(nlev, 0);
     std::vector<double> fval, bval;
+    // ELL width of a level: KW for the narrow kernels, else the level's widest
+    // row rounded up to a multiple of 4
+    auto width = [&](const std::vector<int32_t>& rp, int l) {
+        if (KW <= 4) return KW;
+        int w = 0;
+        for (int i = D.lvl_ptr[l]; i < D.lvl_ptr[l + 1]; ++i) w = std::max(w, rp[i + 1] - rp[i]);
+        return std::min(KW, (w + 3) / 4 * 4);
+    };
     auto build = [&](const std::vector<int32_t>& rp, const std::vector<int32_t>& ci, const std::vector<double>& v,
-                     std::vector<int32_t>& off, std::vector<int32_t>& col, std::vector<double>& val) {
+                     std::vector<int32_t>& off, std::vector<int32_t>& col, std::vector<double>& val, int shift) {
         for (int l = 0; l < nlev; ++l) {
             const int a = D.lvl_ptr[l], e = D.lvl_ptr[l + 1], nr = e - a;
+            const int W = width(rp, l);
+            lwid[l] |= W << shift;
             off[l] = (int32_t)col.size();
-            col.resize(col.size() + (size_t)KW * nr, 0);  // padding: column 0, value 0
-            val.resize(val.size() + (size_t)KW * nr, 0.0);
+            col.resize(col.size() + (size_t)W * nr, 0);  // padding: column 0, value 0
+            val.resize(val.size() + (size_t)W * nr, 0.0);
             for (int i = a; i < e; ++i) {
-                const int t0 = rp[i], t1 = std::min(rp[i + 1], rp[i] + KW);
+                const int t0 = rp[i], t1 = std::min(rp[i + 1], rp[i] + W);
                 for (int t = t0, j = 0; t < t1; ++t, ++j) {
                     col[off[l] + (size_t)j * nr + (i - a)] = ci[t] - D.lvl_row0[l];
                     val[off[l] + (size_t)j * nr + (i - a)] = v[t];
@@ -448,8 +515,8 @@ void build_ring(ddlr_prec* h, const DevHost& D) {
             }
         }
     };
-    build(lrp, lci, D.lv, foff, fcol, fval);
-    build(urp, uci, D.uv, boff, bcol, bval);
+    build(lrp, lci, D.lv, foff, fcol, fval, 0);
+    build(urp, uci, D.uv, boff, bcol, bval, 16);
     std::vector<RingBlock> rb;
     for (const BlockDesc& b : bd) rb.push_back({b.lvl0, b.lvl1, D.lvl_row0[b.lvl0], 0});
     DMem& M = h->mem;
@@ -458,6 +525,7 @@ void build_ring(ddlr_prec* h, const DevHost& D) {
     h->fcol = M.upload(fcol);
     h->boff_ = M.upload(boff);
     h->bcol = M.upload(bcol);
+    h->lwid = M.upload(lwid);
     h->fval64 = M.upload(fval);
     h->bval64 = M.upload(bval);
     if (h->precision != DDLR_FP64) {
@@ -659,28 +727,33 @@ template <typename T> constexpr int ring_rows();
 template <> constexpr int ring_rows<double>() { return kRing64; }
 template <> constexpr int ring_rows<float>() { return kRing32; }
 
-// Workgroup sizes of the one-column ring kernel: 512 always (rows beyond its
-// row sets are done without prefetch); 64 and 256 when every level fits their
-// row sets and the dependency window fits the smaller ring.
-template <int KW> constexpr int ring_sets_host() { return KW <= 16 ? 2 : 1; }
-bool ring_nt_ok(const ddlr_prec* h, int nt) {
-    if (nt == 512) return true;
-    const int ns = h->ring_kw <= 16 ? 2 : 1;
-    return h->ring_maxw <= nt * ns && h->ring_need <= kRingThin;
-}
+// Workgroup sizes of the one-column ring kernel: any of 64, 256 and 512 is
+// correct (rows beyond a workgroup's row sets are done without prefetch).
+// Untuned, 64 or 256 is taken when every level fits their row sets and the
+// dependency window is short (small rings leave LDS for more workgroups).
+bool ring_nt_ok(const ddlr_prec* h, int nt) { return nt == 64 || nt == 256 || nt == 512; }
 int ring_nt_default(const ddlr_prec* h) {
+    const int ns = h->ring_kw <= 16 ? 2 : 1;
     for (int nt : {64, 256})
-        if (ring_nt_ok(h, nt)) return nt;
+        if (h->ring_maxw <= nt * ns && h->ring_need <= kRingThin) return nt;
     return 512;
+}
+
+// ring rows: the dependency window rounded up to a power of two (at least 64)
+int ring_rows_for(const ddlr_prec* h) {
+    int r = 64;
+    while (r < h->ring_need) r <<= 1;
+    return r;
 }
 
 template <typename T, int KW, typename TIn, typename TOut, int NT>
 void launch_ring_nt(ddlr_prec* h, const T* dinv, int nrhs, const TIn* x, int64_t ldx, TOut* z, int64_t ldz,
                     hipStream_t st, const int* done) {
-    constexpr int kRing = NT == 512 ? ring_rows<T>() : kRingThin;
-    hipLaunchKernelGGL((k_trsv_ring<T, KW, kRing, TIn, TOut, NT>), dim3(h->nnarrow_pad * nrhs), dim3(NT), 0, st,
-                       h->rblk, h->nnarrow, h->nnarrow_pad, nrhs, h->lvl_ptr, h->foff, h->fcol, ring_fval<T>(h),
-                       h->boff_, h->bcol, ring_bval<T>(h), dinv, x, ldx, z, ldz, done);
+    const int rows = ring_rows_for(h);  // <= ring_rows<T>(): checked when the ring was enabled
+    hipLaunchKernelGGL((k_trsv_ring<T, KW, TIn, TOut, NT>), dim3(h->nnarrow_pad * nrhs), dim3(NT),
+                       (size_t)rows * sizeof(T), st, h->rblk, h->nnarrow, h->nnarrow_pad, nrhs, h->lvl_ptr, h->foff,
+                       h->fcol, ring_fval<T>(h), h->boff_, h->bcol, ring_bval<T>(h), h->lwid, rows - 1, dinv, x, ldx,
+                       z, ldz, done);
     LAUNCHCHK();
 }
 
@@ -795,6 +868,7 @@ void a0_solve_dev(ddlr_prec* h, const DevFactors<T>& F, int nrhs, const TIn* x, 
                   hipStream_t st, const int* done) {
     bool ov = h->overlap;
     if (auto it = h->tune.find(nrhs); it != h->tune.end()) ov = ov && it->second.overlap;
+    if (h->ov_override >= 0) ov = h->overlap && h->ov_override;
     const bool fork = !h->wide.empty() && h->nnarrow > 0 && ov && h->side;
     hipStream_t cst = st;
     if (fork) {
@@ -996,10 +1070,16 @@ void cg_xr_dev(ddlr_prec* h, int nr, hipStream_t st) {
     LAUNCHCHK();
 }
 
-// streams for the lane-phase CG (created outside any graph capture)
+// Streams of the lane-phase CG: the CG stream (private to the library, so
+// graph capture never touches a caller's stream) and the x-update stream,
+// taken from the device's shared set (created outside any graph capture).
 void ensure_cg_streams(ddlr_prec* h) {
     if (h->x_st) return;
-    HIPCHK(hipStreamCreateWithFlags(&h->x_st, hipStreamNonBlocking));  // default priority
+    DevStreams& D = dev_streams(h->device);
+    h->cg_st = D.cg;
+    h->x_st = D.x;
+    HIPCHK(hipEventCreateWithFlags(&h->ev_in, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&h->ev_out, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&h->ev_xf, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&h->ev_xj, hipEventDisableTiming));
 }
@@ -1408,21 +1488,20 @@ void drop_graphs(ddlr_prec* h) {
         if (g.second.first) (void)hipGraphDestroy(g.second.first);
     }
     h->cg_graphs.clear();
+    h->cg_mode.clear();  // launch shapes changed: measure again
 }
 
+// The streams belong to the device's shared set; only the events are the handle's.
 void release_streams(ddlr_prec* h) {
     drop_graphs(h);
-    if (h->cg_st) (void)hipStreamDestroy(h->cg_st);
     if (h->ev_in) (void)hipEventDestroy(h->ev_in);
     if (h->ev_out) (void)hipEventDestroy(h->ev_out);
     h->cg_st = nullptr;
     h->ev_in = h->ev_out = nullptr;
-    if (h->x_st) (void)hipStreamDestroy(h->x_st);
     if (h->ev_xf) (void)hipEventDestroy(h->ev_xf);
     if (h->ev_xj) (void)hipEventDestroy(h->ev_xj);
     h->x_st = nullptr;
     h->ev_xf = h->ev_xj = nullptr;
-    if (h->side) (void)hipStreamDestroy(h->side);
     if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
     if (h->ev_join) (void)hipEventDestroy(h->ev_join);
     h->side = nullptr;
@@ -1508,15 +1587,17 @@ ddlr_status ddlr_setup(const ddlr_csr* A, const int32_t* part, int32_t p, int32_
         h->device = opt.device;
         if (opt.device >= 0) {
             HIPCHK(hipSetDevice(opt.device));
+            DevLock dl(opt.device);
             upload_structures(h.get());
             if (const char* env = std::getenv("DDLR_NO_OVERLAP")) h->overlap = env[0] != '1';
             h->tune_mode = opt.no_autotune ? 0 : 1;
-            if (const char* env = std::getenv("DDLR_CG_GRAPH")) h->use_graphs = env[0] != '0';
+            if (const char* env = std::getenv("DDLR_CG_GRAPH")) h->graph_mode = env[0] == '0' ? 0 : env[0] == '1' ? 1 : 2;
             if (!h->wide.empty()) {
-                HIPCHK(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));  // default priority
+                h->side = dev_streams(opt.device).side;
                 HIPCHK(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
                 HIPCHK(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
             }
+            ensure_cg_streams(h.get());
             if (variant != 0) {
                 // fixed m steps (default 2k), or the paper's control: at most
                 // lanczos_max steps (default 5k), stopped by eq. (converge)
@@ -1671,6 +1752,7 @@ static ddlr_status run_chunked(ddlr_prec* h, int32_t nrhs, const double* x, int6
                                void* stream, Op op) {
     try {
         HIPCHK(hipSetDevice(h->device));
+        DevLock dl(h->device);
         hipStream_t st = (hipStream_t)stream;
         const int64_t n = h->ndev;
         for (int32_t c0 = 0; c0 < nrhs; c0 += kMaxRhs) {
@@ -1873,10 +1955,10 @@ static void lane_admit(ddlr_prec* h, int nr, const std::vector<int32_t>& start, 
 // PCG on nr columns already gathered into W.r (b); result in W.x.
 constexpr int kCgChunk = 8;
 
-// kCgChunk lane iterations on st: replayed from a graph captured on first use
-// for this column count (eager while profiling, or if capture fails)
-static void cg_chunk(ddlr_prec* h, int nr, hipStream_t st) {
-    if (h->prof || !h->use_graphs) {
+// kCgChunk lane iterations on st: eager launches, or replayed from a graph
+// captured on first use for this column count (eager if capture fails)
+static void cg_chunk(ddlr_prec* h, int nr, hipStream_t st, bool graph) {
+    if (!graph) {
         for (int c = 0; c < kCgChunk; ++c) lane_iteration(h, nr, st);
         return;
     }
@@ -1899,7 +1981,7 @@ static void cg_chunk(ddlr_prec* h, int nr, hipStream_t st) {
         } else {
             (void)hipGetLastError();
             if (g) (void)hipGraphDestroy(g);
-            h->use_graphs = false;  // fall back to eager launches for this handle
+            h->graph_mode = 0;  // fall back to eager launches for this handle
             for (int c = 0; c < kCgChunk; ++c) lane_iteration(h, nr, st);
             return;
         }
@@ -1909,22 +1991,70 @@ static void cg_chunk(ddlr_prec* h, int nr, hipStream_t st) {
 
 static void pcg_dev(ddlr_prec* h, int nr, const ddlr_solve_options& o, hipStream_t ust) {
     ensure_cg_streams(h);
-    if (!h->cg_st) {
-        HIPCHK(hipStreamCreateWithFlags(&h->cg_st, hipStreamNonBlocking));  // default priority
-        HIPCHK(hipEventCreateWithFlags(&h->ev_in, hipEventDisableTiming));
-        HIPCHK(hipEventCreateWithFlags(&h->ev_out, hipEventDisableTiming));
-    }
     hipStream_t st = h->cg_st;
     HIPCHK(hipEventRecord(h->ev_in, ust));
     HIPCHK(hipStreamWaitEvent(st, h->ev_in, 0));
     std::vector<int32_t> start(nr, 1), maxit(nr, o.maxit);
     std::vector<double> tol2(nr, o.rtol * o.rtol);
     lane_admit(h, nr, start, tol2, maxit, st);
+    // Launch form of the chunks, measured on the first solves of a column
+    // count unless DDLR_CG_GRAPH forces one: chunk boundaries are synchronous
+    // anyway, so whole chunks are timed on the host.  First, when the
+    // interface levels can run beside the block solve, two eager chunks each
+    // with and without that overlap (its benefit inside a CG iteration, where
+    // other forked work competes, can differ from the A0 solve's alone); then,
+    // with the better choice, a graph is captured and two replays are timed
+    // against the eager chunks: replay saves launch overhead, but the runtime
+    // may run a replayed graph's forked branches one after the other.
+    ddlr_prec::CgMode& m = h->cg_mode[nr];
+    const bool measure = h->graph_mode == 2 && !h->prof;
+    const bool can_ov = !h->wide.empty() && h->nnarrow > 0 && h->overlap && h->side;
     for (int it = 0; it <= o.maxit; it += kCgChunk) {
-        cg_chunk(h, nr, st);
+        bool graph = !h->prof && h->graph_mode != 0;
+        bool timed = false;
+        int slot = 1;
+        h->ov_override = -1;
+        if (measure) {
+            if (can_ov && m.ov < 0) {
+                slot = m.ne[1] < 2 ? 1 : 0;
+                h->ov_override = slot;
+                graph = false;
+                timed = true;
+            } else {
+                if (can_ov) slot = h->ov_override = m.ov;
+                if (m.ne[slot] < 2) {
+                    graph = false;
+                    timed = true;
+                } else if (m.ng < 3) {
+                    timed = m.ng >= 1;
+                } else {
+                    graph = m.graph_us <= m.eager_us[slot];
+                }
+            }
+        } else if (h->graph_mode == 2 && can_ov && m.ov >= 0) {
+            h->ov_override = m.ov;  // profiled solves keep the measured choice
+        }
+        const auto t0 = std::chrono::steady_clock::now();
+        cg_chunk(h, nr, st, graph);
         HIPCHK(hipMemcpyAsync(h->ws.done_host, h->ws.done, sizeof(int), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
-        if (*h->ws.done_host) break;
+        h->ov_override = -1;
+        const double us = std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
+        const bool done = *h->ws.done_host != 0;
+        if (measure) {
+            if (graph && m.ng == 0) ++m.ng;  // the capture
+            if (timed && !done) {            // a chunk that ran all its iterations
+                if (graph) {
+                    m.graph_us = std::min(m.graph_us, us);
+                    ++m.ng;
+                } else {
+                    m.eager_us[slot] = std::min(m.eager_us[slot], us);
+                    ++m.ne[slot];
+                }
+            }
+            if (can_ov && m.ov < 0 && m.ne[0] >= 2 && m.ne[1] >= 2) m.ov = m.eager_us[1] <= m.eager_us[0] ? 1 : 0;
+        }
+        if (done) break;
     }
     HIPCHK(hipEventRecord(h->ev_out, st));
     HIPCHK(hipStreamWaitEvent(ust, h->ev_out, 0));
@@ -1954,6 +2084,7 @@ ddlr_status ddlr_solve(ddlr_prec* h, int32_t nrhs, const double* b, int64_t ldb,
     ddlr_status result = DDLR_OK;
     try {
         HIPCHK(hipSetDevice(h->device));
+        DevLock dl(h->device);
         hipStream_t st = (hipStream_t)stream;
         const int64_t n = h->ndev;
         for (int32_t c0 = 0; c0 < nrhs; c0 += kMaxRhs) {
@@ -2141,6 +2272,7 @@ ddlr_status ddlr_set_lowrank(ddlr_prec* h, int32_t variant, int32_t k, const dou
     }
     try {
         HIPCHK(hipSetDevice(h->device));
+        DevLock dl(h->device);
         HIPCHK(hipDeviceSynchronize());
         const HostPlan& P = h->plan;
         const int64_t rows = variant == 1 ? P.s : P.n, off = variant == 1 ? P.m : 0;
@@ -2208,6 +2340,7 @@ ddlr_status ddlr_profile(ddlr_prec* h, int32_t on) {
     if (!dev_ok(h)) return h ? DDLR_E_DEVICE : DDLR_E_INVALID;
     try {
         HIPCHK(hipSetDevice(h->device));
+        DevLock dl(h->device);
         HIPCHK(hipDeviceSynchronize());
         prof_reset(h);
         h->prof = on != 0;
@@ -2253,6 +2386,7 @@ ddlr_status ddlr_extend_lowrank(ddlr_prec* h, int32_t k, int32_t more_steps, int
     }
     try {
         HIPCHK(hipSetDevice(h->device));
+        DevLock dl(h->device);
         HIPCHK(hipDeviceSynchronize());
         h->variant = h->lrun.lvariant;
         const int m = (int)std::min<int64_t>((int64_t)h->lrun.steps + more_steps, h->plan.s);
@@ -2282,6 +2416,7 @@ ddlr_status ddlr_tune(ddlr_prec* h, int32_t nrhs, int32_t retune, ddlr_tuning* o
     }
     try {
         HIPCHK(hipSetDevice(h->device));
+        DevLock dl(h->device);
         hipStream_t st = (hipStream_t)stream;
         autotune(h, nrhs, st, retune != 0 || !h->tune.count(nrhs));
         HIPCHK(hipStreamSynchronize(st));
@@ -2290,6 +2425,17 @@ ddlr_status ddlr_tune(ddlr_prec* h, int32_t nrhs, int32_t retune, ddlr_tuning* o
     }
     std::memset(out, 0, sizeof(*out));
     out->nrhs = nrhs;
+    out->cg_graph = h->graph_mode == 2 ? -1 : h->graph_mode;
+    out->cg_overlap = -1;
+    if (auto mi = h->cg_mode.find(nrhs); mi != h->cg_mode.end()) {
+        const ddlr_prec::CgMode& m = mi->second;
+        const int slot = m.ov >= 0 ? m.ov : 1;
+        out->cg_overlap = m.ov;
+        if (m.ne[slot] > 0) out->cg_eager_us = (float)m.eager_us[slot];
+        if (m.ne[0] > 0) out->cg_eager_in_line_us = (float)m.eager_us[0];
+        if (m.ng > 1) out->cg_graph_us = (float)m.graph_us;
+        if (h->graph_mode == 2 && m.ne[slot] >= 2 && m.ng >= 3) out->cg_graph = m.graph_us <= m.eager_us[slot] ? 1 : 0;
+    }
     auto it = h->tune.find(nrhs);
     if (it == h->tune.end()) {  // batches: fixed shape
         out->ring_cols = 1;
@@ -2313,6 +2459,7 @@ void ddlr_destroy(ddlr_prec* h) {
     if (!h) return;
     if (h->device >= 0) {
         (void)hipSetDevice(h->device);
+        DevLock dl(h->device);
         (void)hipDeviceSynchronize();
         prof_reset(h);
         for (hipEvent_t e : h->prof_pool) (void)hipEventDestroy(e);
@@ -2692,6 +2839,7 @@ double now_s() {
 // One pass of the engine: admit queued columns into free slots, run `tick`
 // iterations on every matrix that has lanes, retire finished lanes.
 bool server_step(ddlr_server* S) {
+    DevLock dl(S->device);  // before S->mu, as in ddlr_server_add
     struct Adm {
         int slot;
         SrvRequest* r;
@@ -2850,6 +2998,7 @@ ddlr_status ddlr_server_add(ddlr_server* S, ddlr_prec* h, int32_t* matrix_id) {
     M->h = h;
     try {
         HIPCHK(hipSetDevice(S->device));
+        DevLock dl(S->device);
         std::lock_guard<std::mutex> lk(S->mu);
         const size_t before = prec_bytes(h);
         const size_t stage = (size_t)h->ndev * S->slots * sizeof(double);

@@ -124,22 +124,26 @@ __global__ __launch_bounds__(256) void k_trsv_narrow(
 // ------------------------------------- A0 solve: narrow blocks, LDS ring
 //
 // Same schedule as k_trsv_narrow, restructured for latency:
-//  * each row's dependencies are stored per level in ELL form with a fixed
-//    width KW (entries column-major, column = row index local to the block;
-//    padding has column 0 and value 0), so one level's data is one coalesced
-//    segment and every level issues the same loads;
+//  * each row's dependencies are stored per level in ELL form (entries
+//    column-major, column = row index local to the block; padding has column
+//    0 and value 0), so one level's data is one coalesced segment; kernels of
+//    width KW <= 4 see every level padded to KW, wider ones see each level
+//    padded to its own widest row rounded up to a multiple of 4 (meta.w:
+//    forward width in the low 16 bits, backward width in the high 16), so
+//    irregular rows do not make every level as wide as the widest row;
 //  * the next kD-1 levels' entries, right-hand side values and D^{-1} are
 //    loaded into registers ahead of use, so HBM latency overlaps computation
 //    and barriers; the steady-state loop has no divergent branches, which
 //    lets the compiler wait only for the level being computed;
 //  * lanes beyond a level's last row load and recompute that last row (all
 //    loads are unconditional) but only the owning lane stores it;
-//  * results go to global memory and to a ring of the most recent kRing rows
-//    in LDS; the host has checked that every dependency of every level lies
-//    inside that window (forward: c >= e - kRing; backward: c < a + kRing),
-//    so all gathers hit LDS and levels are separated by LDS-only barriers.
-// 512 threads, two rows per thread per level in registers; levels longer than
-// 1024 rows finish their tail without prefetch.
+//  * results go to global memory and to a ring of the most recent rmask + 1
+//    rows in LDS (a power of two chosen at launch); the host has checked that
+//    every dependency of every level lies inside that window (forward:
+//    c >= e - ring; backward: c < a + ring), so all gathers hit LDS and levels
+//    are separated by LDS-only barriers.
+// NT threads with NS rows each per level in registers; rows beyond NS * NT
+// finish without prefetch.
 struct RingBlock {
     int32_t lvl0, lvl1, row0, pad;
 };
@@ -157,7 +161,7 @@ constexpr int kRingMaxLevels = 511;
 // side value is kept in its storage type TS and converted when used, so no
 // load is waited for early.
 template <typename T, int KW, typename TS, int NS> struct LevelRegs {
-    int a, e, off;
+    int a, e, off, w;
     int c[NS][KW];
     T v[NS][KW];
     TS xv[NS];
@@ -182,6 +186,7 @@ __device__ __forceinline__ void ring_load(LevelRegs<T, KW, TS, NS>& R, int q, in
     R.a = __builtin_amdgcn_readfirstlane(mq.x);
     R.e = __builtin_amdgcn_readfirstlane(meta[q + 1].x);
     R.off = __builtin_amdgcn_readfirstlane(kBwd ? mq.z : mq.y);
+    R.w = KW > 4 ? __builtin_amdgcn_readfirstlane(kBwd ? (mq.w >> 16) : (mq.w & 0xffff)) : KW;
     const int nr = R.e - R.a;
 #pragma unroll
     for (int qq = 0; qq < NS; ++qq) {
@@ -190,6 +195,7 @@ __device__ __forceinline__ void ring_load(LevelRegs<T, KW, TS, NS>& R, int q, in
         const int base = R.off + (i - R.a);
 #pragma unroll
         for (int j = 0; j < KW; ++j) {
+            if (KW > 4 && j % 4 == 0 && j >= R.w) break;  // uniform: the level's width
             R.c[qq][j] = ecol[base + j * nr];
             R.v[qq][j] = eval[base + j * nr];
         }
@@ -198,8 +204,8 @@ __device__ __forceinline__ void ring_load(LevelRegs<T, KW, TS, NS>& R, int q, in
     }
 }
 
-template <typename T, int KW, int kRing, bool kBwd, typename TS, typename TD, int NT, int NS>
-__device__ __forceinline__ void ring_compute(const LevelRegs<T, KW, TS, NS>& R, int row0, T* ring,
+template <typename T, int KW, bool kBwd, typename TS, typename TD, int NT, int NS>
+__device__ __forceinline__ void ring_compute(const LevelRegs<T, KW, TS, NS>& R, int row0, T* ring, int rmask,
                                              const int32_t* __restrict__ ecol, const T* __restrict__ eval,
                                              const T* __restrict__ dinv, const TS* src, TD* dst) {
 #pragma unroll
@@ -209,11 +215,14 @@ __device__ __forceinline__ void ring_compute(const LevelRegs<T, KW, TS, NS>& R, 
         const int i = min(i0, R.e - 1);
         T s = kBwd ? (T)R.xv[q] * R.dv[q] : (T)R.xv[q];
 #pragma unroll
-        for (int j = 0; j < KW; ++j) s = fnms(s, R.v[q][j], ring[R.c[q][j] & (kRing - 1)]);
+        for (int j = 0; j < KW; ++j) {
+            if (KW > 4 && j % 4 == 0 && j >= R.w) break;
+            s = fnms(s, R.v[q][j], ring[R.c[q][j] & rmask]);
+        }
         // only the owning lane stores: duplicate global stores of a forward value
         // from other waves are not ordered against the owner's backward store
         if (i0 < R.e) {
-            ring[i & (kRing - 1)] = s;
+            ring[i & rmask] = s;
             dst[i] = (TD)s;
         }
     }
@@ -222,8 +231,8 @@ __device__ __forceinline__ void ring_compute(const LevelRegs<T, KW, TS, NS>& R, 
     for (int i = R.a + NS * NT + (int)threadIdx.x; i < R.e; i += NT) {
         const int base = R.off + (i - R.a);
         T s = kBwd ? (T)src[i] * dinv[row0 + i] : (T)src[i];
-        for (int j = 0; j < KW; ++j) s = fnms(s, eval[base + j * nr], ring[ecol[base + j * nr] & (kRing - 1)]);
-        ring[i & (kRing - 1)] = s;
+        for (int j = 0; j < R.w; ++j) s = fnms(s, eval[base + j * nr], ring[ecol[base + j * nr] & rmask]);
+        ring[i & rmask] = s;
         dst[i] = (TD)s;
     }
 }
@@ -241,8 +250,8 @@ template <> struct RingDepth<double, 3> { static constexpr int value = 3; };
 template <int KW> constexpr int ring_sets() { return KW <= 16 ? 2 : 1; }
 
 // One sweep over local levels; kBwd walks them from the last to the first.
-template <typename T, int KW, int kRing, bool kBwd, typename TS, typename TD, int NT, int NS>
-__device__ __forceinline__ void ring_sweep(int nlev, int row0, const int4* meta, T* ring,
+template <typename T, int KW, bool kBwd, typename TS, typename TD, int NT, int NS>
+__device__ __forceinline__ void ring_sweep(int nlev, int row0, const int4* meta, T* ring, int rmask,
                                            const int32_t* __restrict__ ecol, const T* __restrict__ eval,
                                            const T* __restrict__ dinv, const TS* src, TD* dst) {
     constexpr int kD = RingDepth<T, KW>::value;
@@ -258,7 +267,7 @@ __device__ __forceinline__ void ring_sweep(int nlev, int row0, const int4* meta,
         for (int u = 0; u < kD; ++u) {
             ring_load<T, KW, kBwd, TS, NT, NS>(buf[(u + kD - 1) % kD], lev(q0 + u + kD - 1), row0, meta, ecol, eval,
                                                dinv, src);
-            ring_compute<T, KW, kRing, kBwd, TS, TD, NT, NS>(buf[u], row0, ring, ecol, eval, dinv, src, dst);
+            ring_compute<T, KW, kBwd, TS, TD, NT, NS>(buf[u], row0, ring, rmask, ecol, eval, dinv, src, dst);
             level_sync<NT>();
         }
     }
@@ -271,7 +280,7 @@ __device__ __forceinline__ void ring_sweep(int nlev, int row0, const int4* meta,
                 if (q + kD - 1 < nlev)
                     ring_load<T, KW, kBwd, TS, NT, NS>(buf[(u + kD - 1) % kD], lev(q + kD - 1), row0, meta, ecol,
                                                        eval, dinv, src);
-                ring_compute<T, KW, kRing, kBwd, TS, TD, NT, NS>(buf[u], row0, ring, ecol, eval, dinv, src, dst);
+                ring_compute<T, KW, kBwd, TS, TD, NT, NS>(buf[u], row0, ring, rmask, ecol, eval, dinv, src, dst);
                 level_sync<NT>();
             }
         }
@@ -279,15 +288,18 @@ __device__ __forceinline__ void ring_sweep(int nlev, int row0, const int4* meta,
 }
 
 // One workgroup of NT threads per (block, column); NT = 512 for wide levels,
-// 64 (one wave, no barriers) or 256 for thin ones, with a smaller ring.
-template <typename T, int KW, int kRing, typename TIn, typename TOut, int NT>
+// 64 (one wave, no barriers) or 256 for thin ones.  The ring is dynamic LDS of
+// rmask + 1 rows (a power of two).
+template <typename T, int KW, typename TIn, typename TOut, int NT>
 __global__ __launch_bounds__(NT) void k_trsv_ring(
     const RingBlock* __restrict__ blk, int nblk, int nblk_pad, int nrhs, const int32_t* __restrict__ lvl_ptr,
     const int32_t* __restrict__ foff, const int32_t* __restrict__ fcol, const T* __restrict__ fval,
     const int32_t* __restrict__ boff, const int32_t* __restrict__ bcol, const T* __restrict__ bval,
-    const T* __restrict__ dinv, const TIn* x, int64_t ldx, TOut* z, int64_t ldz, const int* __restrict__ done) {
+    const int32_t* __restrict__ lwid, int rmask, const T* __restrict__ dinv, const TIn* x, int64_t ldx, TOut* z,
+    int64_t ldz, const int* __restrict__ done) {
     constexpr int NS = ring_sets<KW>();
-    __shared__ T ring[kRing];
+    extern __shared__ __attribute__((aligned(16))) char ring_lds[];
+    T* ring = reinterpret_cast<T*>(ring_lds);
     __shared__ int4 meta[kRingMaxLevels + 1];
     if (done && *done) return;
     const int b = blockIdx.x % nblk_pad, r = blockIdx.x / nblk_pad;
@@ -297,17 +309,17 @@ __global__ __launch_bounds__(NT) void k_trsv_ring(
     if (nlev <= 0) return;
     for (int q = threadIdx.x; q <= nlev; q += NT) {
         const int l = d.lvl0 + q;
-        meta[q] = q < nlev ? int4{lvl_ptr[l] - d.row0, foff[l], boff[l], 0} : int4{lvl_ptr[l] - d.row0, 0, 0, 0};
+        meta[q] = q < nlev ? int4{lvl_ptr[l] - d.row0, foff[l], boff[l], lwid[l]} : int4{lvl_ptr[l] - d.row0, 0, 0, 0};
     }
-    for (int q = threadIdx.x; q < kRing; q += NT) ring[q] = T(0);
+    for (int q = threadIdx.x; q <= rmask; q += NT) ring[q] = T(0);
     __syncthreads();
     const TIn* xr = x + r * ldx + d.row0;
     TOut* zr = z + r * ldz + d.row0;
     // forward sweep: y = x - L y
-    ring_sweep<T, KW, kRing, false, TIn, TOut, NT, NS>(nlev, d.row0, meta, ring, fcol, fval, dinv, xr, zr);
+    ring_sweep<T, KW, false, TIn, TOut, NT, NS>(nlev, d.row0, meta, ring, rmask, fcol, fval, dinv, xr, zr);
     __syncthreads();  // global fence: the backward sweep reads y_i from memory
     // backward sweep: z = D^{-1} y - L^T z
-    ring_sweep<T, KW, kRing, true, TOut, TOut, NT, NS>(nlev, d.row0, meta, ring, bcol, bval, dinv, zr, zr);
+    ring_sweep<T, KW, true, TOut, TOut, NT, NS>(nlev, d.row0, meta, ring, rmask, bcol, bval, dinv, zr, zr);
 }
 
 // ----------------------------- A0 solve: narrow blocks, R columns per workgroup
