@@ -149,6 +149,7 @@ struct Workspace {
     // preconditioner temporaries (type of the preconditioner)
     void *a0 = nullptr, *a1 = nullptr, *a2 = nullptr, *a3 = nullptr, *ys = nullptr, *ws = nullptr;
     double *part = nullptr, *sums = nullptr, *coef = nullptr, *lrsum = nullptr;
+    unsigned* ctr = nullptr;  // workgroup counter of k_reduce_lane, zero between launches
     double* xa = nullptr;  // per-lane step of the deferred x update
     CgLane* lanes = nullptr;
     int* done = nullptr;
@@ -671,6 +672,8 @@ void ensure_ws(ddlr_prec* h, int nrhs) {
     W.adm_maxit = W.mem.alloc<int32_t>(std::max(nrhs, 1));
     W.adm_tol2 = W.mem.alloc<double>(std::max(nrhs, 1));
     W.done = W.mem.alloc<int>(1);
+    W.ctr = W.mem.alloc<unsigned>(1);  // re-armed by k_reduce_lane
+    HIPCHK(hipMemset(W.ctr, 0, sizeof(unsigned)));
     HIPCHK(hipHostMalloc((void**)&W.done_host, sizeof(int)));
     W.nrhs = nrhs;
 }
@@ -1914,21 +1917,23 @@ static void lane_iteration(ddlr_prec* h, int nr, hipStream_t st) {
     Workspace& W = h->ws;
     const int64_t n = h->ndev;
     const int npart_spmv = (int)((n + 255) / 256);
+    // each dot product: partials, then one launch reducing them and updating the lanes
     spmv_il_dev(h, nr, W.p, W.q, n, W.part, st, W.done);
-    hipLaunchKernelGGL(k_reduce_cols, dim3(nr), dim3(256), 0, st, npart_spmv, nr, W.part, W.sums, W.done);
-    LAUNCHCHK();
-    hipLaunchKernelGGL(k_lane_scalar, dim3(1), dim3(64), 0, st, 2, nr, W.sums, W.lanes, W.done);
+    hipLaunchKernelGGL(k_reduce_lane, dim3(nr), dim3(256), 0, st, 2, npart_spmv, nr, W.part, W.sums, W.lanes, W.done,
+                       W.ctr);
     LAUNCHCHK();
     const bool split = h->x_st != nullptr;
     if (split) cg_split_dev(h, nr, st);  // x += alpha p overlaps the preconditioner
     else cg_xr_dev(h, nr, st);
-    hipLaunchKernelGGL(k_reduce_cols, dim3(nr), dim3(256), 0, st, kRedBlocks, nr, W.part, W.sums, W.done);
-    LAUNCHCHK();
-    hipLaunchKernelGGL(k_lane_scalar, dim3(1), dim3(64), 0, st, 3, nr, W.sums, W.lanes, W.done);
+    hipLaunchKernelGGL(k_reduce_lane, dim3(nr), dim3(256), 0, st, 3, kRedBlocks, nr, W.part, W.sums, W.lanes, W.done,
+                       W.ctr);
     LAUNCHCHK();
     apply_dev(h, nr, W.r, n, W.z, n, st, W.done);
-    dot_dev(h, nr, W.r, W.z, n, st, W.done);
-    hipLaunchKernelGGL(k_lane_scalar, dim3(1), dim3(64), 0, st, 4, nr, W.sums, W.lanes, W.done);
+    hipLaunchKernelGGL((k_dot<double, double>), dim3(kRedBlocks), dim3(256), 0, st, n, nr, W.r, n, W.z, n, W.part,
+                       W.done);
+    LAUNCHCHK();
+    hipLaunchKernelGGL(k_reduce_lane, dim3(nr), dim3(256), 0, st, 4, kRedBlocks, nr, W.part, W.sums, W.lanes, W.done,
+                       W.ctr);
     LAUNCHCHK();
     if (split) HIPCHK(hipStreamWaitEvent(st, h->ev_xj, 0));  // x used the old p
     const int S = lane_stride(nr);

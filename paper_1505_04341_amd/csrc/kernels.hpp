@@ -1153,6 +1153,33 @@ struct CgLane {
     int32_t active, its, phase, maxit;
 };
 
+// CG scalar update `what` of one lane from its reduced dot product s
+__device__ __forceinline__ void lane_update(int what, CgLane& l, double s) {
+    if (what == 2) {
+        l.alpha = l.phase == 2 ? l.rz / s : 0.0;
+    } else if (what == 3) {
+        if (l.phase == 1) {
+            l.bb = s;
+            l.rr = s;
+            if (!(s > 0.0)) { l.phase = 3; l.active = 0; }
+        } else if (l.phase == 2) {
+            l.rr = s;
+            l.its += 1;
+            if (s <= l.tol2 * l.bb || l.its >= l.maxit) { l.phase = 3; l.active = 0; }
+        }
+    } else if (what == 4) {
+        if (l.phase == 1) {
+            l.rz = s;
+            l.beta = 0.0;
+            l.phase = 2;
+            l.active = 1;
+        } else if (l.phase == 2) {
+            l.beta = s / l.rz;
+            l.rz = s;
+        }
+    }
+}
+
 // Lane-phase CG scalars (one thread per lane, blockDim >= nlanes); sums[r]
 // is the reduced dot product of lane r.  what: 2 alpha (p.Ap), 3 residual
 // check / initialisation of bb, 4 beta (r.z).  done := no lane initialising
@@ -1165,34 +1192,47 @@ __global__ void k_lane_scalar(int what, int nlanes, const double* __restrict__ s
     __syncthreads();
     for (int r = threadIdx.x; r < nlanes; r += blockDim.x) {
         CgLane& l = L[r];
-        const double s = sums[r];
-        if (what == 2) {
-            l.alpha = l.phase == 2 ? l.rz / s : 0.0;
-        } else if (what == 3) {
-            if (l.phase == 1) {
-                l.bb = s;
-                l.rr = s;
-                if (!(s > 0.0)) { l.phase = 3; l.active = 0; }
-            } else if (l.phase == 2) {
-                l.rr = s;
-                l.its += 1;
-                if (s <= l.tol2 * l.bb || l.its >= l.maxit) { l.phase = 3; l.active = 0; }
-            }
-        } else if (what == 4) {
-            if (l.phase == 1) {
-                l.rz = s;
-                l.beta = 0.0;
-                l.phase = 2;
-                l.active = 1;
-            } else if (l.phase == 2) {
-                l.beta = s / l.rz;
-                l.rz = s;
-            }
-        }
+        lane_update(what, l, sums[r]);
         if (l.phase == 1 || l.phase == 2) any = 1;  // benign race: every writer stores 1
     }
     __syncthreads();
     if (what == 3 && threadIdx.x == 0 && done) *done = any ? 0 : 1;
+}
+
+// k_reduce_cols and k_lane_scalar in one launch: workgroup r sums lane r's
+// partials (the order of k_reduce_cols, so the sum is bitwise the same) and
+// updates lane r.  The residual check (what == 3) also sets done := no lane
+// initialising or running: each workgroup counts itself on a device-scope
+// atomic after a release fence, and the one completing the count reads every
+// lane (acquire fence), stores done and re-arms the counter.  No workgroup
+// waits for another.  256 threads, one workgroup per lane.
+__global__ __launch_bounds__(256) void k_reduce_lane(int what, int nparts, int nlanes,
+                                                     const double* __restrict__ part, double* __restrict__ sums,
+                                                     CgLane* __restrict__ L, int* __restrict__ done,
+                                                     unsigned* __restrict__ ctr) {
+    __shared__ double sh[4];
+    __shared__ int is_last;
+    if (*done) return;
+    const int col = blockIdx.x;
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nparts; b += blockDim.x) acc += part[(int64_t)b * nlanes + col];
+    const double s = block_sum256(acc, sh);
+    if (threadIdx.x == 0) {
+        sums[col] = s;
+        lane_update(what, L[col], s);
+    }
+    if (what != 3) return;
+    if (threadIdx.x == 0) {
+        __threadfence();
+        is_last = atomicAdd(ctr, 1u) == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!is_last || threadIdx.x != 0) return;
+    __threadfence();
+    int any = 0;
+    for (int r = 0; r < nlanes; ++r) any |= (L[r].phase == 1 || L[r].phase == 2);
+    *done = any ? 0 : 1;
+    *ctr = 0u;
 }
 
 // Admission of lanes: lane r in [0, nlanes) with start[r] != 0 enters phase 1
