@@ -66,6 +66,9 @@ def _load():
         lib.orc_gmres.restype = C.c_int
         lib.orc_gmres.argtypes = [P, C.c_int, P, P, C.c_int, C.c_double, C.c_int, P, P]
         lib.orc_matvec.argtypes = [P, P, P]
+        lib.orc_use_cinv.restype = C.c_int
+        lib.orc_use_cinv.argtypes = [P, C.c_int, C.c_double, C.c_int]
+        lib.orc_cinv.argtypes = [P, P, P, P, P]
         lib.orc_threads.restype = C.c_int
         lib.orc_threads.argtypes = []
         _lib = lib
@@ -151,6 +154,29 @@ class Oracle:
         D = np.zeros(self.n)
         _lib.orc_diag(self._h, _p(D))
         return D
+
+    def use_cinv(self, nit=3, tol=0.01, lfil=20):
+        """Solve C_alpha with the MR approximate inverse (Algorithm alg:mr,
+        X_0 = diag(C_alpha)^{-1}, nit steps, dual-threshold dropping tol /
+        lfil). Call before lowrank."""
+        st = _lib.orc_use_cinv(self._h, int(nit), float(tol), int(lfil))
+        if st != OK:
+            raise OracleError(st, "cinv")
+        return self
+
+    def cinv(self):
+        """(X: scipy CSR s x s in interface order, residual norms
+        ||I - C_alpha X_j||_F for j = 0..steps, SPD certificate ||I - C_alpha X||_F < 1)."""
+        import scipy.sparse as sp
+        nnz = int(_lib.orc_size(self._h, 11))
+        steps = int(_lib.orc_size(self._h, 12))
+        rp = np.zeros(self.s + 1, np.int64)
+        ci = np.zeros(max(nnz, 1), np.int32)
+        v = np.zeros(max(nnz, 1))
+        res = np.zeros(steps + 1)
+        _lib.orc_cinv(self._h, _p(rp), _p(ci), _p(v), _p(res))
+        X = sp.csr_matrix((v[:nnz], ci[:nnz], rp), shape=(self.s, self.s))
+        return X, res, bool(_lib.orc_size(self._h, 13))
 
     # ---- operators (user order, columns of an (n, nrhs) array)
     @staticmethod

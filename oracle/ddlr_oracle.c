@@ -19,7 +19,10 @@
  *     Ehat Ehat^T),
  *   - local solvers: incomplete LDL^T with the matrix's own pattern, one per
  *     B_{i,alpha} and one for C_alpha (Sec. 5: "incomplete Cholesky or LDL"),
- *     or exact dense LDL^T per block for the identity tests,
+ *     or exact dense LDL^T per block for the identity tests; alternatively
+ *     C_alpha is solved by a sparse approximate inverse X built with the
+ *     self-preconditioned global MR iteration with dropping (Sec. 4.4,
+ *     Algorithm alg:mr), applied as a product with X,
  *   - Lanczos on E^T A0^{-1} E (DDLR-1) or E^T A0^{-2} E (DDLR-2) with full
  *     reorthogonalisation (Sec. 4.3), Ritz pairs of T_m by cyclic Jacobi,
  *   - G_{k,theta}^{-1} of eq. (gkt) with theta = lambda_{k+1}, applied through
@@ -101,6 +104,12 @@ typedef struct {
     int lvariant;     /* operator of the stored run (1 or 2), 0 if none */
     int broke;        /* the stored run ended in an invariant subspace */
     double amax;      /* max |alpha_i| so far */
+    /* C_alpha approximate inverse (csolve = 1) */
+    int csolve;       /* 0: factor of C_alpha, 1: X ~ C_alpha^{-1} */
+    csr_t X;          /* s x s, symmetric, interface indices */
+    int x_iters;      /* MR steps taken */
+    double *x_res;    /* ||I - C X_j||_F for j = 0..x_iters */
+    int x_spd;        /* 1 if ||I - C X||_F < 1: then C^{1/2} X C^{1/2} has its eigenvalues in (0, 2), so X is SPD */
 } orc_t;
 
 static void *xcalloc(size_t n, size_t sz) {
@@ -428,11 +437,16 @@ static int build_factor(orc_t *o) {
 }
 
 /* z = A0^{-1} x (internal order) with the local factors: per block
- * L y = x (unit lower), w = D^{-1} y, L^T z = w.  Blocks are independent. */
+ * L y = x (unit lower), w = D^{-1} y, L^T z = w; with csolve the interface
+ * block instead takes z_C = X x_C.  Blocks are independent. */
 static void a0_solve(const orc_t *o, const double *x, double *z) {
 #pragma omp parallel for schedule(dynamic, 1)
     for (int b = 0; b <= o->p; ++b) {
         int64_t lo = o->boff[b], hi = o->boff[b + 1];
+        if (b == o->p && o->csolve) {  /* z_C = X x_C */
+            csr_mv(&o->X, o->s, x + lo, z + lo);
+            continue;
+        }
         for (int64_t i = lo; i < hi; ++i) {
             double s = x[i];
             for (int64_t t = o->L.rp[i]; t < o->L.rp[i + 1]; ++t) s -= o->L.v[t] * z[o->L.ci[t]];
@@ -444,6 +458,275 @@ static void a0_solve(const orc_t *o, const double *x, double *z) {
             for (int64_t t = o->L.rp[i]; t < o->L.rp[i + 1]; ++t) z[o->L.ci[t]] -= o->L.v[t] * zi;
         }
     }
+}
+
+/* --------------------------------------- C_alpha approximate inverse (Sec. 4.4)
+ *
+ * X ~ C_alpha^{-1} by the self-preconditioned global minimal residual
+ * iteration with numerical dropping (Algorithm alg:mr), X_0 = diag(C_alpha)^{-1}:
+ *   R = I - C X;  Z = X R;  drop in Z;  beta = tr(R^T C Z) / ||C Z||_F^2;
+ *   X = X + beta Z.
+ * The paper does not state the dropping constants; the reading used here:
+ *   - Z is symmetrised, z_ij := (z_ij + z_ji) / 2 (X R is symmetric in exact
+ *     arithmetic when X is), so that X stays symmetric for CG;
+ *   - dual threshold per column j: off-diagonal entries with
+ *     |z_ij| < tol * ||z_:j||_2 are dropped, of the others the lfil largest in
+ *     magnitude are kept (ties: lower row first); the diagonal is always kept;
+ *     an entry survives only if it survives in its column and in its row's
+ *     column (symmetric pattern);
+ *   - the loop stops early if C Z = 0.
+ * Arithmetic order (fixed so that any implementation can reproduce X
+ * exactly): every entry of a sparse product sum_k a_ik b_kj is accumulated
+ * from 0.0 by adding the terms in ascending k; tr(R^T W) and ||W||_F^2
+ * (W = C Z) are single running sums over the stored entries of W in row-major
+ * order with ascending columns; ||z_:j||^2 runs over column j in ascending
+ * row order.  Matrices are CSR with ascending columns; symmetric ones serve
+ * as their own CSC. */
+
+/* c = a b (Gustavson, rows of a times rows of b) */
+static void sp_mul(const csr_t *a, const csr_t *b, int64_t nrows, int64_t ncols, csr_t *c) {
+    double *acc = xcalloc(ncols, sizeof(double));
+    char *mark = xcalloc(ncols, 1);
+    int32_t *list = xcalloc(ncols, sizeof(int32_t));
+    int64_t cap = a->rp[nrows] + 16, used = 0;
+    c->rp = xcalloc(nrows + 1, sizeof(int64_t));
+    c->ci = xcalloc(cap, sizeof(int32_t));
+    c->v = xcalloc(cap, sizeof(double));
+    for (int64_t i = 0; i < nrows; ++i) {
+        int64_t cnt = 0;
+        for (int64_t t = a->rp[i]; t < a->rp[i + 1]; ++t) {
+            const int32_t k = a->ci[t];
+            const double aik = a->v[t];
+            for (int64_t t2 = b->rp[k]; t2 < b->rp[k + 1]; ++t2) {
+                const int32_t j = b->ci[t2];
+                if (!mark[j]) { mark[j] = 1; acc[j] = 0.0; list[cnt++] = j; }
+                acc[j] += aik * b->v[t2];
+            }
+        }
+        if (used + cnt > cap) {
+            cap = 2 * (used + cnt);
+            c->ci = realloc(c->ci, cap * sizeof(int32_t));
+            c->v = realloc(c->v, cap * sizeof(double));
+        }
+        ent_t *row = xcalloc(cnt > 0 ? cnt : 1, sizeof(ent_t));
+        for (int64_t q = 0; q < cnt; ++q) { row[q].c = list[q]; row[q].v = acc[list[q]]; mark[list[q]] = 0; }
+        qsort(row, cnt, sizeof(ent_t), ent_cmp);
+        for (int64_t q = 0; q < cnt; ++q) { c->ci[used + q] = row[q].c; c->v[used + q] = row[q].v; }
+        free(row);
+        used += cnt;
+        c->rp[i + 1] = used;
+    }
+    free(acc); free(mark); free(list);
+}
+
+/* value of entry (i, j) of a, 0 if not stored */
+static double sp_get(const csr_t *a, int64_t i, int32_t j) {
+    int64_t lo = a->rp[i], hi = a->rp[i + 1] - 1;
+    while (lo <= hi) {
+        int64_t mid = (lo + hi) / 2;
+        if (a->ci[mid] == j) return a->v[mid];
+        if (a->ci[mid] < j) lo = mid + 1; else hi = mid - 1;
+    }
+    return 0.0;
+}
+
+static double frob(const csr_t *a, int64_t nrows) {
+    double t = 0.0;
+    for (int64_t q = 0; q < a->rp[nrows]; ++q) t += a->v[q] * a->v[q];
+    return sqrt(t);
+}
+
+typedef struct { int32_t i; double a; } cand_t;
+
+static int cand_cmp(const void *x, const void *y) {
+    const cand_t *p = x, *q = y;
+    if (p->a != q->a) return p->a < q->a ? 1 : -1;  /* larger magnitude first */
+    return (p->i > q->i) - (p->i < q->i);
+}
+
+/* R = I - W (W = C X) */
+static void sp_i_minus(const csr_t *w, int64_t s, csr_t *r) {
+    r->rp = xcalloc(s + 1, sizeof(int64_t));
+    r->ci = xcalloc(w->rp[s] + s, sizeof(int32_t));
+    r->v = xcalloc(w->rp[s] + s, sizeof(double));
+    int64_t used = 0;
+    for (int64_t i = 0; i < s; ++i) {
+        int diag = 0;
+        for (int64_t t = w->rp[i]; t < w->rp[i + 1]; ++t) {
+            const int32_t j = w->ci[t];
+            if (!diag && j > i) { r->ci[used] = (int32_t)i; r->v[used++] = 1.0; diag = 1; }
+            if (j == i) { r->ci[used] = j; r->v[used++] = 1.0 - w->v[t]; diag = 1; }
+            else { r->ci[used] = j; r->v[used++] = -w->v[t]; }
+        }
+        if (!diag) { r->ci[used] = (int32_t)i; r->v[used++] = 1.0; }
+        r->rp[i + 1] = used;
+    }
+}
+
+/* Builds X (Algorithm alg:mr) from C_alpha = A0[m:n, m:n]. */
+static int build_cinv(orc_t *o, int nit, double tol, int lfil) {
+    const int64_t s = o->s, m = o->m;
+    csr_t C = {0}, X = {0};
+    /* C_alpha with interface indices */
+    C.rp = xcalloc(s + 1, sizeof(int64_t));
+    int64_t cnt = 0;
+    for (int64_t y = 0; y < s; ++y)
+        for (int64_t t = o->A0.rp[m + y]; t < o->A0.rp[m + y + 1]; ++t) ++cnt;
+    C.ci = xcalloc(cnt > 0 ? cnt : 1, sizeof(int32_t));
+    C.v = xcalloc(cnt > 0 ? cnt : 1, sizeof(double));
+    cnt = 0;
+    for (int64_t y = 0; y < s; ++y) {
+        for (int64_t t = o->A0.rp[m + y]; t < o->A0.rp[m + y + 1]; ++t) {
+            C.ci[cnt] = (int32_t)(o->A0.ci[t] - m);
+            C.v[cnt++] = o->A0.v[t];
+        }
+        C.rp[y + 1] = cnt;
+    }
+    /* X_0 = diag(C)^{-1} */
+    X.rp = xcalloc(s + 1, sizeof(int64_t));
+    X.ci = xcalloc(s > 0 ? s : 1, sizeof(int32_t));
+    X.v = xcalloc(s > 0 ? s : 1, sizeof(double));
+    for (int64_t y = 0; y < s; ++y) {
+        const double d = sp_get(&C, y, (int32_t)y);
+        if (!(d > 0.0)) { csr_free(&C); csr_free(&X); return ORC_E_BREAKDOWN; }
+        X.ci[y] = (int32_t)y;
+        X.v[y] = 1.0 / d;
+        X.rp[y + 1] = y + 1;
+    }
+    free(o->x_res);
+    o->x_res = xcalloc(nit + 1, sizeof(double));
+    o->x_iters = 0;
+    for (int it = 0; it <= nit; ++it) {
+        csr_t W = {0}, R = {0};
+        sp_mul(&C, &X, s, s, &W);
+        sp_i_minus(&W, s, &R);
+        csr_free(&W);
+        o->x_res[it] = frob(&R, s);
+        if (it == nit) { csr_free(&R); break; }
+        /* Z = X R, symmetrised */
+        csr_t Zh = {0};
+        sp_mul(&X, &R, s, s, &Zh);
+        csr_t Z = {0};
+        Z.rp = xcalloc(s + 1, sizeof(int64_t));
+        /* pattern of Zh + Zh^T: union of row i of Zh and column i of Zh */
+        csr_t Zt = {0};
+        {
+            Zt.rp = xcalloc(s + 1, sizeof(int64_t));
+            Zt.ci = xcalloc(Zh.rp[s] > 0 ? Zh.rp[s] : 1, sizeof(int32_t));
+            Zt.v = xcalloc(Zh.rp[s] > 0 ? Zh.rp[s] : 1, sizeof(double));
+            for (int64_t q = 0; q < Zh.rp[s]; ++q) Zt.rp[Zh.ci[q] + 1]++;
+            for (int64_t y = 0; y < s; ++y) Zt.rp[y + 1] += Zt.rp[y];
+            int64_t *fill = xcalloc(s > 0 ? s : 1, sizeof(int64_t));
+            for (int64_t i = 0; i < s; ++i)
+                for (int64_t t = Zh.rp[i]; t < Zh.rp[i + 1]; ++t) {
+                    const int32_t j = Zh.ci[t];
+                    const int64_t q = Zt.rp[j] + fill[j]++;
+                    Zt.ci[q] = (int32_t)i;
+                    Zt.v[q] = Zh.v[t];
+                }
+            free(fill);
+        }
+        int64_t cap = 2 * Zh.rp[s] + 1, used = 0;
+        Z.ci = xcalloc(cap, sizeof(int32_t));
+        Z.v = xcalloc(cap, sizeof(double));
+        for (int64_t i = 0; i < s; ++i) {
+            int64_t a = Zh.rp[i], ae = Zh.rp[i + 1], b = Zt.rp[i], be = Zt.rp[i + 1];
+            while (a < ae || b < be) {
+                int32_t j;
+                double u = 0.0, w = 0.0;
+                if (b >= be || (a < ae && Zh.ci[a] < Zt.ci[b])) { j = Zh.ci[a]; u = Zh.v[a++]; }
+                else if (a >= ae || Zt.ci[b] < Zh.ci[a]) { j = Zt.ci[b]; w = Zt.v[b++]; }
+                else { j = Zh.ci[a]; u = Zh.v[a++]; w = Zt.v[b++]; }
+                Z.ci[used] = j;
+                Z.v[used++] = 0.5 * (u + w);
+            }
+            Z.rp[i + 1] = used;
+        }
+        csr_free(&Zh); csr_free(&Zt);
+        /* dual-threshold choice per column (= row, Z symmetric) */
+        char *keep = xcalloc(Z.rp[s] > 0 ? Z.rp[s] : 1, 1);
+        cand_t *cd = xcalloc(s > 0 ? s : 1, sizeof(cand_t));
+        for (int64_t j = 0; j < s; ++j) {
+            double nn = 0.0;
+            for (int64_t t = Z.rp[j]; t < Z.rp[j + 1]; ++t) nn += Z.v[t] * Z.v[t];
+            const double thr = tol * sqrt(nn);
+            int64_t nc = 0;
+            for (int64_t t = Z.rp[j]; t < Z.rp[j + 1]; ++t) {
+                if (Z.ci[t] == j) { keep[t] = 1; continue; }
+                if (fabs(Z.v[t]) < thr) continue;
+                cd[nc].i = (int32_t)t;  /* position; ties broken by row = ascending position */
+                cd[nc].a = fabs(Z.v[t]);
+                ++nc;
+            }
+            qsort(cd, nc, sizeof(cand_t), cand_cmp);
+            for (int64_t q = 0; q < nc && q < lfil; ++q) keep[cd[q].i] = 1;
+        }
+        free(cd);
+        /* symmetric survivors: (i,j) kept in column j and (j,i) kept in column i */
+        csr_t Zd = {0};
+        Zd.rp = xcalloc(s + 1, sizeof(int64_t));
+        Zd.ci = xcalloc(Z.rp[s] > 0 ? Z.rp[s] : 1, sizeof(int32_t));
+        Zd.v = xcalloc(Z.rp[s] > 0 ? Z.rp[s] : 1, sizeof(double));
+        used = 0;
+        for (int64_t i = 0; i < s; ++i) {
+            for (int64_t t = Z.rp[i]; t < Z.rp[i + 1]; ++t) {
+                const int32_t j = Z.ci[t];
+                if (!keep[t]) continue;
+                /* position of (j, i) */
+                int64_t lo = Z.rp[j], hi = Z.rp[j + 1] - 1, hit = -1;
+                while (lo <= hi) {
+                    int64_t mid = (lo + hi) / 2;
+                    if (Z.ci[mid] == i) { hit = mid; break; }
+                    if (Z.ci[mid] < i) lo = mid + 1; else hi = mid - 1;
+                }
+                if (hit < 0 || !keep[hit]) continue;
+                Zd.ci[used] = j;
+                Zd.v[used++] = Z.v[t];
+            }
+            Zd.rp[i + 1] = used;
+        }
+        free(keep);
+        csr_free(&Z);
+        /* beta = tr(R^T C Z) / ||C Z||_F^2 */
+        csr_t CZ = {0};
+        sp_mul(&C, &Zd, s, s, &CZ);
+        double num = 0.0, den = 0.0;
+        for (int64_t i = 0; i < s; ++i)
+            for (int64_t t = CZ.rp[i]; t < CZ.rp[i + 1]; ++t) {
+                const double w = CZ.v[t];
+                num += sp_get(&R, i, CZ.ci[t]) * w;
+                den += w * w;
+            }
+        csr_free(&CZ); csr_free(&R);
+        if (!(den > 0.0)) { csr_free(&Zd); break; }
+        const double beta = num / den;
+        /* X = X + beta Z (pattern union) */
+        csr_t Xn = {0};
+        Xn.rp = xcalloc(s + 1, sizeof(int64_t));
+        Xn.ci = xcalloc(X.rp[s] + Zd.rp[s] + 1, sizeof(int32_t));
+        Xn.v = xcalloc(X.rp[s] + Zd.rp[s] + 1, sizeof(double));
+        used = 0;
+        for (int64_t i = 0; i < s; ++i) {
+            int64_t a = X.rp[i], ae = X.rp[i + 1], b = Zd.rp[i], be = Zd.rp[i + 1];
+            while (a < ae || b < be) {
+                if (b >= be || (a < ae && X.ci[a] < Zd.ci[b])) { Xn.ci[used] = X.ci[a]; Xn.v[used++] = X.v[a++]; }
+                else if (a >= ae || Zd.ci[b] < X.ci[a]) { Xn.ci[used] = Zd.ci[b]; Xn.v[used++] = beta * Zd.v[b++]; }
+                else { Xn.ci[used] = X.ci[a]; Xn.v[used++] = X.v[a++] + beta * Zd.v[b++]; }
+            }
+            Xn.rp[i + 1] = used;
+        }
+        csr_free(&Zd); csr_free(&X);
+        X = Xn;
+        o->x_iters = it + 1;
+    }
+    csr_free(&C);
+    /* SPD certificate: I - C X is similar to I - C^{1/2} X C^{1/2}, whose
+     * spectral radius is at most ||I - C X||_F */
+    o->x_spd = o->x_res[o->x_iters] < 1.0;
+    csr_free(&o->X);
+    o->X = X;
+    o->csolve = 1;
+    return ORC_OK;
 }
 
 /* ---------------------------------------------------------- E and E^T products */
@@ -665,9 +948,10 @@ static int dense_chol(int k, double *a) {
 /* The SPD results (Propositions on SPD-ness of DDLR-1 and DDLR-2) assume A0
  * SPD; with an indefinite local factor the preconditioner is not SPD. */
 static int pivots_positive(const orc_t *o) {
-    for (int64_t i = 0; i < o->n; ++i)
+    const int64_t last = o->csolve ? o->m : o->n;
+    for (int64_t i = 0; i < last; ++i)
         if (!(o->D[i] > 0.0)) return 0;
-    return 1;
+    return o->csolve ? o->x_spd : 1;
 }
 
 /* Low-rank part of the preconditioner from the Lanczos run (Sec. 3.2 / 3.3). */
@@ -806,6 +1090,7 @@ void orc_free(orc_t *o) {
     free(o->part); free(o->iface); free(o->perm); free(o->iperm); free(o->colour); free(o->boff);
     free(o->D); free(o->U); free(o->lam); free(o->dvec); free(o->Hk);
     free(o->ta); free(o->tb); free(o->ritz); free(o->Q);
+    csr_free(&o->X); free(o->x_res);
     free(o);
 }
 
@@ -857,6 +1142,9 @@ int64_t orc_size(const orc_t *o, int what) {
     case 8: return o->breakdown_row;
     case 9: return o->k;
     case 10: return o->spd;
+    case 11: return o->csolve ? o->X.rp[o->s] : 0;
+    case 12: return o->x_iters;
+    case 13: return o->x_spd;
     default: return -1;
     }
 }
@@ -877,6 +1165,27 @@ void orc_csr(const orc_t *o, int which, int64_t *rp, int32_t *ci, double *v) {
 }
 
 void orc_diag(const orc_t *o, double *D) { memcpy(D, o->D, o->n * sizeof(double)); }
+
+/* Switches the C_alpha solve to the MR approximate inverse (nit steps, drop
+ * tolerance tol, at most lfil kept off-diagonal entries per column); a
+ * breakdown of the C_alpha factor no longer matters.  Call before the
+ * low-rank build. */
+int orc_use_cinv(orc_t *o, int nit, double tol, int lfil) {
+    if (nit < 0 || !(tol >= 0.0) || lfil < 0 || o->s < 1) return ORC_E_INVALID;
+    if (o->breakdown_row >= 0 && o->breakdown_row < o->m) return ORC_E_BREAKDOWN;
+    const int st = build_cinv(o, nit, tol, lfil);
+    if (st == ORC_OK && o->breakdown_row >= o->m) o->breakdown_row = -1;
+    return st;
+}
+
+/* X (s x s CSR, interface indices), nnz via orc_size(o, 11); res: the
+ * residual norms ||I - C X_j||_F, j = 0..x_iters (orc_size(o, 12)) */
+void orc_cinv(const orc_t *o, int64_t *rp, int32_t *ci, double *v, double *res) {
+    memcpy(rp, o->X.rp, (o->s + 1) * sizeof(int64_t));
+    memcpy(ci, o->X.ci, o->X.rp[o->s] * sizeof(int32_t));
+    memcpy(v, o->X.v, o->X.rp[o->s] * sizeof(double));
+    memcpy(res, o->x_res, (o->x_iters + 1) * sizeof(double));
+}
 
 /* z = A0^{-1} x, user order, nrhs columns with leading dimension n */
 void orc_a0_solve(const orc_t *o, int nrhs, const double *x, double *z) {

@@ -635,3 +635,123 @@ def test_partition_sizes_and_components():
     B = w._from_triplets(8, np.array([0, 1, 1, 2, 4, 5, 5, 6, 6, 7] + list(range(8))),
                          np.array([1, 0, 2, 1, 5, 4, 6, 5, 7, 6] + list(range(8))), np.ones(18))
     assert partition_graph(B, 2).tolist() == [0, 0, 0, 0, 1, 1, 1, 1]
+
+
+# ------------------------------------- C_alpha approximate inverse (Sec. 4.4)
+
+def _c_alpha(o):
+    """C_alpha = A0[m:, m:] (dense), interface order."""
+    return o.csr("A0").toarray()[o.m:, o.m:]
+
+
+def _ring_matrix():
+    """Six unknowns, two parts: interior 0 and 5, interface 1, 2 (part 0) and
+    3, 4 (part 1).  The interface unknowns form the cycle 1-2-4-3-1 with -1
+    couplings and a_ii = 3, so C_alpha (alpha = 1) has diagonal 4."""
+    edges = [(0, 1), (0, 2), (1, 2), (2, 4), (4, 3), (3, 1), (5, 3), (5, 4)]
+    n = 6
+    rows = [i for i in range(n)] + [a for a, b in edges] + [b for a, b in edges]
+    cols = [i for i in range(n)] + [b for a, b in edges] + [a for a, b in edges]
+    vals = [3.0] * n + [-1.0] * (2 * len(edges))
+    A = w._from_triplets(n, np.array(rows), np.array(cols), np.array(vals))
+    part = np.array([0, 0, 0, 1, 1, 1], np.int32)
+    return A, part
+
+
+def test_cinv_one_step_by_hand():
+    """Worked by hand from Algorithm alg:mr with the stated dropping rule.
+    X_0 = I/4, R_0 = I - C/4 (0.25 on the cycle edges), Z_0 = X_0 R_0 (1/16 on
+    the edges), ||z_j|| = sqrt(2)/16.  tol = 0.5 keeps both neighbours of each
+    column; lfil = 1 keeps the lower row on the tie: columns keep rows
+    (1, 0, 0, 1) for interface positions (0..3) = unknowns (1, 2, 3, 4);
+    only the pair {0, 1} survives in both its columns.  Then
+    tr(R_0^T C Z) = 1/8, ||C Z||_F^2 = 9/64, beta = 8/9, and
+    X_1 = I/4 + (1/18)(e_0 e_1^T + e_1 e_0^T)."""
+    A, part = _ring_matrix()
+    o = Oracle(A, part, 2, corder=CORDER_NATURAL)
+    C = _c_alpha(o)
+    assert np.allclose(np.diag(C), 4.0)
+    o.use_cinv(nit=1, tol=0.5, lfil=1)
+    X, res, spd = o.cinv()
+    Xe = np.eye(4) / 4
+    Xe[0, 1] = Xe[1, 0] = 1.0 / 18.0
+    assert np.abs(X.toarray() - Xe).max() < 1e-16
+    assert abs(res[0] - np.sqrt(0.5)) < 1e-15
+    assert abs(res[1] - np.linalg.norm(np.eye(4) - C @ Xe)) < 1e-14
+    assert spd
+    # a tolerance above 1/16 / (sqrt(2)/16) drops every off-diagonal entry: Z = 0, X stays X_0
+    o2 = Oracle(A, part, 2, corder=CORDER_NATURAL).use_cinv(nit=3, tol=0.8, lfil=4)
+    X2, res2, _ = o2.cinv()
+    assert np.array_equal(X2.toarray(), np.eye(4) / 4) and len(res2) == 1
+
+
+def test_cinv_without_dropping_converges_to_inverse():
+    """No dropping: the self-preconditioned MR iterates converge to C_alpha^{-1}
+    (checked against LAPACK's inverse) with a non-increasing residual."""
+    cfg = w.config("c1")
+    o = Oracle(cfg["A"], cfg["part"], cfg["p"]).use_cinv(nit=8, tol=0.0, lfil=10 ** 6)
+    X, res, spd = o.cinv()
+    Ci = np.linalg.inv(_c_alpha(o))
+    assert np.linalg.norm(X.toarray() - Ci) / np.linalg.norm(Ci) < 1e-12
+    assert np.all(np.diff(res) <= 1e-15 * res[0]) and res[-1] < 1e-12 and spd
+    assert abs(res[0] - np.linalg.norm(np.eye(o.s) - _c_alpha(o) / np.diag(_c_alpha(o))[None, :])) < 1e-12
+
+
+@pytest.mark.parametrize("nit,tol,lfil", [(3, 0.01, 20), (4, 0.05, 6)])
+def test_cinv_dropping_properties(nit, tol, lfil):
+    """With dropping: X exactly symmetric; each step adds a symmetric pattern
+    with at most lfil off-diagonal entries per column; the residual
+    ||I - C X_j||_F never increases (beta is the minimiser over the step)."""
+    cfg = w.config("c1")
+    C = None
+    prev = None
+    for j in range(nit + 1):
+        o = Oracle(cfg["A"], cfg["part"], cfg["p"]).use_cinv(nit=j, tol=tol, lfil=lfil)
+        X, res, spd = o.cinv()
+        if C is None:
+            C = _c_alpha(o)
+        Xd = X.toarray()
+        assert np.array_equal(Xd, Xd.T)
+        assert abs(res[-1] - np.linalg.norm(np.eye(o.s) - C @ Xd)) < 1e-12 * max(1.0, res[-1])
+        if prev is not None:
+            D = Xd - prev
+            pat = D != 0
+            np.fill_diagonal(pat, False)
+            assert np.array_equal(pat, pat.T)
+            assert pat.sum(axis=0).max() <= lfil
+            assert res[-1] <= res[-2] * (1 + 1e-14)
+        prev = Xd
+
+
+def test_cinv_step_is_minimal_residual():
+    """beta minimises ||R - beta C Z||_F: the new residual is orthogonal (in
+    the trace inner product) to C (X_{j+1} - X_j).  X_j is the j-step result
+    (the iteration is deterministic, so shorter runs are prefixes)."""
+    cfg = w.config("c1")
+    o1 = Oracle(cfg["A"], cfg["part"], cfg["p"]).use_cinv(nit=1, tol=0.01, lfil=12)
+    o2 = Oracle(cfg["A"], cfg["part"], cfg["p"]).use_cinv(nit=2, tol=0.01, lfil=12)
+    C = _c_alpha(o1)
+    X1, X2 = o1.cinv()[0].toarray(), o2.cinv()[0].toarray()
+    R2 = np.eye(o1.s) - C @ X2
+    CD = C @ (X2 - X1)
+    assert abs(np.sum(R2 * CD)) < 1e-12 * np.linalg.norm(R2) * np.linalg.norm(CD)
+
+
+def test_cinv_preconditioner_end_to_end():
+    """DDLR-1 with the approximate inverse for C_alpha: certified SPD, CG on C1
+    converges to the direct solution."""
+    cfg = w.config("c1")
+    A = cfg["A"]
+    o = Oracle(A, cfg["part"], cfg["p"]).use_cinv(nit=3, tol=0.01, lfil=20)
+    o.lowrank(1, cfg["k"], cfg["m"], w.lanczos_start(A.n, 0))
+    assert o.spd
+    b, xs = w.rhs_from_solution(A, 0, 2)
+    x, info = o.pcg(b)
+    assert info["status"] == 0 and np.all(info["relres_true"] <= 1.01e-6)
+    xd = spla.spsolve(A.to_scipy().tocsc(), b)
+    assert np.linalg.norm(x - xd) <= 1e-3 * np.linalg.norm(xd)
+    # the factor path on the same problem, for scale: both preconditioners work
+    of = Oracle(A, cfg["part"], cfg["p"])
+    of.lowrank(1, cfg["k"], cfg["m"], w.lanczos_start(A.n, 0))
+    _, infof = of.pcg(b)
+    assert infof["status"] == 0 and abs(int(info["its"][0]) - int(infof["its"][0])) <= 20
