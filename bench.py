@@ -165,6 +165,13 @@ def unstructured_config(D, w):
     return dict(A=A, part=part, p=64, k=32, m=64, nrhs=8, variant=1, method="cg")
 
 
+def alpha_for(args):
+    """u1 with the approximate inverse of C_alpha takes alpha = 2 (the paper's
+    choice for some of its general matrices): at alpha = 1 the interface block
+    is too weakly dominant for 3 MR steps to give ||I - C_alpha X||_inf < 1."""
+    return 2.0 if args.config == "u1" and args.csolve == "mr" else 1.0
+
+
 def run_single(args, D, w, torch):
     cfg = unstructured_config(D, w) if args.config == "u1" else w.config(args.config)
     A = cfg["A"]
@@ -182,7 +189,8 @@ def run_single(args, D, w, torch):
         log("setup", name)
         t0 = time.perf_counter()
         h = D.ddlr_setup(A, cfg["part"], p, k, args.variant, lanczos_steps=m, lanczos_start=v0, precision=prec,
-                         factor=factor)
+                         factor=factor, csolve=D.CSOLVE_MR if args.csolve == "mr" else D.CSOLVE_FACTOR,
+                         alpha=alpha_for(args))
         torch.cuda.synchronize()
         setup_s = time.perf_counter() - t0
         q = D.ddlr_query(h)
@@ -203,7 +211,8 @@ def run_single(args, D, w, torch):
     roof["traffic"] = traffic
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(cfg, b, v0, args.variant, mixed["x"], f64["x"], gm, args.cpu_rhs)
+        cpu = cpu_baseline(cfg, b, v0, args.variant, mixed["x"], f64["x"], gm, args.cpu_rhs, args.csolve == "mr",
+                           alpha_for(args))
     workload = {
         "c1": "5-point Laplacian 64^2, 2x2 boxes",
         "c2": "7-point Laplacian 128^3, 4x4x4 boxes",
@@ -225,8 +234,10 @@ def run_single(args, D, w, torch):
         "dtype": "f32 preconditioner" + (" + bf16 U_k" if gm else "") + " / f64 " + krylov,
         "data": "synthetic",
         "config": {"workload": f"{args.config}: {workload}, DDLR-{args.variant} k={k}, {m} Lanczos steps, "
-                               f"{nrhs} rhs per solve batch, {krylov} to 1e-6",
-                   "n": n, "nrhs": nrhs, "k": k, "p": p, "variant": args.variant},
+                               f"{nrhs} rhs per solve batch, {krylov} to 1e-6"
+                               + (", C_alpha by the MR approximate inverse" if args.csolve == "mr" else "")
+                               + (f", alpha={alpha_for(args):g}" if alpha_for(args) != 1.0 else ""),
+                   "n": n, "nrhs": nrhs, "k": k, "p": p, "variant": args.variant, "csolve": args.csolve},
         "latency_ms": {"p50": pct(mixed["lat"], 50), "p99": pct(mixed["lat"], 99),
                        "note": f"per solve call; the {nrhs} right-hand sides of a batch complete together"},
         "fp64": {"value": round(solves / f64["total"], 3), "ms_per_step": round(1e3 * f64["total"] / K, 3),
@@ -245,14 +256,17 @@ def run_single(args, D, w, torch):
     return out
 
 
-def cpu_baseline(cfg, b, v0, variant, x_mixed, x_f64, gm, ncols):
+def cpu_baseline(cfg, b, v0, variant, x_mixed, x_f64, gm, ncols, cinv=False, alpha=1.0):
     """The oracle (plain C, FP64, OpenMP over blocks/rows) on the host cores:
     full solves of the first `ncols` right-hand sides of the same workload.
     Also states the GPU results' distance to the oracle's on those columns."""
     import oracle
     threads = oracle.threads()
     log("cpu baseline: oracle setup", threads, "threads")
-    o = oracle.Oracle(cfg["A"], cfg["part"], cfg["p"], factor=oracle.FACTOR_ILDL if gm else oracle.FACTOR_IC)
+    o = oracle.Oracle(cfg["A"], cfg["part"], cfg["p"], alpha=alpha,
+                      factor=oracle.FACTOR_ILDL if gm else oracle.FACTOR_IC)
+    if cinv:
+        o.use_cinv(3, 0.01, 20)
     o.lowrank(variant, cfg["k"], cfg["m"], v0)
     ncols = min(ncols, b.shape[1])
     t0 = time.perf_counter()
@@ -422,6 +436,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "u1"])
     ap.add_argument("--variant", type=int, default=1)
+    ap.add_argument("--csolve", default="factor", choices=["factor", "mr"],
+                    help="C_alpha solver: its incomplete factor, or the MR approximate inverse (3 steps, "
+                         "drop tolerance 0.01, 20 entries per column)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-rhs", type=int, default=3, help="right-hand sides the oracle solves for the baseline")
     ap.add_argument("--copy-calibration", action="store_true",

@@ -58,6 +58,19 @@ typedef enum {
 typedef enum { DDLR_THETA_LAMBDA_K1 = 0, DDLR_THETA_ZERO = 1 } ddlr_theta;
 typedef enum { DDLR_FACTOR_IC0 = 0, DDLR_FACTOR_ILDL0 = 1 } ddlr_factor;
 typedef enum { DDLR_CORDER_MULTICOLOR = 0, DDLR_CORDER_NATURAL = 1 } ddlr_corder;
+/* Solver of C_alpha inside every A0 solve (Sec. 4.4): its incomplete LDL^T
+ * like the B blocks, or the sparse approximate inverse X of Algorithm alg:mr
+ * (self-preconditioned global MR with dropping, X_0 = diag(C_alpha)^{-1}),
+ * applied as one sparse product.  X's dropping rule (the paper gives no
+ * details or values): Z is symmetrised; in each column the diagonal stays,
+ * off-diagonal entries below cinv_tol * ||z_:j||_2 are dropped and the
+ * cinv_lfil largest of the rest kept (ties: lower row); an entry stays only if
+ * it stays in its column and its row's column, so X is symmetric.  Sums follow
+ * a fixed order (each product entry from 0.0 in ascending summation index;
+ * traces and norms as running sums in row-major order), so the result is
+ * reproducible bit for bit.  X counts as SPD when ||I - C_alpha X||_inf < 1
+ * (largest absolute row sum; it bounds the spectral radius of I - C_alpha X). */
+typedef enum { DDLR_CSOLVE_FACTOR = 0, DDLR_CSOLVE_MR = 1 } ddlr_csolve;
 typedef enum { DDLR_FP64 = 0, DDLR_FP32 = 1, DDLR_FP32_UK_BF16 = 2 } ddlr_precision;
 
 /* Symmetric matrix, host memory, full storage, sorted columns. */
@@ -83,6 +96,11 @@ typedef struct {
     double lanczos_tol;    /* with lanczos_check > 0: tolerance of eq. (converge); 0 -> 1e-4 (Sec. 5) */
     uint64_t seed;                /* Lanczos start vector when lanczos_start is NULL */
     const double *lanczos_start;  /* host, length n, user order: its interface entries form q_1 */
+    int32_t csolve;        /* ddlr_csolve; default DDLR_CSOLVE_FACTOR */
+    int32_t cinv_iters;    /* DDLR_CSOLVE_MR: MR steps (>= 0); default 3 */
+    double cinv_tol;       /* DDLR_CSOLVE_MR: drop tolerance relative to the column norm (>= 0); default 0.01 */
+    int32_t cinv_lfil;     /* DDLR_CSOLVE_MR: kept off-diagonal entries per column (>= 0); default 20 */
+    int32_t reserved0;
 } ddlr_options;
 
 typedef struct {
@@ -109,6 +127,11 @@ typedef struct {
     double theta, c0;
     double fill_ratio;      /* stored preconditioner entries / nnz(A) */
     double setup_ms, lanczos_ms;
+    int32_t csolve;         /* ddlr_csolve in use */
+    int32_t cinv_iters;     /* MR steps taken (fewer than asked if C Z vanished) */
+    int64_t nnz_cinv;       /* stored entries of X */
+    double cinv_res;        /* ||I - C_alpha X||_F */
+    double cinv_res_inf;    /* ||I - C_alpha X||_inf (the SPD certificate needs < 1) */
 } ddlr_info;
 
 typedef struct ddlr_prec ddlr_prec;
@@ -173,8 +196,17 @@ ddlr_status ddlr_query(const ddlr_prec *h, ddlr_info *info);
 ddlr_status ddlr_get_ordering(const ddlr_prec *h, int32_t *perm, int32_t *iface, int32_t *colour);
 
 /* Local factors in internal order: strict lower L as CSR (row_ptr n+1,
- * col/val nnz_l) and D (n).  Host arrays. */
+ * col/val nnz_l) and D (n).  Host arrays.  With DDLR_CSOLVE_MR the interface
+ * rows of L are empty and D is 1 there. */
 ddlr_status ddlr_get_factor(const ddlr_prec *h, int64_t *row_ptr, int32_t *col, double *val, double *D);
+
+/* The approximate inverse X ~ C_alpha^{-1} of Algorithm alg:mr (Sec. 4.4),
+ * DDLR_CSOLVE_MR only: s x s CSR in interface positions of the internal order
+ * (row_ptr s+1, col/val nnz_cinv of ddlr_query) and, if res is non-NULL, the
+ * residual norms ||I - C_alpha X_j||_F for j = 0..cinv_iters.  Host arrays
+ * owned by the caller.  Errors: DDLR_E_INVALID (null argument, or C_alpha
+ * factored).  Works on host-only handles. */
+ddlr_status ddlr_get_cinv(const ddlr_prec *h, int64_t *row_ptr, int32_t *col, double *val, double *res);
 
 /* A partition of the unknowns for matrices without a geometric split.  The
  * method takes the partition into p subdomains as an input produced by a

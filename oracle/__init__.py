@@ -166,17 +166,19 @@ class Oracle:
 
     def cinv(self):
         """(X: scipy CSR s x s in interface order, residual norms
-        ||I - C_alpha X_j||_F for j = 0..steps, SPD certificate ||I - C_alpha X||_F < 1)."""
+        ||I - C_alpha X_j||_F for j = 0..steps, SPD certificate
+        ||I - C_alpha X||_inf < 1).  .cinv_rinf holds ||I - C_alpha X||_inf."""
         import scipy.sparse as sp
         nnz = int(_lib.orc_size(self._h, 11))
         steps = int(_lib.orc_size(self._h, 12))
         rp = np.zeros(self.s + 1, np.int64)
         ci = np.zeros(max(nnz, 1), np.int32)
         v = np.zeros(max(nnz, 1))
-        res = np.zeros(steps + 1)
+        res = np.zeros(steps + 2)
         _lib.orc_cinv(self._h, _p(rp), _p(ci), _p(v), _p(res))
         X = sp.csr_matrix((v[:nnz], ci[:nnz], rp), shape=(self.s, self.s))
-        return X, res, bool(_lib.orc_size(self._h, 13))
+        self.cinv_rinf = float(res[-1])
+        return X, res[:-1], bool(_lib.orc_size(self._h, 13))
 
     # ---- operators (user order, columns of an (n, nrhs) array)
     @staticmethod

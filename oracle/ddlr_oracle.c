@@ -109,7 +109,8 @@ typedef struct {
     csr_t X;          /* s x s, symmetric, interface indices */
     int x_iters;      /* MR steps taken */
     double *x_res;    /* ||I - C X_j||_F for j = 0..x_iters */
-    int x_spd;        /* 1 if ||I - C X||_F < 1: then C^{1/2} X C^{1/2} has its eigenvalues in (0, 2), so X is SPD */
+    double x_rinf;    /* ||I - C X||_inf (largest absolute row sum) of the final X */
+    int x_spd;        /* 1 if ||I - C X||_inf < 1: then C^{1/2} X C^{1/2} has its eigenvalues in (0, 2), so X is SPD */
 } orc_t;
 
 static void *xcalloc(size_t n, size_t sz) {
@@ -602,6 +603,12 @@ static int build_cinv(orc_t *o, int nit, double tol, int lfil) {
         sp_i_minus(&W, s, &R);
         csr_free(&W);
         o->x_res[it] = frob(&R, s);
+        o->x_rinf = 0.0;
+        for (int64_t i = 0; i < s; ++i) {
+            double rs = 0.0;
+            for (int64_t t = R.rp[i]; t < R.rp[i + 1]; ++t) rs += fabs(R.v[t]);
+            if (rs > o->x_rinf) o->x_rinf = rs;
+        }
         if (it == nit) { csr_free(&R); break; }
         /* Z = X R, symmetrised */
         csr_t Zh = {0};
@@ -721,8 +728,8 @@ static int build_cinv(orc_t *o, int nit, double tol, int lfil) {
     }
     csr_free(&C);
     /* SPD certificate: I - C X is similar to I - C^{1/2} X C^{1/2}, whose
-     * spectral radius is at most ||I - C X||_F */
-    o->x_spd = o->x_res[o->x_iters] < 1.0;
+     * spectral radius is at most any induced norm of I - C X */
+    o->x_spd = o->x_rinf < 1.0;
     csr_free(&o->X);
     o->X = X;
     o->csolve = 1;
@@ -1179,12 +1186,14 @@ int orc_use_cinv(orc_t *o, int nit, double tol, int lfil) {
 }
 
 /* X (s x s CSR, interface indices), nnz via orc_size(o, 11); res: the
- * residual norms ||I - C X_j||_F, j = 0..x_iters (orc_size(o, 12)) */
+ * residual norms ||I - C X_j||_F, j = 0..x_iters (orc_size(o, 12)), then
+ * ||I - C X||_inf of the final X */
 void orc_cinv(const orc_t *o, int64_t *rp, int32_t *ci, double *v, double *res) {
     memcpy(rp, o->X.rp, (o->s + 1) * sizeof(int64_t));
     memcpy(ci, o->X.ci, o->X.rp[o->s] * sizeof(int32_t));
     memcpy(v, o->X.v, o->X.rp[o->s] * sizeof(double));
     memcpy(res, o->x_res, (o->x_iters + 1) * sizeof(double));
+    res[o->x_iters + 1] = o->x_rinf;
 }
 
 /* z = A0^{-1} x, user order, nrhs columns with leading dimension n */

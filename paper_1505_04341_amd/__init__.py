@@ -24,6 +24,7 @@ THETA_LAMBDA_K1, THETA_ZERO = 0, 1
 FACTOR_IC0, FACTOR_ILDL0 = 0, 1
 CORDER_MULTICOLOR, CORDER_NATURAL = 0, 1
 FP64, FP32, FP32_UK_BF16 = 0, 1, 2
+CSOLVE_FACTOR, CSOLVE_MR = 0, 1
 
 
 class ddlr_csr(C.Structure):
@@ -34,7 +35,9 @@ class ddlr_options(C.Structure):
     _fields_ = [("alpha", C.c_double), ("lanczos_steps", C.c_int32), ("theta", C.c_int32),
                 ("factor", C.c_int32), ("corder", C.c_int32), ("precision", C.c_int32), ("device", C.c_int32),
                 ("no_autotune", C.c_int32), ("lanczos_check", C.c_int32), ("lanczos_max", C.c_int32),
-                ("lanczos_tol", C.c_double), ("seed", C.c_uint64), ("lanczos_start", C.c_void_p)]
+                ("lanczos_tol", C.c_double), ("seed", C.c_uint64), ("lanczos_start", C.c_void_p),
+                ("csolve", C.c_int32), ("cinv_iters", C.c_int32), ("cinv_tol", C.c_double), ("cinv_lfil", C.c_int32),
+                ("reserved0", C.c_int32)]
 
 
 class ddlr_tuning(C.Structure):
@@ -66,7 +69,8 @@ class ddlr_info(C.Structure):
                 ("lanczos_steps", C.c_int32), ("ncolours", C.c_int32), ("levels_b_max", C.c_int32),
                 ("levels_c", C.c_int32), ("spd", C.c_int32), ("precision", C.c_int32), ("on_device", C.c_int32),
                 ("theta", C.c_double), ("c0", C.c_double), ("fill_ratio", C.c_double), ("setup_ms", C.c_double),
-                ("lanczos_ms", C.c_double)]
+                ("lanczos_ms", C.c_double), ("csolve", C.c_int32), ("cinv_iters", C.c_int32),
+                ("nnz_cinv", C.c_int64), ("cinv_res", C.c_double), ("cinv_res_inf", C.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -112,6 +116,7 @@ def load_library(path: str = LIB_PATH):
         "ddlr_query": (I32, [P, P]),
         "ddlr_get_ordering": (I32, [P, P, P, P]),
         "ddlr_get_factor": (I32, [P, P, P, P, P]),
+        "ddlr_get_cinv": (I32, [P, P, P, P, P]),
         "ddlr_get_levels": (I32, [P, P]),
         "ddlr_get_lanczos": (I32, [P, P, P, P]),
         "ddlr_get_lowrank": (I32, [P, P, P]),
@@ -198,7 +203,8 @@ class Prec:
 def ddlr_setup(A, part, p: int, k: int, variant: int = DDLR_1, *, alpha: float = 1.0, lanczos_steps: int = 0,
                theta: int = THETA_LAMBDA_K1, factor: int = FACTOR_IC0, corder: int = CORDER_MULTICOLOR,
                precision: int = FP64, device: int = 0, seed: int = 0, lanczos_start=None,
-               autotune: bool = True, lanczos_check: int = 0, lanczos_max: int = 0, lanczos_tol: float = 0.0) -> Prec:
+               autotune: bool = True, lanczos_check: int = 0, lanczos_max: int = 0, lanczos_tol: float = 0.0,
+               csolve: int = CSOLVE_FACTOR, cinv_iters: int = 3, cinv_tol: float = 0.01, cinv_lfil: int = 20) -> Prec:
     """Builds the preconditioner. A: object with n, rowptr (int64), col (int32), val (float64)."""
     lib = load_library()
     rp = np.ascontiguousarray(A.rowptr, dtype=np.int64)
@@ -213,6 +219,8 @@ def ddlr_setup(A, part, p: int, k: int, variant: int = DDLR_1, *, alpha: float =
         device), int(seed)
     opt.no_autotune = 0 if autotune else 1
     opt.lanczos_check, opt.lanczos_max, opt.lanczos_tol = int(lanczos_check), int(lanczos_max), float(lanczos_tol)
+    opt.csolve, opt.cinv_iters, opt.cinv_tol, opt.cinv_lfil = int(csolve), int(cinv_iters), float(cinv_tol), int(
+        cinv_lfil)
     v0 = None
     if lanczos_start is not None:
         v0 = np.ascontiguousarray(lanczos_start, dtype=np.float64)
@@ -296,6 +304,21 @@ def ddlr_get_factor(prec: Prec):
     D = np.zeros(n)
     _check(lib.ddlr_get_factor(prec.handle, _ptr(rp), _ptr(ci), _ptr(v), _ptr(D)), "ddlr_get_factor")
     return sp.csr_matrix((v[:nnz], ci[:nnz], rp), shape=(n, n)), D
+
+
+def ddlr_get_cinv(prec: Prec):
+    """(X as scipy CSR s x s in interface positions of the internal order,
+    residual norms ||I - C_alpha X_j||_F for j = 0..cinv_iters)."""
+    import scipy.sparse as sp
+    lib = load_library()
+    q = ddlr_query(prec)
+    s, nnz = q["s"], q["nnz_cinv"]
+    rp = np.zeros(s + 1, np.int64)
+    ci = np.zeros(max(nnz, 1), np.int32)
+    v = np.zeros(max(nnz, 1))
+    res = np.zeros(q["cinv_iters"] + 1)
+    _check(lib.ddlr_get_cinv(prec.handle, _ptr(rp), _ptr(ci), _ptr(v), _ptr(res)), "ddlr_get_cinv")
+    return sp.csr_matrix((v[:nnz], ci[:nnz], rp), shape=(s, s)), res
 
 
 def ddlr_get_levels(prec: Prec):
@@ -514,6 +537,7 @@ def ddlr_version() -> int:
 
 EXPORTED = ["ddlr_version", "ddlr_options_default", "ddlr_solve_options_default", "ddlr_setup", "ddlr_apply",
             "ddlr_a0_solve", "ddlr_spmv", "ddlr_solve", "ddlr_query", "ddlr_get_ordering", "ddlr_get_factor",
+            "ddlr_get_cinv",
             "ddlr_get_levels", "ddlr_get_lanczos", "ddlr_get_lowrank", "ddlr_set_lowrank", "ddlr_profile",
             "ddlr_profile_read", "ddlr_batch_create", "ddlr_batch_offsets", "ddlr_batch_apply",
             "ddlr_batch_solve", "ddlr_batch_destroy", "ddlr_server_create", "ddlr_server_add", "ddlr_server_submit",

@@ -128,6 +128,7 @@ template <typename T> struct DevFactors {
     T *ev = nullptr, *etv = nullptr;  // E and E^T values
     T *U = nullptr;                   // low-rank basis, row-major (rows x k)
     T *Ut = nullptr;                  // the same in MFMA tile order (k % 16 == 0), for U^T y
+    T *xv = nullptr;                  // approximate inverse of C_alpha (values)
 };
 
 // A Lanczos run kept for continuation: basis Q (s x (cap+1), device
@@ -193,6 +194,9 @@ struct ddlr_prec {
     // ring variant of the narrow A0-solve kernel (per-level ELL, LDS window)
     RingBlock* rblk = nullptr;
     int32_t *foff = nullptr, *fcol = nullptr, *boff_ = nullptr, *bcol = nullptr, *lwid = nullptr;
+    // approximate inverse of C_alpha: SELL-64 slice pointers, slice row -> interface row, columns
+    int32_t *xrp = nullptr, *xrow = nullptr, *xci = nullptr;
+    int64_t xnnz = 0;
     double *fval64 = nullptr, *bval64 = nullptr;
     float *fval32 = nullptr, *bval32 = nullptr;
     int ring_kw = 0;                          // 2, 3, 4, 8, 16 or 0 (ring kernel unusable)
@@ -281,6 +285,8 @@ struct DevHost {
     std::vector<std::pair<int, int>> wide;   // rows of the interface levels launched one by one
     std::vector<int32_t> erp, eci, etrp, etci;
     std::vector<double> ev, etv;
+    std::vector<int32_t> xrp, xci;  // approximate inverse of C_alpha, interface rows in device order
+    std::vector<double> xv;
 };
 
 // c_mode: -1 choose (few, wide interface levels -> level launches), 0 interface
@@ -370,7 +376,7 @@ DevHost build_devhost(const HostPlan& P, int c_mode) {
     const int32_t p = P.p;
     const int32_t c_lv0 = P.blk_lvl[p], c_lv1 = P.blk_lvl[p + 1];
     const int32_t c_levels = c_lv1 - c_lv0;
-    bool c_wide = c_levels > 0 && c_levels <= 64 && s / std::max(1, c_levels) >= 2048;
+    bool c_wide = c_levels > 0 && c_levels <= 64 && s / std::max(1, c_levels) >= 2048 && !P.csolve;
     if (const char* env = std::getenv("DDLR_C_WIDE")) {  // "1" forces level launches, "0" one workgroup
         if (env[0] == '1') c_wide = c_levels > 0;
         if (env[0] == '0') c_wide = false;
@@ -379,7 +385,24 @@ DevHost build_devhost(const HostPlan& P, int c_mode) {
     if (c_mode == 1) c_wide = c_levels > 0;
     for (int32_t b = 0; b < p; ++b)
         if (P.blk_lvl[b + 1] > P.blk_lvl[b]) D.narrow.push_back({P.blk_lvl[b], P.blk_lvl[b + 1]});
-    if (c_wide) {
+    if (P.csolve) {
+        // C_alpha by its approximate inverse: X with device-order interface indices
+        D.xrp.assign(s + 1, 0);
+        std::vector<std::pair<int32_t, double>> row;
+        for (int64_t r = 0; r < s; ++r) {
+            const int64_t y = P.dev2int[m + r] - m;
+            row.clear();
+            for (int64_t t = P.X.rp[y]; t < P.X.rp[y + 1]; ++t)
+                row.emplace_back((int32_t)(P.int2dev[m + P.X.ci[t]] - m), P.X.v[t]);
+            std::sort(row.begin(), row.end());
+            for (const auto& e : row) {
+                D.xci.push_back(e.first);
+                D.xv.push_back(e.second);
+            }
+            if (D.xci.size() > (size_t)INT32_MAX) throw SetupError{DDLR_E_INVALID, "nnz(X) must fit in int32"};
+            D.xrp[r + 1] = (int32_t)D.xci.size();
+        }
+    } else if (c_wide) {
         for (int32_t l = c_lv0; l < c_lv1; ++l) D.wide.emplace_back(P.lvl_ptr[l], P.lvl_ptr[l + 1]);
     } else if (c_levels > 0) {
         D.narrow.push_back({c_lv0, c_lv1});
@@ -589,6 +612,48 @@ void upload_devhost(ddlr_prec* h, const DevHost& D) {
     h->etci = M.upload(D.etci);
     h->f64.ev = M.upload(D.ev);
     h->f64.etv = M.upload(D.etv);
+    std::vector<double> xsell;
+    if (!D.xrp.empty()) {
+        // SELL-64 of X: rows by entry count (longest first, stable), slices of 64
+        const int64_t s = D.s;
+        std::vector<int32_t> order(s);
+        for (int64_t r = 0; r < s; ++r) order[r] = (int32_t)r;
+        std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+            return D.xrp[a + 1] - D.xrp[a] > D.xrp[b + 1] - D.xrp[b];
+        });
+        const int64_t ns = (s + 63) / 64;
+        std::vector<int32_t> sp(ns + 1, 0), xrow(ns * 64, 0), xcol;
+        for (int64_t sl = 0; sl < ns; ++sl) {
+            int64_t wmax = 0;
+            for (int64_t q = sl * 64; q < std::min<int64_t>(s, (sl + 1) * 64); ++q)
+                wmax = std::max<int64_t>(wmax, D.xrp[order[q] + 1] - D.xrp[order[q]]);
+            if ((int64_t)sp[sl] + wmax * 64 > INT32_MAX) throw SetupError{DDLR_E_INVALID, "X too large for SELL-64"};
+            sp[sl + 1] = sp[sl] + (int32_t)(wmax * 64);
+        }
+        xcol.assign(sp[ns], 0);
+        xsell.assign(sp[ns], 0.0);
+        for (int64_t sl = 0; sl < ns; ++sl) {
+            const int w = (sp[sl + 1] - sp[sl]) / 64;
+            for (int lane = 0; lane < 64; ++lane) {
+                const int64_t q = sl * 64 + lane;
+                // padding rows of the last slice repeat row 0 with zero entries; their
+                // threads are not launched (rows = s)
+                const int32_t r = q < s ? order[q] : 0;
+                xrow[q] = r;
+                const int32_t cnt = q < s ? D.xrp[r + 1] - D.xrp[r] : 0;
+                for (int j = 0; j < cnt; ++j) {
+                    xcol[sp[sl] + (int64_t)j * 64 + lane] = D.xci[D.xrp[r] + j];
+                    xsell[sp[sl] + (int64_t)j * 64 + lane] = D.xv[D.xrp[r] + j];
+                }
+                (void)w;
+            }
+        }
+        h->xrp = M.upload(sp);
+        h->xrow = M.upload(xrow);
+        h->xci = M.upload(xcol);
+        h->f64.xv = M.upload(xsell);
+        h->xnnz = (int64_t)D.xv.size();
+    }
     if (h->precision != DDLR_FP64) {
         auto demote = [&](const std::vector<double>& a) {
             std::vector<float> f(a.size());
@@ -600,6 +665,7 @@ void upload_devhost(ddlr_prec* h, const DevHost& D) {
         h->f32.dinv = demote(D.dinv);
         h->f32.ev = demote(D.ev);
         h->f32.etv = demote(D.etv);
+        if (!xsell.empty()) h->f32.xv = demote(xsell);
     }
     h->wide = D.wide;
     h->nnarrow = (int)D.narrow.size();
@@ -866,13 +932,16 @@ void wide_levels(ddlr_prec* h, const DevFactors<T>& F, int nrhs, const TIn* x, i
 }
 
 // z = A0^{-1} x, device order (x may equal z when TIn == TOut)
+// the interface block is solved apart from the B blocks (level launches or X)
+bool has_cpart(const ddlr_prec* h) { return !h->wide.empty() || h->xrp != nullptr; }
+
 template <typename T, typename TIn, typename TOut>
 void a0_solve_dev(ddlr_prec* h, const DevFactors<T>& F, int nrhs, const TIn* x, int64_t ldx, TOut* z, int64_t ldz,
                   hipStream_t st, const int* done) {
     bool ov = h->overlap;
     if (auto it = h->tune.find(nrhs); it != h->tune.end()) ov = ov && it->second.overlap;
     if (h->ov_override >= 0) ov = h->overlap && h->ov_override;
-    const bool fork = !h->wide.empty() && h->nnarrow > 0 && ov && h->side;
+    const bool fork = has_cpart(h) && h->nnarrow > 0 && ov && h->side;
     hipStream_t cst = st;
     if (fork) {
         HIPCHK(hipEventRecord(h->ev_fork, st));
@@ -880,6 +949,16 @@ void a0_solve_dev(ddlr_prec* h, const DevFactors<T>& F, int nrhs, const TIn* x, 
         cst = h->side;
     }
     if (!h->wide.empty()) wide_levels<T, TIn, TOut>(h, F, nrhs, x, ldx, z, ldz, cst, done);
+    if (h->xrp) {  // z_C = X x_C
+        ProfScope ps(h, 1, cst);
+        const int64_t m = h->ndev - h->sdev;
+        for (int c0 = 0; c0 < nrhs; c0 += kMaxRhs) {  // the kernel keeps up to kMaxRhs columns in registers
+            hipLaunchKernelGGL((k_cinv_sell<T, TIn, TOut>), dim3((h->sdev + 255) / 256), dim3(256), 0, cst, h->sdev,
+                               std::min(kMaxRhs, nrhs - c0), h->xrp, h->xrow, h->xci, F.xv, x + m + c0 * ldx, ldx,
+                               z + m + c0 * ldz, ldz, done);
+            LAUNCHCHK();
+        }
+    }
     if (h->nnarrow > 0) {
         ProfScope ps(h, 0, st);
         if (ring_ready<T>(h) && ring_nt_for<T>(h, nrhs) > 0) {
@@ -1548,6 +1627,10 @@ void ddlr_options_default(ddlr_options* o) {
     o->device = 0;
     o->seed = 0;
     o->lanczos_start = nullptr;
+    o->csolve = DDLR_CSOLVE_FACTOR;
+    o->cinv_iters = 3;
+    o->cinv_tol = 0.01;
+    o->cinv_lfil = 20;
 }
 
 void ddlr_solve_options_default(ddlr_solve_options* o) {
@@ -1579,8 +1662,13 @@ ddlr_status ddlr_setup(const ddlr_csr* A, const int32_t* part, int32_t p, int32_
         h->precision = opt.precision;
         h->variant = variant;
         if (const char* env = std::getenv("DDLR_LR_PLAIN")) h->lr_plain = env[0] == '1';
-        build_plan(h->plan, A->n, A->row_ptr, A->col_idx, A->val, part, p, opt.alpha, opt.factor, opt.corder);
+        if (opt.csolve != DDLR_CSOLVE_FACTOR && opt.csolve != DDLR_CSOLVE_MR)
+            throw SetupError{DDLR_E_INVALID, "csolve must be DDLR_CSOLVE_FACTOR or DDLR_CSOLVE_MR"};
+        build_plan(h->plan, A->n, A->row_ptr, A->col_idx, A->val, part, p, opt.alpha, opt.factor, opt.corder,
+                   opt.csolve == DDLR_CSOLVE_MR ? 1 : 0, opt.cinv_iters, opt.cinv_tol, opt.cinv_lfil);
         for (double d : h->plan.D) h->pivots_positive = h->pivots_positive && d > 0.0;
+        // with the approximate inverse, A0 is SPD when the B factors are and X is
+        if (h->plan.csolve) h->pivots_positive = h->pivots_positive && h->plan.x_spd;
         h->spd = variant == 0 ? (int)h->pivots_positive : 0;
         const int64_t s = h->plan.s;
         if (variant != 0) {
@@ -1595,7 +1683,7 @@ ddlr_status ddlr_setup(const ddlr_csr* A, const int32_t* part, int32_t p, int32_
             if (const char* env = std::getenv("DDLR_NO_OVERLAP")) h->overlap = env[0] != '1';
             h->tune_mode = opt.no_autotune ? 0 : 1;
             if (const char* env = std::getenv("DDLR_CG_GRAPH")) h->graph_mode = env[0] == '0' ? 0 : env[0] == '1' ? 1 : 2;
-            if (!h->wide.empty()) {
+            if (has_cpart(h.get())) {
                 h->side = dev_streams(opt.device).side;
                 HIPCHK(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
                 HIPCHK(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
@@ -1730,7 +1818,7 @@ void autotune_T(ddlr_prec* h, const DevFactors<T>& F, int nrhs, hipStream_t st) 
     tn.ring_r = bestR;
     tn.ring_nt = bestR > 1 ? 512 : bestNT;
     tn.overlap = 1;
-    if (h->overlap && h->side && !h->wide.empty() && h->nnarrow > 0) {
+    if (h->overlap && h->side && has_cpart(h) && h->nnarrow > 0) {
         tn.overlap = 0;
         tn.a0_noov_us = time_a0();
         tn.overlap = tn.a0_noov_us < best ? 0 : 1;
@@ -2013,7 +2101,7 @@ static void pcg_dev(ddlr_prec* h, int nr, const ddlr_solve_options& o, hipStream
     // may run a replayed graph's forked branches one after the other.
     ddlr_prec::CgMode& m = h->cg_mode[nr];
     const bool measure = h->graph_mode == 2 && !h->prof;
-    const bool can_ov = !h->wide.empty() && h->nnarrow > 0 && h->overlap && h->side;
+    const bool can_ov = has_cpart(h) && h->nnarrow > 0 && h->overlap && h->side;
     for (int it = 0; it <= o.maxit; it += kCgChunk) {
         bool graph = !h->prof && h->graph_mode != 0;
         bool timed = false;
@@ -2171,6 +2259,29 @@ ddlr_status ddlr_query(const ddlr_prec* h, ddlr_info* info) {
     info->fill_ratio = stored / (double)P.A.nnz();
     info->setup_ms = h->setup_ms;
     info->lanczos_ms = h->lanczos_ms;
+    info->csolve = P.csolve ? DDLR_CSOLVE_MR : DDLR_CSOLVE_FACTOR;
+    info->cinv_iters = P.x_iters;
+    info->nnz_cinv = P.csolve ? P.X.nnz() : 0;
+    info->cinv_res = P.csolve ? P.x_res.back() : 0.0;
+    info->cinv_res_inf = P.csolve ? P.x_rinf : 0.0;
+    if (P.csolve) info->fill_ratio += (double)P.X.nnz() / (double)P.A.nnz();
+    return DDLR_OK;
+}
+
+ddlr_status ddlr_get_cinv(const ddlr_prec* h, int64_t* row_ptr, int32_t* col, double* val, double* res) {
+    if (!h || !row_ptr || !col || !val) {
+        g_err = "null argument";
+        return DDLR_E_INVALID;
+    }
+    const HostPlan& P = h->plan;
+    if (!P.csolve) {
+        g_err = "the preconditioner factors C_alpha (no approximate inverse)";
+        return DDLR_E_INVALID;
+    }
+    std::copy(P.X.rp.begin(), P.X.rp.end(), row_ptr);
+    std::copy(P.X.ci.begin(), P.X.ci.end(), col);
+    std::copy(P.X.v.begin(), P.X.v.end(), val);
+    if (res) std::copy(P.x_res.begin(), P.x_res.end(), res);
     return DDLR_OK;
 }
 
@@ -2578,9 +2689,10 @@ ddlr_status ddlr_batch_create(int32_t nsys, ddlr_prec* const* members, ddlr_batc
     for (int q = 0; q < nsys; ++q) {
         const ddlr_prec* m = members[q];
         if (!m || m->device < 0 || m->nsys != 1 || m->device != m0->device || m->precision != m0->precision ||
-            m->variant != m0->variant || m->variant == DDLR_2 || m->precision == DDLR_FP32_UK_BF16) {
+            m->variant != m0->variant || m->variant == DDLR_2 || m->precision == DDLR_FP32_UK_BF16 ||
+            m->plan.csolve) {
             g_err = "batch members must be single-system device handles with the same device, precision and "
-                    "variant (DDLR-1 or A0 only; FP64 or FP32)";
+                    "variant (DDLR-1 or A0 only; FP64 or FP32; C_alpha factored)";
             return DDLR_E_INVALID;
         }
     }

@@ -208,6 +208,7 @@ void form_a0(HostPlan& P) {
 // a symmetric matrix U = D L^T, so L is the strict lower part and D the
 // diagonal of the result.
 void factor_blocks(HostPlan& P, int factor) {
+    const int32_t nfact = P.csolve ? P.p : P.p + 1;  // blocks factored (C_alpha last)
     const int64_t n = P.n;
     HostCsr W = P.A0;  // working copy, both triangles
     std::vector<int64_t> diagpos(n, -1);
@@ -215,7 +216,7 @@ void factor_blocks(HostPlan& P, int factor) {
         for (int64_t t = W.rp[i]; t < W.rp[i + 1]; ++t)
             if (W.ci[t] == i) diagpos[i] = t;
     std::vector<int64_t> where(n, -1);
-    for (int32_t b = 0; b <= P.p; ++b) {
+    for (int32_t b = 0; b < nfact; ++b) {
         const int64_t lo = P.boff[b], hi = P.boff[b + 1];
         for (int64_t i = lo; i < hi; ++i) {
             for (int64_t t = W.rp[i]; t < W.rp[i + 1]; ++t) where[W.ci[t]] = t;
@@ -244,16 +245,18 @@ void factor_blocks(HostPlan& P, int factor) {
     P.L.rp.assign(n + 1, 0);
     P.L.ci.clear();
     P.L.v.clear();
-    P.D.assign(n, 0.0);
+    P.D.assign(n, 1.0);
     for (int32_t b = 0; b <= P.p; ++b) {
         const int64_t lo = P.boff[b];
         for (int64_t i = lo; i < P.boff[b + 1]; ++i) {
-            for (int64_t t = W.rp[i]; t < diagpos[i]; ++t)
-                if (W.ci[t] >= lo) {
-                    P.L.ci.push_back(W.ci[t]);
-                    P.L.v.push_back(W.v[t]);
-                }
-            P.D[i] = W.v[diagpos[i]];
+            if (b < nfact) {
+                for (int64_t t = W.rp[i]; t < diagpos[i]; ++t)
+                    if (W.ci[t] >= lo) {
+                        P.L.ci.push_back(W.ci[t]);
+                        P.L.v.push_back(W.v[t]);
+                    }
+                P.D[i] = W.v[diagpos[i]];
+            }
             P.L.rp[i + 1] = (int64_t)P.L.ci.size();
         }
     }
@@ -301,7 +304,8 @@ void schedule(HostPlan& P) {
 }  // namespace
 
 void build_plan(HostPlan& P, int64_t n, const int64_t* rp, const int32_t* ci, const double* v, const int32_t* part,
-                int32_t p, double alpha, int factor, int corder) {
+                int32_t p, double alpha, int factor, int corder, int csolve, int cinv_iters, double cinv_tol,
+                int cinv_lfil) {
     if (!(alpha > 0.0) || !std::isfinite(alpha)) fail(DDLR_E_INVALID, "alpha must be positive");
     validate(n, rp, ci, v, part, p);
     P.n = n;
@@ -311,7 +315,9 @@ void build_plan(HostPlan& P, int64_t n, const int64_t* rp, const int32_t* ci, co
     if (P.s == 0) fail(DDLR_E_INVALID, "partition has no interface unknowns");
     permute_matrix(P, rp, ci, v);
     form_a0(P);
+    P.csolve = csolve;
     factor_blocks(P, factor);
+    if (csolve) build_cinv(P, cinv_iters, cinv_tol, cinv_lfil);
     schedule(P);
 }
 

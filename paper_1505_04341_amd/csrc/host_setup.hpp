@@ -49,6 +49,14 @@ struct HostPlan {
     std::vector<int32_t> lvl_ptr; // device-order row offsets of all levels, all blocks, concatenated
     std::vector<int32_t> blk_lvl; // p+2: levels of block b are lvl_ptr[blk_lvl[b] .. blk_lvl[b+1]]
     int32_t levels_b_max = 0, levels_c = 0;
+    // C_alpha solved by its approximate inverse (csolve = 1; cinv.cpp): the
+    // interface rows of L are then empty and D is 1 there
+    int csolve = 0;
+    HostCsr X;                  // s x s, symmetric, interface positions (internal order)
+    std::vector<double> x_res;  // ||I - C_alpha X_j||_F, j = 0..x_iters
+    int x_iters = 0;
+    double x_rinf = 0.0;        // ||I - C_alpha X||_inf of the final X
+    bool x_spd = false;         // x_rinf < 1
 };
 
 // Validates A (sorted columns, symmetric values) and part.
@@ -56,8 +64,15 @@ void validate(int64_t n, const int64_t* rp, const int32_t* ci, const double* v, 
 
 // Steps 1-3.  factor: 0 = IC(0) (pivots must be > 0), 1 = ILDL(0) (|pivot| >=
 // 1e-14 |a_ii|).  corder: 0 = greedy multicolour interface order, 1 = natural.
+// csolve: 0 = C_alpha factored like the B blocks; 1 = C_alpha by the
+// approximate inverse of Algorithm alg:mr (cinv_iters steps, drop tolerance
+// cinv_tol, at most cinv_lfil kept off-diagonal entries per column).
 void build_plan(HostPlan& P, int64_t n, const int64_t* rp, const int32_t* ci, const double* v,
-                const int32_t* part, int32_t p, double alpha, int factor, int corder);
+                const int32_t* part, int32_t p, double alpha, int factor, int corder, int csolve = 0,
+                int cinv_iters = 3, double cinv_tol = 0.01, int cinv_lfil = 20);
+
+// X ~ C_alpha^{-1} by Algorithm alg:mr into P.X, P.x_res, P.x_iters, P.x_spd.
+void build_cinv(HostPlan& P, int nit, double tol, int lfil);
 
 // Eigen-decomposition of a symmetric tridiagonal matrix (diag a[0..m-1],
 // off-diagonal b[0..m-2]) by implicit QR steps with Wilkinson shifts.

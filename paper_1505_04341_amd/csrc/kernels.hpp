@@ -656,6 +656,43 @@ __global__ __launch_bounds__(256) void k_csr_mv(int64_t rows, int nrhs, const in
     }
 }
 
+// z_C = X x_C: the C_alpha solve by its approximate inverse (Sec. 4.4,
+// Algorithm alg:mr).  X is stored in SELL-64 over the interface rows: rows
+// sorted by entry count (longest first) and cut into slices of 64, entries
+// column-major inside a slice so that a wave's loads of one entry position
+// are one segment; xrow maps a slice row to its interface row, padding has
+// column 0 and value 0.  One thread per row keeps all right-hand sides in
+// registers, so each entry is loaded once; the sum runs over the row's
+// entries in ascending column order.  x and z point at the first interface
+// row (device order, ld = n).
+template <typename T, typename TIn, typename TOut>
+__global__ __launch_bounds__(256) void k_cinv_sell(int64_t rows, int nrhs, const int32_t* __restrict__ sptr,
+                                                   const int32_t* __restrict__ xrow, const int32_t* __restrict__ col,
+                                                   const T* __restrict__ val, const TIn* x, int64_t ldx, TOut* z,
+                                                   int64_t ldz, const int* __restrict__ done) {
+    if (done && *done) return;
+    const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (q >= rows) return;
+    const int64_t sl = q >> 6;
+    const int lane = (int)(q & 63);
+    const int base = sptr[sl], width = (sptr[sl + 1] - base) >> 6;
+    T acc[kMaxRhs];
+#pragma unroll
+    for (int r = 0; r < kMaxRhs; ++r) acc[r] = T(0);
+    for (int j = 0; j < width; ++j) {
+        const int e = base + j * 64 + lane;
+        const int c = col[e];
+        const T a = val[e];
+#pragma unroll
+        for (int r = 0; r < kMaxRhs; ++r)
+            if (r < nrhs) acc[r] = fnms(acc[r], -a, (T)x[c + r * ldx]);  // acc + a x, one rounding
+    }
+    const int64_t i = xrow[q];
+#pragma unroll
+    for (int r = 0; r < kMaxRhs; ++r)
+        if (r < nrhs) z[i + r * ldz] = (TOut)acc[r];
+}
+
 // ------------------------------------------------------- low-rank correction
 //
 // DDLR-1 (eq. gkt):  w = c0 y + U_k (d .* (U_k^T y)),   U_k: s x k

@@ -642,3 +642,101 @@ def test_ring_workgroup_sizes_bitwise(case, prec):
     t = D.ddlr_tune(h, 1, retune=True)
     say("tune", case, prec, t)
     assert t["ring_threads"] in (-1, 64, 256, 512)
+
+
+# ------------------------------ C_alpha by its approximate inverse (Sec. 4.4)
+
+def setup_pair_mr(cfg, variant=1, nit=3, tol=0.01, lfil=20, env=None, **kw):
+    """GPU preconditioner and oracle, both solving C_alpha with the MR approximate inverse."""
+    env = dict(env or {})
+    os.environ.update(env)
+    try:
+        h = D.ddlr_setup(cfg["A"], cfg["part"], cfg["p"], cfg["k"], variant, lanczos_steps=cfg.get("m", 0),
+                         lanczos_start=w.lanczos_start(cfg["A"].n, 0), csolve=D.CSOLVE_MR, cinv_iters=nit,
+                         cinv_tol=tol, cinv_lfil=lfil, **kw)
+    finally:
+        for key in env:
+            os.environ.pop(key, None)
+    o = Oracle(cfg["A"], cfg["part"], cfg["p"], alpha=kw.get("alpha", 1.0), corder=kw.get("corder", 0))
+    o.use_cinv(nit, tol, lfil)
+    return h, o
+
+
+@pytest.mark.parametrize("name", ["c1", "small3d", "irregular", "big3d"])
+@pytest.mark.parametrize("overlap", ["0", "1"])
+def test_cinv_a0_solve(name, overlap):
+    cfg = CASES[name]()
+    say("cinv a0_solve", name, "overlap", overlap)
+    h, o = setup_pair_mr(cfg, variant=D.VARIANT_A0, env={"DDLR_NO_OVERLAP": "1" if overlap == "0" else "0"})
+    q = D.ddlr_query(h)
+    X, res, spd = o.cinv()
+    assert q["csolve"] == D.CSOLVE_MR and q["nnz_cinv"] == X.nnz and q["cinv_res"] == res[-1]
+    n = cfg["A"].n
+    rng = np.random.default_rng(11)
+    for nrhs in (1, 3, 17):
+        x = rng.standard_normal((n, nrhs))
+        y = torch.empty((nrhs, n), dtype=torch.float64, device=DEV)
+        D.ddlr_a0_solve(h, to_dev(x), y)
+        ref = o.a0_solve(x)
+        assert rel(to_host(y), ref) <= 1e-12, (nrhs, rel(to_host(y), ref))
+
+
+@pytest.mark.parametrize("name", ["c1", "irregular", "small3d"])
+@pytest.mark.parametrize("variant", [1, 2])
+def test_cinv_lanczos_and_apply(name, variant):
+    """Own Lanczos on the operator with X: Ritz values as the oracle's; the
+    application with the oracle's low-rank data imported."""
+    cfg = CASES[name]()
+    say("cinv lanczos/apply", name, variant)
+    h, o = setup_pair_mr(cfg, variant=variant)
+    o.lowrank(variant, cfg["k"], cfg["m"], w.lanczos_start(cfg["A"].n, 0))
+    gr = D.ddlr_get_lanczos(h)[2]
+    orz = o.lanczos_record()[2]
+    k = cfg["k"]
+    assert np.abs(gr[: k + 1] - orz[: k + 1]).max() <= 1e-8 * max(1.0, abs(orz[0]))
+    assert bool(D.ddlr_query(h)["spd"]) == bool(o.spd)
+    if variant == 1:
+        U, lam, th = o.get_lowrank()
+        D.ddlr_set_lowrank(h, 1, U, lam, th)
+    else:
+        U, H = o.get_lowrank()
+        D.ddlr_set_lowrank(h, 2, U, H)
+    x = np.random.default_rng(3).standard_normal((cfg["A"].n, 4))
+    y = torch.empty((4, cfg["A"].n), dtype=torch.float64, device=DEV)
+    D.ddlr_apply(h, to_dev(x), y)
+    assert rel(to_host(y), o.apply(x)) <= 1e-10
+
+
+@pytest.mark.parametrize("name", ["c1", "small3d"])
+@pytest.mark.parametrize("prec", [D.FP64, D.FP32])
+def test_cinv_pcg_end_to_end(name, prec):
+    cfg = CASES[name]()
+    say("cinv pcg", name, prec)
+    h, o = setup_pair_mr(cfg, variant=1, precision=prec)
+    o.lowrank(1, cfg["k"], cfg["m"], w.lanczos_start(cfg["A"].n, 0))
+    assert D.ddlr_query(h)["spd"] and o.spd
+    b, xs = w.rhs_from_solution(cfg["A"], 0, 3)
+    x = torch.zeros((3, cfg["A"].n), dtype=torch.float64, device=DEV)
+    st, info = D.ddlr_solve(h, to_dev(b), x)
+    assert st == D.OK
+    xo, infoo = o.pcg(b)
+    for i, io in zip(info, infoo["its"]):
+        assert i["relres_true"] <= 1.05e-6
+        if prec == D.FP64:
+            assert abs(i["iters"] - int(io)) <= 1
+        else:
+            assert i["iters"] <= int(1.1 * io) + 1
+    assert rel(to_host(x), xo) <= 1e-5
+
+
+def test_cinv_ddlr2_rank_above_register_block():
+    """DDLR-2 builds U_k = A0^{-1} E V_k with k columns at once; k = 20 takes
+    the X product in two column groups."""
+    cfg = dict(w.config("small3d"), k=20, m=48)
+    say("cinv ddlr2 k=20")
+    h, o = setup_pair_mr(cfg, variant=2)
+    o.lowrank(2, cfg["k"], cfg["m"], w.lanczos_start(cfg["A"].n, 0))
+    x = np.random.default_rng(5).standard_normal((cfg["A"].n, 2))
+    y = torch.empty((2, cfg["A"].n), dtype=torch.float64, device=DEV)
+    D.ddlr_apply(h, to_dev(x), y)
+    assert rel(to_host(y), o.apply(x)) <= 1e-8

@@ -135,3 +135,38 @@ def test_partitioner_errors():
     with pytest.raises(D.DDLRError) as e:
         D.ddlr_partition_graph(G, 7)  # more parts than vertices
     assert e.value.status == D.E_INVALID
+
+
+@pytest.mark.parametrize("name,cfg,kw", list(_cases()), ids=[c[0] for c in _cases()])
+@pytest.mark.parametrize("nit,tol,lfil", [(3, 0.01, 20), (2, 0.0, 6), (4, 0.1, 4)])
+def test_cinv_matches_oracle_bitwise(name, cfg, kw, nit, tol, lfil):
+    """The library's approximate inverse of C_alpha (host build, Algorithm
+    alg:mr) equals the oracle's bit for bit: both follow the stated arithmetic
+    order, so every drop decision agrees."""
+    A = cfg["A"]
+    h = D.ddlr_setup(A, cfg["part"], cfg["p"], cfg["k"], D.DDLR_1, device=-1, csolve=D.CSOLVE_MR,
+                     cinv_iters=nit, cinv_tol=tol, cinv_lfil=lfil, **kw)
+    o = Oracle(A, cfg["part"], cfg["p"], alpha=kw.get("alpha", 1.0), corder=kw.get("corder", 0))
+    o.use_cinv(nit, tol, lfil)
+    X, res = D.ddlr_get_cinv(h)
+    Xo, reso, spdo = o.cinv()
+    assert np.array_equal(X.indptr, Xo.indptr) and np.array_equal(X.indices, Xo.indices)
+    assert np.array_equal(X.data, Xo.data)
+    assert np.array_equal(res, reso)
+    q = D.ddlr_query(h)
+    assert q["csolve"] == D.CSOLVE_MR and q["nnz_cinv"] == Xo.nnz and q["cinv_res"] == reso[-1]
+    assert q["cinv_res_inf"] == o.cinv_rinf
+    # interface rows of L are empty, D is 1 there
+    L, Dg = D.ddlr_get_factor(h)
+    assert L.indptr[-1] == L.indptr[q["m"]] and np.all(Dg[q["m"]:] == 1.0)
+
+
+def test_cinv_option_errors():
+    c = w.config("c1")
+    with pytest.raises(D.DDLRError):
+        D.ddlr_setup(c["A"], c["part"], c["p"], c["k"], D.DDLR_1, device=-1, csolve=7)
+    with pytest.raises(D.DDLRError):
+        D.ddlr_setup(c["A"], c["part"], c["p"], c["k"], D.DDLR_1, device=-1, csolve=D.CSOLVE_MR, cinv_iters=-1)
+    h = D.ddlr_setup(c["A"], c["part"], c["p"], c["k"], D.DDLR_1, device=-1)
+    with pytest.raises(D.DDLRError):
+        D.ddlr_get_cinv(h)

@@ -755,3 +755,18 @@ def test_cinv_preconditioner_end_to_end():
     of.lowrank(1, cfg["k"], cfg["m"], w.lanczos_start(A.n, 0))
     _, infof = of.pcg(b)
     assert infof["status"] == 0 and abs(int(info["its"][0]) - int(infof["its"][0])) <= 20
+
+
+@pytest.mark.parametrize("name", ["c1", "small3d"])
+def test_cinv_spd_certificate(name):
+    """||I - C X||_inf bounds the spectral radius of I - C X (LAPACK
+    eigenvalues), and when it is below 1, X is SPD."""
+    cfg = w.config(name)
+    o = Oracle(cfg["A"], cfg["part"], cfg["p"]).use_cinv(nit=3, tol=0.01, lfil=20)
+    X, res, spd = o.cinv()
+    C = _c_alpha(o)
+    R = np.eye(o.s) - C @ X.toarray()
+    assert abs(o.cinv_rinf - np.abs(R).sum(axis=1).max()) <= 1e-12
+    assert np.abs(np.linalg.eigvals(R)).max() <= o.cinv_rinf + 1e-12
+    assert spd == (o.cinv_rinf < 1.0) and spd
+    assert np.linalg.eigvalsh(X.toarray()).min() > 0.0
