@@ -227,6 +227,7 @@ struct ddlr_prec {
     // the first solves of each column count and the faster is kept), 1 = graphs,
     // 0 = eager (DDLR_CG_GRAPH=1 / 0 force one)
     int graph_mode = 2;
+    int level_kernel = 0;  // interface levels: 0 by level size, 1 one thread per row, 2 per (row, column)
     struct CgMode {
         double eager_us[2] = {1e30, 1e30};  // fastest eager chunk, interface levels in line / beside
         double graph_us = 1e30;
@@ -912,21 +913,42 @@ void wide_levels(ddlr_prec* h, const DevFactors<T>& F, int nrhs, const TIn* x, i
                  hipStream_t st, const int* done) {
     ProfScope ps(h, 1, st);
     const int nl = (int)h->wide.size();
+    // levels of at least 256 workgroups of rows take one thread per row for all
+    // columns (entries loaded once); smaller ones one thread per (row, column)
+    auto by_rows = [&](int a, int e) {
+        if (nrhs > kMaxRhs || h->level_kernel == 2) return false;
+        return h->level_kernel == 1 || e - a >= 256 * 256;
+    };
     for (int l = 0; l < nl; ++l) {
         const int a = h->wide[l].first, e = h->wide[l].second;
-        const dim3 g((e - a + 255) / 256, nrhs);
-        if (l + 1 < nl)
-            hipLaunchKernelGGL((k_trsv_level<T, 0, TIn, TOut>), g, dim3(256), 0, st, a, e, nrhs, h->lrp, h->lci, F.lv,
-                               F.dinv, x, ldx, z, ldz, done);
-        else
-            hipLaunchKernelGGL((k_trsv_level<T, 2, TIn, TOut>), g, dim3(256), 0, st, a, e, nrhs, h->lrp, h->lci, F.lv,
-                               F.dinv, x, ldx, z, ldz, done);
+        const bool last = l + 1 == nl;
+        if (by_rows(a, e)) {
+            const dim3 g((e - a + 255) / 256);
+            if (!last)
+                hipLaunchKernelGGL((k_trsv_level_rows<T, 0, TIn, TOut>), g, dim3(256), 0, st, a, e, nrhs, h->lrp,
+                                   h->lci, F.lv, F.dinv, x, ldx, z, ldz, done);
+            else
+                hipLaunchKernelGGL((k_trsv_level_rows<T, 2, TIn, TOut>), g, dim3(256), 0, st, a, e, nrhs, h->lrp,
+                                   h->lci, F.lv, F.dinv, x, ldx, z, ldz, done);
+        } else {
+            const dim3 g((e - a + 255) / 256, nrhs);
+            if (!last)
+                hipLaunchKernelGGL((k_trsv_level<T, 0, TIn, TOut>), g, dim3(256), 0, st, a, e, nrhs, h->lrp, h->lci,
+                                   F.lv, F.dinv, x, ldx, z, ldz, done);
+            else
+                hipLaunchKernelGGL((k_trsv_level<T, 2, TIn, TOut>), g, dim3(256), 0, st, a, e, nrhs, h->lrp, h->lci,
+                                   F.lv, F.dinv, x, ldx, z, ldz, done);
+        }
         LAUNCHCHK();
     }
     for (int l = nl - 2; l >= 0; --l) {
         const int a = h->wide[l].first, e = h->wide[l].second;
-        hipLaunchKernelGGL((k_trsv_level<T, 1, TIn, TOut>), dim3((e - a + 255) / 256, nrhs),
-                           dim3(256), 0, st, a, e, nrhs, h->urp, h->uci, F.uv, F.dinv, x, ldx, z, ldz, done);
+        if (by_rows(a, e))
+            hipLaunchKernelGGL((k_trsv_level_rows<T, 1, TIn, TOut>), dim3((e - a + 255) / 256), dim3(256), 0, st, a, e,
+                               nrhs, h->urp, h->uci, F.uv, F.dinv, x, ldx, z, ldz, done);
+        else
+            hipLaunchKernelGGL((k_trsv_level<T, 1, TIn, TOut>), dim3((e - a + 255) / 256, nrhs), dim3(256), 0, st, a, e,
+                               nrhs, h->urp, h->uci, F.uv, F.dinv, x, ldx, z, ldz, done);
         LAUNCHCHK();
     }
 }
@@ -1683,6 +1705,8 @@ ddlr_status ddlr_setup(const ddlr_csr* A, const int32_t* part, int32_t p, int32_
             if (const char* env = std::getenv("DDLR_NO_OVERLAP")) h->overlap = env[0] != '1';
             h->tune_mode = opt.no_autotune ? 0 : 1;
             if (const char* env = std::getenv("DDLR_CG_GRAPH")) h->graph_mode = env[0] == '0' ? 0 : env[0] == '1' ? 1 : 2;
+            if (const char* env = std::getenv("DDLR_LEVEL_KERNEL"))  // "rows" / "cols" force one form
+                h->level_kernel = env[0] == 'r' ? 1 : env[0] == 'c' ? 2 : 0;
             if (has_cpart(h.get())) {
                 h->side = dev_streams(opt.device).side;
                 HIPCHK(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));

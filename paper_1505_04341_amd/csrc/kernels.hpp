@@ -509,6 +509,39 @@ __global__ __launch_bounds__(256) void k_trsv_level(int a, int e, int nrhs, cons
     zr[i] = (TOut)s;
 }
 
+// The same level with one thread per row for all nrhs <= kMaxRhs columns: the
+// row's entries are loaded once instead of once per column; per column the
+// arithmetic is k_trsv_level's (same terms, same order).
+template <typename T, int kKind, typename TIn, typename TOut>
+__global__ __launch_bounds__(256) void k_trsv_level_rows(int a, int e, int nrhs, const int32_t* __restrict__ rp,
+                                                         const int32_t* __restrict__ ci, const T* __restrict__ v,
+                                                         const T* __restrict__ dinv, const TIn* x, int64_t ldx,
+                                                         TOut* z, int64_t ldz, const int* __restrict__ done) {
+    if (done && *done) return;
+    const int i = a + (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i >= e) return;
+    T s[kMaxRhs];
+    const T di = dinv[i];
+#pragma unroll
+    for (int r = 0; r < kMaxRhs; ++r)
+        if (r < nrhs) s[r] = kKind == 1 ? (T)z[i + r * ldz] * di : (T)x[i + r * ldx];
+    const int t1 = rp[i + 1];
+    for (int t = rp[i]; t < t1; ++t) {
+        const int c = ci[t];
+        const T vt = v[t];
+#pragma unroll
+        for (int r = 0; r < kMaxRhs; ++r)
+            if (r < nrhs) s[r] = fnms(s[r], vt, (T)z[c + r * ldz]);
+    }
+#pragma unroll
+    for (int r = 0; r < kMaxRhs; ++r) {
+        if (r < nrhs) {
+            if (kKind == 2) s[r] *= di;
+            z[i + r * ldz] = (TOut)s[r];
+        }
+    }
+}
+
 // ------------------------------------------------------------ SpMV (SELL-64)
 //
 // y = A x for up to kMaxRhs columns; A is FP64 in SELL-64 (slices of 64 rows,

@@ -77,12 +77,17 @@ CASES = {"c1": lambda: w.config("c1"), "small2d": lambda: w.config("small2d"),
 
 
 @pytest.mark.parametrize("name", ["c1", "small3d", "irregular", "big3d"])
-@pytest.mark.parametrize("wide", [False, True])
+@pytest.mark.parametrize("wide", [False, "rows", "cols"])
 @pytest.mark.parametrize("kernel", ["ring", "plain"])
 def test_a0_solve_and_spmv(name, wide, kernel):
+    """wide: the interface block as one narrow block, or its colour levels
+    launched one by one with one thread per row / per (row, column)."""
     cfg = CASES[name]()
     say("a0_solve", name, "wide", wide, kernel)
-    h, o = setup_pair(cfg, variant=D.VARIANT_A0, wide=wide, env={"DDLR_TRSV_PLAIN": "1" if kernel == "plain" else "0"})
+    env = {"DDLR_TRSV_PLAIN": "1" if kernel == "plain" else "0"}
+    if wide:
+        env["DDLR_LEVEL_KERNEL"] = wide
+    h, o = setup_pair(cfg, variant=D.VARIANT_A0, wide=bool(wide), env=env)
     n = cfg["A"].n
     rng = np.random.default_rng(7)
     for nrhs in (1, 3, 17):  # 17: two launches of up to 16 columns, ragged tail
