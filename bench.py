@@ -199,7 +199,8 @@ def run_single(args, D, w, torch):
         r.update(h=h, q=q, setup_s=setup_s, xerr=float(np.linalg.norm(r["x"] - xs) / np.linalg.norm(xs)))
         tn = D.ddlr_tune(h, nrhs)  # the shapes the solves used (not re-run)
         r["tuning"] = {key: tn[key] for key in ("ring_cols", "ring_threads", "overlap", "cg_overlap", "cg_graph",
-                                                "cg_eager_us", "cg_eager_in_line_us", "cg_graph_us")}
+                                                "cg_eager_us", "cg_eager_in_line_us", "cg_graph_us",
+                                                "cg_graph_in_line_us")}
         log(name, "tuning", r["tuning"])
         res[name] = r
     mixed, f64 = res["mixed"], res["fp64"]

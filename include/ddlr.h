@@ -286,12 +286,12 @@ ddlr_status ddlr_extend_lowrank(ddlr_prec *h, int32_t k, int32_t more_steps, int
  * launch overhead, but forked branches of a replayed graph (the interface
  * levels beside the block solve) may run one after the other.  Unless the
  * environment forces one form (DDLR_CG_GRAPH=1 graphs, 0 eager), the first
- * solves with a column count time whole chunks on the host: eager chunks
- * with the interface levels beside and in line with the block solve (that
- * overlap competes with other forked work inside an iteration, so its A0-only
- * timing above does not decide it for PCG), then replayed chunks with the
- * better choice; the faster forms are kept.  cg_* below report that
- * measurement. */
+ * solves with a column count time whole chunks on the host, two per
+ * candidate: replayed and eager, each with the interface block's solve beside
+ * and in line with the block solve (that overlap competes with other forked
+ * work inside an iteration and a replayed graph may serialise it, so its
+ * A0-only timing above does not decide it for PCG); the fastest is kept.
+ * cg_* below report that measurement. */
 typedef struct {
     int32_t nrhs;            /* column count the shape is for */
     int32_t ring_cols;       /* right-hand sides per workgroup of the block triangular solve */
@@ -304,12 +304,13 @@ typedef struct {
     float a0_plain_us;       /* the plain per-level kernel (0: not measured) */
     int32_t cg_graph;        /* PCG chunks of this column count: 1 replayed graphs, 0 eager launches,
                                 -1 still being measured */
-    float cg_eager_us;       /* fastest timed eager chunk of 8 PCG iterations with the chosen overlap
-                                (0: none yet) */
-    float cg_graph_us;       /* fastest timed replayed chunk (0: none yet) */
-    int32_t cg_overlap;      /* PCG: interface levels beside (1) or in line with (0) the block solve; -1: still
-                                being measured, or no interface levels to overlap */
-    float cg_eager_in_line_us; /* fastest eager chunk with the interface levels in line (0: not timed) */
+    float cg_eager_us;       /* fastest timed eager chunk of 8 PCG iterations with the chosen overlap, or with
+                                the interface solve beside the block solve while undecided (0: none yet) */
+    float cg_graph_us;       /* the same for replayed chunks */
+    int32_t cg_overlap;      /* PCG: interface solve beside (1) or in line with (0) the block solve; -1: still
+                                being measured, or nothing to overlap */
+    float cg_eager_in_line_us; /* fastest eager chunk with the interface solve in line (0: not timed) */
+    float cg_graph_in_line_us; /* fastest replayed chunk with the interface solve in line (0: not timed) */
 } ddlr_tuning;
 ddlr_status ddlr_tune(ddlr_prec *h, int32_t nrhs, int32_t retune, ddlr_tuning *out, void *stream);
 

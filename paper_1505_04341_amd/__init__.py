@@ -44,14 +44,15 @@ class ddlr_tuning(C.Structure):
     _fields_ = [("nrhs", C.c_int32), ("ring_cols", C.c_int32), ("overlap", C.c_int32), ("ring_threads", C.c_int32),
                 ("a0_us", C.c_float * 4), ("a0_no_overlap_us", C.c_float), ("a0_thin_us", C.c_float * 2),
                 ("a0_plain_us", C.c_float), ("cg_graph", C.c_int32), ("cg_eager_us", C.c_float),
-                ("cg_graph_us", C.c_float), ("cg_overlap", C.c_int32), ("cg_eager_in_line_us", C.c_float)]
+                ("cg_graph_us", C.c_float), ("cg_overlap", C.c_int32), ("cg_eager_in_line_us", C.c_float),
+                ("cg_graph_in_line_us", C.c_float)]
 
     def as_dict(self):
         return dict(nrhs=self.nrhs, ring_cols=self.ring_cols, overlap=self.overlap, ring_threads=self.ring_threads,
                     a0_us=list(self.a0_us), a0_no_overlap_us=self.a0_no_overlap_us, a0_thin_us=list(self.a0_thin_us),
                     a0_plain_us=self.a0_plain_us, cg_graph=self.cg_graph, cg_eager_us=self.cg_eager_us,
                     cg_graph_us=self.cg_graph_us, cg_overlap=self.cg_overlap,
-                    cg_eager_in_line_us=self.cg_eager_in_line_us)
+                    cg_eager_in_line_us=self.cg_eager_in_line_us, cg_graph_in_line_us=self.cg_graph_in_line_us)
 
 
 class ddlr_solve_options(C.Structure):

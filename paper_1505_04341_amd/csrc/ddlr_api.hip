@@ -222,17 +222,21 @@ struct ddlr_prec {
     // x += alpha p runs on its own stream beside the preconditioner
     hipStream_t x_st = nullptr;
     hipEvent_t ev_xf = nullptr, ev_xj = nullptr;
-    std::map<int, std::pair<hipGraph_t, hipGraphExec_t>> cg_graphs;
+    std::map<int, std::pair<hipGraph_t, hipGraphExec_t>> cg_graphs;  // key: column count * 4 + overlap + 1
     // CG chunk launches: 2 = measured (eager and replayed chunks are timed on
     // the first solves of each column count and the faster is kept), 1 = graphs,
     // 0 = eager (DDLR_CG_GRAPH=1 / 0 force one)
     int graph_mode = 2;
     int level_kernel = 0;  // interface levels: 0 by level size, 1 one thread per row, 2 per (row, column)
     struct CgMode {
-        double eager_us[2] = {1e30, 1e30};  // fastest eager chunk, interface levels in line / beside
-        double graph_us = 1e30;
-        int ne[2] = {0, 0}, ng = 0;  // timed eager chunks; graph chunks (the capture included)
-        int ov = -1;                 // measured choice of overlap for CG (-1: not yet / not eligible)
+        double us[2][3];     // fastest chunk [graph][overlap + 1], overlap -1: not applicable
+        int timed[2][3] = {};
+        bool captured[3] = {};
+        int graph = -1, ov = -2;  // decided form (ov -1: no interface overlap to choose)
+        CgMode() {
+            for (auto& a : us)
+                for (double& v : a) v = 1e30;
+        }
     };
     std::map<int, CgMode> cg_mode;
     int ov_override = -1;  // >= 0: overlap for the A0 solves being launched (set by the CG driver)
@@ -2079,7 +2083,8 @@ static void cg_chunk(ddlr_prec* h, int nr, hipStream_t st, bool graph) {
         for (int c = 0; c < kCgChunk; ++c) lane_iteration(h, nr, st);
         return;
     }
-    auto it = h->cg_graphs.find(nr);
+    const int key = nr * 4 + h->ov_override + 1;  // the overlap choice is baked into the capture
+    auto it = h->cg_graphs.find(key);
     if (it == h->cg_graphs.end()) {
         h->capturing = true;
         HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
@@ -2094,7 +2099,7 @@ static void cg_chunk(ddlr_prec* h, int nr, hipStream_t st, bool graph) {
         h->capturing = false;
         hipGraphExec_t ge = nullptr;
         if (ok && ec == hipSuccess && g && hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) == hipSuccess) {
-            it = h->cg_graphs.emplace(nr, std::make_pair(g, ge)).first;
+            it = h->cg_graphs.emplace(key, std::make_pair(g, ge)).first;
         } else {
             (void)hipGetLastError();
             if (g) (void)hipGraphDestroy(g);
@@ -2115,61 +2120,68 @@ static void pcg_dev(ddlr_prec* h, int nr, const ddlr_solve_options& o, hipStream
     std::vector<double> tol2(nr, o.rtol * o.rtol);
     lane_admit(h, nr, start, tol2, maxit, st);
     // Launch form of the chunks, measured on the first solves of a column
-    // count unless DDLR_CG_GRAPH forces one: chunk boundaries are synchronous
-    // anyway, so whole chunks are timed on the host.  First, when the
-    // interface levels can run beside the block solve, two eager chunks each
-    // with and without that overlap (its benefit inside a CG iteration, where
-    // other forked work competes, can differ from the A0 solve's alone); then,
-    // with the better choice, a graph is captured and two replays are timed
-    // against the eager chunks: replay saves launch overhead, but the runtime
-    // may run a replayed graph's forked branches one after the other.
+    // count: chunk boundaries are synchronous anyway, so whole chunks are timed
+    // on the host.  Candidates: replayed graph or eager launches (unless
+    // DDLR_CG_GRAPH forces one), each with the interface levels beside or in
+    // line with the block solve when both are possible (inside an iteration the
+    // overlapped levels compete with other forked work, and a replayed graph
+    // may run forked branches one after the other, so neither the A0-only
+    // timing nor eager timing decides it).  Each candidate gets two timed
+    // chunks (a graph's capture chunk is not timed); the fastest is kept.
     ddlr_prec::CgMode& m = h->cg_mode[nr];
-    const bool measure = h->graph_mode == 2 && !h->prof;
     const bool can_ov = has_cpart(h) && h->nnarrow > 0 && h->overlap && h->side;
+    const int gfirst = h->graph_mode == 0 ? 0 : 1, glast = h->graph_mode == 1 ? 1 : 0;
+    const int ofirst = can_ov ? 1 : -1, olast = can_ov ? 0 : -1;
     for (int it = 0; it <= o.maxit; it += kCgChunk) {
-        bool graph = !h->prof && h->graph_mode != 0;
+        int g = gfirst, ov = ofirst;
         bool timed = false;
-        int slot = 1;
-        h->ov_override = -1;
-        if (measure) {
-            if (can_ov && m.ov < 0) {
-                slot = m.ne[1] < 2 ? 1 : 0;
-                h->ov_override = slot;
-                graph = false;
-                timed = true;
-            } else {
-                if (can_ov) slot = h->ov_override = m.ov;
-                if (m.ne[slot] < 2) {
-                    graph = false;
-                    timed = true;
-                } else if (m.ng < 3) {
-                    timed = m.ng >= 1;
-                } else {
-                    graph = m.graph_us <= m.eager_us[slot];
-                }
-            }
-        } else if (h->graph_mode == 2 && can_ov && m.ov >= 0) {
-            h->ov_override = m.ov;  // profiled solves keep the measured choice
+        if (h->prof) {
+            g = 0;  // per-launch events need eager launches; keep the measured overlap
+            ov = m.ov >= -1 ? m.ov : ofirst;
+        } else if (m.graph >= 0) {
+            g = m.graph;
+            ov = m.ov;
+        } else {
+            // first candidate (graph form descending, overlap descending) with fewer than two samples
+            bool found = false;
+            for (int gg = gfirst; gg >= glast && !found; --gg)
+                for (int oo = ofirst; oo >= olast && !found; --oo)
+                    if (m.timed[gg][oo + 1] < 2) {
+                        g = gg;
+                        ov = oo;
+                        found = true;
+                    }
+            timed = !(g == 1 && !m.captured[ov + 1]);
         }
+        h->ov_override = ov;
         const auto t0 = std::chrono::steady_clock::now();
-        cg_chunk(h, nr, st, graph);
+        cg_chunk(h, nr, st, g == 1 && h->graph_mode != 0);
         HIPCHK(hipMemcpyAsync(h->ws.done_host, h->ws.done, sizeof(int), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         h->ov_override = -1;
         const double us = std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
         const bool done = *h->ws.done_host != 0;
-        if (measure) {
-            if (graph && m.ng == 0) ++m.ng;  // the capture
-            if (timed && !done) {            // a chunk that ran all its iterations
-                if (graph) {
-                    m.graph_us = std::min(m.graph_us, us);
-                    ++m.ng;
-                } else {
-                    m.eager_us[slot] = std::min(m.eager_us[slot], us);
-                    ++m.ne[slot];
-                }
+        if (!h->prof && m.graph < 0) {
+            if (g == 1) m.captured[ov + 1] = true;
+            if (timed && !done) {  // a chunk that ran all its iterations
+                m.us[g][ov + 1] = std::min(m.us[g][ov + 1], us);
+                ++m.timed[g][ov + 1];
             }
-            if (can_ov && m.ov < 0 && m.ne[0] >= 2 && m.ne[1] >= 2) m.ov = m.eager_us[1] <= m.eager_us[0] ? 1 : 0;
+            bool all = true;
+            double best = 1e30;
+            for (int gg = gfirst; gg >= glast; --gg)
+                for (int oo = ofirst; oo >= olast; --oo) {
+                    all = all && m.timed[gg][oo + 1] >= 2;
+                    if (m.us[gg][oo + 1] < best) {
+                        best = m.us[gg][oo + 1];
+                        m.graph = gg;  // provisional; kept only when all are measured
+                        m.ov = oo;
+                    }
+                }
+            if (!all) {
+                m.graph = -1;
+                m.ov = -2;
+            }
         }
         if (done) break;
     }
@@ -2565,16 +2577,18 @@ ddlr_status ddlr_tune(ddlr_prec* h, int32_t nrhs, int32_t retune, ddlr_tuning* o
     }
     std::memset(out, 0, sizeof(*out));
     out->nrhs = nrhs;
-    out->cg_graph = h->graph_mode == 2 ? -1 : h->graph_mode;
+    out->cg_graph = -1;
     out->cg_overlap = -1;
     if (auto mi = h->cg_mode.find(nrhs); mi != h->cg_mode.end()) {
         const ddlr_prec::CgMode& m = mi->second;
-        const int slot = m.ov >= 0 ? m.ov : 1;
-        out->cg_overlap = m.ov;
-        if (m.ne[slot] > 0) out->cg_eager_us = (float)m.eager_us[slot];
-        if (m.ne[0] > 0) out->cg_eager_in_line_us = (float)m.eager_us[0];
-        if (m.ng > 1) out->cg_graph_us = (float)m.graph_us;
-        if (h->graph_mode == 2 && m.ne[slot] >= 2 && m.ng >= 3) out->cg_graph = m.graph_us <= m.eager_us[slot] ? 1 : 0;
+        out->cg_graph = m.graph;
+        out->cg_overlap = m.ov >= 0 ? m.ov : -1;
+        const int o = m.ov >= -1 ? m.ov + 1 : 2;  // the chosen overlap, else "beside"
+        auto val = [](double v) { return v < 1e29 ? (float)v : 0.0f; };
+        out->cg_eager_us = val(m.us[0][o]);
+        out->cg_graph_us = val(m.us[1][o]);
+        out->cg_eager_in_line_us = val(m.us[0][1]);
+        out->cg_graph_in_line_us = val(m.us[1][1]);
     }
     auto it = h->tune.find(nrhs);
     if (it == h->tune.end()) {  // batches: fixed shape

@@ -625,8 +625,9 @@ __global__ __launch_bounds__(256) void k_spmv_sell_il(int64_t n, int nrhs, const
         const int base = sptr[sl], width = (sptr[sl + 1] - base) >> 6;
         for (int j = 0; j < width; ++j) {
             const int q = base + j * kSell + lane;
-            const int c = col[q];
-            const double a = val[q];
+            // A streams through once: non-temporal loads keep the gathered x lines in L2
+            const int c = __builtin_nontemporal_load(col + q);
+            const double a = __builtin_nontemporal_load(val + q);
             const double* xc = x + (int64_t)c * S;
             double xv[S];
             if constexpr (S == 1) {
@@ -644,7 +645,7 @@ __global__ __launch_bounds__(256) void k_spmv_sell_il(int64_t n, int nrhs, const
         }
 #pragma unroll
         for (int r = 0; r < S; ++r)
-            if (r < nrhs) y[row + r * ldy] = acc[r];
+            if (r < nrhs) __builtin_nontemporal_store(acc[r], y + row + r * ldy);
     }
     if (part) {
         const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
