@@ -102,9 +102,13 @@ def roofline_of(D, h, q, nrhs, tbytes, prof):
         kname = f"k_trsv_ring<{t}, KW, {nt} threads>"
     else:
         kname = f"k_trsv_narrow<{t}>"
+    form = ("beside the interface-block solve on a side stream" if tn["cg_overlap"] == 1
+            else "alone (interface-block solve in line)")
     return {"bound": "hbm", "kernel": kname, "columns_per_workgroup": R, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "bytes_per_launch": by,
-            "avg_launch_us": round(avg_s * 1e6, 2), "launches": launches}
+            "avg_launch_us": round(avg_s * 1e6, 2), "launches": launches,
+            "runs": f"{form}; CG chunks {'replayed from graphs' if tn['cg_graph'] == 1 else 'launched eagerly'} "
+                    "in the timed solves (the library's measured choice)"}
 
 
 def breakdown_of(D, prof, K, step_ms):

@@ -290,7 +290,9 @@ ddlr_status ddlr_extend_lowrank(ddlr_prec *h, int32_t k, int32_t more_steps, int
  * candidate: replayed and eager, each with the interface block's solve beside
  * and in line with the block solve (that overlap competes with other forked
  * work inside an iteration and a replayed graph may serialise it, so its
- * A0-only timing above does not decide it for PCG); the fastest is kept.
+ * A0-only timing above does not decide it for PCG); the fastest is kept, but
+ * replayed chunks with the interface solve in line stay unless another
+ * candidate is more than 3 % faster (chunk timings vary by a few percent).
  * cg_* below report that measurement. */
 typedef struct {
     int32_t nrhs;            /* column count the shape is for */

@@ -2178,6 +2178,12 @@ static void pcg_dev(ddlr_prec* h, int nr, const ddlr_solve_options& o, hipStream
                         m.ov = oo;
                     }
                 }
+            // the plain form (replayed if allowed, interface solve in line) stays
+            // unless another is clearly faster: chunk timings vary by a few percent
+            if (m.us[gfirst][olast + 1] <= best / 0.97) {
+                m.graph = gfirst;
+                m.ov = olast;
+            }
             if (!all) {
                 m.graph = -1;
                 m.ov = -2;
