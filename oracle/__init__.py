@@ -54,6 +54,8 @@ def _load():
         lib.orc_lowrank.argtypes = [P, C.c_int, C.c_int, C.c_int, C.c_int, P]
         lib.orc_lowrank_ctl.restype = C.c_int
         lib.orc_lowrank_ctl.argtypes = [P, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, C.c_int, P]
+        lib.orc_lowrank_gk.restype = C.c_int
+        lib.orc_lowrank_gk.argtypes = [P, C.c_int, C.c_int, P]
         lib.orc_extend.restype = C.c_int
         lib.orc_extend.argtypes = [P, C.c_int, C.c_int, C.c_int, C.c_double, C.c_int]
         lib.orc_lanczos_record.argtypes = [P, P, P, P]
@@ -204,6 +206,17 @@ class Oracle:
         if st != OK:
             raise OracleError(st, "lowrank")
         self.variant, self.k = int(variant), int(k)
+        self.spd = bool(_lib.orc_size(self._h, 10))
+        return self
+
+    def lowrank_gk(self, k, m, v0):
+        """DDLR-2 with U_k, V_k from m steps of the bidiagonalisation of
+        A0^{-1} E (Sec. 4.3 alternative)."""
+        v0 = np.ascontiguousarray(v0, dtype=np.float64)
+        st = _lib.orc_lowrank_gk(self._h, int(k), int(m), _p(v0))
+        if st != OK:
+            raise OracleError(st, "lowrank_gk")
+        self.variant, self.k = 2, int(k)
         self.spd = bool(_lib.orc_size(self._h, 10))
         return self
 

@@ -961,6 +961,8 @@ static int pivots_positive(const orc_t *o) {
     return o->csolve ? o->x_spd : 1;
 }
 
+static int ddlr2_hk(orc_t *o, int k, const double *EV);
+
 /* Low-rank part of the preconditioner from the Lanczos run (Sec. 3.2 / 3.3). */
 static int build_lowrank(orc_t *o, int variant, int k, int thetamode) {
     const int m = o->msteps;
@@ -1007,6 +1009,20 @@ static int build_lowrank(orc_t *o, int variant, int k, int thetamode) {
             e_mul(o, QY + s * (int64_t)j, EV + n * (int64_t)j);
             a0_solve(o, EV + n * (int64_t)j, o->U + n * (int64_t)j);
         }
+        free(QY);
+        st = ddlr2_hk(o, k, EV);
+        free(EV);
+    }
+    return st;
+}
+
+/* H_k = (I - U_k^T E V_k)^{-1} from o->U and EV = E V_k (both n x k), the
+ * product symmetrised; the preconditioner of eq. (Form2a) is SPD only if
+ * I - sym(K) is (Lemma on H_k). */
+static int ddlr2_hk(orc_t *o, int k, const double *EV) {
+    const int64_t n = o->n;
+    int st = ORC_OK;
+    {
         double *K = xcalloc((int64_t)k * k, sizeof(double));
         for (int j = 0; j < k; ++j)
             for (int i = 0; i < k; ++i) K[i + j * k] = dot(o->U + n * (int64_t)i, EV + n * (int64_t)j, n);
@@ -1033,7 +1049,7 @@ static int build_lowrank(orc_t *o, int variant, int k, int thetamode) {
                 }
             }
         }
-        free(K); free(Mx); free(EV); free(QY);
+        free(K); free(Mx);
         o->spd = (st == ORC_OK) && pivots_positive(o);
         o->theta = 0.0;
         o->c0 = 0.0;
@@ -1224,6 +1240,148 @@ int orc_lowrank_ctl(orc_t *o, int variant, int k, int m, int check, double eps, 
     return build_lowrank(o, variant, k, thetamode);
 }
 
+/* DDLR-2 with U_k and V_k from the Lanczos (Golub-Kahan) bidiagonalisation of
+ * B = A0^{-1} E (n x s), the alternative build named in Sec. 4.3 (Golub & Van
+ * Loan, Sec. 10.4).  From a unit q_1 (the interface entries of v0):
+ *   p_j = (B q_j - beta_{j-1} p_{j-1}) / alpha_j,
+ *   q_{j+1} = (B^T p_j - alpha_j q_j) / beta_j,   B^T = E^T A0^{-1},
+ * with alpha_j, beta_j the norms and full reorthogonalisation of p_j against
+ * p_1..p_{j-1} and of q_{j+1} against q_1..q_j (classical Gram-Schmidt
+ * twice), so B Q_m = P_m B_m with B_m upper bidiagonal (alpha on the
+ * diagonal, beta above).  The right singular vectors Z of B_m are the
+ * eigenvectors of B_m^T B_m (cyclic Jacobi; eigenvalues sigma^2 descending,
+ * largest-|.| entry of each vector positive); then V_k = Q_m Z_k and
+ * U_k = P_m B_m Z_k (= B V_k), and H_k as in the Lanczos route.  Two A0
+ * solves per step and none afterwards.  The run stops early when alpha_j or
+ * beta_j <= 1e-12 times the largest alpha so far.  The record keeps alpha,
+ * beta and the sigma^2 (Ritz values of E^T A0^{-2} E). */
+int orc_lowrank_gk(orc_t *o, int k, int m, const double *v0) {
+    const int64_t s = o->s, n = o->n;
+    if (k < 1 || k + 1 > s || m < k + 1) return ORC_E_INVALID;
+    if (m > s) m = (int)s;
+    double *Q = xcalloc(s * (int64_t)(m + 1), sizeof(double));
+    double *P = xcalloc(n * (int64_t)m, sizeof(double));
+    double *al = xcalloc(m, sizeof(double)), *be = xcalloc(m, sizeof(double));
+    double *c = xcalloc(m + 1, sizeof(double));
+    double *t = xcalloc(n, sizeof(double)), *w = xcalloc(s, sizeof(double));
+    for (int64_t y = 0; y < s; ++y) Q[y] = v0[o->perm[o->m + y]];
+    const double nq = nrm2(Q, s);
+    for (int64_t y = 0; y < s; ++y) Q[y] /= nq;
+    double amax = 0.0;
+    int meff = 0;
+    for (int j = 0; j < m; ++j) {
+        double *pj = P + n * (int64_t)j;
+        const double *qj = Q + s * (int64_t)j;
+        e_mul(o, qj, t);
+        a0_solve(o, t, pj);  /* B q_j */
+        if (j > 0) {
+            const double *pp = P + n * (int64_t)(j - 1);
+            for (int64_t i = 0; i < n; ++i) pj[i] -= be[j - 1] * pp[i];
+        }
+        for (int pass = 0; pass < 2; ++pass) {
+            for (int l = 0; l < j; ++l) c[l] = dot(P + n * (int64_t)l, pj, n);
+            for (int l = 0; l < j; ++l) {
+                const double *pl = P + n * (int64_t)l;
+                for (int64_t i = 0; i < n; ++i) pj[i] -= c[l] * pl[i];
+            }
+        }
+        al[j] = nrm2(pj, n);
+        if (al[j] > amax) amax = al[j];
+        if (!(al[j] > 1e-12 * amax)) break;
+        for (int64_t i = 0; i < n; ++i) pj[i] /= al[j];
+        a0_solve(o, pj, t);
+        et_mul(o, t, w);  /* B^T p_j */
+        for (int64_t i = 0; i < s; ++i) w[i] -= al[j] * qj[i];
+        for (int pass = 0; pass < 2; ++pass) {
+            for (int l = 0; l <= j; ++l) c[l] = dot(Q + s * (int64_t)l, w, s);
+            for (int l = 0; l <= j; ++l) {
+                const double *ql = Q + s * (int64_t)l;
+                for (int64_t i = 0; i < s; ++i) w[i] -= c[l] * ql[i];
+            }
+        }
+        be[j] = nrm2(w, s);
+        meff = j + 1;
+        if (!(be[j] > 1e-12 * amax)) break;
+        double *qn = Q + s * (int64_t)(j + 1);
+        for (int64_t i = 0; i < s; ++i) qn[i] = w[i] / be[j];
+    }
+    free(c); free(t); free(w);
+    int st = ORC_OK;
+    if (meff < k + 1) st = ORC_E_LANCZOS;
+    if (st == ORC_OK) {
+        /* B_m^T B_m: diagonal alpha_j^2 + beta_{j-1}^2, off-diagonal alpha_j beta_j */
+        const int mm = meff;
+        double *T = xcalloc((int64_t)mm * mm, sizeof(double));
+        double *V = xcalloc((int64_t)mm * mm, sizeof(double));
+        double *ev = xcalloc(mm, sizeof(double));
+        for (int i = 0; i < mm; ++i) {
+            T[i + i * mm] = al[i] * al[i] + (i > 0 ? be[i - 1] * be[i - 1] : 0.0);
+            if (i + 1 < mm) T[i + 1 + i * mm] = T[i + (i + 1) * mm] = al[i] * be[i];
+        }
+        jacobi_eig(mm, T, ev, V);
+        int *idx = xcalloc(mm, sizeof(int));
+        for (int i = 0; i < mm; ++i) idx[i] = i;
+        for (int i = 1; i < mm; ++i) {  /* insertion sort, descending, stable */
+            int v = idx[i], q = i;
+            while (q > 0 && ev[idx[q - 1]] < ev[v]) { idx[q] = idx[q - 1]; --q; }
+            idx[q] = v;
+        }
+        double *Z = xcalloc((int64_t)mm * k, sizeof(double));
+        for (int c2 = 0; c2 < k; ++c2) {
+            const double *src = V + (int64_t)idx[c2] * mm;
+            int big = 0;
+            for (int r = 1; r < mm; ++r) if (fabs(src[r]) > fabs(src[big])) big = r;
+            const double sg = src[big] < 0 ? -1.0 : 1.0;
+            for (int r = 0; r < mm; ++r) Z[r + (int64_t)c2 * mm] = sg * src[r];
+        }
+        /* record: alpha, beta, sigma^2 */
+        free(o->ta); free(o->tb); free(o->ritz);
+        o->ta = xcalloc(mm, sizeof(double));
+        o->tb = xcalloc(mm, sizeof(double));
+        o->ritz = xcalloc(mm, sizeof(double));
+        memcpy(o->ta, al, mm * sizeof(double));
+        memcpy(o->tb, be, mm * sizeof(double));
+        for (int i = 0; i < mm; ++i) o->ritz[i] = ev[idx[i]];
+        o->msteps = mm;
+        o->qcap = 0;
+        free(o->Q);
+        o->Q = NULL;
+        o->lvariant = 0;  /* the stored run cannot be continued by orc_extend */
+        /* V_k = Q_m Z_k; W = B_m Z_k (m x k); U_k = P_m W */
+        double *Vk = xcalloc(s * (int64_t)k, sizeof(double));
+        double *W = xcalloc((int64_t)mm * k, sizeof(double));
+        for (int c2 = 0; c2 < k; ++c2) {
+            for (int l = 0; l < mm; ++l) {
+                const double zl = Z[l + (int64_t)c2 * mm];
+                const double *ql = Q + s * (int64_t)l;
+                double *dst = Vk + s * (int64_t)c2;
+                for (int64_t i = 0; i < s; ++i) dst[i] += zl * ql[i];
+            }
+            for (int r = 0; r < mm; ++r)
+                W[r + (int64_t)c2 * mm] = al[r] * Z[r + (int64_t)c2 * mm] +
+                                          (r + 1 < mm ? be[r] * Z[r + 1 + (int64_t)c2 * mm] : 0.0);
+        }
+        free(o->U); free(o->lam); free(o->dvec); free(o->Hk);
+        o->lam = NULL; o->dvec = NULL; o->Hk = NULL;
+        o->U = xcalloc(n * (int64_t)k, sizeof(double));
+        for (int c2 = 0; c2 < k; ++c2)
+            for (int l = 0; l < mm; ++l) {
+                const double wl = W[l + (int64_t)c2 * mm];
+                const double *pl = P + n * (int64_t)l;
+                double *dst = o->U + n * (int64_t)c2;
+                for (int64_t i = 0; i < n; ++i) dst[i] += wl * pl[i];
+            }
+        o->variant = 2;
+        o->k = k;
+        double *EV = xcalloc(n * (int64_t)k, sizeof(double));
+        for (int c2 = 0; c2 < k; ++c2) e_mul(o, Vk + s * (int64_t)c2, EV + n * (int64_t)c2);
+        st = ddlr2_hk(o, k, EV);
+        free(EV); free(Vk); free(W); free(Z); free(idx); free(T); free(V); free(ev);
+    }
+    free(Q); free(P); free(al); free(be);
+    return st;
+}
+
 int orc_lowrank(orc_t *o, int variant, int k, int m, int thetamode, const double *v0) {
     return orc_lowrank_ctl(o, variant, k, m, 0, 0.0, thetamode, v0);
 }
@@ -1247,7 +1405,9 @@ void orc_lanczos_record(const orc_t *o, double *ta, double *tb, double *ritzv) {
 }
 
 /* Q_m (s x m, internal interface order) */
-void orc_lanczos_basis(const orc_t *o, double *Q) { memcpy(Q, o->Q, o->s * (int64_t)o->msteps * sizeof(double)); }
+void orc_lanczos_basis(const orc_t *o, double *Q) {
+    if (o->Q) memcpy(Q, o->Q, o->s * (int64_t)o->msteps * sizeof(double));  /* none after a bidiagonalisation build */
+}
 
 /* Low-rank data in user order: DDLR-1 U is n x k with zero interior rows and
  * aux = lambda (k) then theta; DDLR-2 U is n x k and aux = H_k (k x k). */

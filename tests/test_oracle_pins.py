@@ -770,3 +770,57 @@ def test_cinv_spd_certificate(name):
     assert np.abs(np.linalg.eigvals(R)).max() <= o.cinv_rinf + 1e-12
     assert spd == (o.cinv_rinf < 1.0) and spd
     assert np.linalg.eigvalsh(X.toarray()).min() > 0.0
+
+
+# ------------------ DDLR-2 by bidiagonalisation of A0^{-1} E (Sec. 4.3 alternative)
+
+def test_gk_full_run_gives_singular_values():
+    """A full bidiagonalisation (m = s) recovers the singular values of
+    A0^{-1} E (LAPACK SVD of the dense operator); sigma^2 are recorded."""
+    A, part, p = tiny_irregular()
+    o = Oracle(A, part, p, factor=FACTOR_EXACT)
+    k = 4
+    o.lowrank_gk(k, o.s, w.lanczos_start(A.n, 5))
+    _, _, sv = _ddlr2_from_svd(o, k)
+    ta, tb, rz = o.lanczos_record()
+    assert len(rz) == o.s
+    assert np.abs(np.sqrt(np.maximum(rz, 0)) - sv[: len(rz)]).max() <= 1e-10 * sv[0]
+
+
+def test_gk_build_matches_svd_and_spectral_theorem():
+    """The bidiagonalisation build gives the U_k H_k U_k^T of the SVD of
+    A0^{-1} E (as the Lanczos build does) and the DDLR-2 theorem holds:
+    0 < eta <= 1 with n-s+k unit eigenvalues."""
+    A, part, p = tiny_irregular()
+    o = Oracle(A, part, p, factor=FACTOR_EXACT)
+    k = 4
+    o.lowrank_gk(k, o.s, w.lanczos_start(A.n, 5))
+    U, Hk = o.get_lowrank()
+    Uk_ref, Hk_ref, sv = _ddlr2_from_svd(o, k)
+    perm, *_ = o.ordering()
+    C_or = (U @ Hk @ U.T)[np.ix_(perm, perm)]
+    C_ref = Uk_ref @ Hk_ref @ Uk_ref.T
+    assert np.abs(C_or - C_ref).max() <= 1e-9 * np.abs(C_ref).max()
+    ev = np.linalg.eigvals(A.to_dense() @ _dense_minv(o)).real
+    assert ev.min() > 0 and ev.max() <= 1 + 1e-9
+    assert (np.abs(ev - 1) <= 1e-8).sum() == o.n - o.s + k
+
+
+def test_gk_short_run_close_to_lanczos_route():
+    """With incomplete factors and m = 2k steps both builds approximate the
+    same dominant singular subspace: the two preconditioners agree closely,
+    and CG converges with either."""
+    cfg = w.config("c1")
+    A = cfg["A"]
+    v0 = w.lanczos_start(A.n, 0)
+    og = Oracle(A, cfg["part"], cfg["p"]).lowrank_gk(cfg["k"], cfg["m"], v0)
+    ol = Oracle(A, cfg["part"], cfg["p"]).lowrank(2, cfg["k"], cfg["m"], v0)
+    rg, rl = og.lanczos_record()[2], ol.lanczos_record()[2]
+    # sigma^2 of the bidiagonal and the Ritz values of E^T A0^{-2} E: both Krylov
+    # approximations of the same largest eigenvalues
+    assert np.abs(rg[:3] - rl[:3]).max() <= 1e-6 * rl[0]
+    b, _ = w.rhs_from_solution(A, 0, 2)
+    xg, ig = og.pcg(b)
+    xl, il = ol.pcg(b)
+    assert ig["status"] == 0 and il["status"] == 0 and og.spd
+    assert np.all(np.abs(ig["its"] - il["its"]) <= 2)
