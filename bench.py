@@ -194,7 +194,8 @@ def run_single(args, D, w, torch):
         t0 = time.perf_counter()
         h = D.ddlr_setup(A, cfg["part"], p, k, args.variant, lanczos_steps=m, lanczos_start=v0, precision=prec,
                          factor=factor, csolve=D.CSOLVE_MR if args.csolve == "mr" else D.CSOLVE_FACTOR,
-                         alpha=alpha_for(args))
+                         alpha=alpha_for(args),
+                         lowrank_build=D.BUILD_BIDIAG if args.lowrank_build == "bidiag" else D.BUILD_LANCZOS)
         torch.cuda.synchronize()
         setup_s = time.perf_counter() - t0
         q = D.ddlr_query(h)
@@ -241,7 +242,8 @@ def run_single(args, D, w, torch):
         "config": {"workload": f"{args.config}: {workload}, DDLR-{args.variant} k={k}, {m} Lanczos steps, "
                                f"{nrhs} rhs per solve batch, {krylov} to 1e-6"
                                + (", C_alpha by the MR approximate inverse" if args.csolve == "mr" else "")
-                               + (f", alpha={alpha_for(args):g}" if alpha_for(args) != 1.0 else ""),
+                               + (f", alpha={alpha_for(args):g}" if alpha_for(args) != 1.0 else "")
+                               + (", U_k V_k by bidiagonalisation" if args.lowrank_build == "bidiag" else ""),
                    "n": n, "nrhs": nrhs, "k": k, "p": p, "variant": args.variant, "csolve": args.csolve},
         "latency_ms": {"p50": pct(mixed["lat"], 50), "p99": pct(mixed["lat"], 99),
                        "note": f"per solve call; the {nrhs} right-hand sides of a batch complete together"},
@@ -441,6 +443,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "u1"])
     ap.add_argument("--variant", type=int, default=1)
+    ap.add_argument("--lowrank-build", default="lanczos", choices=["lanczos", "bidiag"],
+                    help="DDLR-2 only: U_k, V_k by Lanczos on E^T A0^-2 E, or by bidiagonalisation of A0^-1 E")
     ap.add_argument("--csolve", default="factor", choices=["factor", "mr"],
                     help="C_alpha solver: its incomplete factor, or the MR approximate inverse (3 steps, "
                          "drop tolerance 0.01, 20 entries per column)")

@@ -71,6 +71,14 @@ typedef enum { DDLR_CORDER_MULTICOLOR = 0, DDLR_CORDER_NATURAL = 1 } ddlr_corder
  * reproducible bit for bit.  X counts as SPD when ||I - C_alpha X||_inf < 1
  * (largest absolute row sum; it bounds the spectral radius of I - C_alpha X). */
 typedef enum { DDLR_CSOLVE_FACTOR = 0, DDLR_CSOLVE_MR = 1 } ddlr_csolve;
+/* How DDLR-2's U_k and V_k are computed (Sec. 4.3): Lanczos on
+ * E^T A0^{-2} E, then U_k = A0^{-1} E V_k (k more solves); or the Lanczos
+ * (Golub-Kahan) bidiagonalisation of A0^{-1} E, which gives both at once:
+ * B Q_m = P_m B_m, Z_k = leading right singular vectors of B_m,
+ * V_k = Q_m Z_k, U_k = P_m B_m Z_k.  Both use full reorthogonalisation;
+ * the bidiagonalisation keeps the n x m basis P_m during the build and its
+ * run cannot be continued by ddlr_extend_lowrank. */
+typedef enum { DDLR_BUILD_LANCZOS = 0, DDLR_BUILD_BIDIAG = 1 } ddlr_lowrank_build;
 typedef enum { DDLR_FP64 = 0, DDLR_FP32 = 1, DDLR_FP32_UK_BF16 = 2 } ddlr_precision;
 
 /* Symmetric matrix, host memory, full storage, sorted columns. */
@@ -83,7 +91,7 @@ typedef struct {
 
 typedef struct {
     double alpha;          /* splitting scale of eq. (EF); default 1 */
-    int32_t lanczos_steps; /* Lanczos steps m; 0 -> 2k */
+    int32_t lanczos_steps; /* Lanczos steps m (k+1..1024); 0 -> 2k */
     int32_t theta;         /* ddlr_theta; default lambda_{k+1} (Sec. 5) */
     int32_t factor;        /* ddlr_factor: IC(0) (positive pivots) or ILDL(0) (nonzero pivots) */
     int32_t corder;        /* ddlr_corder: order of the interface block inside C_alpha's factor */
@@ -92,7 +100,7 @@ typedef struct {
     int32_t no_autotune;   /* 0: tune launch shapes on the first solve with a column count (default) */
     int32_t lanczos_check; /* 0: lanczos_steps fixed steps; > 0: the control of Sec. 5 -- eq. (converge) on the
                               sum of the k largest Ritz values, tested every lanczos_check steps (paper: 10) */
-    int32_t lanczos_max;   /* with lanczos_check > 0: step limit; 0 -> 5k (Sec. 5) */
+    int32_t lanczos_max;   /* with lanczos_check > 0: step limit; 0 -> 5k (Sec. 5); steps are at most 1024 */
     double lanczos_tol;    /* with lanczos_check > 0: tolerance of eq. (converge); 0 -> 1e-4 (Sec. 5) */
     uint64_t seed;                /* Lanczos start vector when lanczos_start is NULL */
     const double *lanczos_start;  /* host, length n, user order: its interface entries form q_1 */
@@ -100,7 +108,8 @@ typedef struct {
     int32_t cinv_iters;    /* DDLR_CSOLVE_MR: MR steps (>= 0); default 3 */
     double cinv_tol;       /* DDLR_CSOLVE_MR: drop tolerance relative to the column norm (>= 0); default 0.01 */
     int32_t cinv_lfil;     /* DDLR_CSOLVE_MR: kept off-diagonal entries per column (>= 0); default 20 */
-    int32_t reserved0;
+    int32_t lowrank_build; /* ddlr_lowrank_build; DDLR_BUILD_BIDIAG needs DDLR_2 and lanczos_check = 0; default
+                              DDLR_BUILD_LANCZOS */
 } ddlr_options;
 
 typedef struct {

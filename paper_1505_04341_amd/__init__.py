@@ -25,6 +25,7 @@ FACTOR_IC0, FACTOR_ILDL0 = 0, 1
 CORDER_MULTICOLOR, CORDER_NATURAL = 0, 1
 FP64, FP32, FP32_UK_BF16 = 0, 1, 2
 CSOLVE_FACTOR, CSOLVE_MR = 0, 1
+BUILD_LANCZOS, BUILD_BIDIAG = 0, 1
 
 
 class ddlr_csr(C.Structure):
@@ -37,7 +38,7 @@ class ddlr_options(C.Structure):
                 ("no_autotune", C.c_int32), ("lanczos_check", C.c_int32), ("lanczos_max", C.c_int32),
                 ("lanczos_tol", C.c_double), ("seed", C.c_uint64), ("lanczos_start", C.c_void_p),
                 ("csolve", C.c_int32), ("cinv_iters", C.c_int32), ("cinv_tol", C.c_double), ("cinv_lfil", C.c_int32),
-                ("reserved0", C.c_int32)]
+                ("lowrank_build", C.c_int32)]
 
 
 class ddlr_tuning(C.Structure):
@@ -205,7 +206,8 @@ def ddlr_setup(A, part, p: int, k: int, variant: int = DDLR_1, *, alpha: float =
                theta: int = THETA_LAMBDA_K1, factor: int = FACTOR_IC0, corder: int = CORDER_MULTICOLOR,
                precision: int = FP64, device: int = 0, seed: int = 0, lanczos_start=None,
                autotune: bool = True, lanczos_check: int = 0, lanczos_max: int = 0, lanczos_tol: float = 0.0,
-               csolve: int = CSOLVE_FACTOR, cinv_iters: int = 3, cinv_tol: float = 0.01, cinv_lfil: int = 20) -> Prec:
+               csolve: int = CSOLVE_FACTOR, cinv_iters: int = 3, cinv_tol: float = 0.01, cinv_lfil: int = 20,
+               lowrank_build: int = BUILD_LANCZOS) -> Prec:
     """Builds the preconditioner. A: object with n, rowptr (int64), col (int32), val (float64)."""
     lib = load_library()
     rp = np.ascontiguousarray(A.rowptr, dtype=np.int64)
@@ -222,6 +224,7 @@ def ddlr_setup(A, part, p: int, k: int, variant: int = DDLR_1, *, alpha: float =
     opt.lanczos_check, opt.lanczos_max, opt.lanczos_tol = int(lanczos_check), int(lanczos_max), float(lanczos_tol)
     opt.csolve, opt.cinv_iters, opt.cinv_tol, opt.cinv_lfil = int(csolve), int(cinv_iters), float(cinv_tol), int(
         cinv_lfil)
+    opt.lowrank_build = int(lowrank_build)
     v0 = None
     if lanczos_start is not None:
         v0 = np.ascontiguousarray(lanczos_start, dtype=np.float64)

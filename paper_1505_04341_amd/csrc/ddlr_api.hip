@@ -273,7 +273,8 @@ namespace {
 // ------------------------------------------------------------ device upload
 
 constexpr int kRing64 = 8192, kRing32 = 16384;  // LDS ring rows: 64 KB either way
-constexpr int kRingThin = 2048;                  // widest window the untuned 64/256-thread choice takes
+constexpr int kRingThin = 2048;
+constexpr int kMaxLanczos = 1024;  // Lanczos / bidiagonalisation steps (k_gemv_sub stages 1024 coefficients)                  // widest window the untuned 64/256-thread choice takes
 
 // Device-order arrays of one preconditioner (or of several merged), built on
 // the host before upload.
@@ -1445,6 +1446,80 @@ void lanczos_advance(ddlr_prec* h, int m_max, int check, double eps, int k) {
     lanczos_sync(h, m_max);
 }
 
+// Reduced-precision copies and the MFMA/BF16 layouts of U_k
+void lowrank_copies(ddlr_prec* h, int k) {
+    hipStream_t st = nullptr;
+    if (h->precision != DDLR_FP64) {
+        h->f32.U = h->lrmem.alloc<float>((size_t)h->urows * k);
+        hipLaunchKernelGGL((k_cast<double, float>), dim3(grid_for(h->urows * k)), dim3(256), 0, st, h->urows * k, 1,
+                           h->f64.U, (int64_t)0, h->f32.U, (int64_t)0, nullptr);
+        LAUNCHCHK();
+    }
+    make_bf16_basis(h);
+    make_tiled_basis(h);
+}
+
+// DDLR-2 from U_k (column-major n x k, device order) and EV = E V_k:
+// K = U_k^T E V_k, H_k = (I - sym(K))^{-1} by Cholesky (not SPD: error), U_k
+// stored row-major.
+void ddlr2_finish(ddlr_prec* h, int k, const double* Ucm, const double* EV, DMem& tmp) {
+    const int64_t n = h->plan.n;
+    hipStream_t st = nullptr;
+    h->urows = n;
+    const int gblk = 512;
+    double* gp = tmp.alloc<double>((size_t)gblk * k * k);
+    hipLaunchKernelGGL(k_gram, dim3(gblk), dim3(256), 0, st, n, k, Ucm, n, EV, n, gp);
+    LAUNCHCHK();
+    std::vector<double> gh((size_t)gblk * k * k);
+    HIPCHK(hipMemcpy(gh.data(), gp, gh.size() * sizeof(double), hipMemcpyDeviceToHost));
+    std::vector<double> K((size_t)k * k, 0.0);
+    for (int b = 0; b < gblk; ++b)
+        for (int q = 0; q < k * k; ++q) K[q] += gh[(size_t)b * k * k + q];
+    // I - (K + K^T)/2, Cholesky (lower, column-major), then its inverse
+    std::vector<double> Mx((size_t)k * k);
+    for (int j = 0; j < k; ++j)
+        for (int i = 0; i < k; ++i)
+            Mx[i + j * k] = (i == j ? 1.0 : 0.0) - 0.5 * (K[i * k + j] + K[j * k + i]);
+    for (int j = 0; j < k; ++j) {
+        double d = Mx[j + j * k];
+        for (int t = 0; t < j; ++t) d -= Mx[j + t * k] * Mx[j + t * k];
+        if (!(d > 0.0)) {
+            tmp.release();
+            throw SetupError{DDLR_E_NOT_SPD, "I - U_k^T E V_k is not SPD (DDLR-2 preconditioner not SPD)"};
+        }
+        d = std::sqrt(d);
+        Mx[j + j * k] = d;
+        for (int i = j + 1; i < k; ++i) {
+            double v = Mx[i + j * k];
+            for (int t = 0; t < j; ++t) v -= Mx[i + t * k] * Mx[j + t * k];
+            Mx[i + j * k] = v / d;
+        }
+    }
+    h->H_h.assign((size_t)k * k, 0.0);
+    for (int c = 0; c < k; ++c) {
+        std::vector<double> e(k, 0.0);
+        e[c] = 1.0;
+        for (int i = 0; i < k; ++i) {
+            double v = e[i];
+            for (int t = 0; t < i; ++t) v -= Mx[i + t * k] * e[t];
+            e[i] = v / Mx[i + i * k];
+        }
+        for (int i = k - 1; i >= 0; --i) {
+            double v = e[i];
+            for (int t = i + 1; t < k; ++t) v -= Mx[t + i * k] * e[t];
+            e[i] = v / Mx[i + i * k];
+        }
+        for (int i = 0; i < k; ++i) h->H_h[i + (size_t)c * k] = e[i];
+    }
+    h->spd = h->pivots_positive;
+    h->f64.U = h->lrmem.alloc<double>((size_t)n * k);
+    hipLaunchKernelGGL(k_to_rowmajor<double>, dim3(grid_for(n * k)), dim3(256), 0, st, n, k, Ucm, n, h->f64.U);
+    LAUNCHCHK();
+    h->Hk = h->lrmem.upload(h->H_h);
+    h->theta = 0.0;
+    h->c0 = 0.0;
+}
+
 // U_k and G_k^{-1} (DDLR-1) or H_k (DDLR-2) of rank k from the run's Ritz pairs.
 void lanczos_finish(ddlr_prec* h, int k, int theta_mode) {
     HostPlan& P = h->plan;
@@ -1518,67 +1593,160 @@ void lanczos_finish(ddlr_prec* h, int k, int theta_mode) {
                            V, s, (const double*)nullptr, 0, EV, n, nullptr);
         LAUNCHCHK();
         a0_solve_dev<double, double, double>(h, h->f64, k, EV, n, Ucm, n, st, nullptr);
-        const int gblk = 512;
-        double* gp = tmp.alloc<double>((size_t)gblk * k * k);
-        hipLaunchKernelGGL(k_gram, dim3(gblk), dim3(256), 0, st, n, k, Ucm, n, EV, n, gp);
-        LAUNCHCHK();
-        std::vector<double> gh((size_t)gblk * k * k);
-        HIPCHK(hipMemcpy(gh.data(), gp, gh.size() * sizeof(double), hipMemcpyDeviceToHost));
-        std::vector<double> K((size_t)k * k, 0.0);
-        for (int b = 0; b < gblk; ++b)
-            for (int q = 0; q < k * k; ++q) K[q] += gh[(size_t)b * k * k + q];
-        // I - (K + K^T)/2, Cholesky (lower, column-major), then its inverse
-        std::vector<double> Mx((size_t)k * k);
-        for (int j = 0; j < k; ++j)
-            for (int i = 0; i < k; ++i)
-                Mx[i + j * k] = (i == j ? 1.0 : 0.0) - 0.5 * (K[i * k + j] + K[j * k + i]);
-        for (int j = 0; j < k; ++j) {
-            double d = Mx[j + j * k];
-            for (int t = 0; t < j; ++t) d -= Mx[j + t * k] * Mx[j + t * k];
-            if (!(d > 0.0)) {
-                tmp.release();
-                throw SetupError{DDLR_E_NOT_SPD, "I - U_k^T E V_k is not SPD (DDLR-2 preconditioner not SPD)"};
-            }
-            d = std::sqrt(d);
-            Mx[j + j * k] = d;
-            for (int i = j + 1; i < k; ++i) {
-                double v = Mx[i + j * k];
-                for (int t = 0; t < j; ++t) v -= Mx[i + t * k] * Mx[j + t * k];
-                Mx[i + j * k] = v / d;
-            }
-        }
-        h->H_h.assign((size_t)k * k, 0.0);
-        for (int c = 0; c < k; ++c) {
-            std::vector<double> e(k, 0.0);
-            e[c] = 1.0;
-            for (int i = 0; i < k; ++i) {
-                double v = e[i];
-                for (int t = 0; t < i; ++t) v -= Mx[i + t * k] * e[t];
-                e[i] = v / Mx[i + i * k];
-            }
-            for (int i = k - 1; i >= 0; --i) {
-                double v = e[i];
-                for (int t = i + 1; t < k; ++t) v -= Mx[t + i * k] * e[t];
-                e[i] = v / Mx[i + i * k];
-            }
-            for (int i = 0; i < k; ++i) h->H_h[i + (size_t)c * k] = e[i];
-        }
-        h->spd = h->pivots_positive;
-        h->f64.U = h->lrmem.alloc<double>((size_t)n * k);
-        hipLaunchKernelGGL(k_to_rowmajor<double>, dim3(grid_for(n * k)), dim3(256), 0, st, n, k, Ucm, n, h->f64.U);
-        LAUNCHCHK();
-        h->Hk = h->lrmem.upload(h->H_h);
-        h->theta = 0.0;
-        h->c0 = 0.0;
+        ddlr2_finish(h, k, Ucm, EV, tmp);
     }
-    if (h->precision != DDLR_FP64) {
-        h->f32.U = h->lrmem.alloc<float>((size_t)h->urows * k);
-        hipLaunchKernelGGL((k_cast<double, float>), dim3(grid_for(h->urows * k)), dim3(256), 0, st, h->urows * k, 1,
-                           h->f64.U, (int64_t)0, h->f32.U, (int64_t)0, nullptr);
+    lowrank_copies(h, k);
+    HIPCHK(hipDeviceSynchronize());
+    tmp.release();
+}
+
+// DDLR-2 with U_k and V_k from m steps of the Lanczos (Golub-Kahan)
+// bidiagonalisation of B = A0^{-1} E, the alternative build of Sec. 4.3
+// (Golub & Van Loan, Sec. 10.4).  From the unit interface vector q_1:
+//   p_j = (B q_j - beta_{j-1} p_{j-1}) / alpha_j,   B q = A0^{-1} (E q)
+//   q_{j+1} = (B^T p_j - alpha_j q_j) / beta_j,     B^T p = E^T (A0^{-1} p)
+// with full reorthogonalisation (classical Gram-Schmidt twice) of p_j against
+// p_1..p_{j-1} (n-vectors) and of q_{j+1} against q_1..q_j, so that
+// B Q_m = P_m B_m with B_m upper bidiagonal.  Right singular vectors Z of B_m
+// = eigenvectors of the tridiagonal B_m^T B_m (implicit QR on the host,
+// descending, largest-|.| entry positive); V_k = Q_m Z_k, U_k = P_m (B_m Z_k)
+// = B V_k, then H_k as in the Lanczos build.  Two A0 solves per step and none
+// afterwards.  The run is cut at the first alpha_j or beta_j <= 1e-12 times
+// the largest alpha (breakdown); it is not kept for ddlr_extend_lowrank.
+void gk_build(ddlr_prec* h, int k, int m, const double* v0_user, uint64_t seed) {
+    HostPlan& P = h->plan;
+    const int64_t n = P.n, s = P.s;
+    m = (int)std::min<int64_t>(m, s);
+    lanczos_start(h, v0_user, seed);  // q_1 in R.Q (device interface order)
+    LanczosRun& R = h->lrun;
+    hipStream_t st = nullptr;
+    DMem tmp;
+    double* Qb = tmp.alloc<double>((size_t)s * (m + 1));
+    double* Pb = tmp.alloc<double>((size_t)n * m);
+    double* al = tmp.alloc<double>(m);
+    double* be = tmp.alloc<double>(m);
+    double* sc = tmp.alloc<double>(3);  // amax, inv, sum
+    double* t = tmp.alloc<double>(n);
+    double* w = tmp.alloc<double>(s);
+    double* part = tmp.alloc<double>((size_t)kRedBlocks * (m + 1));
+    double* csum = tmp.alloc<double>(m + 1);
+    HIPCHK(hipMemcpy(Qb, R.Q, sizeof(double) * s, hipMemcpyDeviceToDevice));
+    HIPCHK(hipMemset(sc, 0, sizeof(double) * 3));
+    R.steps = 0;  // the bidiagonalisation replaces the Lanczos run
+    R.lvariant = 0;
+    double *amax = sc, *inv = sc + 1, *sum1 = sc + 2;
+    const int gn = grid_for(n, 256, kRedBlocks), gs = grid_for(s, 256, kRedBlocks);
+    // CGS2 of v (len) against the first ncols columns of V (ld = len)
+    auto reorth = [&](int64_t len, int g, int ncols, const double* V, double* v) {
+        if (ncols == 0) return;
+        for (int pass = 0; pass < 2; ++pass) {
+            hipLaunchKernelGGL(k_multidot, dim3(g), dim3(256), 0, st, len, ncols, V, len, v, part);
+            LAUNCHCHK();
+            hipLaunchKernelGGL(k_reduce_cols, dim3(ncols), dim3(256), 0, st, g, ncols, part, csum, nullptr);
+            LAUNCHCHK();
+            hipLaunchKernelGGL(k_gemv_sub, dim3(g), dim3(256), 0, st, len, ncols, V, len, csum, v);
+            LAUNCHCHK();
+        }
+    };
+    auto norm = [&](int64_t len, int g, double* v, double* dst, int grow) {
+        hipLaunchKernelGGL((k_dot<double, double>), dim3(g), dim3(256), 0, st, len, 1, v, len, v, len, part, nullptr);
         LAUNCHCHK();
+        hipLaunchKernelGGL(k_reduce_cols, dim3(1), dim3(256), 0, st, g, 1, part, sum1, nullptr);
+        LAUNCHCHK();
+        hipLaunchKernelGGL(k_gk_norm, dim3(1), dim3(64), 0, st, sum1, dst, grow, amax, inv);
+        LAUNCHCHK();
+        hipLaunchKernelGGL(k_scale_to, dim3(g), dim3(256), 0, st, len, v, inv, v);
+        LAUNCHCHK();
+    };
+    for (int j = 0; j < m; ++j) {
+        const double* qj = Qb + (size_t)j * s;
+        double* pj = Pb + (size_t)j * n;
+        hipLaunchKernelGGL(k_csr_mv<double>, dim3(grid_for(n)), dim3(256), 0, st, n, 1, h->erp, h->eci, h->f64.ev, qj,
+                           s, (const double*)nullptr, 0, t, n, nullptr);
+        LAUNCHCHK();
+        a0_solve_dev<double, double, double>(h, h->f64, 1, t, n, pj, n, st, nullptr);  // B q_j
+        if (j > 0) {
+            hipLaunchKernelGGL(k_sub_scaled, dim3(gn), dim3(256), 0, st, n, be + j - 1, Pb + (size_t)(j - 1) * n, pj);
+            LAUNCHCHK();
+        }
+        reorth(n, gn, j, Pb, pj);
+        norm(n, gn, pj, al + j, 1);  // alpha_j, p_j
+        a0_solve_dev<double, double, double>(h, h->f64, 1, pj, n, t, n, st, nullptr);
+        hipLaunchKernelGGL(k_csr_mv<double>, dim3(grid_for(s)), dim3(256), 0, st, s, 1, h->etrp, h->etci, h->f64.etv,
+                           t, n, (const double*)nullptr, 0, w, s, nullptr);  // B^T p_j
+        LAUNCHCHK();
+        hipLaunchKernelGGL(k_sub_scaled, dim3(gs), dim3(256), 0, st, s, al + j, qj, w);
+        LAUNCHCHK();
+        reorth(s, gs, j + 1, Qb, w);
+        norm(s, gs, w, be + j, 0);  // beta_j
+        HIPCHK(hipMemcpyAsync(Qb + (size_t)(j + 1) * s, w, sizeof(double) * s, hipMemcpyDeviceToDevice, st));
     }
-    make_bf16_basis(h);
-    make_tiled_basis(h);
+    std::vector<double> ha(m), hb(m);
+    HIPCHK(hipMemcpy(ha.data(), al, m * sizeof(double), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(hb.data(), be, m * sizeof(double), hipMemcpyDeviceToHost));
+    int meff = m;
+    double am = 0.0;
+    for (int j = 0; j < m; ++j) {
+        am = std::max(am, ha[j]);
+        if (!(ha[j] > 1e-12 * am)) {
+            meff = j;
+            break;
+        }
+        if (!(hb[j] > 1e-12 * am)) {
+            meff = j + 1;
+            break;
+        }
+    }
+    ha.resize(meff);
+    hb.resize(meff);
+    drop_graphs(h);
+    if (meff < k + 1) {
+        tmp.release();
+        throw SetupError{DDLR_E_LANCZOS, "bidiagonalisation broke down after " + std::to_string(meff) +
+                                             " steps (k+1 = " + std::to_string(k + 1) + " needed)"};
+    }
+    // B_m^T B_m: diagonal alpha_j^2 + beta_{j-1}^2, off-diagonal alpha_j beta_j
+    std::vector<double> td(meff), to(meff > 1 ? meff - 1 : 1, 0.0);
+    for (int j = 0; j < meff; ++j) td[j] = ha[j] * ha[j] + (j > 0 ? hb[j - 1] * hb[j - 1] : 0.0);
+    for (int j = 0; j + 1 < meff; ++j) to[j] = ha[j] * hb[j];
+    std::vector<double> ev, Z;
+    tridiag_eig(meff, td.data(), to.data(), ev, Z);
+    std::vector<int> idx(meff);
+    for (int i = 0; i < meff; ++i) idx[i] = i;
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return ev[a] > ev[b]; });
+    std::vector<double> Zk((size_t)meff * k), Wk((size_t)meff * k);
+    for (int c = 0; c < k; ++c) {
+        const double* z = Z.data() + (size_t)idx[c] * meff;
+        int big = 0;
+        for (int r = 1; r < meff; ++r)
+            if (std::fabs(z[r]) > std::fabs(z[big])) big = r;
+        const double sg = z[big] < 0 ? -1.0 : 1.0;
+        for (int r = 0; r < meff; ++r) Zk[r + (size_t)c * meff] = sg * z[r];
+        for (int r = 0; r < meff; ++r)  // W = B_m Z_k
+            Wk[r + (size_t)c * meff] = ha[r] * Zk[r + (size_t)c * meff] +
+                                       (r + 1 < meff ? hb[r] * sg * z[r + 1] : 0.0);
+    }
+    h->ta = ha;
+    h->tb = hb;
+    h->msteps = meff;
+    h->ritz.resize(meff);
+    for (int c = 0; c < meff; ++c) h->ritz[c] = ev[idx[c]];
+    double* Zd = tmp.upload(Zk);
+    double* Wd = tmp.upload(Wk);
+    h->lrmem.release();
+    h->k = k;
+    double* V = tmp.alloc<double>((size_t)s * k);
+    hipLaunchKernelGGL(k_qy<double>, dim3(grid_for(s)), dim3(256), 0, st, s, meff, k, Qb, s, Zd, V, 1, s);
+    LAUNCHCHK();
+    double* Ucm = tmp.alloc<double>((size_t)n * k);
+    hipLaunchKernelGGL(k_qy<double>, dim3(grid_for(n)), dim3(256), 0, st, n, meff, k, Pb, n, Wd, Ucm, 1, n);
+    LAUNCHCHK();
+    double* EV = tmp.alloc<double>((size_t)n * k);
+    hipLaunchKernelGGL(k_csr_mv<double>, dim3(grid_for(n)), dim3(256), 0, st, n, k, h->erp, h->eci, h->f64.ev, V, s,
+                       (const double*)nullptr, 0, EV, n, nullptr);
+    LAUNCHCHK();
+    ddlr2_finish(h, k, Ucm, EV, tmp);
+    lowrank_copies(h, k);
     HIPCHK(hipDeviceSynchronize());
     tmp.release();
 }
@@ -1724,13 +1892,23 @@ ddlr_status ddlr_setup(const ddlr_csr* A, const int32_t* part, int32_t p, int32_
                 const bool ctl = opt.lanczos_check > 0;
                 int m = ctl ? (opt.lanczos_max > 0 ? opt.lanczos_max : 5 * k)
                             : (opt.lanczos_steps > 0 ? opt.lanczos_steps : 2 * k);
-                if (m < k + 1 || m > 2000)
-                    throw SetupError{DDLR_E_INVALID, "Lanczos step limit must be in [k+1, 2000]"};
+                // reorthogonalisation coefficients of one step are staged in LDS (k_gemv_sub: 1024)
+                if (m < k + 1 || m > kMaxLanczos)
+                    throw SetupError{DDLR_E_INVALID, "Lanczos step limit must be in [k+1, 1024]"};
                 if (ctl && !(opt.lanczos_tol >= 0.0))
                     throw SetupError{DDLR_E_INVALID, "lanczos_tol must be >= 0"};
                 const double eps = ctl ? (opt.lanczos_tol > 0.0 ? opt.lanczos_tol : 1e-4) : 0.0;
                 auto l0 = std::chrono::steady_clock::now();
-                lanczos_build(h.get(), k, m, opt.lanczos_start, opt.seed, opt.theta, ctl ? opt.lanczos_check : 0, eps);
+                if (opt.lowrank_build != DDLR_BUILD_LANCZOS && opt.lowrank_build != DDLR_BUILD_BIDIAG)
+                    throw SetupError{DDLR_E_INVALID, "lowrank_build must be DDLR_BUILD_LANCZOS or DDLR_BUILD_BIDIAG"};
+                if (opt.lowrank_build == DDLR_BUILD_BIDIAG) {
+                    if (variant != DDLR_2 || ctl)
+                        throw SetupError{DDLR_E_INVALID, "the bidiagonalisation build is for DDLR-2 with fixed steps"};
+                    gk_build(h.get(), k, m, opt.lanczos_start, opt.seed);
+                } else {
+                    lanczos_build(h.get(), k, m, opt.lanczos_start, opt.seed, opt.theta, ctl ? opt.lanczos_check : 0,
+                                  eps);
+                }
                 h->lanczos_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - l0).count();
             }
             HIPCHK(hipDeviceSynchronize());
@@ -2538,8 +2716,8 @@ ddlr_status ddlr_extend_lowrank(ddlr_prec* h, int32_t k, int32_t more_steps, int
         return DDLR_E_INVALID;
     }
     if (k < 1 || k > 128 || more_steps < 0 || check < 0 || !(tol >= 0.0) ||
-        (int64_t)h->lrun.steps + more_steps > 2000) {
-        g_err = "bad extend arguments (1 <= k <= 128, more_steps >= 0, total steps <= 2000, check >= 0, tol >= 0)";
+        (int64_t)h->lrun.steps + more_steps > kMaxLanczos) {
+        g_err = "bad extend arguments (1 <= k <= 128, more_steps >= 0, total steps <= 1024, check >= 0, tol >= 0)";
         return DDLR_E_INVALID;
     }
     try {

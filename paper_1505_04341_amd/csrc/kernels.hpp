@@ -1876,7 +1876,7 @@ __global__ __launch_bounds__(256) void k_multidot(int64_t s, int ncols, const do
     }
 }
 
-// w -= Q c  (columns 0..ncols-1)
+// w -= Q c  (columns 0..ncols-1, ncols <= 1024: the coefficients are staged in LDS)
 __global__ __launch_bounds__(256) void k_gemv_sub(int64_t s, int ncols, const double* __restrict__ Q, int64_t ldq,
                                                   const double* __restrict__ c, double* __restrict__ w) {
     __shared__ double cs[1024];
@@ -1916,6 +1916,26 @@ __global__ void k_lanczos_scalar(const double* __restrict__ sum, double* __restr
             *dst = s;
             if (fabs(s) > *amax) *amax = fabs(s);
         }
+    }
+}
+
+// y -= (*c) x  (a scalar kept on the device)
+__global__ __launch_bounds__(256) void k_sub_scaled(int64_t len, const double* __restrict__ c,
+                                                    const double* __restrict__ x, double* __restrict__ y) {
+    const double f = *c;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < len; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] -= f * x[i];
+}
+
+// Bidiagonalisation norms: dst = sqrt(sum); with grow, amax = max(amax, dst);
+// inv = dst > 1e-12 amax ? 1 / dst : 0 (a breakdown leaves zero vectors)
+__global__ void k_gk_norm(const double* __restrict__ sum, double* __restrict__ dst, int grow,
+                          double* __restrict__ amax, double* __restrict__ inv) {
+    if (threadIdx.x == 0) {
+        const double v = sqrt(*sum);
+        *dst = v;
+        if (grow && v > *amax) *amax = v;
+        *inv = (v > 1e-12 * (*amax)) ? 1.0 / v : 0.0;
     }
 }
 

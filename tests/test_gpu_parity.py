@@ -745,3 +745,54 @@ def test_cinv_ddlr2_rank_above_register_block():
     y = torch.empty((2, cfg["A"].n), dtype=torch.float64, device=DEV)
     D.ddlr_apply(h, to_dev(x), y)
     assert rel(to_host(y), o.apply(x)) <= 1e-8
+
+
+# ------------------- DDLR-2 by bidiagonalisation of A0^{-1} E (Sec. 4.3 alternative)
+
+@pytest.mark.parametrize("name", ["c1", "irregular", "small3d"])
+def test_bidiag_build_matches_oracle(name):
+    cfg = CASES[name]()
+    say("bidiag build", name)
+    h, o = setup_pair(cfg, variant=2, lowrank_build=D.BUILD_BIDIAG)
+    o.lowrank_gk(cfg["k"], cfg["m"], w.lanczos_start(cfg["A"].n, 0))
+    ga, gb, gr = D.ddlr_get_lanczos(h)
+    oa, ob, orz = o.lanczos_record()
+    assert len(gr) == len(orz)
+    k = cfg["k"]
+    assert np.abs(gr[: k + 1] - orz[: k + 1]).max() <= 1e-8 * orz[0]
+    assert np.abs(ga[:4] - oa[:4]).max() <= 1e-10 * np.abs(oa).max()
+    x = np.random.default_rng(9).standard_normal((cfg["A"].n, 2))
+    y = torch.empty((2, cfg["A"].n), dtype=torch.float64, device=DEV)
+    D.ddlr_apply(h, to_dev(x), y)
+    assert rel(to_host(y), o.apply(x)) <= 1e-6
+    # the same preconditioner (imported) gives the oracle's application to 1e-10
+    U, H = o.get_lowrank()
+    D.ddlr_set_lowrank(h, 2, U, H)
+    D.ddlr_apply(h, to_dev(x), y)
+    assert rel(to_host(y), o.apply(x)) <= 1e-10
+
+
+def test_bidiag_solve_and_limits():
+    cfg = w.config("small3d")
+    say("bidiag solve")
+    h, o = setup_pair(cfg, variant=2, lowrank_build=D.BUILD_BIDIAG)
+    o.lowrank_gk(cfg["k"], cfg["m"], w.lanczos_start(cfg["A"].n, 0))
+    assert D.ddlr_query(h)["spd"] and o.spd
+    b, _ = w.rhs_from_solution(cfg["A"], 0, 2)
+    x = torch.zeros((2, cfg["A"].n), dtype=torch.float64, device=DEV)
+    st, info = D.ddlr_solve(h, to_dev(b), x)
+    xo, infoo = o.pcg(b)
+    assert st == D.OK
+    for i, io in zip(info, infoo["its"]):
+        assert abs(i["iters"] - int(io)) <= 1 and i["relres_true"] <= 1.05e-6
+    # the run is not kept: no continuation
+    with pytest.raises(D.DDLRError):
+        D.ddlr_extend_lowrank(h, cfg["k"], 4)
+    # DDLR-1, or the convergence control, with the bidiagonalisation: refused
+    with pytest.raises(D.DDLRError):
+        D.ddlr_setup(cfg["A"], cfg["part"], cfg["p"], cfg["k"], 1, lowrank_build=D.BUILD_BIDIAG)
+    with pytest.raises(D.DDLRError):
+        D.ddlr_setup(cfg["A"], cfg["part"], cfg["p"], cfg["k"], 2, lowrank_build=D.BUILD_BIDIAG, lanczos_check=4)
+    # step limit
+    with pytest.raises(D.DDLRError):
+        D.ddlr_setup(cfg["A"], cfg["part"], cfg["p"], cfg["k"], 2, lanczos_steps=1100)
