@@ -184,8 +184,11 @@ struct ddlr_prec {
     DMem mem;
     // device structures (device order)
     int32_t* perm_dev = nullptr;  // device position -> user row
+    // SELL-64 of A: values FP64 or (when all exact) FP32, columns int32 or 16-bit row offsets
     int32_t *sell_ptr = nullptr, *sell_col = nullptr;
+    int16_t* sell_cold = nullptr;
     double* sell_val = nullptr;
+    float* sell_valf = nullptr;
     int64_t nslices = 0, sell_nnz = 0;
     int32_t *lrp = nullptr, *lci = nullptr, *urp = nullptr, *uci = nullptr, *lvl_ptr = nullptr;
     int32_t *erp = nullptr, *eci = nullptr, *etrp = nullptr, *etci = nullptr;
@@ -602,8 +605,30 @@ void upload_devhost(ddlr_prec* h, const DevHost& D) {
         }
     }
     h->sell_ptr = M.upload(sptr);
-    h->sell_col = M.upload(scol);
-    h->sell_val = M.upload(sval);
+    bool f32ok = true, i16ok = true;
+    for (int64_t sl = 0; sl < h->nslices && (f32ok || i16ok); ++sl)
+        for (int64_t q = sptr[sl]; q < sptr[sl + 1]; ++q) {
+            const int64_t row = sl * kSell + (q - sptr[sl]) % kSell;
+            f32ok = f32ok && (double)(float)sval[q] == sval[q];
+            i16ok = i16ok && std::llabs((long long)scol[q] - (long long)row) <= 32767;
+        }
+    if (const char* env = std::getenv("DDLR_SELL_WIDE"))  // "1": FP64 values and int32 columns always
+        if (env[0] == '1') f32ok = i16ok = false;
+    if (i16ok) {
+        std::vector<int16_t> d(scol.size());
+        for (int64_t sl = 0; sl < h->nslices; ++sl)
+            for (int64_t q = sptr[sl]; q < sptr[sl + 1]; ++q)
+                d[q] = (int16_t)(scol[q] - (sl * kSell + (q - sptr[sl]) % kSell));
+        h->sell_cold = M.upload(d);
+    } else {
+        h->sell_col = M.upload(scol);
+    }
+    if (f32ok) {
+        std::vector<float> f(sval.begin(), sval.end());
+        h->sell_valf = M.upload(f);
+    } else {
+        h->sell_val = M.upload(sval);
+    }
     h->lrp = M.upload(D.lrp);
     h->lci = M.upload(D.lci);
     h->urp = M.upload(D.urp);
@@ -1112,13 +1137,28 @@ void apply_dev(ddlr_prec* h, int nrhs, const double* in, int64_t ldin, double* o
     else apply_dev_T<float>(h, nrhs, in, ldin, out, ldout, st, done);
 }
 
+// Calls f(col, val) with the SELL arrays in their stored types.
+template <typename F> void with_sell(const ddlr_prec* h, F&& f) {
+    if (h->sell_cold) {
+        if (h->sell_valf) f(h->sell_cold, h->sell_valf);
+        else f(h->sell_cold, h->sell_val);
+    } else {
+        if (h->sell_valf) f(h->sell_col, h->sell_valf);
+        else f(h->sell_col, h->sell_val);
+    }
+}
+
 void spmv_dev(ddlr_prec* h, int nrhs, const double* x, int64_t ldx, double* y, int64_t ldy, double* part,
               hipStream_t st, const int* done) {
     const int64_t n = h->ndev;
     ProfScope ps(h, 2, st);
     const int64_t chunks = (n + 255) / 256;
-    hipLaunchKernelGGL(k_spmv_sell, dim3((chunks + 7) / 8 * 8), dim3(256), 0, st, n, nrhs, h->sell_ptr, h->sell_col,
-                       h->sell_val, x, ldx, y, ldy, part, done);
+    with_sell(h, [&](auto col, auto val) {
+        using IT = std::remove_const_t<std::remove_pointer_t<decltype(col)>>;
+        using VT = std::remove_const_t<std::remove_pointer_t<decltype(val)>>;
+        hipLaunchKernelGGL((k_spmv_sell<VT, IT>), dim3((chunks + 7) / 8 * 8), dim3(256), 0, st, n, nrhs, h->sell_ptr,
+                           col, val, x, ldx, y, ldy, part, done);
+    });
     LAUNCHCHK();
 }
 
@@ -1129,28 +1169,32 @@ void spmv_il_dev(ddlr_prec* h, int nrhs, const double* x, double* y, int64_t ldy
     ProfScope ps(h, 2, st);
     const int64_t chunks = (n + 255) / 256;
     const dim3 grid((chunks + 7) / 8 * 8), blk(256);
-    switch (lane_stride(nrhs)) {
+    with_sell(h, [&](auto col, auto val) {
+        using IT = std::remove_const_t<std::remove_pointer_t<decltype(col)>>;
+        using VT = std::remove_const_t<std::remove_pointer_t<decltype(val)>>;
+        switch (lane_stride(nrhs)) {
         case 1:
-            hipLaunchKernelGGL(k_spmv_sell_il<1>, grid, blk, 0, st, n, nrhs, h->sell_ptr, h->sell_col, h->sell_val, x,
-                               y, ldy, part, done);
+            hipLaunchKernelGGL((k_spmv_sell_il<1, VT, IT>), grid, blk, 0, st, n, nrhs, h->sell_ptr, col, val, x, y, ldy,
+                               part, done);
             break;
         case 2:
-            hipLaunchKernelGGL(k_spmv_sell_il<2>, grid, blk, 0, st, n, nrhs, h->sell_ptr, h->sell_col, h->sell_val, x,
-                               y, ldy, part, done);
+            hipLaunchKernelGGL((k_spmv_sell_il<2, VT, IT>), grid, blk, 0, st, n, nrhs, h->sell_ptr, col, val, x, y, ldy,
+                               part, done);
             break;
         case 4:
-            hipLaunchKernelGGL(k_spmv_sell_il<4>, grid, blk, 0, st, n, nrhs, h->sell_ptr, h->sell_col, h->sell_val, x,
-                               y, ldy, part, done);
+            hipLaunchKernelGGL((k_spmv_sell_il<4, VT, IT>), grid, blk, 0, st, n, nrhs, h->sell_ptr, col, val, x, y, ldy,
+                               part, done);
             break;
         case 8:
-            hipLaunchKernelGGL(k_spmv_sell_il<8>, grid, blk, 0, st, n, nrhs, h->sell_ptr, h->sell_col, h->sell_val, x,
-                               y, ldy, part, done);
+            hipLaunchKernelGGL((k_spmv_sell_il<8, VT, IT>), grid, blk, 0, st, n, nrhs, h->sell_ptr, col, val, x, y, ldy,
+                               part, done);
             break;
         default:
-            hipLaunchKernelGGL(k_spmv_sell_il<16>, grid, blk, 0, st, n, nrhs, h->sell_ptr, h->sell_col, h->sell_val,
-                               x, y, ldy, part, done);
+            hipLaunchKernelGGL((k_spmv_sell_il<16, VT, IT>), grid, blk, 0, st, n, nrhs, h->sell_ptr, col, val, x, y,
+                               ldy, part, done);
             break;
-    }
+        }
+    });
     LAUNCHCHK();
 }
 

@@ -549,8 +549,18 @@ __global__ __launch_bounds__(256) void k_trsv_level_rows(int a, int e, int nrhs,
 // value 0).  Optionally accumulates per-chunk partial dot products x.y per
 // right-hand side into part[chunk*nrhs + r], chunk = 256-row chunk index
 // (used for p^T A p in CG).
+// Compact SELL-64 storage: values in FP32 when every value of A is exactly an
+// FP32 number (VT = float; the products are then the same doubles), columns
+// as 16-bit offsets from the row when every |column - row| <= 32767
+// (IT = int16_t).  The arithmetic is that of the FP64 / int32 storage.
+template <typename IT> __device__ __forceinline__ int64_t sell_col(IT c, int64_t row) {
+    if constexpr (sizeof(IT) == 2) return row + (int64_t)c;
+    else return (int64_t)c;
+}
+
+template <typename VT, typename IT>
 __global__ __launch_bounds__(256) void k_spmv_sell(int64_t n, int nrhs, const int32_t* __restrict__ sptr,
-                                                   const int32_t* __restrict__ col, const double* __restrict__ val,
+                                                   const IT* __restrict__ col, const VT* __restrict__ val,
                                                    const double* __restrict__ x, int64_t ldx, double* __restrict__ y,
                                                    int64_t ldy, double* __restrict__ part,
                                                    const int* __restrict__ done) {
@@ -572,8 +582,8 @@ __global__ __launch_bounds__(256) void k_spmv_sell(int64_t n, int nrhs, const in
         const int base = sptr[sl], width = (sptr[sl + 1] - base) >> 6;
         for (int j = 0; j < width; ++j) {
             const int q = base + j * kSell + lane;
-            const int c = col[q];
-            const double a = val[q];
+            const int64_t c = sell_col<IT>(col[q], row);
+            const double a = (double)val[q];
 #pragma unroll
             for (int r = 0; r < kMaxRhs; ++r)
                 if (r < nrhs) acc[r] += a * x[c + r * ldx];
@@ -605,10 +615,10 @@ __global__ __launch_bounds__(256) void k_spmv_sell(int64_t n, int nrhs, const in
 // 2M rows the column-major lines in flight overflow the L2 and are fetched
 // several times.  Per-row sums run over the slice entries in the same order
 // as k_spmv_sell, so both give bitwise the same y.
-template <int S>
+template <int S, typename VT, typename IT>
 __global__ __launch_bounds__(256) void k_spmv_sell_il(int64_t n, int nrhs, const int32_t* __restrict__ sptr,
-                                                      const int32_t* __restrict__ col,
-                                                      const double* __restrict__ val, const double* __restrict__ x,
+                                                      const IT* __restrict__ col,
+                                                      const VT* __restrict__ val, const double* __restrict__ x,
                                                       double* __restrict__ y, int64_t ldy, double* __restrict__ part,
                                                       const int* __restrict__ done) {
     __shared__ double sh[4 * S];
@@ -626,9 +636,9 @@ __global__ __launch_bounds__(256) void k_spmv_sell_il(int64_t n, int nrhs, const
         for (int j = 0; j < width; ++j) {
             const int q = base + j * kSell + lane;
             // A streams through once: non-temporal loads keep the gathered x lines in L2
-            const int c = __builtin_nontemporal_load(col + q);
-            const double a = __builtin_nontemporal_load(val + q);
-            const double* xc = x + (int64_t)c * S;
+            const int64_t c = sell_col<IT>(__builtin_nontemporal_load(col + q), row);
+            const double a = (double)__builtin_nontemporal_load(val + q);
+            const double* xc = x + c * S;
             double xv[S];
             if constexpr (S == 1) {
                 xv[0] = xc[0];

@@ -796,3 +796,29 @@ def test_bidiag_solve_and_limits():
     # step limit
     with pytest.raises(D.DDLRError):
         D.ddlr_setup(cfg["A"], cfg["part"], cfg["p"], cfg["k"], 2, lanczos_steps=1100)
+
+
+@pytest.mark.parametrize("name", ["c1", "irregular", "big3d"])
+def test_spmv_compact_storage_bitwise(name):
+    """SELL with FP32 values (when all are exact) and 16-bit column offsets
+    gives bitwise the results of FP64 / int32 storage: the SpMV, and CG
+    (interleaved SpMV) after a few steps.  c1/big3d: Laplacians (compact
+    values); irregular: random coefficients (FP64 values, 16-bit columns)."""
+    cfg = CASES[name]()
+    say("spmv compact", name)
+    h1, _ = setup_pair(cfg, variant=D.VARIANT_A0)
+    h2, _ = setup_pair(cfg, variant=D.VARIANT_A0, env={"DDLR_SELL_WIDE": "1"})
+    n = cfg["A"].n
+    x = np.random.default_rng(2).standard_normal((n, 3))
+    y1 = torch.empty((3, n), dtype=torch.float64, device=DEV)
+    y2 = torch.empty_like(y1)
+    D.ddlr_spmv(h1, to_dev(x), y1)
+    D.ddlr_spmv(h2, to_dev(x), y2)
+    assert torch.equal(y1, y2)
+    assert rel(to_host(y1), cfg["A"].to_scipy() @ x) <= 1e-14
+    b, _ = w.rhs_from_solution(cfg["A"], 0, 3)
+    x1 = torch.zeros((3, n), dtype=torch.float64, device=DEV)
+    x2 = torch.zeros_like(x1)
+    D.ddlr_solve(h1, to_dev(b), x1, maxit=5)
+    D.ddlr_solve(h2, to_dev(b), x2, maxit=5)
+    assert torch.equal(x1, x2)
