@@ -71,6 +71,9 @@ def _load():
         lib.orc_use_cinv.restype = C.c_int
         lib.orc_use_cinv.argtypes = [P, C.c_int, C.c_double, C.c_int]
         lib.orc_cinv.argtypes = [P, P, P, P, P]
+        lib.orc_use_cheb.restype = C.c_int
+        lib.orc_use_cheb.argtypes = [P, C.c_int, C.c_int]
+        lib.orc_cheb.argtypes = [P, P]
         lib.orc_threads.restype = C.c_int
         lib.orc_threads.argtypes = []
         _lib = lib
@@ -165,6 +168,21 @@ class Oracle:
         if st != OK:
             raise OracleError(st, "cinv")
         return self
+
+    def use_cheb(self, nu=5, mc=10):
+        """Solve C_alpha with nu preconditioned Chebyshev steps, block-Jacobi
+        D_alpha = blockdiag(C_i) by incomplete LDL^T, spectrum from mc Lanczos
+        steps on (C_alpha, D_alpha) with residual safeguards. Call before lowrank."""
+        st = _lib.orc_use_cheb(self._h, int(nu), int(mc))
+        if st != OK:
+            raise OracleError(st, "cheb")
+        return self
+
+    def cheb(self):
+        """(lo, hi) safeguarded interval and (smallest, largest) Ritz value."""
+        out = np.zeros(4)
+        _lib.orc_cheb(self._h, _p(out))
+        return tuple(out)
 
     def cinv(self):
         """(X: scipy CSR s x s in interface order, residual norms

@@ -22,7 +22,9 @@
  *     or exact dense LDL^T per block for the identity tests; alternatively
  *     C_alpha is solved by a sparse approximate inverse X built with the
  *     self-preconditioned global MR iteration with dropping (Sec. 4.4,
- *     Algorithm alg:mr), applied as a product with X,
+ *     Algorithm alg:mr), applied as a product with X, or by 5 preconditioned
+ *     Chebyshev iterations with the block-Jacobi matrix D_alpha of the local
+ *     blocks C_i and spectrum estimates from Lanczos on (C_alpha, D_alpha),
  *   - Lanczos on E^T A0^{-1} E (DDLR-1) or E^T A0^{-2} E (DDLR-2) with full
  *     reorthogonalisation (Sec. 4.3), Ritz pairs of T_m by cyclic Jacobi,
  *   - G_{k,theta}^{-1} of eq. (gkt) with theta = lambda_{k+1}, applied through
@@ -111,6 +113,10 @@ typedef struct {
     double *x_res;    /* ||I - C X_j||_F for j = 0..x_iters */
     double x_rinf;    /* ||I - C X||_inf (largest absolute row sum) of the final X */
     int x_spd;        /* 1 if ||I - C X||_inf < 1: then C^{1/2} X C^{1/2} has its eigenvalues in (0, 2), so X is SPD */
+    /* csolve = 2: Chebyshev on C_alpha with D_alpha = blockdiag(C_i) (factored in L, D) */
+    int ch_nu;            /* iterations per solve */
+    double ch_lo, ch_hi;  /* safeguarded spectrum interval of D_alpha^{-1} C_alpha */
+    double ch_rlo, ch_rhi;/* extreme Ritz values of the estimate */
 } orc_t;
 
 static void *xcalloc(size_t n, size_t sz) {
@@ -364,17 +370,35 @@ static int block_of(const orc_t *o, int64_t r) {
  *   L_ij = (a_ij - sum_{t<j} L_it D_t L_jt) / D_j   for j in pattern(i), j < i,
  *   D_i  = a_ii - sum_{t<i} L_it^2 D_t,
  * all sums over t ascending, restricted to positions present in both rows. */
-static int build_factor(orc_t *o) {
+/* with the Chebyshev C_alpha solver the interface block is factored as
+ * D_alpha = blockdiag(C_i): only couplings inside one subdomain's interface */
+static int in_pattern(const orc_t *o, int b, int64_t i, int64_t j) {
+    if (o->csolve != 2 || b != o->p) return 1;
+    return o->part[o->perm[i]] == o->part[o->perm[j]];
+}
+
+/* Factors rows from..n-1 (from = 0: everything; from = m: the interface
+ * block again, keeping the B factors). */
+static int factor_from(orc_t *o, int64_t from) {
     const int64_t n = o->n;
-    int64_t cap = o->A0.rp[n] + 16, used = 0;
-    o->L.rp = xcalloc(n + 1, sizeof(int64_t));
-    o->L.ci = xcalloc(cap, sizeof(int32_t));
-    o->L.v = xcalloc(cap, sizeof(double));
-    o->D = xcalloc(n, sizeof(double));
+    int64_t cap, used;
+    if (from == 0) {
+        cap = o->A0.rp[n] + 16;
+        used = 0;
+        o->L.rp = xcalloc(n + 1, sizeof(int64_t));
+        o->L.ci = xcalloc(cap, sizeof(int32_t));
+        o->L.v = xcalloc(cap, sizeof(double));
+        o->D = xcalloc(n, sizeof(double));
+    } else {
+        used = o->L.rp[from];
+        cap = used + (o->A0.rp[n] - o->A0.rp[from]) + 16;
+        o->L.ci = realloc(o->L.ci, cap * sizeof(int32_t));
+        o->L.v = realloc(o->L.v, cap * sizeof(double));
+    }
     o->breakdown_row = -1;
     double *w = xcalloc(n, sizeof(double));
     char *inrow = xcalloc(n, 1);
-    for (int64_t i = 0; i < n; ++i) {
+    for (int64_t i = from; i < n; ++i) {
         int b = block_of(o, i);
         int64_t lo = o->boff[b];
         /* pattern of row i strictly below the diagonal, inside block b */
@@ -387,7 +411,7 @@ static int build_factor(orc_t *o) {
         for (int64_t t = o->A0.rp[i]; t < o->A0.rp[i + 1]; ++t) {
             int32_t j = o->A0.ci[t];
             if (j == i) aii = o->A0.v[t];
-            else if (j < i && j >= lo) {
+            else if (j < i && j >= lo && in_pattern(o, b, i, j)) {
                 if (o->factor != 2) ++cnt;
                 w[j] = o->A0.v[t];
             }
@@ -403,7 +427,7 @@ static int build_factor(orc_t *o) {
         } else {
             for (int64_t t = o->A0.rp[i]; t < o->A0.rp[i + 1]; ++t) {
                 int32_t j = o->A0.ci[t];
-                if (j < i && j >= lo) o->L.ci[used++] = j;
+                if (j < i && j >= lo && in_pattern(o, b, i, j)) o->L.ci[used++] = j;
             }
         }
         for (int64_t q = start; q < used; ++q) inrow[o->L.ci[q]] = 1;
@@ -437,17 +461,35 @@ static int build_factor(orc_t *o) {
     return ORC_OK;
 }
 
+static int build_factor(orc_t *o) { return factor_from(o, 0); }
+
+static void cheb_solve(const orc_t *o, const double *x, double *z);
+
 /* z = A0^{-1} x (internal order) with the local factors: per block
  * L y = x (unit lower), w = D^{-1} y, L^T z = w; with csolve the interface
  * block instead takes z_C = X x_C.  Blocks are independent. */
+static void block_solve(const orc_t *o, int b, const double *x, double *z);
+
 static void a0_solve(const orc_t *o, const double *x, double *z) {
 #pragma omp parallel for schedule(dynamic, 1)
     for (int b = 0; b <= o->p; ++b) {
-        int64_t lo = o->boff[b], hi = o->boff[b + 1];
-        if (b == o->p && o->csolve) {  /* z_C = X x_C */
+        int64_t lo = o->boff[b];
+        if (b == o->p && o->csolve == 1) {  /* z_C = X x_C */
             csr_mv(&o->X, o->s, x + lo, z + lo);
             continue;
         }
+        if (b == o->p && o->csolve == 2) {
+            cheb_solve(o, x, z);
+            continue;
+        }
+        block_solve(o, b, x, z);
+    }
+}
+
+/* L y = x, w = D^{-1} y, L^T z = w on the rows of block b (full-length vectors) */
+static void block_solve(const orc_t *o, int b, const double *x, double *z) {
+    {
+        int64_t lo = o->boff[b], hi = o->boff[b + 1];
         for (int64_t i = lo; i < hi; ++i) {
             double s = x[i];
             for (int64_t t = o->L.rp[i]; t < o->L.rp[i + 1]; ++t) s -= o->L.v[t] * z[o->L.ci[t]];
@@ -736,6 +778,109 @@ static int build_cinv(orc_t *o, int nit, double tol, int lfil) {
     return ORC_OK;
 }
 
+/* ------------------------- C_alpha by preconditioned Chebyshev (Sec. 4.4)
+ *
+ * D_alpha = blockdiag(C_i), C_i the coupling of subdomain i's interface
+ * unknowns, factored by incomplete LDL^T (the interface block of L, D).  The
+ * spectrum of D_alpha^{-1} C_alpha is estimated by mc Lanczos steps on the
+ * pencil (C_alpha, D_alpha) from the vector of ones, in the D_alpha inner
+ * product; each extreme Ritz value is widened by its residual bound
+ * beta_mc |s_mc| (the safeguard; a non-positive lower end becomes half the
+ * smallest Ritz value).  A solve is nu steps of Chebyshev acceleration
+ * (Saad, Iterative Methods for Sparse Linear Systems, Alg. 12.1) from 0 on
+ * [lo, hi]: theta = (hi+lo)/2, delta = (hi-lo)/2, sigma = theta/delta,
+ * rho_0 = 1/sigma, d_0 = D^{-1} r_0 / theta, x_{k+1} = x_k + d_k,
+ * r_{k+1} = r_k - C d_k, rho_{k+1} = 1/(2 sigma - rho_k),
+ * d_{k+1} = rho_{k+1} rho_k d_k + (2 rho_{k+1}/delta) D^{-1} r_{k+1}. */
+
+/* y_C = C_alpha x_C (full-length vectors, interface rows) */
+static void c_mul(const orc_t *o, const double *x, double *y) {
+    for (int64_t i = o->m; i < o->n; ++i) {
+        double acc = 0.0;
+        for (int64_t t = o->A0.rp[i]; t < o->A0.rp[i + 1]; ++t) acc += o->A0.v[t] * x[o->A0.ci[t]];
+        y[i] = acc;
+    }
+}
+
+static double c_dot(const orc_t *o, const double *a, const double *b) {
+    double t = 0.0;
+    for (int64_t i = o->m; i < o->n; ++i) t += a[i] * b[i];
+    return t;
+}
+
+static void jacobi_eig(int m, double *T, double *ev, double *V);
+
+static void cheb_solve(const orc_t *o, const double *x, double *z) {
+    const int64_t m = o->m, n = o->n;
+    const double th = 0.5 * (o->ch_hi + o->ch_lo), de = 0.5 * (o->ch_hi - o->ch_lo), sg = th / de;
+    double *r = xcalloc(n, sizeof(double)), *d = xcalloc(n, sizeof(double)), *t = xcalloc(n, sizeof(double));
+    double *cd = xcalloc(n, sizeof(double));
+    for (int64_t i = m; i < n; ++i) r[i] = x[i];
+    block_solve(o, o->p, r, t);
+    for (int64_t i = m; i < n; ++i) { d[i] = t[i] / th; z[i] = d[i]; }
+    double rho = 1.0 / sg;
+    for (int k = 1; k < o->ch_nu; ++k) {
+        c_mul(o, d, cd);
+        for (int64_t i = m; i < n; ++i) r[i] -= cd[i];
+        const double rn = 1.0 / (2.0 * sg - rho);
+        block_solve(o, o->p, r, t);
+        for (int64_t i = m; i < n; ++i) {
+            d[i] = rn * rho * d[i] + (2.0 * rn / de) * t[i];
+            z[i] += d[i];
+        }
+        rho = rn;
+    }
+    free(r); free(d); free(t); free(cd);
+}
+
+static void cheb_bounds(orc_t *o, int mc) {
+    const int64_t m = o->m, n = o->n;
+    double *r = xcalloc(n, sizeof(double)), *zz = xcalloc(n, sizeof(double));
+    double *v = xcalloc(n, sizeof(double)), *y = xcalloc(n, sizeof(double));
+    double *vp = xcalloc(n, sizeof(double)), *yp = xcalloc(n, sizeof(double)), *w = xcalloc(n, sizeof(double));
+    double *al = xcalloc(mc, sizeof(double)), *be = xcalloc(mc, sizeof(double));
+    for (int64_t i = m; i < n; ++i) r[i] = 1.0;
+    block_solve(o, o->p, r, zz);
+    const double b0 = sqrt(c_dot(o, r, zz));
+    for (int64_t i = m; i < n; ++i) { v[i] = zz[i] / b0; y[i] = r[i] / b0; }
+    double bprev = 0.0;
+    int mm = 0;
+    for (int j = 0; j < mc; ++j) {
+        c_mul(o, v, w);
+        al[j] = c_dot(o, v, w);
+        for (int64_t i = m; i < n; ++i) w[i] -= al[j] * y[i] + bprev * yp[i];
+        block_solve(o, o->p, w, zz);
+        const double wz = c_dot(o, w, zz);
+        mm = j + 1;
+        be[j] = wz > 0.0 ? sqrt(wz) : 0.0;
+        if (!(be[j] > 1e-14 * fabs(al[0]))) { be[j] = 0.0; break; }
+        for (int64_t i = m; i < n; ++i) {
+            vp[i] = v[i]; yp[i] = y[i];
+            v[i] = zz[i] / be[j]; y[i] = w[i] / be[j];
+        }
+        bprev = be[j];
+    }
+    double *T = xcalloc((int64_t)mm * mm, sizeof(double)), *S = xcalloc((int64_t)mm * mm, sizeof(double));
+    double *ev = xcalloc(mm, sizeof(double));
+    for (int i = 0; i < mm; ++i) {
+        T[i + i * mm] = al[i];
+        if (i + 1 < mm) T[i + 1 + i * mm] = T[i + (i + 1) * mm] = be[i];
+    }
+    jacobi_eig(mm, T, ev, S);
+    int imax = 0, imin = 0;
+    for (int i = 1; i < mm; ++i) {
+        if (ev[i] > ev[imax]) imax = i;
+        if (ev[i] < ev[imin]) imin = i;
+    }
+    const double bl = be[mm - 1];
+    o->ch_rhi = ev[imax];
+    o->ch_rlo = ev[imin];
+    o->ch_hi = ev[imax] + bl * fabs(S[(mm - 1) + (int64_t)imax * mm]);
+    o->ch_lo = ev[imin] - bl * fabs(S[(mm - 1) + (int64_t)imin * mm]);
+    if (!(o->ch_lo > 0.0)) o->ch_lo = 0.5 * ev[imin];
+    free(r); free(zz); free(v); free(y); free(vp); free(yp); free(w); free(al); free(be); free(T); free(S); free(ev);
+}
+
 /* ---------------------------------------------------------- E and E^T products */
 
 static void e_mul(const orc_t *o, const double *w, double *v) { csr_mv(&o->E, o->n, w, v); }
@@ -955,10 +1100,12 @@ static int dense_chol(int k, double *a) {
 /* The SPD results (Propositions on SPD-ness of DDLR-1 and DDLR-2) assume A0
  * SPD; with an indefinite local factor the preconditioner is not SPD. */
 static int pivots_positive(const orc_t *o) {
-    const int64_t last = o->csolve ? o->m : o->n;
+    const int64_t last = o->csolve == 1 ? o->m : o->n;
     for (int64_t i = 0; i < last; ++i)
         if (!(o->D[i] > 0.0)) return 0;
-    return o->csolve ? o->x_spd : 1;
+    if (o->csolve == 1) return o->x_spd;
+    if (o->csolve == 2) return o->ch_rlo > 0.0;  /* the polynomial is positive on the safeguarded interval */
+    return 1;
 }
 
 static int ddlr2_hk(orc_t *o, int k, const double *EV);
@@ -1165,7 +1312,7 @@ int64_t orc_size(const orc_t *o, int what) {
     case 8: return o->breakdown_row;
     case 9: return o->k;
     case 10: return o->spd;
-    case 11: return o->csolve ? o->X.rp[o->s] : 0;
+    case 11: return o->csolve == 1 ? o->X.rp[o->s] : 0;
     case 12: return o->x_iters;
     case 13: return o->x_spd;
     default: return -1;
@@ -1199,6 +1346,26 @@ int orc_use_cinv(orc_t *o, int nit, double tol, int lfil) {
     const int st = build_cinv(o, nit, tol, lfil);
     if (st == ORC_OK && o->breakdown_row >= o->m) o->breakdown_row = -1;
     return st;
+}
+
+/* Switches the C_alpha solve to nu preconditioned Chebyshev steps with the
+ * block-Jacobi D_alpha (the interface block is factored again on the
+ * subdomains' own couplings) and a spectrum estimate from mc Lanczos steps
+ * on (C_alpha, D_alpha).  Call before the low-rank build. */
+int orc_use_cheb(orc_t *o, int nu, int mc) {
+    if (nu < 1 || mc < 2 || o->s < 2 || o->factor == 2) return ORC_E_INVALID;
+    if (o->breakdown_row >= 0 && o->breakdown_row < o->m) return ORC_E_BREAKDOWN;
+    o->csolve = 2;
+    const int st = factor_from(o, o->m);
+    if (st != ORC_OK) return st;
+    cheb_bounds(o, mc);
+    o->ch_nu = nu;
+    return ORC_OK;
+}
+
+/* lo, hi (safeguarded interval), smallest and largest Ritz value */
+void orc_cheb(const orc_t *o, double *out) {
+    out[0] = o->ch_lo; out[1] = o->ch_hi; out[2] = o->ch_rlo; out[3] = o->ch_rhi;
 }
 
 /* X (s x s CSR, interface indices), nnz via orc_size(o, 11); res: the

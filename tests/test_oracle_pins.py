@@ -824,3 +824,69 @@ def test_gk_short_run_close_to_lanczos_route():
     xl, il = ol.pcg(b)
     assert ig["status"] == 0 and il["status"] == 0 and og.spd
     assert np.all(np.abs(ig["its"] - il["its"]) <= 2)
+
+
+# ---------------------- C_alpha by preconditioned Chebyshev (Sec. 4.4, Table 3)
+
+def _cheb_setup(name, nu=5, mc=10):
+    cfg = w.config(name)
+    o = Oracle(cfg["A"], cfg["part"], cfg["p"]).use_cheb(nu, mc)
+    m = o.m
+    C = o.csr("A0").toarray()[m:, m:]
+    L = o.csr("L").toarray()[m:, m:]
+    Dg = o.diag()[m:]
+    M = (np.eye(o.s) + L) @ np.diag(Dg) @ (np.eye(o.s) + L).T
+    return cfg, o, C, M
+
+
+def test_cheb_block_jacobi_factor():
+    """D_alpha keeps only couplings inside one subdomain's interface, and its
+    LDL^T reproduces C_alpha on that pattern (incomplete-factor property)."""
+    cfg, o, C, M = _cheb_setup("c1")
+    perm, *_ = o.ordering()
+    part = np.asarray(cfg["part"])[perm[o.m:]]
+    L = o.csr("L").toarray()[o.m:, o.m:]
+    nz = np.nonzero(L)
+    assert np.all(part[nz[0]] == part[nz[1]])
+    pat = (C != 0) & (part[:, None] == part[None, :])
+    assert np.abs((M - C)[pat]).max() <= 1e-12 * np.abs(C).max()
+
+
+@pytest.mark.parametrize("nu", [1, 3, 5])
+def test_cheb_matches_chebyshev_polynomial(nu):
+    """The solve is nu steps of Chebyshev acceleration on [lo, hi]: the error
+    operator I - X C (X = the solve) has eigenvalues
+    T_nu((theta - lambda)/delta) / T_nu(theta/delta) at the eigenvalues lambda
+    of D_alpha^{-1} C_alpha (closed form of the scaled Chebyshev residual
+    polynomial; eigenvalues from LAPACK)."""
+    cfg, o, C, M = _cheb_setup("c1", nu=nu)
+    lo, hi, rlo, rhi = o.cheb()
+    s, m, n = o.s, o.m, o.n
+    perm, *_ = o.ordering()
+    E = np.zeros((n, s))
+    E[perm[m:], np.arange(s)] = 1.0  # unit vectors on the interface, user order
+    Z = o.a0_solve(E)
+    X = Z[perm[m:], :]
+    lam = np.sort(np.linalg.eigvals(np.linalg.solve(M, C)).real)
+    th, de = (hi + lo) / 2, (hi - lo) / 2
+    T = np.polynomial.chebyshev.Chebyshev.basis(nu)
+    want = np.sort(T((th - lam) / de) / T(th / de))
+    got = np.sort(np.linalg.eigvals(np.eye(s) - X @ C).real)
+    assert np.abs(got - want).max() <= 1e-10
+    # the safeguarded interval covers the spectrum here, and X is SPD
+    assert lo <= lam[0] and hi >= lam[-1] and rlo >= lam[0] - 1e-12 and rhi <= lam[-1] + 1e-12
+    assert np.abs(X - X.T).max() <= 1e-12 * np.abs(X).max()
+    assert np.linalg.eigvalsh((X + X.T) / 2).min() > 0
+
+
+def test_cheb_preconditioner_end_to_end():
+    cfg = w.config("c1")
+    A = cfg["A"]
+    o = Oracle(A, cfg["part"], cfg["p"]).use_cheb(5, 10)
+    o.lowrank(1, cfg["k"], cfg["m"], w.lanczos_start(A.n, 0))
+    assert o.spd
+    b, _ = w.rhs_from_solution(A, 0, 2)
+    x, info = o.pcg(b)
+    assert info["status"] == 0 and np.all(info["relres_true"] <= 1.01e-6)
+    xd = spla.spsolve(A.to_scipy().tocsc(), b)
+    assert np.linalg.norm(x - xd) <= 1e-3 * np.linalg.norm(xd)
