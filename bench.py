@@ -193,7 +193,8 @@ def run_single(args, D, w, torch):
         log("setup", name)
         t0 = time.perf_counter()
         h = D.ddlr_setup(A, cfg["part"], p, k, args.variant, lanczos_steps=m, lanczos_start=v0, precision=prec,
-                         factor=factor, csolve=D.CSOLVE_MR if args.csolve == "mr" else D.CSOLVE_FACTOR,
+                         factor=factor, csolve={"factor": D.CSOLVE_FACTOR, "mr": D.CSOLVE_MR,
+                                                "cheb": D.CSOLVE_CHEB}[args.csolve],
                          alpha=alpha_for(args),
                          lowrank_build=D.BUILD_BIDIAG if args.lowrank_build == "bidiag" else D.BUILD_LANCZOS)
         torch.cuda.synchronize()
@@ -217,7 +218,7 @@ def run_single(args, D, w, torch):
     roof["traffic"] = traffic
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(cfg, b, v0, args.variant, mixed["x"], f64["x"], gm, args.cpu_rhs, args.csolve == "mr",
+        cpu = cpu_baseline(cfg, b, v0, args.variant, mixed["x"], f64["x"], gm, args.cpu_rhs, args.csolve,
                            alpha_for(args))
     workload = {
         "c1": "5-point Laplacian 64^2, 2x2 boxes",
@@ -241,7 +242,8 @@ def run_single(args, D, w, torch):
         "data": "synthetic",
         "config": {"workload": f"{args.config}: {workload}, DDLR-{args.variant} k={k}, {m} Lanczos steps, "
                                f"{nrhs} rhs per solve batch, {krylov} to 1e-6"
-                               + (", C_alpha by the MR approximate inverse" if args.csolve == "mr" else "")
+                               + {"factor": "", "mr": ", C_alpha by the MR approximate inverse",
+                                  "cheb": ", C_alpha by 5 Chebyshev steps"}[args.csolve]
                                + (f", alpha={alpha_for(args):g}" if alpha_for(args) != 1.0 else "")
                                + (", U_k V_k by bidiagonalisation" if args.lowrank_build == "bidiag" else ""),
                    "n": n, "nrhs": nrhs, "k": k, "p": p, "variant": args.variant, "csolve": args.csolve},
@@ -263,7 +265,7 @@ def run_single(args, D, w, torch):
     return out
 
 
-def cpu_baseline(cfg, b, v0, variant, x_mixed, x_f64, gm, ncols, cinv=False, alpha=1.0):
+def cpu_baseline(cfg, b, v0, variant, x_mixed, x_f64, gm, ncols, csolve="factor", alpha=1.0):
     """The oracle (plain C, FP64, OpenMP over blocks/rows) on the host cores:
     full solves of the first `ncols` right-hand sides of the same workload.
     Also states the GPU results' distance to the oracle's on those columns."""
@@ -272,8 +274,10 @@ def cpu_baseline(cfg, b, v0, variant, x_mixed, x_f64, gm, ncols, cinv=False, alp
     log("cpu baseline: oracle setup", threads, "threads")
     o = oracle.Oracle(cfg["A"], cfg["part"], cfg["p"], alpha=alpha,
                       factor=oracle.FACTOR_ILDL if gm else oracle.FACTOR_IC)
-    if cinv:
+    if csolve == "mr":
         o.use_cinv(3, 0.01, 20)
+    elif csolve == "cheb":
+        o.use_cheb(5, 10)
     o.lowrank(variant, cfg["k"], cfg["m"], v0)
     ncols = min(ncols, b.shape[1])
     t0 = time.perf_counter()
@@ -445,9 +449,9 @@ def main():
     ap.add_argument("--variant", type=int, default=1)
     ap.add_argument("--lowrank-build", default="lanczos", choices=["lanczos", "bidiag"],
                     help="DDLR-2 only: U_k, V_k by Lanczos on E^T A0^-2 E, or by bidiagonalisation of A0^-1 E")
-    ap.add_argument("--csolve", default="factor", choices=["factor", "mr"],
-                    help="C_alpha solver: its incomplete factor, or the MR approximate inverse (3 steps, "
-                         "drop tolerance 0.01, 20 entries per column)")
+    ap.add_argument("--csolve", default="factor", choices=["factor", "mr", "cheb"],
+                    help="C_alpha solver: its incomplete factor, the MR approximate inverse (3 steps, drop "
+                         "tolerance 0.01, 20 entries per column), or 5 preconditioned Chebyshev steps")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-rhs", type=int, default=3, help="right-hand sides the oracle solves for the baseline")
     ap.add_argument("--copy-calibration", action="store_true",

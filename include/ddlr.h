@@ -70,7 +70,16 @@ typedef enum { DDLR_CORDER_MULTICOLOR = 0, DDLR_CORDER_NATURAL = 1 } ddlr_corder
  * traces and norms as running sums in row-major order), so the result is
  * reproducible bit for bit.  X counts as SPD when ||I - C_alpha X||_inf < 1
  * (largest absolute row sum; it bounds the spectral radius of I - C_alpha X). */
-typedef enum { DDLR_CSOLVE_FACTOR = 0, DDLR_CSOLVE_MR = 1 } ddlr_csolve;
+/* DDLR_CSOLVE_CHEB: the paper's other C_alpha solver, cheb_iters steps of
+ * Chebyshev acceleration (Saad, Iterative Methods for Sparse Linear Systems,
+ * Alg. 12.1) from 0, preconditioned by the block-Jacobi matrix
+ * D_alpha = blockdiag(C_i) of each subdomain's interface couplings (factored
+ * by incomplete LDL^T), on an interval from cheb_lanczos Lanczos steps on the
+ * pencil (C_alpha, D_alpha) started from the vector of ones, each extreme Ritz
+ * value widened by its residual bound (a non-positive lower end becomes half
+ * the smallest Ritz value).  The polynomial solve is symmetric; it counts as
+ * SPD when D_alpha's pivots and the smallest Ritz value are positive. */
+typedef enum { DDLR_CSOLVE_FACTOR = 0, DDLR_CSOLVE_MR = 1, DDLR_CSOLVE_CHEB = 2 } ddlr_csolve;
 /* How DDLR-2's U_k and V_k are computed (Sec. 4.3): Lanczos on
  * E^T A0^{-2} E, then U_k = A0^{-1} E V_k (k more solves); or the Lanczos
  * (Golub-Kahan) bidiagonalisation of A0^{-1} E, which gives both at once:
@@ -110,6 +119,8 @@ typedef struct {
     int32_t cinv_lfil;     /* DDLR_CSOLVE_MR: kept off-diagonal entries per column (>= 0); default 20 */
     int32_t lowrank_build; /* ddlr_lowrank_build; DDLR_BUILD_BIDIAG needs DDLR_2 and lanczos_check = 0; default
                               DDLR_BUILD_LANCZOS */
+    int32_t cheb_iters;    /* DDLR_CSOLVE_CHEB: Chebyshev steps per solve (1..64); default 5 (the paper's) */
+    int32_t cheb_lanczos;  /* DDLR_CSOLVE_CHEB: Lanczos steps of the spectrum estimate (2..200); default 10 */
 } ddlr_options;
 
 typedef struct {
@@ -141,6 +152,8 @@ typedef struct {
     int64_t nnz_cinv;       /* stored entries of X */
     double cinv_res;        /* ||I - C_alpha X||_F */
     double cinv_res_inf;    /* ||I - C_alpha X||_inf (the SPD certificate needs < 1) */
+    double cheb_lo, cheb_hi;           /* DDLR_CSOLVE_CHEB: safeguarded interval of D_alpha^{-1} C_alpha */
+    double cheb_ritz_lo, cheb_ritz_hi; /* its smallest and largest Ritz value */
 } ddlr_info;
 
 typedef struct ddlr_prec ddlr_prec;
@@ -206,7 +219,8 @@ ddlr_status ddlr_get_ordering(const ddlr_prec *h, int32_t *perm, int32_t *iface,
 
 /* Local factors in internal order: strict lower L as CSR (row_ptr n+1,
  * col/val nnz_l) and D (n).  Host arrays.  With DDLR_CSOLVE_MR the interface
- * rows of L are empty and D is 1 there. */
+ * rows of L are empty and D is 1 there; with DDLR_CSOLVE_CHEB they hold the
+ * factor of D_alpha = blockdiag(C_i). */
 ddlr_status ddlr_get_factor(const ddlr_prec *h, int64_t *row_ptr, int32_t *col, double *val, double *D);
 
 /* The approximate inverse X ~ C_alpha^{-1} of Algorithm alg:mr (Sec. 4.4),

@@ -24,7 +24,7 @@ THETA_LAMBDA_K1, THETA_ZERO = 0, 1
 FACTOR_IC0, FACTOR_ILDL0 = 0, 1
 CORDER_MULTICOLOR, CORDER_NATURAL = 0, 1
 FP64, FP32, FP32_UK_BF16 = 0, 1, 2
-CSOLVE_FACTOR, CSOLVE_MR = 0, 1
+CSOLVE_FACTOR, CSOLVE_MR, CSOLVE_CHEB = 0, 1, 2
 BUILD_LANCZOS, BUILD_BIDIAG = 0, 1
 
 
@@ -38,7 +38,7 @@ class ddlr_options(C.Structure):
                 ("no_autotune", C.c_int32), ("lanczos_check", C.c_int32), ("lanczos_max", C.c_int32),
                 ("lanczos_tol", C.c_double), ("seed", C.c_uint64), ("lanczos_start", C.c_void_p),
                 ("csolve", C.c_int32), ("cinv_iters", C.c_int32), ("cinv_tol", C.c_double), ("cinv_lfil", C.c_int32),
-                ("lowrank_build", C.c_int32)]
+                ("lowrank_build", C.c_int32), ("cheb_iters", C.c_int32), ("cheb_lanczos", C.c_int32)]
 
 
 class ddlr_tuning(C.Structure):
@@ -72,7 +72,9 @@ class ddlr_info(C.Structure):
                 ("levels_c", C.c_int32), ("spd", C.c_int32), ("precision", C.c_int32), ("on_device", C.c_int32),
                 ("theta", C.c_double), ("c0", C.c_double), ("fill_ratio", C.c_double), ("setup_ms", C.c_double),
                 ("lanczos_ms", C.c_double), ("csolve", C.c_int32), ("cinv_iters", C.c_int32),
-                ("nnz_cinv", C.c_int64), ("cinv_res", C.c_double), ("cinv_res_inf", C.c_double)]
+                ("nnz_cinv", C.c_int64), ("cinv_res", C.c_double), ("cinv_res_inf", C.c_double),
+                ("cheb_lo", C.c_double), ("cheb_hi", C.c_double), ("cheb_ritz_lo", C.c_double),
+                ("cheb_ritz_hi", C.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -207,7 +209,7 @@ def ddlr_setup(A, part, p: int, k: int, variant: int = DDLR_1, *, alpha: float =
                precision: int = FP64, device: int = 0, seed: int = 0, lanczos_start=None,
                autotune: bool = True, lanczos_check: int = 0, lanczos_max: int = 0, lanczos_tol: float = 0.0,
                csolve: int = CSOLVE_FACTOR, cinv_iters: int = 3, cinv_tol: float = 0.01, cinv_lfil: int = 20,
-               lowrank_build: int = BUILD_LANCZOS) -> Prec:
+               lowrank_build: int = BUILD_LANCZOS, cheb_iters: int = 5, cheb_lanczos: int = 10) -> Prec:
     """Builds the preconditioner. A: object with n, rowptr (int64), col (int32), val (float64)."""
     lib = load_library()
     rp = np.ascontiguousarray(A.rowptr, dtype=np.int64)
@@ -225,6 +227,7 @@ def ddlr_setup(A, part, p: int, k: int, variant: int = DDLR_1, *, alpha: float =
     opt.csolve, opt.cinv_iters, opt.cinv_tol, opt.cinv_lfil = int(csolve), int(cinv_iters), float(cinv_tol), int(
         cinv_lfil)
     opt.lowrank_build = int(lowrank_build)
+    opt.cheb_iters, opt.cheb_lanczos = int(cheb_iters), int(cheb_lanczos)
     v0 = None
     if lanczos_start is not None:
         v0 = np.ascontiguousarray(lanczos_start, dtype=np.float64)

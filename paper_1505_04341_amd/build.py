@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libddlr.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("ddlr_api.hip", "host_setup.cpp", "partition.cpp", "cinv.cpp")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("ddlr_api.hip", "host_setup.cpp", "partition.cpp", "cinv.cpp", "cheb.cpp")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # Packed FP32 instructions are disabled for all device code (some forms have

@@ -129,6 +129,7 @@ template <typename T> struct DevFactors {
     T *U = nullptr;                   // low-rank basis, row-major (rows x k)
     T *Ut = nullptr;                  // the same in MFMA tile order (k % 16 == 0), for U^T y
     T *xv = nullptr;                  // approximate inverse of C_alpha (values)
+    T *cneg = nullptr;                // -C_alpha (values), for the Chebyshev residual update
 };
 
 // A Lanczos run kept for continuation: basis Q (s x (cap+1), device
@@ -200,6 +201,11 @@ struct ddlr_prec {
     // approximate inverse of C_alpha: SELL-64 slice pointers, slice row -> interface row, columns
     int32_t *xrp = nullptr, *xrow = nullptr, *xci = nullptr;
     int64_t xnnz = 0;
+    // Chebyshev solver of C_alpha: C_alpha (CSR, device interface order), steps, scratch
+    int32_t *crp = nullptr, *cci = nullptr;
+    int cheb_nu = 0;
+    DMem chmem;
+    void *ch_t = nullptr, *ch_r = nullptr, *ch_d = nullptr, *ch_x = nullptr;  // n x kMaxRhs each, type T
     double *fval64 = nullptr, *bval64 = nullptr;
     float *fval32 = nullptr, *bval32 = nullptr;
     int ring_kw = 0;                          // 2, 3, 4, 8, 16 or 0 (ring kernel unusable)
@@ -296,6 +302,8 @@ struct DevHost {
     std::vector<double> ev, etv;
     std::vector<int32_t> xrp, xci;  // approximate inverse of C_alpha, interface rows in device order
     std::vector<double> xv;
+    std::vector<int32_t> crp, cci;  // C_alpha (Chebyshev solver), interface rows in device order, local columns
+    std::vector<double> cv;
 };
 
 // c_mode: -1 choose (few, wide interface levels -> level launches), 0 interface
@@ -392,9 +400,27 @@ DevHost build_devhost(const HostPlan& P, int c_mode) {
     }
     if (c_mode == 0) c_wide = false;
     if (c_mode == 1) c_wide = c_levels > 0;
+    if (P.csolve == 2) {
+        // Chebyshev: D_alpha solves by the interface levels alone; C_alpha for the residual
+        c_wide = c_levels > 0;
+        D.crp.assign(s + 1, 0);
+        std::vector<std::pair<int32_t, double>> row;
+        for (int64_t r = 0; r < s; ++r) {
+            const int64_t i = P.dev2int[m + r];
+            row.clear();
+            for (int64_t t = P.A0.rp[i]; t < P.A0.rp[i + 1]; ++t)
+                row.emplace_back((int32_t)(P.int2dev[P.A0.ci[t]] - m), P.A0.v[t]);
+            std::sort(row.begin(), row.end());
+            for (const auto& e : row) {
+                D.cci.push_back(e.first);
+                D.cv.push_back(-e.second);
+            }
+            D.crp[r + 1] = (int32_t)D.cci.size();
+        }
+    }
     for (int32_t b = 0; b < p; ++b)
         if (P.blk_lvl[b + 1] > P.blk_lvl[b]) D.narrow.push_back({P.blk_lvl[b], P.blk_lvl[b + 1]});
-    if (P.csolve) {
+    if (P.csolve == 1) {
         // C_alpha by its approximate inverse: X with device-order interface indices
         D.xrp.assign(s + 1, 0);
         std::vector<std::pair<int32_t, double>> row;
@@ -643,6 +669,11 @@ void upload_devhost(ddlr_prec* h, const DevHost& D) {
     h->etci = M.upload(D.etci);
     h->f64.ev = M.upload(D.ev);
     h->f64.etv = M.upload(D.etv);
+    if (!D.crp.empty()) {
+        h->crp = M.upload(D.crp);
+        h->cci = M.upload(D.cci);
+        h->f64.cneg = M.upload(D.cv);
+    }
     std::vector<double> xsell;
     if (!D.xrp.empty()) {
         // SELL-64 of X: rows by entry count (longest first, stable), slices of 64
@@ -697,6 +728,7 @@ void upload_devhost(ddlr_prec* h, const DevHost& D) {
         h->f32.ev = demote(D.ev);
         h->f32.etv = demote(D.etv);
         if (!xsell.empty()) h->f32.xv = demote(xsell);
+        if (!D.cv.empty()) h->f32.cneg = demote(D.cv);
     }
     h->wide = D.wide;
     h->nnarrow = (int)D.narrow.size();
@@ -987,6 +1019,46 @@ void wide_levels(ddlr_prec* h, const DevFactors<T>& F, int nrhs, const TIn* x, i
 // the interface block is solved apart from the B blocks (level launches or X)
 bool has_cpart(const ddlr_prec* h) { return !h->wide.empty() || h->xrp != nullptr; }
 
+// z_C = nu steps of Chebyshev acceleration for C_alpha z = x with the
+// block-Jacobi D_alpha (its solves: the interface levels), on the safeguarded
+// interval from setup; groups of kMaxRhs columns through the scratch.
+template <typename T, typename TIn, typename TOut>
+void cheb_dev(ddlr_prec* h, const DevFactors<T>& F, int nrhs, const TIn* x, int64_t ldx, TOut* z, int64_t ldz,
+              hipStream_t st, const int* done) {
+    // (the D_alpha level solves are timed by wide_levels under class 1)
+    const int64_t n = h->ndev, s = h->sdev, m = n - s;
+    const HostPlan& P = h->plan;
+    const double th = 0.5 * (P.ch_hi + P.ch_lo), de = 0.5 * (P.ch_hi - P.ch_lo), sg = th / de;
+    T* t = static_cast<T*>(h->ch_t);
+    T* r = static_cast<T*>(h->ch_r);
+    T* d = static_cast<T*>(h->ch_d);
+    T* acc = static_cast<T*>(h->ch_x);
+    for (int c0 = 0; c0 < nrhs; c0 += kMaxRhs) {
+        const int nr = std::min(kMaxRhs, nrhs - c0);
+        const TIn* xc = x + c0 * ldx;
+        TOut* zc = z + c0 * ldz;
+        const dim3 g = grid2(s, nr);
+        wide_levels<T, TIn, T>(h, F, nr, xc, ldx, t, n, st, done);  // t = D^{-1} x
+        hipLaunchKernelGGL((k_cheb_first<T, TIn>), g, dim3(256), 0, st, s, xc + m, ldx, t + m, r + m, d + m, acc + m, n,
+                           (T)(1.0 / th), done);
+        LAUNCHCHK();
+        double rho = 1.0 / sg;
+        for (int k = 1; k < h->cheb_nu; ++k) {
+            hipLaunchKernelGGL((k_csr_mv<T, T>), dim3(grid_for(s)), dim3(256), 0, st, s, nr, h->crp, h->cci, F.cneg,
+                               d + m, n, r + m, n, r + m, n, done);  // r -= C d
+            LAUNCHCHK();
+            const double rn = 1.0 / (2.0 * sg - rho);
+            wide_levels<T, T, T>(h, F, nr, r, n, t, n, st, done);  // t = D^{-1} r
+            hipLaunchKernelGGL((k_cheb_step<T>), g, dim3(256), 0, st, s, (T)(rn * rho), (T)(2.0 * rn / de), t + m,
+                               d + m, acc + m, n, done);
+            LAUNCHCHK();
+            rho = rn;
+        }
+        hipLaunchKernelGGL((k_cheb_out<T, TOut>), g, dim3(256), 0, st, s, acc + m, n, zc + m, ldz, done);
+        LAUNCHCHK();
+    }
+}
+
 template <typename T, typename TIn, typename TOut>
 void a0_solve_dev(ddlr_prec* h, const DevFactors<T>& F, int nrhs, const TIn* x, int64_t ldx, TOut* z, int64_t ldz,
                   hipStream_t st, const int* done) {
@@ -1000,7 +1072,8 @@ void a0_solve_dev(ddlr_prec* h, const DevFactors<T>& F, int nrhs, const TIn* x, 
         HIPCHK(hipStreamWaitEvent(h->side, h->ev_fork, 0));
         cst = h->side;
     }
-    if (!h->wide.empty()) wide_levels<T, TIn, TOut>(h, F, nrhs, x, ldx, z, ldz, cst, done);
+    if (h->cheb_nu > 0) cheb_dev<T, TIn, TOut>(h, F, nrhs, x, ldx, z, ldz, cst, done);
+    else if (!h->wide.empty()) wide_levels<T, TIn, TOut>(h, F, nrhs, x, ldx, z, ldz, cst, done);
     if (h->xrp) {  // z_C = X x_C
         ProfScope ps(h, 1, cst);
         const int64_t m = h->ndev - h->sdev;
@@ -1869,6 +1942,8 @@ void ddlr_options_default(ddlr_options* o) {
     o->cinv_iters = 3;
     o->cinv_tol = 0.01;
     o->cinv_lfil = 20;
+    o->cheb_iters = 5;
+    o->cheb_lanczos = 10;
 }
 
 void ddlr_solve_options_default(ddlr_solve_options* o) {
@@ -1900,13 +1975,21 @@ ddlr_status ddlr_setup(const ddlr_csr* A, const int32_t* part, int32_t p, int32_
         h->precision = opt.precision;
         h->variant = variant;
         if (const char* env = std::getenv("DDLR_LR_PLAIN")) h->lr_plain = env[0] == '1';
-        if (opt.csolve != DDLR_CSOLVE_FACTOR && opt.csolve != DDLR_CSOLVE_MR)
-            throw SetupError{DDLR_E_INVALID, "csolve must be DDLR_CSOLVE_FACTOR or DDLR_CSOLVE_MR"};
+        if (opt.csolve != DDLR_CSOLVE_FACTOR && opt.csolve != DDLR_CSOLVE_MR && opt.csolve != DDLR_CSOLVE_CHEB)
+            throw SetupError{DDLR_E_INVALID, "csolve must be DDLR_CSOLVE_FACTOR, DDLR_CSOLVE_MR or DDLR_CSOLVE_CHEB"};
+        if (opt.csolve == DDLR_CSOLVE_CHEB && (opt.cheb_iters < 1 || opt.cheb_iters > 64 || opt.cheb_lanczos < 2 ||
+                                               opt.cheb_lanczos > 200))
+            throw SetupError{DDLR_E_INVALID, "Chebyshev: 1 <= cheb_iters <= 64 and 2 <= cheb_lanczos <= 200"};
         build_plan(h->plan, A->n, A->row_ptr, A->col_idx, A->val, part, p, opt.alpha, opt.factor, opt.corder,
-                   opt.csolve == DDLR_CSOLVE_MR ? 1 : 0, opt.cinv_iters, opt.cinv_tol, opt.cinv_lfil);
+                   opt.csolve == DDLR_CSOLVE_MR ? 1 : opt.csolve == DDLR_CSOLVE_CHEB ? 2 : 0, opt.cinv_iters,
+                   opt.cinv_tol, opt.cinv_lfil, opt.cheb_lanczos);
         for (double d : h->plan.D) h->pivots_positive = h->pivots_positive && d > 0.0;
-        // with the approximate inverse, A0 is SPD when the B factors are and X is
-        if (h->plan.csolve) h->pivots_positive = h->pivots_positive && h->plan.x_spd;
+        // with the approximate inverse, A0 is SPD when the B factors are and X is;
+        // with Chebyshev, when D_alpha's pivots are positive and so is the
+        // estimated spectrum of D_alpha^{-1} C_alpha (the polynomial is then
+        // positive on the safeguarded interval)
+        if (h->plan.csolve == 1) h->pivots_positive = h->pivots_positive && h->plan.x_spd;
+        if (h->plan.csolve == 2) h->pivots_positive = h->pivots_positive && h->plan.ch_rlo > 0.0;
         h->spd = variant == 0 ? (int)h->pivots_positive : 0;
         const int64_t s = h->plan.s;
         if (variant != 0) {
@@ -1918,6 +2001,15 @@ ddlr_status ddlr_setup(const ddlr_csr* A, const int32_t* part, int32_t p, int32_
             HIPCHK(hipSetDevice(opt.device));
             DevLock dl(opt.device);
             upload_structures(h.get());
+            if (h->plan.csolve == 2) {  // Chebyshev scratch, kMaxRhs columns
+                h->cheb_nu = opt.cheb_iters;
+                const size_t tsz = h->precision == DDLR_FP64 ? sizeof(double) : sizeof(float);
+                const size_t bytes = tsz * (size_t)h->plan.n * kMaxRhs;
+                h->ch_t = h->chmem.alloc<char>(bytes);
+                h->ch_r = h->chmem.alloc<char>(bytes);
+                h->ch_d = h->chmem.alloc<char>(bytes);
+                h->ch_x = h->chmem.alloc<char>(bytes);
+            }
             if (const char* env = std::getenv("DDLR_NO_OVERLAP")) h->overlap = env[0] != '1';
             h->tune_mode = opt.no_autotune ? 0 : 1;
             if (const char* env = std::getenv("DDLR_CG_GRAPH")) h->graph_mode = env[0] == '0' ? 0 : env[0] == '1' ? 1 : 2;
@@ -1963,12 +2055,16 @@ ddlr_status ddlr_setup(const ddlr_csr* A, const int32_t* part, int32_t p, int32_
         release_streams(h.get());
         h->ws.mem.release();
         h->lrmem.release();
+        h->lrun.mem.release();
+        h->chmem.release();
         h->mem.release();
         return fail_status(e);
     } catch (const std::bad_alloc&) {
         release_streams(h.get());
         h->ws.mem.release();
         h->lrmem.release();
+        h->lrun.mem.release();
+        h->chmem.release();
         h->mem.release();
         g_err = "host out of memory";
         return DDLR_E_OOM;
@@ -2523,12 +2619,16 @@ ddlr_status ddlr_query(const ddlr_prec* h, ddlr_info* info) {
     info->fill_ratio = stored / (double)P.A.nnz();
     info->setup_ms = h->setup_ms;
     info->lanczos_ms = h->lanczos_ms;
-    info->csolve = P.csolve ? DDLR_CSOLVE_MR : DDLR_CSOLVE_FACTOR;
+    info->csolve = P.csolve == 1 ? DDLR_CSOLVE_MR : P.csolve == 2 ? DDLR_CSOLVE_CHEB : DDLR_CSOLVE_FACTOR;
+    info->cheb_lo = P.ch_lo;
+    info->cheb_hi = P.ch_hi;
+    info->cheb_ritz_lo = P.ch_rlo;
+    info->cheb_ritz_hi = P.ch_rhi;
     info->cinv_iters = P.x_iters;
-    info->nnz_cinv = P.csolve ? P.X.nnz() : 0;
-    info->cinv_res = P.csolve ? P.x_res.back() : 0.0;
-    info->cinv_res_inf = P.csolve ? P.x_rinf : 0.0;
-    if (P.csolve) info->fill_ratio += (double)P.X.nnz() / (double)P.A.nnz();
+    info->nnz_cinv = P.csolve == 1 ? P.X.nnz() : 0;
+    info->cinv_res = P.csolve == 1 ? P.x_res.back() : 0.0;
+    info->cinv_res_inf = P.csolve == 1 ? P.x_rinf : 0.0;
+    if (P.csolve == 1) info->fill_ratio += (double)P.X.nnz() / (double)P.A.nnz();
     return DDLR_OK;
 }
 
@@ -2538,8 +2638,8 @@ ddlr_status ddlr_get_cinv(const ddlr_prec* h, int64_t* row_ptr, int32_t* col, do
         return DDLR_E_INVALID;
     }
     const HostPlan& P = h->plan;
-    if (!P.csolve) {
-        g_err = "the preconditioner factors C_alpha (no approximate inverse)";
+    if (P.csolve != 1) {
+        g_err = "the preconditioner does not solve C_alpha by the approximate inverse";
         return DDLR_E_INVALID;
     }
     std::copy(P.X.rp.begin(), P.X.rp.end(), row_ptr);
@@ -2852,6 +2952,7 @@ void ddlr_destroy(ddlr_prec* h) {
     if (h->ws.done_host) (void)hipHostFree(h->ws.done_host);
     h->lrmem.release();
     h->lrun.mem.release();
+    h->chmem.release();
     h->mem.release();
     delete h;
 }
@@ -3344,7 +3445,7 @@ void server_loop(ddlr_server* S) {
 }
 
 size_t prec_bytes(const ddlr_prec* h) {
-    return h->mem.bytes + h->lrmem.bytes + h->ws.mem.bytes + h->ws.gmem.bytes + h->lrun.mem.bytes;
+    return h->mem.bytes + h->lrmem.bytes + h->ws.mem.bytes + h->ws.gmem.bytes + h->lrun.mem.bytes + h->chmem.bytes;
 }
 
 }  // namespace

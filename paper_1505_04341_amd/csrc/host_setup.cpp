@@ -207,10 +207,25 @@ void form_a0(HostPlan& P) {
 // zero-fill incomplete LU factorisation on the block's symmetric pattern; for
 // a symmetric matrix U = D L^T, so L is the strict lower part and D the
 // diagonal of the result.
-void factor_blocks(HostPlan& P, int factor) {
-    const int32_t nfact = P.csolve ? P.p : P.p + 1;  // blocks factored (C_alpha last)
+void factor_blocks(HostPlan& P, int factor, const int32_t* part) {
+    const int32_t nfact = P.csolve == 1 ? P.p : P.p + 1;  // blocks factored (C_alpha last)
     const int64_t n = P.n;
     HostCsr W = P.A0;  // working copy, both triangles
+    if (P.csolve == 2) {
+        // D_alpha = blockdiag(C_i): drop the interface couplings between subdomains
+        HostCsr F;
+        F.rp.assign(n + 1, 0);
+        for (int64_t i = 0; i < n; ++i) {
+            for (int64_t t = W.rp[i]; t < W.rp[i + 1]; ++t) {
+                const int64_t j = W.ci[t];
+                if (i >= P.m && j >= P.m && part[P.perm[i]] != part[P.perm[j]]) continue;
+                F.ci.push_back(W.ci[t]);
+                F.v.push_back(W.v[t]);
+            }
+            F.rp[i + 1] = (int64_t)F.ci.size();
+        }
+        W = std::move(F);
+    }
     std::vector<int64_t> diagpos(n, -1);
     for (int64_t i = 0; i < n; ++i)
         for (int64_t t = W.rp[i]; t < W.rp[i + 1]; ++t)
@@ -305,7 +320,7 @@ void schedule(HostPlan& P) {
 
 void build_plan(HostPlan& P, int64_t n, const int64_t* rp, const int32_t* ci, const double* v, const int32_t* part,
                 int32_t p, double alpha, int factor, int corder, int csolve, int cinv_iters, double cinv_tol,
-                int cinv_lfil) {
+                int cinv_lfil, int cheb_lanczos) {
     if (!(alpha > 0.0) || !std::isfinite(alpha)) fail(DDLR_E_INVALID, "alpha must be positive");
     validate(n, rp, ci, v, part, p);
     P.n = n;
@@ -316,8 +331,9 @@ void build_plan(HostPlan& P, int64_t n, const int64_t* rp, const int32_t* ci, co
     permute_matrix(P, rp, ci, v);
     form_a0(P);
     P.csolve = csolve;
-    factor_blocks(P, factor);
-    if (csolve) build_cinv(P, cinv_iters, cinv_tol, cinv_lfil);
+    factor_blocks(P, factor, part);
+    if (csolve == 1) build_cinv(P, cinv_iters, cinv_tol, cinv_lfil);
+    if (csolve == 2) cheb_bounds(P, cheb_lanczos);
     schedule(P);
 }
 

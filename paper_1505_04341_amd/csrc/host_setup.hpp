@@ -57,6 +57,10 @@ struct HostPlan {
     int x_iters = 0;
     double x_rinf = 0.0;        // ||I - C_alpha X||_inf of the final X
     bool x_spd = false;         // x_rinf < 1
+    // C_alpha by preconditioned Chebyshev (csolve = 2; cheb.cpp): the interface
+    // block of L, D factors D_alpha = blockdiag(C_i); safeguarded interval
+    // [ch_lo, ch_hi] and extreme Ritz values of D_alpha^{-1} C_alpha
+    double ch_lo = 0.0, ch_hi = 0.0, ch_rlo = 0.0, ch_rhi = 0.0;
 };
 
 // Validates A (sorted columns, symmetric values) and part.
@@ -66,10 +70,15 @@ void validate(int64_t n, const int64_t* rp, const int32_t* ci, const double* v, 
 // 1e-14 |a_ii|).  corder: 0 = greedy multicolour interface order, 1 = natural.
 // csolve: 0 = C_alpha factored like the B blocks; 1 = C_alpha by the
 // approximate inverse of Algorithm alg:mr (cinv_iters steps, drop tolerance
-// cinv_tol, at most cinv_lfil kept off-diagonal entries per column).
+// cinv_tol, at most cinv_lfil kept off-diagonal entries per column); 2 =
+// preconditioned Chebyshev with D_alpha = blockdiag(C_i), its spectrum from
+// cheb_lanczos Lanczos steps on (C_alpha, D_alpha).
 void build_plan(HostPlan& P, int64_t n, const int64_t* rp, const int32_t* ci, const double* v,
                 const int32_t* part, int32_t p, double alpha, int factor, int corder, int csolve = 0,
-                int cinv_iters = 3, double cinv_tol = 0.01, int cinv_lfil = 20);
+                int cinv_iters = 3, double cinv_tol = 0.01, int cinv_lfil = 20, int cheb_lanczos = 10);
+
+// Spectrum interval of D_alpha^{-1} C_alpha for the Chebyshev solver (cheb.cpp).
+void cheb_bounds(HostPlan& P, int mc);
 
 // X ~ C_alpha^{-1} by Algorithm alg:mr into P.X, P.x_res, P.x_iters, P.x_spd.
 void build_cinv(HostPlan& P, int nit, double tol, int lfil);

@@ -737,6 +737,47 @@ __global__ __launch_bounds__(256) void k_cinv_sell(int64_t rows, int nrhs, const
         if (r < nrhs) z[i + r * ldz] = (TOut)acc[r];
 }
 
+// Chebyshev acceleration for the C_alpha solve (Sec. 4.4; Saad, Iterative
+// Methods for Sparse Linear Systems, Alg. 12.1), on the interface rows:
+// pointers at the first interface row, ld = n, grid (row chunks, nrhs).
+//   first:  r = x, d = t / theta (t = D^{-1} x), acc = d
+//   step:   d = c1 d + c2 t (t = D^{-1} r), acc += d
+//   out:    z = acc
+template <typename T, typename TIn>
+__global__ void k_cheb_first(int64_t rows, const TIn* x, int64_t ldx, const T* t, T* r, T* d, T* acc, int64_t ld,
+                             T inv_theta, const int* __restrict__ done) {
+    if (done && *done) return;
+    const int64_t c = blockIdx.y;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < rows; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t q = i + c * ld;
+        r[q] = (T)x[i + c * ldx];
+        const T v = t[q] * inv_theta;
+        d[q] = v;
+        acc[q] = v;
+    }
+}
+
+template <typename T>
+__global__ void k_cheb_step(int64_t rows, T c1, T c2, const T* t, T* d, T* acc, int64_t ld,
+                            const int* __restrict__ done) {
+    if (done && *done) return;
+    const int64_t c = blockIdx.y;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < rows; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t q = i + c * ld;
+        const T v = c1 * d[q] + c2 * t[q];
+        d[q] = v;
+        acc[q] += v;
+    }
+}
+
+template <typename T, typename TOut>
+__global__ void k_cheb_out(int64_t rows, const T* acc, int64_t ld, TOut* z, int64_t ldz, const int* __restrict__ done) {
+    if (done && *done) return;
+    const int64_t c = blockIdx.y;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < rows; i += (int64_t)gridDim.x * blockDim.x)
+        z[i + c * ldz] = (TOut)acc[i + c * ld];
+}
+
 // ------------------------------------------------------- low-rank correction
 //
 // DDLR-1 (eq. gkt):  w = c0 y + U_k (d .* (U_k^T y)),   U_k: s x k

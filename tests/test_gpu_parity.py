@@ -822,3 +822,80 @@ def test_spmv_compact_storage_bitwise(name):
     D.ddlr_solve(h1, to_dev(b), x1, maxit=5)
     D.ddlr_solve(h2, to_dev(b), x2, maxit=5)
     assert torch.equal(x1, x2)
+
+
+# ------------------------ C_alpha by preconditioned Chebyshev (Sec. 4.4, Table 3)
+
+def setup_pair_cheb(cfg, variant=1, nu=5, mc=10, env=None, **kw):
+    env = dict(env or {})
+    os.environ.update(env)
+    try:
+        h = D.ddlr_setup(cfg["A"], cfg["part"], cfg["p"], cfg["k"], variant, lanczos_steps=cfg.get("m", 0),
+                         lanczos_start=w.lanczos_start(cfg["A"].n, 0), csolve=D.CSOLVE_CHEB, cheb_iters=nu,
+                         cheb_lanczos=mc, **kw)
+    finally:
+        for key in env:
+            os.environ.pop(key, None)
+    o = Oracle(cfg["A"], cfg["part"], cfg["p"], alpha=kw.get("alpha", 1.0), corder=kw.get("corder", 0))
+    o.use_cheb(nu, mc)
+    return h, o
+
+
+@pytest.mark.parametrize("name", ["c1", "small3d", "irregular", "big3d"])
+@pytest.mark.parametrize("overlap", ["0", "1"])
+def test_cheb_a0_solve(name, overlap):
+    cfg = CASES[name]()
+    say("cheb a0_solve", name, "overlap", overlap)
+    h, o = setup_pair_cheb(cfg, variant=D.VARIANT_A0, env={"DDLR_NO_OVERLAP": "1" if overlap == "0" else "0"})
+    n = cfg["A"].n
+    rng = np.random.default_rng(13)
+    for nrhs in (1, 3, 17):  # 17: two column groups of the scratch
+        x = rng.standard_normal((n, nrhs))
+        y = torch.empty((nrhs, n), dtype=torch.float64, device=DEV)
+        D.ddlr_a0_solve(h, to_dev(x), y)
+        ref = o.a0_solve(x)
+        assert rel(to_host(y), ref) <= 1e-11, (nrhs, rel(to_host(y), ref))
+
+
+@pytest.mark.parametrize("name", ["c1", "small3d"])
+@pytest.mark.parametrize("variant", [1, 2])
+def test_cheb_lanczos_apply_and_solve(name, variant):
+    cfg = CASES[name]()
+    say("cheb lanczos/apply/solve", name, variant)
+    h, o = setup_pair_cheb(cfg, variant=variant)
+    o.lowrank(variant, cfg["k"], cfg["m"], w.lanczos_start(cfg["A"].n, 0))
+    gr, orz = D.ddlr_get_lanczos(h)[2], o.lanczos_record()[2]
+    k = cfg["k"]
+    assert np.abs(gr[: k + 1] - orz[: k + 1]).max() <= 1e-8 * max(1.0, abs(orz[0]))
+    assert bool(D.ddlr_query(h)["spd"]) == bool(o.spd) and o.spd
+    b, _ = w.rhs_from_solution(cfg["A"], 0, 2)
+    x = torch.zeros((2, cfg["A"].n), dtype=torch.float64, device=DEV)
+    st, info = D.ddlr_solve(h, to_dev(b), x)
+    xo, infoo = o.pcg(b)
+    assert st == D.OK
+    for i, io in zip(info, infoo["its"]):
+        assert abs(i["iters"] - int(io)) <= 1 and i["relres_true"] <= 1.05e-6
+    if variant == 1:
+        U, lam, th = o.get_lowrank()
+        D.ddlr_set_lowrank(h, 1, U, lam, th)
+    else:
+        U, H = o.get_lowrank()
+        D.ddlr_set_lowrank(h, 2, U, H)
+    xx = np.random.default_rng(4).standard_normal((cfg["A"].n, 3))
+    y = torch.empty((3, cfg["A"].n), dtype=torch.float64, device=DEV)
+    D.ddlr_apply(h, to_dev(xx), y)
+    assert rel(to_host(y), o.apply(xx)) <= 1e-10
+
+
+def test_cheb_mixed_precision_solve():
+    cfg = CASES["small3d"]()
+    say("cheb mixed")
+    h, o = setup_pair_cheb(cfg, variant=1, precision=D.FP32)
+    o.lowrank(1, cfg["k"], cfg["m"], w.lanczos_start(cfg["A"].n, 0))
+    b, _ = w.rhs_from_solution(cfg["A"], 0, 3)
+    x = torch.zeros((3, cfg["A"].n), dtype=torch.float64, device=DEV)
+    st, info = D.ddlr_solve(h, to_dev(b), x)
+    _, infoo = o.pcg(b)
+    assert st == D.OK
+    for i, io in zip(info, infoo["its"]):
+        assert i["relres_true"] <= 1.05e-6 and i["iters"] <= int(1.1 * io) + 1

@@ -170,3 +170,25 @@ def test_cinv_option_errors():
     h = D.ddlr_setup(c["A"], c["part"], c["p"], c["k"], D.DDLR_1, device=-1)
     with pytest.raises(D.DDLRError):
         D.ddlr_get_cinv(h)
+
+
+@pytest.mark.parametrize("name,cfg,kw", list(_cases()), ids=[c[0] for c in _cases()])
+def test_cheb_factor_and_interval_match_oracle(name, cfg, kw):
+    """Chebyshev C_alpha solver: the block-Jacobi factor of D_alpha (interface
+    rows of L, D) equals the oracle's; the spectrum interval from the pencil
+    Lanczos agrees to rounding (the two use different tridiagonal eigensolvers)."""
+    A = cfg["A"]
+    h = D.ddlr_setup(A, cfg["part"], cfg["p"], cfg["k"], D.DDLR_1, device=-1, csolve=D.CSOLVE_CHEB, **kw)
+    o = Oracle(A, cfg["part"], cfg["p"], alpha=kw.get("alpha", 1.0), corder=kw.get("corder", 0))
+    o.use_cheb(5, 10)
+    L, Dg = D.ddlr_get_factor(h)
+    Lo = o.csr("L")
+    assert np.array_equal(L.indptr, Lo.indptr) and np.array_equal(L.indices, Lo.indices)
+    assert np.abs(L.data - Lo.data).max(initial=0) <= 1e-12 * max(1.0, np.abs(Lo.data).max(initial=0))
+    assert np.abs(Dg - o.diag()).max() <= 1e-12 * np.abs(o.diag()).max()
+    q = D.ddlr_query(h)
+    lo, hi, rlo, rhi = o.cheb()
+    assert q["csolve"] == D.CSOLVE_CHEB
+    for a, b in ((q["cheb_lo"], lo), (q["cheb_hi"], hi), (q["cheb_ritz_lo"], rlo), (q["cheb_ritz_hi"], rhi)):
+        assert abs(a - b) <= 1e-10 * abs(b)
+    assert 0 < q["cheb_lo"] <= q["cheb_ritz_lo"] <= q["cheb_ritz_hi"] <= q["cheb_hi"]
