@@ -144,7 +144,7 @@ def test_greedy_colouring_bruteforce():
     assert o.ncolours == max(col.values()) + 1
 
 
-def test_survey_counts_c1():
+def test_structure_counts_c1():
     c = w.config("c1")
     o = Oracle(c["A"], c["part"], c["p"])
     assert (o.m, o.s, o.ncolours) == (3844, 252, 2)
@@ -155,7 +155,7 @@ def test_survey_counts_c1():
 
 
 @pytest.mark.slow
-def test_survey_counts_c2():
+def test_structure_counts_c2():
     c = w.config("c2")
     o = Oracle(c["A"], c["part"], c["p"])
     assert (o.n, o.s, o.ncolours) == (2097152, 281304, 2)
