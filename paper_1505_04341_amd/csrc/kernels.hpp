@@ -257,19 +257,29 @@ __device__ __forceinline__ void ring_sweep(int nlev, int row0, const int4* meta,
     constexpr int kD = RingDepth<T, KW>::value;
     LevelRegs<T, KW, TS, NS> buf[kD];
     auto lev = [&](int q) { return kBwd ? nlev - 1 - q : q; };
-#pragma unroll
-    for (int u = 0; u < kD - 1; ++u)
-        if (u < nlev) ring_load<T, KW, kBwd, TS, NT, NS>(buf[u], lev(u), row0, meta, ecol, eval, dinv, src);
     int q0 = 0;
-    // steady state: every prefetch in the group is a real level
-    for (; q0 + 2 * kD - 1 <= nlev; q0 += kD) {
+    if (nlev >= 2 * kD - 1) {
+        // The steady state sits on its own path behind an unconditional
+        // prologue: the compiler's load-counter waits then see every prefetch
+        // of the kD - 1 levels ahead on each path into the loop, and wait for
+        // the one level being computed, not for all but the newest loads.
 #pragma unroll
-        for (int u = 0; u < kD; ++u) {
-            ring_load<T, KW, kBwd, TS, NT, NS>(buf[(u + kD - 1) % kD], lev(q0 + u + kD - 1), row0, meta, ecol, eval,
-                                               dinv, src);
-            ring_compute<T, KW, kBwd, TS, TD, NT, NS>(buf[u], row0, ring, rmask, ecol, eval, dinv, src, dst);
-            level_sync<NT>();
+        for (int u = 0; u < kD - 1; ++u)
+            ring_load<T, KW, kBwd, TS, NT, NS>(buf[u], lev(u), row0, meta, ecol, eval, dinv, src);
+        // every prefetch in the group is a real level
+        for (; q0 + 2 * kD - 1 <= nlev; q0 += kD) {
+#pragma unroll
+            for (int u = 0; u < kD; ++u) {
+                ring_load<T, KW, kBwd, TS, NT, NS>(buf[(u + kD - 1) % kD], lev(q0 + u + kD - 1), row0, meta, ecol,
+                                                   eval, dinv, src);
+                ring_compute<T, KW, kBwd, TS, TD, NT, NS>(buf[u], row0, ring, rmask, ecol, eval, dinv, src, dst);
+                level_sync<NT>();
+            }
         }
+    } else {
+#pragma unroll
+        for (int u = 0; u < kD - 1; ++u)
+            if (u < nlev) ring_load<T, KW, kBwd, TS, NT, NS>(buf[u], lev(u), row0, meta, ecol, eval, dinv, src);
     }
     // tail
     for (; q0 < nlev; q0 += kD) {
@@ -430,18 +440,25 @@ __device__ __forceinline__ void ringr_sweep(int nlev, int row0, const int4* meta
     constexpr int kD = RingDepthR<T, R>::value;
     LevelRegsR<T, KW, R, TS> buf[kD];
     auto lev = [&](int q) { return kBwd ? nlev - 1 - q : q; };
-#pragma unroll
-    for (int u = 0; u < kD - 1; ++u)
-        if (u < nlev) ringr_load<T, KW, R, kBwd, TS>(buf[u], lev(u), row0, meta, ecol, eval, dinv, src, lds);
     int q0 = 0;
-    for (; q0 + 2 * kD - 1 <= nlev; q0 += kD) {
+    if (nlev >= 2 * kD - 1) {  // steady state behind an unconditional prologue, as in ring_sweep
 #pragma unroll
-        for (int u = 0; u < kD; ++u) {
-            ringr_load<T, KW, R, kBwd, TS>(buf[(u + kD - 1) % kD], lev(q0 + u + kD - 1), row0, meta, ecol, eval,
-                                           dinv, src, lds);
-            ringr_compute<T, KW, kRing, R, kBwd, TS, TD>(buf[u], row0, ring, ecol, eval, dinv, src, lds, dst, ldd);
-            lds_barrier();
+        for (int u = 0; u < kD - 1; ++u)
+            ringr_load<T, KW, R, kBwd, TS>(buf[u], lev(u), row0, meta, ecol, eval, dinv, src, lds);
+        for (; q0 + 2 * kD - 1 <= nlev; q0 += kD) {
+#pragma unroll
+            for (int u = 0; u < kD; ++u) {
+                ringr_load<T, KW, R, kBwd, TS>(buf[(u + kD - 1) % kD], lev(q0 + u + kD - 1), row0, meta, ecol, eval,
+                                               dinv, src, lds);
+                ringr_compute<T, KW, kRing, R, kBwd, TS, TD>(buf[u], row0, ring, ecol, eval, dinv, src, lds, dst,
+                                                             ldd);
+                lds_barrier();
+            }
         }
+    } else {
+#pragma unroll
+        for (int u = 0; u < kD - 1; ++u)
+            if (u < nlev) ringr_load<T, KW, R, kBwd, TS>(buf[u], lev(u), row0, meta, ecol, eval, dinv, src, lds);
     }
     for (; q0 < nlev; q0 += kD) {
 #pragma unroll
