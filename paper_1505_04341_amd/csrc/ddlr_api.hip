@@ -10,6 +10,7 @@
 #include <thread>
 #include <unordered_map>
 #include <cmath>
+#include <cstring>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -208,6 +209,7 @@ struct ddlr_prec {
     void *ch_t = nullptr, *ch_r = nullptr, *ch_d = nullptr, *ch_x = nullptr;  // n x kMaxRhs each, type T
     double *fval64 = nullptr, *bval64 = nullptr;
     float *fval32 = nullptr, *bval32 = nullptr;
+    int2 *fpk32 = nullptr, *bpk32 = nullptr;  // the FP32 entries as (column, value bits) pairs
     int ring_kw = 0;                          // 2, 3, 4, 8, 16 or 0 (ring kernel unusable)
     bool ring_ok64 = false, ring_ok32 = false;  // dependency window fits the LDS ring
     int ring_need = 0;                          // rows the ring must hold (dependency window)
@@ -591,6 +593,17 @@ void build_ring(ddlr_prec* h, const DevHost& D) {
         std::vector<float> f(fval.begin(), fval.end()), g(bval.begin(), bval.end());
         h->fval32 = M.upload(f);
         h->bval32 = M.upload(g);
+        auto pack = [](const std::vector<int32_t>& col, const std::vector<float>& val) {
+            std::vector<int2> pk(col.size());
+            for (size_t q = 0; q < col.size(); ++q) {
+                int32_t bits;
+                std::memcpy(&bits, &val[q], sizeof bits);
+                pk[q] = int2{col[q], bits};
+            }
+            return pk;
+        };
+        h->fpk32 = M.upload(pack(fcol, f));
+        h->bpk32 = M.upload(pack(bcol, g));
     }
 }
 
@@ -931,8 +944,8 @@ void launch_ring_rk(ddlr_prec* h, const T* dinv, int nrhs, const TIn* x, int64_t
                     hipStream_t st, const int* done) {
     const int ng = nrhs / R;
     hipLaunchKernelGGL((k_trsv_ring_r<T, KW, R, TIn, TOut>), dim3(h->nnarrow_pad * ng), dim3(kRingThreads), 0, st,
-                       h->rblk, h->nnarrow, h->nnarrow_pad, ng, h->lvl_ptr, h->foff, h->fcol, ring_fval<T>(h), h->boff_,
-                       h->bcol, ring_bval<T>(h), dinv, x, ldx, z, ldz, done);
+                       h->rblk, h->nnarrow, h->nnarrow_pad, ng, h->lvl_ptr, h->foff, h->fcol, ring_fval<T>(h),
+                       h->fpk32, h->boff_, h->bcol, ring_bval<T>(h), h->bpk32, dinv, x, ldx, z, ldz, done);
     LAUNCHCHK();
 }
 

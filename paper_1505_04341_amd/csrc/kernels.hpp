@@ -353,10 +353,29 @@ template <typename T, int KW, int R, typename TS> struct LevelRegsR {
     T dv[2];
 };
 
+// FP32 factors come as (column, value) pairs in one 8-byte word per entry
+// (epk), so an entry takes one vector load instead of two: the kernel is bound
+// by vector-memory instructions per level.  FP64 keeps separate arrays.
+template <typename T> constexpr bool ring_packed() { return sizeof(T) == 4; }
+
+template <typename T>
+__device__ __forceinline__ void ring_entry(const int32_t* __restrict__ ecol, const T* __restrict__ eval,
+                                           const int2* __restrict__ epk, int q, int& c, T& v) {
+    if constexpr (ring_packed<T>()) {
+        const int2 t = epk[q];
+        c = t.x;
+        v = __int_as_float(t.y);
+    } else {
+        c = ecol[q];
+        v = eval[q];
+    }
+}
+
 template <typename T, int KW, int R, bool kBwd, typename TS>
 __device__ __forceinline__ void ringr_load(LevelRegsR<T, KW, R, TS>& L, int q, int row0, const int4* meta,
                                            const int32_t* __restrict__ ecol, const T* __restrict__ eval,
-                                           const T* __restrict__ dinv, const TS* src, int64_t lds) {
+                                           const int2* __restrict__ epk, const T* __restrict__ dinv, const TS* src,
+                                           int64_t lds) {
     const int4 mq = meta[q];
     L.a = __builtin_amdgcn_readfirstlane(mq.x);
     L.e = __builtin_amdgcn_readfirstlane(meta[q + 1].x);
@@ -368,10 +387,7 @@ __device__ __forceinline__ void ringr_load(LevelRegsR<T, KW, R, TS>& L, int q, i
         const int i = min(L.a + (int)threadIdx.x + qq * kRingThreads, L.e - 1);
         const int base = L.off + (i - L.a);
 #pragma unroll
-        for (int j = 0; j < KW; ++j) {
-            L.c[qq][j] = ecol[base + j * nr];
-            L.v[qq][j] = eval[base + j * nr];
-        }
+        for (int j = 0; j < KW; ++j) ring_entry<T>(ecol, eval, epk, base + j * nr, L.c[qq][j], L.v[qq][j]);
 #pragma unroll
         for (int rr = 0; rr < R; ++rr) L.xv[qq][rr] = src[i + rr * lds];
         if (kBwd) L.dv[qq] = dinv[row0 + i];
@@ -381,8 +397,8 @@ __device__ __forceinline__ void ringr_load(LevelRegsR<T, KW, R, TS>& L, int q, i
 template <typename T, int KW, int kRing, int R, bool kBwd, typename TS, typename TD>
 __device__ __forceinline__ void ringr_compute(const LevelRegsR<T, KW, R, TS>& L, int row0, T* ring,
                                               const int32_t* __restrict__ ecol, const T* __restrict__ eval,
-                                              const T* __restrict__ dinv, const TS* src, int64_t lds, TD* dst,
-                                              int64_t ldd) {
+                                              const int2* __restrict__ epk, const T* __restrict__ dinv,
+                                              const TS* src, int64_t lds, TD* dst, int64_t ldd) {
     using V = T __attribute__((ext_vector_type(R)));
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
@@ -413,8 +429,10 @@ __device__ __forceinline__ void ringr_compute(const LevelRegsR<T, KW, R, TS>& L,
 #pragma unroll
         for (int rr = 0; rr < R; ++rr) sv[rr] = kBwd ? (T)src[i + rr * lds] * dvi : (T)src[i + rr * lds];
         for (int j = 0; j < KW; ++j) {
-            const T vj = eval[base + j * nr];
-            const V g = *reinterpret_cast<const V*>(ring + (size_t)(ecol[base + j * nr] & (kRing - 1)) * R);
+            int cj;
+            T vj;
+            ring_entry<T>(ecol, eval, epk, base + j * nr, cj, vj);
+            const V g = *reinterpret_cast<const V*>(ring + (size_t)(cj & (kRing - 1)) * R);
 #pragma unroll
             for (int rr = 0; rr < R; ++rr) sv[rr] = fnms(sv[rr], vj, g[rr]);
         }
@@ -435,8 +453,8 @@ template <int R> struct RingDepthR<double, R> { static constexpr int value = R <
 template <typename T, int KW, int kRing, int R, bool kBwd, typename TS, typename TD>
 __device__ __forceinline__ void ringr_sweep(int nlev, int row0, const int4* meta, T* ring,
                                             const int32_t* __restrict__ ecol, const T* __restrict__ eval,
-                                            const T* __restrict__ dinv, const TS* src, int64_t lds, TD* dst,
-                                            int64_t ldd) {
+                                            const int2* __restrict__ epk, const T* __restrict__ dinv, const TS* src,
+                                            int64_t lds, TD* dst, int64_t ldd) {
     constexpr int kD = RingDepthR<T, R>::value;
     LevelRegsR<T, KW, R, TS> buf[kD];
     auto lev = [&](int q) { return kBwd ? nlev - 1 - q : q; };
@@ -444,13 +462,13 @@ __device__ __forceinline__ void ringr_sweep(int nlev, int row0, const int4* meta
     if (nlev >= 2 * kD - 1) {  // steady state behind an unconditional prologue, as in ring_sweep
 #pragma unroll
         for (int u = 0; u < kD - 1; ++u)
-            ringr_load<T, KW, R, kBwd, TS>(buf[u], lev(u), row0, meta, ecol, eval, dinv, src, lds);
+            ringr_load<T, KW, R, kBwd, TS>(buf[u], lev(u), row0, meta, ecol, eval, epk, dinv, src, lds);
         for (; q0 + 2 * kD - 1 <= nlev; q0 += kD) {
 #pragma unroll
             for (int u = 0; u < kD; ++u) {
                 ringr_load<T, KW, R, kBwd, TS>(buf[(u + kD - 1) % kD], lev(q0 + u + kD - 1), row0, meta, ecol, eval,
-                                               dinv, src, lds);
-                ringr_compute<T, KW, kRing, R, kBwd, TS, TD>(buf[u], row0, ring, ecol, eval, dinv, src, lds, dst,
+                                               epk, dinv, src, lds);
+                ringr_compute<T, KW, kRing, R, kBwd, TS, TD>(buf[u], row0, ring, ecol, eval, epk, dinv, src, lds, dst,
                                                              ldd);
                 lds_barrier();
             }
@@ -458,7 +476,7 @@ __device__ __forceinline__ void ringr_sweep(int nlev, int row0, const int4* meta
     } else {
 #pragma unroll
         for (int u = 0; u < kD - 1; ++u)
-            if (u < nlev) ringr_load<T, KW, R, kBwd, TS>(buf[u], lev(u), row0, meta, ecol, eval, dinv, src, lds);
+            if (u < nlev) ringr_load<T, KW, R, kBwd, TS>(buf[u], lev(u), row0, meta, ecol, eval, epk, dinv, src, lds);
     }
     for (; q0 < nlev; q0 += kD) {
 #pragma unroll
@@ -467,8 +485,8 @@ __device__ __forceinline__ void ringr_sweep(int nlev, int row0, const int4* meta
             if (q < nlev) {
                 if (q + kD - 1 < nlev)
                     ringr_load<T, KW, R, kBwd, TS>(buf[(u + kD - 1) % kD], lev(q + kD - 1), row0, meta, ecol, eval,
-                                                   dinv, src, lds);
-                ringr_compute<T, KW, kRing, R, kBwd, TS, TD>(buf[u], row0, ring, ecol, eval, dinv, src, lds, dst,
+                                                   epk, dinv, src, lds);
+                ringr_compute<T, KW, kRing, R, kBwd, TS, TD>(buf[u], row0, ring, ecol, eval, epk, dinv, src, lds, dst,
                                                              ldd);
                 lds_barrier();
             }
@@ -482,8 +500,9 @@ template <typename T, int KW, int R, typename TIn, typename TOut>
 __global__ __launch_bounds__(kRingThreads) void k_trsv_ring_r(
     const RingBlock* __restrict__ blk, int nblk, int nblk_pad, int ngroups, const int32_t* __restrict__ lvl_ptr,
     const int32_t* __restrict__ foff, const int32_t* __restrict__ fcol, const T* __restrict__ fval,
-    const int32_t* __restrict__ boff, const int32_t* __restrict__ bcol, const T* __restrict__ bval,
-    const T* __restrict__ dinv, const TIn* x, int64_t ldx, TOut* z, int64_t ldz, const int* __restrict__ done) {
+    const int2* __restrict__ fpk, const int32_t* __restrict__ boff, const int32_t* __restrict__ bcol,
+    const T* __restrict__ bval, const int2* __restrict__ bpk, const T* __restrict__ dinv, const TIn* x, int64_t ldx,
+    TOut* z, int64_t ldz, const int* __restrict__ done) {
     constexpr int kRing = ring_rows_r<T, R>();
     __shared__ __attribute__((aligned(16))) T ring[kRing * R];
     __shared__ int4 meta[kRingMaxLevels + 1];
@@ -501,9 +520,11 @@ __global__ __launch_bounds__(kRingThreads) void k_trsv_ring_r(
     __syncthreads();
     const TIn* xr = x + (int64_t)g * R * ldx + d.row0;
     TOut* zr = z + (int64_t)g * R * ldz + d.row0;
-    ringr_sweep<T, KW, kRing, R, false, TIn, TOut>(nlev, d.row0, meta, ring, fcol, fval, dinv, xr, ldx, zr, ldz);
+    ringr_sweep<T, KW, kRing, R, false, TIn, TOut>(nlev, d.row0, meta, ring, fcol, fval, fpk, dinv, xr, ldx, zr,
+                                                   ldz);
     __syncthreads();  // global fence: the backward sweep reads y_i from memory
-    ringr_sweep<T, KW, kRing, R, true, TOut, TOut>(nlev, d.row0, meta, ring, bcol, bval, dinv, zr, ldz, zr, ldz);
+    ringr_sweep<T, KW, kRing, R, true, TOut, TOut>(nlev, d.row0, meta, ring, bcol, bval, bpk, dinv, zr, ldz, zr,
+                                                   ldz);
 }
 
 // ------------------------------------------------ A0 solve: one wide level
