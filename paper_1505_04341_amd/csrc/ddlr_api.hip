@@ -2259,7 +2259,7 @@ ddlr_status ddlr_spmv(ddlr_prec* h, int32_t nrhs, const double* x, int64_t ldx, 
 
 }  // extern "C"
 
-constexpr int kGmChunks = 64;
+constexpr int kGmChunks = 1024;  // row chunks of the Gram-Schmidt dot products (per group of basis vectors)
 
 static void ensure_gmres(ddlr_prec* h, int nr, int m) {
     Workspace& W = h->ws;
@@ -2314,11 +2314,11 @@ static void gmres_dev(ddlr_prec* h, int nr, const ddlr_solve_options& o, hipStre
             apply_dev(h, nr, Vj, n, W.z, n, st, W.done);               // z = M^{-1} v_j
             spmv_dev(h, nr, W.z, n, W.q, n, nullptr, st, W.done);      // w = A z
             for (int pass = 0; pass < 2; ++pass) {
-                hipLaunchKernelGGL(k_gm_dots, dim3(kGmChunks, j + 1), dim3(256), 0, st, n, nr, W.gV, W.q, W.gpart,
-                                   W.done);
+                hipLaunchKernelGGL(k_gm_dots, dim3(kGmChunks, (j + kGmGroup) / kGmGroup, nr), dim3(256), 0, st, n, nr,
+                                   j + 1, W.gV, W.q, W.gpart, W.done);
                 LAUNCHCHK();
-                hipLaunchKernelGGL(k_gm_coef, dim3(1), dim3(256), 0, st, kGmChunks, nr, j + 1, m, j, W.gpart, W.gcoef,
-                                   W.gH, W.glanes, W.done);
+                hipLaunchKernelGGL(k_gm_coef, dim3((nr * (j + 1) + 3) / 4), dim3(256), 0, st, kGmChunks, nr, j + 1, m,
+                                   j, W.gpart, W.gcoef, W.gH, W.glanes, W.done);
                 LAUNCHCHK();
                 hipLaunchKernelGGL(k_gm_sub, grid2(n, nr), dim3(256), 0, st, n, nr, j + 1, W.gV, W.gcoef,
                                    W.q, W.done);

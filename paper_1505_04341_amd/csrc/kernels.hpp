@@ -1753,44 +1753,60 @@ struct GmLane {
     int32_t its, kc, active, conv, dead, pad;  // kc: steps taken in the current cycle
 };
 
-// part[(l * nchunk + chunk) * nrhs + r] = V[l][r] . w[r] over the chunk's rows
-__global__ __launch_bounds__(256) void k_gm_dots(int64_t n, int nrhs, const double* __restrict__ V,
+// part[(l * nchunk + chunk) * nrhs + r] = V[l][r] . w[r] over the chunk's rows.
+// Grid (nchunk, ceil(ncols / kGmGroup), nrhs): a workgroup takes kGmGroup basis
+// vectors of one right-hand side, so w is read once per group instead of once
+// per basis vector; per (l, chunk, r) the terms and the reduction tree are
+// those of one vector at a time.
+constexpr int kGmGroup = 8;
+__global__ __launch_bounds__(256) void k_gm_dots(int64_t n, int nrhs, int ncols, const double* __restrict__ V,
                                                  const double* __restrict__ w, double* __restrict__ part,
                                                  const int* __restrict__ done) {
-    __shared__ double sh[4][kMaxRhs];
+    __shared__ double sh[4][kGmGroup];
     if (done && *done) return;
-    const int l = blockIdx.y, chunk = blockIdx.x, nchunk = gridDim.x;
-    double acc[kMaxRhs];
+    const int chunk = blockIdx.x, nchunk = gridDim.x;
+    const int l0 = blockIdx.y * kGmGroup, r = blockIdx.z;
+    const int ng = min(kGmGroup, ncols - l0);
+    double acc[kGmGroup];
 #pragma unroll
-    for (int r = 0; r < kMaxRhs; ++r) acc[r] = 0.0;
-    const double* Vl = V + (int64_t)l * nrhs * n;
+    for (int g = 0; g < kGmGroup; ++g) acc[g] = 0.0;
+    const double* wr = w + (int64_t)r * n;
     for (int64_t i = (int64_t)chunk * blockDim.x + threadIdx.x; i < n; i += (int64_t)nchunk * blockDim.x) {
+        const double wi = wr[i];
 #pragma unroll
-        for (int r = 0; r < kMaxRhs; ++r)
-            if (r < nrhs) acc[r] += Vl[r * n + i] * w[r * n + i];
+        for (int g = 0; g < kGmGroup; ++g)
+            if (g < ng) acc[g] += V[((int64_t)(l0 + g) * nrhs + r) * n + i] * wi;
     }
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int r = 0; r < nrhs; ++r) {
-        const double v = wave_sum(acc[r]);
-        if (lane == 0) sh[wv][r] = v;
+#pragma unroll
+    for (int g = 0; g < kGmGroup; ++g) {
+        const double v = wave_sum(acc[g]);
+        if (lane == 0) sh[wv][g] = v;
     }
     __syncthreads();
-    if (threadIdx.x < nrhs) {
-        const int r = threadIdx.x;
-        part[((int64_t)l * nchunk + chunk) * nrhs + r] = (sh[0][r] + sh[1][r]) + (sh[2][r] + sh[3][r]);
+    if ((int)threadIdx.x < ng) {
+        const int g = threadIdx.x;
+        part[((int64_t)(l0 + g) * nchunk + chunk) * nrhs + r] = (sh[0][g] + sh[1][g]) + (sh[2][g] + sh[3][g]);
     }
 }
 
 // coef[r][l] = sum over chunks; H column j of lane r accumulates coef (two
-// Gram-Schmidt passes add up to the Hessenberg entries)
-__global__ void k_gm_coef(int nchunk, int nrhs, int ncols, int m, int j, const double* __restrict__ part,
-                          double* __restrict__ coef, double* __restrict__ H, const GmLane* __restrict__ L,
-                          const int* __restrict__ done) {
+// Gram-Schmidt passes add up to the Hessenberg entries).  One wave per (r, l):
+// lane c sums chunks c, c + 64, ..., then a fixed shuffle tree; grid
+// ceil(nrhs * ncols / 4) workgroups of 256 threads.
+__global__ __launch_bounds__(256) void k_gm_coef(int nchunk, int nrhs, int ncols, int m, int j,
+                                                 const double* __restrict__ part, double* __restrict__ coef,
+                                                 double* __restrict__ H, const GmLane* __restrict__ L,
+                                                 const int* __restrict__ done) {
     if (done && *done) return;
-    for (int q = threadIdx.x; q < nrhs * ncols; q += blockDim.x) {
-        const int r = q / ncols, l = q - r * ncols;
-        double s = 0.0;
-        for (int c = 0; c < nchunk; ++c) s += part[((int64_t)l * nchunk + c) * nrhs + r];
+    const int lane = threadIdx.x & 63;
+    const int q = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (q >= nrhs * ncols) return;  // uniform across the wave
+    const int r = q / ncols, l = q - r * ncols;
+    double s = 0.0;
+    for (int c = lane; c < nchunk; c += 64) s += part[((int64_t)l * nchunk + c) * nrhs + r];
+    s = wave_sum(s);
+    if (lane == 0) {
         const bool act = L[r].active;
         coef[r * ncols + l] = act ? s : 0.0;
         if (act) H[((int64_t)r * m + j) * (m + 1) + l] += s;
