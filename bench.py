@@ -444,7 +444,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "u1"])
     ap.add_argument("--variant", type=int, default=1)
     ap.add_argument("--lowrank-build", default="lanczos", choices=["lanczos", "bidiag"],

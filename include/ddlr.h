@@ -309,13 +309,13 @@ ddlr_status ddlr_extend_lowrank(ddlr_prec *h, int32_t k, int32_t more_steps, int
  * launch overhead, but forked branches of a replayed graph (the interface
  * levels beside the block solve) may run one after the other.  Unless the
  * environment forces one form (DDLR_CG_GRAPH=1 graphs, 0 eager), the first
- * solves with a column count time whole chunks on the host, two per
+ * solves with a column count time whole chunks on the host, three per
  * candidate: replayed and eager, each with the interface block's solve beside
  * and in line with the block solve (that overlap competes with other forked
  * work inside an iteration and a replayed graph may serialise it, so its
- * A0-only timing above does not decide it for PCG); the fastest is kept, but
- * replayed chunks with the interface solve in line stay unless another
- * candidate is more than 3 % faster (chunk timings vary by a few percent).
+ * A0-only timing above does not decide it for PCG); the fastest (minimum over
+ * its chunks) is kept, but replayed chunks with the interface solve in line
+ * stay unless another candidate is more than 1 % faster.
  * cg_* below report that measurement. */
 typedef struct {
     int32_t nrhs;            /* column count the shape is for */
@@ -329,8 +329,8 @@ typedef struct {
     float a0_plain_us;       /* the plain per-level kernel (0: not measured) */
     int32_t cg_graph;        /* PCG chunks of this column count: 1 replayed graphs, 0 eager launches,
                                 -1 still being measured */
-    float cg_eager_us;       /* fastest timed eager chunk of 8 PCG iterations with the chosen overlap, or with
-                                the interface solve beside the block solve while undecided (0: none yet) */
+    float cg_eager_us;       /* fastest timed eager chunk of 8 PCG iterations with the interface solve beside
+                                the block solve, or in the only form when nothing overlaps (0: none yet) */
     float cg_graph_us;       /* the same for replayed chunks */
     int32_t cg_overlap;      /* PCG: interface solve beside (1) or in line with (0) the block solve; -1: still
                                 being measured, or nothing to overlap */

@@ -244,6 +244,7 @@ struct ddlr_prec {
         int timed[2][3] = {};
         bool captured[3] = {};
         int graph = -1, ov = -2;  // decided form (ov -1: no interface overlap to choose)
+        int solves = 0;           // solves run while measuring
         CgMode() {
             for (auto& a : us)
                 for (double& v : a) v = 1e30;
@@ -2442,6 +2443,9 @@ static void cg_chunk(ddlr_prec* h, int nr, hipStream_t st, bool graph) {
     HIPCHK(hipGraphLaunch(it->second.second, st));
 }
 
+constexpr int kCgSamples = 3;        // timed chunks per launch-form candidate
+constexpr int kCgMeasureSolves = 6;  // after this many solves, chunks where lanes finished count too
+
 static void pcg_dev(ddlr_prec* h, int nr, const ddlr_solve_options& o, hipStream_t ust) {
     ensure_cg_streams(h);
     hipStream_t st = h->cg_st;
@@ -2457,9 +2461,15 @@ static void pcg_dev(ddlr_prec* h, int nr, const ddlr_solve_options& o, hipStream
     // line with the block solve when both are possible (inside an iteration the
     // overlapped levels compete with other forked work, and a replayed graph
     // may run forked branches one after the other, so neither the A0-only
-    // timing nor eager timing decides it).  Each candidate gets two timed
-    // chunks (a graph's capture chunk is not timed); the fastest is kept.
+    // timing nor eager timing decides it).  Each candidate gets kCgSamples
+    // timed chunks (a graph's capture chunk is not timed); the fastest is kept.
+    // A chunk is a sample only when every lane ran through all of it: lanes
+    // that finish leave later chunks of a solve cheaper, and the candidates
+    // are sampled at different points of the solves.
     ddlr_prec::CgMode& m = h->cg_mode[nr];
+    if (m.graph < 0) ++m.solves;
+    std::vector<CgLane> lh(nr);
+    int run_prev = -1;  // lanes running at the end of the previous chunk of this solve
     const bool can_ov = has_cpart(h) && h->nnarrow > 0 && h->overlap && h->side;
     const int gfirst = h->graph_mode == 0 ? 0 : 1, glast = h->graph_mode == 1 ? 1 : 0;
     const int ofirst = can_ov ? 1 : -1, olast = can_ov ? 0 : -1;
@@ -2477,7 +2487,7 @@ static void pcg_dev(ddlr_prec* h, int nr, const ddlr_solve_options& o, hipStream
             bool found = false;
             for (int gg = gfirst; gg >= glast && !found; --gg)
                 for (int oo = ofirst; oo >= olast && !found; --oo)
-                    if (m.timed[gg][oo + 1] < 2) {
+                    if (m.timed[gg][oo + 1] < kCgSamples) {
                         g = gg;
                         ov = oo;
                         found = true;
@@ -2493,8 +2503,14 @@ static void pcg_dev(ddlr_prec* h, int nr, const ddlr_solve_options& o, hipStream
         const double us = std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
         const bool done = *h->ws.done_host != 0;
         if (!h->prof && m.graph < 0) {
+            HIPCHK(hipMemcpyAsync(lh.data(), h->ws.lanes, sizeof(CgLane) * nr, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            int run = 0;
+            for (const CgLane& l : lh) run += l.phase == 2;
+            const bool full = (run_prev == nr && run == nr) || m.solves > kCgMeasureSolves;
+            run_prev = run;
             if (g == 1) m.captured[ov + 1] = true;
-            if (timed && !done) {  // a chunk that ran all its iterations
+            if (timed && !done && full) {  // a chunk that ran all its iterations on every lane
                 m.us[g][ov + 1] = std::min(m.us[g][ov + 1], us);
                 ++m.timed[g][ov + 1];
             }
@@ -2502,7 +2518,7 @@ static void pcg_dev(ddlr_prec* h, int nr, const ddlr_solve_options& o, hipStream
             double best = 1e30;
             for (int gg = gfirst; gg >= glast; --gg)
                 for (int oo = ofirst; oo >= olast; --oo) {
-                    all = all && m.timed[gg][oo + 1] >= 2;
+                    all = all && m.timed[gg][oo + 1] >= kCgSamples;
                     if (m.us[gg][oo + 1] < best) {
                         best = m.us[gg][oo + 1];
                         m.graph = gg;  // provisional; kept only when all are measured
@@ -2510,8 +2526,9 @@ static void pcg_dev(ddlr_prec* h, int nr, const ddlr_solve_options& o, hipStream
                     }
                 }
             // the plain form (replayed if allowed, interface solve in line) stays
-            // unless another is clearly faster: chunk timings vary by a few percent
-            if (m.us[gfirst][olast + 1] <= best / 0.97) {
+            // unless another is faster by more than the noise of a minimum over
+            // kCgSamples chunks
+            if (m.us[gfirst][olast + 1] <= best / 0.99) {
                 m.graph = gfirst;
                 m.ov = olast;
             }
@@ -2924,7 +2941,7 @@ ddlr_status ddlr_tune(ddlr_prec* h, int32_t nrhs, int32_t retune, ddlr_tuning* o
         const ddlr_prec::CgMode& m = mi->second;
         out->cg_graph = m.graph;
         out->cg_overlap = m.ov >= 0 ? m.ov : -1;
-        const int o = m.ov >= -1 ? m.ov + 1 : 2;  // the chosen overlap, else "beside"
+        const int o = m.ov == -1 ? 0 : 2;  // "beside", or the only form when nothing overlaps
         auto val = [](double v) { return v < 1e29 ? (float)v : 0.0f; };
         out->cg_eager_us = val(m.us[0][o]);
         out->cg_graph_us = val(m.us[1][o]);
