@@ -601,6 +601,22 @@ template <typename IT> __device__ __forceinline__ int64_t sell_col(IT c, int64_t
     else return (int64_t)c;
 }
 
+// Loads entries j0 .. j0+7 of a lane's row in one slice without branches: an
+// entry beyond the slice's width repeats the last one with weight 0, and
+// adding 0 * x leaves a sum unchanged (a -0 sum may become +0), so every load
+// of the group is issued before the first use.
+template <typename VT, typename IT>
+__device__ __forceinline__ void sell_group8(const IT* __restrict__ col, const VT* __restrict__ val, int base, int lane,
+                                            int j0, int width, IT (&cg)[8], double (&ag)[8]) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const int q = base + min(j0 + u, width - 1) * kSell + lane;
+        cg[u] = col[q];
+        const double a = (double)val[q];
+        ag[u] = j0 + u < width ? a : 0.0;
+    }
+}
+
 template <typename VT, typename IT>
 __global__ __launch_bounds__(256) void k_spmv_sell(int64_t n, int nrhs, const int32_t* __restrict__ sptr,
                                                    const IT* __restrict__ col, const VT* __restrict__ val,
@@ -622,14 +638,25 @@ __global__ __launch_bounds__(256) void k_spmv_sell(int64_t n, int nrhs, const in
     if (row < n) {
         const int64_t sl = row >> 6;
         const int lane = (int)(row & 63);
-        const int base = sptr[sl], width = (sptr[sl + 1] - base) >> 6;
-        for (int j = 0; j < width; ++j) {
-            const int q = base + j * kSell + lane;
-            const int64_t c = sell_col<IT>(col[q], row);
-            const double a = (double)val[q];
+        const int base = sptr[sl], width = (sptr[sl + 1] - base) >> 6;  // uniform: a wave is one slice
+        for (int j0 = 0; j0 < width; j0 += 8) {
+            IT cg[8];
+            double ag[8];
+            sell_group8<VT, IT>(col, val, base, lane, j0, width, cg, ag);
+            int64_t c[8];
 #pragma unroll
-            for (int r = 0; r < kMaxRhs; ++r)
-                if (r < nrhs) acc[r] += a * x[c + r * ldx];
+            for (int u = 0; u < 8; ++u) c[u] = sell_col<IT>(cg[u], row);
+            // per column the group's 8 gathers go out together, then its terms in entry order
+#pragma unroll
+            for (int r = 0; r < kMaxRhs; ++r) {
+                if (r < nrhs) {
+                    double xv[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) xv[u] = x[c[u] + r * ldx];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) acc[r] += ag[u] * xv[u];
+                }
+            }
         }
 #pragma unroll
         for (int r = 0; r < kMaxRhs; ++r)
@@ -657,7 +684,8 @@ __global__ __launch_bounds__(256) void k_spmv_sell(int64_t n, int nrhs, const in
 // column-major x needs one cache line per right-hand side; with 8 columns of
 // 2M rows the column-major lines in flight overflow the L2 and are fetched
 // several times.  Per-row sums run over the slice entries in the same order
-// as k_spmv_sell, so both give bitwise the same y.
+// as k_spmv_sell, so both give the same y (k_spmv_sell's weight-0 group
+// padding can turn a -0 row sum into +0).
 template <int S, typename VT, typename IT>
 __global__ __launch_bounds__(256) void k_spmv_sell_il(int64_t n, int nrhs, const int32_t* __restrict__ sptr,
                                                       const IT* __restrict__ col,
