@@ -1029,6 +1029,28 @@ void wide_levels(ddlr_prec* h, const DevFactors<T>& F, int nrhs, const TIn* x, i
     }
 }
 
+// E / E^T / C products for 1..kMaxRhs columns: the power-of-two kernel that
+// covers nrhs, else the generic one
+template <typename T, typename TX>
+void csr_mv(int64_t rows, int nrhs, const int32_t* rp, const int32_t* ci, const T* v, const T* w, int64_t ldw,
+            const TX* x, int64_t ldx, T* y, int64_t ldy, hipStream_t st, const int* done) {
+    const dim3 g(grid_for(rows)), b(256);
+    if (nrhs <= 1)
+        hipLaunchKernelGGL((k_csr_mv_n<T, TX, 1>), g, b, 0, st, rows, nrhs, rp, ci, v, w, ldw, x, ldx, y, ldy, done);
+    else if (nrhs <= 2)
+        hipLaunchKernelGGL((k_csr_mv_n<T, TX, 2>), g, b, 0, st, rows, nrhs, rp, ci, v, w, ldw, x, ldx, y, ldy, done);
+    else if (nrhs <= 4)
+        hipLaunchKernelGGL((k_csr_mv_n<T, TX, 4>), g, b, 0, st, rows, nrhs, rp, ci, v, w, ldw, x, ldx, y, ldy, done);
+    else if (nrhs <= 8)
+        hipLaunchKernelGGL((k_csr_mv_n<T, TX, 8>), g, b, 0, st, rows, nrhs, rp, ci, v, w, ldw, x, ldx, y, ldy, done);
+    else if (nrhs <= kMaxRhs)
+        hipLaunchKernelGGL((k_csr_mv_n<T, TX, kMaxRhs>), g, b, 0, st, rows, nrhs, rp, ci, v, w, ldw, x, ldx, y, ldy,
+                           done);
+    else
+        hipLaunchKernelGGL((k_csr_mv<T, TX>), g, b, 0, st, rows, nrhs, rp, ci, v, w, ldw, x, ldx, y, ldy, done);
+    LAUNCHCHK();
+}
+
 // z = A0^{-1} x, device order (x may equal z when TIn == TOut)
 // the interface block is solved apart from the B blocks (level launches or X)
 bool has_cpart(const ddlr_prec* h) { return !h->wide.empty() || h->xrp != nullptr; }
@@ -1058,9 +1080,7 @@ void cheb_dev(ddlr_prec* h, const DevFactors<T>& F, int nrhs, const TIn* x, int6
         LAUNCHCHK();
         double rho = 1.0 / sg;
         for (int k = 1; k < h->cheb_nu; ++k) {
-            hipLaunchKernelGGL((k_csr_mv<T, T>), dim3(grid_for(s)), dim3(256), 0, st, s, nr, h->crp, h->cci, F.cneg,
-                               d + m, n, r + m, n, r + m, n, done);  // r -= C d
-            LAUNCHCHK();
+            csr_mv<T, T>(s, nr, h->crp, h->cci, F.cneg, d + m, n, r + m, n, r + m, n, st, done);  // r -= C d
             const double rn = 1.0 / (2.0 * sg - rho);
             wide_levels<T, T, T>(h, F, nr, r, n, t, n, st, done);  // t = D^{-1} r
             hipLaunchKernelGGL((k_cheb_step<T>), g, dim3(256), 0, st, s, (T)(rn * rho), (T)(2.0 * rn / de), t + m,
@@ -1189,9 +1209,8 @@ void apply_dev_T(ddlr_prec* h, int nrhs, const double* in, int64_t ldin, double*
         T* ys = (T*)W.ys;
         T* wsv = (T*)W.ws;
         a0_solve_dev<T, double, T>(h, F, nrhs, in, ldin, a1, n, st, done);  // step 1: A0 z = x
-        hipLaunchKernelGGL((k_csr_mv<T, T>), dim3(grid_for(s)), dim3(256), 0, st, s, nrhs, h->etrp, h->etci,
-                           F.etv, a1, n, (const T*)nullptr, 0, ys, s, done);  // step 2: y = E^T z
-        LAUNCHCHK();
+        csr_mv<T, T>(s, nrhs, h->etrp, h->etci, F.etv, a1, n, (const T*)nullptr, 0, ys, s, st,
+                     done);  // step 2: y = E^T z
         if (h->nsys > 1) {  // per system of a batch (one column)
             ProfScope ps(h, 3, st);
             hipLaunchKernelGGL(k_seg_lr_coef<T>, dim3(h->nsys), dim3(256), 0, st, h->seg_soff, h->k, F.U, ys, h->dvecs,
@@ -1204,9 +1223,8 @@ void apply_dev_T(ddlr_prec* h, int nrhs, const double* in, int64_t ldin, double*
             lr_coef<T, T>(h, F.U, s, nrhs, ys, s, 1, st, done);  // step 3: w = G_{k,theta}^{-1} y (eq. gkt)
             lr_expand<T, T>(h, F.U, s, nrhs, h->c0, ys, s, wsv, s, st, done);
         }
-        hipLaunchKernelGGL((k_csr_mv<T, double>), dim3(grid_for(n)), dim3(256), 0, st, n, nrhs, h->erp, h->eci,
-                           F.ev, wsv, s, in, ldin, a2, n, done);  // step 4: v = E w, fused x + v
-        LAUNCHCHK();
+        csr_mv<T, double>(n, nrhs, h->erp, h->eci, F.ev, wsv, s, in, ldin, a2, n, st,
+                          done);  // step 4: v = E w, fused x + v
         a0_solve_dev<T, T, double>(h, F, nrhs, a2, n, out, ldout, st, done);  // step 5: A0 u = x + v
     } else if (h->variant == DDLR_2) {
         a0_solve_dev<T, double, double>(h, F, nrhs, in, ldin, out, ldout, st, done);

@@ -786,6 +786,39 @@ __global__ __launch_bounds__(256) void k_csr_mv(int64_t rows, int nrhs, const in
     }
 }
 
+// The same product for nrhs <= NR <= kMaxRhs columns (NR a power of two):
+// column indices past nrhs are clamped to the last column, so every load of a
+// row is issued before the first use (no branch per column; the surplus
+// sums are not stored).  Per column the terms and their order are those of
+// k_csr_mv, so both give bitwise the same y.
+template <typename T, typename TX, int NR>
+__global__ __launch_bounds__(256) void k_csr_mv_n(int64_t rows, int nrhs, const int32_t* __restrict__ rp,
+                                                  const int32_t* __restrict__ ci, const T* __restrict__ v,
+                                                  const T* __restrict__ w, int64_t ldw, const TX* x, int64_t ldx,
+                                                  T* y, int64_t ldy, const int* __restrict__ done) {
+    if (done && *done) return;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < rows; i += (int64_t)gridDim.x * blockDim.x) {
+        const int t0 = rp[i], t1 = rp[i + 1];
+        T s[NR];
+        if (x) {  // one uniform branch around all the loads, so they are issued together
+#pragma unroll
+            for (int r = 0; r < NR; ++r) s[r] = (T)x[i + (int64_t)min(r, nrhs - 1) * ldx];
+        } else {
+#pragma unroll
+            for (int r = 0; r < NR; ++r) s[r] = T(0);
+        }
+        for (int t = t0; t < t1; ++t) {
+            const int c = ci[t];
+            const T vt = v[t];
+#pragma unroll
+            for (int r = 0; r < NR; ++r) s[r] += vt * w[c + (int64_t)min(r, nrhs - 1) * ldw];
+        }
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+            if (r < nrhs) y[i + (int64_t)r * ldy] = s[r];
+    }
+}
+
 // z_C = X x_C: the C_alpha solve by its approximate inverse (Sec. 4.4,
 // Algorithm alg:mr).  X is stored in SELL-64 over the interface rows: rows
 // sorted by entry count (longest first) and cut into slices of 64, entries
