@@ -982,6 +982,28 @@ template <typename T> int ring_nt_for(const ddlr_prec* h, int nrhs) {
     return ring_nt_ok(h, nt) ? nt : 512;
 }
 
+// k_trsv_level_rows for 1..kMaxRhs columns: the power-of-two width that covers nrhs
+template <typename T, int kKind, typename TIn, typename TOut>
+void launch_level_rows(int a, int e, int nrhs, const int32_t* rp, const int32_t* ci, const T* v, const T* dinv,
+                       const TIn* x, int64_t ldx, TOut* z, int64_t ldz, hipStream_t st, const int* done) {
+    const dim3 g((e - a + 255) / 256), b(256);
+    if (nrhs <= 1)
+        hipLaunchKernelGGL((k_trsv_level_rows<T, kKind, TIn, TOut, 1>), g, b, 0, st, a, e, nrhs, rp, ci, v, dinv, x,
+                           ldx, z, ldz, done);
+    else if (nrhs <= 2)
+        hipLaunchKernelGGL((k_trsv_level_rows<T, kKind, TIn, TOut, 2>), g, b, 0, st, a, e, nrhs, rp, ci, v, dinv, x,
+                           ldx, z, ldz, done);
+    else if (nrhs <= 4)
+        hipLaunchKernelGGL((k_trsv_level_rows<T, kKind, TIn, TOut, 4>), g, b, 0, st, a, e, nrhs, rp, ci, v, dinv, x,
+                           ldx, z, ldz, done);
+    else if (nrhs <= 8)
+        hipLaunchKernelGGL((k_trsv_level_rows<T, kKind, TIn, TOut, 8>), g, b, 0, st, a, e, nrhs, rp, ci, v, dinv, x,
+                           ldx, z, ldz, done);
+    else
+        hipLaunchKernelGGL((k_trsv_level_rows<T, kKind, TIn, TOut, kMaxRhs>), g, b, 0, st, a, e, nrhs, rp, ci, v,
+                           dinv, x, ldx, z, ldz, done);
+}
+
 // Interface-block levels (multicolour order): forward levels, the last one
 // fused with the diagonal scaling, then backward levels.
 template <typename T, typename TIn, typename TOut>
@@ -999,13 +1021,10 @@ void wide_levels(ddlr_prec* h, const DevFactors<T>& F, int nrhs, const TIn* x, i
         const int a = h->wide[l].first, e = h->wide[l].second;
         const bool last = l + 1 == nl;
         if (by_rows(a, e)) {
-            const dim3 g((e - a + 255) / 256);
             if (!last)
-                hipLaunchKernelGGL((k_trsv_level_rows<T, 0, TIn, TOut>), g, dim3(256), 0, st, a, e, nrhs, h->lrp,
-                                   h->lci, F.lv, F.dinv, x, ldx, z, ldz, done);
+                launch_level_rows<T, 0, TIn, TOut>(a, e, nrhs, h->lrp, h->lci, F.lv, F.dinv, x, ldx, z, ldz, st, done);
             else
-                hipLaunchKernelGGL((k_trsv_level_rows<T, 2, TIn, TOut>), g, dim3(256), 0, st, a, e, nrhs, h->lrp,
-                                   h->lci, F.lv, F.dinv, x, ldx, z, ldz, done);
+                launch_level_rows<T, 2, TIn, TOut>(a, e, nrhs, h->lrp, h->lci, F.lv, F.dinv, x, ldx, z, ldz, st, done);
         } else {
             const dim3 g((e - a + 255) / 256, nrhs);
             if (!last)
@@ -1020,8 +1039,7 @@ void wide_levels(ddlr_prec* h, const DevFactors<T>& F, int nrhs, const TIn* x, i
     for (int l = nl - 2; l >= 0; --l) {
         const int a = h->wide[l].first, e = h->wide[l].second;
         if (by_rows(a, e))
-            hipLaunchKernelGGL((k_trsv_level_rows<T, 1, TIn, TOut>), dim3((e - a + 255) / 256), dim3(256), 0, st, a, e,
-                               nrhs, h->urp, h->uci, F.uv, F.dinv, x, ldx, z, ldz, done);
+            launch_level_rows<T, 1, TIn, TOut>(a, e, nrhs, h->urp, h->uci, F.uv, F.dinv, x, ldx, z, ldz, st, done);
         else
             hipLaunchKernelGGL((k_trsv_level<T, 1, TIn, TOut>), dim3((e - a + 255) / 256, nrhs), dim3(256), 0, st, a, e,
                                nrhs, h->urp, h->uci, F.uv, F.dinv, x, ldx, z, ldz, done);

@@ -552,10 +552,13 @@ __global__ __launch_bounds__(256) void k_trsv_level(int a, int e, int nrhs, cons
     zr[i] = (TOut)s;
 }
 
-// The same level with one thread per row for all nrhs <= kMaxRhs columns: the
-// row's entries are loaded once instead of once per column; per column the
-// arithmetic is k_trsv_level's (same terms, same order).
-template <typename T, int kKind, typename TIn, typename TOut>
+// The same level with one thread per row for nrhs <= NR <= kMaxRhs columns
+// (NR a power of two): the row's entries are loaded once instead of once per
+// column, and column indices past nrhs are clamped to the last column, so all
+// loads of a row go out together (no branch per column; the surplus sums are
+// not stored).  Per column the arithmetic is k_trsv_level's (same terms, same
+// order).
+template <typename T, int kKind, typename TIn, typename TOut, int NR>
 __global__ __launch_bounds__(256) void k_trsv_level_rows(int a, int e, int nrhs, const int32_t* __restrict__ rp,
                                                          const int32_t* __restrict__ ci, const T* __restrict__ v,
                                                          const T* __restrict__ dinv, const TIn* x, int64_t ldx,
@@ -563,24 +566,25 @@ __global__ __launch_bounds__(256) void k_trsv_level_rows(int a, int e, int nrhs,
     if (done && *done) return;
     const int i = a + (int)(blockIdx.x * blockDim.x + threadIdx.x);
     if (i >= e) return;
-    T s[kMaxRhs];
+    T s[NR];
     const T di = dinv[i];
 #pragma unroll
-    for (int r = 0; r < kMaxRhs; ++r)
-        if (r < nrhs) s[r] = kKind == 1 ? (T)z[i + r * ldz] * di : (T)x[i + r * ldx];
+    for (int r = 0; r < NR; ++r) {
+        const int64_t rc = min(r, nrhs - 1);
+        s[r] = kKind == 1 ? (T)z[i + rc * ldz] * di : (T)x[i + rc * ldx];
+    }
     const int t1 = rp[i + 1];
     for (int t = rp[i]; t < t1; ++t) {
         const int c = ci[t];
         const T vt = v[t];
 #pragma unroll
-        for (int r = 0; r < kMaxRhs; ++r)
-            if (r < nrhs) s[r] = fnms(s[r], vt, (T)z[c + r * ldz]);
+        for (int r = 0; r < NR; ++r) s[r] = fnms(s[r], vt, (T)z[c + (int64_t)min(r, nrhs - 1) * ldz]);
     }
 #pragma unroll
-    for (int r = 0; r < kMaxRhs; ++r) {
+    for (int r = 0; r < NR; ++r) {
         if (r < nrhs) {
             if (kKind == 2) s[r] *= di;
-            z[i + r * ldz] = (TOut)s[r];
+            z[i + (int64_t)r * ldz] = (TOut)s[r];
         }
     }
 }
