@@ -749,10 +749,25 @@ __global__ __launch_bounds__(256) void k_spmv_sell_il(int64_t n, int nrhs, const
     }
     if (part) {
         const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+        double xr[S];  // the row's own segment, loaded at once
+#pragma unroll
+        for (int r = 0; r < S; ++r) xr[r] = 0.0;
+        if (row < n) {
+            if constexpr (S == 1) {
+                xr[0] = x[row];
+            } else {
+#pragma unroll
+                for (int r = 0; r < S; r += 2) {
+                    const double2 t = *reinterpret_cast<const double2*>(x + row * S + r);
+                    xr[r] = t.x;
+                    xr[r + 1] = t.y;
+                }
+            }
+        }
 #pragma unroll
         for (int r = 0; r < S; ++r) {
             if (r < nrhs) {
-                double v = row < n ? acc[r] * x[row * S + r] : 0.0;
+                double v = acc[r] * xr[r];
                 v = wave_sum(v);
                 if (lane == 0) sh[w * S + r] = v;
             }
