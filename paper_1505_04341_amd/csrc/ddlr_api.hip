@@ -1160,6 +1160,21 @@ void a0_solve_dev(ddlr_prec* h, const DevFactors<T>& F, int nrhs, const TIn* x, 
 
 // ------------------------------------------------------------ low-rank part
 
+// Calls f(std::integral_constant<int, t>) for t = ntiles in 1..8 (16-column
+// tiles of U_k), so the low-rank kernels get the tile count at compile time.
+template <typename F> void with_tiles(int ntiles, F&& f) {
+    switch (ntiles) {
+    case 1: f(std::integral_constant<int, 1>{}); break;
+    case 2: f(std::integral_constant<int, 2>{}); break;
+    case 3: f(std::integral_constant<int, 3>{}); break;
+    case 4: f(std::integral_constant<int, 4>{}); break;
+    case 5: f(std::integral_constant<int, 5>{}); break;
+    case 6: f(std::integral_constant<int, 6>{}); break;
+    case 7: f(std::integral_constant<int, 7>{}); break;
+    default: f(std::integral_constant<int, 8>{});
+    }
+}
+
 // coef = d .* (U^T y) (mode 1) or H (U^T y) (mode 2)
 template <typename T, typename TY>
 void lr_coef(ddlr_prec* h, const T* U, int64_t rows, int nrhs, const TY* y, int64_t ldy, int mode, hipStream_t st,
@@ -1174,8 +1189,10 @@ void lr_coef(ddlr_prec* h, const T* U, int64_t rows, int nrhs, const TY* y, int6
         hipLaunchKernelGGL((k_lr_reduce<T, TY>), dim3(kLrBlocks), dim3(256), 0, st, rows, k, nrhs, U, y, ldy, W.part,
                            done);
     else if (factors<T>(h).Ut && factors<T>(h).U == U)
-        hipLaunchKernelGGL((k_lr_reduce_t<T, TY>), dim3(kLrBlocks), dim3(256), 0, st, rows, k, nrhs,
-                           factors<T>(h).Ut, y, ldy, W.part, done);
+        with_tiles(k >> 4, [&](auto nt) {
+            hipLaunchKernelGGL((k_lr_reduce_t<T, TY, decltype(nt)::value>), dim3(kLrBlocks), dim3(256), 0, st, rows,
+                               k, nrhs, factors<T>(h).Ut, y, ldy, W.part, done);
+        });
     else
         hipLaunchKernelGGL((k_lr_reduce_mfma<T, TY>), dim3(kLrBlocks), dim3(256), 0, st, rows, k, nrhs, U, y, ldy,
                            W.part, done);
@@ -1198,10 +1215,12 @@ void lr_expand(ddlr_prec* h, const T* U, int64_t rows, int nrhs, double beta, co
     } else if (h->lr_plain) {
         hipLaunchKernelGGL((k_lr_expand<T, TIO>), dim3(grid_for(rows)), dim3(256), 0, st, rows, h->k, nrhs, U,
                            h->ws.coef, beta, in, ldin, out, ldout, done);
-    } else if (h->k % 16 == 0 && h->k <= 128) {
+    } else if (h->k >= 16 && h->k % 16 == 0 && h->k <= 128) {
         const int64_t tiles = (rows + 15) / 16;
-        hipLaunchKernelGGL((k_lr_expand_v<T, TIO>), dim3(grid_for(tiles, 4)), dim3(256), 0, st, rows, h->k, nrhs,
-                           U, h->ws.coef, beta, in, ldin, out, ldout, done);
+        with_tiles(h->k >> 4, [&](auto nt) {
+            hipLaunchKernelGGL((k_lr_expand_v<T, TIO, decltype(nt)::value>), dim3(grid_for(tiles, 4)), dim3(256), 0,
+                               st, rows, h->k, nrhs, U, h->ws.coef, beta, in, ldin, out, ldout, done);
+        });
     } else {
         const int64_t tiles = (rows + 15) / 16;
         hipLaunchKernelGGL((k_lr_expand_mfma<T, TIO>), dim3(grid_for(tiles, 4)), dim3(256), 0, st, rows, h->k, nrhs,

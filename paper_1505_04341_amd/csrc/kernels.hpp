@@ -708,9 +708,9 @@ __global__ __launch_bounds__(256) void k_spmv_sell_il(int64_t n, int nrhs, const
         const int64_t sl = row >> 6;
         const int lane = (int)(row & 63);
         const int base = sptr[sl], width = (sptr[sl + 1] - base) >> 6;  // uniform: a wave is one slice
-        // entries in groups of 8: the group's column and value loads go out
-        // together, then its gathers, instead of one column -> gather round
-        // trip per entry
+        // entries in groups of 8, each guarded by the slice's width (the
+        // compiler still waits for each guarded load; the unguarded grouping
+        // of k_spmv_sell was slower here on wide irregular slices)
         for (int j0 = 0; j0 < width; j0 += 8) {
             int64_t cg[8];
             double ag[8];
@@ -1149,7 +1149,7 @@ __global__ void k_make_ut(int64_t rows, int k, const T* __restrict__ U, T* __res
 
 template <typename T> struct Vec4 { typedef T __attribute__((ext_vector_type(4))) type; };
 
-template <typename T, typename TY = T>
+template <typename T, typename TY, int NJT>
 __global__ __launch_bounds__(256) void k_lr_reduce_t(int64_t rows, int k, int nrhs, const T* __restrict__ Ut,
                                                      const TY* __restrict__ y, int64_t ldy, double* __restrict__ part,
                                                      const int* __restrict__ done) {
@@ -1163,11 +1163,13 @@ __global__ __launch_bounds__(256) void k_lr_reduce_t(int64_t rows, int k, int nr
     const int64_t nrt = (rows + 15) >> 4;
     const int64_t per = (nrt + nwaves - 1) / nwaves;
     const int64_t t0 = gw * per, t1 = t0 + per < nrt ? t0 + per : nrt;
-    const int njt = k >> 4;  // <= 8
-    acc_t acc[8];
+    // NJT = k / 16 column tiles (a template parameter, so no load sits in a
+    // per-tile branch); y is read at clamped indices and zeroed by selection
+    acc_t acc[NJT];
 #pragma unroll
-    for (int t = 0; t < 8; ++t) acc[t] = acc_t{0, 0, 0, 0};
+    for (int t = 0; t < NJT; ++t) acc[t] = acc_t{0, 0, 0, 0};
     const int n = lane & 15, q = lane >> 4;
+    const int nc = min(n, nrhs - 1);
     const v4* Ut4 = reinterpret_cast<const v4*>(Ut);
 #pragma unroll 2
     for (int64_t rt = t0; rt < t1; ++rt) {
@@ -1175,18 +1177,18 @@ __global__ __launch_bounds__(256) void k_lr_reduce_t(int64_t rows, int k, int nr
 #pragma unroll
         for (int st = 0; st < 4; ++st) {
             const int64_t row = 16 * rt + 4 * q + st;
-            b[st] = (row < rows && n < nrhs) ? (T)y[row + n * ldy] : T(0);
+            const T yv = (T)y[(row < rows ? row : rows - 1) + nc * ldy];
+            b[st] = (row < rows && n < nrhs) ? yv : T(0);
         }
 #pragma unroll
-        for (int jt = 0; jt < 8; ++jt)
-            if (jt < njt) {
-                const v4 a = Ut4[(rt * njt + jt) * 64 + lane];
+        for (int jt = 0; jt < NJT; ++jt) {
+            const v4 a = Ut4[(rt * NJT + jt) * 64 + lane];
 #pragma unroll
-                for (int st = 0; st < 4; ++st) acc[jt] = MfmaAcc<T>::step(a[st], b[st], acc[jt]);
-            }
+            for (int st = 0; st < 4; ++st) acc[jt] = MfmaAcc<T>::step(a[st], b[st], acc[jt]);
+        }
     }
     // acc[t] holds C[j = 16t + row(lane, v)][rhs = lane%16]; fold the 4 waves through LDS
-    for (int t = 0; t < njt; ++t) {
+    for (int t = 0; t < NJT; ++t) {
         for (int v = 0; v < 4; ++v) {
             stage[wv][lane] = (double)acc[t][v];
             __syncthreads();
@@ -1204,7 +1206,7 @@ __global__ __launch_bounds__(256) void k_lr_reduce_t(int64_t rows, int k, int nr
 // 16c + 4q + 3] in one go and uses element s at K step s, whose K index q
 // stands for column j = 16c + 4q + s; the coefficient operand follows the
 // same j.  M = 16 rows, N = nrhs (<= 16).
-template <typename T, typename TIO = T>
+template <typename T, typename TIO, int NC>
 __global__ __launch_bounds__(256) void k_lr_expand_v(int64_t rows, int k, int nrhs, const T* __restrict__ U,
                                                      const double* __restrict__ coef, double beta, const TIO* in,
                                                      int64_t ldin, TIO* out, int64_t ldout,
@@ -1220,26 +1222,33 @@ __global__ __launch_bounds__(256) void k_lr_expand_v(int64_t rows, int k, int nr
     __syncthreads();
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int m = lane & 15, q = lane >> 4;
-    const int nc = k >> 4;
     const int64_t ntiles = (rows + 15) >> 4;
+    // NC = k / 16 column chunks (a template parameter, so no load sits in a
+    // per-chunk branch); the input is read at clamped indices before the stores
     for (int64_t tile = (int64_t)blockIdx.x * 4 + wv; tile < ntiles; tile += (int64_t)gridDim.x * 4) {
         const int64_t i = tile * 16 + m;
         const int64_t ic = i < rows ? i : rows - 1;  // clamped row: loaded, never stored
         acc_t acc = acc_t{0, 0, 0, 0};
+        v4 a[NC];
 #pragma unroll
-        for (int c = 0; c < 8; ++c)
-            if (c < nc) {
-                const v4 a = *reinterpret_cast<const v4*>(U + ic * k + 16 * c + 4 * q);
+        for (int c = 0; c < NC; ++c) a[c] = *reinterpret_cast<const v4*>(U + ic * k + 16 * c + 4 * q);
 #pragma unroll
-                for (int st = 0; st < 4; ++st)
-                    acc = MfmaAcc<T>::step(a[st], cf[(16 * c + 4 * q + st) * 16 + m], acc);
-            }
-        const int rr = lane & 15;
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+            for (int st = 0; st < 4; ++st)
+                acc = MfmaAcc<T>::step(a[c][st], cf[(16 * c + 4 * q + st) * 16 + m], acc);
+        const int rr = lane & 15, rc = min(rr, nrhs - 1);
+        double iv[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int64_t row = tile * 16 + MfmaAcc<T>::row(lane, v);
+            iv[v] = (double)in[(row < rows ? row : rows - 1) + rc * ldin];
+        }
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int64_t row = tile * 16 + MfmaAcc<T>::row(lane, v);
             if (row < rows && rr < nrhs) {
-                const double o = beta * (double)in[row + rr * ldin] + (double)acc[v];
+                const double o = beta * iv[v] + (double)acc[v];
                 out[row + rr * ldout] = (TIO)o;
             }
         }
