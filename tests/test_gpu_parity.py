@@ -102,6 +102,40 @@ def test_a0_solve_and_spmv(name, wide, kernel):
         assert rel(to_host(y), ref) <= 1e-14
 
 
+@pytest.mark.parametrize("name", ["small3d", "irregular"])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_columns_independent_of_batch_width(name, prec):
+    """A column's A0 solve is bitwise the same whether it is solved alone or
+    with 1..16 others (interface levels and E products come in column widths
+    1, 2, 4, 8 and 16 with clamped surplus columns), and its full DDLR-1
+    apply agrees to rounding; both match the oracle."""
+    cfg = CASES[name]()
+    say("column widths", name, prec)
+    h, o = setup_pair(cfg, variant=1, wide=True, precision=[D.FP64, D.FP32][prec])
+    n = cfg["A"].n
+    x = np.random.default_rng(17).standard_normal((n, 16))
+    alone_a0, alone_ap = [], []
+    for j in range(16):
+        y = torch.empty((1, n), dtype=torch.float64, device=DEV)
+        D.ddlr_a0_solve(h, to_dev(x[:, j:j + 1]), y)
+        alone_a0.append(y.cpu())
+        D.ddlr_apply(h, to_dev(x[:, j:j + 1]), y)
+        alone_ap.append(y.cpu())
+    tol = 1e-13 if prec == 0 else 1e-6
+    for w in (2, 3, 5, 8, 11, 16):
+        y = torch.empty((w, n), dtype=torch.float64, device=DEV)
+        D.ddlr_a0_solve(h, to_dev(x[:, :w]), y)
+        got = y.cpu()
+        for j in range(w):
+            assert torch.equal(got[j:j + 1], alone_a0[j]), (w, j)
+        D.ddlr_apply(h, to_dev(x[:, :w]), y)
+        got = y.cpu().numpy()
+        for j in range(w):
+            assert rel(got[j], alone_ap[j].numpy()[0]) <= tol, (w, j)
+    ref = o.a0_solve(x[:, :3])
+    assert rel(torch.cat(alone_a0[:3]).numpy().T, ref) <= (1e-12 if prec == 0 else 1e-5)
+
+
 @pytest.mark.parametrize("name", ["c1", "small2d", "irregular"])
 @pytest.mark.parametrize("variant", [1, 2])
 @pytest.mark.parametrize("lr", ["mfma", "plain"])
