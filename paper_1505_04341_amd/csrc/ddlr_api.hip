@@ -2440,7 +2440,15 @@ static void lane_iteration(ddlr_prec* h, int nr, hipStream_t st) {
     LAUNCHCHK();
     if (split) HIPCHK(hipStreamWaitEvent(st, h->ev_xj, 0));  // x used the old p
     const int S = lane_stride(nr);
-    hipLaunchKernelGGL(k_cg_p, dim3(grid_for(n * S)), dim3(256), 0, st, n, nr, ilog2(S), W.lanes, W.z, W.p, n, W.done);
+    const dim3 gp(grid_for(n)), bp(256);
+    switch (S) {
+    case 1: hipLaunchKernelGGL(k_cg_p<1>, gp, bp, 0, st, n, nr, W.lanes, W.z, W.p, n, W.done); break;
+    case 2: hipLaunchKernelGGL(k_cg_p<2>, gp, bp, 0, st, n, nr, W.lanes, W.z, W.p, n, W.done); break;
+    case 4: hipLaunchKernelGGL(k_cg_p<4>, gp, bp, 0, st, n, nr, W.lanes, W.z, W.p, n, W.done); break;
+    case 8: hipLaunchKernelGGL(k_cg_p<8>, gp, bp, 0, st, n, nr, W.lanes, W.z, W.p, n, W.done); break;
+    case 16: hipLaunchKernelGGL(k_cg_p<16>, gp, bp, 0, st, n, nr, W.lanes, W.z, W.p, n, W.done); break;
+    default: throw SetupError{DDLR_E_INVALID, "CG runs at most 16 lanes per launch"};
+    }
     LAUNCHCHK();
 }
 

@@ -1675,17 +1675,47 @@ __global__ __launch_bounds__(256) void k_cg_x(int64_t n, int nrhs, const double*
     }
 }
 
-// p = z + beta p (active lanes); z column-major (ld), p interleaved (stride
-// S = 2^lgS)
-__global__ __launch_bounds__(256) void k_cg_p(int64_t n, int nrhs, int lgS, const CgLane* __restrict__ L,
+// p = z + beta p (active lanes); z column-major (ld), p interleaved with
+// stride S.  One thread per row: a wave reads and writes 64 whole p segments
+// (contiguous) and 64 consecutive rows of each z column; z is read at clamped
+// column indices so every load of a row goes out before the first use.  An
+// inactive lane's p values are written back unchanged.
+template <int S>
+__global__ __launch_bounds__(256) void k_cg_p(int64_t n, int nrhs, const CgLane* __restrict__ L,
                                               const double* __restrict__ z, double* __restrict__ p, int64_t ld,
                                               const int* __restrict__ done) {
     if (done && *done) return;
-    const int64_t total = n << lgS;
-    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t i = g >> lgS;
-        const int c = (int)(g & ((1 << lgS) - 1));
-        if (c < nrhs && L[c].active) p[g] = z[i + c * ld] + L[c].beta * p[g];
+    bool act[S];
+    double bt[S];
+#pragma unroll
+    for (int c = 0; c < S; ++c) {
+        act[c] = c < nrhs && L[c].active;
+        bt[c] = act[c] ? L[c].beta : 0.0;
+    }
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double pv[S], zv[S];
+        if constexpr (S == 1) {
+            pv[0] = p[i];
+        } else {
+#pragma unroll
+            for (int c = 0; c < S; c += 2) {
+                const double2 t = *reinterpret_cast<const double2*>(p + i * S + c);
+                pv[c] = t.x;
+                pv[c + 1] = t.y;
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < S; ++c) zv[c] = z[i + (int64_t)min(c, nrhs - 1) * ld];
+#pragma unroll
+        for (int c = 0; c < S; ++c)
+            if (act[c]) pv[c] = zv[c] + bt[c] * pv[c];
+        if constexpr (S == 1) {
+            p[i] = pv[0];
+        } else {
+#pragma unroll
+            for (int c = 0; c < S; c += 2)
+                *reinterpret_cast<double2*>(p + i * S + c) = double2{pv[c], pv[c + 1]};
+        }
     }
 }
 
