@@ -969,15 +969,30 @@ __global__ void k_lr_coef(int k, int nrhs, const double* __restrict__ c, int mod
     }
 }
 
+// Sum of part[b * stride + col] over b = threadIdx.x, threadIdx.x + blockDim.x,
+// ... < nparts, in that order; groups of 8 loads are issued before their adds.
+__device__ __forceinline__ double strided_sum(const double* __restrict__ part, int nparts, int stride, int col) {
+    double acc = 0.0;
+    const int step = blockDim.x;
+    int b = threadIdx.x;
+    for (; b + 7 * step < nparts; b += 8 * step) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(b + u * step) * stride + col];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += v[u];
+    }
+    for (; b < nparts; b += step) acc += part[(int64_t)b * stride + col];
+    return acc;
+}
+
 // out[col] = sum over parts of part[b*ncols + col], one workgroup per column, fixed order
 __global__ __launch_bounds__(256) void k_reduce_cols(int nparts, int ncols, const double* __restrict__ part,
                                                      double* __restrict__ out, const int* __restrict__ done) {
     __shared__ double sh[4];
     if (done && *done) return;
     const int col = blockIdx.x;
-    double acc = 0.0;
-    for (int b = threadIdx.x; b < nparts; b += blockDim.x) acc += part[(int64_t)b * ncols + col];
-    const double s = block_sum256(acc, sh);
+    const double s = block_sum256(strided_sum(part, nparts, ncols, col), sh);
     if (threadIdx.x == 0) out[col] = s;
 }
 
@@ -1483,9 +1498,7 @@ __global__ __launch_bounds__(256) void k_reduce_lane(int what, int nparts, int n
     __shared__ int is_last;
     if (*done) return;
     const int col = blockIdx.x;
-    double acc = 0.0;
-    for (int b = threadIdx.x; b < nparts; b += blockDim.x) acc += part[(int64_t)b * nlanes + col];
-    const double s = block_sum256(acc, sh);
+    const double s = block_sum256(strided_sum(part, nparts, nlanes, col), sh);
     if (threadIdx.x == 0) {
         sums[col] = s;
         lane_update(what, L[col], s);
