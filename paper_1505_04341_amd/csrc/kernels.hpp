@@ -1904,10 +1904,14 @@ __global__ __launch_bounds__(256) void k_gm_dots(int64_t n, int nrhs, int ncols,
     for (int g = 0; g < kGmGroup; ++g) acc[g] = 0.0;
     const double* wr = w + (int64_t)r * n;
     for (int64_t i = (int64_t)chunk * blockDim.x + threadIdx.x; i < n; i += (int64_t)nchunk * blockDim.x) {
+        // all of the row's loads first (basis indices past the group clamped,
+        // their sums unused), then the adds in basis order
         const double wi = wr[i];
+        double vv[kGmGroup];
 #pragma unroll
-        for (int g = 0; g < kGmGroup; ++g)
-            if (g < ng) acc[g] += V[((int64_t)(l0 + g) * nrhs + r) * n + i] * wi;
+        for (int g = 0; g < kGmGroup; ++g) vv[g] = V[((int64_t)(l0 + min(g, ng - 1)) * nrhs + r) * n + i];
+#pragma unroll
+        for (int g = 0; g < kGmGroup; ++g) acc[g] += vv[g] * wi;
     }
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
