@@ -546,8 +546,26 @@ __global__ __launch_bounds__(256) void k_trsv_level(int a, int e, int nrhs, cons
     if (i >= e) return;
     TOut* zr = z + r * ldz;
     T s = kKind == 1 ? (T)zr[i] * dinv[i] : (T)x[i + r * ldx];
-    const int t1 = rp[i + 1];
-    for (int t = rp[i]; t < t1; ++t) s = fnms(s, v[t], (T)zr[ci[t]]);
+    const int t0 = rp[i], t1 = rp[i + 1];
+    // entries in groups of 4 with unconditional loads: an index past the row's
+    // end repeats its last entry with weight 0 (s - 0 z leaves s unchanged up
+    // to the sign of a zero), so a group's index, value and gather loads go out
+    // together; the terms keep their order
+    for (int t = t0; t < t1; t += 4) {
+        int c[4];
+        T w[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int q = min(t + u, t1 - 1);
+            c[u] = ci[q];
+            w[u] = t + u < t1 ? v[q] : T(0);
+        }
+        T g[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) g[u] = (T)zr[c[u]];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) s = fnms(s, w[u], g[u]);
+    }
     if (kKind == 2) s *= dinv[i];
     zr[i] = (TOut)s;
 }
