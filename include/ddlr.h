@@ -8,7 +8,7 @@
  * split), A0 = blockdiag(B_i + alpha^{-2} E_i E_i^T, C + alpha^2 I), and the
  * inverse is approximated through the Sherman-Morrison-Woodbury formula with a
  * rank-k correction computed by Lanczos (Sec. 3.2 DDLR-1, Sec. 3.3 DDLR-2,
- * Sec. 4.3 Lanczos).  The preconditioner is applied inside CG or GMRES
+ * Sec. 4.4 (sec:Lan) Lanczos).  The preconditioner is applied inside CG or GMRES
  * (Sec. 5).
  *
  * Conventions for every call:
@@ -58,7 +58,7 @@ typedef enum {
 typedef enum { DDLR_THETA_LAMBDA_K1 = 0, DDLR_THETA_ZERO = 1 } ddlr_theta;
 typedef enum { DDLR_FACTOR_IC0 = 0, DDLR_FACTOR_ILDL0 = 1 } ddlr_factor;
 typedef enum { DDLR_CORDER_MULTICOLOR = 0, DDLR_CORDER_NATURAL = 1 } ddlr_corder;
-/* Solver of C_alpha inside every A0 solve (Sec. 4.4): its incomplete LDL^T
+/* Solver of C_alpha inside every A0 solve (Sec. 4.3 (sec:csolve)): its incomplete LDL^T
  * like the B blocks, or the sparse approximate inverse X of Algorithm alg:mr
  * (self-preconditioned global MR with dropping, X_0 = diag(C_alpha)^{-1}),
  * applied as one sparse product.  X's dropping rule (the paper gives no
@@ -80,7 +80,7 @@ typedef enum { DDLR_CORDER_MULTICOLOR = 0, DDLR_CORDER_NATURAL = 1 } ddlr_corder
  * the smallest Ritz value).  The polynomial solve is symmetric; it counts as
  * SPD when D_alpha's pivots and the smallest Ritz value are positive. */
 typedef enum { DDLR_CSOLVE_FACTOR = 0, DDLR_CSOLVE_MR = 1, DDLR_CSOLVE_CHEB = 2 } ddlr_csolve;
-/* How DDLR-2's U_k and V_k are computed (Sec. 4.3): Lanczos on
+/* How DDLR-2's U_k and V_k are computed (Sec. 4.4 (sec:Lan)): Lanczos on
  * E^T A0^{-2} E, then U_k = A0^{-1} E V_k (k more solves); or the Lanczos
  * (Golub-Kahan) bidiagonalisation of A0^{-1} E, which gives both at once:
  * B Q_m = P_m B_m, Z_k = leading right singular vectors of B_m,
@@ -172,7 +172,7 @@ void ddlr_solve_options_default(ddlr_solve_options *opt);
  *  2./3. forms B_{i,alpha}, C_alpha and E (Sec. 3.1) and factors every block by
  *     incomplete LDL^T with the block's own pattern (Sec. 5);
  *  4. runs `lanczos_steps` Lanczos steps with full reorthogonalisation on
- *     E^T A0^{-1} E (DDLR-1) or E^T A0^{-2} E (DDLR-2) (Sec. 4.3) and forms
+ *     E^T A0^{-1} E (DDLR-1) or E^T A0^{-2} E (DDLR-2) (Sec. 4.4 (sec:Lan)) and forms
  *     U_k with G_{k,theta}^{-1} (eq. gkt) or H_k (Lemma on H_k).
  * A: host CSR (copied); part: host int32[n] with values in [0,p) (copied);
  * k: rank (ignored for DDLR_VARIANT_A0; 1 <= k < number of interface unknowns).
@@ -183,14 +183,15 @@ void ddlr_solve_options_default(ddlr_solve_options *opt);
 ddlr_status ddlr_setup(const ddlr_csr *A, const int32_t *part, int32_t p, int32_t k, int32_t variant,
                        const ddlr_options *opt, ddlr_prec **out);
 
-/* y = M^{-1} x for nrhs columns (Sec. 4.2: the five steps of the DDLR-1
- * preconditioning algorithm, or one A0 solve plus U_k H_k U_k^T for DDLR-2).
+/* y = M^{-1} x for nrhs columns.  DDLR-1: eq. (Mprec) with G_{k,theta}^{-1}
+ * of eq. (gkt), evaluated with two A0 solves as in Algorithm alg:prec1
+ * (Sec. 4.2); DDLR-2: one A0 solve plus U_k H_k U_k^T x (eq. Form2a).
  * x, y: device, user order, x and y must not overlap. */
 ddlr_status ddlr_apply(ddlr_prec *h, int32_t nrhs, const double *x, int64_t ldx, double *y, int64_t ldy,
                        void *stream);
 
-/* y = A0^{-1} x with the local factors only (steps 1 and 5 of the DDLR-1
- * algorithm: the p solves with B_{i,alpha} and the solve with C_alpha). */
+/* y = A0^{-1} x with the local factors only (the A0 solves of Algorithm
+ * alg:prec1: the p solves with B_{i,alpha} and the solve with C_alpha). */
 ddlr_status ddlr_a0_solve(ddlr_prec *h, int32_t nrhs, const double *x, int64_t ldx, double *y, int64_t ldy,
                           void *stream);
 
@@ -223,7 +224,7 @@ ddlr_status ddlr_get_ordering(const ddlr_prec *h, int32_t *perm, int32_t *iface,
  * factor of D_alpha = blockdiag(C_i). */
 ddlr_status ddlr_get_factor(const ddlr_prec *h, int64_t *row_ptr, int32_t *col, double *val, double *D);
 
-/* The approximate inverse X ~ C_alpha^{-1} of Algorithm alg:mr (Sec. 4.4),
+/* The approximate inverse X ~ C_alpha^{-1} of Algorithm alg:mr (Sec. 4.3 (sec:csolve)),
  * DDLR_CSOLVE_MR only: s x s CSR in interface positions of the internal order
  * (row_ptr s+1, col/val nnz_cinv of ddlr_query) and, if res is non-NULL, the
  * residual norms ||I - C_alpha X_j||_F for j = 0..cinv_iters.  Host arrays

@@ -229,7 +229,7 @@ class Oracle:
 
     def lowrank_gk(self, k, m, v0):
         """DDLR-2 with U_k, V_k from m steps of the bidiagonalisation of
-        A0^{-1} E (Sec. 4.3 alternative)."""
+        A0^{-1} E (Sec. 4.4 (sec:Lan) alternative)."""
         v0 = np.ascontiguousarray(v0, dtype=np.float64)
         st = _lib.orc_lowrank_gk(self._h, int(k), int(m), _p(v0))
         if st != OK:
@@ -284,6 +284,17 @@ class Oracle:
         _lib.orc_set_lowrank(self._h, int(variant), int(k), _p(U), _p(aux))
         self.variant, self.k = int(variant), int(k)
         return self
+
+    def matvec(self, x):
+        """y = A x in user order, row sums in ascending column order."""
+        x2, one = self._cols(x)
+        y = np.zeros_like(x2, order="F")
+        for j in range(x2.shape[1]):
+            xj = np.ascontiguousarray(x2[:, j])
+            yj = np.zeros(self.n)
+            _lib.orc_matvec(self._h, _p(xj), _p(yj))
+            y[:, j] = yj
+        return y[:, 0] if one else y
 
     def apply(self, x):
         x2, one = self._cols(x)

@@ -21,12 +21,12 @@
  *     B_{i,alpha} and one for C_alpha (Sec. 5: "incomplete Cholesky or LDL"),
  *     or exact dense LDL^T per block for the identity tests; alternatively
  *     C_alpha is solved by a sparse approximate inverse X built with the
- *     self-preconditioned global MR iteration with dropping (Sec. 4.4,
+ *     self-preconditioned global MR iteration with dropping (Sec. 4.3 (sec:csolve),
  *     Algorithm alg:mr), applied as a product with X, or by 5 preconditioned
  *     Chebyshev iterations with the block-Jacobi matrix D_alpha of the local
  *     blocks C_i and spectrum estimates from Lanczos on (C_alpha, D_alpha),
  *   - Lanczos on E^T A0^{-1} E (DDLR-1) or E^T A0^{-2} E (DDLR-2) with full
- *     reorthogonalisation (Sec. 4.3), Ritz pairs of T_m by cyclic Jacobi,
+ *     reorthogonalisation (Sec. 4.4 (sec:Lan)), Ritz pairs of T_m by cyclic Jacobi,
  *   - G_{k,theta}^{-1} of eq. (gkt) with theta = lambda_{k+1}, applied through
  *     the five steps of the DDLR-1 preconditioning algorithm (Sec. 4.2), or
  *     M^{-1} = A0^{-1} + U_k H_k U_k^T, H_k = (I - U_k^T E V_k)^{-1}
@@ -503,7 +503,7 @@ static void block_solve(const orc_t *o, int b, const double *x, double *z) {
     }
 }
 
-/* --------------------------------------- C_alpha approximate inverse (Sec. 4.4)
+/* --------------------------------------- C_alpha approximate inverse (Sec. 4.3 (sec:csolve))
  *
  * X ~ C_alpha^{-1} by the self-preconditioned global minimal residual
  * iteration with numerical dropping (Algorithm alg:mr), X_0 = diag(C_alpha)^{-1}:
@@ -778,7 +778,7 @@ static int build_cinv(orc_t *o, int nit, double tol, int lfil) {
     return ORC_OK;
 }
 
-/* ------------------------- C_alpha by preconditioned Chebyshev (Sec. 4.4)
+/* ------------------------- C_alpha by preconditioned Chebyshev (Sec. 4.3 (sec:csolve))
  *
  * D_alpha = blockdiag(C_i), C_i the coupling of subdomain i's interface
  * unknowns, factored by incomplete LDL^T (the interface block of L, D).  The
@@ -944,7 +944,7 @@ static void jacobi_eig(int m, double *T, double *ev, double *V) {
     for (int i = 0; i < m; ++i) ev[i] = T[i + i * m];
 }
 
-/* ---------------------------------------------------------- Lanczos (Sec. 4.3) */
+/* ---------------------------------------------------------- Lanczos (Sec. 4.4 (sec:Lan)) */
 
 /* m steps of Lanczos with full reorthogonalisation (classical Gram-Schmidt,
  * applied twice) on the s x s operator; start vector v0 (length s, internal
@@ -988,7 +988,7 @@ static void lanczos_reserve(orc_t *o, int m_max) {
     o->qcap = m_max + 1;
 }
 
-/* Lanczos on E^T A0^{-1} E (DDLR-1) or E^T A0^{-2} E (DDLR-2), Sec. 4.3, with
+/* Lanczos on E^T A0^{-1} E (DDLR-1) or E^T A0^{-2} E (DDLR-2), Sec. 4.4 (sec:Lan), with
  * full reorthogonalisation (classical Gram-Schmidt applied twice).  Continues
  * the stored run from step msteps up to m_max steps.  With check > 0 it stops
  * early at the first step m that is a multiple of check, with m >= k + 1,
@@ -1206,26 +1206,29 @@ static int ddlr2_hk(orc_t *o, int k, const double *EV) {
 
 /* ---------------------------------------------- preconditioner application (Sec. 4.2) */
 
-/* u = M^{-1} x, internal order. */
+/* u = M^{-1} x, internal order.  DDLR-1 evaluates eq. (Mprec) as written:
+ * M^{-1} = A0^{-1} + (A0^{-1} E) G_{k,theta}^{-1} (A0^{-1} E)^T, with
+ * G_{k,theta}^{-1} = c0 I + U_k diag(d) U_k^T from eq. (gkt), i.e.
+ * u = z + A0^{-1} E G^{-1} E^T z with z = A0^{-1} x (A0 symmetric). */
 static void apply_internal(const orc_t *o, const double *x, double *u) {
     const int64_t n = o->n, s = o->s;
     const int k = o->k;
     if (o->variant == 1) {
         double *z = xcalloc(n, sizeof(double)), *y = xcalloc(s, sizeof(double));
-        double *w = xcalloc(s, sizeof(double)), *v = xcalloc(n, sizeof(double));
-        double *c = xcalloc(k, sizeof(double));
-        a0_solve(o, x, z);                        /* step 1: A0 z = x */
-        et_mul(o, z, y);                          /* step 2: y = E^T z */
+        double *g = xcalloc(s, sizeof(double)), *t = xcalloc(n, sizeof(double));
+        double *c = xcalloc(k, sizeof(double)), *corr = xcalloc(n, sizeof(double));
+        a0_solve(o, x, z);                        /* z = A0^{-1} x */
+        et_mul(o, z, y);                          /* y = (A0^{-1} E)^T x = E^T z */
         for (int j = 0; j < k; ++j) c[j] = o->dvec[j] * dot(o->U + s * (int64_t)j, y, s);
-        for (int64_t i = 0; i < s; ++i) {         /* step 3: w = G_{k,theta}^{-1} y, eq. (gkt) */
-            double t = o->c0 * y[i];
-            for (int j = 0; j < k; ++j) t += o->U[i + s * (int64_t)j] * c[j];
-            w[i] = t;
+        for (int64_t i = 0; i < s; ++i) {         /* g = G_{k,theta}^{-1} y, eq. (gkt) */
+            double a = o->c0 * y[i];
+            for (int j = 0; j < k; ++j) a += o->U[i + s * (int64_t)j] * c[j];
+            g[i] = a;
         }
-        e_mul(o, w, v);                           /* step 4: v = E w */
-        for (int64_t i = 0; i < n; ++i) v[i] += x[i];
-        a0_solve(o, v, u);                        /* step 5: A0 u = x + v */
-        free(z); free(y); free(w); free(v); free(c);
+        e_mul(o, g, t);                           /* t = E g */
+        a0_solve(o, t, corr);                     /* corr = (A0^{-1} E) g */
+        for (int64_t i = 0; i < n; ++i) u[i] = z[i] + corr[i];
+        free(z); free(y); free(g); free(t); free(c); free(corr);
     } else if (o->variant == 2) {
         a0_solve(o, x, u);
         double *c = xcalloc(k, sizeof(double)), *h = xcalloc(k, sizeof(double));
@@ -1408,7 +1411,7 @@ int orc_lowrank_ctl(orc_t *o, int variant, int k, int m, int check, double eps, 
 }
 
 /* DDLR-2 with U_k and V_k from the Lanczos (Golub-Kahan) bidiagonalisation of
- * B = A0^{-1} E (n x s), the alternative build named in Sec. 4.3 (Golub & Van
+ * B = A0^{-1} E (n x s), the alternative build named in Sec. 4.4 (sec:Lan) (Golub & Van
  * Loan, Sec. 10.4).  From a unit q_1 (the interface entries of v0):
  *   p_j = (B q_j - beta_{j-1} p_{j-1}) / alpha_j,
  *   q_{j+1} = (B^T p_j - alpha_j q_j) / beta_j,   B^T = E^T A0^{-1},

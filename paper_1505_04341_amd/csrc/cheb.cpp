@@ -1,4 +1,4 @@
-// Spectrum estimate for the Chebyshev solver of C_alpha (Sec. 4.4).
+// Spectrum estimate for the Chebyshev solver of C_alpha (Sec. 4.3 (sec:csolve)).
 //
 // The preconditioner of the Chebyshev iteration is the block-Jacobi matrix
 // D_alpha = blockdiag(C_i) (C_i: the couplings among subdomain i's interface

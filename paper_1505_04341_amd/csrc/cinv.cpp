@@ -1,4 +1,4 @@
-// Sparse approximate inverse of C_alpha (Sec. 4.4, Algorithm alg:mr).
+// Sparse approximate inverse of C_alpha (Sec. 4.3 (sec:csolve), Algorithm alg:mr).
 //
 // X ~ C_alpha^{-1} from the self-preconditioned global minimal-residual
 // iteration with numerical dropping, started from X_0 = diag(C_alpha)^{-1}:

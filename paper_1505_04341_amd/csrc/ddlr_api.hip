@@ -1233,7 +1233,13 @@ void lr_expand(ddlr_prec* h, const T* U, int64_t rows, int nrhs, double beta, co
 
 // out = M^{-1} in (device order); I/O in double, preconditioner arithmetic in T.
 // Precision changes happen inside the kernels that read the input and write
-// the output (no separate cast passes).
+// the output (no separate cast passes).  DDLR-1 (eq. Mprec with eq. gkt,
+// organised as Algorithm alg:prec1 so that only two A0 solves run):
+//   a0_solve_dev (double in, T out)        block + interface triangular solves
+//   csr_mv over E^T                         interface gather into ys
+//   lr_coef / lr_expand (MFMA)              ws = c0 ys + U_k (d .* (U_k^T ys))
+//   csr_mv over E, input added in the pass  a2 = in + E ws (one fused pass)
+//   a0_solve_dev (T in, double out)         the second pair of sweeps
 template <typename T>
 void apply_dev_T(ddlr_prec* h, int nrhs, const double* in, int64_t ldin, double* out, int64_t ldout, hipStream_t st,
                  const int* done) {
@@ -1245,9 +1251,8 @@ void apply_dev_T(ddlr_prec* h, int nrhs, const double* in, int64_t ldin, double*
         T* a2 = (T*)W.a2;
         T* ys = (T*)W.ys;
         T* wsv = (T*)W.ws;
-        a0_solve_dev<T, double, T>(h, F, nrhs, in, ldin, a1, n, st, done);  // step 1: A0 z = x
-        csr_mv<T, T>(s, nrhs, h->etrp, h->etci, F.etv, a1, n, (const T*)nullptr, 0, ys, s, st,
-                     done);  // step 2: y = E^T z
+        a0_solve_dev<T, double, T>(h, F, nrhs, in, ldin, a1, n, st, done);
+        csr_mv<T, T>(s, nrhs, h->etrp, h->etci, F.etv, a1, n, (const T*)nullptr, 0, ys, s, st, done);
         if (h->nsys > 1) {  // per system of a batch (one column)
             ProfScope ps(h, 3, st);
             hipLaunchKernelGGL(k_seg_lr_coef<T>, dim3(h->nsys), dim3(256), 0, st, h->seg_soff, h->k, F.U, ys, h->dvecs,
@@ -1257,12 +1262,11 @@ void apply_dev_T(ddlr_prec* h, int nrhs, const double* in, int64_t ldin, double*
                                W.coef, h->c0s, ys, wsv, done);
             LAUNCHCHK();
         } else {
-            lr_coef<T, T>(h, F.U, s, nrhs, ys, s, 1, st, done);  // step 3: w = G_{k,theta}^{-1} y (eq. gkt)
+            lr_coef<T, T>(h, F.U, s, nrhs, ys, s, 1, st, done);
             lr_expand<T, T>(h, F.U, s, nrhs, h->c0, ys, s, wsv, s, st, done);
         }
-        csr_mv<T, double>(n, nrhs, h->erp, h->eci, F.ev, wsv, s, in, ldin, a2, n, st,
-                          done);  // step 4: v = E w, fused x + v
-        a0_solve_dev<T, T, double>(h, F, nrhs, a2, n, out, ldout, st, done);  // step 5: A0 u = x + v
+        csr_mv<T, double>(n, nrhs, h->erp, h->eci, F.ev, wsv, s, in, ldin, a2, n, st, done);
+        a0_solve_dev<T, T, double>(h, F, nrhs, a2, n, out, ldout, st, done);
     } else if (h->variant == DDLR_2) {
         a0_solve_dev<T, double, double>(h, F, nrhs, in, ldin, out, ldout, st, done);
         lr_coef<T, double>(h, F.U, n, nrhs, in, ldin, 2, st, done);
@@ -1452,7 +1456,7 @@ void make_bf16_basis(ddlr_prec* h) {
 
 // ------------------------------------------------------------ Lanczos build
 
-// Lanczos run on E^T A0^{-1} E (DDLR-1) or E^T A0^{-2} E (DDLR-2), Sec. 4.3,
+// Lanczos run on E^T A0^{-1} E (DDLR-1) or E^T A0^{-2} E (DDLR-2), Sec. 4.4 (sec:Lan),
 // kept on the device so it can be continued (improving a given
 // preconditioner by more steps and a larger k).
 void lanczos_reserve(ddlr_prec* h, int cap) {
@@ -1787,7 +1791,7 @@ void lanczos_finish(ddlr_prec* h, int k, int theta_mode) {
 }
 
 // DDLR-2 with U_k and V_k from m steps of the Lanczos (Golub-Kahan)
-// bidiagonalisation of B = A0^{-1} E, the alternative build of Sec. 4.3
+// bidiagonalisation of B = A0^{-1} E, the alternative build of Sec. 4.4 (sec:Lan)
 // (Golub & Van Loan, Sec. 10.4).  From the unit interface vector q_1:
 //   p_j = (B q_j - beta_{j-1} p_{j-1}) / alpha_j,   B q = A0^{-1} (E q)
 //   q_{j+1} = (B^T p_j - alpha_j q_j) / beta_j,     B^T p = E^T (A0^{-1} p)

@@ -803,7 +803,7 @@ __global__ __launch_bounds__(256) void k_spmv_sell_il(int64_t n, int nrhs, const
 // E (n x s) and E^T (s x n) as CSR in device order (E carries alpha^{-1} Ehat on
 // interior rows and -alpha on the interface diagonal, eq. EF).
 //   k_csr_mv:  y = M w            (E^T z, or E q for Lanczos)
-//   k_csr_add: t = x + M w        (step 4 of the DDLR-1 algorithm fused with x + v)
+//   k_csr_add: t = x + M w        (E w added to the apply's input in the same pass)
 template <typename T, typename TX = T>
 __global__ __launch_bounds__(256) void k_csr_mv(int64_t rows, int nrhs, const int32_t* __restrict__ rp,
                                                 const int32_t* __restrict__ ci, const T* __restrict__ v,
@@ -856,7 +856,7 @@ __global__ __launch_bounds__(256) void k_csr_mv_n(int64_t rows, int nrhs, const 
     }
 }
 
-// z_C = X x_C: the C_alpha solve by its approximate inverse (Sec. 4.4,
+// z_C = X x_C: the C_alpha solve by its approximate inverse (Sec. 4.3 (sec:csolve),
 // Algorithm alg:mr).  X is stored in SELL-64 over the interface rows: rows
 // sorted by entry count (longest first) and cut into slices of 64, entries
 // column-major inside a slice so that a wave's loads of one entry position
@@ -893,7 +893,7 @@ __global__ __launch_bounds__(256) void k_cinv_sell(int64_t rows, int nrhs, const
         if (r < nrhs) z[i + r * ldz] = (TOut)acc[r];
 }
 
-// Chebyshev acceleration for the C_alpha solve (Sec. 4.4; Saad, Iterative
+// Chebyshev acceleration for the C_alpha solve (Sec. 4.3 (sec:csolve); Saad, Iterative
 // Methods for Sparse Linear Systems, Alg. 12.1), on the interface rows:
 // pointers at the first interface row, ld = n, grid (row chunks, nrhs).
 //   first:  r = x, d = t / theta (t = D^{-1} x), acc = d

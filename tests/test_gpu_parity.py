@@ -39,8 +39,7 @@ def to_host(t):
     return a if a.ndim == 1 else a.T
 
 
-def rel(a, b):
-    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+from parity import assert_close, rel  # noqa: E402
 
 
 def setup_pair(cfg, variant=1, wide=None, env=None, **kw):
@@ -96,10 +95,9 @@ def test_a0_solve_and_spmv(name, wide, kernel):
         D.ddlr_a0_solve(h, to_dev(x), y)
         got = to_host(y)
         ref = o.a0_solve(x)
-        assert rel(got, ref) <= 1e-12, (nrhs, rel(got, ref))
+        assert_close(got, ref, 1e-12)
         D.ddlr_spmv(h, to_dev(x), y)
-        ref = cfg["A"].to_scipy() @ x
-        assert rel(to_host(y), ref) <= 1e-14
+        assert_close(to_host(y), o.matvec(x), 1e-14)
 
 
 @pytest.mark.parametrize("name", ["small3d", "irregular"])
@@ -131,9 +129,9 @@ def test_columns_independent_of_batch_width(name, prec):
         D.ddlr_apply(h, to_dev(x[:, :w]), y)
         got = y.cpu().numpy()
         for j in range(w):
-            assert rel(got[j], alone_ap[j].numpy()[0]) <= tol, (w, j)
+            assert_close(got[j], alone_ap[j].numpy()[0], tol)
     ref = o.a0_solve(x[:, :3])
-    assert rel(torch.cat(alone_a0[:3]).numpy().T, ref) <= (1e-12 if prec == 0 else 1e-5)
+    assert_close(torch.cat(alone_a0[:3]).numpy().T, ref, (1e-12 if prec == 0 else 1e-5))
 
 
 @pytest.mark.parametrize("name", ["c1", "small2d", "irregular"])
@@ -154,7 +152,7 @@ def test_apply_with_imported_lowrank(name, variant, lr):
     y = torch.empty((5, n), dtype=torch.float64, device=DEV)
     D.ddlr_apply(h, to_dev(x), y)
     ref = o.apply(x)
-    assert rel(to_host(y), ref) <= 1e-10
+    assert_close(to_host(y), ref, 1e-10)
     # round trip of the low-rank data through the ABI
     back = D.ddlr_get_lowrank(h)
     assert np.array_equal(back[0], lr[0])
@@ -192,13 +190,13 @@ def test_pcg_fixed_steps_matches_oracle(name):
     st, info = D.ddlr_solve(h, to_dev(b), x, maxit=6)
     assert st == D.E_NO_CONVERGENCE and all(i["iters"] == 6 for i in info)
     xo, infoo = o.pcg(b, maxit=6)
-    assert rel(to_host(x), xo) <= 1e-10
+    assert_close(to_host(x), xo, 1e-10)
     st, info = D.ddlr_solve(h, to_dev(b), x)
     xo, infoo = o.pcg(b)
     assert st == D.OK
     # the iterates agree to rounding, so the step that crosses 1e-6 may differ by one
     assert all(abs(i["iters"] - int(io)) <= 1 for i, io in zip(info, infoo["its"]))
-    assert rel(to_host(x), xo) <= 1e-5
+    assert_close(to_host(x), xo, 1e-5)
 
 
 @pytest.mark.parametrize("name", ["c1", "small3d"])
@@ -216,8 +214,8 @@ def test_pcg_end_to_end_own_setup(name, variant):
     xo, infoo = o.pcg(b)
     for i, io in zip(info, infoo["its"]):
         assert abs(i["iters"] - io) <= 1
-        assert i["relres_true"] <= 1.05e-6
-    assert rel(to_host(x), xo) <= 1e-5
+        assert i["relres_true"] <= 1e-6
+    assert_close(to_host(x), xo, 1e-5)
 
 
 @pytest.mark.parametrize("variant", [1, 2])
@@ -236,7 +234,7 @@ def test_fp32_apply_matches_oracle(variant, lr):
         x = np.random.default_rng(nrhs).standard_normal((n, nrhs))
         y = torch.empty((nrhs, n), dtype=torch.float64, device=DEV)
         D.ddlr_apply(h, to_dev(x), y)
-        assert rel(to_host(y), o.apply(x)) <= 1e-4
+        assert_close(to_host(y), o.apply(x), 1e-4)
 
 
 @pytest.mark.parametrize("variant", [1, 2])
@@ -253,7 +251,7 @@ def test_bf16_basis_apply_matches_oracle(variant):
         x = np.random.default_rng(nrhs).standard_normal((n, nrhs))
         y = torch.empty((nrhs, n), dtype=torch.float64, device=DEV)
         D.ddlr_apply(h, to_dev(x), y)
-        assert rel(to_host(y), o.apply(x)) <= 5e-3
+        assert_close(to_host(y), o.apply(x), 5e-3)
 
 
 @pytest.mark.parametrize("prec", [D.FP32, D.FP32_UK_BF16])
@@ -332,7 +330,7 @@ def test_interface_levels_on_side_stream(overlap):
     y = torch.empty((8, n), dtype=torch.float64, device=DEV)
     for _ in range(3):
         D.ddlr_a0_solve(h, to_dev(x), y)
-    assert rel(to_host(y), o.a0_solve(x)) <= 1e-5
+    assert_close(to_host(y), o.a0_solve(x), 1e-5)
 
 
 def shifted2d(sig, nx=24, ny=20):
@@ -370,12 +368,12 @@ def test_gmres_matches_oracle(restart, variant):
         if st == D.OK:
             assert i["relres"] <= 1e-6 and i["relres_true"] <= 2e-6
     if st == D.OK:
-        assert rel(to_host(x), xo) <= 1e-5
+        assert_close(to_host(x), xo, 1e-5)
     # a fixed number of steps gives the same iterate
     st, info = D.ddlr_solve(h, to_dev(b), x, method=1, restart=restart, maxit=restart + 3)
     xo, io = o.gmres(b, restart=restart, maxit=restart + 3)
     assert st == D.E_NO_CONVERGENCE and all(i["iters"] == restart + 3 for i in info)
-    assert rel(to_host(x), xo) <= 1e-9
+    assert_close(to_host(x), xo, 1e-9)
 
 
 def batch_members(count, prec, seed=0):
@@ -424,10 +422,10 @@ def test_batch_matches_single_and_oracle(prec):
         # path's FP32 MFMA in FP32 (operators equal to ~1e-7)
         slack = 1 if prec == D.FP64 else max(1, int(0.1 * i1[0]["iters"]))
         assert abs(info[q]["iters"] - i1[0]["iters"]) <= slack
-        assert info[q]["relres_true"] <= 1.05e-6
+        assert info[q]["relres_true"] <= 1e-6
         # two CG runs stopped at 1e-6 residual differ by up to ~cond * 1e-6 in x;
         # these random-coefficient systems (contrast 1e4) are ill-conditioned
-        assert rel(xb, xq.cpu().numpy()) <= 1e-4
+        assert_close(xb, xq.cpu().numpy(), 1e-4)
         o = Oracle(A, part, p)
         o.lowrank(1, k, m, w.lanczos_start(A.n, 3))
         xo, io = o.pcg(bs[q])
@@ -435,7 +433,7 @@ def test_batch_matches_single_and_oracle(prec):
             assert abs(info[q]["iters"] - int(io["its"][0])) <= 1
         else:  # mixed-precision bar against the FP64 oracle
             assert info[q]["iters"] <= int(1.1 * int(io["its"][0])) + 1
-        assert rel(xb, xo) <= 1e-4
+        assert_close(xb, xo, 1e-4)
     # the batch's preconditioner application equals each member's
     y = torch.empty_like(bt)
     D.ddlr_batch_apply(B, bt, y)
@@ -443,7 +441,7 @@ def test_batch_matches_single_and_oracle(prec):
         b = torch.from_numpy(bs[q]).to(DEV)
         yq = torch.empty_like(b)
         D.ddlr_apply(h, b, yq)
-        assert rel(y.cpu().numpy()[off[q]:off[q + 1]], yq.cpu().numpy()) <= (1e-12 if prec == D.FP64 else 1e-6)
+        assert_close(y.cpu().numpy()[off[q]:off[q + 1]], yq.cpu().numpy(), (1e-12 if prec == D.FP64 else 1e-6))
 
 
 def test_serving_same_alone_and_in_mix():
@@ -562,7 +560,7 @@ def test_apply_wide_lowrank_kernels(variant, prec, k):
         x = np.random.default_rng(nrhs).standard_normal((n, nrhs))
         y = torch.empty((nrhs, n), dtype=torch.float64, device=DEV)
         D.ddlr_apply(h, to_dev(x), y)
-        assert rel(to_host(y), o.apply(x)) <= tol, nrhs
+        assert_close(to_host(y), o.apply(x), tol, f"nrhs {nrhs}")
 
 
 @pytest.mark.parametrize("variant", [1, 2])
@@ -584,7 +582,7 @@ def test_lanczos_control_matches_oracle(variant):
     y = torch.empty((3, n), dtype=torch.float64, device=DEV)
     D.ddlr_set_lowrank(h, variant, *o.get_lowrank())
     D.ddlr_apply(h, to_dev(x), y)
-    assert rel(to_host(y), o.apply(x)) <= 1e-10
+    assert_close(to_host(y), o.apply(x), 1e-10)
 
 
 @pytest.mark.parametrize("variant", [1, 2])
@@ -611,7 +609,7 @@ def test_extend_lowrank(variant):
     o = Oracle(cfg["A"], cfg["part"], cfg["p"]).lowrank(variant, 6, 16, v0)
     o.extend(10, 12)
     # same operator as the oracle up to the eigensolver's rounding of T_m
-    assert rel(to_host(y1), o.apply(x)) <= 1e-8
+    assert_close(to_host(y1), o.apply(x), 1e-8)
     # errors: no run to continue after imported low-rank data
     D.ddlr_set_lowrank(h2, variant, *o.get_lowrank())
     with pytest.raises(D.DDLRError):
@@ -627,15 +625,17 @@ def test_unstructured_rgg_end_to_end():
     A, _ = w.rgg_laplacian(30000, 10, 5)
     p = 16
     part = D.ddlr_partition_graph(A, p)
-    assert np.array_equal(part, partition_graph(A, p))
+    part_o = partition_graph(A, p)
+    assert np.array_equal(part, part_o)
     cfg = dict(A=A, part=part, p=p, k=16, m=32)
     say("rgg", A.n, len(A.col))
-    h, o = setup_pair(cfg, variant=1)
+    h, _ = setup_pair(cfg, variant=1)
+    o = Oracle(A, part_o, p)  # the oracle takes the partition its own rule produced
     n = A.n
     x = np.random.default_rng(9).standard_normal((n, 3))
     y = torch.empty((3, n), dtype=torch.float64, device=DEV)
     D.ddlr_a0_solve(h, to_dev(x), y)
-    assert rel(to_host(y), o.a0_solve(x)) <= 1e-12
+    assert_close(to_host(y), o.a0_solve(x), 1e-12)
     o.lowrank(1, cfg["k"], cfg["m"], w.lanczos_start(n, 0))
     b, xs = w.rhs_from_solution(A, 3, 2)
     xt = torch.zeros((2, n), dtype=torch.float64, device=DEV)
@@ -643,8 +643,8 @@ def test_unstructured_rgg_end_to_end():
     xo, io = o.pcg(b)
     assert st == D.OK
     for i, its in zip(info, io["its"]):
-        assert abs(i["iters"] - int(its)) <= 1 and i["relres_true"] <= 1.05e-6
-    assert rel(to_host(xt), xo) <= 1e-5
+        assert abs(i["iters"] - int(its)) <= 1 and i["relres_true"] <= 1e-6
+    assert_close(to_host(xt), xo, 1e-5)
 
 
 @pytest.mark.parametrize("case", ["small3d", "rgg", "tpfa"])
@@ -677,13 +677,13 @@ def test_ring_workgroup_sizes_bitwise(case, prec):
     for nt in ("64", "256", "-1"):  # -1: the plain per-level kernel
         assert torch.equal(outs[nt], outs["512"]), nt
     ref = o.a0_solve(x)
-    assert rel(outs["512"].numpy().T, ref) <= (1e-12 if prec == 0 else 1e-5)
+    assert_close(outs["512"].numpy().T, ref, (1e-12 if prec == 0 else 1e-5))
     t = D.ddlr_tune(h, 1, retune=True)
     say("tune", case, prec, t)
     assert t["ring_threads"] in (-1, 64, 256, 512)
 
 
-# ------------------------------ C_alpha by its approximate inverse (Sec. 4.4)
+# ------------------------------ C_alpha by its approximate inverse (Sec. 4.3 (sec:csolve))
 
 def setup_pair_mr(cfg, variant=1, nit=3, tol=0.01, lfil=20, env=None, **kw):
     """GPU preconditioner and oracle, both solving C_alpha with the MR approximate inverse."""
@@ -717,7 +717,7 @@ def test_cinv_a0_solve(name, overlap):
         y = torch.empty((nrhs, n), dtype=torch.float64, device=DEV)
         D.ddlr_a0_solve(h, to_dev(x), y)
         ref = o.a0_solve(x)
-        assert rel(to_host(y), ref) <= 1e-12, (nrhs, rel(to_host(y), ref))
+        assert_close(to_host(y), ref, 1e-12)
 
 
 @pytest.mark.parametrize("name", ["c1", "irregular", "small3d"])
@@ -743,7 +743,7 @@ def test_cinv_lanczos_and_apply(name, variant):
     x = np.random.default_rng(3).standard_normal((cfg["A"].n, 4))
     y = torch.empty((4, cfg["A"].n), dtype=torch.float64, device=DEV)
     D.ddlr_apply(h, to_dev(x), y)
-    assert rel(to_host(y), o.apply(x)) <= 1e-10
+    assert_close(to_host(y), o.apply(x), 1e-10)
 
 
 @pytest.mark.parametrize("name", ["c1", "small3d"])
@@ -760,12 +760,12 @@ def test_cinv_pcg_end_to_end(name, prec):
     assert st == D.OK
     xo, infoo = o.pcg(b)
     for i, io in zip(info, infoo["its"]):
-        assert i["relres_true"] <= 1.05e-6
+        assert i["relres_true"] <= 1e-6
         if prec == D.FP64:
             assert abs(i["iters"] - int(io)) <= 1
         else:
             assert i["iters"] <= int(1.1 * io) + 1
-    assert rel(to_host(x), xo) <= 1e-5
+    assert_close(to_host(x), xo, 1e-5)
 
 
 def test_cinv_ddlr2_rank_above_register_block():
@@ -778,10 +778,10 @@ def test_cinv_ddlr2_rank_above_register_block():
     x = np.random.default_rng(5).standard_normal((cfg["A"].n, 2))
     y = torch.empty((2, cfg["A"].n), dtype=torch.float64, device=DEV)
     D.ddlr_apply(h, to_dev(x), y)
-    assert rel(to_host(y), o.apply(x)) <= 1e-8
+    assert_close(to_host(y), o.apply(x), 1e-8)
 
 
-# ------------------- DDLR-2 by bidiagonalisation of A0^{-1} E (Sec. 4.3 alternative)
+# ------------------- DDLR-2 by bidiagonalisation of A0^{-1} E (Sec. 4.4 (sec:Lan) alternative)
 
 @pytest.mark.parametrize("name", ["c1", "irregular", "small3d"])
 def test_bidiag_build_matches_oracle(name):
@@ -798,12 +798,12 @@ def test_bidiag_build_matches_oracle(name):
     x = np.random.default_rng(9).standard_normal((cfg["A"].n, 2))
     y = torch.empty((2, cfg["A"].n), dtype=torch.float64, device=DEV)
     D.ddlr_apply(h, to_dev(x), y)
-    assert rel(to_host(y), o.apply(x)) <= 1e-6
+    assert_close(to_host(y), o.apply(x), 1e-6)
     # the same preconditioner (imported) gives the oracle's application to 1e-10
     U, H = o.get_lowrank()
     D.ddlr_set_lowrank(h, 2, U, H)
     D.ddlr_apply(h, to_dev(x), y)
-    assert rel(to_host(y), o.apply(x)) <= 1e-10
+    assert_close(to_host(y), o.apply(x), 1e-10)
 
 
 def test_bidiag_solve_and_limits():
@@ -818,7 +818,7 @@ def test_bidiag_solve_and_limits():
     xo, infoo = o.pcg(b)
     assert st == D.OK
     for i, io in zip(info, infoo["its"]):
-        assert abs(i["iters"] - int(io)) <= 1 and i["relres_true"] <= 1.05e-6
+        assert abs(i["iters"] - int(io)) <= 1 and i["relres_true"] <= 1e-6
     # the run is not kept: no continuation
     with pytest.raises(D.DDLRError):
         D.ddlr_extend_lowrank(h, cfg["k"], 4)
@@ -840,7 +840,7 @@ def test_spmv_compact_storage_bitwise(name):
     values); irregular: random coefficients (FP64 values, 16-bit columns)."""
     cfg = CASES[name]()
     say("spmv compact", name)
-    h1, _ = setup_pair(cfg, variant=D.VARIANT_A0)
+    h1, o = setup_pair(cfg, variant=D.VARIANT_A0)
     h2, _ = setup_pair(cfg, variant=D.VARIANT_A0, env={"DDLR_SELL_WIDE": "1"})
     n = cfg["A"].n
     x = np.random.default_rng(2).standard_normal((n, 3))
@@ -849,7 +849,7 @@ def test_spmv_compact_storage_bitwise(name):
     D.ddlr_spmv(h1, to_dev(x), y1)
     D.ddlr_spmv(h2, to_dev(x), y2)
     assert torch.equal(y1, y2)
-    assert rel(to_host(y1), cfg["A"].to_scipy() @ x) <= 1e-14
+    assert_close(to_host(y1), o.matvec(x), 1e-14)
     b, _ = w.rhs_from_solution(cfg["A"], 0, 3)
     x1 = torch.zeros((3, n), dtype=torch.float64, device=DEV)
     x2 = torch.zeros_like(x1)
@@ -858,7 +858,7 @@ def test_spmv_compact_storage_bitwise(name):
     assert torch.equal(x1, x2)
 
 
-# ------------------------ C_alpha by preconditioned Chebyshev (Sec. 4.4, Table 3)
+# ------------------------ C_alpha by preconditioned Chebyshev (Sec. 4.3 (sec:csolve), Table 3)
 
 def setup_pair_cheb(cfg, variant=1, nu=5, mc=10, env=None, **kw):
     env = dict(env or {})
@@ -888,7 +888,7 @@ def test_cheb_a0_solve(name, overlap):
         y = torch.empty((nrhs, n), dtype=torch.float64, device=DEV)
         D.ddlr_a0_solve(h, to_dev(x), y)
         ref = o.a0_solve(x)
-        assert rel(to_host(y), ref) <= 1e-11, (nrhs, rel(to_host(y), ref))
+        assert_close(to_host(y), ref, 1e-11)
 
 
 @pytest.mark.parametrize("name", ["c1", "small3d"])
@@ -908,7 +908,7 @@ def test_cheb_lanczos_apply_and_solve(name, variant):
     xo, infoo = o.pcg(b)
     assert st == D.OK
     for i, io in zip(info, infoo["its"]):
-        assert abs(i["iters"] - int(io)) <= 1 and i["relres_true"] <= 1.05e-6
+        assert abs(i["iters"] - int(io)) <= 1 and i["relres_true"] <= 1e-6
     if variant == 1:
         U, lam, th = o.get_lowrank()
         D.ddlr_set_lowrank(h, 1, U, lam, th)
@@ -918,7 +918,7 @@ def test_cheb_lanczos_apply_and_solve(name, variant):
     xx = np.random.default_rng(4).standard_normal((cfg["A"].n, 3))
     y = torch.empty((3, cfg["A"].n), dtype=torch.float64, device=DEV)
     D.ddlr_apply(h, to_dev(xx), y)
-    assert rel(to_host(y), o.apply(xx)) <= 1e-10
+    assert_close(to_host(y), o.apply(xx), 1e-10)
 
 
 def test_cheb_mixed_precision_solve():
@@ -932,4 +932,4 @@ def test_cheb_mixed_precision_solve():
     _, infoo = o.pcg(b)
     assert st == D.OK
     for i, io in zip(info, infoo["its"]):
-        assert i["relres_true"] <= 1.05e-6 and i["iters"] <= int(1.1 * io) + 1
+        assert i["relres_true"] <= 1e-6 and i["iters"] <= int(1.1 * io) + 1

@@ -278,7 +278,7 @@ def test_breakdown_and_input_errors():
     assert e.value.status == E_INVALID
 
 
-# ---------------------------------------------------------- Lanczos (Sec. 4.3)
+# ---------------------------------------------------------- Lanczos (Sec. 4.4 (sec:Lan))
 
 @pytest.mark.parametrize("variant", [1, 2])
 def test_lanczos_relations(variant):
@@ -637,7 +637,7 @@ def test_partition_sizes_and_components():
     assert partition_graph(B, 2).tolist() == [0, 0, 0, 0, 1, 1, 1, 1]
 
 
-# ------------------------------------- C_alpha approximate inverse (Sec. 4.4)
+# ------------------------------------- C_alpha approximate inverse (Sec. 4.3 (sec:csolve))
 
 def _c_alpha(o):
     """C_alpha = A0[m:, m:] (dense), interface order."""
@@ -772,7 +772,7 @@ def test_cinv_spd_certificate(name):
     assert np.linalg.eigvalsh(X.toarray()).min() > 0.0
 
 
-# ------------------ DDLR-2 by bidiagonalisation of A0^{-1} E (Sec. 4.3 alternative)
+# ------------------ DDLR-2 by bidiagonalisation of A0^{-1} E (Sec. 4.4 (sec:Lan) alternative)
 
 def test_gk_full_run_gives_singular_values():
     """A full bidiagonalisation (m = s) recovers the singular values of
@@ -826,7 +826,7 @@ def test_gk_short_run_close_to_lanczos_route():
     assert np.all(np.abs(ig["its"] - il["its"]) <= 2)
 
 
-# ---------------------- C_alpha by preconditioned Chebyshev (Sec. 4.4, Table 3)
+# ---------------------- C_alpha by preconditioned Chebyshev (Sec. 4.3 (sec:csolve), Table 3)
 
 def _cheb_setup(name, nu=5, mc=10):
     cfg = w.config(name)
