@@ -30,8 +30,8 @@ def max_rel_cols(a, b):
     return out
 
 
-def assert_close(got, ref, tol, what=""):
-    """Both rules above at the same tolerance."""
+def assert_close(got, ref, tol, what="", elem_tol=None):
+    """Both rules above, at the same tolerance unless elem_tol is given."""
     got = np.asarray(got, dtype=np.float64)
     ref = np.asarray(ref, dtype=np.float64)
     assert got.shape == ref.shape, (what, got.shape, ref.shape)
@@ -39,4 +39,15 @@ def assert_close(got, ref, tol, what=""):
     cols = max_rel_cols(got, ref)
     assert r2 <= tol, f"{what}: relative 2-norm difference {r2:.3e} > {tol:.1e}"
     worst = int(np.argmax(cols))
-    assert cols[worst] <= tol, f"{what}: column {worst} elementwise difference {cols[worst]:.3e} > {tol:.1e}"
+    et = tol if elem_tol is None else elem_tol
+    assert cols[worst] <= et, f"{what}: column {worst} elementwise difference {cols[worst]:.3e} > {et:.1e}"
+
+
+def assert_converged_close(got, ref, tol, what=""):
+    """Two solutions of the same system, each from a Krylov run stopped at
+    ||r|| <= 1e-6 ||b|| (possibly one step apart).  They are not the same
+    computation: they differ by the runs' final errors, A^{-1} r, which are
+    bounded in norm by the stopping rule but can concentrate near strong
+    coefficient jumps.  The 2-norm rule keeps `tol`; the elementwise rule
+    allows ten times it."""
+    assert_close(got, ref, tol, what, elem_tol=10 * tol)
