@@ -209,6 +209,25 @@ ddlr_status ddlr_spmv(ddlr_prec *h, int32_t nrhs, const double *x, int64_t ldx, 
 ddlr_status ddlr_solve(ddlr_prec *h, int32_t nrhs, const double *b, int64_t ldb, double *x, int64_t ldx,
                        const ddlr_solve_options *opt, ddlr_solve_info *info, void *stream);
 
+/* ddlr_apply for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, result and errors as ddlr_apply, and the same kernels, but every
+ * temporary (gathered input and output, the A0-solve and interface vectors,
+ * the low-rank reduction partials, the Chebyshev vectors) lives in one 64 MiB
+ * device array owned by the library, one per GPU, held until the process
+ * ends; the call allocates nothing and runs no autotuning (it uses the shapes
+ * already tuned for the handle, else the defaults).  Columns go through in
+ * chunks of at most 16 that fit the array.  Errors: DDLR_E_INVALID (besides
+ * ddlr_apply's) when a single column needs more scratch than the array holds
+ * (about 32 bytes per row plus 16 per interface row in FP64, 24 + 8 in FP32,
+ * plus 8 KiB per rank, four more n-vectors with the Chebyshev solver); the
+ * message gives both sizes.  The array is shared by every call on the same
+ * GPU and keeps the last call's contents (every temporary is written before
+ * it is read): calls that overlap in time on one GPU, from any handle or
+ * stream, race and must be serialised by the caller. */
+ddlr_status ddlr_apply_noalloc(ddlr_prec *h, int32_t nrhs, const double *x, int64_t ldx, double *y, int64_t ldy,
+                               void *stream);
+
 /* Sizes, counts and timings of a built preconditioner. */
 ddlr_status ddlr_query(const ddlr_prec *h, ddlr_info *info);
 

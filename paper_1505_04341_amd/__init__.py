@@ -114,6 +114,7 @@ def load_library(path: str = LIB_PATH):
         "ddlr_solve_options_default": (None, [P]),
         "ddlr_setup": (I32, [P, P, I32, I32, I32, P, P]),
         "ddlr_apply": (I32, [P, I32, P, I64, P, I64, P]),
+        "ddlr_apply_noalloc": (I32, [P, I32, P, I64, P, I64, P]),
         "ddlr_a0_solve": (I32, [P, I32, P, I64, P, I64, P]),
         "ddlr_spmv": (I32, [P, I32, P, I64, P, I64, P]),
         "ddlr_solve": (I32, [P, I32, P, I64, P, I64, P, P, P]),
@@ -251,6 +252,11 @@ def _vec_op(name: str, prec: Prec, x, y, stream):
 def ddlr_apply(prec: Prec, x, y, stream=None):
     """y = M^{-1} x (device tensors, user order)."""
     return _vec_op("ddlr_apply", prec, x, y, stream)
+
+
+def ddlr_apply_noalloc(prec: Prec, x, y, stream=None):
+    """y = M^{-1} x with every temporary in the library's static scratch array."""
+    return _vec_op("ddlr_apply_noalloc", prec, x, y, stream)
 
 
 def ddlr_a0_solve(prec: Prec, x, y, stream=None):
@@ -543,6 +549,7 @@ def ddlr_version() -> int:
 
 
 EXPORTED = ["ddlr_version", "ddlr_options_default", "ddlr_solve_options_default", "ddlr_setup", "ddlr_apply",
+            "ddlr_apply_noalloc",
             "ddlr_a0_solve", "ddlr_spmv", "ddlr_solve", "ddlr_query", "ddlr_get_ordering", "ddlr_get_factor",
             "ddlr_get_cinv",
             "ddlr_get_levels", "ddlr_get_lanczos", "ddlr_get_lowrank", "ddlr_set_lowrank", "ddlr_profile",

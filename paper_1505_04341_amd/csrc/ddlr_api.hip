@@ -113,6 +113,30 @@ struct DevLock {
     explicit DevLock(int dev) : lk(dev_streams(dev).mu) {}
 };
 
+// Scratch memory of ddlr_apply_noalloc: a file-scope device array, one copy on
+// every GPU the library runs on, held until the process ends.  Host code never
+// passes the array's name to a kernel (on the host it is only a stand-in
+// symbol); scratch_ptr() resolves its address per device with
+// hipGetSymbolAddress, and kernels take that pointer.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+}  // namespace
+static __device__ __align__(256) char scratch[kScratchBytes];
+namespace {
+
+// Device address of `scratch` on device `dev`, which must be current; resolved
+// on the first call per device (ddlr_setup makes that call) and kept.
+char* scratch_ptr(int dev) {
+    static std::mutex mu;
+    static std::map<int, char*> addr;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = addr.find(dev);
+    if (it != addr.end()) return it->second;
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    addr[dev] = static_cast<char*>(p);
+    return static_cast<char*>(p);
+}
+
 int grid_for(int64_t work, int block = 256, int cap = 8192) {
     int64_t g = (work + block - 1) / block;
     if (g < 1) g = 1;
@@ -2073,6 +2097,7 @@ ddlr_status ddlr_setup(const ddlr_csr* A, const int32_t* part, int32_t p, int32_
         if (opt.device >= 0) {
             HIPCHK(hipSetDevice(opt.device));
             DevLock dl(opt.device);
+            (void)scratch_ptr(opt.device);  // ddlr_apply_noalloc's array on this device
             upload_structures(h.get());
             if (h->plan.csolve == 2) {  // Chebyshev scratch, kMaxRhs columns
                 h->cheb_nu = opt.cheb_iters;
@@ -2315,6 +2340,121 @@ ddlr_status ddlr_spmv(ddlr_prec* h, int32_t nrhs, const double* x, int64_t ldx, 
     return run_chunked(h, nrhs, x, ldx, y, ldy, stream, [&](int nr, double* in, double* out, hipStream_t s) {
         spmv_dev(h, nr, in, h->ndev, out, h->ndev, nullptr, s, nullptr);
     });
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------ apply without allocation
+
+namespace {
+
+// Bytes one column of ddlr_apply_noalloc takes in the scratch array, each
+// buffer rounded up to 256 bytes: the gathered input and the output (double),
+// the two A0-solve results a1, a2 and the interface vectors ys, ws (type of the
+// preconditioner), the low-rank reduction partials (kLrBlocks x k doubles) with
+// the k sums and coefficients, and the Chebyshev solver's four vectors.
+size_t noalloc_bytes(const ddlr_prec* h, int nr) {
+    auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t tsz = h->precision == DDLR_FP64 ? sizeof(double) : sizeof(float);
+    const size_t n = (size_t)h->ndev, s = (size_t)h->sdev, k = (size_t)std::max(1, h->k), c = (size_t)nr;
+    size_t b = 2 * up(8 * n * c) + 2 * up(tsz * n * c) + 2 * up(tsz * s * c) + up(8 * kLrBlocks * k * c) +
+               2 * up(8 * k * c);
+    if (h->cheb_nu > 0) b += 4 * up(tsz * n * c);
+    return b;
+}
+
+// Points the apply's temporaries at the scratch array for one chunk of nr
+// columns and restores the handle's own buffers when it goes out of scope.
+// Profiling is off meanwhile (its events would be created on demand).
+struct ScratchView {
+    ddlr_prec* h;
+    void *a1, *a2, *ys, *ws, *ct, *cr, *cd, *cx;
+    double *part, *lrsum, *coef;
+    bool prof;
+    double *in = nullptr, *out = nullptr;
+    ScratchView(ddlr_prec* h_, char* base, int nr) : h(h_) {
+        Workspace& W = h->ws;
+        a1 = W.a1, a2 = W.a2, ys = W.ys, ws = W.ws, part = W.part, lrsum = W.lrsum, coef = W.coef;
+        ct = h->ch_t, cr = h->ch_r, cd = h->ch_d, cx = h->ch_x;
+        prof = h->prof;
+        auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+        const size_t tsz = h->precision == DDLR_FP64 ? sizeof(double) : sizeof(float);
+        const size_t n = (size_t)h->ndev, s = (size_t)h->sdev, k = (size_t)std::max(1, h->k), c = (size_t)nr;
+        char* p = base;
+        auto take = [&](size_t b) {
+            char* q = p;
+            p += up(b);
+            return q;
+        };
+        in = (double*)take(8 * n * c);
+        out = (double*)take(8 * n * c);
+        W.a1 = take(tsz * n * c);
+        W.a2 = take(tsz * n * c);
+        W.ys = take(tsz * s * c);
+        W.ws = take(tsz * s * c);
+        W.part = (double*)take(8 * kLrBlocks * k * c);
+        W.lrsum = (double*)take(8 * k * c);
+        W.coef = (double*)take(8 * k * c);
+        if (h->cheb_nu > 0) {
+            h->ch_t = take(tsz * n * c);
+            h->ch_r = take(tsz * n * c);
+            h->ch_d = take(tsz * n * c);
+            h->ch_x = take(tsz * n * c);
+        }
+        h->prof = false;
+    }
+    ~ScratchView() {
+        Workspace& W = h->ws;
+        W.a1 = a1, W.a2 = a2, W.ys = ys, W.ws = ws, W.part = part, W.lrsum = lrsum, W.coef = coef;
+        h->ch_t = ct, h->ch_r = cr, h->ch_d = cd, h->ch_x = cx;
+        h->prof = prof;
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+ddlr_status ddlr_apply_noalloc(ddlr_prec* h, int32_t nrhs, const double* x, int64_t ldx, double* y, int64_t ldy,
+                               void* stream) {
+    ddlr_status st = check_vec(h, nrhs, x, ldx, y, ldy);
+    if (st != DDLR_OK) return st;
+    if (nrhs == 0) return DDLR_OK;
+    try {
+        int cur = -1;
+        HIPCHK(hipGetDevice(&cur));
+        if (cur != h->device) HIPCHK(hipSetDevice(h->device));
+        DevLock dl(h->device);
+        char* base = scratch_ptr(h->device);
+        size_t cap = kScratchBytes;
+        if (const char* env = std::getenv("DDLR_NOALLOC_CAP")) {  // may only lower the usable size
+            const long long c = std::atoll(env);
+            if (c >= 0 && (size_t)c < cap) cap = (size_t)c;
+        }
+        int nr = std::min<int>(kMaxRhs, nrhs);
+        while (nr > 0 && noalloc_bytes(h, nr) > cap) --nr;
+        if (nr == 0) {
+            g_err = "ddlr_apply_noalloc: one column needs " + std::to_string(noalloc_bytes(h, 1)) +
+                    " bytes of scratch; the library's scratch array holds " + std::to_string(cap);
+            return DDLR_E_INVALID;
+        }
+        hipStream_t sm = (hipStream_t)stream;
+        const int64_t n = h->ndev;
+        for (int32_t c0 = 0; c0 < nrhs; c0 += nr) {
+            const int w = std::min<int>(nr, nrhs - c0);
+            ScratchView v(h, base, w);
+            hipLaunchKernelGGL((k_gather<double, double>), grid2(n, w), dim3(256), 0, sm, n, w, h->perm_dev,
+                               x + c0 * ldx, ldx, v.in, n);
+            LAUNCHCHK();
+            apply_dev(h, w, v.in, n, v.out, n, sm, nullptr);
+            hipLaunchKernelGGL((k_scatter<double, double>), grid2(n, w), dim3(256), 0, sm, n, w, h->perm_dev, v.out,
+                               n, y + c0 * ldy, ldy);
+            LAUNCHCHK();
+        }
+    } catch (const SetupError& e) {
+        return fail_status(e);
+    }
+    return DDLR_OK;
 }
 
 }  // extern "C"
