@@ -158,6 +158,25 @@ typedef struct {
 
 typedef struct ddlr_prec ddlr_prec;
 
+/* A context: the device that handles created in it run on and a budget of
+ * device memory (HBM) that all of their allocations share.  The problem
+ * statement (Sec. 2.1) places one linear system on one machine; a context is
+ * that machine's share: device ordinal (-1: host-only handles, setup and
+ * factors without device work) and budget in bytes (0 = unlimited).  Every
+ * device allocation of a handle in the context -- matrix, factors, U_k,
+ * Lanczos basis, solver workspaces grown later -- is counted while it lives;
+ * one that would exceed the budget fails with DDLR_E_BUDGET (a failing setup
+ * frees what it took, *out = NULL).  ddlr_ctx_destroy may be called while
+ * handles of the context still exist: the context is freed when the last of
+ * them is destroyed.  Errors: DDLR_E_INVALID (null out, device < -1),
+ * DDLR_E_DEVICE (no such device). */
+typedef struct ddlr_ctx ddlr_ctx;
+ddlr_status ddlr_ctx_create(int32_t device, size_t hbm_budget_bytes, ddlr_ctx **out);
+/* Bytes currently allocated by the context's handles, the most ever held at
+ * once, and the budget (0 = unlimited).  Any output may be NULL. */
+ddlr_status ddlr_ctx_usage(const ddlr_ctx *ctx, size_t *used, size_t *peak, size_t *budget);
+void ddlr_ctx_destroy(ddlr_ctx *ctx);
+
 /* Library version (major*100 + minor). */
 int32_t ddlr_version(void);
 
@@ -174,14 +193,59 @@ void ddlr_solve_options_default(ddlr_solve_options *opt);
  *  4. runs `lanczos_steps` Lanczos steps with full reorthogonalisation on
  *     E^T A0^{-1} E (DDLR-1) or E^T A0^{-2} E (DDLR-2) (Sec. 4.4 (sec:Lan)) and forms
  *     U_k with G_{k,theta}^{-1} (eq. gkt) or H_k (Lemma on H_k).
+ * ctx: context (device and memory budget; its device replaces opt->device), or
+ * NULL for opt->device and no budget.
  * A: host CSR (copied); part: host int32[n] with values in [0,p) (copied);
  * k: rank (ignored for DDLR_VARIANT_A0; 1 <= k < number of interface unknowns).
  * Errors: DDLR_E_INVALID, DDLR_E_NOT_SYMMETRIC, DDLR_E_BREAKDOWN (message names
  * the row), DDLR_E_LANCZOS, DDLR_E_NOT_SPD (theta >= 1 or I - U_k^T E V_k not
- * SPD), DDLR_E_OOM, DDLR_E_DEVICE.  On failure *out is NULL and nothing leaks.
+ * SPD), DDLR_E_OOM, DDLR_E_BUDGET (the context's budget), DDLR_E_DEVICE.  On
+ * failure *out is NULL and nothing leaks.
  */
-ddlr_status ddlr_setup(const ddlr_csr *A, const int32_t *part, int32_t p, int32_t k, int32_t variant,
-                       const ddlr_options *opt, ddlr_prec **out);
+ddlr_status ddlr_setup(ddlr_ctx *ctx, const ddlr_csr *A, const int32_t *part, int32_t p, int32_t k,
+                       int32_t variant, const ddlr_options *opt, ddlr_prec **out);
+
+/* Saving and restoring a built preconditioner (the computed data that Sec.
+ * 4.7, sec:improv, keeps and reuses).  ddlr_export_setup writes to `path`
+ * everything the build computed from A and the partition: the ordering of
+ * step 1 (perm, block offsets, interface colours), the local factors (strict
+ * lower L in internal order as CSR, and D), the level of every row, the
+ * approximate inverse X of C_alpha or the Chebyshev interval when those
+ * solvers are used, and the low-rank part (U_k in user order with
+ * lambda_1..lambda_k and theta, or H_k).  ddlr_import_setup rebuilds a handle
+ * from A and such a file without classifying, factoring or running Lanczos;
+ * the result applies the same operator as the exported handle.  A file written
+ * by another program with the same layout (e.g. another implementation of
+ * the same build) is accepted after these checks: perm is a permutation; the interiors
+ * of different blocks are not coupled in A; L is strictly lower with sorted
+ * columns inside its row's block; pivots are finite and nonzero; stored levels,
+ * if present, equal the schedule recomputed from L.
+ *
+ * File layout (little-endian): the 8 bytes "DDLRSET1", int32 version (1),
+ * int32 record count, then per record: 16-byte NUL-padded name, int32 type (1
+ * int32, 2 int64, 3 float64), int32 0, int64 element count, the elements.
+ * Records: "n_p" int64 {n, p}; "alpha" f64 {alpha}; "csolve_prec_nu" int32
+ * {ddlr_csolve, ddlr_precision, Chebyshev steps}; "perm" int32[n] (internal
+ * position -> user row: interiors of blocks 0..p-1, then the interface);
+ * "boff" int64[p+2] (block starts, boff[p] = interior count, boff[p+1] = n);
+ * "colour" int32[s]; "L.rowptr" int64[n+1], "L.col" int32, "L.val" f64 (strict
+ * lower, internal order); "D" f64[n]; optional "level" int32[n]; with
+ * DDLR_CSOLVE_MR "X.rowptr" int64[s+1], "X.col" int32, "X.val" f64 (interface
+ * positions), "X.cert" f64 {||I - C_alpha X||_inf, SPD flag} and "X.res" f64
+ * (||I - C_alpha X_j||_F for j = 0..steps, as ddlr_get_cinv returns); with
+ * DDLR_CSOLVE_CHEB "cheb" f64 {lo, hi, smallest Ritz, largest Ritz}; with a
+ * low-rank part "lowrank" int32 {variant, k}, "U" f64[n*k] (user order,
+ * column-major) and "aux" f64 (DDLR-1: lambda_1..lambda_k, theta; DDLR-2:
+ * H_k column-major), the layout of ddlr_get_lowrank.
+ *
+ * Export: any handle (host-only handles have no low-rank part).  Import: ctx
+ * as in ddlr_setup (NULL: device 0, no budget); the precision is the stored
+ * one; a host-only context ignores the low-rank records.  Errors:
+ * DDLR_E_INVALID (IO error, bad file, data that fail the checks above, another
+ * matrix order), DDLR_E_OOM, DDLR_E_BUDGET, DDLR_E_DEVICE.  On failure *out is
+ * NULL and nothing leaks. */
+ddlr_status ddlr_export_setup(const ddlr_prec *h, const char *path);
+ddlr_status ddlr_import_setup(ddlr_ctx *ctx, const ddlr_csr *A, const char *path, ddlr_prec **out);
 
 /* y = M^{-1} x for nrhs columns.  DDLR-1: eq. (Mprec) with G_{k,theta}^{-1}
  * of eq. (gkt), evaluated with two A0 solves as in Algorithm alg:prec1

@@ -112,7 +112,12 @@ def load_library(path: str = LIB_PATH):
         "ddlr_version": (I32, []),
         "ddlr_options_default": (None, [P]),
         "ddlr_solve_options_default": (None, [P]),
-        "ddlr_setup": (I32, [P, P, I32, I32, I32, P, P]),
+        "ddlr_setup": (I32, [P, P, P, I32, I32, I32, P, P]),
+        "ddlr_ctx_create": (I32, [I32, C.c_size_t, P]),
+        "ddlr_ctx_usage": (I32, [P, P, P, P]),
+        "ddlr_ctx_destroy": (None, [P]),
+        "ddlr_export_setup": (I32, [P, C.c_char_p]),
+        "ddlr_import_setup": (I32, [P, P, C.c_char_p, P]),
         "ddlr_apply": (I32, [P, I32, P, I64, P, I64, P]),
         "ddlr_apply_noalloc": (I32, [P, I32, P, I64, P, I64, P]),
         "ddlr_a0_solve": (I32, [P, I32, P, I64, P, I64, P]),
@@ -187,13 +192,43 @@ def _dev_cols(t, n: int):
     return C.c_void_p(t.data_ptr()), t.shape[0], n
 
 
-class Prec:
-    """Handle of a built preconditioner (ddlr_prec*)."""
+class Ctx:
+    """Handle of a context (ddlr_ctx*): device and device-memory budget."""
 
-    def __init__(self, handle: int, n: int, keep=()):
+    def __init__(self, handle: int):
+        self._h = C.c_void_p(handle)
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.ddlr_ctx_destroy(self._h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+
+def ddlr_ctx_create(device: int = 0, hbm_budget_bytes: int = 0) -> Ctx:
+    h = C.c_void_p()
+    _check(load_library().ddlr_ctx_create(int(device), int(hbm_budget_bytes), C.byref(h)), "ddlr_ctx_create")
+    return Ctx(h.value)
+
+
+def ddlr_ctx_usage(ctx: Ctx) -> dict:
+    used, peak, budget = C.c_size_t(), C.c_size_t(), C.c_size_t()
+    _check(load_library().ddlr_ctx_usage(ctx.handle, C.byref(used), C.byref(peak), C.byref(budget)),
+           "ddlr_ctx_usage")
+    return dict(used=used.value, peak=peak.value, budget=budget.value)
+
+
+class Prec:
+    """Handle of a built preconditioner (ddlr_prec*); keeps its context alive."""
+
+    def __init__(self, handle: int, n: int, keep=(), ctx=None):
         self._h = C.c_void_p(handle)
         self.n = n
         self._keep = keep
+        self._ctx = ctx
 
     def __del__(self):
         if getattr(self, "_h", None) and _lib is not None:
@@ -210,8 +245,10 @@ def ddlr_setup(A, part, p: int, k: int, variant: int = DDLR_1, *, alpha: float =
                precision: int = FP64, device: int = 0, seed: int = 0, lanczos_start=None,
                autotune: bool = True, lanczos_check: int = 0, lanczos_max: int = 0, lanczos_tol: float = 0.0,
                csolve: int = CSOLVE_FACTOR, cinv_iters: int = 3, cinv_tol: float = 0.01, cinv_lfil: int = 20,
-               lowrank_build: int = BUILD_LANCZOS, cheb_iters: int = 5, cheb_lanczos: int = 10) -> Prec:
-    """Builds the preconditioner. A: object with n, rowptr (int64), col (int32), val (float64)."""
+               lowrank_build: int = BUILD_LANCZOS, cheb_iters: int = 5, cheb_lanczos: int = 10,
+               ctx: "Ctx | None" = None) -> Prec:
+    """Builds the preconditioner. A: object with n, rowptr (int64), col (int32), val (float64).
+    ctx: a context (its device replaces `device`) or None."""
     lib = load_library()
     rp = np.ascontiguousarray(A.rowptr, dtype=np.int64)
     ci = np.ascontiguousarray(A.col, dtype=np.int32)
@@ -234,9 +271,27 @@ def ddlr_setup(A, part, p: int, k: int, variant: int = DDLR_1, *, alpha: float =
         v0 = np.ascontiguousarray(lanczos_start, dtype=np.float64)
         opt.lanczos_start = v0.ctypes.data
     h = C.c_void_p()
-    st = lib.ddlr_setup(C.byref(csr), _ptr(pa), int(p), int(k), int(variant), C.byref(opt), C.byref(h))
+    st = lib.ddlr_setup(ctx.handle if ctx is not None else None, C.byref(csr), _ptr(pa), int(p), int(k),
+                        int(variant), C.byref(opt), C.byref(h))
     _check(st, "ddlr_setup")
-    return Prec(h.value, int(A.n))
+    return Prec(h.value, int(A.n), ctx=ctx)
+
+
+def ddlr_export_setup(prec: Prec, path: str) -> None:
+    _check(load_library().ddlr_export_setup(prec.handle, os.fsencode(path)), "ddlr_export_setup")
+
+
+def ddlr_import_setup(A, path: str, ctx: "Ctx | None" = None) -> Prec:
+    """Rebuilds a preconditioner for A from a file of ddlr_export_setup's layout."""
+    lib = load_library()
+    rp = np.ascontiguousarray(A.rowptr, dtype=np.int64)
+    ci = np.ascontiguousarray(A.col, dtype=np.int32)
+    va = np.ascontiguousarray(A.val, dtype=np.float64)
+    csr = ddlr_csr(int(A.n), rp.ctypes.data, ci.ctypes.data, va.ctypes.data)
+    h = C.c_void_p()
+    _check(lib.ddlr_import_setup(ctx.handle if ctx is not None else None, C.byref(csr), os.fsencode(path),
+                                 C.byref(h)), "ddlr_import_setup")
+    return Prec(h.value, int(A.n), ctx=ctx)
 
 
 def _vec_op(name: str, prec: Prec, x, y, stream):
@@ -549,7 +604,8 @@ def ddlr_version() -> int:
 
 
 EXPORTED = ["ddlr_version", "ddlr_options_default", "ddlr_solve_options_default", "ddlr_setup", "ddlr_apply",
-            "ddlr_apply_noalloc",
+            "ddlr_apply_noalloc", "ddlr_ctx_create", "ddlr_ctx_usage", "ddlr_ctx_destroy", "ddlr_export_setup",
+            "ddlr_import_setup",
             "ddlr_a0_solve", "ddlr_spmv", "ddlr_solve", "ddlr_query", "ddlr_get_ordering", "ddlr_get_factor",
             "ddlr_get_cinv",
             "ddlr_get_levels", "ddlr_get_lanczos", "ddlr_get_lowrank", "ddlr_set_lowrank", "ddlr_profile",

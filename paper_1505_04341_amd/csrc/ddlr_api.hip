@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -43,16 +44,44 @@ constexpr int kProfClasses = 4;
 
 #define LAUNCHCHK() HIPCHK(hipGetLastError())
 
-// Device allocation owned by a handle.
+// Device-memory budget of a context: every allocation of a handle created in
+// the context is counted while it lives; limit 0 means unlimited.
+struct Budget {
+    std::mutex mu;
+    size_t limit = 0, used = 0, peak = 0;
+    void take(size_t b) {
+        std::lock_guard<std::mutex> lk(mu);
+        if (limit && used + b > limit)
+            throw SetupError{DDLR_E_BUDGET, "device memory budget exceeded: " + std::to_string(used) + " + " +
+                                                std::to_string(b) + " > " + std::to_string(limit) + " bytes"};
+        used += b;
+        peak = std::max(peak, used);
+    }
+    void give(size_t b) {
+        std::lock_guard<std::mutex> lk(mu);
+        used -= std::min(used, b);
+    }
+};
+
+// Device allocation owned by a handle (counted in its context's budget, if any).
 struct DMem {
     std::vector<void*> ptrs;
     size_t bytes = 0;
+    Budget* budget = nullptr;
     template <typename T> T* alloc(size_t count) {
         void* p = nullptr;
         if (count == 0) count = 1;
-        HIPCHK(hipMalloc(&p, count * sizeof(T)));
+        const size_t b = count * sizeof(T);
+        if (budget) budget->take(b);
+        const hipError_t e = hipMalloc(&p, b);
+        if (e != hipSuccess) {
+            if (budget) budget->give(b);
+            (void)hipGetLastError();
+            throw SetupError{e == hipErrorOutOfMemory ? DDLR_E_OOM : DDLR_E_DEVICE,
+                             "hipMalloc of " + std::to_string(b) + " bytes: " + hipGetErrorString(e)};
+        }
         ptrs.push_back(p);
-        bytes += count * sizeof(T);
+        bytes += b;
         return static_cast<T*>(p);
     }
     template <typename T> T* upload(const std::vector<T>& h) {
@@ -63,6 +92,7 @@ struct DMem {
     void release() {
         for (void* p : ptrs) (void)hipFree(p);
         ptrs.clear();
+        if (budget) budget->give(bytes);
         bytes = 0;
     }
 };
@@ -195,8 +225,18 @@ struct Workspace {
 
 }  // namespace
 
+// A device and a device-memory budget shared by the handles created in it
+// (ddlr_ctx_create).  Freed when the context is destroyed and its last handle
+// is gone.
+struct ddlr_ctx {
+    int device = 0;
+    Budget budget;
+    std::atomic<int> refs{1};  // the context itself plus every live handle
+};
+
 struct ddlr_prec {
     HostPlan plan;
+    ddlr_ctx* ctx = nullptr;  // context whose budget counts this handle's memory (NULL: none)
     int device = -1;
     int variant = 0, k = 0, precision = 0, msteps = 0, spd = 0;
     // Proposition (SPD-ness of DDLR-1) assumes A0 SPD: with indefinite local
@@ -305,6 +345,21 @@ struct ddlr_prec {
 };
 
 namespace {
+
+Budget* budget_of(const ddlr_prec* h) { return h->ctx ? &h->ctx->budget : nullptr; }
+
+// Counts every device allocation of h in ctx's budget from now on.
+void attach_ctx(ddlr_prec* h, ddlr_ctx* ctx) {
+    if (!ctx) return;
+    h->ctx = ctx;
+    ctx->refs.fetch_add(1);
+    Budget* b = &ctx->budget;
+    for (DMem* m : {&h->mem, &h->lrmem, &h->ws.mem, &h->ws.gmem, &h->lrun.mem, &h->chmem}) m->budget = b;
+}
+
+void ctx_unref(ddlr_ctx* ctx) {
+    if (ctx && ctx->refs.fetch_sub(1) == 1) delete ctx;
+}
 
 // ------------------------------------------------------------ device upload
 
@@ -1488,6 +1543,7 @@ void lanczos_reserve(ddlr_prec* h, int cap) {
     if (cap <= R.cap) return;
     const int64_t n = h->plan.n, s = h->plan.s;
     DMem nm;
+    nm.budget = budget_of(h);
     double* Q = nm.alloc<double>((size_t)s * (cap + 1));
     double* al = nm.alloc<double>(cap);
     double* be = nm.alloc<double>(cap);
@@ -1748,6 +1804,7 @@ void lanczos_finish(ddlr_prec* h, int k, int theta_mode) {
     h->theta_mode = theta_mode;
     drop_graphs(h);  // captured kernels hold the low-rank pointers
     DMem tmp;
+    tmp.budget = budget_of(h);
     if (meff < k + 1)
         throw SetupError{DDLR_E_LANCZOS, "Lanczos broke down after " + std::to_string(meff) + " steps (k+1 = " +
                                              std::to_string(k + 1) + " needed)"};
@@ -1835,6 +1892,7 @@ void gk_build(ddlr_prec* h, int k, int m, const double* v0_user, uint64_t seed) 
     LanczosRun& R = h->lrun;
     hipStream_t st = nullptr;
     DMem tmp;
+    tmp.budget = budget_of(h);
     double* Qb = tmp.alloc<double>((size_t)s * (m + 1));
     double* Pb = tmp.alloc<double>((size_t)n * m);
     double* al = tmp.alloc<double>(m);
@@ -1998,6 +2056,48 @@ void release_streams(ddlr_prec* h) {
     h->ev_fork = h->ev_join = nullptr;
 }
 
+// Device part of a build once the host plan exists: scratch address, device
+// structures, Chebyshev vectors, launch options and streams.  The device is
+// current and its lock held.
+void device_init(ddlr_prec* h, int cheb_iters, int no_autotune) {
+    (void)scratch_ptr(h->device);  // ddlr_apply_noalloc's array on this device
+    upload_structures(h);
+    if (h->plan.csolve == 2) {  // Chebyshev scratch, kMaxRhs columns
+        h->cheb_nu = cheb_iters;
+        const size_t tsz = h->precision == DDLR_FP64 ? sizeof(double) : sizeof(float);
+        const size_t bytes = tsz * (size_t)h->plan.n * kMaxRhs;
+        h->ch_t = h->chmem.alloc<char>(bytes);
+        h->ch_r = h->chmem.alloc<char>(bytes);
+        h->ch_d = h->chmem.alloc<char>(bytes);
+        h->ch_x = h->chmem.alloc<char>(bytes);
+    }
+    if (const char* env = std::getenv("DDLR_NO_OVERLAP")) h->overlap = env[0] != '1';
+    h->tune_mode = no_autotune ? 0 : 1;
+    if (const char* env = std::getenv("DDLR_CG_GRAPH")) h->graph_mode = env[0] == '0' ? 0 : env[0] == '1' ? 1 : 2;
+    if (const char* env = std::getenv("DDLR_LEVEL_KERNEL"))  // "rows" / "cols" force one form
+        h->level_kernel = env[0] == 'r' ? 1 : env[0] == 'c' ? 2 : 0;
+    if (has_cpart(h)) {
+        h->side = dev_streams(h->device).side;
+        HIPCHK(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
+    }
+    ensure_cg_streams(h);
+}
+
+// Frees what a handle that failed to build holds and leaves its context.
+void discard_handle(ddlr_prec* h) {
+    if (h->device >= 0) (void)hipDeviceSynchronize();
+    release_streams(h);
+    h->ws.mem.release();
+    h->ws.gmem.release();
+    h->lrmem.release();
+    h->lrun.mem.release();
+    h->chmem.release();
+    h->mem.release();
+    ctx_unref(h->ctx);
+    h->ctx = nullptr;
+}
+
 ddlr_status fail_status(const SetupError& e) {
     g_err = e.msg;
     return (ddlr_status)e.status;
@@ -2052,7 +2152,7 @@ void ddlr_solve_options_default(ddlr_solve_options* o) {
     o->rtol = 1e-6;
 }
 
-ddlr_status ddlr_setup(const ddlr_csr* A, const int32_t* part, int32_t p, int32_t k, int32_t variant,
+ddlr_status ddlr_setup(ddlr_ctx* ctx, const ddlr_csr* A, const int32_t* part, int32_t p, int32_t k, int32_t variant,
                        const ddlr_options* opt_in, ddlr_prec** out) {
     if (out) *out = nullptr;
     if (!A || !part || !out) {
@@ -2062,7 +2162,9 @@ ddlr_status ddlr_setup(const ddlr_csr* A, const int32_t* part, int32_t p, int32_
     ddlr_options opt;
     if (opt_in) opt = *opt_in;
     else ddlr_options_default(&opt);
+    if (ctx) opt.device = ctx->device;
     std::unique_ptr<ddlr_prec> h(new ddlr_prec());
+    attach_ctx(h.get(), ctx);
     auto t0 = std::chrono::steady_clock::now();
     try {
         if (variant < 0 || variant > 2) throw SetupError{DDLR_E_INVALID, "variant must be 0, 1 or 2"};
@@ -2094,31 +2196,11 @@ ddlr_status ddlr_setup(const ddlr_csr* A, const int32_t* part, int32_t p, int32_
                 throw SetupError{DDLR_E_INVALID, "k must satisfy 1 <= k, k+1 <= s and k <= 128"};
         }
         h->device = opt.device;
+        if (h->plan.csolve == 2) h->cheb_nu = opt.cheb_iters;
         if (opt.device >= 0) {
             HIPCHK(hipSetDevice(opt.device));
             DevLock dl(opt.device);
-            (void)scratch_ptr(opt.device);  // ddlr_apply_noalloc's array on this device
-            upload_structures(h.get());
-            if (h->plan.csolve == 2) {  // Chebyshev scratch, kMaxRhs columns
-                h->cheb_nu = opt.cheb_iters;
-                const size_t tsz = h->precision == DDLR_FP64 ? sizeof(double) : sizeof(float);
-                const size_t bytes = tsz * (size_t)h->plan.n * kMaxRhs;
-                h->ch_t = h->chmem.alloc<char>(bytes);
-                h->ch_r = h->chmem.alloc<char>(bytes);
-                h->ch_d = h->chmem.alloc<char>(bytes);
-                h->ch_x = h->chmem.alloc<char>(bytes);
-            }
-            if (const char* env = std::getenv("DDLR_NO_OVERLAP")) h->overlap = env[0] != '1';
-            h->tune_mode = opt.no_autotune ? 0 : 1;
-            if (const char* env = std::getenv("DDLR_CG_GRAPH")) h->graph_mode = env[0] == '0' ? 0 : env[0] == '1' ? 1 : 2;
-            if (const char* env = std::getenv("DDLR_LEVEL_KERNEL"))  // "rows" / "cols" force one form
-                h->level_kernel = env[0] == 'r' ? 1 : env[0] == 'c' ? 2 : 0;
-            if (has_cpart(h.get())) {
-                h->side = dev_streams(opt.device).side;
-                HIPCHK(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
-                HIPCHK(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
-            }
-            ensure_cg_streams(h.get());
+            device_init(h.get(), opt.cheb_iters, opt.no_autotune);
             if (variant != 0) {
                 // fixed m steps (default 2k), or the paper's control: at most
                 // lanczos_max steps (default 5k), stopped by eq. (converge)
@@ -2150,20 +2232,10 @@ ddlr_status ddlr_setup(const ddlr_csr* A, const int32_t* part, int32_t p, int32_
             h->k = 0;
         }
     } catch (const SetupError& e) {
-        release_streams(h.get());
-        h->ws.mem.release();
-        h->lrmem.release();
-        h->lrun.mem.release();
-        h->chmem.release();
-        h->mem.release();
+        discard_handle(h.get());
         return fail_status(e);
     } catch (const std::bad_alloc&) {
-        release_streams(h.get());
-        h->ws.mem.release();
-        h->lrmem.release();
-        h->lrun.mem.release();
-        h->chmem.release();
-        h->mem.release();
+        discard_handle(h.get());
         g_err = "host out of memory";
         return DDLR_E_OOM;
     }
@@ -3043,6 +3115,296 @@ ddlr_status ddlr_set_lowrank(ddlr_prec* h, int32_t variant, int32_t k, const dou
     return DDLR_OK;
 }
 
+}  // extern "C"
+
+// ------------------------------------------------------------ setup files
+
+namespace {
+
+// One array of a setup file: name (at most 15 characters), element type
+// (1 int32, 2 int64, 3 float64) and the elements.
+struct SetupRec {
+    int32_t type = 0;
+    int64_t count = 0;
+    std::vector<char> data;
+};
+constexpr char kSetupMagic[8] = {'D', 'D', 'L', 'R', 'S', 'E', 'T', '1'};
+
+size_t rec_elem(int32_t type) { return type == 1 ? 4 : 8; }
+
+template <typename T> int32_t rec_type();
+template <> int32_t rec_type<int32_t>() { return 1; }
+template <> int32_t rec_type<int64_t>() { return 2; }
+template <> int32_t rec_type<double>() { return 3; }
+
+template <typename T> void rec_put(std::map<std::string, SetupRec>& R, const char* name, const T* p, size_t count) {
+    SetupRec& r = R[name];
+    r.type = rec_type<T>();
+    r.count = (int64_t)count;
+    r.data.resize(count * sizeof(T));
+    if (count) std::memcpy(r.data.data(), p, count * sizeof(T));
+}
+
+template <typename T> std::vector<T> rec_get(const std::map<std::string, SetupRec>& R, const char* name,
+                                            int64_t want = -1) {
+    auto it = R.find(name);
+    if (it == R.end()) throw SetupError{DDLR_E_INVALID, std::string("setup file lacks the array ") + name};
+    const SetupRec& r = it->second;
+    if (r.type != rec_type<T>() || (want >= 0 && r.count != want))
+        throw SetupError{DDLR_E_INVALID, std::string("setup file array ") + name + " has the wrong type or length"};
+    std::vector<T> out((size_t)r.count);
+    if (r.count) std::memcpy(out.data(), r.data.data(), (size_t)r.count * sizeof(T));
+    return out;
+}
+
+void write_setup_file(const char* path, const std::map<std::string, SetupRec>& R) {
+    FILE* f = std::fopen(path, "wb");
+    if (!f) throw SetupError{DDLR_E_INVALID, std::string("cannot open ") + path + " for writing"};
+    bool ok = std::fwrite(kSetupMagic, 1, 8, f) == 8;
+    const int32_t head[2] = {1, (int32_t)R.size()};
+    ok = ok && std::fwrite(head, sizeof(head), 1, f) == 1;
+    for (const auto& kv : R) {
+        char name[16] = {0};
+        std::strncpy(name, kv.first.c_str(), 15);
+        const int32_t tr[2] = {kv.second.type, 0};
+        ok = ok && std::fwrite(name, 1, 16, f) == 16 && std::fwrite(tr, sizeof(tr), 1, f) == 1 &&
+             std::fwrite(&kv.second.count, sizeof(int64_t), 1, f) == 1;
+        if (!kv.second.data.empty())
+            ok = ok && std::fwrite(kv.second.data.data(), 1, kv.second.data.size(), f) == kv.second.data.size();
+    }
+    ok = (std::fclose(f) == 0) && ok;
+    if (!ok) throw SetupError{DDLR_E_INVALID, std::string("write error on ") + path};
+}
+
+std::map<std::string, SetupRec> read_setup_file(const char* path) {
+    FILE* f = std::fopen(path, "rb");
+    if (!f) throw SetupError{DDLR_E_INVALID, std::string("cannot open ") + path};
+    std::map<std::string, SetupRec> R;
+    auto bad = [&](const char* what) {
+        std::fclose(f);
+        return SetupError{DDLR_E_INVALID, std::string(path) + ": " + what};
+    };
+    char magic[8];
+    int32_t head[2];
+    if (std::fread(magic, 1, 8, f) != 8 || std::memcmp(magic, kSetupMagic, 8) != 0) throw bad("not a DDLR setup file");
+    if (std::fread(head, sizeof(head), 1, f) != 1 || head[0] != 1 || head[1] < 0) throw bad("unsupported version");
+    std::fseek(f, 0, SEEK_END);
+    const long fsize = std::ftell(f);
+    std::fseek(f, 16, SEEK_SET);
+    for (int32_t q = 0; q < head[1]; ++q) {
+        char name[17] = {0};
+        int32_t tr[2];
+        int64_t count = 0;
+        if (std::fread(name, 1, 16, f) != 16 || std::fread(tr, sizeof(tr), 1, f) != 1 ||
+            std::fread(&count, sizeof(count), 1, f) != 1)
+            throw bad("truncated record header");
+        if (tr[0] < 1 || tr[0] > 3 || count < 0) throw bad("bad record type or count");
+        const size_t bytes = (size_t)count * rec_elem(tr[0]);
+        if ((long)bytes > fsize - std::ftell(f)) throw bad("record longer than the file");
+        SetupRec& r = R[name];
+        r.type = tr[0];
+        r.count = count;
+        r.data.resize(bytes);
+        if (bytes && std::fread(r.data.data(), 1, bytes, f) != bytes) throw bad("truncated record");
+    }
+    std::fclose(f);
+    return R;
+}
+
+}  // namespace
+
+extern "C" {
+
+ddlr_status ddlr_ctx_create(int32_t device, size_t hbm_budget_bytes, ddlr_ctx** out) {
+    if (!out) {
+        g_err = "null argument";
+        return DDLR_E_INVALID;
+    }
+    *out = nullptr;
+    if (device < -1) {
+        g_err = "device must be a HIP device ordinal or -1 (host only)";
+        return DDLR_E_INVALID;
+    }
+    if (device >= 0) {
+        int count = 0;
+        if (hipGetDeviceCount(&count) != hipSuccess || device >= count) {
+            (void)hipGetLastError();
+            g_err = "no HIP device " + std::to_string(device);
+            return DDLR_E_DEVICE;
+        }
+    }
+    ddlr_ctx* c = new ddlr_ctx();
+    c->device = device;
+    c->budget.limit = hbm_budget_bytes;
+    *out = c;
+    return DDLR_OK;
+}
+
+ddlr_status ddlr_ctx_usage(const ddlr_ctx* ctx, size_t* used, size_t* peak, size_t* budget) {
+    if (!ctx) {
+        g_err = "null context";
+        return DDLR_E_INVALID;
+    }
+    ddlr_ctx* c = const_cast<ddlr_ctx*>(ctx);
+    std::lock_guard<std::mutex> lk(c->budget.mu);
+    if (used) *used = c->budget.used;
+    if (peak) *peak = c->budget.peak;
+    if (budget) *budget = c->budget.limit;
+    return DDLR_OK;
+}
+
+void ddlr_ctx_destroy(ddlr_ctx* ctx) { ctx_unref(ctx); }
+
+ddlr_status ddlr_export_setup(const ddlr_prec* h, const char* path) {
+    if (!h || !path) {
+        g_err = "null argument";
+        return DDLR_E_INVALID;
+    }
+    try {
+        const HostPlan& P = h->plan;
+        std::map<std::string, SetupRec> R;
+        const int64_t np[2] = {P.n, P.p};
+        rec_put(R, "n_p", np, 2);
+        const double alpha = P.alpha;
+        rec_put(R, "alpha", &alpha, 1);
+        const int32_t flags[3] = {P.csolve, h->precision, h->cheb_nu};
+        rec_put(R, "csolve_prec_nu", flags, 3);
+        rec_put(R, "perm", P.perm.data(), P.perm.size());
+        rec_put(R, "boff", P.boff.data(), P.boff.size());
+        rec_put(R, "colour", P.colour.data(), P.colour.size());
+        rec_put(R, "L.rowptr", P.L.rp.data(), P.L.rp.size());
+        rec_put(R, "L.col", P.L.ci.data(), P.L.ci.size());
+        rec_put(R, "L.val", P.L.v.data(), P.L.v.size());
+        rec_put(R, "D", P.D.data(), P.D.size());
+        rec_put(R, "level", P.level.data(), P.level.size());
+        if (P.csolve == 1) {
+            rec_put(R, "X.rowptr", P.X.rp.data(), P.X.rp.size());
+            rec_put(R, "X.col", P.X.ci.data(), P.X.ci.size());
+            rec_put(R, "X.val", P.X.v.data(), P.X.v.size());
+            const double xi[2] = {P.x_rinf, P.x_spd ? 1.0 : 0.0};
+            rec_put(R, "X.cert", xi, 2);
+            rec_put(R, "X.res", P.x_res.data(), P.x_res.size());
+        }
+        if (P.csolve == 2) {
+            const double ch[4] = {P.ch_lo, P.ch_hi, P.ch_rlo, P.ch_rhi};
+            rec_put(R, "cheb", ch, 4);
+        }
+        if (h->device >= 0 && h->variant != 0 && h->k > 0) {
+            const int k = h->k;
+            std::vector<double> U((size_t)P.n * k), aux(h->variant == DDLR_1 ? (size_t)k + 1 : (size_t)k * k);
+            ddlr_status st = ddlr_get_lowrank(h, U.data(), aux.data());
+            if (st != DDLR_OK) return st;
+            const int32_t vk[2] = {h->variant, k};
+            rec_put(R, "lowrank", vk, 2);
+            rec_put(R, "U", U.data(), U.size());
+            rec_put(R, "aux", aux.data(), aux.size());
+        }
+        write_setup_file(path, R);
+    } catch (const SetupError& e) {
+        return fail_status(e);
+    } catch (const std::bad_alloc&) {
+        g_err = "host out of memory";
+        return DDLR_E_OOM;
+    }
+    return DDLR_OK;
+}
+
+ddlr_status ddlr_import_setup(ddlr_ctx* ctx, const ddlr_csr* A, const char* path, ddlr_prec** out) {
+    if (out) *out = nullptr;
+    if (!A || !path || !out || !A->row_ptr || !A->col_idx || !A->val) {
+        g_err = "null argument";
+        return DDLR_E_INVALID;
+    }
+    std::unique_ptr<ddlr_prec> h(new ddlr_prec());
+    attach_ctx(h.get(), ctx);
+    auto t0 = std::chrono::steady_clock::now();
+    try {
+        const auto R = read_setup_file(path);
+        const std::vector<int64_t> np = rec_get<int64_t>(R, "n_p", 2);
+        if (np[0] != A->n) throw SetupError{DDLR_E_INVALID, "setup file is for another matrix order"};
+        const int64_t n = np[0];
+        const int32_t p = (int32_t)np[1];
+        const double alpha = rec_get<double>(R, "alpha", 1)[0];
+        const std::vector<int32_t> flags = rec_get<int32_t>(R, "csolve_prec_nu", 3);
+        const int csolve = flags[0];
+        if (csolve < 0 || csolve > 2 || flags[1] < 0 || flags[1] > 2 || (csolve == 2 && (flags[2] < 1 || flags[2] > 64)))
+            throw SetupError{DDLR_E_INVALID, "setup file has a bad C_alpha solver, precision or step count"};
+        h->precision = flags[1];
+        HostCsr L;
+        L.rp = rec_get<int64_t>(R, "L.rowptr", n + 1);
+        L.ci = rec_get<int32_t>(R, "L.col");
+        L.v = rec_get<double>(R, "L.val");
+        build_plan_imported(h->plan, n, A->row_ptr, A->col_idx, A->val, p, alpha, rec_get<int32_t>(R, "perm", n),
+                            rec_get<int64_t>(R, "boff", (int64_t)p + 2), rec_get<int32_t>(R, "colour"), std::move(L),
+                            rec_get<double>(R, "D", n), csolve);
+        HostPlan& P = h->plan;
+        if (csolve == 1)
+            for (int64_t r = P.m; r < n; ++r)
+                if (P.L.rp[r + 1] != P.L.rp[r] || P.D[r] != 1.0)
+                    throw SetupError{DDLR_E_INVALID,
+                                     "with the approximate inverse of C_alpha the interface rows of L must be empty "
+                                     "and D must be 1 there"};
+        if (R.count("level") && rec_get<int32_t>(R, "level", n) != P.level)
+            throw SetupError{DDLR_E_INVALID, "stored levels differ from the schedule of the stored factor"};
+        if (csolve == 1) {
+            P.X.rp = rec_get<int64_t>(R, "X.rowptr", P.s + 1);
+            P.X.ci = rec_get<int32_t>(R, "X.col", P.X.rp.back());
+            P.X.v = rec_get<double>(R, "X.val", P.X.rp.back());
+            for (int64_t y = 0; y < P.s; ++y)
+                for (int64_t t = P.X.rp[y]; t < P.X.rp[y + 1]; ++t)
+                    if (P.X.ci[t] < 0 || P.X.ci[t] >= P.s || P.X.rp[y + 1] < P.X.rp[y])
+                        throw SetupError{DDLR_E_INVALID, "stored X has a column outside the interface"};
+            const std::vector<double> xc = rec_get<double>(R, "X.cert", 2);
+            P.x_rinf = xc[0];
+            P.x_spd = xc[1] != 0.0;
+            P.x_res = rec_get<double>(R, "X.res");
+            if (P.x_res.empty()) throw SetupError{DDLR_E_INVALID, "stored X has no residual history"};
+            P.x_iters = (int)P.x_res.size() - 1;
+        }
+        if (csolve == 2) {
+            const std::vector<double> ch = rec_get<double>(R, "cheb", 4);
+            P.ch_lo = ch[0], P.ch_hi = ch[1], P.ch_rlo = ch[2], P.ch_rhi = ch[3];
+            if (!(P.ch_hi > P.ch_lo)) throw SetupError{DDLR_E_INVALID, "stored Chebyshev interval is empty"};
+        }
+        for (double d : P.D) h->pivots_positive = h->pivots_positive && d > 0.0;
+        if (csolve == 1) h->pivots_positive = h->pivots_positive && P.x_spd;
+        if (csolve == 2) h->pivots_positive = h->pivots_positive && P.ch_rlo > 0.0;
+        h->variant = 0;
+        h->spd = (int)h->pivots_positive;
+        if (csolve == 2) h->cheb_nu = flags[2];
+        h->device = ctx ? ctx->device : 0;
+        if (h->device >= 0) {
+            HIPCHK(hipSetDevice(h->device));
+            {
+                DevLock dl(h->device);
+                device_init(h.get(), flags[2], 0);
+                HIPCHK(hipDeviceSynchronize());
+            }
+            if (R.count("lowrank")) {
+                const std::vector<int32_t> vk = rec_get<int32_t>(R, "lowrank", 2);
+                const int variant = vk[0], k = vk[1];
+                if ((variant != 1 && variant != 2) || k < 1 || k > 128)
+                    throw SetupError{DDLR_E_INVALID, "setup file has a bad low-rank variant or rank"};
+                const std::vector<double> U = rec_get<double>(R, "U", n * (int64_t)k);
+                const std::vector<double> aux =
+                    rec_get<double>(R, "aux", variant == 1 ? (int64_t)k + 1 : (int64_t)k * k);
+                const ddlr_status st = ddlr_set_lowrank(h.get(), variant, k, U.data(), aux.data());
+                if (st != DDLR_OK) throw SetupError{st, g_err};
+            }
+        }
+    } catch (const SetupError& e) {
+        discard_handle(h.get());
+        return fail_status(e);
+    } catch (const std::bad_alloc&) {
+        discard_handle(h.get());
+        g_err = "host out of memory";
+        return DDLR_E_OOM;
+    }
+    h->setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    *out = h.release();
+    return DDLR_OK;
+}
+
 static void prof_reset(ddlr_prec* h) {
     for (int c = 0; c < kProfClasses; ++c) {
         for (auto& pr : h->prof_ev[c]) {
@@ -3191,6 +3553,7 @@ void ddlr_destroy(ddlr_prec* h) {
     h->lrun.mem.release();
     h->chmem.release();
     h->mem.release();
+    ctx_unref(h->ctx);
     delete h;
 }
 

@@ -337,6 +337,82 @@ void build_plan(HostPlan& P, int64_t n, const int64_t* rp, const int32_t* ci, co
     schedule(P);
 }
 
+void build_plan_imported(HostPlan& P, int64_t n, const int64_t* rp, const int32_t* ci, const double* v, int32_t p,
+                         double alpha, std::vector<int32_t> perm, std::vector<int64_t> boff,
+                         std::vector<int32_t> colour, HostCsr L, std::vector<double> D, int csolve) {
+    if (!(alpha > 0.0) || !std::isfinite(alpha)) fail(DDLR_E_INVALID, "alpha must be positive");
+    if (p < 1 || p > n) fail(DDLR_E_INVALID, "stored p outside [1, n]");
+    if ((int64_t)perm.size() != n || (int64_t)boff.size() != p + 2 || (int64_t)D.size() != n ||
+        L.rows() != n)
+        fail(DDLR_E_INVALID, "stored setup does not match the matrix order");
+    if (boff[0] != 0 || boff[p + 1] != n) fail(DDLR_E_INVALID, "stored block offsets must run from 0 to n");
+    for (int32_t b = 0; b <= p; ++b)
+        if (boff[b + 1] < boff[b]) fail(DDLR_E_INVALID, "stored block offsets not monotone");
+    // the interior row of internal position q belongs to block blk[q]; interface rows to block p
+    std::vector<int32_t> blk(n), part(n, 0);
+    for (int32_t b = 0; b <= p; ++b)
+        for (int64_t q = boff[b]; q < boff[b + 1]; ++q) blk[q] = b;
+    std::vector<int32_t> seen(n, 0);
+    for (int64_t q = 0; q < n; ++q) {
+        const int32_t u = perm[q];
+        if (u < 0 || u >= n || seen[u]) fail(DDLR_E_INVALID, "stored ordering is not a permutation");
+        seen[u] = 1;
+        if (blk[q] < p) part[u] = blk[q];
+    }
+    validate(n, rp, ci, v, part.data(), p);
+    P.n = n;
+    P.p = p;
+    P.alpha = alpha;
+    P.perm = std::move(perm);
+    P.boff = std::move(boff);
+    P.m = P.boff[p];
+    P.s = n - P.m;
+    if (P.s == 0) fail(DDLR_E_INVALID, "stored ordering has no interface unknowns");
+    P.iperm.assign(n, 0);
+    for (int64_t q = 0; q < n; ++q) P.iperm[P.perm[q]] = (int32_t)q;
+    P.iface.assign(n, 0);
+    for (int64_t u = 0; u < n; ++u) P.iface[u] = P.iperm[u] >= P.m;
+    if ((int64_t)colour.size() != P.s) fail(DDLR_E_INVALID, "stored colours must have one entry per interface row");
+    P.colour = std::move(colour);
+    P.ncolours = 0;
+    for (int32_t c : P.colour) {
+        if (c < 0) fail(DDLR_E_INVALID, "negative stored colour");
+        P.ncolours = std::max(P.ncolours, c + 1);
+    }
+    permute_matrix(P, rp, ci, v);
+    // the splitting needs interior rows coupled only to their own block and the interface
+    for (int64_t r = 0; r < P.m; ++r)
+        for (int64_t t = P.A.rp[r]; t < P.A.rp[r + 1]; ++t) {
+            const int32_t c = P.A.ci[t];
+            if (c < P.m && blk[c] != blk[r])
+                fail(DDLR_E_INVALID, "stored ordering couples the interiors of blocks " + std::to_string(blk[r]) +
+                                         " and " + std::to_string(blk[c]) + " (internal row " + std::to_string(r) +
+                                         ")");
+        }
+    form_a0(P);
+    // the factor: strict lower, columns inside the row's block, ascending
+    if (L.rp[0] != 0) fail(DDLR_E_INVALID, "stored L row pointer must start at 0");
+    for (int64_t r = 0; r < n; ++r) {
+        if (L.rp[r + 1] < L.rp[r] || L.rp[r + 1] > (int64_t)L.ci.size())
+            fail(DDLR_E_INVALID, "stored L row pointer not monotone");
+        const int64_t lo = P.boff[blk[r]];
+        for (int64_t t = L.rp[r]; t < L.rp[r + 1]; ++t) {
+            const int32_t c = L.ci[t];
+            if (c < lo || c >= r || (t > L.rp[r] && c <= L.ci[t - 1]))
+                fail(DDLR_E_INVALID, "stored L entry outside the strict lower block pattern in row " +
+                                         std::to_string(r));
+            if (!std::isfinite(L.v[t])) fail(DDLR_E_INVALID, "stored L value not finite");
+        }
+        if (!std::isfinite(D[r]) || D[r] == 0.0) fail(DDLR_E_INVALID, "stored pivot zero or not finite");
+    }
+    if ((int64_t)L.v.size() != L.rp[n] || (int64_t)L.ci.size() != L.rp[n])
+        fail(DDLR_E_INVALID, "stored L arrays do not match its row pointer");
+    P.L = std::move(L);
+    P.D = std::move(D);
+    P.csolve = csolve;
+    schedule(P);
+}
+
 // Implicit symmetric QR with Wilkinson shifts (the implicit QR step of the
 // symmetric tridiagonal eigenproblem, Golub & Van Loan, Sec. 8.3), on a dense
 // copy with rotations restricted to the band.

@@ -77,6 +77,17 @@ void build_plan(HostPlan& P, int64_t n, const int64_t* rp, const int32_t* ci, co
                 const int32_t* part, int32_t p, double alpha, int factor, int corder, int csolve = 0,
                 int cinv_iters = 3, double cinv_tol = 0.01, int cinv_lfil = 20, int cheb_lanczos = 10);
 
+// Steps 1-3 from stored data (ddlr_import_setup): the ordering (perm,
+// block offsets, interface colours) and the local factors (strict lower L and
+// D in internal order) are taken as given and checked against A (perm a
+// permutation, interiors of different blocks uncoupled, L strictly lower
+// inside its row's block with sorted columns, pivots finite and nonzero);
+// P A P^T and A0 are formed and the level schedule recomputed from L as in
+// build_plan.  The caller sets X or the Chebyshev interval for csolve 1 / 2.
+void build_plan_imported(HostPlan& P, int64_t n, const int64_t* rp, const int32_t* ci, const double* v, int32_t p,
+                         double alpha, std::vector<int32_t> perm, std::vector<int64_t> boff,
+                         std::vector<int32_t> colour, HostCsr L, std::vector<double> D, int csolve);
+
 // Spectrum interval of D_alpha^{-1} C_alpha for the Chebyshev solver (cheb.cpp).
 void cheb_bounds(HostPlan& P, int mc);
 

@@ -1,0 +1,150 @@
+"""The library run on the oracle's complete setup, and contexts with a
+device-memory budget, through the C ABI.
+
+The oracle's ordering, factors, X or Chebyshev interval and low-rank data are
+written in the documented setup-file layout (tests/setup_file.py) and imported
+with ddlr_import_setup; no classification, factorisation or Lanczos of the
+library runs.  The A0 solve must match the oracle's to 1e-12 (Chebyshev
+1e-11), the preconditioner to 1e-10 and the 6-step CG iterate to 1e-10 (FP64);
+with the FP32 preconditioner the apply to 1e-4.  Export followed by import
+gives a handle whose apply and CG are bitwise those of the exported one.
+"""
+import gc
+import sys
+
+import numpy as np
+import pytest
+
+import paper_1505_04341_amd as D
+import setup_file as SF
+import workloads as w
+from oracle import Oracle
+from parity import assert_close
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def say(*a):
+    print("[case]", *a, file=sys.stderr, flush=True)
+
+
+def to_dev(x):
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(x, np.float64).T)).to(DEV)
+
+
+def to_host(t):
+    return t.cpu().numpy().T
+
+
+def irregular():
+    A = w.tpfa_2d(37, 29, 11)
+    return dict(A=A, part=w.box_partition((37, 29), (3, 2)), p=6, k=6, m=20)
+
+
+CASES = {"c1": lambda: w.config("c1"), "small3d": lambda: w.config("small3d"), "irregular": irregular}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("variant", [1, 2])
+@pytest.mark.parametrize("csolve", [0, 1, 2])
+def test_import_oracle_setup(name, variant, csolve, tmp_path):
+    cfg = CASES[name]()
+    A, n = cfg["A"], cfg["A"].n
+    say("import oracle setup", name, variant, csolve)
+    o = Oracle(A, cfg["part"], cfg["p"])
+    if csolve == 1:
+        o.use_cinv()
+    if csolve == 2:
+        o.use_cheb()
+    o.lowrank(variant, cfg["k"], cfg["m"], w.lanczos_start(n, 0))
+    f = str(tmp_path / "oracle.ddlr")
+    SF.write(f, SF.from_oracle(o, csolve=csolve, cheb_nu=5 if csolve == 2 else 0))
+    h = D.ddlr_import_setup(A, f)
+    q = D.ddlr_query(h)
+    assert (q["variant"], q["k"], q["csolve"]) == (variant, cfg["k"], csolve)
+    x = np.random.default_rng(8).standard_normal((n, 5))
+    y = torch.empty((5, n), dtype=torch.float64, device=DEV)
+    D.ddlr_a0_solve(h, to_dev(x), y)
+    assert_close(to_host(y), o.a0_solve(x), 1e-11 if csolve == 2 else 1e-12, "A0 solve")
+    D.ddlr_apply(h, to_dev(x), y)
+    assert_close(to_host(y), o.apply(x), 1e-10, "apply")
+    if o.spd:
+        b, _ = w.rhs_from_solution(A, 0, 3)
+        xt = torch.zeros((3, n), dtype=torch.float64, device=DEV)
+        st, info = D.ddlr_solve(h, to_dev(b), xt, maxit=6)
+        assert st == D.E_NO_CONVERGENCE and all(i["iters"] == 6 for i in info)
+        xo, _ = o.pcg(b, maxit=6)
+        assert_close(to_host(xt), xo, 1e-10, "CG iterate")
+
+
+def test_import_oracle_setup_fp32(tmp_path):
+    cfg = irregular()
+    A, n = cfg["A"], cfg["A"].n
+    say("import oracle setup fp32")
+    o = Oracle(A, cfg["part"], cfg["p"]).lowrank(1, cfg["k"], cfg["m"], w.lanczos_start(n, 0))
+    f = str(tmp_path / "oracle32.ddlr")
+    SF.write(f, SF.from_oracle(o, precision=D.FP32))
+    h = D.ddlr_import_setup(A, f)
+    assert D.ddlr_query(h)["precision"] == D.FP32
+    x = np.random.default_rng(9).standard_normal((n, 4))
+    y = torch.empty((4, n), dtype=torch.float64, device=DEV)
+    D.ddlr_apply(h, to_dev(x), y)
+    assert_close(to_host(y), o.apply(x), 1e-4, "FP32 apply")
+
+
+@pytest.mark.parametrize("prec", [D.FP64, D.FP32])
+@pytest.mark.parametrize("variant", [1, 2])
+def test_export_import_same_operator(prec, variant, tmp_path):
+    cfg = w.config("small3d")
+    A, n = cfg["A"], cfg["A"].n
+    say("export/import", prec, variant)
+    h = D.ddlr_setup(A, cfg["part"], cfg["p"], cfg["k"], variant, lanczos_steps=cfg["m"],
+                     lanczos_start=w.lanczos_start(n, 0), precision=prec)
+    f = str(tmp_path / "own.ddlr")
+    D.ddlr_export_setup(h, f)
+    h2 = D.ddlr_import_setup(A, f)
+    x = to_dev(np.random.default_rng(10).standard_normal((n, 6)))
+    y1, y2 = torch.empty_like(x), torch.empty_like(x)
+    D.ddlr_apply(h, x, y1)
+    D.ddlr_apply(h2, x, y2)
+    assert torch.equal(y1, y2)
+    b = to_dev(w.rhs_from_solution(A, 0, 2)[0])
+    x1, x2 = torch.zeros_like(b), torch.zeros_like(b)
+    s1, i1 = D.ddlr_solve(h, b, x1)
+    s2, i2 = D.ddlr_solve(h2, b, x2)
+    assert s1 == s2 == D.OK and [i["iters"] for i in i1] == [i["iters"] for i in i2]
+    assert torch.equal(x1, x2)
+
+
+def test_context_budget():
+    cfg = w.config("small3d")
+    A, n = cfg["A"], cfg["A"].n
+    say("context budget")
+    args = (A, cfg["part"], cfg["p"], cfg["k"], 1)
+    kw = dict(lanczos_steps=cfg["m"], lanczos_start=w.lanczos_start(n, 0))
+    small = D.ddlr_ctx_create(0, 1 << 16)  # 64 KiB cannot hold the matrix
+    with pytest.raises(D.DDLRError) as e:
+        D.ddlr_setup(*args, ctx=small, **kw)
+    assert e.value.status == D.E_BUDGET
+    assert D.ddlr_ctx_usage(small)["used"] == 0  # the failed setup gave everything back
+    free = D.ddlr_ctx_create(0, 0)
+    h = D.ddlr_setup(*args, ctx=free, **kw)
+    u = D.ddlr_ctx_usage(free)
+    assert u["used"] > 0 and u["peak"] >= u["used"] and u["budget"] == 0
+    del h
+    gc.collect()
+    assert D.ddlr_ctx_usage(free)["used"] == 0
+    # enough for the setup, not for an 8-column solve's workspace
+    tight = D.ddlr_ctx_create(0, u["peak"] + (1 << 12))
+    h = D.ddlr_setup(*args, ctx=tight, **kw)
+    b = to_dev(w.rhs_from_solution(A, 0, 8)[0])
+    with pytest.raises(D.DDLRError) as e:
+        D.ddlr_solve(h, b, torch.zeros_like(b))
+    assert e.value.status == D.E_BUDGET
+    e = None  # the traceback holds the handle
+    del h
+    gc.collect()
+    assert D.ddlr_ctx_usage(tight)["used"] == 0
