@@ -329,6 +329,16 @@ ddlr_status ddlr_get_cinv(const ddlr_prec *h, int64_t *row_ptr, int32_t *col, do
  * piece). */
 ddlr_status ddlr_partition_graph(const ddlr_csr *A, int32_t p, int32_t *part);
 
+/* The geometric partition of the model problems (the configurations' box
+ * splits; the paper partitions with an external tool, Sec. 2.1): a grid of
+ * nx*ny*nz points numbered lexicographically (x fastest; nz = 1 for 2-D) is
+ * cut into px*py*pz boxes, each axis into P runs of consecutive points whose
+ * first (N mod P) runs are one point longer; the point (x, y, z) gets part
+ * bx + px*(by + py*bz).  part: host array of nx*ny*nz entries.  Errors:
+ * DDLR_E_INVALID (null part, a count < 1, more parts than points on an axis). */
+ddlr_status ddlr_partition_box(int32_t nx, int32_t ny, int32_t nz, int32_t px, int32_t py, int32_t pz,
+                               int32_t *part);
+
 /* Level of each internal row in its block's forward triangular schedule. */
 ddlr_status ddlr_get_levels(const ddlr_prec *h, int32_t *level);
 

@@ -149,6 +149,7 @@ def load_library(path: str = LIB_PATH):
         "ddlr_tune": (I32, [P, I32, I32, P, P]),
         "ddlr_extend_lowrank": (I32, [P, I32, I32, I32, C.c_double]),
         "ddlr_partition_graph": (I32, [P, I32, P]),
+        "ddlr_partition_box": (I32, [I32, I32, I32, I32, I32, I32, P]),
         "ddlr_destroy": (None, [P]),
         "ddlr_status_string": (C.c_char_p, [I32]),
         "ddlr_last_error": (C.c_char_p, []),
@@ -389,6 +390,16 @@ def ddlr_get_cinv(prec: Prec):
     return sp.csr_matrix((v[:nnz], ci[:nnz], rp), shape=(s, s)), res
 
 
+def ddlr_partition_box(dims, parts) -> np.ndarray:
+    """Box partition of a lexicographic 2-D or 3-D grid (x fastest)."""
+    d = list(dims) + [1] * (3 - len(dims))
+    q = list(parts) + [1] * (3 - len(parts))
+    part = np.zeros(int(np.prod(d)), np.int32)
+    _check(load_library().ddlr_partition_box(*[int(v) for v in d], *[int(v) for v in q], _ptr(part)),
+           "ddlr_partition_box")
+    return part
+
+
 def ddlr_get_levels(prec: Prec):
     lib = load_library()
     lev = np.zeros(prec.n, np.int32)
@@ -605,7 +616,7 @@ def ddlr_version() -> int:
 
 EXPORTED = ["ddlr_version", "ddlr_options_default", "ddlr_solve_options_default", "ddlr_setup", "ddlr_apply",
             "ddlr_apply_noalloc", "ddlr_ctx_create", "ddlr_ctx_usage", "ddlr_ctx_destroy", "ddlr_export_setup",
-            "ddlr_import_setup",
+            "ddlr_import_setup", "ddlr_partition_box",
             "ddlr_a0_solve", "ddlr_spmv", "ddlr_solve", "ddlr_query", "ddlr_get_ordering", "ddlr_get_factor",
             "ddlr_get_cinv",
             "ddlr_get_levels", "ddlr_get_lanczos", "ddlr_get_lowrank", "ddlr_set_lowrank", "ddlr_profile",

@@ -2999,6 +2999,29 @@ ddlr_status ddlr_partition_graph(const ddlr_csr* A, int32_t p, int32_t* part) {
     return DDLR_OK;
 }
 
+ddlr_status ddlr_partition_box(int32_t nx, int32_t ny, int32_t nz, int32_t px, int32_t py, int32_t pz,
+                               int32_t* part) {
+    if (!part || nx < 1 || ny < 1 || nz < 1 || px < 1 || py < 1 || pz < 1 || px > nx || py > ny || pz > nz) {
+        g_err = "ddlr_partition_box: need 1 <= p_d <= n_d on every axis and a non-null output";
+        return DDLR_E_INVALID;
+    }
+    // first index of each part along an axis: the first (N mod P) parts hold one point more
+    auto cuts = [](int32_t N, int32_t P) {
+        std::vector<int32_t> lab(N);
+        const int32_t base = N / P, extra = N % P;
+        int32_t i = 0;
+        for (int32_t q = 0; q < P; ++q)
+            for (int32_t c = 0; c < base + (q < extra ? 1 : 0); ++c) lab[i++] = q;
+        return lab;
+    };
+    const std::vector<int32_t> lx = cuts(nx, px), ly = cuts(ny, py), lz = cuts(nz, pz);
+    int64_t u = 0;
+    for (int32_t z = 0; z < nz; ++z)
+        for (int32_t y = 0; y < ny; ++y)
+            for (int32_t x = 0; x < nx; ++x) part[u++] = lx[x] + px * (ly[y] + py * lz[z]);
+    return DDLR_OK;
+}
+
 ddlr_status ddlr_get_levels(const ddlr_prec* h, int32_t* level) {
     if (!h || !level) {
         g_err = "null argument";

@@ -192,3 +192,23 @@ def test_cheb_factor_and_interval_match_oracle(name, cfg, kw):
     for a, b in ((q["cheb_lo"], lo), (q["cheb_hi"], hi), (q["cheb_ritz_lo"], rlo), (q["cheb_ritz_hi"], rhi)):
         assert abs(a - b) <= 1e-10 * abs(b)
     assert 0 < q["cheb_lo"] <= q["cheb_ritz_lo"] <= q["cheb_ritz_hi"] <= q["cheb_hi"]
+
+
+@pytest.mark.parametrize("dims,parts", [((64, 64), (2, 2)), ((37, 29), (3, 2)), ((25, 25, 25), (4, 4, 8)),
+                                        ((100, 100, 100), (4, 4, 8)), ((7, 5, 3), (7, 1, 3))])
+def test_partition_box_matches_generator(dims, parts):
+    """The library's box split equals the workload generator's (an independent
+    statement of the same rule), and every box has the sizes the rule gives."""
+    got = D.ddlr_partition_box(dims, parts)
+    assert np.array_equal(got, w.box_partition(dims, parts))
+    counts = np.bincount(got, minlength=int(np.prod(parts)))
+    d3, p3 = list(dims) + [1] * (3 - len(dims)), list(parts) + [1] * (3 - len(parts))
+    sx, sy, sz = [[N // P + (1 if i < N % P else 0) for i in range(P)] for N, P in zip(d3, p3)]
+    expect = np.zeros_like(counts)
+    for bz in range(p3[2]):
+        for by in range(p3[1]):
+            for bx in range(p3[0]):
+                expect[bx + p3[0] * (by + p3[1] * bz)] = sx[bx] * sy[by] * sz[bz]
+    assert np.array_equal(counts, expect)
+    with pytest.raises(D.DDLRError):
+        D.ddlr_partition_box((4, 4), (5, 1))
