@@ -47,12 +47,40 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def trsv_bytes(nrhs: int, tbytes: int, nnz_b: int, rows_b: int) -> float:
+EARLY_EXIT_US = 4.0  # launches shorter than this returned at once: every column had converged
+
+
+def trsv_bytes(nrhs: int, tbytes: int, nnz_b: int, rows_b: int, io_bytes: int, round_trip: bool = True) -> float:
     """Algorithmic HBM bytes of one launch of the per-block triangular-solve
-    kernel: L and L^T of the B blocks (value + 4-byte column, once per launch),
-    their row pointers, D^{-1}, and per right-hand side one read of x and one
-    write of z over the B rows."""
-    return 2.0 * nnz_b * (tbytes + 4) + 2.0 * 4 * rows_b + tbytes * rows_b + nrhs * 2.0 * tbytes * rows_b
+    kernel over the B blocks: L and L^T once (value + 4-byte column), D^{-1}
+    and 8 bytes of row/level metadata per row, and per right-hand side the
+    input read and the output written (io_bytes per row together: 12 in the
+    mixed apply, whose first solve reads FP64 and writes FP32 and whose second
+    does the reverse; 16 in FP64).  round_trip adds, per right-hand side, the
+    forward solution written and read back between the two sweeps (2 * tbytes
+    per row): the model of the scope table's A0-solve row.  Without it, the
+    kernel's own minimum."""
+    per_col = io_bytes + (2 * tbytes if round_trip else 0)
+    return 2.0 * nnz_b * (tbytes + 4) + rows_b * (tbytes + 8.0) + nrhs * per_col * float(rows_b)
+
+
+def spmv_bytes(nrhs: int, nnz: int, n: int) -> float:
+    """Algorithmic bytes of one CG SpMV over nrhs columns: CSR entries at 12 B
+    (FP64 value, 4-byte column), 4 B of row pointer per row, and per column x
+    read and y written (8 B each per row)."""
+    return 12.0 * nnz + 4.0 * n + nrhs * 16.0 * n
+
+
+def solve_bytes_per_rhs_iter(prec_bytes: int, nrhs: int, nnz_a: int, nnz_l: int, s: int, k: int, n: int) -> float:
+    """Algorithmic bytes of one DDLR-1 PCG iteration per right-hand side, the
+    scope table's model: SpMV 12 B/nnz(A), two A0 solves reading L and L^T
+    (2 * 2 * (value + column) per strict-lower entry), U_k read twice (reduce
+    and expand), all shared by the nrhs columns of a batch; plus the vector
+    traffic per column: 192 B/row with the FP32 preconditioner, 212 with FP64
+    (SpMV 20, two A0 solves, x + E w, the CG vectors)."""
+    shared = 12.0 * nnz_a + 4.0 * (prec_bytes + 4) * nnz_l + 2.0 * prec_bytes * s * k
+    per_col = (192.0 if prec_bytes == 4 else 212.0) * n
+    return shared / nrhs + per_col
 
 
 def measured_traffic():
@@ -91,7 +119,9 @@ def roofline_of(D, h, q, nrhs, tbytes, prof):
     nnz_b = int(L.indptr[rows_b])
     tot_ms, launches = prof[D.PROF_TRSV_BLOCKS]
     avg_s = tot_ms / max(launches, 1) / 1e3
-    by = trsv_bytes(nrhs, tbytes, nnz_b, rows_b)
+    io = 12 if tbytes == 4 else 16
+    by = trsv_bytes(nrhs, tbytes, nnz_b, rows_b, io, round_trip=True)
+    by_min = trsv_bytes(nrhs, tbytes, nnz_b, rows_b, io, round_trip=False)
     achieved = by / avg_s / 1e9 if avg_s > 0 else 0.0
     tn = D.ddlr_tune(h, nrhs)  # tuned shape (reported, not re-run)
     R, nt = tn["ring_cols"], tn["ring_threads"]
@@ -104,11 +134,37 @@ def roofline_of(D, h, q, nrhs, tbytes, prof):
         kname = f"k_trsv_narrow<{t}>"
     form = ("beside the interface-block solve on a side stream" if tn["cg_overlap"] == 1
             else "alone (interface-block solve in line)")
-    return {"bound": "hbm", "kernel": kname, "columns_per_workgroup": R, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "bytes_per_launch": by,
+    return {"bound": "hbm", "kernel": kname, "columns_per_workgroup": R, "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "bytes_per_launch": by, "bytes_model": "L and L^T once, D^-1 + metadata, per column input, output and "
+                                                  "the forward solution's round trip",
+            "kernel_min_bytes_per_launch": by_min,
+            "kernel_min_frac": round(by_min / avg_s / 1e9 / HBM_PEAK_GBS, 4) if avg_s > 0 else 0.0,
             "avg_launch_us": round(avg_s * 1e6, 2), "launches": launches,
+            "launches_counted": f"launches of at least {EARLY_EXIT_US} us (early exits after convergence left out)",
             "runs": f"{form}; CG chunks {'replayed from graphs' if tn['cg_graph'] == 1 else 'launched eagerly'} "
                     "in the timed solves (the library's measured choice)"}
+
+
+def spmv_roofline(prof, D, nrhs, nnz, n):
+    tot_ms, launches = prof[D.PROF_SPMV]
+    if not launches:
+        return None
+    avg_s = tot_ms / launches / 1e3
+    by = spmv_bytes(nrhs, nnz, n)
+    return {"kernel": f"k_spmv_sell_il<{nrhs if nrhs in (1, 2, 4, 8, 16) else 'S'}>", "bytes_per_launch": by,
+            "avg_launch_us": round(avg_s * 1e6, 2), "achieved": round(by / avg_s / 1e9, 1), "unit": "GB/s",
+            "frac": round(by / avg_s / 1e9 / HBM_PEAK_GBS, 4), "launches": launches}
+
+
+def solve_roofline(r, q, nrhs, prec_bytes, nnz_a, steps):
+    """Whole PCG solve against HBM: the model bytes per right-hand side and
+    iteration, times the iterations every column took, over the timed step."""
+    per = solve_bytes_per_rhs_iter(prec_bytes, nrhs, nnz_a, int(q["nnz_l"]), int(q["s"]), int(q["k"]), int(q["n"]))
+    work = per * float(sum(r["its"]))
+    t = r["total"] / steps
+    return {"bytes_per_rhs_iteration": round(per), "rhs_iterations": int(sum(r["its"])),
+            "achieved": round(work / t / 1e9, 1), "unit": "GB/s", "frac": round(work / t / 1e9 / HBM_PEAK_GBS, 4)}
 
 
 def breakdown_of(D, prof, K, step_ms):
@@ -146,7 +202,7 @@ def timed_solves(D, torch, h, bt, xt, steps, warmup, method, label, prof_steps=2
         D.ddlr_solve(h, bt, xt, method=method)
     torch.cuda.synchronize()
     prof_ms = 1e3 * (time.perf_counter() - tp) / max(prof_steps, 1)
-    prof = {c: D.ddlr_profile_read(h, c) for c in range(4)}
+    prof = {c: D.ddlr_profile_read(h, c, EARLY_EXIT_US) for c in range(4)}
     D.ddlr_profile(h, False)
     its = [i["iters"] for i in info]
     rtrue = max(i["relres_true"] for i in info)
@@ -216,10 +272,15 @@ def run_single(args, D, w, torch):
     roof = roofline_of(D, mixed["h"], mixed["q"], nrhs, 4, mixed["prof"])
     traffic = measured_traffic() if args.config == "c2" and args.variant == 1 else None
     roof["traffic"] = traffic
+    nnz_a = int(mixed["q"]["nnz_a"])
+    roof["spmv"] = spmv_roofline(mixed["prof"], D, nrhs, nnz_a, n)
+    if args.variant == 1 and not gm:
+        roof["whole_solve"] = {"mixed": solve_roofline(mixed, mixed["q"], nrhs, 4, nnz_a, K),
+                               "fp64": solve_roofline(f64, f64["q"], nrhs, 8, nnz_a, K)}
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(cfg, b, v0, args.variant, mixed["x"], f64["x"], gm, args.cpu_rhs, args.csolve,
-                           alpha_for(args))
+        cpu = cpu_baseline(cfg, b, v0, args.variant, mixed["x"], f64["x"], gm, args.cpu_rhs, args.cpu_rhs_1t,
+                           args.csolve, alpha_for(args))
     workload = {
         "c1": "5-point Laplacian 64^2, 2x2 boxes",
         "c2": "7-point Laplacian 128^3, 4x4x4 boxes",
@@ -265,11 +326,50 @@ def run_single(args, D, w, torch):
     return out
 
 
-def cpu_baseline(cfg, b, v0, variant, x_mixed, x_f64, gm, ncols, csolve="factor", alpha=1.0):
-    """The oracle (plain C, FP64, OpenMP over blocks/rows) on the host cores:
-    full solves of the first `ncols` right-hand sides of the same workload.
-    Also states the GPU results' distance to the oracle's on those columns."""
+def oracle_native():
+    """The oracle for the timed CPU baseline: an -O3 -march=native build made on
+    this machine (the tests' copy is built portably)."""
+    import tempfile
+
     import oracle
+    try:
+        path = oracle.use_native_build(tempfile.mkdtemp(prefix="ddlr_oracle_"))
+        log("cpu baseline: oracle built with -O3 -march=native at", path)
+    except RuntimeError:
+        pass  # already loaded in this process
+    return oracle
+
+
+def host_info(oracle):
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"cpu": model, "os_cpu_count": os.cpu_count(), "omp_threads": oracle.threads()}
+
+
+def timed_oracle(oracle, threads, fn):
+    prev = oracle.threads()
+    oracle.set_threads(threads)
+    try:
+        t0 = time.perf_counter()
+        out = fn()
+        return out, time.perf_counter() - t0
+    finally:
+        oracle.set_threads(prev)
+
+
+def cpu_baseline(cfg, b, v0, variant, x_mixed, x_f64, gm, ncols, ncols_1t, csolve="factor", alpha=1.0):
+    """The oracle (plain C, FP64, OpenMP over blocks and rows) on the host
+    cores: full solves of the first `ncols` right-hand sides of the same
+    workload with every OpenMP thread, and of the first `ncols_1t` with one
+    thread (setup excluded).  Also states the GPU results' distance to the
+    oracle's on those columns."""
+    oracle = oracle_native()
     threads = oracle.threads()
     log("cpu baseline: oracle setup", threads, "threads")
     o = oracle.Oracle(cfg["A"], cfg["part"], cfg["p"], alpha=alpha,
@@ -280,21 +380,27 @@ def cpu_baseline(cfg, b, v0, variant, x_mixed, x_f64, gm, ncols, csolve="factor"
         o.use_cheb(5, 10)
     o.lowrank(variant, cfg["k"], cfg["m"], v0)
     ncols = min(ncols, b.shape[1])
-    t0 = time.perf_counter()
-    if gm:
-        x, info = o.gmres(b[:, :ncols])
-    else:
-        x, info = o.pcg(b[:, :ncols])
-    dt = time.perf_counter() - t0
+    ncols_1t = min(ncols_1t, b.shape[1])
+    solve = (lambda c: o.gmres(b[:, :c])) if gm else (lambda c: o.pcg(b[:, :c]))
+    (x, info), dt = timed_oracle(oracle, threads, lambda: solve(ncols))
     x = np.asarray(x).reshape(b.shape[0], -1)
     its = [int(i) for i in info["its"]]
-    log("cpu baseline: its", its, f"{dt:.1f}s")
+    log("cpu baseline: all threads, its", its, f"{dt:.1f}s")
+    one = None
+    if ncols_1t > 0:
+        (_, info1), dt1 = timed_oracle(oracle, 1, lambda: solve(ncols_1t))
+        log("cpu baseline: one thread", f"{dt1:.1f}s")
+        one = {"value": round(ncols_1t / dt1, 4), "unit": "solves/s", "cores": 1,
+               "sample": f"the first {ncols_1t} right-hand side(s), {[int(i) for i in info1['its']]} iterations, "
+                         f"{dt1:.1f} s"}
 
     def rel(a):
         return float(np.linalg.norm(a[:, :ncols] - x) / np.linalg.norm(x))
     return {"value": round(ncols / dt, 4), "unit": "solves/s", "cores": threads, "kind": "oracle",
             "sample": f"the first {ncols} of the {b.shape[1]} right-hand sides (seeds 0..{ncols - 1}), each solved "
-                      f"to 1e-6 by the oracle ({its} iterations, {dt:.1f} s, setup excluded)",
+                      f"to 1e-6 by the oracle with {threads} OpenMP threads ({its} iterations, {dt:.1f} s, setup "
+                      f"excluded); oracle built with -O3 -march=native on this host",
+            "single_thread": one, "host": host_info(oracle),
             "gpu_x_rel_diff": {"fp64": rel(x_f64), "mixed": rel(x_mixed)}}
 
 
@@ -345,8 +451,29 @@ def run_batch(args, D, w, torch):
         "latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99), "note": "per batch solve (all systems)"},
         "batch": {"status": st, "iters_min": int(its.min()), "iters_median": float(np.median(its)),
                   "iters_max": int(its.max()), "max_relres_true": rtrue, "setup_s": round(setup_s, 2)},
-        "roofline": None, "cpu_baseline": None,
+        "roofline": None,
+        "cpu_baseline": None if args.no_cpu else cpu_baseline_batch(systems, bs, args.cpu_systems),
     }
+
+
+def cpu_baseline_batch(systems, bs, count):
+    """The oracle on the first `count` systems of the batch, one after another
+    with every OpenMP thread (setup excluded), CG to 1e-6 each."""
+    oracle = oracle_native()
+    count = min(count, len(systems))
+    dt, its = 0.0, []
+    for s, b in zip(systems[:count], bs[:count]):
+        o = oracle.Oracle(s["A"], s["part"], s["p"]).lowrank(1, s["k"], s["m"], __import__("workloads").lanczos_start(
+            s["A"].n, s["seed"]))
+        (_, info), t = timed_oracle(oracle, oracle.threads(), lambda: o.pcg(b))
+        dt += t
+        its.append(int(info["its"][0]))
+    ns = [s["A"].n for s in systems[:count]]
+    log("cpu baseline (batch):", count, "systems", f"{dt:.1f}s")
+    return {"value": round(count / dt, 3), "unit": "solves/s", "cores": oracle.threads(), "kind": "oracle",
+            "sample": f"the first {count} of the {len(systems)} systems (n {min(ns)}..{max(ns)}), each solved to 1e-6 "
+                      f"by the oracle in turn ({min(its)}..{max(its)} iterations, {dt:.1f} s, setup excluded)",
+            "host": host_info(oracle)}
 
 
 # ---------------------------------------------------------------- c5: serving
@@ -440,6 +567,57 @@ def run_serving(args, D, w, torch):
     }
 
 
+def trace_summary(path, min_us):
+    """Markdown table of a rocprofv3 kernel trace: per kernel name, dispatches,
+    average duration over all of them and over those of at least min_us
+    (launches after every column converged return at once), total time."""
+    import csv
+    per = {}
+    with open(path, newline="") as f:
+        for row in csv.DictReader(f):
+            name = row.get("Kernel_Name") or row.get("Kernel-Name") or row.get("KernelName")
+            t = (float(row["End_Timestamp"]) - float(row["Start_Timestamp"])) / 1e3  # ns -> us
+            per.setdefault(name, []).append(t)
+    rows = sorted(per.items(), key=lambda kv: -sum(kv[1]))
+    print(f"| kernel | dispatches | avg us (all) | dispatches >= {min_us:g} us | avg us (>= {min_us:g} us) | total ms |")
+    print("|---|---|---|---|---|---|")
+    for name, ts in rows:
+        a = np.asarray(ts)
+        big = a[a >= min_us]
+        short = name if len(name) <= 110 else name[:107] + "..."
+        print(f"| `{short}` | {len(a)} | {a.mean():.2f} | {len(big)} | {big.mean() if len(big) else 0.0:.2f} | "
+              f"{a.sum() / 1e3:.3f} |")
+
+
+def pmc_summary(path, min_us):
+    """Markdown table of a rocprofv3 --pmc counter_collection.csv: per kernel
+    name, dispatches of at least min_us, their average duration and the
+    average of every counter per dispatch; counters named MfmaFlops* are also
+    given as TFLOP/s (flops / duration, averaged over dispatches)."""
+    import csv
+    disp = {}
+    with open(path, newline="") as f:
+        for row in csv.DictReader(f):
+            d = disp.setdefault(row["Dispatch_Id"], {"name": row["Kernel_Name"], "c": {}})
+            d["us"] = (float(row["End_Timestamp"]) - float(row["Start_Timestamp"])) / 1e3
+            d["c"][row["Counter_Name"]] = d["c"].get(row["Counter_Name"], 0.0) + float(row["Counter_Value"])
+    per = {}
+    for d in disp.values():
+        if d["us"] >= min_us:
+            per.setdefault(d["name"], []).append(d)
+    counters = sorted({c for d in disp.values() for c in d["c"]})
+    flops = [c for c in counters if c.startswith("MfmaFlops")]
+    head = ["kernel", "dispatches", "avg us"] + counters + [f"{c} TFLOP/s" for c in flops]
+    print("| " + " | ".join(head) + " |")
+    print("|" + "---|" * len(head))
+    for name, ds in sorted(per.items(), key=lambda kv: -sum(d["us"] for d in kv[1])):
+        short = name.split("(")[0]
+        cells = [f"`{short}`", str(len(ds)), f"{np.mean([d['us'] for d in ds]):.2f}"]
+        cells += [f"{np.mean([d['c'].get(c, 0.0) for d in ds]):.4g}" for c in counters]
+        cells += [f"{np.mean([d['c'].get(c, 0.0) / (d['us'] * 1e-6) / 1e12 for d in ds]):.3f}" for c in flops]
+        print("| " + " | ".join(cells) + " |")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -453,13 +631,29 @@ def main():
                     help="C_alpha solver: its incomplete factor, the MR approximate inverse (3 steps, drop "
                          "tolerance 0.01, 20 entries per column), or 5 preconditioned Chebyshev steps")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-rhs", type=int, default=3, help="right-hand sides the oracle solves for the baseline")
+    ap.add_argument("--cpu-rhs", type=int, default=8,
+                    help="right-hand sides the oracle solves with all OpenMP threads for the baseline")
+    ap.add_argument("--cpu-rhs-1t", type=int, default=1,
+                    help="right-hand sides the oracle solves with one thread for the baseline (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="launch a plain copy kernel of known size (for hardware-counter scaling)")
     ap.add_argument("--batch-count", type=int, default=256)
+    ap.add_argument("--cpu-systems", type=int, default=24, help="c4: systems the oracle solves for the baseline")
+    ap.add_argument("--trace-summary", default=None,
+                    help="summarise a rocprofv3 kernel_trace.csv (per kernel: dispatches, average duration over all "
+                         "and over those of at least --min-us) and exit; needs no GPU")
+    ap.add_argument("--pmc-summary", default=None,
+                    help="summarise a rocprofv3 --pmc counter_collection.csv per kernel and exit; needs no GPU")
+    ap.add_argument("--min-us", type=float, default=EARLY_EXIT_US)
     ap.add_argument("--burst", type=int, default=64, help="c5: requests in the saturation burst")
     ap.add_argument("--requests", type=int, default=200, help="c5: requests per Poisson load level")
     args = ap.parse_args()
+    if args.trace_summary:
+        trace_summary(args.trace_summary, args.min_us)
+        return
+    if args.pmc_summary:
+        pmc_summary(args.pmc_summary, args.min_us)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 (the design notes describe "
                                    "how the path would shard across GPUs)"}))

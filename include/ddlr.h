@@ -364,8 +364,11 @@ ddlr_status ddlr_set_lowrank(ddlr_prec *h, int32_t variant, int32_t k, const dou
 ddlr_status ddlr_profile(ddlr_prec *h, int32_t on);
 
 /* Accumulated milliseconds and launches of kernel class `which` since
- * profiling was enabled.  Synchronises the device. */
-ddlr_status ddlr_profile_read(ddlr_prec *h, int32_t which, double *total_ms, int64_t *launches);
+ * profiling was enabled, counting only launches that took at least min_us
+ * microseconds (0: all; a launch after every column of a solve has converged
+ * returns at once, and a threshold of a few microseconds leaves those out).
+ * Synchronises the device. */
+ddlr_status ddlr_profile_read(ddlr_prec *h, int32_t which, double min_us, double *total_ms, int64_t *launches);
 
 /* Improving a given preconditioner (Sec. on improving a given
  * preconditioner): continues the Lanczos run of ddlr_setup (kept on the

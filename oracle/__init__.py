@@ -21,24 +21,38 @@ FACTOR_IC, FACTOR_ILDL, FACTOR_EXACT = 0, 1, 2
 CORDER_MULTICOLOR, CORDER_NATURAL = 0, 1
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (-O2, OpenMP)."""
-    if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-Wall", "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB)
-    return _LIB
+def build(force: bool = True, out: str = _LIB, native: bool = False) -> str:
+    """Compile the oracle with gcc (-O3, OpenMP).  native=True adds
+    -march=native: only for a build made and run on the same machine (the
+    CPU-baseline timing builds its own copy that way)."""
+    if force or not os.path.exists(out):
+        tmp = out + ".tmp"
+        flags = ["-O3"] + (["-march=native"] if native else [])
+        subprocess.check_call(["gcc", *flags, "-fopenmp", "-fPIC", "-shared", "-Wall", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, out)
+    return out
 
 
 _lib = None
+_lib_path = _LIB
+
+
+def use_native_build(directory: str) -> str:
+    """Builds an -O3 -march=native copy of the oracle in `directory` and makes
+    it the one this process loads (call before the first Oracle)."""
+    global _lib_path
+    if _lib is not None:
+        raise RuntimeError("the oracle library is already loaded")
+    _lib_path = build(True, os.path.join(directory, "libddlr_oracle_native.so"), native=True)
+    return _lib_path
 
 
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        if _lib_path == _LIB and (not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC)):
             build()
-        lib = C.CDLL(_LIB)
+        lib = C.CDLL(_lib_path)
         P = C.c_void_p
         lib.orc_create.restype = P
         lib.orc_create.argtypes = [C.c_int64, P, P, P, P, C.c_int32, C.c_double, C.c_int, C.c_int,
@@ -76,6 +90,8 @@ def _load():
         lib.orc_cheb.argtypes = [P, P]
         lib.orc_threads.restype = C.c_int
         lib.orc_threads.argtypes = []
+        lib.orc_set_threads.restype = None
+        lib.orc_set_threads.argtypes = [C.c_int]
         _lib = lib
     return _lib
 
@@ -83,6 +99,11 @@ def _load():
 def threads() -> int:
     """OpenMP threads the oracle's parallel loops use."""
     return int(_load().orc_threads())
+
+
+def set_threads(n: int) -> None:
+    """Sets the OpenMP thread count of the oracle's parallel loops."""
+    _load().orc_set_threads(int(n))
 
 
 def _p(a: np.ndarray):

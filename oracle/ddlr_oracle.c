@@ -1781,6 +1781,15 @@ int orc_gmres(const orc_t *o, int nrhs, const double *b, double *x, int restart,
 /* y = A x in user order (used by tests for residuals) */
 void orc_matvec(const orc_t *o, const double *x, double *y) { csr_mv(&o->A, o->n, x, y); }
 
+/* sets the number of OpenMP threads of the parallel loops */
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* number of OpenMP threads the parallel loops above run with */
 int orc_threads(void) {
 #ifdef _OPENMP

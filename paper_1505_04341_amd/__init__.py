@@ -132,7 +132,7 @@ def load_library(path: str = LIB_PATH):
         "ddlr_get_lowrank": (I32, [P, P, P]),
         "ddlr_set_lowrank": (I32, [P, I32, I32, P, P]),
         "ddlr_profile": (I32, [P, I32]),
-        "ddlr_profile_read": (I32, [P, I32, P, P]),
+        "ddlr_profile_read": (I32, [P, I32, C.c_double, P, P]),
         "ddlr_batch_create": (I32, [I32, P, P]),
         "ddlr_batch_offsets": (I32, [P, P]),
         "ddlr_batch_apply": (I32, [P, P, P, P]),
@@ -601,11 +601,12 @@ def ddlr_profile(prec: Prec, on: bool = True):
     _check(load_library().ddlr_profile(prec.handle, 1 if on else 0), "ddlr_profile")
 
 
-def ddlr_profile_read(prec: Prec, which: int):
-    """(total milliseconds, launches) of a kernel class since profiling was enabled."""
+def ddlr_profile_read(prec: Prec, which: int, min_us: float = 0.0):
+    """(total milliseconds, launches) of a kernel class since profiling was
+    enabled, counting launches of at least min_us microseconds."""
     t = C.c_double()
     cnt = C.c_int64()
-    _check(load_library().ddlr_profile_read(prec.handle, int(which), C.byref(t), C.byref(cnt)),
+    _check(load_library().ddlr_profile_read(prec.handle, int(which), float(min_us), C.byref(t), C.byref(cnt)),
            "ddlr_profile_read")
     return t.value, cnt.value
 

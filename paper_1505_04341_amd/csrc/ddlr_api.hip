@@ -3452,7 +3452,7 @@ ddlr_status ddlr_profile(ddlr_prec* h, int32_t on) {
     return DDLR_OK;
 }
 
-ddlr_status ddlr_profile_read(ddlr_prec* h, int32_t which, double* total_ms, int64_t* launches) {
+ddlr_status ddlr_profile_read(ddlr_prec* h, int32_t which, double min_us, double* total_ms, int64_t* launches) {
     if (!dev_ok(h)) return h ? DDLR_E_DEVICE : DDLR_E_INVALID;
     if (which < 0 || which >= kProfClasses || !total_ms || !launches) {
         g_err = "bad profile query";
@@ -3462,13 +3462,16 @@ ddlr_status ddlr_profile_read(ddlr_prec* h, int32_t which, double* total_ms, int
         HIPCHK(hipSetDevice(h->device));
         HIPCHK(hipDeviceSynchronize());
         double t = 0.0;
+        int64_t cnt = 0;
         for (auto& pr : h->prof_ev[which]) {
             float ms = 0.f;
             HIPCHK(hipEventElapsedTime(&ms, pr.first, pr.second));
+            if (1e3 * ms < min_us) continue;
             t += ms;
+            ++cnt;
         }
         *total_ms = t;
-        *launches = (int64_t)h->prof_ev[which].size();
+        *launches = cnt;
     } catch (const SetupError& e) {
         return fail_status(e);
     }
