@@ -413,7 +413,16 @@ ddlr_status ddlr_extend_lowrank(ddlr_prec *h, int32_t k, int32_t more_steps, int
  * A0-only timing above does not decide it for PCG); the fastest (minimum over
  * its chunks) is kept, but replayed chunks with the interface solve in line
  * stay unless another candidate is more than 1 % faster.
- * cg_* below report that measurement. */
+ * cg_* below report that measurement.  For systems of at most 262,144 rows
+ * with the interface block factored, DDLR-1 or A0 alone, FP64 or FP32 and
+ * k <= 64, PCG may also run in the persistent form: one launch per solve, one
+ * workgroup per right-hand side running every step of every iteration (the
+ * A0 solve over the merged levels of all blocks, the solve vector in LDS when
+ * it fits) until its residual test holds.  Its workgroup size (256, 512 or
+ * 1024 threads) is tuned on its first launch (a few timed iterations each);
+ * the first such solve of a column count runs persistent and records its time
+ * per iteration, and once the chunked forms are measured the faster per
+ * iteration is used.  DDLR_CG_PERSIST=1 / 0 forces it on / off. */
 typedef struct {
     int32_t nrhs;            /* column count the shape is for */
     int32_t ring_cols;       /* right-hand sides per workgroup of the block triangular solve */
@@ -433,6 +442,11 @@ typedef struct {
                                 being measured, or nothing to overlap */
     float cg_eager_in_line_us; /* fastest eager chunk with the interface solve in line (0: not timed) */
     float cg_graph_in_line_us; /* fastest replayed chunk with the interface solve in line (0: not timed) */
+    int32_t cg_persist;        /* PCG in the persistent form (one launch per solve, one workgroup per column):
+                                  1 chosen, 0 not (not eligible, or slower per iteration), -1 not yet decided */
+    float cg_persist_us;       /* measured time per iteration of the persistent form (0: not measured) */
+    int32_t persist_threads;   /* workgroup size the persistent form uses (0: not tuned yet) */
+    float persist_nt_us[3];    /* its tuning: time per iteration with 256, 512, 1024 threads */
 } ddlr_tuning;
 ddlr_status ddlr_tune(ddlr_prec *h, int32_t nrhs, int32_t retune, ddlr_tuning *out, void *stream);
 
@@ -458,6 +472,14 @@ typedef struct ddlr_batch ddlr_batch;
 ddlr_status ddlr_batch_create(int32_t nsys, ddlr_prec *const *members, ddlr_batch **out);
 ddlr_status ddlr_batch_offsets(const ddlr_batch *b, int64_t *offsets);
 /* y = M_q^{-1} x_q for every system q. */
+/* The batch's solve form: persistent = 1 when ddlr_batch_solve runs the
+ * persistent PCG (one workgroup per system, the whole solve in one launch,
+ * captured once into a HIP graph and replayed; batches whose rank exceeds 64
+ * or with DDLR_BATCH_PERSIST=0 replay captured chunks of 8 iterations
+ * instead); threads = the workgroup size tuned on the first solve (0 before);
+ * us_per_iter[3] = its tuning: microseconds per iteration of the launch with
+ * 256, 512 and 1024 threads. */
+ddlr_status ddlr_batch_tuning(const ddlr_batch *b, int32_t *persistent, int32_t *threads, float *us_per_iter);
 ddlr_status ddlr_batch_apply(ddlr_batch *b, const double *x, double *y, void *stream);
 /* PCG on every system (x0 = 0, stopping rule of Sec. 5); info: host array of
  * nsys entries.  Synchronises the stream.  DDLR_E_NO_CONVERGENCE if any system

@@ -46,14 +46,17 @@ class ddlr_tuning(C.Structure):
                 ("a0_us", C.c_float * 4), ("a0_no_overlap_us", C.c_float), ("a0_thin_us", C.c_float * 2),
                 ("a0_plain_us", C.c_float), ("cg_graph", C.c_int32), ("cg_eager_us", C.c_float),
                 ("cg_graph_us", C.c_float), ("cg_overlap", C.c_int32), ("cg_eager_in_line_us", C.c_float),
-                ("cg_graph_in_line_us", C.c_float)]
+                ("cg_graph_in_line_us", C.c_float), ("cg_persist", C.c_int32), ("cg_persist_us", C.c_float),
+                ("persist_threads", C.c_int32), ("persist_nt_us", C.c_float * 3)]
 
     def as_dict(self):
         return dict(nrhs=self.nrhs, ring_cols=self.ring_cols, overlap=self.overlap, ring_threads=self.ring_threads,
                     a0_us=list(self.a0_us), a0_no_overlap_us=self.a0_no_overlap_us, a0_thin_us=list(self.a0_thin_us),
                     a0_plain_us=self.a0_plain_us, cg_graph=self.cg_graph, cg_eager_us=self.cg_eager_us,
                     cg_graph_us=self.cg_graph_us, cg_overlap=self.cg_overlap,
-                    cg_eager_in_line_us=self.cg_eager_in_line_us, cg_graph_in_line_us=self.cg_graph_in_line_us)
+                    cg_eager_in_line_us=self.cg_eager_in_line_us, cg_graph_in_line_us=self.cg_graph_in_line_us,
+                    cg_persist=self.cg_persist, cg_persist_us=self.cg_persist_us,
+                    persist_threads=self.persist_threads, persist_nt_us=list(self.persist_nt_us))
 
 
 class ddlr_solve_options(C.Structure):
@@ -136,6 +139,7 @@ def load_library(path: str = LIB_PATH):
         "ddlr_batch_create": (I32, [I32, P, P]),
         "ddlr_batch_offsets": (I32, [P, P]),
         "ddlr_batch_apply": (I32, [P, P, P, P]),
+        "ddlr_batch_tuning": (I32, [P, P, P, P]),
         "ddlr_batch_solve": (I32, [P, P, P, P, P, P]),
         "ddlr_batch_destroy": (None, [P]),
         "ddlr_server_create": (I32, [I32, C.c_size_t, I32, P]),
@@ -476,6 +480,14 @@ def ddlr_batch_apply(batch: Batch, x, y, stream=None):
     return y
 
 
+def ddlr_batch_tuning(batch: Batch) -> dict:
+    """The batch's solve form and the tuned workgroup size of its persistent launch."""
+    pers, nt = C.c_int32(), C.c_int32()
+    us = (C.c_float * 3)()
+    _check(load_library().ddlr_batch_tuning(batch.handle, C.byref(pers), C.byref(nt), us), "ddlr_batch_tuning")
+    return dict(persistent=pers.value, threads=nt.value, us_per_iter=list(us))
+
+
 def ddlr_batch_solve(batch: Batch, b, x, *, maxit: int = 500, rtol: float = 1e-6, stream=None):
     """PCG on every system; returns (status, list of per-system info dicts)."""
     lib = load_library()
@@ -617,7 +629,7 @@ def ddlr_version() -> int:
 
 EXPORTED = ["ddlr_version", "ddlr_options_default", "ddlr_solve_options_default", "ddlr_setup", "ddlr_apply",
             "ddlr_apply_noalloc", "ddlr_ctx_create", "ddlr_ctx_usage", "ddlr_ctx_destroy", "ddlr_export_setup",
-            "ddlr_import_setup", "ddlr_partition_box",
+            "ddlr_import_setup", "ddlr_partition_box", "ddlr_batch_tuning",
             "ddlr_a0_solve", "ddlr_spmv", "ddlr_solve", "ddlr_query", "ddlr_get_ordering", "ddlr_get_factor",
             "ddlr_get_cinv",
             "ddlr_get_levels", "ddlr_get_lanczos", "ddlr_get_lowrank", "ddlr_set_lowrank", "ddlr_profile",

@@ -23,6 +23,7 @@
 #include "ddlr.h"
 #include "host_setup.hpp"
 #include "kernels.hpp"
+#include "pcg_persist.hpp"
 
 using namespace ddlr;
 
@@ -225,6 +226,28 @@ struct Workspace {
 
 }  // namespace
 
+// Device tables of the persistent PCG form (pcg_persist.hpp) for a handle or
+// a batch: systems, merged level lists, A in CSR (device order), lanes and
+// results, the lanes' right-hand sides and search directions, and the tuned
+// workgroup size.
+struct PersistData {
+    DMem mem;
+    std::vector<PSys> hsys;
+    PSys* sys = nullptr;
+    int32_t *mlev = nullptr, *mrow = nullptr;
+    int64_t* arp = nullptr;
+    int32_t* aci = nullptr;
+    double* av = nullptr;
+    PLane* lanes = nullptr;
+    PRes* res = nullptr;
+    double *b = nullptr, *p = nullptr;  // n x cols each
+    int cols = 0;                       // columns b and p hold
+    int nlanes = 0;                     // lanes the tables hold
+    size_t lds_bytes = 0;               // dynamic LDS of a launch (largest solve vector that fits)
+    int nt = 0;                         // threads per workgroup (256, 512, 1024); 0: not tuned
+    float nt_us[3] = {0, 0, 0};         // tuning: microseconds per iteration for 256, 512, 1024 threads
+};
+
 // A device and a device-memory budget shared by the handles created in it
 // (ddlr_ctx_create).  Freed when the context is destroyed and its last handle
 // is gone.
@@ -315,6 +338,11 @@ struct ddlr_prec {
         }
     };
     std::map<int, CgMode> cg_mode;
+    // persistent PCG (one launch per solve, one workgroup per column): tables,
+    // and per column count the measured time per iteration (-1: not measured)
+    std::unique_ptr<PersistData> pers;
+    std::map<int, double> pers_us;
+    int pers_mode = 2;  // 2 measured, 1 forced on, 0 off (DDLR_CG_PERSIST)
     int ov_override = -1;  // >= 0: overlap for the A0 solves being launched (set by the CG driver)
     bool lr_plain = false;                      // low-rank kernels without MFMA (comparison only)
     // the interface block's level kernels run on a side stream, overlapping the
@@ -2037,6 +2065,11 @@ void drop_graphs(ddlr_prec* h) {
     }
     h->cg_graphs.clear();
     h->cg_mode.clear();  // launch shapes changed: measure again
+    if (h->pers) {       // the persistent form's tables hold the rank and c0
+        h->pers->mem.release();
+        h->pers.reset();
+    }
+    h->pers_us.clear();
 }
 
 // The streams belong to the device's shared set; only the events are the handle's.
@@ -2074,6 +2107,7 @@ void device_init(ddlr_prec* h, int cheb_iters, int no_autotune) {
     if (const char* env = std::getenv("DDLR_NO_OVERLAP")) h->overlap = env[0] != '1';
     h->tune_mode = no_autotune ? 0 : 1;
     if (const char* env = std::getenv("DDLR_CG_GRAPH")) h->graph_mode = env[0] == '0' ? 0 : env[0] == '1' ? 1 : 2;
+    if (const char* env = std::getenv("DDLR_CG_PERSIST")) h->pers_mode = env[0] == '0' ? 0 : env[0] == '1' ? 1 : 2;
     if (const char* env = std::getenv("DDLR_LEVEL_KERNEL"))  // "rows" / "cols" force one form
         h->level_kernel = env[0] == 'r' ? 1 : env[0] == 'c' ? 2 : 0;
     if (has_cpart(h)) {
@@ -2822,6 +2856,287 @@ static void pcg_dev(ddlr_prec* h, int nr, const ddlr_solve_options& o, hipStream
     HIPCHK(hipStreamWaitEvent(ust, h->ev_out, 0));
 }
 
+namespace {
+
+// ------------------------------------------------------------ persistent PCG
+
+constexpr int64_t kPersistMaxRows = 262144;  // rows of a system the one-workgroup form is tried on
+
+// Merged levels of one system (plan P, rows offset by r0 in the concatenated
+// device order): level j lists the device rows of level j of every block,
+// blocks in order.  Appends level starts to mlev (the caller closes the list).
+void persist_levels(const HostPlan& P, int64_t r0, std::vector<int32_t>& mlev, std::vector<int32_t>& mrow,
+                    int32_t& l0, int32_t& l1) {
+    int depth = 0;
+    for (int32_t b = 0; b <= P.p; ++b) depth = std::max(depth, P.blk_lvl[b + 1] - P.blk_lvl[b]);
+    l0 = (int32_t)mlev.size();
+    for (int j = 0; j < depth; ++j) {
+        mlev.push_back((int32_t)mrow.size());
+        for (int32_t b = 0; b <= P.p; ++b) {
+            const int32_t l = P.blk_lvl[b] + j;
+            if (l >= P.blk_lvl[b + 1]) continue;
+            for (int32_t d = P.lvl_ptr[l]; d < P.lvl_ptr[l + 1]; ++d) mrow.push_back((int32_t)(r0 + d));
+        }
+    }
+    l1 = (int32_t)mlev.size();
+}
+
+// A of one plan in device order as CSR, rows and columns offset by r0.
+void persist_csr(const HostPlan& P, int64_t r0, std::vector<int64_t>& arp, std::vector<int32_t>& aci,
+                 std::vector<double>& av) {
+    for (int64_t d = 0; d < P.n; ++d) {
+        const int64_t i = P.dev2int[d];
+        for (int64_t t = P.A.rp[i]; t < P.A.rp[i + 1]; ++t) {
+            aci.push_back((int32_t)(r0 + P.int2dev[P.A.ci[t]]));
+            av.push_back(P.A.v[t]);
+        }
+        arp.push_back((int64_t)aci.size());
+    }
+}
+
+// Largest dynamic LDS a persistent launch may take on device `dev`.
+size_t persist_lds_budget(int dev) {
+    if (const char* env = std::getenv("DDLR_PERSIST_NO_LDS"))  // "1": every solve vector in global memory
+        if (env[0] == '1') return 0;
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0) {
+        (void)hipGetLastError();
+        v = 65536;
+    }
+    const size_t cap = std::min<size_t>((size_t)v, 160 * 1024);
+    return cap > 8192 ? cap - 8192 : 0;  // the static reduction arrays and a margin
+}
+
+// Tables for the systems of `plans` (one per system; offsets r0 / s0 / d0, c0
+// per system, rank k), tsz = bytes of the preconditioner's type.
+void persist_build(PersistData& PD, const std::vector<const HostPlan*>& plans, const std::vector<int64_t>& roff,
+                   const std::vector<int64_t>& soff, const std::vector<int>& ks, const std::vector<double>& c0s,
+                   int kstride, size_t tsz, int dev) {
+    std::vector<int32_t> mlev, mrow;
+    std::vector<int64_t> arp(1, 0);
+    std::vector<int32_t> aci;
+    std::vector<double> av;
+    const size_t budget = persist_lds_budget(dev);
+    PD.hsys.clear();
+    PD.lds_bytes = 0;
+    for (size_t q = 0; q < plans.size(); ++q) {
+        const HostPlan& P = *plans[q];
+        PSys S{};
+        S.r0 = roff[q];
+        S.s0 = soff[q];
+        S.d0 = (int64_t)q * kstride;
+        S.n = (int32_t)P.n;
+        S.m = (int32_t)P.m;
+        S.s = (int32_t)P.s;
+        S.k = ks[q];
+        S.c0 = c0s[q];
+        persist_levels(P, roff[q], mlev, mrow, S.l0, S.l1);
+        persist_csr(P, roff[q], arp, aci, av);
+        const size_t need = (size_t)P.n * tsz;
+        S.lds = need <= budget;
+        if (S.lds) PD.lds_bytes = std::max(PD.lds_bytes, need);
+        PD.hsys.push_back(S);
+    }
+    mlev.push_back((int32_t)mrow.size());
+    PD.sys = PD.mem.upload(PD.hsys);
+    PD.mlev = PD.mem.upload(mlev);
+    PD.mrow = PD.mem.upload(mrow);
+    PD.arp = PD.mem.upload(arp);
+    PD.aci = PD.mem.upload(aci);
+    PD.av = PD.mem.upload(av);
+}
+
+// Lane table and per-lane results / vectors for `nl` lanes (columns `cols`).
+void persist_lanes(PersistData& PD, const std::vector<PLane>& lanes, int cols, int64_t n) {
+    if ((int)lanes.size() > PD.nlanes) {
+        PD.lanes = PD.mem.alloc<PLane>(lanes.size());
+        PD.res = PD.mem.alloc<PRes>(lanes.size());
+        PD.nlanes = (int)lanes.size();
+    }
+    HIPCHK(hipMemcpy(PD.lanes, lanes.data(), lanes.size() * sizeof(PLane), hipMemcpyHostToDevice));
+    if (cols > PD.cols) {
+        PD.b = PD.mem.alloc<double>((size_t)n * cols);
+        PD.p = PD.mem.alloc<double>((size_t)n * cols);
+        PD.cols = cols;
+    }
+}
+
+template <typename T, int NT>
+void persist_launch_nt(ddlr_prec* h, PersistData& PD, int nl, double tol2, int maxit, hipStream_t st) {
+    const DevFactors<T>& F = factors<T>(h);
+    Workspace& W = h->ws;
+    const bool multi = h->nsys > 1;
+    const T* U = F.U;
+    const int ustride = std::max(1, h->k);
+    const double* dco = multi ? h->dvecs : h->dvec;
+    auto kern = k_pcg_persist<T, NT>;
+    hipLaunchKernelGGL(kern, dim3(nl), dim3(NT), PD.lds_bytes, st, PD.sys, PD.lanes, PD.arp, PD.aci, PD.av, PD.mlev,
+                       PD.mrow, h->lrp, h->lci, F.lv, h->urp, h->uci, F.uv, F.dinv, h->erp, h->eci, F.ev, h->etrp,
+                       h->etci, F.etv, U, ustride, dco, PD.b, W.x, W.r, PD.p, W.q, W.z, (T*)W.a1, (T*)W.ys,
+                       (T*)W.ws, h->ndev, h->sdev, tol2, maxit, PD.res);
+    LAUNCHCHK();
+}
+
+// Allows the kernel of `nt` threads the dynamic LDS of PD (above 64 KB it must be
+// raised first; done once per device, kernel and size, outside any capture).
+template <typename T, int NT> void persist_lds_attr_nt(int dev, size_t bytes) {
+    static std::mutex mu;
+    static std::map<std::pair<int, size_t>, bool> done;
+    if (bytes <= 65536) return;
+    std::lock_guard<std::mutex> lk(mu);
+    bool& d = done[std::make_pair(dev, bytes)];
+    if (d) return;
+    HIPCHK(hipFuncSetAttribute((const void*)k_pcg_persist<T, NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)bytes));
+    d = true;
+}
+
+void persist_lds_attr(const ddlr_prec* h, const PersistData& PD, int nt) {
+    const bool f64 = h->precision == DDLR_FP64;
+    switch (nt) {
+    case 256:
+        f64 ? persist_lds_attr_nt<double, 256>(h->device, PD.lds_bytes) : persist_lds_attr_nt<float, 256>(h->device, PD.lds_bytes);
+        break;
+    case 512:
+        f64 ? persist_lds_attr_nt<double, 512>(h->device, PD.lds_bytes) : persist_lds_attr_nt<float, 512>(h->device, PD.lds_bytes);
+        break;
+    default:
+        f64 ? persist_lds_attr_nt<double, 1024>(h->device, PD.lds_bytes)
+            : persist_lds_attr_nt<float, 1024>(h->device, PD.lds_bytes);
+    }
+}
+
+template <typename T> void persist_launch_T(ddlr_prec* h, PersistData& PD, int nl, double tol2, int maxit,
+                                            hipStream_t st, int nt) {
+    switch (nt) {
+    case 256: persist_launch_nt<T, 256>(h, PD, nl, tol2, maxit, st); break;
+    case 512: persist_launch_nt<T, 512>(h, PD, nl, tol2, maxit, st); break;
+    default: persist_launch_nt<T, 1024>(h, PD, nl, tol2, maxit, st);
+    }
+}
+
+void persist_launch(ddlr_prec* h, PersistData& PD, int nl, double tol2, int maxit, hipStream_t st, int nt) {
+    if (!h->capturing) persist_lds_attr(h, PD, nt);
+    if (h->precision == DDLR_FP64) persist_launch_T<double>(h, PD, nl, tol2, maxit, st, nt);
+    else persist_launch_T<float>(h, PD, nl, tol2, maxit, st, nt);
+}
+
+// Tunes the workgroup size of a persistent launch over nl lanes whose b is in
+// PD.b: each candidate runs min(maxit, 12) iterations, timed with events on
+// st; the fastest per iteration is kept.  The trial results are overwritten by
+// the real solve.
+void persist_tune(ddlr_prec* h, PersistData& PD, int nl, double tol2, int maxit, hipStream_t st) {
+    if (const char* env = std::getenv("DDLR_PERSIST_NT")) {
+        const int v = std::atoi(env);
+        if (v == 256 || v == 512 || v == 1024) {
+            PD.nt = v;
+            return;
+        }
+    }
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    const int trial = std::min(maxit, 12);
+    const int cand[3] = {256, 512, 1024};
+    float best = 1e30f;
+    std::vector<PRes> r(nl);
+    for (int c = 0; c < 3; ++c) {
+        HIPCHK(hipEventRecord(e0, st));
+        persist_launch(h, PD, nl, tol2, trial, st, cand[c]);
+        HIPCHK(hipEventRecord(e1, st));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        HIPCHK(hipMemcpy(r.data(), PD.res, nl * sizeof(PRes), hipMemcpyDeviceToHost));
+        int its = 1;
+        for (const PRes& x : r) its = std::max(its, x.its);
+        PD.nt_us[c] = 1e3f * ms / (float)its;
+        if (PD.nt_us[c] < best) {
+            best = PD.nt_us[c];
+            PD.nt = cand[c];
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+}
+
+// Whether a handle may solve with the persistent form: CG, DDLR-1 or A0 only,
+// C_alpha factored, FP64 or FP32, rank at most kPersistMaxK.
+bool persist_eligible(const ddlr_prec* h) {
+    return (h->variant == DDLR_1 || h->variant == DDLR_VARIANT_A0) && h->plan.csolve == 0 &&
+           h->precision != DDLR_FP32_UK_BF16 && h->k <= kPersistMaxK && h->nsys == 1;
+}
+
+// Tables of a single-system handle, built on first use.
+PersistData& persist_single(ddlr_prec* h) {
+    if (!h->pers) {
+        std::unique_ptr<PersistData> PD(new PersistData());
+        PD->mem.budget = budget_of(h);
+        persist_build(*PD, {&h->plan}, {0}, {0}, {h->variant == DDLR_1 ? h->k : 0}, {h->c0}, 0,
+                      h->precision == DDLR_FP64 ? sizeof(double) : sizeof(float), h->device);
+        h->pers = std::move(PD);
+    }
+    return *h->pers;
+}
+
+// Whether ddlr_solve runs an nr-column CG with the persistent form: forced by
+// DDLR_CG_PERSIST, else measured -- the first eligible solve of a column count
+// runs persistent (its time per iteration is kept), the following ones run the
+// chunked forms until their measurement is done, then the faster per
+// iteration is used.
+bool persist_choose(ddlr_prec* h, int nr) {
+    if (h->pers_mode == 0 || !persist_eligible(h) || h->ndev > kPersistMaxRows || h->capturing) return false;
+    if (h->pers_mode == 1) return true;
+    auto it = h->pers_us.find(nr);
+    if (it == h->pers_us.end()) return true;
+    const ddlr_prec::CgMode& m = h->cg_mode[nr];
+    if (m.graph < 0) return false;
+    const double chunk = m.us[m.graph][m.ov + 1];
+    return it->second < chunk / 8.0;
+}
+
+// One persistent launch solving nr columns (b, x user order); fills info,
+// returns DDLR_E_NO_CONVERGENCE if a column hit maxit.
+ddlr_status persist_solve(ddlr_prec* h, int nr, const double* b, int64_t ldb, double* x, int64_t ldx,
+                          const ddlr_solve_options& o, hipStream_t st, ddlr_solve_info* info) {
+    PersistData& PD = persist_single(h);
+    const int64_t n = h->ndev;
+    std::vector<PLane> lanes(nr);
+    for (int c = 0; c < nr; ++c) lanes[c] = PLane{0, c};
+    persist_lanes(PD, lanes, nr, n);
+    hipLaunchKernelGGL((k_gather<double, double>), grid2(n, nr), dim3(256), 0, st, n, nr, h->perm_dev, b, ldb, PD.b,
+                       n);
+    LAUNCHCHK();
+    const double tol2 = o.rtol * o.rtol;
+    if (PD.nt == 0) persist_tune(h, PD, nr, tol2, o.maxit, st);
+    const bool measure = h->pers_mode == 2 && !h->pers_us.count(nr);
+    const auto t0 = std::chrono::steady_clock::now();
+    persist_launch(h, PD, nr, tol2, o.maxit, st, PD.nt);
+    hipLaunchKernelGGL((k_scatter<double, double>), grid2(n, nr), dim3(256), 0, st, n, nr, h->perm_dev, h->ws.x, n, x,
+                       ldx);
+    LAUNCHCHK();
+    std::vector<PRes> r(nr);
+    HIPCHK(hipMemcpyAsync(r.data(), PD.res, nr * sizeof(PRes), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    int its = 1;
+    ddlr_status out = DDLR_OK;
+    for (int c = 0; c < nr; ++c) {
+        ddlr_solve_info& inf = info[c];
+        inf.iters = r[c].its;
+        inf.status = r[c].status == 0 ? DDLR_OK : DDLR_E_NO_CONVERGENCE;
+        inf.relres = r[c].bb > 0 ? std::sqrt(r[c].rr / r[c].bb) : 0.0;
+        inf.relres_true = r[c].bb > 0 ? std::sqrt(r[c].rtrue / r[c].bb) : 0.0;
+        if (r[c].status) out = DDLR_E_NO_CONVERGENCE;
+        its = std::max(its, r[c].its);
+    }
+    if (measure)
+        h->pers_us[nr] = std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count() / its;
+    return out;
+}
+
+
+}  // namespace
+
 extern "C" {
 
 ddlr_status ddlr_solve(ddlr_prec* h, int32_t nrhs, const double* b, int64_t ldb, double* x, int64_t ldx,
@@ -2854,6 +3169,11 @@ ddlr_status ddlr_solve(ddlr_prec* h, int32_t nrhs, const double* b, int64_t ldb,
             ensure_ws(h, nr);
             autotune(h, nr, st, false);
             Workspace& W = h->ws;
+            if (o.method == 0 && persist_choose(h, nr)) {
+                const ddlr_status ps = persist_solve(h, nr, b + c0 * ldb, ldb, x + c0 * ldx, ldx, o, st, info + c0);
+                if (ps != DDLR_OK) result = ps;
+                continue;
+            }
             hipLaunchKernelGGL((k_gather<double, double>), grid2(n, nr), dim3(256), 0, st, n, nr,
                                h->perm_dev, b + c0 * ldb, ldb, W.r, n);
             LAUNCHCHK();
@@ -3543,6 +3863,17 @@ ddlr_status ddlr_tune(ddlr_prec* h, int32_t nrhs, int32_t retune, ddlr_tuning* o
         out->cg_eager_in_line_us = val(m.us[0][1]);
         out->cg_graph_in_line_us = val(m.us[1][1]);
     }
+    out->cg_persist = h->pers_mode == 0 || !persist_eligible(h) || h->ndev > kPersistMaxRows ? 0 : -1;
+    if (auto pi = h->pers_us.find(nrhs); pi != h->pers_us.end()) {
+        out->cg_persist_us = (float)pi->second;
+        if (auto mi = h->cg_mode.find(nrhs); mi != h->cg_mode.end() && mi->second.graph >= 0)
+            out->cg_persist = pi->second < mi->second.us[mi->second.graph][mi->second.ov + 1] / 8.0 ? 1 : 0;
+    }
+    if (h->pers_mode == 1 && out->cg_persist != 0) out->cg_persist = 1;
+    if (h->pers) {
+        out->persist_threads = h->pers->nt;
+        for (int c = 0; c < 3; ++c) out->persist_nt_us[c] = h->pers->nt_us[c];
+    }
     auto it = h->tune.find(nrhs);
     if (it == h->tune.end()) {  // batches: fixed shape
         out->ring_cols = 1;
@@ -3616,6 +3947,12 @@ struct ddlr_batch {
     hipGraphExec_t gexec = nullptr;
     int graph_chunk = 0, graph_maxit = -1;
     double graph_tol2 = -1.0;
+    // persistent form: one workgroup per system, the launch captured into a graph
+    std::unique_ptr<PersistData> pers;
+    hipGraph_t pgraph = nullptr;
+    hipGraphExec_t pgexec = nullptr;
+    int pg_maxit = -1, pg_nt = 0;
+    double pg_tol2 = -1.0;
 };
 
 namespace {
@@ -3623,6 +3960,10 @@ namespace {
 constexpr int kBatchChunk = 8;  // CG iterations per graph launch
 
 void batch_release(ddlr_batch* B) {
+    if (B->pgexec) (void)hipGraphExecDestroy(B->pgexec);
+    if (B->pgraph) (void)hipGraphDestroy(B->pgraph);
+    if (B->pers) B->pers->mem.release();
+    B->pers.reset();
     if (B->gexec) (void)hipGraphExecDestroy(B->gexec);
     if (B->graph) (void)hipGraphDestroy(B->graph);
     if (B->own) (void)hipStreamDestroy(B->own);
@@ -3746,6 +4087,24 @@ ddlr_status ddlr_batch_create(int32_t nsys, ddlr_prec* const* members, ddlr_batc
             h->dvecs = h->lrmem.upload(dv);
             h->c0s = h->lrmem.upload(c0);
         }
+        // persistent form (rank at most kPersistMaxK), unless DDLR_BATCH_PERSIST=0
+        const char* pe = std::getenv("DDLR_BATCH_PERSIST");
+        if (h->k <= kPersistMaxK && !(pe && pe[0] == '0')) {
+            std::vector<const HostPlan*> plans(nsys);
+            std::vector<int> ks(nsys);
+            std::vector<double> c0v(nsys);
+            for (int q = 0; q < nsys; ++q) {
+                plans[q] = &members[q]->plan;
+                ks[q] = h->variant == DDLR_1 ? members[q]->k : 0;
+                c0v[q] = members[q]->c0;
+            }
+            B->pers.reset(new PersistData());
+            persist_build(*B->pers, plans, B->roff, B->soff, ks, c0v, std::max(1, h->k),
+                          h->precision == DDLR_FP64 ? sizeof(double) : sizeof(float), h->device);
+            std::vector<PLane> lanes(nsys);
+            for (int q = 0; q < nsys; ++q) lanes[q] = PLane{q, 0};
+            persist_lanes(*B->pers, lanes, 1, h->ndev);
+        }
         HIPCHK(hipStreamCreateWithFlags(&B->own, hipStreamNonBlocking));  // default priority
         HIPCHK(hipEventCreateWithFlags(&B->ev_in, hipEventDisableTiming));
         HIPCHK(hipEventCreateWithFlags(&B->ev_out, hipEventDisableTiming));
@@ -3769,6 +4128,17 @@ ddlr_status ddlr_batch_offsets(const ddlr_batch* B, int64_t* offsets) {
         return DDLR_E_INVALID;
     }
     std::copy(B->roff.begin(), B->roff.end(), offsets);
+    return DDLR_OK;
+}
+
+ddlr_status ddlr_batch_tuning(const ddlr_batch* B, int32_t* persistent, int32_t* threads, float* us_per_iter) {
+    if (!B || !persistent || !threads || !us_per_iter) {
+        g_err = "null argument";
+        return DDLR_E_INVALID;
+    }
+    *persistent = B->pers ? 1 : 0;
+    *threads = B->pers ? B->pers->nt : 0;
+    for (int c = 0; c < 3; ++c) us_per_iter[c] = B->pers ? B->pers->nt_us[c] : 0.f;
     return DDLR_OK;
 }
 
@@ -3803,6 +4173,62 @@ ddlr_status ddlr_batch_solve(ddlr_batch* B, const double* b, double* x, const dd
     }
     const double tol2 = o.rtol * o.rtol;
     ddlr_status result = DDLR_OK;
+    if (B->pers) {
+        try {
+            HIPCHK(hipSetDevice(h->device));
+            hipStream_t ust = (hipStream_t)stream, st = B->own;
+            HIPCHK(hipEventRecord(B->ev_in, ust));
+            HIPCHK(hipStreamWaitEvent(st, B->ev_in, 0));
+            PersistData& PD = *B->pers;
+            const int64_t n = h->ndev;
+            const int ns = B->nsys;
+            hipLaunchKernelGGL((k_gather<double, double>), dim3(grid_for(n)), dim3(256), 0, st, n, 1, h->perm_dev, b,
+                               n, PD.b, n);
+            LAUNCHCHK();
+            if (PD.nt == 0) persist_tune(h, PD, ns, tol2, o.maxit, st);
+            if (!B->pgexec || B->pg_tol2 != tol2 || B->pg_maxit != o.maxit || B->pg_nt != PD.nt) {
+                if (B->pgexec) (void)hipGraphExecDestroy(B->pgexec);
+                if (B->pgraph) (void)hipGraphDestroy(B->pgraph);
+                B->pgexec = nullptr;
+                B->pgraph = nullptr;
+                persist_lds_attr(h, PD, PD.nt);
+                h->capturing = true;
+                HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+                persist_launch(h, PD, ns, tol2, o.maxit, st, PD.nt);
+                hipGraph_t g = nullptr;
+                const hipError_t ec = hipStreamEndCapture(st, &g);
+                h->capturing = false;
+                HIPCHK(ec);
+                B->pgraph = g;
+                HIPCHK(hipGraphInstantiate(&B->pgexec, B->pgraph, nullptr, nullptr, 0));
+                B->pg_tol2 = tol2;
+                B->pg_maxit = o.maxit;
+                B->pg_nt = PD.nt;
+            }
+            HIPCHK(hipGraphLaunch(B->pgexec, st));
+            hipLaunchKernelGGL((k_scatter<double, double>), dim3(grid_for(n)), dim3(256), 0, st, n, 1, h->perm_dev,
+                               h->ws.x, n, x, n);
+            LAUNCHCHK();
+            std::vector<PRes> r(ns);
+            HIPCHK(hipMemcpyAsync(r.data(), PD.res, ns * sizeof(PRes), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            HIPCHK(hipEventRecord(B->ev_out, st));
+            HIPCHK(hipStreamWaitEvent(ust, B->ev_out, 0));
+            for (int q = 0; q < ns; ++q) {
+                ddlr_solve_info& inf = info[q];
+                inf.iters = r[q].its;
+                inf.status = r[q].status == 0 ? DDLR_OK : DDLR_E_NO_CONVERGENCE;
+                inf.relres = r[q].bb > 0 ? std::sqrt(r[q].rr / r[q].bb) : 0.0;
+                inf.relres_true = r[q].bb > 0 ? std::sqrt(r[q].rtrue / r[q].bb) : 0.0;
+                if (r[q].status) result = DDLR_E_NO_CONVERGENCE;
+            }
+        } catch (const SetupError& e) {
+            h->capturing = false;
+            return fail_status(e);
+        }
+        if (result != DDLR_OK) g_err = "some systems did not converge";
+        return result;
+    }
     try {
         HIPCHK(hipSetDevice(h->device));
         hipStream_t ust = (hipStream_t)stream, st = B->own;

@@ -454,8 +454,14 @@ def test_serving_same_alone_and_in_mix():
     hs, refs, bsets = [], [], []
     for q, cfg in enumerate(cfgs):
         say("serving setup", q)
-        h = D.ddlr_setup(cfg["A"], cfg["part"], cfg["p"], cfg["k"], 1, lanczos_steps=cfg["m"],
-                         lanczos_start=w.lanczos_start(cfg["A"].n, 0), precision=D.FP32)
+        # the reference solves take the served form's lane-phase CG (the persistent form sums its dot
+        # products in another order)
+        os.environ["DDLR_CG_PERSIST"] = "0"
+        try:
+            h = D.ddlr_setup(cfg["A"], cfg["part"], cfg["p"], cfg["k"], 1, lanczos_steps=cfg["m"],
+                             lanczos_start=w.lanczos_start(cfg["A"].n, 0), precision=D.FP32)
+        finally:
+            os.environ.pop("DDLR_CG_PERSIST")
         b, _ = w.rhs_from_solution(cfg["A"], 10 * q, 6)
         bt = torch.from_numpy(np.ascontiguousarray(b.T)).to(DEV)
         xt = torch.zeros_like(bt)
