@@ -418,8 +418,8 @@ ddlr_status ddlr_extend_lowrank(ddlr_prec *h, int32_t k, int32_t more_steps, int
  * k <= 64, PCG may also run in the persistent form: one launch per solve, one
  * workgroup per right-hand side running every step of every iteration (the
  * A0 solve over the merged levels of all blocks, the solve vector in LDS when
- * it fits) until its residual test holds.  Its workgroup size (256, 512 or
- * 1024 threads) is tuned on its first launch (a few timed iterations each);
+ * it fits) until its residual test holds.  Its workgroup size (64 to 1024
+ * threads) is tuned on its first launch (a few timed iterations each);
  * the first such solve of a column count runs persistent and records its time
  * per iteration, and once the chunked forms are measured the faster per
  * iteration is used.  DDLR_CG_PERSIST=1 / 0 forces it on / off. */
@@ -446,7 +446,7 @@ typedef struct {
                                   1 chosen, 0 not (not eligible, or slower per iteration), -1 not yet decided */
     float cg_persist_us;       /* measured time per iteration of the persistent form (0: not measured) */
     int32_t persist_threads;   /* workgroup size the persistent form uses (0: not tuned yet) */
-    float persist_nt_us[3];    /* its tuning: time per iteration with 256, 512, 1024 threads */
+    float persist_nt_us[5];    /* its tuning: time per iteration with 64, 128, 256, 512, 1024 threads */
 } ddlr_tuning;
 ddlr_status ddlr_tune(ddlr_prec *h, int32_t nrhs, int32_t retune, ddlr_tuning *out, void *stream);
 
@@ -477,8 +477,8 @@ ddlr_status ddlr_batch_offsets(const ddlr_batch *b, int64_t *offsets);
  * captured once into a HIP graph and replayed; batches whose rank exceeds 64
  * or with DDLR_BATCH_PERSIST=0 replay captured chunks of 8 iterations
  * instead); threads = the workgroup size tuned on the first solve (0 before);
- * us_per_iter[3] = its tuning: microseconds per iteration of the launch with
- * 256, 512 and 1024 threads. */
+ * us_per_iter[5] = its tuning: microseconds per iteration of the launch with
+ * 64, 128, 256, 512 and 1024 threads. */
 ddlr_status ddlr_batch_tuning(const ddlr_batch *b, int32_t *persistent, int32_t *threads, float *us_per_iter);
 ddlr_status ddlr_batch_apply(ddlr_batch *b, const double *x, double *y, void *stream);
 /* PCG on every system (x0 = 0, stopping rule of Sec. 5); info: host array of

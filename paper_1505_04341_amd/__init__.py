@@ -47,7 +47,7 @@ class ddlr_tuning(C.Structure):
                 ("a0_plain_us", C.c_float), ("cg_graph", C.c_int32), ("cg_eager_us", C.c_float),
                 ("cg_graph_us", C.c_float), ("cg_overlap", C.c_int32), ("cg_eager_in_line_us", C.c_float),
                 ("cg_graph_in_line_us", C.c_float), ("cg_persist", C.c_int32), ("cg_persist_us", C.c_float),
-                ("persist_threads", C.c_int32), ("persist_nt_us", C.c_float * 3)]
+                ("persist_threads", C.c_int32), ("persist_nt_us", C.c_float * 5)]
 
     def as_dict(self):
         return dict(nrhs=self.nrhs, ring_cols=self.ring_cols, overlap=self.overlap, ring_threads=self.ring_threads,
@@ -483,7 +483,7 @@ def ddlr_batch_apply(batch: Batch, x, y, stream=None):
 def ddlr_batch_tuning(batch: Batch) -> dict:
     """The batch's solve form and the tuned workgroup size of its persistent launch."""
     pers, nt = C.c_int32(), C.c_int32()
-    us = (C.c_float * 3)()
+    us = (C.c_float * 5)()
     _check(load_library().ddlr_batch_tuning(batch.handle, C.byref(pers), C.byref(nt), us), "ddlr_batch_tuning")
     return dict(persistent=pers.value, threads=nt.value, us_per_iter=list(us))
 

@@ -234,7 +234,10 @@ struct PersistData {
     DMem mem;
     std::vector<PSys> hsys;
     PSys* sys = nullptr;
-    int32_t *mlev = nullptr, *mrow = nullptr;
+    int4* meta = nullptr;  // per merged level: rows, widths, ELL starts
+    int32_t *mrow = nullptr, *fcol = nullptr, *bcol = nullptr;
+    void *fval = nullptr, *bval = nullptr;  // ELL values in the preconditioner's type
+    void* dq = nullptr;                      // D^{-1} in merged-level order, same type
     int64_t* arp = nullptr;
     int32_t* aci = nullptr;
     double* av = nullptr;
@@ -243,9 +246,10 @@ struct PersistData {
     double *b = nullptr, *p = nullptr;  // n x cols each
     int cols = 0;                       // columns b and p hold
     int nlanes = 0;                     // lanes the tables hold
-    size_t lds_bytes = 0;               // dynamic LDS of a launch (largest solve vector that fits)
+    size_t lds_bytes = 0;               // dynamic LDS of a launch: largest solve vector that fits, then the
+    int meta_off = 0;                   // level metadata of the lane, staged at this byte offset
     int nt = 0;                         // threads per workgroup (256, 512, 1024); 0: not tuned
-    float nt_us[3] = {0, 0, 0};         // tuning: microseconds per iteration for 256, 512, 1024 threads
+    float nt_us[5] = {0, 0, 0, 0, 0};   // tuning: microseconds per iteration, 64 .. 1024 threads
 };
 
 // A device and a device-memory budget shared by the handles created in it
@@ -2864,21 +2868,74 @@ constexpr int64_t kPersistMaxRows = 262144;  // rows of a system the one-workgro
 
 // Merged levels of one system (plan P, rows offset by r0 in the concatenated
 // device order): level j lists the device rows of level j of every block,
-// blocks in order.  Appends level starts to mlev (the caller closes the list).
-void persist_levels(const HostPlan& P, int64_t r0, std::vector<int32_t>& mlev, std::vector<int32_t>& mrow,
-                    int32_t& l0, int32_t& l1) {
+// blocks in order, with slot-major ELL copies of their rows of L (forward) and
+// of L^T (backward), entries in the CSR order of the other A0-solve kernels
+// (L: ascending internal column; L^T: ascending internal row), short rows
+// padded with their own index and weight 0.  Appends to the batch-wide lists.
+struct MergedLevels {
+    std::vector<int4> meta;
+    std::vector<int32_t> mrow, fcol, bcol;
+    std::vector<double> fval, bval, dq;
+};
+
+void persist_levels(const HostPlan& P, int64_t r0, MergedLevels& M, int32_t& l0, int32_t& l1) {
+    const int64_t n = P.n;
+    // L^T rows of every device row, in ascending internal row order
+    std::vector<int32_t> tcnt(n + 1, 0);
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t t = P.L.rp[i]; t < P.L.rp[i + 1]; ++t) tcnt[P.int2dev[P.L.ci[t]] + 1]++;
+    for (int64_t d = 0; d < n; ++d) tcnt[d + 1] += tcnt[d];
+    std::vector<int32_t> tcol(tcnt[n]);
+    std::vector<double> tval(tcnt[n]);
+    std::vector<int32_t> fill(tcnt.begin(), tcnt.end() - 1);
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t t = P.L.rp[i]; t < P.L.rp[i + 1]; ++t) {
+            const int32_t q = fill[P.int2dev[P.L.ci[t]]]++;
+            tcol[q] = P.int2dev[i];
+            tval[q] = P.L.v[t];
+        }
     int depth = 0;
     for (int32_t b = 0; b <= P.p; ++b) depth = std::max(depth, P.blk_lvl[b + 1] - P.blk_lvl[b]);
-    l0 = (int32_t)mlev.size();
+    l0 = (int32_t)M.meta.size();
+    std::vector<int32_t> rows;
     for (int j = 0; j < depth; ++j) {
-        mlev.push_back((int32_t)mrow.size());
+        rows.clear();
         for (int32_t b = 0; b <= P.p; ++b) {
             const int32_t l = P.blk_lvl[b] + j;
             if (l >= P.blk_lvl[b + 1]) continue;
-            for (int32_t d = P.lvl_ptr[l]; d < P.lvl_ptr[l + 1]; ++d) mrow.push_back((int32_t)(r0 + d));
+            for (int32_t d = P.lvl_ptr[l]; d < P.lvl_ptr[l + 1]; ++d) rows.push_back(d);
         }
+        const int nr = (int)rows.size();
+        int fw = 0, bw = 0;
+        for (int32_t d : rows) {
+            const int64_t i = P.dev2int[d];
+            fw = std::max(fw, (int)(P.L.rp[i + 1] - P.L.rp[i]));
+            bw = std::max(bw, tcnt[d + 1] - tcnt[d]);
+        }
+        if (fw > 0xffff || bw > 0x7fff) throw SetupError{DDLR_E_INVALID, "a factor row is too long for the persistent form"};
+        M.meta.push_back(int4{(int)M.mrow.size(), fw | (bw << 16), (int)M.fcol.size(), (int)M.bcol.size()});
+        for (int32_t d : rows) {
+            M.mrow.push_back((int32_t)(r0 + d));
+            M.dq.push_back(1.0 / P.D[P.dev2int[d]]);
+        }
+        for (int u = 0; u < fw; ++u)
+            for (int32_t d : rows) {
+                const int64_t i = P.dev2int[d];
+                const int64_t t = P.L.rp[i] + u;
+                const bool has = t < P.L.rp[i + 1];
+                M.fcol.push_back((int32_t)(r0 + (has ? P.int2dev[P.L.ci[t]] : d)));
+                M.fval.push_back(has ? P.L.v[t] : 0.0);
+            }
+        for (int u = 0; u < bw; ++u)
+            for (int32_t d : rows) {
+                const int32_t t = tcnt[d] + u;
+                const bool has = t < tcnt[d + 1];
+                M.bcol.push_back((int32_t)(r0 + (has ? tcol[t] : d)));
+                M.bval.push_back(has ? tval[t] : 0.0);
+            }
+        (void)nr;
     }
-    l1 = (int32_t)mlev.size();
+    l1 = (int32_t)M.meta.size();
 }
 
 // A of one plan in device order as CSR, rows and columns offset by r0.
@@ -2912,13 +2969,24 @@ size_t persist_lds_budget(int dev) {
 void persist_build(PersistData& PD, const std::vector<const HostPlan*>& plans, const std::vector<int64_t>& roff,
                    const std::vector<int64_t>& soff, const std::vector<int>& ks, const std::vector<double>& c0s,
                    int kstride, size_t tsz, int dev) {
-    std::vector<int32_t> mlev, mrow;
+    MergedLevels M;
     std::vector<int64_t> arp(1, 0);
     std::vector<int32_t> aci;
     std::vector<double> av;
-    const size_t budget = persist_lds_budget(dev);
+    size_t budget = persist_lds_budget(dev);
     PD.hsys.clear();
     PD.lds_bytes = 0;
+    // the level metadata of the deepest system takes (levels + 1) x 16 bytes of LDS
+    int maxlev = 0;
+    for (const HostPlan* P : plans) {
+        int depth = 0;
+        for (int32_t b = 0; b <= P->p; ++b) depth = std::max(depth, P->blk_lvl[b + 1] - P->blk_lvl[b]);
+        maxlev = std::max(maxlev, depth);
+    }
+    const size_t meta_bytes = 16 * (size_t)(maxlev + 1);
+    if (meta_bytes + 16 > persist_lds_budget(dev) + 8192 - 4096)
+        throw SetupError{DDLR_E_INVALID, "too many levels for the persistent form"};
+    budget = budget > meta_bytes ? budget - meta_bytes : 0;
     for (size_t q = 0; q < plans.size(); ++q) {
         const HostPlan& P = *plans[q];
         PSys S{};
@@ -2930,17 +2998,37 @@ void persist_build(PersistData& PD, const std::vector<const HostPlan*>& plans, c
         S.s = (int32_t)P.s;
         S.k = ks[q];
         S.c0 = c0s[q];
-        persist_levels(P, roff[q], mlev, mrow, S.l0, S.l1);
+        persist_levels(P, roff[q], M, S.l0, S.l1);
         persist_csr(P, roff[q], arp, aci, av);
         const size_t need = (size_t)P.n * tsz;
         S.lds = need <= budget;
         if (S.lds) PD.lds_bytes = std::max(PD.lds_bytes, need);
         PD.hsys.push_back(S);
     }
-    mlev.push_back((int32_t)mrow.size());
+    PD.meta_off = (int)((PD.lds_bytes + 15) & ~(size_t)15);
+    PD.lds_bytes = PD.meta_off + meta_bytes;
+    M.meta.push_back(int4{(int)M.mrow.size(), 0, (int)M.fcol.size(), (int)M.bcol.size()});
+    // clamped prefetch loads of a level without entries read up to 1024 entries past its start
+    for (int u = 0; u < 1024; ++u) {
+        M.fcol.push_back(0);
+        M.fval.push_back(0.0);
+        M.bcol.push_back(0);
+        M.bval.push_back(0.0);
+    }
     PD.sys = PD.mem.upload(PD.hsys);
-    PD.mlev = PD.mem.upload(mlev);
-    PD.mrow = PD.mem.upload(mrow);
+    PD.meta = PD.mem.upload(M.meta);
+    PD.mrow = PD.mem.upload(M.mrow);
+    PD.fcol = PD.mem.upload(M.fcol);
+    PD.bcol = PD.mem.upload(M.bcol);
+    if (tsz == sizeof(double)) {
+        PD.fval = PD.mem.upload(M.fval);
+        PD.bval = PD.mem.upload(M.bval);
+        PD.dq = PD.mem.upload(M.dq);
+    } else {
+        PD.fval = PD.mem.upload(std::vector<float>(M.fval.begin(), M.fval.end()));
+        PD.bval = PD.mem.upload(std::vector<float>(M.bval.begin(), M.bval.end()));
+        PD.dq = PD.mem.upload(std::vector<float>(M.dq.begin(), M.dq.end()));
+    }
     PD.arp = PD.mem.upload(arp);
     PD.aci = PD.mem.upload(aci);
     PD.av = PD.mem.upload(av);
@@ -2970,10 +3058,11 @@ void persist_launch_nt(ddlr_prec* h, PersistData& PD, int nl, double tol2, int m
     const int ustride = std::max(1, h->k);
     const double* dco = multi ? h->dvecs : h->dvec;
     auto kern = k_pcg_persist<T, NT>;
-    hipLaunchKernelGGL(kern, dim3(nl), dim3(NT), PD.lds_bytes, st, PD.sys, PD.lanes, PD.arp, PD.aci, PD.av, PD.mlev,
-                       PD.mrow, h->lrp, h->lci, F.lv, h->urp, h->uci, F.uv, F.dinv, h->erp, h->eci, F.ev, h->etrp,
-                       h->etci, F.etv, U, ustride, dco, PD.b, W.x, W.r, PD.p, W.q, W.z, (T*)W.a1, (T*)W.ys,
-                       (T*)W.ws, h->ndev, h->sdev, tol2, maxit, PD.res);
+    hipLaunchKernelGGL(kern, dim3(nl), dim3(NT), PD.lds_bytes, st, PD.sys, PD.lanes, PD.arp, PD.aci, PD.av, PD.meta,
+                       PD.mrow, PD.fcol, (const T*)PD.fval, PD.bcol, (const T*)PD.bval, (const T*)PD.dq, h->erp,
+                       h->eci, F.ev, h->etrp,
+                       h->etci, F.etv, U, ustride, dco, PD.b, W.x, W.r, PD.p, W.q, W.z, (T*)W.a1, (T*)W.a2, (T*)W.ys,
+                       (T*)W.ws, h->ndev, h->sdev, PD.meta_off, tol2, maxit, PD.res);
     LAUNCHCHK();
 }
 
@@ -2994,6 +3083,12 @@ template <typename T, int NT> void persist_lds_attr_nt(int dev, size_t bytes) {
 void persist_lds_attr(const ddlr_prec* h, const PersistData& PD, int nt) {
     const bool f64 = h->precision == DDLR_FP64;
     switch (nt) {
+    case 64:
+        f64 ? persist_lds_attr_nt<double, 64>(h->device, PD.lds_bytes) : persist_lds_attr_nt<float, 64>(h->device, PD.lds_bytes);
+        break;
+    case 128:
+        f64 ? persist_lds_attr_nt<double, 128>(h->device, PD.lds_bytes) : persist_lds_attr_nt<float, 128>(h->device, PD.lds_bytes);
+        break;
     case 256:
         f64 ? persist_lds_attr_nt<double, 256>(h->device, PD.lds_bytes) : persist_lds_attr_nt<float, 256>(h->device, PD.lds_bytes);
         break;
@@ -3009,6 +3104,8 @@ void persist_lds_attr(const ddlr_prec* h, const PersistData& PD, int nt) {
 template <typename T> void persist_launch_T(ddlr_prec* h, PersistData& PD, int nl, double tol2, int maxit,
                                             hipStream_t st, int nt) {
     switch (nt) {
+    case 64: persist_launch_nt<T, 64>(h, PD, nl, tol2, maxit, st); break;
+    case 128: persist_launch_nt<T, 128>(h, PD, nl, tol2, maxit, st); break;
     case 256: persist_launch_nt<T, 256>(h, PD, nl, tol2, maxit, st); break;
     case 512: persist_launch_nt<T, 512>(h, PD, nl, tol2, maxit, st); break;
     default: persist_launch_nt<T, 1024>(h, PD, nl, tol2, maxit, st);
@@ -3028,7 +3125,7 @@ void persist_launch(ddlr_prec* h, PersistData& PD, int nl, double tol2, int maxi
 void persist_tune(ddlr_prec* h, PersistData& PD, int nl, double tol2, int maxit, hipStream_t st) {
     if (const char* env = std::getenv("DDLR_PERSIST_NT")) {
         const int v = std::atoi(env);
-        if (v == 256 || v == 512 || v == 1024) {
+        if (v == 64 || v == 128 || v == 256 || v == 512 || v == 1024) {
             PD.nt = v;
             return;
         }
@@ -3037,10 +3134,10 @@ void persist_tune(ddlr_prec* h, PersistData& PD, int nl, double tol2, int maxit,
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
     const int trial = std::min(maxit, 12);
-    const int cand[3] = {256, 512, 1024};
+    const int cand[5] = {64, 128, 256, 512, 1024};
     float best = 1e30f;
     std::vector<PRes> r(nl);
-    for (int c = 0; c < 3; ++c) {
+    for (int c = 0; c < 5; ++c) {
         HIPCHK(hipEventRecord(e0, st));
         persist_launch(h, PD, nl, tol2, trial, st, cand[c]);
         HIPCHK(hipEventRecord(e1, st));
@@ -3872,7 +3969,7 @@ ddlr_status ddlr_tune(ddlr_prec* h, int32_t nrhs, int32_t retune, ddlr_tuning* o
     if (h->pers_mode == 1 && out->cg_persist != 0) out->cg_persist = 1;
     if (h->pers) {
         out->persist_threads = h->pers->nt;
-        for (int c = 0; c < 3; ++c) out->persist_nt_us[c] = h->pers->nt_us[c];
+        for (int c = 0; c < 5; ++c) out->persist_nt_us[c] = h->pers->nt_us[c];
     }
     auto it = h->tune.find(nrhs);
     if (it == h->tune.end()) {  // batches: fixed shape
@@ -4138,7 +4235,7 @@ ddlr_status ddlr_batch_tuning(const ddlr_batch* B, int32_t* persistent, int32_t*
     }
     *persistent = B->pers ? 1 : 0;
     *threads = B->pers ? B->pers->nt : 0;
-    for (int c = 0; c < 3; ++c) us_per_iter[c] = B->pers ? B->pers->nt_us[c] : 0.f;
+    for (int c = 0; c < 5; ++c) us_per_iter[c] = B->pers ? B->pers->nt_us[c] : 0.f;
     return DDLR_OK;
 }
 

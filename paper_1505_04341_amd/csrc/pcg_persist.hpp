@@ -11,8 +11,9 @@
 //     the A0 solve walks "merged levels": level j of every block of the system
 //     (the p subdomain blocks and the interface block are independent, so
 //     their level-j rows go together), forward over L then backward over L^T
-//     with D^{-1}; the solve vector stays in LDS when the system fits, else in
-//     a global buffer of the lane;
+//     with D^{-1}, each level's entries in a slot-major ELL copy and the next
+//     level's loaded while the current one is computed; the solve vector
+//     stays in LDS when the system fits, else in a global buffer of the lane;
 //     y = E^T z1, the k coefficients d .* (U_k^T y), w = c0 y + U_k coef,
 //     v = r + E w, and the second A0 solve;
 //   the CG scalars, and p = z + beta p.
@@ -33,7 +34,7 @@ struct PSys {
     int64_t d0;      // offset of d_1..d_k in the coefficient array
     int32_t n, m;    // rows; interior rows (the interface rows follow)
     int32_t s, k;    // interface rows; rank of the correction (0: A0 alone)
-    int32_t l0, l1;  // merged levels l0..l1-1 (row lists in mrow[mlev[j] .. mlev[j+1]])
+    int32_t l0, l1;  // merged levels l0..l1-1 (level metadata meta[j], row lists in mrow)
     int32_t lds;     // 1: the solve vector fits the dynamic LDS
     int32_t pad;
     double c0;       // eq. (gkt): G^{-1} = c0 I + U_k diag(d) U_k^T
@@ -66,58 +67,182 @@ template <int NT> __device__ __forceinline__ double wg_sum(double v, double* red
     return s;
 }
 
+// Per merged level j: meta[j] = {first entry of its rows in mrow, forward width
+// | backward width << 16, start of its forward ELL entries, start of its
+// backward ones}; meta[j + 1].x ends the row list.  ELL entries of a level with
+// nr rows are stored slot-major (entry u of row r at base + u * nr + r); a row
+// shorter than the level's width is padded with its own index and weight 0.
+// The solve vector is zeroed before the first sweep, so a padded term adds 0
+// times a finite value (the row sum keeps its value; its terms keep their
+// CSR order).
+constexpr int kPersistKW = 4;  // entries per row held in registers one level ahead
+
+template <typename T> struct PLev {
+    int nr, fw, i;
+    T in;  // forward: input x_i; backward: D_i^{-1}
+    int c[kPersistKW];
+    T v[kPersistKW];
+};
+
+// Loads the first row (threadIdx.x, clamped) of merged level j into registers.
+// kBwd selects the backward entries; inq holds the forward input or D^{-1}
+// in merged-level order.
+template <typename T, bool kBwd>
+__device__ __forceinline__ void plev_load(PLev<T>& L, int j, const int4* __restrict__ meta,
+                                          const int32_t* __restrict__ mrow, const int32_t* __restrict__ ecol,
+                                          const T* __restrict__ eval, const T* inq) {
+    const int4 m = meta[j];
+    const int a = __builtin_amdgcn_readfirstlane(m.x);
+    L.nr = __builtin_amdgcn_readfirstlane(meta[j + 1].x) - a;
+    L.fw = __builtin_amdgcn_readfirstlane(kBwd ? (m.y >> 16) : (m.y & 0xffff));
+    const int base = __builtin_amdgcn_readfirstlane(kBwd ? m.w : m.z);
+    const int r = min((int)threadIdx.x, L.nr - 1);
+    L.i = mrow[a + r];
+    L.in = inq[a + r];  // input or D^{-1}, stored in merged-level order: no load waits for another
+#pragma unroll
+    for (int u = 0; u < kPersistKW; ++u) {
+        const int q = base + min(u, max(L.fw, 1) - 1) * L.nr + r;  // clamped: every load in bounds
+        const int c = ecol[q];
+        const T v = eval[q];
+        L.c[u] = u < L.fw ? c : L.i;
+        L.v[u] = u < L.fw ? v : T(0);
+    }
+}
+
+// Row sums of merged level j: the prefetched first row of each thread, then
+// the rows beyond the first NT (loaded here), entries beyond kPersistKW too.
+template <typename T, int NT, bool kBwd>
+__device__ __forceinline__ void plev_step(const PLev<T>& L, int j, int64_t off, const int4* __restrict__ meta,
+                                          const int32_t* __restrict__ mrow, const int32_t* __restrict__ ecol,
+                                          const T* __restrict__ eval, const T* inq, T* vec) {
+    const int nr = L.nr;
+    if ((int)threadIdx.x < nr) {
+        T s = kBwd ? vec[L.i - off] * L.in : L.in;
+#pragma unroll
+        for (int u = 0; u < kPersistKW; ++u) s = fnms(s, L.v[u], vec[L.c[u] - off]);
+        if (L.fw > kPersistKW) {
+            const int4 m = meta[j];
+            const int base = kBwd ? m.w : m.z;
+            for (int u = kPersistKW; u < L.fw; ++u) {
+                const int q = base + u * nr + (int)threadIdx.x;
+                s = fnms(s, eval[q], vec[ecol[q] - off]);
+            }
+        }
+        vec[L.i - off] = s;
+    }
+    if (nr > NT) {
+        const int4 m = meta[j];
+        const int base = kBwd ? m.w : m.z;
+        for (int r = NT + (int)threadIdx.x; r < nr; r += NT) {
+            const int i = mrow[m.x + r];
+            T s = kBwd ? vec[i - off] * inq[m.x + r] : inq[m.x + r];
+            for (int u = 0; u < L.fw; ++u) {
+                const int q = base + u * nr + r;
+                s = fnms(s, eval[q], vec[ecol[q] - off]);
+            }
+            vec[i - off] = s;
+        }
+    }
+}
+
+// Barrier between two levels.  With the solve vector in LDS only LDS traffic
+// must be complete (the next level's global loads stay in flight across it);
+// with the solve vector in global memory a full workgroup fence.
+template <bool kLds> __device__ __forceinline__ void level_barrier() {
+    if constexpr (kLds) lds_barrier();
+    else __syncthreads();
+}
+
+// Levels in flight: the next kPersistDepth - 1 levels' first rows are loaded
+// while the current level is computed, so a global load has that many level
+// steps to arrive.
+template <typename T> struct PersistDepth { static constexpr int value = sizeof(T) == 4 ? 5 : 4; };
+
+// One sweep over merged levels l0..l1-1 (forward ascending, backward
+// descending).  As in the block triangular-solve kernels, the steady state
+// runs behind an unconditional prologue (every load of a group is issued on
+// the single path into its use, so the compiler's load-counter waits leave
+// the newer levels' loads in flight); a conditional tail finishes.
+template <typename T, int NT, bool kBwd, bool kLds>
+__device__ __forceinline__ void plev_sweep(int l0, int l1, int64_t off, const int4* __restrict__ meta,
+                                           const int32_t* __restrict__ mrow, const int32_t* __restrict__ ecol,
+                                           const T* __restrict__ eval, const T* inq, T* vec) {
+    constexpr int kD = PersistDepth<T>::value;
+    const int nl = l1 - l0;
+    if (nl <= 0) return;
+    auto lev = [&](int q) { return kBwd ? l1 - 1 - q : l0 + q; };
+    PLev<T> buf[kD];
+    int q0 = 0;
+    if (nl >= 2 * kD - 1) {
+#pragma unroll
+        for (int u = 0; u < kD - 1; ++u) plev_load<T, kBwd>(buf[u], lev(u), meta, mrow, ecol, eval, inq);
+        for (; q0 + 2 * kD - 1 <= nl; q0 += kD) {
+#pragma unroll
+            for (int u = 0; u < kD; ++u) {
+                plev_load<T, kBwd>(buf[(u + kD - 1) % kD], lev(q0 + u + kD - 1), meta, mrow, ecol, eval, inq);
+                plev_step<T, NT, kBwd>(buf[u], lev(q0 + u), off, meta, mrow, ecol, eval, inq, vec);
+                level_barrier<kLds>();
+            }
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < kD - 1; ++u)
+            if (u < nl) plev_load<T, kBwd>(buf[u], lev(u), meta, mrow, ecol, eval, inq);
+    }
+    for (; q0 < nl; q0 += kD) {
+#pragma unroll
+        for (int u = 0; u < kD; ++u) {
+            const int q = q0 + u;
+            if (q < nl) {
+                if (q + kD - 1 < nl)
+                    plev_load<T, kBwd>(buf[(u + kD - 1) % kD], lev(q + kD - 1), meta, mrow, ecol, eval, inq);
+                plev_step<T, NT, kBwd>(buf[u], lev(q), off, meta, mrow, ecol, eval, inq, vec);
+                level_barrier<kLds>();
+            }
+        }
+    }
+}
+
 // The A0 solve of one lane: forward sweep over the merged levels (unit lower L),
-// then backward (z_i = D_i^{-1} y_i - sum_j L_ji z_j).  x: input at global device
-// rows; vec: the solve vector, indexed by local row (LDS) or by global row.
-template <typename T, int NT, bool kLds, typename TIn>
-__device__ void wg_a0_solve(const PSys& S, const int32_t* __restrict__ mlev, const int32_t* __restrict__ mrow,
-                            const int32_t* __restrict__ lrp, const int32_t* __restrict__ lci, const T* __restrict__ lv,
-                            const int32_t* __restrict__ urp, const int32_t* __restrict__ uci, const T* __restrict__ uv,
-                            const T* __restrict__ dinv, const TIn* x, T* vec) {
+// then backward (z_i = D_i^{-1} y_i - sum_j L_ji z_j).  xq: the input and dq:
+// D^{-1}, both in merged-level order; vec: the solve vector, indexed by local
+// row (LDS) or by global row.
+template <typename T, int NT, bool kLds>
+__device__ __forceinline__ void wg_a0_solve(const PSys& S, const int4* __restrict__ meta, const int32_t* __restrict__ mrow,
+                            const int32_t* __restrict__ fcol, const T* __restrict__ fval,
+                            const int32_t* __restrict__ bcol, const T* __restrict__ bval, const T* __restrict__ dq,
+                            const T* xq, T* vec) {
     const int64_t off = kLds ? S.r0 : 0;
-    for (int j = S.l0; j < S.l1; ++j) {
-        const int a = mlev[j], e = mlev[j + 1];
-        for (int q = a + (int)threadIdx.x; q < e; q += NT) {
-            const int i = mrow[q];
-            T s = (T)x[i];
-            const int t1 = lrp[i + 1];
-            for (int t = lrp[i]; t < t1; ++t) s = fnms(s, lv[t], vec[lci[t] - off]);
-            vec[i - off] = s;
-        }
-        __syncthreads();
-    }
-    for (int j = S.l1 - 1; j >= S.l0; --j) {
-        const int a = mlev[j], e = mlev[j + 1];
-        for (int q = a + (int)threadIdx.x; q < e; q += NT) {
-            const int i = mrow[q];
-            T s = vec[i - off] * dinv[i];
-            const int t1 = urp[i + 1];
-            for (int t = urp[i]; t < t1; ++t) s = fnms(s, uv[t], vec[uci[t] - off]);
-            vec[i - off] = s;
-        }
-        __syncthreads();
-    }
+    plev_sweep<T, NT, false, kLds>(S.l0, S.l1, off, meta, mrow, fcol, fval, xq, vec);
+    plev_sweep<T, NT, true, kLds>(S.l0, S.l1, off, meta, mrow, bcol, bval, dq, vec);
+    if constexpr (kLds) __syncthreads();  // the callers' next phases read and write global memory
 }
 
 // z = M^{-1} r for one lane (r, z: double at global device rows; tg: the lane's
 // global T buffer of n rows used when the solve vector is not in LDS; y, w: the
 // lane's interface vectors).  Ends with a barrier.
 template <typename T, int NT, bool kLds>
-__device__ void wg_apply(const PSys& S, const int32_t* __restrict__ mlev, const int32_t* __restrict__ mrow,
-                         const int32_t* __restrict__ lrp, const int32_t* __restrict__ lci, const T* __restrict__ lv,
-                         const int32_t* __restrict__ urp, const int32_t* __restrict__ uci, const T* __restrict__ uv,
-                         const T* __restrict__ dinv, const int32_t* __restrict__ erp, const int32_t* __restrict__ eci,
+__device__ __forceinline__ void wg_apply(const PSys& S, const int4* __restrict__ meta, const int32_t* __restrict__ mrow,
+                         const int32_t* __restrict__ fcol, const T* __restrict__ fval,
+                         const int32_t* __restrict__ bcol, const T* __restrict__ bval, const T* __restrict__ dq,
+                         const int32_t* __restrict__ erp, const int32_t* __restrict__ eci,
                          const T* __restrict__ ev, const int32_t* __restrict__ etrp, const int32_t* __restrict__ etci,
                          const T* __restrict__ etv, const T* __restrict__ U, int ustride,
-                         const double* __restrict__ dcoef, const double* r, double* z, T* tg, T* y, T* w, T* lvec,
-                         double* red, double* coef) {
+                         const double* __restrict__ dcoef, const double* __restrict__ r, double* __restrict__ z, T* tg,
+                         T* tq, T* y, T* w, T* lvec, double* red, double* coef) {
     T* vec = kLds ? lvec : tg;
     const int64_t off = kLds ? S.r0 : 0;
     const int64_t r0 = S.r0, r1 = S.r0 + S.n;
-    wg_a0_solve<T, NT, kLds, double>(S, mlev, mrow, lrp, lci, lv, urp, uci, uv, dinv, r, vec);
+    const int q0 = meta[S.l0].x, q1 = meta[S.l1].x;  // the system's rows in merged-level order
+    // the first solve's input in merged-level order
+#pragma unroll 4
+    for (int q = q0 + (int)threadIdx.x; q < q1; q += NT) tq[q] = (T)r[mrow[q]];
+    __syncthreads();
+    wg_a0_solve<T, NT, kLds>(S, meta, mrow, fcol, fval, bcol, bval, dq, tq, vec);
     if (S.k > 0) {
         const int64_t s0 = S.s0, s1 = S.s0 + S.s;
         // y = E^T z1 over the lane's interface positions (terms in CSR order, one rounding each)
+#pragma unroll 4
         for (int64_t jg = s0 + threadIdx.x; jg < s1; jg += NT) {
             T acc = T(0);
             const int t1 = etrp[jg + 1];
@@ -131,6 +256,7 @@ __device__ void wg_apply(const PSys& S, const int32_t* __restrict__ mlev, const 
             double acc[16];
 #pragma unroll
             for (int u = 0; u < 16; ++u) acc[u] = 0.0;
+#pragma unroll 4
             for (int64_t ig = s0 + threadIdx.x; ig < s1; ig += NT) {
                 const double yi = (double)y[ig];
                 const T* Ui = U + ig * ustride + j0;
@@ -152,6 +278,7 @@ __device__ void wg_apply(const PSys& S, const int32_t* __restrict__ mlev, const 
             __syncthreads();
         }
         // w = c0 y + U_k coef
+#pragma unroll 4
         for (int64_t ig = s0 + threadIdx.x; ig < s1; ig += NT) {
             double acc = S.c0 * (double)y[ig];
             const T* Ui = U + ig * ustride;
@@ -159,16 +286,19 @@ __device__ void wg_apply(const PSys& S, const int32_t* __restrict__ mlev, const 
             w[ig] = (T)acc;
         }
         __syncthreads();
-        // v = r + E w, kept in the lane's global buffer tg (the solve vector may be in LDS)
-        for (int64_t i = r0 + threadIdx.x; i < r1; i += NT) {
+        // v = r + E w, the second solve's input, in merged-level order
+#pragma unroll 4
+        for (int q = q0 + (int)threadIdx.x; q < q1; q += NT) {
+            const int i = mrow[q];
             T acc = (T)r[i];
             const int t1 = erp[i + 1];
             for (int t = erp[i]; t < t1; ++t) acc = fnms(acc, -ev[t], w[eci[t]]);
-            tg[i] = acc;
+            tq[q] = acc;
         }
         __syncthreads();
-        wg_a0_solve<T, NT, kLds, T>(S, mlev, mrow, lrp, lci, lv, urp, uci, uv, dinv, tg, vec);
+        wg_a0_solve<T, NT, kLds>(S, meta, mrow, fcol, fval, bcol, bval, dq, tq, vec);
     }
+#pragma unroll 4
     for (int64_t i = r0 + threadIdx.x; i < r1; i += NT) z[i] = (double)vec[i - off];
     __syncthreads();
 }
@@ -179,34 +309,42 @@ __device__ void wg_apply(const PSys& S, const int32_t* __restrict__ mlev, const 
 template <typename T, int NT>
 __global__ __launch_bounds__(NT) void k_pcg_persist(
     const PSys* __restrict__ sys, const PLane* __restrict__ lanes, const int64_t* __restrict__ arp,
-    const int32_t* __restrict__ aci, const double* __restrict__ av, const int32_t* __restrict__ mlev,
-    const int32_t* __restrict__ mrow, const int32_t* __restrict__ lrp, const int32_t* __restrict__ lci,
-    const T* __restrict__ lv, const int32_t* __restrict__ urp, const int32_t* __restrict__ uci,
-    const T* __restrict__ uv, const T* __restrict__ dinv, const int32_t* __restrict__ erp,
+    const int32_t* __restrict__ aci, const double* __restrict__ av, const int4* meta,
+    const int32_t* __restrict__ mrow, const int32_t* __restrict__ fcol, const T* __restrict__ fval,
+    const int32_t* __restrict__ bcol, const T* __restrict__ bval, const T* __restrict__ dq,
+    const int32_t* __restrict__ erp,
     const int32_t* __restrict__ eci, const T* __restrict__ ev, const int32_t* __restrict__ etrp,
     const int32_t* __restrict__ etci, const T* __restrict__ etv, const T* __restrict__ U, int ustride,
-    const double* __restrict__ dcoef, const double* b, double* x, double* r, double* p, double* q, double* z, T* tg,
-    T* yv, T* wv, int64_t ld, int64_t lds_s, double tol2, int maxit, PRes* __restrict__ res) {
+    const double* __restrict__ dcoef, const double* __restrict__ b, double* __restrict__ x, double* __restrict__ r,
+    double* __restrict__ p, double* __restrict__ q, double* __restrict__ z, T* tg, T* tq,
+    T* yv, T* wv, int64_t ld, int64_t lds_s, int meta_off, double tol2, int maxit, PRes* __restrict__ res) {
     extern __shared__ __attribute__((aligned(16))) unsigned char persist_lds[];
     __shared__ double red[(NT / 64) * 16];
     __shared__ double coef[kPersistMaxK];
     const PLane L = lanes[blockIdx.x];
-    const PSys S = sys[L.sys];
+    PSys S = sys[L.sys];
     const int64_t c = L.col;
-    b += c * ld, x += c * ld, r += c * ld, p += c * ld, q += c * ld, z += c * ld, tg += c * ld;
+    b += c * ld, x += c * ld, r += c * ld, p += c * ld, q += c * ld, z += c * ld, tg += c * ld, tq += c * ld;
     yv += c * lds_s, wv += c * lds_s;
     T* lvec = reinterpret_cast<T*>(persist_lds);
+    // the lane's level metadata, staged in LDS (read at every level step)
+    int4* smeta = reinterpret_cast<int4*>(persist_lds + meta_off);
+    for (int j = threadIdx.x; j <= S.l1 - S.l0; j += NT) smeta[j] = meta[S.l0 + j];
+    __syncthreads();
+    meta = smeta;
+    S.l1 -= S.l0;
+    S.l0 = 0;
     const int64_t r0 = S.r0, r1 = S.r0 + S.n;
-    auto apply = [&]() {
-        if (S.lds)
-            wg_apply<T, NT, true>(S, mlev, mrow, lrp, lci, lv, urp, uci, uv, dinv, erp, eci, ev, etrp, etci, etv, U,
-                                  ustride, dcoef, r, z, tg, yv, wv, lvec, red, coef);
-        else
-            wg_apply<T, NT, false>(S, mlev, mrow, lrp, lci, lv, urp, uci, uv, dinv, erp, eci, ev, etrp, etci, etv, U,
-                                   ustride, dcoef, r, z, tg, yv, wv, lvec, red, coef);
-    };
+    // the solve vector starts at zero (padded ELL terms read it with weight 0)
+    if (S.lds) {
+        for (int i = threadIdx.x; i < S.n; i += NT) lvec[i] = T(0);
+    } else {
+#pragma unroll 4
+        for (int64_t i = r0 + threadIdx.x; i < r1; i += NT) tg[i] = T(0);
+    }
     // x0 = 0, r0 = b
     double acc = 0.0;
+#pragma unroll 4
     for (int64_t i = r0 + threadIdx.x; i < r1; i += NT) {
         const double bi = b[i];
         x[i] = 0.0;
@@ -216,47 +354,52 @@ __global__ __launch_bounds__(NT) void k_pcg_persist(
     const double bb = wg_sum<NT>(acc, red);
     int its = 0;
     double rr = bb;
-    if (bb > 0.0) {
-        apply();
+    // PCG with the preconditioner applied at one place of the loop: each pass
+    // forms z = M^{-1} r, then p (z on the first pass, z + beta p after), then
+    // one iteration's q = A p, alpha, x, r and the residual test.
+    double rz = 0.0;
+    while (bb > 0.0) {
+        if (S.lds)
+            wg_apply<T, NT, true>(S, meta, mrow, fcol, fval, bcol, bval, dq, erp, eci, ev, etrp, etci, etv, U,
+                                  ustride, dcoef, r, z, tg, tq, yv, wv, lvec, red, coef);
+        else
+            wg_apply<T, NT, false>(S, meta, mrow, fcol, fval, bcol, bval, dq, erp, eci, ev, etrp, etci, etv, U,
+                                   ustride, dcoef, r, z, tg, tq, yv, wv, lvec, red, coef);
         acc = 0.0;
+#pragma unroll 4
+        for (int64_t i = r0 + threadIdx.x; i < r1; i += NT) acc += r[i] * z[i];
+        const double rzn = wg_sum<NT>(acc, red);
+        const double beta = its == 0 ? 0.0 : rzn / rz;
+        rz = rzn;
+#pragma unroll 4
+        for (int64_t i = r0 + threadIdx.x; i < r1; i += NT) p[i] = its == 0 ? z[i] : z[i] + beta * p[i];
+        __syncthreads();
+        ++its;
+        acc = 0.0;
+#pragma unroll 4
         for (int64_t i = r0 + threadIdx.x; i < r1; i += NT) {
-            p[i] = z[i];
-            acc += r[i] * z[i];
+            double s = 0.0;
+            const int64_t t1 = arp[i + 1];
+            for (int64_t t = arp[i]; t < t1; ++t) s += av[t] * p[aci[t]];
+            q[i] = s;
+            acc += p[i] * s;
         }
-        double rz = wg_sum<NT>(acc, red);  // includes the barrier that publishes p
-        for (its = 1; its <= maxit; ++its) {
-            acc = 0.0;
-            for (int64_t i = r0 + threadIdx.x; i < r1; i += NT) {
-                double s = 0.0;
-                const int64_t t1 = arp[i + 1];
-                for (int64_t t = arp[i]; t < t1; ++t) s += av[t] * p[aci[t]];
-                q[i] = s;
-                acc += p[i] * s;
-            }
-            const double pq = wg_sum<NT>(acc, red);
-            const double alpha = rz / pq;
-            acc = 0.0;
-            for (int64_t i = r0 + threadIdx.x; i < r1; i += NT) {
-                x[i] += alpha * p[i];
-                const double ri = r[i] - alpha * q[i];
-                r[i] = ri;
-                acc += ri * ri;
-            }
-            rr = wg_sum<NT>(acc, red);
-            if (rr <= tol2 * bb || its == maxit) break;
-            apply();
-            acc = 0.0;
-            for (int64_t i = r0 + threadIdx.x; i < r1; i += NT) acc += r[i] * z[i];
-            const double rzn = wg_sum<NT>(acc, red);
-            const double beta = rzn / rz;
-            rz = rzn;
-            for (int64_t i = r0 + threadIdx.x; i < r1; i += NT) p[i] = z[i] + beta * p[i];
-            __syncthreads();
+        const double pq = wg_sum<NT>(acc, red);
+        const double alpha = rz / pq;
+        acc = 0.0;
+#pragma unroll 4
+        for (int64_t i = r0 + threadIdx.x; i < r1; i += NT) {
+            x[i] += alpha * p[i];
+            const double ri = r[i] - alpha * q[i];
+            r[i] = ri;
+            acc += ri * ri;
         }
-        if (its > maxit) its = maxit;
+        rr = wg_sum<NT>(acc, red);
+        if (rr <= tol2 * bb || its >= maxit) break;
     }
     // true residual ||b - A x||
     acc = 0.0;
+#pragma unroll 4
     for (int64_t i = r0 + threadIdx.x; i < r1; i += NT) {
         double s = 0.0;
         const int64_t t1 = arp[i + 1];
