@@ -88,6 +88,10 @@ def _load():
         lib.orc_use_cheb.restype = C.c_int
         lib.orc_use_cheb.argtypes = [P, C.c_int, C.c_int]
         lib.orc_cheb.argtypes = [P, P]
+        lib.orc_set_reorth.restype = C.c_int
+        lib.orc_set_reorth.argtypes = [P, C.c_int]
+        lib.orc_reorth_steps.restype = C.c_int
+        lib.orc_reorth_steps.argtypes = [P, P]
         lib.orc_threads.restype = C.c_int
         lib.orc_threads.argtypes = []
         lib.orc_set_threads.restype = None
@@ -234,6 +238,20 @@ class Oracle:
         z = np.zeros_like(x2, order="F")
         _lib.orc_a0_solve(self._h, x2.shape[1], _p(x2), _p(z))
         return z[:, 0] if one else z
+
+    def set_reorth(self, mode):
+        """Reorthogonalisation of the following Lanczos runs: 0 full (CGS2 every
+        step), 1 partial (Simon's omega recurrence), 2 none (tests only)."""
+        if _lib.orc_set_reorth(self._h, int(mode)) != 0:
+            raise OracleError(E_INVALID, "reorth mode")
+        return self
+
+    def reorth_steps(self):
+        """Per-step flags (1: the new vector was reorthogonalised) of the stored run."""
+        msteps = int(_lib.orc_size(self._h, 7))
+        f = np.zeros(max(msteps, 1), np.int32)
+        _lib.orc_reorth_steps(self._h, _p(f))
+        return f[:msteps]
 
     def lowrank(self, variant, k, m, v0, theta_zero=False, check=0, eps=1e-4):
         """Lanczos of m steps (check = 0) or of at most m steps stopped by the

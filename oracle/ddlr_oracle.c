@@ -106,6 +106,14 @@ typedef struct {
     int lvariant;     /* operator of the stored run (1 or 2), 0 if none */
     int broke;        /* the stored run ended in an invariant subspace */
     double amax;      /* max |alpha_i| so far */
+    /* reorthogonalisation: 0 full (classical Gram-Schmidt twice, every step),
+     * 1 partial (Simon's omega recurrence), 2 none (tests only) */
+    int reorth;
+    double *om_prev, *om_cur;  /* omega estimates of q_i^T q_{j-1} and q_i^T q_j, length qcap + 1 */
+    double tnorm;              /* running estimate of ||T_j|| in the omega recurrence */
+    int force_next;            /* the step after a partial reorthogonalisation is reorthogonalised too */
+    int *rsteps;               /* 1 for the steps whose new vector was reorthogonalised */
+    int nreorth;
     /* C_alpha approximate inverse (csolve = 1) */
     int csolve;       /* 0: factor of C_alpha, 1: X ~ C_alpha^{-1} */
     csr_t X;          /* s x s, symmetric, interface indices */
@@ -980,16 +988,81 @@ static void lanczos_reserve(orc_t *o, int m_max) {
     const int64_t s = o->s;
     double *Q = xcalloc(s * (int64_t)(m_max + 1), sizeof(double));
     double *ta = xcalloc(m_max + 1, sizeof(double)), *tb = xcalloc(m_max + 1, sizeof(double));
+    double *op = xcalloc(m_max + 2, sizeof(double)), *oc = xcalloc(m_max + 2, sizeof(double));
+    int *rs = xcalloc(m_max + 1, sizeof(int));
     if (o->Q) memcpy(Q, o->Q, s * (int64_t)(o->msteps + 1) * sizeof(double));
     if (o->ta) memcpy(ta, o->ta, o->msteps * sizeof(double));
     if (o->tb) memcpy(tb, o->tb, o->msteps * sizeof(double));
-    free(o->Q); free(o->ta); free(o->tb);
-    o->Q = Q; o->ta = ta; o->tb = tb;
+    if (o->om_prev) memcpy(op, o->om_prev, (o->msteps + 1) * sizeof(double));
+    if (o->om_cur) memcpy(oc, o->om_cur, (o->msteps + 1) * sizeof(double));
+    if (o->rsteps) memcpy(rs, o->rsteps, o->msteps * sizeof(int));
+    free(o->Q); free(o->ta); free(o->tb); free(o->om_prev); free(o->om_cur); free(o->rsteps);
+    o->Q = Q; o->ta = ta; o->tb = tb; o->om_prev = op; o->om_cur = oc; o->rsteps = rs;
     o->qcap = m_max + 1;
 }
 
+/* Classical Gram-Schmidt applied twice: w loses its components along q_0..q_j. */
+static void cgs2(const orc_t *o, int j, double *w, double *c) {
+    const int64_t s = o->s;
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int l = 0; l <= j; ++l) c[l] = dot(o->Q + s * (int64_t)l, w, s);
+        for (int l = 0; l <= j; ++l) {
+            const double *ql = o->Q + s * (int64_t)l;
+            for (int64_t i = 0; i < s; ++i) w[i] -= c[l] * ql[i];
+        }
+    }
+}
+
+/* Partial reorthogonalisation (Simon, "The Lanczos algorithm with partial
+ * reorthogonalization", Math. Comp. 42, 1984), the scheme the paper uses.
+ * omega_i estimates q_i^T q of the Lanczos vectors; for the new vector j+1
+ * (before normalisation, norm b0) Simon's recurrence gives, for i < j,
+ *   b0 om_new_i = beta_i om_cur_{i+1} + (alpha_i - alpha_j) om_cur_i
+ *                 + beta_{i-1} om_cur_{i-1} - beta_{j-1} om_prev_i + theta,
+ * theta = 2 eps ||T||_est with the sign of the rest (the rounding term, eps =
+ * 2^-52, ||T||_est the running max of |alpha_i| + beta_i + beta_{i-1});
+ * om_new_j = eps sqrt(s) (the local rounding level) and om_new_{j+1} = 1.
+ * When some |om_new_i| (i <= j) exceeds sqrt(eps) -- or when the previous
+ * step was reorthogonalised, as Simon requires for the next vector too --
+ * the new vector is orthogonalised against q_0..q_j (classical Gram-Schmidt
+ * twice) and its estimates reset to eps.  Returns 1 if it did so. */
+static int pro_step(orc_t *o, int j, double aj, double b0, double *w, double *c) {
+    const double eps = 2.220446049250313e-16;
+    const double bprev = j > 0 ? o->tb[j - 1] : 0.0;
+    const double tn = fabs(aj) + b0 + bprev;
+    if (tn > o->tnorm) o->tnorm = tn;
+    double *on = xcalloc(j + 2, sizeof(double));
+    double big = 0.0;
+    for (int i = 0; i < j; ++i) {
+        double t = o->tb[i] * o->om_cur[i + 1] + (o->ta[i] - aj) * o->om_cur[i];
+        if (i > 0) t += o->tb[i - 1] * o->om_cur[i - 1];
+        t -= bprev * o->om_prev[i];
+        t += (t >= 0.0 ? 1.0 : -1.0) * 2.0 * eps * o->tnorm;
+        on[i] = t / b0;
+        if (fabs(on[i]) > big) big = fabs(on[i]);
+    }
+    on[j] = eps * sqrt((double)o->s);
+    if (on[j] > big) big = on[j];
+    on[j + 1] = 1.0;
+    const int forced = o->force_next;
+    const int need = forced || big > sqrt(eps);
+    if (need) {
+        cgs2(o, j, w, c);
+        for (int i = 0; i <= j; ++i) on[i] = eps;
+        o->force_next = forced ? 0 : 1;
+        o->nreorth++;
+    } else {
+        o->force_next = 0;
+    }
+    memcpy(o->om_prev, o->om_cur, (j + 1) * sizeof(double));
+    memcpy(o->om_cur, on, (j + 2) * sizeof(double));
+    free(on);
+    return need;
+}
+
 /* Lanczos on E^T A0^{-1} E (DDLR-1) or E^T A0^{-2} E (DDLR-2), Sec. 4.4 (sec:Lan), with
- * full reorthogonalisation (classical Gram-Schmidt applied twice).  Continues
+ * full reorthogonalisation (classical Gram-Schmidt applied twice), or with
+ * partial reorthogonalisation (pro_step) as the paper does.  Continues
  * the stored run from step msteps up to m_max steps.  With check > 0 it stops
  * early at the first step m that is a multiple of check, with m >= k + 1,
  * where the sums of the k largest Ritz values of T_{m-1} and T_m satisfy
@@ -1013,14 +1086,18 @@ static int lanczos_run(orc_t *o, int m_max, int check, double eps, int k) {
             double *qp = o->Q + s * (int64_t)(j - 1);
             for (int64_t i = 0; i < s; ++i) w[i] -= o->tb[j - 1] * qp[i];
         }
-        for (int pass = 0; pass < 2; ++pass) {
-            for (int l = 0; l <= j; ++l) c[l] = dot(o->Q + s * (int64_t)l, w, s);
-            for (int l = 0; l <= j; ++l) {
-                const double *ql = o->Q + s * (int64_t)l;
-                for (int64_t i = 0; i < s; ++i) w[i] -= c[l] * ql[i];
+        double bj;
+        o->rsteps[j] = 0;
+        if (o->reorth == 0) {
+            cgs2(o, j, w, c);
+            bj = nrm2(w, s);
+        } else {
+            bj = nrm2(w, s);
+            if (o->reorth == 1 && bj > 1e-12 * o->amax) {
+                o->rsteps[j] = pro_step(o, j, aj, bj, w, c);
+                if (o->rsteps[j]) bj = nrm2(w, s);
             }
         }
-        double bj = nrm2(w, s);
         o->tb[j] = bj;
         o->msteps = j + 1;
         if (bj <= 1e-12 * o->amax) { o->broke = 1; break; }  /* invariant subspace found */
@@ -1043,7 +1120,11 @@ static void lanczos_start(orc_t *o, int variant, const double *v0) {
     o->broke = 0;
     o->amax = 0.0;
     o->lvariant = variant;
+    o->tnorm = 0.0;
+    o->force_next = 0;
+    o->nreorth = 0;
     lanczos_reserve(o, 1);
+    o->om_cur[0] = 1.0;  /* q_0^T q_0 */
     double nv = nrm2(v0, s);
     for (int64_t i = 0; i < s; ++i) o->Q[i] = v0[i] / nv;
 }
@@ -1260,6 +1341,7 @@ static void to_user(const orc_t *o, const double *xi, double *xu) {
 void orc_free(orc_t *o) {
     if (!o) return;
     csr_free(&o->A); csr_free(&o->Ap); csr_free(&o->A0); csr_free(&o->E); csr_free(&o->Et); csr_free(&o->L);
+    free(o->om_prev); free(o->om_cur); free(o->rsteps);
     free(o->part); free(o->iface); free(o->perm); free(o->iperm); free(o->colour); free(o->boff);
     free(o->D); free(o->U); free(o->lam); free(o->dvec); free(o->Hk);
     free(o->ta); free(o->tb); free(o->ritz); free(o->Q);
@@ -1780,6 +1862,26 @@ int orc_gmres(const orc_t *o, int nrhs, const double *b, double *x, int restart,
 
 /* y = A x in user order (used by tests for residuals) */
 void orc_matvec(const orc_t *o, const double *x, double *y) { csr_mv(&o->A, o->n, x, y); }
+
+/* Reorthogonalisation of the next Lanczos runs: 0 full, 1 partial, 2 none
+ * (tests only).  Returns 0, or -1 for another value. */
+int orc_set_reorth(orc_t *o, int mode) {
+    if (mode < 0 || mode > 2) return -1;
+    o->reorth = mode;
+    return 0;
+}
+
+/* Steps of the stored run whose new vector was reorthogonalised (partial
+ * reorthogonalisation): flags[0..msteps-1]; returns their count. */
+int orc_reorth_steps(const orc_t *o, int32_t *flags) {
+    int cnt = 0;
+    for (int j = 0; j < o->msteps; ++j) {
+        const int f = o->rsteps ? o->rsteps[j] : 0;
+        if (flags) flags[j] = f;
+        cnt += f;
+    }
+    return cnt;
+}
 
 /* sets the number of OpenMP threads of the parallel loops */
 void orc_set_threads(int n) {

@@ -890,3 +890,90 @@ def test_cheb_preconditioner_end_to_end():
     assert info["status"] == 0 and np.all(info["relres_true"] <= 1.01e-6)
     xd = spla.spsolve(A.to_scipy().tocsc(), b)
     assert np.linalg.norm(x - xd) <= 1e-3 * np.linalg.norm(xd)
+
+
+# ------------------------------------- partial reorthogonalisation (Sec. 4.4)
+
+def _pro_case():
+    """Random-coefficient diffusion on 48x40 in 4x3 boxes (s = 408): a run of
+    120 steps converges Ritz values and, without reorthogonalisation, loses
+    orthogonality of the Lanczos vectors by many orders of magnitude."""
+    dims = (48, 40)
+    return w.tpfa_2d(*dims, 5), w.box_partition(dims, (4, 3)), 12
+
+
+def _pro_run(mode, m=120):
+    A, part, p = _pro_case()
+    o = Oracle(A, part, p).set_reorth(mode)
+    o.lowrank(1, 8, m, w.lanczos_start(A.n, 0))
+    return o
+
+
+def test_partial_reorth_semi_orthogonality_and_projection():
+    """Simon's theorem behind partial reorthogonalisation: with |q_i^T q_j| kept
+    below sqrt(eps), Q^T H Q equals T_m to rounding level, so the Ritz values
+    are eigenvalues of the exactly projected operator.  The same run without
+    reorthogonalisation shows both fail (so the pin has teeth), and a Ritz
+    value whose residual bound beta_m |s_mi| is small lies within that bound
+    of an eigenvalue of H computed by LAPACK."""
+    m = 120
+    out = {}
+    for mode in (1, 2):
+        o = _pro_run(mode, m)
+        ta, tb, rz = o.lanczos_record()
+        Q = o.lanczos_basis()
+        H = dense_H(o_ic_dense(o))
+        T = np.diag(ta) + np.diag(tb[:-1], 1) + np.diag(tb[:-1], -1)
+        th, S = np.linalg.eigh(T)
+        orth = np.abs(Q.T @ Q - np.eye(m)).max()
+        proj = np.abs(np.linalg.eigvalsh(Q.T @ H @ Q) - th).max()
+        out[mode] = (orth, proj)
+        if mode == 1:
+            ev = np.linalg.eigvalsh(H)
+            bound = np.abs(tb[-1] * S[-1, :])
+            conv = bound <= 1e-8
+            assert conv.sum() >= 3
+            for t, b in zip(th[conv], bound[conv]):
+                assert np.abs(ev - t).min() <= b + 1e-12
+    assert out[1][0] <= 1e-7 and out[1][1] <= 1e-11
+    assert out[2][0] >= 1e-2 and out[2][1] >= 1e-4
+
+
+def test_partial_reorth_schedule():
+    """Reorthogonalisation happens at few steps, never in the first ones (the
+    estimates start at rounding level), and each triggered step is followed by
+    a reorthogonalised step (Simon: the next vector is orthogonalised too)."""
+    m = 120
+    f = _pro_run(1, m).reorth_steps()
+    assert len(f) == m
+    steps = np.nonzero(f)[0]
+    assert 0 < len(steps) <= m // 8
+    assert steps[0] >= 10
+    runs = np.split(steps, np.nonzero(np.diff(steps) != 1)[0] + 1)
+    assert all(len(r) >= 2 or r[-1] == m - 1 for r in runs)
+    assert not _pro_run(0, m).reorth_steps().any()
+
+
+def test_partial_reorth_same_preconditioner_as_full():
+    """The preconditioner built from a partially reorthogonalised run equals the
+    one from full reorthogonalisation: Ritz values to 1e-12 (relative), the
+    action of M^{-1} to sqrt(eps) (relative: the basis is orthonormal to that
+    order, and so are the Ritz vectors built from it), in DDLR-1 and DDLR-2."""
+    x = np.random.default_rng(4).standard_normal((1920, 4))
+    for variant in (1, 2):
+        ys, rzs = [], []
+        for mode in (0, 1):
+            A, part, p = _pro_case()
+            o = Oracle(A, part, p).set_reorth(mode)
+            o.lowrank(variant, 8, 120, w.lanczos_start(A.n, 0))
+            rzs.append(o.lanczos_record()[2])
+            ys.append(o.apply(x))
+        assert np.abs(rzs[0] - rzs[1]).max() <= 1e-12 * abs(rzs[0][0])
+        assert np.abs(ys[0] - ys[1]).max() <= np.sqrt(2.0 ** -52) * np.abs(ys[0]).max()
+
+
+def test_partial_reorth_mode_checked():
+    A, part, p = tiny_irregular()
+    o = Oracle(A, part, p)
+    with pytest.raises(OracleError):
+        o.set_reorth(3)
