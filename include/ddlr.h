@@ -88,6 +88,23 @@ typedef enum { DDLR_CSOLVE_FACTOR = 0, DDLR_CSOLVE_MR = 1, DDLR_CSOLVE_CHEB = 2 
  * the bidiagonalisation keeps the n x m basis P_m during the build and its
  * run cannot be continued by ddlr_extend_lowrank. */
 typedef enum { DDLR_BUILD_LANCZOS = 0, DDLR_BUILD_BIDIAG = 1 } ddlr_lowrank_build;
+
+/* Reorthogonalisation of the Lanczos vectors (Sec. 4.4, sec:Lan).
+ * FULL: every new vector is orthogonalised against all earlier ones
+ * (classical Gram-Schmidt twice).  PARTIAL: the scheme the paper uses,
+ * Simon's partial reorthogonalisation (Math. Comp. 42, 1984): a recurrence
+ * estimates omega_i = q_i^T q_{j+1} from alpha and beta alone,
+ *   beta_j omega'_i = beta_i omega_{i+1} + (alpha_i - alpha_j) omega_i
+ *                     + beta_{i-1} omega_{i-1} - beta_{j-1} omega''_i + theta
+ * (omega: estimates against q_j, omega'': against q_{j-1}; theta = 2 eps
+ * ||T||, ||T|| the running max of |alpha_i| + beta_i + beta_{i-1}, with the
+ * sign of the rest; omega'_j = eps sqrt(s), omega'_{j+1} = 1; eps = 2^-52);
+ * when some |omega'_i| exceeds sqrt(eps), q_{j+1} and q_{j+2} are
+ * orthogonalised against all earlier vectors (classical Gram-Schmidt twice)
+ * and their estimates reset to eps.  The basis then stays orthogonal to
+ * sqrt(eps), the Ritz values are those of full reorthogonalisation to
+ * rounding level and the preconditioner agrees to about sqrt(eps). */
+typedef enum { DDLR_REORTH_FULL = 0, DDLR_REORTH_PARTIAL = 1 } ddlr_reorth;
 typedef enum { DDLR_FP64 = 0, DDLR_FP32 = 1, DDLR_FP32_UK_BF16 = 2 } ddlr_precision;
 
 /* Symmetric matrix, host memory, full storage, sorted columns. */
@@ -121,6 +138,8 @@ typedef struct {
                               DDLR_BUILD_LANCZOS */
     int32_t cheb_iters;    /* DDLR_CSOLVE_CHEB: Chebyshev steps per solve (1..64); default 5 (the paper's) */
     int32_t cheb_lanczos;  /* DDLR_CSOLVE_CHEB: Lanczos steps of the spectrum estimate (2..200); default 10 */
+    int32_t lanczos_reorth; /* ddlr_reorth of the low-rank Lanczos run (DDLR_BUILD_LANCZOS only); default
+                               DDLR_REORTH_FULL */
 } ddlr_options;
 
 typedef struct {
@@ -154,6 +173,8 @@ typedef struct {
     double cinv_res_inf;    /* ||I - C_alpha X||_inf (the SPD certificate needs < 1) */
     double cheb_lo, cheb_hi;           /* DDLR_CSOLVE_CHEB: safeguarded interval of D_alpha^{-1} C_alpha */
     double cheb_ritz_lo, cheb_ritz_hi; /* its smallest and largest Ritz value */
+    int32_t lanczos_reorth;            /* ddlr_reorth of the run */
+    int32_t lanczos_reorth_steps;      /* steps whose new vector was reorthogonalised (FULL: every step) */
 } ddlr_info;
 
 typedef struct ddlr_prec ddlr_prec;
@@ -190,7 +211,8 @@ void ddlr_solve_options_default(ddlr_solve_options *opt);
  *     `part` (Sec. 2.1) and reorders to the form of eq. (Bmat);
  *  2./3. forms B_{i,alpha}, C_alpha and E (Sec. 3.1) and factors every block by
  *     incomplete LDL^T with the block's own pattern (Sec. 5);
- *  4. runs `lanczos_steps` Lanczos steps with full reorthogonalisation on
+ *  4. runs `lanczos_steps` Lanczos steps with full or partial
+ *     reorthogonalisation (opt->lanczos_reorth) on
  *     E^T A0^{-1} E (DDLR-1) or E^T A0^{-2} E (DDLR-2) (Sec. 4.4 (sec:Lan)) and forms
  *     U_k with G_{k,theta}^{-1} (eq. gkt) or H_k (Lemma on H_k).
  * ctx: context (device and memory budget; its device replaces opt->device), or
@@ -345,6 +367,13 @@ ddlr_status ddlr_get_levels(const ddlr_prec *h, int32_t *level);
 /* Lanczos record: alpha_1..alpha_m, beta_1..beta_m and Ritz values (descending),
  * m = info.lanczos_steps.  Host arrays. */
 ddlr_status ddlr_get_lanczos(const ddlr_prec *h, double *alpha, double *beta, double *ritz);
+
+/* Per-step reorthogonalisation of the stored Lanczos run (Sec. 4.4,
+ * sec:Lan, with DDLR_REORTH_PARTIAL): flags host int32[lanczos_steps],
+ * flags[j] = 1 when the vector q_{j+1} made at step j was orthogonalised
+ * against the earlier ones (with DDLR_REORTH_FULL every flag is 1).  Errors:
+ * DDLR_E_INVALID for a null handle or a handle without a Lanczos run. */
+ddlr_status ddlr_get_lanczos_reorth(const ddlr_prec *h, int32_t *flags);
 
 /* Low-rank data in user order (host).  U: n x k column-major (DDLR-1: only the
  * interface rows are nonzero).  aux: DDLR-1 lambda_1..lambda_k then theta

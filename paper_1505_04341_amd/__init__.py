@@ -26,6 +26,7 @@ CORDER_MULTICOLOR, CORDER_NATURAL = 0, 1
 FP64, FP32, FP32_UK_BF16 = 0, 1, 2
 CSOLVE_FACTOR, CSOLVE_MR, CSOLVE_CHEB = 0, 1, 2
 BUILD_LANCZOS, BUILD_BIDIAG = 0, 1
+REORTH_FULL, REORTH_PARTIAL = 0, 1
 
 
 class ddlr_csr(C.Structure):
@@ -38,7 +39,8 @@ class ddlr_options(C.Structure):
                 ("no_autotune", C.c_int32), ("lanczos_check", C.c_int32), ("lanczos_max", C.c_int32),
                 ("lanczos_tol", C.c_double), ("seed", C.c_uint64), ("lanczos_start", C.c_void_p),
                 ("csolve", C.c_int32), ("cinv_iters", C.c_int32), ("cinv_tol", C.c_double), ("cinv_lfil", C.c_int32),
-                ("lowrank_build", C.c_int32), ("cheb_iters", C.c_int32), ("cheb_lanczos", C.c_int32)]
+                ("lowrank_build", C.c_int32), ("cheb_iters", C.c_int32), ("cheb_lanczos", C.c_int32),
+                ("lanczos_reorth", C.c_int32)]
 
 
 class ddlr_tuning(C.Structure):
@@ -77,7 +79,7 @@ class ddlr_info(C.Structure):
                 ("lanczos_ms", C.c_double), ("csolve", C.c_int32), ("cinv_iters", C.c_int32),
                 ("nnz_cinv", C.c_int64), ("cinv_res", C.c_double), ("cinv_res_inf", C.c_double),
                 ("cheb_lo", C.c_double), ("cheb_hi", C.c_double), ("cheb_ritz_lo", C.c_double),
-                ("cheb_ritz_hi", C.c_double)]
+                ("cheb_ritz_hi", C.c_double), ("lanczos_reorth", C.c_int32), ("lanczos_reorth_steps", C.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -132,6 +134,7 @@ def load_library(path: str = LIB_PATH):
         "ddlr_get_cinv": (I32, [P, P, P, P, P]),
         "ddlr_get_levels": (I32, [P, P]),
         "ddlr_get_lanczos": (I32, [P, P, P, P]),
+        "ddlr_get_lanczos_reorth": (I32, [P, P]),
         "ddlr_get_lowrank": (I32, [P, P, P]),
         "ddlr_set_lowrank": (I32, [P, I32, I32, P, P]),
         "ddlr_profile": (I32, [P, I32]),
@@ -251,7 +254,7 @@ def ddlr_setup(A, part, p: int, k: int, variant: int = DDLR_1, *, alpha: float =
                autotune: bool = True, lanczos_check: int = 0, lanczos_max: int = 0, lanczos_tol: float = 0.0,
                csolve: int = CSOLVE_FACTOR, cinv_iters: int = 3, cinv_tol: float = 0.01, cinv_lfil: int = 20,
                lowrank_build: int = BUILD_LANCZOS, cheb_iters: int = 5, cheb_lanczos: int = 10,
-               ctx: "Ctx | None" = None) -> Prec:
+               lanczos_reorth: int = REORTH_FULL, ctx: "Ctx | None" = None) -> Prec:
     """Builds the preconditioner. A: object with n, rowptr (int64), col (int32), val (float64).
     ctx: a context (its device replaces `device`) or None."""
     lib = load_library()
@@ -271,6 +274,7 @@ def ddlr_setup(A, part, p: int, k: int, variant: int = DDLR_1, *, alpha: float =
         cinv_lfil)
     opt.lowrank_build = int(lowrank_build)
     opt.cheb_iters, opt.cheb_lanczos = int(cheb_iters), int(cheb_lanczos)
+    opt.lanczos_reorth = int(lanczos_reorth)
     v0 = None
     if lanczos_start is not None:
         v0 = np.ascontiguousarray(lanczos_start, dtype=np.float64)
@@ -417,6 +421,14 @@ def ddlr_get_lanczos(prec: Prec):
     a, b, r = np.zeros(max(m, 1)), np.zeros(max(m, 1)), np.zeros(max(m, 1))
     _check(lib.ddlr_get_lanczos(prec.handle, _ptr(a), _ptr(b), _ptr(r)), "ddlr_get_lanczos")
     return a[:m], b[:m], r[:m]
+
+
+def ddlr_get_lanczos_reorth(prec: Prec):
+    """Per-step flags of the stored Lanczos run: 1 where the new vector was reorthogonalised."""
+    m = ddlr_query(prec)["lanczos_steps"]
+    f = np.zeros(max(m, 1), np.int32)
+    _check(load_library().ddlr_get_lanczos_reorth(prec.handle, _ptr(f)), "ddlr_get_lanczos_reorth")
+    return f[:m]
 
 
 def ddlr_get_lowrank(prec: Prec):
@@ -632,7 +644,7 @@ EXPORTED = ["ddlr_version", "ddlr_options_default", "ddlr_solve_options_default"
             "ddlr_import_setup", "ddlr_partition_box", "ddlr_batch_tuning",
             "ddlr_a0_solve", "ddlr_spmv", "ddlr_solve", "ddlr_query", "ddlr_get_ordering", "ddlr_get_factor",
             "ddlr_get_cinv",
-            "ddlr_get_levels", "ddlr_get_lanczos", "ddlr_get_lowrank", "ddlr_set_lowrank", "ddlr_profile",
+            "ddlr_get_levels", "ddlr_get_lanczos", "ddlr_get_lanczos_reorth", "ddlr_get_lowrank", "ddlr_set_lowrank", "ddlr_profile",
             "ddlr_profile_read", "ddlr_batch_create", "ddlr_batch_offsets", "ddlr_batch_apply",
             "ddlr_batch_solve", "ddlr_batch_destroy", "ddlr_server_create", "ddlr_server_add", "ddlr_server_submit",
             "ddlr_server_poll", "ddlr_server_wait", "ddlr_server_stats", "ddlr_server_reset_stats", "ddlr_server_destroy", "ddlr_extend_lowrank", "ddlr_partition_graph", "ddlr_tune", "ddlr_destroy",

@@ -198,6 +198,14 @@ struct LanczosRun {
     int lvariant = 0;  // operator of the run: DDLR_1 or DDLR_2
     bool broke = false;
     std::vector<double> ha, hb;
+    // partial reorthogonalisation (reorth = DDLR_REORTH_PARTIAL): three rows of
+    // omega estimates of length cap + 2 (the row of step j is j mod 3), then the
+    // running ||T|| estimate; pst = {force next step, skip this step's
+    // reorthogonalisation, flag of step 0, 1, ...}
+    int reorth = 0;
+    double* om = nullptr;
+    int* pst = nullptr;
+    std::vector<int32_t> hf;  // host copy of the per-step flags
 };
 
 struct Workspace {
@@ -271,6 +279,8 @@ struct ddlr_prec {
     bool pivots_positive = true;
     double theta = 0.0, c0 = 0.0;
     std::vector<double> lam, dvec_h, H_h, ta, tb, ritz;
+    int lreorth = DDLR_REORTH_FULL;  // ddlr_reorth of the stored run
+    std::vector<int32_t> rflags;     // per step: 1 if the new vector was reorthogonalised
     double setup_ms = 0.0, lanczos_ms = 0.0;
     LanczosRun lrun;     // the setup's Lanczos run (for ddlr_extend_lowrank)
     int theta_mode = 0;  // ddlr_theta of the low-rank build
@@ -397,7 +407,7 @@ void ctx_unref(ddlr_ctx* ctx) {
 
 constexpr int kRing64 = 8192, kRing32 = 16384;  // LDS ring rows: 64 KB either way
 constexpr int kRingThin = 2048;
-constexpr int kMaxLanczos = 1024;  // Lanczos / bidiagonalisation steps (k_gemv_sub stages 1024 coefficients)                  // widest window the untuned 64/256-thread choice takes
+constexpr int kMaxLanczos = 1024;  // Lanczos / bidiagonalisation steps (k_gemv_sub stages 1024 coefficients)
 
 // Device-order arrays of one preconditioner (or of several merged), built on
 // the host before upload.
@@ -1595,6 +1605,18 @@ void lanczos_reserve(ddlr_prec* h, int cap) {
     R.t2 = nm.alloc<double>(n);
     R.part = nm.alloc<double>((size_t)kRedBlocks * (cap + 1));
     R.csum = nm.alloc<double>(cap + 1);
+    const size_t orow = (size_t)cap + 2;
+    double* om = nm.alloc<double>(3 * orow + 1);
+    int* pst = nm.alloc<int>((size_t)cap + 2);
+    HIPCHK(hipMemset(om, 0, sizeof(double) * (3 * orow + 1)));
+    HIPCHK(hipMemset(pst, 0, sizeof(int) * ((size_t)cap + 2)));
+    if (R.om) {
+        const size_t oold = (size_t)R.cap + 2;
+        for (int r = 0; r < 3; ++r)
+            HIPCHK(hipMemcpy(om + r * orow, R.om + r * oold, sizeof(double) * oold, hipMemcpyDeviceToDevice));
+        HIPCHK(hipMemcpy(om + 3 * orow, R.om + 3 * oold, sizeof(double), hipMemcpyDeviceToDevice));
+        HIPCHK(hipMemcpy(pst, R.pst, sizeof(int) * ((size_t)R.steps + 2), hipMemcpyDeviceToDevice));
+    }
     HIPCHK(hipDeviceSynchronize());
     R.mem.release();
     R.mem = std::move(nm);
@@ -1602,6 +1624,8 @@ void lanczos_reserve(ddlr_prec* h, int cap) {
     R.alpha = al;
     R.beta = be;
     R.sc = sc;
+    R.om = om;
+    R.pst = pst;
     R.cap = cap;
 }
 
@@ -1635,9 +1659,17 @@ void lanczos_start(ddlr_prec* h, const double* v0_user, uint64_t seed) {
     R.lvariant = h->variant;
     R.ha.clear();
     R.hb.clear();
+    R.hf.clear();
     lanczos_reserve(h, 1);
     HIPCHK(hipMemcpy(R.Q, q0.data(), s * sizeof(double), hipMemcpyHostToDevice));
     HIPCHK(hipMemset(R.sc, 0, sizeof(double) * 4));
+    // omega estimates: q_0^T q_0 = 1 in the row of step 0, ||T|| estimate 0,
+    // no forced step
+    const size_t orow = (size_t)R.cap + 2;
+    HIPCHK(hipMemset(R.om, 0, sizeof(double) * (3 * orow + 1)));
+    HIPCHK(hipMemset(R.pst, 0, sizeof(int) * orow));
+    const double one = 1.0;
+    HIPCHK(hipMemcpy(R.om, &one, sizeof(double), hipMemcpyHostToDevice));
 }
 
 // Sum of the k largest eigenvalues of the leading j x j block of T
@@ -1657,8 +1689,11 @@ void lanczos_sync(ddlr_prec* h, int done_steps) {
     LanczosRun& R = h->lrun;
     R.ha.resize(done_steps);
     R.hb.resize(done_steps);
+    R.hf.assign(done_steps, 0);
     HIPCHK(hipMemcpy(R.ha.data(), R.alpha, done_steps * sizeof(double), hipMemcpyDeviceToHost));
     HIPCHK(hipMemcpy(R.hb.data(), R.beta, done_steps * sizeof(double), hipMemcpyDeviceToHost));
+    if (R.reorth == DDLR_REORTH_PARTIAL && done_steps > 0)
+        HIPCHK(hipMemcpy(R.hf.data(), R.pst + 2, done_steps * sizeof(int), hipMemcpyDeviceToHost));
     double am = 0.0;
     R.steps = done_steps;
     for (int j = 0; j < done_steps; ++j) {
@@ -1671,6 +1706,7 @@ void lanczos_sync(ddlr_prec* h, int done_steps) {
     }
     R.ha.resize(R.steps);
     R.hb.resize(R.steps);
+    R.hf.resize(R.steps);
 }
 
 // Continues the run up to m_max steps.  With check > 0 it stops at the first
@@ -1715,25 +1751,47 @@ void lanczos_advance(ddlr_prec* h, int m_max, int check, double eps, int k) {
         LAUNCHCHK();
         hipLaunchKernelGGL(k_reduce_cols, dim3(1), dim3(256), 0, st, gs, 1, part, sum1, nullptr);
         LAUNCHCHK();
-        hipLaunchKernelGGL(k_lanczos_scalar, dim3(1), dim3(64), 0, st, sum1, alpha + j, 0, amax, inv);
+        hipLaunchKernelGGL(k_lanczos_scalar, dim3(1), dim3(64), 0, st, sum1, alpha + j, 0, amax, inv,
+                           (const int*)nullptr);
         LAUNCHCHK();
         hipLaunchKernelGGL(k_lanczos_3term, dim3(gs), dim3(256), 0, st, s, j, Q, s, alpha, beta, w);
         LAUNCHCHK();
-        // full reorthogonalisation, classical Gram-Schmidt twice
+        // Full reorthogonalisation: classical Gram-Schmidt twice at every step.
+        // Partial: ||w|| first, Simon's omega recurrence decides on the device
+        // whether this step is reorthogonalised (skip = 0); the skipped
+        // kernels return at once and beta_j keeps the norm already taken.
+        const int* skip = nullptr;
+        if (R.reorth == DDLR_REORTH_PARTIAL) {
+            hipLaunchKernelGGL((k_dot<double, double>), dim3(gs), dim3(256), 0, st, s, 1, w, s, w, s, part, nullptr);
+            LAUNCHCHK();
+            hipLaunchKernelGGL(k_reduce_cols, dim3(1), dim3(256), 0, st, gs, 1, part, sum1, nullptr);
+            LAUNCHCHK();
+            hipLaunchKernelGGL(k_lanczos_scalar, dim3(1), dim3(64), 0, st, sum1, beta + j, 1, amax, inv,
+                               (const int*)nullptr);
+            LAUNCHCHK();
+            const size_t orow = (size_t)R.cap + 2;
+            double* om_cur = R.om + (size_t)(j % 3) * orow;
+            double* om_prev = R.om + (size_t)((j + 2) % 3) * orow;
+            double* om_new = R.om + (size_t)((j + 1) % 3) * orow;
+            hipLaunchKernelGGL(k_pro_omega, dim3(1), dim3(1024), 0, st, j, s, alpha, beta, beta + j, amax, om_prev,
+                               om_cur, om_new, R.om + 3 * orow, R.pst, R.pst + 2);
+            LAUNCHCHK();
+            skip = R.pst + 1;
+        }
         for (int pass = 0; pass < 2; ++pass) {
-            hipLaunchKernelGGL(k_multidot, dim3(gs), dim3(256), 0, st, s, j + 1, Q, s, w, part);
+            hipLaunchKernelGGL(k_multidot, dim3(gs), dim3(256), 0, st, s, j + 1, Q, s, w, part, skip);
             LAUNCHCHK();
-            hipLaunchKernelGGL(k_reduce_cols, dim3(j + 1), dim3(256), 0, st, gs, j + 1, part, csum, nullptr);
+            hipLaunchKernelGGL(k_reduce_cols, dim3(j + 1), dim3(256), 0, st, gs, j + 1, part, csum, skip);
             LAUNCHCHK();
-            hipLaunchKernelGGL(k_gemv_sub, dim3(gs), dim3(256), 0, st, s, j + 1, Q, s, csum, w);
+            hipLaunchKernelGGL(k_gemv_sub, dim3(gs), dim3(256), 0, st, s, j + 1, Q, s, csum, w, skip);
             LAUNCHCHK();
         }
         // beta_j = ||w||, q_{j+1} = w / beta_j
-        hipLaunchKernelGGL((k_dot<double, double>), dim3(gs), dim3(256), 0, st, s, 1, w, s, w, s, part, nullptr);
+        hipLaunchKernelGGL((k_dot<double, double>), dim3(gs), dim3(256), 0, st, s, 1, w, s, w, s, part, skip);
         LAUNCHCHK();
-        hipLaunchKernelGGL(k_reduce_cols, dim3(1), dim3(256), 0, st, gs, 1, part, sum1, nullptr);
+        hipLaunchKernelGGL(k_reduce_cols, dim3(1), dim3(256), 0, st, gs, 1, part, sum1, skip);
         LAUNCHCHK();
-        hipLaunchKernelGGL(k_lanczos_scalar, dim3(1), dim3(64), 0, st, sum1, beta + j, 1, amax, inv);
+        hipLaunchKernelGGL(k_lanczos_scalar, dim3(1), dim3(64), 0, st, sum1, beta + j, 1, amax, inv, skip);
         LAUNCHCHK();
         hipLaunchKernelGGL(k_scale_to, dim3(gs), dim3(256), 0, st, s, w, inv, Q + (size_t)(j + 1) * s);
         LAUNCHCHK();
@@ -1832,6 +1890,9 @@ void lanczos_finish(ddlr_prec* h, int k, int theta_mode) {
     const double* Q = R.Q;
     h->ta = R.ha;
     h->tb = R.hb;
+    h->lreorth = R.reorth;
+    if (R.reorth == DDLR_REORTH_PARTIAL) h->rflags = R.hf;
+    else h->rflags.assign(meff, 1);
     h->msteps = meff;
     h->theta_mode = theta_mode;
     drop_graphs(h);  // captured kernels hold the low-rank pointers
@@ -1920,6 +1981,7 @@ void gk_build(ddlr_prec* h, int k, int m, const double* v0_user, uint64_t seed) 
     HostPlan& P = h->plan;
     const int64_t n = P.n, s = P.s;
     m = (int)std::min<int64_t>(m, s);
+    h->lrun.reorth = DDLR_REORTH_FULL;
     lanczos_start(h, v0_user, seed);  // q_1 in R.Q (device interface order)
     LanczosRun& R = h->lrun;
     hipStream_t st = nullptr;
@@ -1944,11 +2006,11 @@ void gk_build(ddlr_prec* h, int k, int m, const double* v0_user, uint64_t seed) 
     auto reorth = [&](int64_t len, int g, int ncols, const double* V, double* v) {
         if (ncols == 0) return;
         for (int pass = 0; pass < 2; ++pass) {
-            hipLaunchKernelGGL(k_multidot, dim3(g), dim3(256), 0, st, len, ncols, V, len, v, part);
+            hipLaunchKernelGGL(k_multidot, dim3(g), dim3(256), 0, st, len, ncols, V, len, v, part, (const int*)nullptr);
             LAUNCHCHK();
             hipLaunchKernelGGL(k_reduce_cols, dim3(ncols), dim3(256), 0, st, g, ncols, part, csum, nullptr);
             LAUNCHCHK();
-            hipLaunchKernelGGL(k_gemv_sub, dim3(g), dim3(256), 0, st, len, ncols, V, len, csum, v);
+            hipLaunchKernelGGL(k_gemv_sub, dim3(g), dim3(256), 0, st, len, ncols, V, len, csum, v, (const int*)nullptr);
             LAUNCHCHK();
         }
     };
@@ -2032,6 +2094,8 @@ void gk_build(ddlr_prec* h, int k, int m, const double* v0_user, uint64_t seed) 
     }
     h->ta = ha;
     h->tb = hb;
+    h->lreorth = DDLR_REORTH_FULL;
+    h->rflags.assign(meff, 1);
     h->msteps = meff;
     h->ritz.resize(meff);
     for (int c = 0; c < meff; ++c) h->ritz[c] = ev[idx[c]];
@@ -2217,6 +2281,10 @@ ddlr_status ddlr_setup(ddlr_ctx* ctx, const ddlr_csr* A, const int32_t* part, in
         if (opt.csolve == DDLR_CSOLVE_CHEB && (opt.cheb_iters < 1 || opt.cheb_iters > 64 || opt.cheb_lanczos < 2 ||
                                                opt.cheb_lanczos > 200))
             throw SetupError{DDLR_E_INVALID, "Chebyshev: 1 <= cheb_iters <= 64 and 2 <= cheb_lanczos <= 200"};
+        if (opt.lanczos_reorth != DDLR_REORTH_FULL && opt.lanczos_reorth != DDLR_REORTH_PARTIAL)
+            throw SetupError{DDLR_E_INVALID, "lanczos_reorth must be DDLR_REORTH_FULL or DDLR_REORTH_PARTIAL"};
+        if (opt.lanczos_reorth == DDLR_REORTH_PARTIAL && opt.lowrank_build == DDLR_BUILD_BIDIAG)
+            throw SetupError{DDLR_E_INVALID, "partial reorthogonalisation is for the Lanczos build"};
         build_plan(h->plan, A->n, A->row_ptr, A->col_idx, A->val, part, p, opt.alpha, opt.factor, opt.corder,
                    opt.csolve == DDLR_CSOLVE_MR ? 1 : opt.csolve == DDLR_CSOLVE_CHEB ? 2 : 0, opt.cinv_iters,
                    opt.cinv_tol, opt.cinv_lfil, opt.cheb_lanczos);
@@ -2260,6 +2328,7 @@ ddlr_status ddlr_setup(ddlr_ctx* ctx, const ddlr_csr* A, const int32_t* part, in
                         throw SetupError{DDLR_E_INVALID, "the bidiagonalisation build is for DDLR-2 with fixed steps"};
                     gk_build(h.get(), k, m, opt.lanczos_start, opt.seed);
                 } else {
+                    h->lrun.reorth = opt.lanczos_reorth;
                     lanczos_build(h.get(), k, m, opt.lanczos_start, opt.seed, opt.theta, ctl ? opt.lanczos_check : 0,
                                   eps);
                 }
@@ -3345,6 +3414,9 @@ ddlr_status ddlr_query(const ddlr_prec* h, ddlr_info* info) {
     info->fill_ratio = stored / (double)P.A.nnz();
     info->setup_ms = h->setup_ms;
     info->lanczos_ms = h->lanczos_ms;
+    info->lanczos_reorth = h->lreorth;
+    info->lanczos_reorth_steps = 0;
+    for (int32_t f : h->rflags) info->lanczos_reorth_steps += f;
     info->csolve = P.csolve == 1 ? DDLR_CSOLVE_MR : P.csolve == 2 ? DDLR_CSOLVE_CHEB : DDLR_CSOLVE_FACTOR;
     info->cheb_lo = P.ch_lo;
     info->cheb_hi = P.ch_hi;
@@ -3456,6 +3528,19 @@ ddlr_status ddlr_get_lanczos(const ddlr_prec* h, double* alpha, double* beta, do
     if (alpha) std::copy(h->ta.begin(), h->ta.end(), alpha);
     if (beta) std::copy(h->tb.begin(), h->tb.end(), beta);
     if (ritz) std::copy(h->ritz.begin(), h->ritz.end(), ritz);
+    return DDLR_OK;
+}
+
+ddlr_status ddlr_get_lanczos_reorth(const ddlr_prec* h, int32_t* flags) {
+    if (!h || !flags) {
+        g_err = "null argument";
+        return DDLR_E_INVALID;
+    }
+    if (h->ta.empty()) {
+        g_err = "no Lanczos run";
+        return DDLR_E_INVALID;
+    }
+    std::copy(h->rflags.begin(), h->rflags.end(), flags);
     return DDLR_OK;
 }
 

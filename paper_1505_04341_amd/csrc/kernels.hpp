@@ -2144,8 +2144,10 @@ __global__ __launch_bounds__(256) void k_gm_xupdate(int64_t n, int nrhs, const G
 // Q holds the Lanczos vectors as columns (s x (m+1), column-major, ld s).
 // coeffs: c_l = q_l . w for l <= j, as per-block partials part[block][l]
 __global__ __launch_bounds__(256) void k_multidot(int64_t s, int ncols, const double* __restrict__ Q, int64_t ldq,
-                                                  const double* __restrict__ w, double* __restrict__ part) {
+                                                  const double* __restrict__ w, double* __restrict__ part,
+                                                  const int* __restrict__ skip) {
     __shared__ double sh[4];
+    if (skip && *skip) return;
     for (int l = 0; l < ncols; ++l) {
         double acc = 0.0;
         for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < s; i += (int64_t)gridDim.x * blockDim.x)
@@ -2157,8 +2159,10 @@ __global__ __launch_bounds__(256) void k_multidot(int64_t s, int ncols, const do
 
 // w -= Q c  (columns 0..ncols-1, ncols <= 1024: the coefficients are staged in LDS)
 __global__ __launch_bounds__(256) void k_gemv_sub(int64_t s, int ncols, const double* __restrict__ Q, int64_t ldq,
-                                                  const double* __restrict__ c, double* __restrict__ w) {
+                                                  const double* __restrict__ c, double* __restrict__ w,
+                                                  const int* __restrict__ skip) {
     __shared__ double cs[1024];
+    if (skip && *skip) return;
     for (int l = threadIdx.x; l < ncols; l += blockDim.x) cs[l] = c[l];
     __syncthreads();
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < s; i += (int64_t)gridDim.x * blockDim.x) {
@@ -2182,10 +2186,74 @@ __global__ __launch_bounds__(256) void k_lanczos_3term(int64_t s, int j, const d
     }
 }
 
-// dst = reduced sum; beta form: dst = sqrt(sum), inv = dst > 1e-12 max|alpha| ? 1/dst : 0
-__global__ void k_lanczos_scalar(const double* __restrict__ sum, double* __restrict__ dst, int sqrt_it,
-                                 double* __restrict__ amax, double* __restrict__ inv) {
+// Partial reorthogonalisation bookkeeping of Lanczos step j (Simon's omega
+// recurrence; the new vector is w with norm *b0 before any reorthogonalisation):
+// for i < j
+//   om_new_i = (beta_i om_cur_{i+1} + (alpha_i - alpha_j) om_cur_i
+//               + beta_{i-1} om_cur_{i-1} - beta_{j-1} om_prev_i + theta) / b0,
+// theta = 2 eps ||T||_est carrying the sign of the rest (eps = 2^-52; ||T||_est
+// the running max of |alpha_i| + beta_i + beta_{i-1}, kept in *tnorm);
+// om_new_j = eps sqrt(s), om_new_{j+1} = 1.  The step is reorthogonalised
+// (state[1] = 0) when some |om_new_i|, i <= j, exceeds sqrt(eps) or the
+// previous step was (state[0]); its estimates are then reset to eps.
+// state[0]: force the next step; state[1]: 1 = skip the reorthogonalisation;
+// flags[j]: 1 if step j was reorthogonalised.  One workgroup of 1024 threads,
+// j + 2 <= 1024.  A breakdown (b0 <= 1e-12 max|alpha|) skips and leaves the
+// estimates alone.
+__global__ __launch_bounds__(1024) void k_pro_omega(int j, int64_t s, const double* __restrict__ alpha,
+                                                    const double* __restrict__ beta, const double* __restrict__ b0p,
+                                                    const double* __restrict__ amax, const double* __restrict__ om_prev,
+                                                    const double* __restrict__ om_cur, double* __restrict__ om_new,
+                                                    double* __restrict__ tnorm, int* __restrict__ state,
+                                                    int* __restrict__ flags) {
+    __shared__ double red[16];
+    __shared__ int need;
+    const double eps = 2.220446049250313e-16;
+    const double b0 = *b0p, aj = alpha[j], bprev = j > 0 ? beta[j - 1] : 0.0;
+    if (!(b0 > 1e-12 * (*amax))) {
+        if (threadIdx.x == 0) {
+            state[1] = 1;
+            flags[j] = 0;
+        }
+        return;
+    }
+    const double tn = fmax(*tnorm, fabs(aj) + b0 + bprev);
+    const int i = threadIdx.x;
+    double v = 0.0;
+    if (i < j) {
+        double t = beta[i] * om_cur[i + 1] + (alpha[i] - aj) * om_cur[i];
+        if (i > 0) t += beta[i - 1] * om_cur[i - 1];
+        t -= bprev * om_prev[i];
+        t += (t >= 0.0 ? 1.0 : -1.0) * 2.0 * eps * tn;
+        v = t / b0;
+        om_new[i] = v;
+    }
+    double big = fabs(v);
+    for (int off = 32; off > 0; off >>= 1) big = fmax(big, __shfl_down(big, off, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = big;
+    __syncthreads();
     if (threadIdx.x == 0) {
+        const double psi = eps * sqrt((double)s);
+        double m = psi;
+        for (int w = 0; w < 16; ++w) m = fmax(m, red[w]);
+        const int forced = state[0];
+        need = forced || m > sqrt(eps);
+        om_new[j] = psi;
+        om_new[j + 1] = 1.0;
+        *tnorm = tn;
+        state[0] = need ? (forced ? 0 : 1) : 0;
+        state[1] = need ? 0 : 1;
+        flags[j] = need;
+    }
+    __syncthreads();
+    if (need && i <= j) om_new[i] = eps;
+}
+
+// dst = reduced sum; beta form: dst = sqrt(sum), inv = dst > 1e-12 max|alpha| ? 1/dst : 0;
+// nothing when *skip is set
+__global__ void k_lanczos_scalar(const double* __restrict__ sum, double* __restrict__ dst, int sqrt_it,
+                                 double* __restrict__ amax, double* __restrict__ inv, const int* __restrict__ skip) {
+    if (threadIdx.x == 0 && !(skip && *skip)) {
         double s = *sum;
         if (sqrt_it) {
             s = sqrt(s);

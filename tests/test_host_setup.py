@@ -172,6 +172,23 @@ def test_cinv_option_errors():
         D.ddlr_get_cinv(h)
 
 
+def test_reorth_option_errors():
+    """lanczos_reorth takes DDLR_REORTH_FULL or _PARTIAL, and partial
+    reorthogonalisation belongs to the Lanczos build, not the
+    bidiagonalisation; a handle without a Lanczos run has no flags."""
+    c = w.config("c1")
+    args = (c["A"], c["part"], c["p"], c["k"])
+    for kw in (dict(lanczos_reorth=2), dict(lanczos_reorth=-1),
+               dict(lanczos_reorth=D.REORTH_PARTIAL, lowrank_build=D.BUILD_BIDIAG)):
+        with pytest.raises(D.DDLRError) as e:
+            D.ddlr_setup(*args, D.DDLR_2, device=-1, **kw)
+        assert e.value.status == D.E_INVALID
+    h = D.ddlr_setup(*args, D.DDLR_1, device=-1, lanczos_reorth=D.REORTH_PARTIAL)
+    assert D.ddlr_query(h)["lanczos_reorth_steps"] == 0
+    with pytest.raises(D.DDLRError):
+        D.ddlr_get_lanczos_reorth(h)
+
+
 @pytest.mark.parametrize("name,cfg,kw", list(_cases()), ids=[c[0] for c in _cases()])
 def test_cheb_factor_and_interval_match_oracle(name, cfg, kw):
     """Chebyshev C_alpha solver: the block-Jacobi factor of D_alpha (interface
