@@ -213,7 +213,9 @@ struct Workspace {
     // Krylov (double, device order)
     double *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
     // preconditioner temporaries (type of the preconditioner)
-    void *a0 = nullptr, *a1 = nullptr, *a2 = nullptr, *a3 = nullptr, *ys = nullptr, *ws = nullptr;
+    void *a1 = nullptr, *a2 = nullptr, *ys = nullptr, *ws = nullptr;
+    void* ry = nullptr;  // forward results of the R-column ring kernel (ry_cols columns, R values per row)
+    int ry_cols = 0;
     double *part = nullptr, *sums = nullptr, *coef = nullptr, *lrsum = nullptr;
     unsigned* ctr = nullptr;  // workgroup counter of k_reduce_lane, zero between launches
     double* xa = nullptr;  // per-lane step of the deferred x update
@@ -310,8 +312,11 @@ struct ddlr_prec {
     void *ch_t = nullptr, *ch_r = nullptr, *ch_d = nullptr, *ch_x = nullptr;  // n x kMaxRhs each, type T
     double *fval64 = nullptr, *bval64 = nullptr;
     float *fval32 = nullptr, *bval32 = nullptr;
-    int2 *fpk32 = nullptr, *bpk32 = nullptr;  // the FP32 entries as (column, value bits) pairs
-    int ring_kw = 0;                          // 2, 3, 4, 8, 16 or 0 (ring kernel unusable)
+    // packed per-row records of the R-column ring kernel (RecLayout), in the
+    // handle's precision, with per-level word offsets; null when KW > 4
+    int32_t *rfoff = nullptr, *rboff = nullptr, *frec = nullptr, *brec = nullptr;
+    int rec_prec = -1;  // DDLR_FP64 (double records) or DDLR_FP32 (float records)
+    int ring_kw = 0;    // 2, 3, 4, 8, 16 or 0 (ring kernel unusable)
     bool ring_ok64 = false, ring_ok32 = false;  // dependency window fits the LDS ring
     int ring_need = 0;                          // rows the ring must hold (dependency window)
     int ring_maxw = 0;                          // widest level of the narrow blocks
@@ -628,6 +633,55 @@ void merge_devhost(const std::vector<const DevHost*>& parts, DevHost& out) {
     out.s = S;
 }
 
+// Packed records (RecLayout) of one sweep's factor for the R-column ring
+// kernel: per level, the chunk arrays of its rows one after another, level
+// offsets in words (multiples of four).  Values are rounded to T as the
+// factor's own T copy is; D^{-1} (backward) likewise.
+template <typename T, int KW, bool kBwd>
+void pack_records(const DevHost& D, const std::vector<int32_t>& rp, const std::vector<int32_t>& ci,
+                  const std::vector<double>& v, std::vector<int32_t>& off, std::vector<int32_t>& rec) {
+    using L = RecLayout<T, KW, kBwd>;
+    const int nlev = (int)D.lvl_ptr.size() - 1;
+    off.assign(nlev, 0);
+    rec.clear();
+    auto put = [](uint32_t* w, int word, double x) {
+        const T t = (T)x;
+        std::memcpy(w + word, &t, sizeof(T));
+    };
+    for (int l = 0; l < nlev; ++l) {
+        const int a = D.lvl_ptr[l], e = D.lvl_ptr[l + 1], nr = e - a;
+        const size_t o = rec.size();
+        off[l] = (int32_t)std::min<size_t>(o, INT32_MAX);
+        rec.resize(o + (size_t)L::kPadded * nr, 0);
+        for (int i = a; i < e; ++i) {
+            uint32_t w[L::kPadded] = {};
+            for (int t = rp[i], j = 0; t < rp[i + 1] && j < KW; ++t, ++j) {
+                put(w, j * L::kTW, v[t]);
+                w[L::kColW + j / 2] |= ((uint32_t)(ci[t] - D.lvl_row0[l]) & 0xffffu) << (16 * (j & 1));
+            }
+            if (kBwd) put(w, L::kDiag, D.dinv[i]);
+            const size_t r = (size_t)(i - a);
+            for (int c = 0; c < L::kN4; ++c)
+                for (int k = 0; k < 4; ++k) rec[o + ((size_t)c * nr + r) * 4 + k] = (int32_t)w[4 * c + k];
+            for (int k = 0; k < L::kRem; ++k)
+                rec[o + (size_t)4 * L::kN4 * nr + r * L::kRem + k] = (int32_t)w[4 * L::kN4 + k];
+        }
+        rec.resize((rec.size() + 3) / 4 * 4, 0);
+    }
+}
+
+template <int KW>
+void pack_all(const DevHost& D, bool f64, std::vector<int32_t>& rfo, std::vector<int32_t>& frec,
+              std::vector<int32_t>& rbo, std::vector<int32_t>& brec) {
+    if (f64) {
+        pack_records<double, KW, false>(D, D.lrp, D.lci, D.lv, rfo, frec);
+        pack_records<double, KW, true>(D, D.urp, D.uci, D.uv, rbo, brec);
+    } else {
+        pack_records<float, KW, false>(D, D.lrp, D.lci, D.lv, rfo, frec);
+        pack_records<float, KW, true>(D, D.urp, D.uci, D.uv, rbo, brec);
+    }
+}
+
 // Per-level ELL copies of L (forward) and L^T (backward) for the ring kernel,
 // fixed width KW for every level, block-local column indices, and the check
 // that every dependency falls inside the LDS window of the most recent kRing
@@ -715,17 +769,22 @@ void build_ring(ddlr_prec* h, const DevHost& D) {
         std::vector<float> f(fval.begin(), fval.end()), g(bval.begin(), bval.end());
         h->fval32 = M.upload(f);
         h->bval32 = M.upload(g);
-        auto pack = [](const std::vector<int32_t>& col, const std::vector<float>& val) {
-            std::vector<int2> pk(col.size());
-            for (size_t q = 0; q < col.size(); ++q) {
-                int32_t bits;
-                std::memcpy(&bits, &val[q], sizeof bits);
-                pk[q] = int2{col[q], bits};
-            }
-            return pk;
-        };
-        h->fpk32 = M.upload(pack(fcol, f));
-        h->bpk32 = M.upload(pack(bcol, g));
+    }
+    if (KW <= 4) {
+        std::vector<int32_t> rfo, rbo, frec, brec;
+        const bool f64 = h->precision == DDLR_FP64;
+        switch (KW) {
+        case 2: pack_all<2>(D, f64, rfo, frec, rbo, brec); break;
+        case 3: pack_all<3>(D, f64, rfo, frec, rbo, brec); break;
+        default: pack_all<4>(D, f64, rfo, frec, rbo, brec); break;
+        }
+        if (frec.size() <= (size_t)INT32_MAX && brec.size() <= (size_t)INT32_MAX) {
+            h->rfoff = M.upload(rfo);
+            h->rboff = M.upload(rbo);
+            h->frec = M.upload(frec);
+            h->brec = M.upload(brec);
+            h->rec_prec = f64 ? DDLR_FP64 : DDLR_FP32;
+        }
     }
 }
 
@@ -917,10 +976,10 @@ void ensure_ws(ddlr_prec* h, int nrhs) {
     W.p = W.mem.alloc<double>(n * lane_stride(nrhs));
     HIPCHK(hipMemset(W.p, 0, sizeof(double) * n * lane_stride(nrhs)));
     W.q = W.mem.alloc<double>(n * nrhs);
-    W.a0 = W.mem.alloc<char>(tsz * n * nrhs);
     W.a1 = W.mem.alloc<char>(tsz * n * nrhs);
     W.a2 = W.mem.alloc<char>(tsz * n * nrhs);
-    W.a3 = W.mem.alloc<char>(tsz * n * nrhs);
+    W.ry = W.mem.alloc<char>(tsz * n * nrhs);
+    W.ry_cols = nrhs;
     W.ys = W.mem.alloc<char>(tsz * s * nrhs);
     W.ws = W.mem.alloc<char>(tsz * s * nrhs);
     const int kk = std::max(1, h->k);
@@ -1049,10 +1108,14 @@ void launch_ring(ddlr_prec* h, const T* dinv, int nrhs, const TIn* x, int64_t ld
     }
 }
 
-// R columns per workgroup (the ring holds ring_rows_r<T, R>() rows of R values)
-template <typename T> bool ring_r_ok(const ddlr_prec* h, int R) {
+// R columns per workgroup (the ring holds ring_rows_r<T, R>() rows of R values);
+// R > 1 needs the packed records in T and the workspace's buffer for the
+// forward results of nrhs columns
+template <typename T> bool ring_r_ok(const ddlr_prec* h, int R, int nrhs) {
     if (R == 1) return true;  // the one-column kernel, or the plain fallback
-    if (!ring_ready<T>(h) || h->ring_kw > 4) return false;
+    if (!ring_ready<T>(h) || h->ring_kw > 4 || !h->frec) return false;
+    if (h->rec_prec != (sizeof(T) == 8 ? DDLR_FP64 : DDLR_FP32)) return false;
+    if (!h->ws.ry || h->ws.ry_cols < nrhs) return false;
     switch (R) {
     case 2: return h->ring_need <= ring_rows_r<T, 2>();
     case 4: return h->ring_need <= ring_rows_r<T, 4>();
@@ -1064,10 +1127,12 @@ template <typename T> bool ring_r_ok(const ddlr_prec* h, int R) {
 template <typename T, int KW, int R, typename TIn, typename TOut>
 void launch_ring_rk(ddlr_prec* h, const T* dinv, int nrhs, const TIn* x, int64_t ldx, TOut* z, int64_t ldz,
                     hipStream_t st, const int* done) {
+    (void)dinv;  // D^{-1} is inside the backward records
     const int ng = nrhs / R;
+    const int64_t n = h->ndev;
     hipLaunchKernelGGL((k_trsv_ring_r<T, KW, R, TIn, TOut>), dim3(h->nnarrow_pad * ng), dim3(kRingThreads), 0, st,
-                       h->rblk, h->nnarrow, h->nnarrow_pad, ng, h->lvl_ptr, h->foff, h->fcol, ring_fval<T>(h),
-                       h->fpk32, h->boff_, h->bcol, ring_bval<T>(h), h->bpk32, dinv, x, ldx, z, ldz, done);
+                       h->rblk, h->nnarrow, h->nnarrow_pad, ng, h->lvl_ptr, h->rfoff, h->rboff, h->frec, h->brec, x,
+                       ldx, (T*)h->ws.ry, (int64_t)R * n, z, ldz, done);
     LAUNCHCHK();
 }
 
@@ -1088,7 +1153,7 @@ template <typename T> int ring_r_for(const ddlr_prec* h, int nrhs) {
     auto it = h->tune.find(nrhs);
     if (it != h->tune.end()) R = it->second.ring_r;
     if (const char* env = std::getenv("DDLR_RING_R")) R = std::atoi(env);
-    while (R > 1 && (nrhs % R != 0 || !ring_r_ok<T>(h, R))) R >>= 1;
+    while (R > 1 && (nrhs % R != 0 || !ring_r_ok<T>(h, R, nrhs))) R >>= 1;
     return std::max(R, 1);
 }
 
@@ -2404,7 +2469,7 @@ void autotune_T(ddlr_prec* h, const DevFactors<T>& F, int nrhs, hipStream_t st) 
     tn.ring_nt = 512;
     for (int q = 0; q < 4; ++q) {
         const int R = Rs[q];
-        if (nrhs % R != 0 || !ring_r_ok<T>(h, R) || (R > 1 && h->nnarrow == 0)) continue;
+        if (nrhs % R != 0 || !ring_r_ok<T>(h, R, nrhs) || (R > 1 && h->nnarrow == 0)) continue;
         tn.ring_r = R;
         tn.a0_us[q] = time_a0();
         if (tn.a0_us[q] < best) {
@@ -2549,11 +2614,14 @@ struct ScratchView {
     ddlr_prec* h;
     void *a1, *a2, *ys, *ws, *ct, *cr, *cd, *cx;
     double *part, *lrsum, *coef;
+    int ry_cols;
     bool prof;
     double *in = nullptr, *out = nullptr;
     ScratchView(ddlr_prec* h_, char* base, int nr) : h(h_) {
         Workspace& W = h->ws;
         a1 = W.a1, a2 = W.a2, ys = W.ys, ws = W.ws, part = W.part, lrsum = W.lrsum, coef = W.coef;
+        ry_cols = W.ry_cols;
+        W.ry_cols = 0;  // no buffer for the R-column ring kernel: one column per workgroup
         ct = h->ch_t, cr = h->ch_r, cd = h->ch_d, cx = h->ch_x;
         prof = h->prof;
         auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
@@ -2585,6 +2653,7 @@ struct ScratchView {
     ~ScratchView() {
         Workspace& W = h->ws;
         W.a1 = a1, W.a2 = a2, W.ys = ys, W.ws = ws, W.part = part, W.lrsum = lrsum, W.coef = coef;
+        W.ry_cols = ry_cols;
         h->ch_t = ct, h->ch_r = cr, h->ch_d = cd, h->ch_x = cx;
         h->prof = prof;
     }

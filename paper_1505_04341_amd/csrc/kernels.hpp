@@ -343,39 +343,88 @@ __global__ __launch_bounds__(NT) void k_trsv_ring(
 // operations in the same order), so the results are bitwise the same for any
 // R.  The ring holds kRing rows of R values (64 KB); the host checks the
 // dependency window against kRing as for the one-column kernel.
+//
+// The kernel is bound by vector-memory instructions per level, so each row's
+// factor data is one packed record read with as few wide loads as possible,
+// and the forward result y goes to a private buffer with the R values of a
+// row side by side (one store, one load) instead of R column stores and loads.
 template <typename T, int R> constexpr int ring_rows_r() { return 65536 / (int)(sizeof(T) * R); }
 
-template <typename T, int KW, int R, typename TS> struct LevelRegsR {
-    int a, e, off;
-    int c[2][KW];
-    T v[2][KW];
-    TS xv[2][R];
-    T dv[2];
+// Packed record of one row (at most KW <= 4 entries) in 32-bit words: the KW
+// values of T; in the backward sweep D_i^{-1} as T; then the KW block-local
+// columns modulo 65536 as 16-bit halves (entry j in word kColW + j/2, high
+// half for odd j; the ring index only needs the column modulo the ring size, a
+// power of two that divides 65536).  A level's records are stored chunk by
+// chunk for coalescing: kN4 arrays of four-word chunks, then one array of the
+// kRem remaining words (1, 2, or 4 when three remain).  Level offsets are
+// multiples of four words.  Padding entries have column 0 and value 0.
+template <typename T, int KW, bool kBwd> struct RecLayout {
+    static constexpr int kTW = (int)(sizeof(T) / 4);
+    static constexpr int kDiag = KW * kTW;
+    static constexpr int kColW = kDiag + (kBwd ? kTW : 0);
+    static constexpr int kWords = kColW + (KW + 1) / 2;
+    static constexpr int kN4 = kWords / 4;
+    static constexpr int kRem = kWords % 4 == 3 ? 4 : kWords % 4;
+    static constexpr int kPadded = kN4 * 4 + kRem;
 };
 
-// FP32 factors come as (column, value) pairs in one 8-byte word per entry
-// (epk), so an entry takes one vector load instead of two: the kernel is bound
-// by vector-memory instructions per level.  FP64 keeps separate arrays.
-template <typename T> constexpr bool ring_packed() { return sizeof(T) == 4; }
+template <typename T> __device__ __forceinline__ T rec_value(const uint32_t* w, int word) {
+    if constexpr (sizeof(T) == 4) return __uint_as_float(w[word]);
+    else return __hiloint2double((int)w[word + 1], (int)w[word]);
+}
 
-template <typename T>
-__device__ __forceinline__ void ring_entry(const int32_t* __restrict__ ecol, const T* __restrict__ eval,
-                                           const int2* __restrict__ epk, int q, int& c, T& v) {
-    if constexpr (ring_packed<T>()) {
-        const int2 t = epk[q];
-        c = t.x;
-        v = __int_as_float(t.y);
-    } else {
-        c = ecol[q];
-        v = eval[q];
+// words of record r (0-based row of the level) of a level with nr rows at word offset off
+template <typename T, int KW, bool kBwd>
+__device__ __forceinline__ void rec_load(const int32_t* __restrict__ rec, int off, int nr, int r,
+                                         uint32_t (&w)[RecLayout<T, KW, kBwd>::kPadded]) {
+    using L = RecLayout<T, KW, kBwd>;
+    const int4* p4 = reinterpret_cast<const int4*>(rec + off);
+#pragma unroll
+    for (int c = 0; c < L::kN4; ++c) {
+        const int4 t = p4[c * nr + r];
+        w[4 * c] = (uint32_t)t.x, w[4 * c + 1] = (uint32_t)t.y, w[4 * c + 2] = (uint32_t)t.z,
+                 w[4 * c + 3] = (uint32_t)t.w;
+    }
+    const int32_t* tail = rec + off + 4 * L::kN4 * nr;
+    if constexpr (L::kRem == 1) {
+        w[4 * L::kN4] = (uint32_t)tail[r];
+    } else if constexpr (L::kRem == 2) {
+        const int2 t = reinterpret_cast<const int2*>(tail)[r];
+        w[4 * L::kN4] = (uint32_t)t.x, w[4 * L::kN4 + 1] = (uint32_t)t.y;
+    } else if constexpr (L::kRem == 4) {
+        const int4 t = reinterpret_cast<const int4*>(tail)[r];
+        w[4 * L::kN4] = (uint32_t)t.x, w[4 * L::kN4 + 1] = (uint32_t)t.y, w[4 * L::kN4 + 2] = (uint32_t)t.z,
+                   w[4 * L::kN4 + 3] = (uint32_t)t.w;
     }
 }
 
-template <typename T, int KW, int R, bool kBwd, typename TS>
-__device__ __forceinline__ void ringr_load(LevelRegsR<T, KW, R, TS>& L, int q, int row0, const int4* meta,
-                                           const int32_t* __restrict__ ecol, const T* __restrict__ eval,
-                                           const int2* __restrict__ epk, const T* __restrict__ dinv, const TS* src,
-                                           int64_t lds) {
+// Registers of one prefetched level: up to two row sets (rows a + tid and
+// a + tid + kRingThreads), each a packed record and the R right-hand-side
+// values in their storage type TS.
+template <typename T, int KW, int R, bool kBwd, typename TS> struct LevelRegsR {
+    int a, e, off;
+    uint32_t w[2][RecLayout<T, KW, kBwd>::kPadded];
+    TS xv[2][R];
+};
+
+// The right-hand side of row i: interleaved (kIl: R values of T side by side,
+// the private forward result) or column-major with leading dimension ld.
+template <int R, bool kIl, typename TS>
+__device__ __forceinline__ void rhs_load(const TS* src, int64_t ld, int i, TS (&xv)[R]) {
+    if constexpr (kIl) {
+        using V = TS __attribute__((ext_vector_type(R)));
+        const V t = *reinterpret_cast<const V*>(src + (size_t)i * R);
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr) xv[rr] = t[rr];
+    } else {
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr) xv[rr] = src[i + rr * ld];
+    }
+}
+
+template <typename T, int KW, int R, bool kBwd, typename TS, bool kSrcIl>
+__device__ __forceinline__ void ringr_load(LevelRegsR<T, KW, R, kBwd, TS>& L, int q, const int4* meta,
+                                           const int32_t* __restrict__ rec, const TS* src, int64_t lds) {
     const int4 mq = meta[q];
     L.a = __builtin_amdgcn_readfirstlane(mq.x);
     L.e = __builtin_amdgcn_readfirstlane(meta[q + 1].x);
@@ -385,60 +434,64 @@ __device__ __forceinline__ void ringr_load(LevelRegsR<T, KW, R, TS>& L, int q, i
     for (int qq = 0; qq < 2; ++qq) {
         if (qq == 1 && nr <= kRingThreads) break;  // uniform: one row set covers the level
         const int i = min(L.a + (int)threadIdx.x + qq * kRingThreads, L.e - 1);
-        const int base = L.off + (i - L.a);
-#pragma unroll
-        for (int j = 0; j < KW; ++j) ring_entry<T>(ecol, eval, epk, base + j * nr, L.c[qq][j], L.v[qq][j]);
-#pragma unroll
-        for (int rr = 0; rr < R; ++rr) L.xv[qq][rr] = src[i + rr * lds];
-        if (kBwd) L.dv[qq] = dinv[row0 + i];
+        rec_load<T, KW, kBwd>(rec, L.off, nr, i - L.a, L.w[qq]);
+        rhs_load<R, kSrcIl>(src, lds, i, L.xv[qq]);
     }
 }
 
-template <typename T, int KW, int kRing, int R, bool kBwd, typename TS, typename TD>
-__device__ __forceinline__ void ringr_compute(const LevelRegsR<T, KW, R, TS>& L, int row0, T* ring,
-                                              const int32_t* __restrict__ ecol, const T* __restrict__ eval,
-                                              const int2* __restrict__ epk, const T* __restrict__ dinv,
-                                              const TS* src, int64_t lds, TD* dst, int64_t ldd) {
+// One row: s = x_i (backward: D_i^{-1} x_i), minus its KW entries times the
+// gathered ring values, in entry order; the result goes to the ring and to dst.
+template <typename T, int KW, int kRing, int R, bool kBwd, typename TS, typename TD, bool kDstIl>
+__device__ __forceinline__ void ringr_row(const uint32_t* w, const TS (&xv)[R], int i, bool store, T* ring, TD* dst,
+                                          int64_t ldd) {
+    using L = RecLayout<T, KW, kBwd>;
     using V = T __attribute__((ext_vector_type(R)));
+    V sv;
+    if constexpr (kBwd) {
+        const T dv = rec_value<T>(w, L::kDiag);
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-        if (q == 1 && L.e - L.a <= kRingThreads) break;
-        const int i0 = L.a + (int)threadIdx.x + q * kRingThreads;
-        const int i = min(i0, L.e - 1);
-        V sv;
+        for (int rr = 0; rr < R; ++rr) sv[rr] = (T)xv[rr] * dv;
+    } else {
 #pragma unroll
-        for (int rr = 0; rr < R; ++rr) sv[rr] = kBwd ? (T)L.xv[q][rr] * L.dv[q] : (T)L.xv[q][rr];
+        for (int rr = 0; rr < R; ++rr) sv[rr] = (T)xv[rr];
+    }
 #pragma unroll
-        for (int j = 0; j < KW; ++j) {
-            const V g = *reinterpret_cast<const V*>(ring + (size_t)(L.c[q][j] & (kRing - 1)) * R);
+    for (int j = 0; j < KW; ++j) {
+        const int c = (int)((w[L::kColW + j / 2] >> (16 * (j & 1))) & 0xffffu);
+        const T v = rec_value<T>(w, j * L::kTW);
+        const V g = *reinterpret_cast<const V*>(ring + (size_t)(c & (kRing - 1)) * R);
 #pragma unroll
-            for (int rr = 0; rr < R; ++rr) sv[rr] = fnms(sv[rr], L.v[q][j], g[rr]);
-        }
-        if (i0 < L.e) {
-            *reinterpret_cast<V*>(ring + (size_t)(i & (kRing - 1)) * R) = sv;
+        for (int rr = 0; rr < R; ++rr) sv[rr] = fnms(sv[rr], v, g[rr]);
+    }
+    if (store) {
+        *reinterpret_cast<V*>(ring + (size_t)(i & (kRing - 1)) * R) = sv;
+        if constexpr (kDstIl) {
+            *reinterpret_cast<V*>(dst + (size_t)i * R) = sv;
+        } else {
 #pragma unroll
             for (int rr = 0; rr < R; ++rr) dst[i + rr * ldd] = (TD)sv[rr];
         }
     }
+}
+
+template <typename T, int KW, int kRing, int R, bool kBwd, typename TS, bool kSrcIl, typename TD, bool kDstIl>
+__device__ __forceinline__ void ringr_compute(const LevelRegsR<T, KW, R, kBwd, TS>& L, T* ring,
+                                              const int32_t* __restrict__ rec, const TS* src, int64_t lds, TD* dst,
+                                              int64_t ldd) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        if (q == 1 && L.e - L.a <= kRingThreads) break;
+        const int i0 = L.a + (int)threadIdx.x + q * kRingThreads;
+        ringr_row<T, KW, kRing, R, kBwd, TS, TD, kDstIl>(L.w[q], L.xv[q], min(i0, L.e - 1), i0 < L.e, ring, dst, ldd);
+    }
     // rows beyond 2 * kRingThreads: no prefetch
     const int nr = L.e - L.a;
     for (int i = L.a + 2 * kRingThreads + (int)threadIdx.x; i < L.e; i += kRingThreads) {
-        const int base = L.off + (i - L.a);
-        V sv;
-        const T dvi = kBwd ? dinv[row0 + i] : T(1);
-#pragma unroll
-        for (int rr = 0; rr < R; ++rr) sv[rr] = kBwd ? (T)src[i + rr * lds] * dvi : (T)src[i + rr * lds];
-        for (int j = 0; j < KW; ++j) {
-            int cj;
-            T vj;
-            ring_entry<T>(ecol, eval, epk, base + j * nr, cj, vj);
-            const V g = *reinterpret_cast<const V*>(ring + (size_t)(cj & (kRing - 1)) * R);
-#pragma unroll
-            for (int rr = 0; rr < R; ++rr) sv[rr] = fnms(sv[rr], vj, g[rr]);
-        }
-        *reinterpret_cast<V*>(ring + (size_t)(i & (kRing - 1)) * R) = sv;
-#pragma unroll
-        for (int rr = 0; rr < R; ++rr) dst[i + rr * ldd] = (TD)sv[rr];
+        uint32_t w[RecLayout<T, KW, kBwd>::kPadded];
+        TS xv[R];
+        rec_load<T, KW, kBwd>(rec, L.off, nr, i - L.a, w);
+        rhs_load<R, kSrcIl>(src, lds, i, xv);
+        ringr_row<T, KW, kRing, R, kBwd, TS, TD, kDstIl>(w, xv, i, true, ring, dst, ldd);
     }
 }
 
@@ -450,59 +503,56 @@ __device__ __forceinline__ void ringr_compute(const LevelRegsR<T, KW, R, TS>& L,
 template <typename T, int R> struct RingDepthR { static constexpr int value = R <= 2 ? 5 : 3; };
 template <int R> struct RingDepthR<double, R> { static constexpr int value = R <= 2 ? 4 : 2; };
 
-template <typename T, int KW, int kRing, int R, bool kBwd, typename TS, typename TD>
-__device__ __forceinline__ void ringr_sweep(int nlev, int row0, const int4* meta, T* ring,
-                                            const int32_t* __restrict__ ecol, const T* __restrict__ eval,
-                                            const int2* __restrict__ epk, const T* __restrict__ dinv, const TS* src,
-                                            int64_t lds, TD* dst, int64_t ldd) {
+template <typename T, int KW, int kRing, int R, bool kBwd, typename TS, bool kSrcIl, typename TD, bool kDstIl>
+__device__ __forceinline__ void ringr_sweep(int nlev, const int4* meta, T* ring, const int32_t* __restrict__ rec,
+                                            const TS* src, int64_t lds, TD* dst, int64_t ldd) {
     constexpr int kD = RingDepthR<T, R>::value;
-    LevelRegsR<T, KW, R, TS> buf[kD];
-    auto lev = [&](int q) { return kBwd ? nlev - 1 - q : q; };
+    LevelRegsR<T, KW, R, kBwd, TS> buf[kD];
+#define DDLR_RINGR_LOAD(u, q) \
+    ringr_load<T, KW, R, kBwd, TS, kSrcIl>(buf[u], kBwd ? nlev - 1 - (q) : (q), meta, rec, src, lds)
+#define DDLR_RINGR_COMPUTE(u) \
+    ringr_compute<T, KW, kRing, R, kBwd, TS, kSrcIl, TD, kDstIl>(buf[u], ring, rec, src, lds, dst, ldd)
     int q0 = 0;
     if (nlev >= 2 * kD - 1) {  // steady state behind an unconditional prologue, as in ring_sweep
 #pragma unroll
-        for (int u = 0; u < kD - 1; ++u)
-            ringr_load<T, KW, R, kBwd, TS>(buf[u], lev(u), row0, meta, ecol, eval, epk, dinv, src, lds);
+        for (int u = 0; u < kD - 1; ++u) DDLR_RINGR_LOAD(u, u);
         for (; q0 + 2 * kD - 1 <= nlev; q0 += kD) {
 #pragma unroll
             for (int u = 0; u < kD; ++u) {
-                ringr_load<T, KW, R, kBwd, TS>(buf[(u + kD - 1) % kD], lev(q0 + u + kD - 1), row0, meta, ecol, eval,
-                                               epk, dinv, src, lds);
-                ringr_compute<T, KW, kRing, R, kBwd, TS, TD>(buf[u], row0, ring, ecol, eval, epk, dinv, src, lds, dst,
-                                                             ldd);
+                DDLR_RINGR_LOAD((u + kD - 1) % kD, q0 + u + kD - 1);
+                DDLR_RINGR_COMPUTE(u);
                 lds_barrier();
             }
         }
     } else {
 #pragma unroll
         for (int u = 0; u < kD - 1; ++u)
-            if (u < nlev) ringr_load<T, KW, R, kBwd, TS>(buf[u], lev(u), row0, meta, ecol, eval, epk, dinv, src, lds);
+            if (u < nlev) DDLR_RINGR_LOAD(u, u);
     }
     for (; q0 < nlev; q0 += kD) {
 #pragma unroll
         for (int u = 0; u < kD; ++u) {
             const int q = q0 + u;
             if (q < nlev) {
-                if (q + kD - 1 < nlev)
-                    ringr_load<T, KW, R, kBwd, TS>(buf[(u + kD - 1) % kD], lev(q + kD - 1), row0, meta, ecol, eval,
-                                                   epk, dinv, src, lds);
-                ringr_compute<T, KW, kRing, R, kBwd, TS, TD>(buf[u], row0, ring, ecol, eval, epk, dinv, src, lds, dst,
-                                                             ldd);
+                if (q + kD - 1 < nlev) DDLR_RINGR_LOAD((u + kD - 1) % kD, q + kD - 1);
+                DDLR_RINGR_COMPUTE(u);
                 lds_barrier();
             }
         }
     }
+#undef DDLR_RINGR_LOAD
+#undef DDLR_RINGR_COMPUTE
 }
 
 // grid: nblk_pad * ngroups workgroups; workgroup (b, g) solves block b for
-// columns g*R .. g*R+R-1 (the host launches only ngroups = nrhs / R).
+// columns g*R .. g*R+R-1 (the host launches only ngroups = nrhs / R).  The
+// forward result of the group goes to ry + g * ldry, R values per row.
 template <typename T, int KW, int R, typename TIn, typename TOut>
 __global__ __launch_bounds__(kRingThreads) void k_trsv_ring_r(
     const RingBlock* __restrict__ blk, int nblk, int nblk_pad, int ngroups, const int32_t* __restrict__ lvl_ptr,
-    const int32_t* __restrict__ foff, const int32_t* __restrict__ fcol, const T* __restrict__ fval,
-    const int2* __restrict__ fpk, const int32_t* __restrict__ boff, const int32_t* __restrict__ bcol,
-    const T* __restrict__ bval, const int2* __restrict__ bpk, const T* __restrict__ dinv, const TIn* x, int64_t ldx,
-    TOut* z, int64_t ldz, const int* __restrict__ done) {
+    const int32_t* __restrict__ rfoff, const int32_t* __restrict__ rboff, const int32_t* __restrict__ frec,
+    const int32_t* __restrict__ brec, const TIn* x, int64_t ldx, T* ry, int64_t ldry, TOut* z, int64_t ldz,
+    const int* __restrict__ done) {
     constexpr int kRing = ring_rows_r<T, R>();
     __shared__ __attribute__((aligned(16))) T ring[kRing * R];
     __shared__ int4 meta[kRingMaxLevels + 1];
@@ -514,17 +564,16 @@ __global__ __launch_bounds__(kRingThreads) void k_trsv_ring_r(
     if (nlev <= 0) return;
     for (int q = threadIdx.x; q <= nlev; q += kRingThreads) {
         const int l = d.lvl0 + q;
-        meta[q] = q < nlev ? int4{lvl_ptr[l] - d.row0, foff[l], boff[l], 0} : int4{lvl_ptr[l] - d.row0, 0, 0, 0};
+        meta[q] = q < nlev ? int4{lvl_ptr[l] - d.row0, rfoff[l], rboff[l], 0} : int4{lvl_ptr[l] - d.row0, 0, 0, 0};
     }
     for (int q = threadIdx.x; q < kRing * R; q += kRingThreads) ring[q] = T(0);
     __syncthreads();
     const TIn* xr = x + (int64_t)g * R * ldx + d.row0;
+    T* yr = ry + (int64_t)g * ldry + (int64_t)d.row0 * R;
     TOut* zr = z + (int64_t)g * R * ldz + d.row0;
-    ringr_sweep<T, KW, kRing, R, false, TIn, TOut>(nlev, d.row0, meta, ring, fcol, fval, fpk, dinv, xr, ldx, zr,
-                                                   ldz);
-    __syncthreads();  // global fence: the backward sweep reads y_i from memory
-    ringr_sweep<T, KW, kRing, R, true, TOut, TOut>(nlev, d.row0, meta, ring, bcol, bval, bpk, dinv, zr, ldz, zr,
-                                                   ldz);
+    ringr_sweep<T, KW, kRing, R, false, TIn, false, T, true>(nlev, meta, ring, frec, xr, ldx, yr, 0);
+    __syncthreads();
+    ringr_sweep<T, KW, kRing, R, true, T, true, TOut, false>(nlev, meta, ring, brec, yr, 0, zr, ldz);
 }
 
 // ------------------------------------------------ A0 solve: one wide level
