@@ -458,7 +458,8 @@ typedef struct {
     int32_t overlap;         /* 1: interface levels on the side stream, 0: in line */
     int32_t ring_threads;    /* threads per workgroup of the block triangular solve (64, 256, 512), or -1:
                                 the plain per-level kernel (CSR rows, no LDS ring) */
-    float a0_us[4];          /* A0 solve time, 512 threads, 1, 2, 4, 8 columns per workgroup (0: not eligible) */
+    float a0_us[4];          /* A0 solve time, 512 threads, 1, 2, 4, 8 columns per workgroup (0: not eligible);
+                                one column runs the packed-record kernel when its data exist */
     float a0_no_overlap_us;  /* best shape with the interface levels in line (0: not measured) */
     float a0_thin_us[2];     /* one column per workgroup of 64 / 256 threads (0: not eligible) */
     float a0_plain_us;       /* the plain per-level kernel (0: not measured) */

@@ -216,6 +216,8 @@ struct Workspace {
     void *a1 = nullptr, *a2 = nullptr, *ys = nullptr, *ws = nullptr;
     void* ry = nullptr;  // forward results of the R-column ring kernel (ry_cols columns, R values per row)
     int ry_cols = 0;
+    void* iy = nullptr;  // interface levels' values, iy_cols (a power of two) per interface row
+    int iy_cols = 0;
     double *part = nullptr, *sums = nullptr, *coef = nullptr, *lrsum = nullptr;
     unsigned* ctr = nullptr;  // workgroup counter of k_reduce_lane, zero between launches
     double* xa = nullptr;  // per-lane step of the deferred x update
@@ -316,6 +318,12 @@ struct ddlr_prec {
     // handle's precision, with per-level word offsets; null when KW > 4
     int32_t *rfoff = nullptr, *rboff = nullptr, *frec = nullptr, *brec = nullptr;
     int rec_prec = -1;  // DDLR_FP64 (double records) or DDLR_FP32 (float records)
+    // interface rows' L and L^T as CSR of packed (value, column) entries
+    // (IfacePk) in the handle's precision, for the interface levels through
+    // the private buffer; null unless the levels cover exactly the interface
+    int32_t *iprp_l = nullptr, *iprp_u = nullptr;
+    void *ipk_l = nullptr, *ipk_u = nullptr;
+    int ipk_prec = -1;
     int ring_kw = 0;    // 2, 3, 4, 8, 16 or 0 (ring kernel unusable)
     bool ring_ok64 = false, ring_ok32 = false;  // dependency window fits the LDS ring
     int ring_need = 0;                          // rows the ring must hold (dependency window)
@@ -345,6 +353,7 @@ struct ddlr_prec {
     // 0 = eager (DDLR_CG_GRAPH=1 / 0 force one)
     int graph_mode = 2;
     int level_kernel = 0;  // interface levels: 0 by level size, 1 one thread per row, 2 per (row, column)
+    bool cg_xp = true;     // CG: x update in the p-update pass (else on a side stream beside the preconditioner)
     struct CgMode {
         double us[2][3];     // fastest chunk [graph][overlap + 1], overlap -1: not applicable
         int timed[2][3] = {};
@@ -788,6 +797,61 @@ void build_ring(ddlr_prec* h, const DevHost& D) {
     }
 }
 
+// The interface rows' L (forward) and L^T (backward) as CSR of packed
+// (value, column) entries for k_iface_rows / k_iface_cols, when the interface
+// levels cover the rows m .. n-1 one after another.
+template <typename T>
+void pack_iface(const DevHost& D, int64_t m, const std::vector<int32_t>& rp, const std::vector<int32_t>& ci,
+                const std::vector<double>& v, std::vector<int32_t>& prp, std::vector<typename IfacePk<T>::type>& pk) {
+    const int64_t n = D.n;
+    prp.assign(n - m + 1, 0);
+    pk.clear();
+    for (int64_t i = m; i < n; ++i) {
+        for (int32_t t = rp[i]; t < rp[i + 1]; ++t) {
+            const T val = (T)v[t];
+            typename IfacePk<T>::type e{};
+            if constexpr (sizeof(T) == 4) {
+                e.x = ci[t];
+                std::memcpy(&e.y, &val, 4);
+            } else {
+                uint64_t bits;
+                std::memcpy(&bits, &val, 8);
+                e.x = (int32_t)(uint32_t)(bits & 0xffffffffu);
+                e.y = (int32_t)(uint32_t)(bits >> 32);
+                e.z = ci[t];
+                e.w = 0;
+            }
+            pk.push_back(e);
+        }
+        prp[i - m + 1] = (int32_t)pk.size();
+    }
+}
+
+void build_iface_packs(ddlr_prec* h, const DevHost& D) {
+    const int64_t n = D.n, m = D.n - D.s;
+    if (D.wide.empty() || D.wide.front().first != m || D.wide.back().second != n) return;
+    for (size_t l = 1; l < D.wide.size(); ++l)
+        if (D.wide[l].first != D.wide[l - 1].second) return;
+    DMem& M = h->mem;
+    std::vector<int32_t> pl, pu;
+    if (h->precision == DDLR_FP64) {
+        std::vector<int4> kl, ku;
+        pack_iface<double>(D, m, D.lrp, D.lci, D.lv, pl, kl);
+        pack_iface<double>(D, m, D.urp, D.uci, D.uv, pu, ku);
+        h->ipk_l = M.upload(kl);
+        h->ipk_u = M.upload(ku);
+    } else {
+        std::vector<int2> kl, ku;
+        pack_iface<float>(D, m, D.lrp, D.lci, D.lv, pl, kl);
+        pack_iface<float>(D, m, D.urp, D.uci, D.uv, pu, ku);
+        h->ipk_l = M.upload(kl);
+        h->ipk_u = M.upload(ku);
+    }
+    h->iprp_l = M.upload(pl);
+    h->iprp_u = M.upload(pu);
+    h->ipk_prec = h->precision == DDLR_FP64 ? DDLR_FP64 : DDLR_FP32;
+}
+
 // Uploads the device-order arrays and builds SELL-64 for A.
 void upload_devhost(ddlr_prec* h, const DevHost& D) {
     DMem& M = h->mem;
@@ -929,6 +993,7 @@ void upload_devhost(ddlr_prec* h, const DevHost& D) {
     h->nnarrow_pad = (h->nnarrow + 7) / 8 * 8;
     h->blk = M.upload(D.narrow);
     build_ring(h, D);
+    build_iface_packs(h, D);
 }
 
 void upload_structures(ddlr_prec* h, int c_mode = -1) { upload_devhost(h, build_devhost(h->plan, c_mode)); }
@@ -980,6 +1045,9 @@ void ensure_ws(ddlr_prec* h, int nrhs) {
     W.a2 = W.mem.alloc<char>(tsz * n * nrhs);
     W.ry = W.mem.alloc<char>(tsz * n * nrhs);
     W.ry_cols = nrhs;
+    W.iy_cols = 1;
+    while (W.iy_cols < std::min(nrhs, kMaxRhs)) W.iy_cols <<= 1;
+    W.iy = W.mem.alloc<char>(tsz * s * W.iy_cols);
     W.ys = W.mem.alloc<char>(tsz * s * nrhs);
     W.ws = W.mem.alloc<char>(tsz * s * nrhs);
     const int kk = std::max(1, h->k);
@@ -1108,20 +1176,26 @@ void launch_ring(ddlr_prec* h, const T* dinv, int nrhs, const TIn* x, int64_t ld
     }
 }
 
-// R columns per workgroup (the ring holds ring_rows_r<T, R>() rows of R values);
-// R > 1 needs the packed records in T and the workspace's buffer for the
-// forward results of nrhs columns
-template <typename T> bool ring_r_ok(const ddlr_prec* h, int R, int nrhs) {
-    if (R == 1) return true;  // the one-column kernel, or the plain fallback
+// The packed-record kernel for R columns per workgroup: its records in T, the
+// workspace's buffer for the forward results of nrhs columns, and a
+// dependency window that fits its ring of ring_rows_r<T, R>() rows.
+template <typename T> bool rec_ok(const ddlr_prec* h, int R, int nrhs) {
     if (!ring_ready<T>(h) || h->ring_kw > 4 || !h->frec) return false;
     if (h->rec_prec != (sizeof(T) == 8 ? DDLR_FP64 : DDLR_FP32)) return false;
     if (!h->ws.ry || h->ws.ry_cols < nrhs) return false;
     switch (R) {
+    case 1: return h->ring_need <= ring_rows_r<T, 1>();
     case 2: return h->ring_need <= ring_rows_r<T, 2>();
     case 4: return h->ring_need <= ring_rows_r<T, 4>();
     case 8: return h->ring_need <= ring_rows_r<T, 8>();
     default: return false;
     }
+}
+
+// R columns per workgroup: R > 1 needs the packed-record kernel; one column
+// runs it too when it can (512 threads), else the one-column kernel
+template <typename T> bool ring_r_ok(const ddlr_prec* h, int R, int nrhs) {
+    return R == 1 || rec_ok<T>(h, R, nrhs);
 }
 
 template <typename T, int KW, int R, typename TIn, typename TOut>
@@ -1190,6 +1264,66 @@ void launch_level_rows(int a, int e, int nrhs, const int32_t* rp, const int32_t*
                            dinv, x, ldx, z, ldz, done);
 }
 
+template <typename T, int kKind, typename TIn, typename TOut>
+void launch_iface(ddlr_prec* h, bool rows, int a, int e, int nrhs, int NR, const T* dinv, const TIn* x, int64_t ldx,
+                  TOut* z, int64_t ldz, hipStream_t st, const int* done) {
+    using PK = typename IfacePk<T>::type;
+    const int m = (int)(h->ndev - h->sdev);
+    const int32_t* prp = kKind == 1 ? h->iprp_u : h->iprp_l;
+    const PK* pk = (const PK*)(kKind == 1 ? h->ipk_u : h->ipk_l);
+    T* Y = (T*)h->ws.iy;
+    const dim3 b(256);
+    if (!rows) {
+        hipLaunchKernelGGL((k_iface_cols<T, kKind, TIn, TOut>), dim3((e - a + 255) / 256, NR), b, 0, st, a, e, m, nrhs,
+                           NR, prp, pk, dinv, x, ldx, Y, z, ldz, done);
+    } else {
+        // NC columns per thread: 16-byte vectors of Y (4 FP32 or 2 FP64 values)
+        constexpr int NC = sizeof(T) == 4 ? 4 : 2;
+        auto grid = [&](int nr) { return dim3((unsigned)(((int64_t)(e - a) * (nr / std::min(nr, NC)) + 255) / 256)); };
+        switch (NR) {
+        case 1:
+            hipLaunchKernelGGL((k_iface_rows<T, kKind, TIn, TOut, 1, 1>), grid(1), b, 0, st, a, e, m, nrhs, prp, pk,
+                               dinv, x, ldx, Y, z, ldz, done);
+            break;
+        case 2:
+            hipLaunchKernelGGL((k_iface_rows<T, kKind, TIn, TOut, 2, 2>), grid(2), b, 0, st, a, e, m, nrhs, prp, pk,
+                               dinv, x, ldx, Y, z, ldz, done);
+            break;
+        case 4:
+            hipLaunchKernelGGL((k_iface_rows<T, kKind, TIn, TOut, 4, std::min(4, NC)>), grid(4), b, 0, st, a, e, m,
+                               nrhs, prp, pk, dinv, x, ldx, Y, z, ldz, done);
+            break;
+        case 8:
+            hipLaunchKernelGGL((k_iface_rows<T, kKind, TIn, TOut, 8, NC>), grid(8), b, 0, st, a, e, m, nrhs, prp, pk,
+                               dinv, x, ldx, Y, z, ldz, done);
+            break;
+        default:
+            hipLaunchKernelGGL((k_iface_rows<T, kKind, TIn, TOut, kMaxRhs, NC>), grid(kMaxRhs), b, 0, st, a, e, m,
+                               nrhs, prp, pk, dinv, x, ldx, Y, z, ldz, done);
+            break;
+        }
+    }
+    LAUNCHCHK();
+}
+
+// The interface levels through the private buffer (k_iface_rows / _cols)
+template <typename T, typename TIn, typename TOut, typename ByRows>
+void iface_levels(ddlr_prec* h, const DevFactors<T>& F, int nrhs, int NR, const TIn* x, int64_t ldx, TOut* z,
+                  int64_t ldz, hipStream_t st, const int* done, ByRows&& by_rows) {
+    const int nl = (int)h->wide.size();
+    for (int l = 0; l < nl; ++l) {
+        const int a = h->wide[l].first, e = h->wide[l].second;
+        if (l + 1 < nl)
+            launch_iface<T, 0, TIn, TOut>(h, by_rows(a, e), a, e, nrhs, NR, F.dinv, x, ldx, z, ldz, st, done);
+        else
+            launch_iface<T, 2, TIn, TOut>(h, by_rows(a, e), a, e, nrhs, NR, F.dinv, x, ldx, z, ldz, st, done);
+    }
+    for (int l = nl - 2; l >= 0; --l) {
+        const int a = h->wide[l].first, e = h->wide[l].second;
+        launch_iface<T, 1, TIn, TOut>(h, by_rows(a, e), a, e, nrhs, NR, F.dinv, x, ldx, z, ldz, st, done);
+    }
+}
+
 // Interface-block levels (multicolour order): forward levels, the last one
 // fused with the diagonal scaling, then backward levels.
 template <typename T, typename TIn, typename TOut>
@@ -1203,6 +1337,13 @@ void wide_levels(ddlr_prec* h, const DevFactors<T>& F, int nrhs, const TIn* x, i
         if (nrhs > kMaxRhs || h->level_kernel == 2) return false;
         return h->level_kernel == 1 || e - a >= 256 * 256;
     };
+    int NR = 1;
+    while (NR < nrhs) NR <<= 1;
+    if (nrhs <= kMaxRhs && h->level_kernel != 2 && h->ipk_l && h->ipk_prec == (sizeof(T) == 8 ? DDLR_FP64 : DDLR_FP32) &&
+        h->ws.iy && h->ws.iy_cols >= NR) {
+        iface_levels<T, TIn, TOut>(h, F, nrhs, NR, x, ldx, z, ldz, st, done, by_rows);
+        return;
+    }
     for (int l = 0; l < nl; ++l) {
         const int a = h->wide[l].first, e = h->wide[l].second;
         const bool last = l + 1 == nl;
@@ -1329,7 +1470,11 @@ void a0_solve_dev(ddlr_prec* h, const DevFactors<T>& F, int nrhs, const TIn* x, 
             case 2: launch_ring_r<T, 2, TIn, TOut>(h, F.dinv, nrhs, x, ldx, z, ldz, st, done); break;
             case 4: launch_ring_r<T, 4, TIn, TOut>(h, F.dinv, nrhs, x, ldx, z, ldz, st, done); break;
             case 8: launch_ring_r<T, 8, TIn, TOut>(h, F.dinv, nrhs, x, ldx, z, ldz, st, done); break;
-            default: launch_ring<T, TIn, TOut>(h, F.dinv, nrhs, x, ldx, z, ldz, st, done);
+            default:
+                if (ring_nt_for<T>(h, nrhs) == 512 && rec_ok<T>(h, 1, nrhs))
+                    launch_ring_r<T, 1, TIn, TOut>(h, F.dinv, nrhs, x, ldx, z, ldz, st, done);
+                else
+                    launch_ring<T, TIn, TOut>(h, F.dinv, nrhs, x, ldx, z, ldz, st, done);
             }
         } else {
             hipLaunchKernelGGL((k_trsv_narrow<T, TIn, TOut>), dim3(h->nnarrow_pad * nrhs), dim3(256), 0, st, h->blk,
@@ -1580,6 +1725,21 @@ template <int S> void cg_split_launch(ddlr_prec* h, int nr, hipStream_t st) {
     hipLaunchKernelGGL(k_cg_x<S>, dim3(grid_for(n)), dim3(256), 0, h->x_st, n, nr, W.xa, W.p, W.x, n);
     LAUNCHCHK();
     HIPCHK(hipEventRecord(h->ev_xj, h->x_st));
+}
+
+// r -= alpha q (with r.r partials and the step record xa) on st
+void cg_r_dev(ddlr_prec* h, int nr, hipStream_t st) {
+    Workspace& W = h->ws;
+    const int64_t n = h->ndev;
+    const dim3 g(kRedBlocks), b(256);
+    switch (lane_stride(nr)) {
+    case 1: hipLaunchKernelGGL(k_cg_r<1>, g, b, 0, st, n, nr, W.lanes, W.q, W.r, n, W.xa, W.part, W.done); break;
+    case 2: hipLaunchKernelGGL(k_cg_r<2>, g, b, 0, st, n, nr, W.lanes, W.q, W.r, n, W.xa, W.part, W.done); break;
+    case 4: hipLaunchKernelGGL(k_cg_r<4>, g, b, 0, st, n, nr, W.lanes, W.q, W.r, n, W.xa, W.part, W.done); break;
+    case 8: hipLaunchKernelGGL(k_cg_r<8>, g, b, 0, st, n, nr, W.lanes, W.q, W.r, n, W.xa, W.part, W.done); break;
+    default: hipLaunchKernelGGL(k_cg_r<16>, g, b, 0, st, n, nr, W.lanes, W.q, W.r, n, W.xa, W.part, W.done); break;
+    }
+    LAUNCHCHK();
 }
 
 // r -= alpha q (with r.r partials) on st; x += alpha p forked to the x stream
@@ -2241,6 +2401,7 @@ void device_init(ddlr_prec* h, int cheb_iters, int no_autotune) {
     h->tune_mode = no_autotune ? 0 : 1;
     if (const char* env = std::getenv("DDLR_CG_GRAPH")) h->graph_mode = env[0] == '0' ? 0 : env[0] == '1' ? 1 : 2;
     if (const char* env = std::getenv("DDLR_CG_PERSIST")) h->pers_mode = env[0] == '0' ? 0 : env[0] == '1' ? 1 : 2;
+    if (const char* env = std::getenv("DDLR_CG_XP")) h->cg_xp = env[0] != '0';
     if (const char* env = std::getenv("DDLR_LEVEL_KERNEL"))  // "rows" / "cols" force one form
         h->level_kernel = env[0] == 'r' ? 1 : env[0] == 'c' ? 2 : 0;
     if (has_cpart(h)) {
@@ -2614,14 +2775,15 @@ struct ScratchView {
     ddlr_prec* h;
     void *a1, *a2, *ys, *ws, *ct, *cr, *cd, *cx;
     double *part, *lrsum, *coef;
-    int ry_cols;
+    int ry_cols, iy_cols;
     bool prof;
     double *in = nullptr, *out = nullptr;
     ScratchView(ddlr_prec* h_, char* base, int nr) : h(h_) {
         Workspace& W = h->ws;
         a1 = W.a1, a2 = W.a2, ys = W.ys, ws = W.ws, part = W.part, lrsum = W.lrsum, coef = W.coef;
-        ry_cols = W.ry_cols;
+        ry_cols = W.ry_cols, iy_cols = W.iy_cols;
         W.ry_cols = 0;  // no buffer for the R-column ring kernel: one column per workgroup
+        W.iy_cols = 0;  // nor for the interface levels: the column-major kernels
         ct = h->ch_t, cr = h->ch_r, cd = h->ch_d, cx = h->ch_x;
         prof = h->prof;
         auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
@@ -2653,7 +2815,7 @@ struct ScratchView {
     ~ScratchView() {
         Workspace& W = h->ws;
         W.a1 = a1, W.a2 = a2, W.ys = ys, W.ws = ws, W.part = part, W.lrsum = lrsum, W.coef = coef;
-        W.ry_cols = ry_cols;
+        W.ry_cols = ry_cols, W.iy_cols = iy_cols;
         h->ch_t = ct, h->ch_r = cr, h->ch_d = cd, h->ch_x = cx;
         h->prof = prof;
     }
@@ -2817,8 +2979,12 @@ static void lane_iteration(ddlr_prec* h, int nr, hipStream_t st) {
     hipLaunchKernelGGL(k_reduce_lane, dim3(nr), dim3(256), 0, st, 2, npart_spmv, nr, W.part, W.sums, W.lanes, W.done,
                        W.ctr);
     LAUNCHCHK();
-    const bool split = h->x_st != nullptr;
-    if (split) cg_split_dev(h, nr, st);  // x += alpha p overlaps the preconditioner
+    // x += alpha p: with the p update (k_cg_xp), on the x stream beside the
+    // preconditioner, or with the r update
+    const bool xp = h->cg_xp;
+    const bool split = !xp && h->x_st != nullptr;
+    if (xp) cg_r_dev(h, nr, st);
+    else if (split) cg_split_dev(h, nr, st);
     else cg_xr_dev(h, nr, st);
     hipLaunchKernelGGL(k_reduce_lane, dim3(nr), dim3(256), 0, st, 3, kRedBlocks, nr, W.part, W.sums, W.lanes, W.done,
                        W.ctr);
@@ -2833,6 +2999,18 @@ static void lane_iteration(ddlr_prec* h, int nr, hipStream_t st) {
     if (split) HIPCHK(hipStreamWaitEvent(st, h->ev_xj, 0));  // x used the old p
     const int S = lane_stride(nr);
     const dim3 gp(grid_for(n)), bp(256);
+    if (xp) {
+        switch (S) {
+        case 1: hipLaunchKernelGGL(k_cg_xp<1>, gp, bp, 0, st, n, nr, W.lanes, W.xa, W.z, W.p, W.x, n); break;
+        case 2: hipLaunchKernelGGL(k_cg_xp<2>, gp, bp, 0, st, n, nr, W.lanes, W.xa, W.z, W.p, W.x, n); break;
+        case 4: hipLaunchKernelGGL(k_cg_xp<4>, gp, bp, 0, st, n, nr, W.lanes, W.xa, W.z, W.p, W.x, n); break;
+        case 8: hipLaunchKernelGGL(k_cg_xp<8>, gp, bp, 0, st, n, nr, W.lanes, W.xa, W.z, W.p, W.x, n); break;
+        case 16: hipLaunchKernelGGL(k_cg_xp<16>, gp, bp, 0, st, n, nr, W.lanes, W.xa, W.z, W.p, W.x, n); break;
+        default: throw SetupError{DDLR_E_INVALID, "CG runs at most 16 lanes per launch"};
+        }
+        LAUNCHCHK();
+        return;
+    }
     switch (S) {
     case 1: hipLaunchKernelGGL(k_cg_p<1>, gp, bp, 0, st, n, nr, W.lanes, W.z, W.p, n, W.done); break;
     case 2: hipLaunchKernelGGL(k_cg_p<2>, gp, bp, 0, st, n, nr, W.lanes, W.z, W.p, n, W.done); break;

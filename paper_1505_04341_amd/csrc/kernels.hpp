@@ -656,6 +656,120 @@ __global__ __launch_bounds__(256) void k_trsv_level_rows(int a, int e, int nrhs,
     }
 }
 
+// ------------------------------------------------ A0 solve: interface levels through a private buffer
+//
+// The interface block's levels as in k_trsv_level_rows, with the values of
+// interface row i also kept in a private buffer Y (row i - m holds NR values
+// side by side, NR a power of two >= nrhs): a dependency of all columns is one
+// vector load instead of one load per column, and each entry is one load of a
+// packed (value, column) pair.  The operations and their order per column
+// are those of k_trsv_level_rows.
+//   kind 0 (forward):             Y_i = x_i - sum_j L_ij Y_j
+//   kind 2 (last forward level):  Y_i = z_i = D_i^{-1} (x_i - sum_j L_ij Y_j)
+//   kind 1 (backward):            Y_i = z_i = D_i^{-1} Y_i - sum_j L_ji Y_j
+// Entry q of the interface rows' CSR: FP32 {column, value bits}, FP64
+// {value low word, value high word, column, 0}.
+template <typename T> struct IfacePk { using type = int2; };
+template <> struct IfacePk<double> { using type = int4; };
+
+__device__ __forceinline__ void pk_unpack(int2 t, int& c, float& v) {
+    c = t.x;
+    v = __int_as_float(t.y);
+}
+__device__ __forceinline__ void pk_unpack(int4 t, int& c, double& v) {
+    c = t.z;
+    v = __hiloint2double(t.y, t.x);
+}
+
+// NC columns of one row per thread (NR / NC consecutive threads share a
+// row, so a row's vector of Y is read and written by neighbouring lanes).
+// The entries go in groups of four with unconditional loads: an index past the
+// row's end repeats its last entry with weight 0 (s - 0 g leaves s unchanged up
+// to the sign of a zero), so a group's entry and gather loads go out together;
+// the terms keep their order.
+template <typename T, int kKind, typename TIn, typename TOut, int NR, int NC>
+__global__ __launch_bounds__(256) void k_iface_rows(int a, int e, int m, int nrhs, const int32_t* __restrict__ prp,
+                                                    const typename IfacePk<T>::type* __restrict__ pk,
+                                                    const T* __restrict__ dinv, const TIn* x, int64_t ldx,
+                                                    T* __restrict__ Y, TOut* z, int64_t ldz,
+                                                    const int* __restrict__ done) {
+    using V = T __attribute__((ext_vector_type(NC)));
+    constexpr int G = NR / NC;
+    if (done && *done) return;
+    const int gid = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    const int i = a + gid / G, c0 = (gid % G) * NC;
+    if (i >= e) return;
+    const int j = i - m;
+    V s;
+    T di = T(1);
+    if constexpr (kKind != 0) di = dinv[i];
+    if constexpr (kKind == 1) {
+        const V y = *reinterpret_cast<const V*>(Y + (size_t)j * NR + c0);
+#pragma unroll
+        for (int r = 0; r < NC; ++r) s[r] = y[r] * di;
+    } else {
+#pragma unroll
+        for (int r = 0; r < NC; ++r) s[r] = (T)x[i + (int64_t)min(c0 + r, nrhs - 1) * ldx];
+    }
+    const int t0 = prp[j], t1 = prp[j + 1];
+    for (int t = t0; t < t1; t += 4) {
+        int c[4];
+        T w[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            T v;
+            pk_unpack(pk[min(t + u, t1 - 1)], c[u], v);
+            w[u] = t + u < t1 ? v : T(0);
+        }
+        V g[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) g[u] = *reinterpret_cast<const V*>(Y + (size_t)(c[u] - m) * NR + c0);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int r = 0; r < NC; ++r) s[r] = fnms(s[r], w[u], g[u][r]);
+    }
+    if constexpr (kKind == 2) {
+#pragma unroll
+        for (int r = 0; r < NC; ++r) s[r] *= di;
+    }
+    *reinterpret_cast<V*>(Y + (size_t)j * NR + c0) = s;
+    if constexpr (kKind != 0) {
+#pragma unroll
+        for (int r = 0; r < NC; ++r)
+            if (c0 + r < nrhs) z[i + (int64_t)(c0 + r) * ldz] = (TOut)s[r];
+    }
+}
+
+// one thread per (row, column), grid (row chunks, NR): for levels too small
+// to fill the chip one row per thread; padding columns repeat column nrhs - 1
+template <typename T, int kKind, typename TIn, typename TOut>
+__global__ __launch_bounds__(256) void k_iface_cols(int a, int e, int m, int nrhs, int NR,
+                                                    const int32_t* __restrict__ prp,
+                                                    const typename IfacePk<T>::type* __restrict__ pk,
+                                                    const T* __restrict__ dinv, const TIn* x, int64_t ldx,
+                                                    T* __restrict__ Y, TOut* z, int64_t ldz,
+                                                    const int* __restrict__ done) {
+    if (done && *done) return;
+    const int r = blockIdx.y;
+    const int i = a + (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i >= e) return;
+    const int j = i - m;
+    T s;
+    if constexpr (kKind == 1) s = Y[(size_t)j * NR + r] * dinv[i];
+    else s = (T)x[i + (int64_t)min(r, nrhs - 1) * ldx];
+    const int t1 = prp[j + 1];
+    for (int t = prp[j]; t < t1; ++t) {
+        int c;
+        T v;
+        pk_unpack(pk[t], c, v);
+        s = fnms(s, v, Y[(size_t)(c - m) * NR + r]);
+    }
+    if constexpr (kKind == 2) s *= dinv[i];
+    Y[(size_t)j * NR + r] = s;
+    if (kKind != 0 && r < nrhs) z[i + (int64_t)r * ldz] = (TOut)s;
+}
+
 // ------------------------------------------------------------ SpMV (SELL-64)
 //
 // y = A x for up to kMaxRhs columns; A is FP64 in SELL-64 (slices of 64 rows,
@@ -1752,6 +1866,57 @@ __global__ __launch_bounds__(256) void k_cg_x(int64_t n, int nrhs, const double*
 #pragma unroll
         for (int c = 0; c < S; ++c)
             if (c < nrhs && a[c] != 0.0) x[i + c * ld] += a[c] * pv[c];
+    }
+}
+
+// k_cg_x and k_cg_p in one pass: x += xa p with the old p (xa: the step
+// k_cg_r recorded, zero for lanes that were not running), then p = z + beta p
+// for the active lanes; same per-element arithmetic as the two kernels.  It
+// does not read the done flag: the last iteration's x step must still be
+// applied after the residual check has set it; with no step and no active
+// lane it returns at once.
+template <int S>
+__global__ __launch_bounds__(256) void k_cg_xp(int64_t n, int nrhs, const CgLane* __restrict__ L,
+                                               const double* __restrict__ xa, const double* __restrict__ z,
+                                               double* __restrict__ p, double* __restrict__ x, int64_t ld) {
+    bool act[S];
+    double bt[S], a[S];
+    bool any = false;
+#pragma unroll
+    for (int c = 0; c < S; ++c) {
+        act[c] = c < nrhs && L[c].active;
+        bt[c] = act[c] ? L[c].beta : 0.0;
+        a[c] = c < nrhs ? xa[c] : 0.0;
+        any = any || act[c] || a[c] != 0.0;
+    }
+    if (!any) return;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double pv[S], zv[S];
+        if constexpr (S == 1) {
+            pv[0] = p[i];
+        } else {
+#pragma unroll
+            for (int c = 0; c < S; c += 2) {
+                const double2 t = *reinterpret_cast<const double2*>(p + i * S + c);
+                pv[c] = t.x;
+                pv[c + 1] = t.y;
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < S; ++c) zv[c] = z[i + (int64_t)min(c, nrhs - 1) * ld];
+#pragma unroll
+        for (int c = 0; c < S; ++c)
+            if (c < nrhs && a[c] != 0.0) x[i + c * ld] += a[c] * pv[c];
+#pragma unroll
+        for (int c = 0; c < S; ++c)
+            if (act[c]) pv[c] = zv[c] + bt[c] * pv[c];
+        if constexpr (S == 1) {
+            p[i] = pv[0];
+        } else {
+#pragma unroll
+            for (int c = 0; c < S; c += 2)
+                *reinterpret_cast<double2*>(p + i * S + c) = double2{pv[c], pv[c + 1]};
+        }
     }
 }
 

@@ -76,15 +76,17 @@ CASES = {"c1": lambda: w.config("c1"), "small2d": lambda: w.config("small2d"),
 
 
 @pytest.mark.parametrize("name", ["c1", "small3d", "irregular", "big3d"])
-@pytest.mark.parametrize("wide", [False, "rows", "cols"])
+@pytest.mark.parametrize("wide", [False, "auto", "rows", "cols"])
 @pytest.mark.parametrize("kernel", ["ring", "plain"])
 def test_a0_solve_and_spmv(name, wide, kernel):
     """wide: the interface block as one narrow block, or its colour levels
-    launched one by one with one thread per row / per (row, column)."""
+    launched one by one: through the private buffer with the form chosen by
+    level size (auto) or one thread per row (rows), or the column-major
+    kernel with one thread per (row, column) (cols)."""
     cfg = CASES[name]()
     say("a0_solve", name, "wide", wide, kernel)
     env = {"DDLR_TRSV_PLAIN": "1" if kernel == "plain" else "0"}
-    if wide:
+    if wide in ("rows", "cols"):
         env["DDLR_LEVEL_KERNEL"] = wide
     h, o = setup_pair(cfg, variant=D.VARIANT_A0, wide=bool(wide), env=env)
     n = cfg["A"].n
@@ -174,6 +176,30 @@ def test_own_lanczos_matches_oracle(name, variant):
     q = D.ddlr_query(h)
     if variant == 1:
         assert abs(q["theta"] - orz[k]) <= 1e-8
+
+
+def test_interface_and_cg_forms_bitwise():
+    """Launch forms that leave the arithmetic unchanged give bitwise the same
+    results: the interface levels through the private buffer (one thread per
+    row, or per (row, column)) or column-major (per (row, column)), and the CG
+    x update with the p update or on a side stream beside the preconditioner.
+    Checked on the apply and on 30 CG iterations of 8 columns."""
+    cfg = big3d()
+    n = cfg["A"].n
+    say("interface / CG forms")
+    forms = [{}, {"DDLR_LEVEL_KERNEL": "rows"}, {"DDLR_LEVEL_KERNEL": "cols"}, {"DDLR_CG_XP": "0"}]
+    x = to_dev(np.random.default_rng(21).standard_normal((n, 8)))
+    b = to_dev(w.rhs_from_solution(cfg["A"], 0, 8)[0])
+    outs = []
+    for env in forms:
+        h, _ = setup_pair(cfg, variant=1, wide=True, env=dict(env, DDLR_CG_PERSIST="0"), precision=D.FP32)
+        y = torch.empty_like(x)
+        D.ddlr_apply(h, x, y)
+        xt = torch.zeros_like(b)
+        D.ddlr_solve(h, b, xt, maxit=30)
+        outs.append((y.cpu().numpy(), xt.cpu().numpy()))
+    for y, xs in outs[1:]:
+        assert np.array_equal(y, outs[0][0]) and np.array_equal(xs, outs[0][1])
 
 
 @pytest.mark.parametrize("name", ["c1", "small3d", "irregular"])
