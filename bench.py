@@ -506,16 +506,110 @@ def cpu_baseline_batch(systems, bs, count):
 
 
 # ---------------------------------------------------------------- c5: serving
-def run_serving(args, D, w, torch):
-    mats, hs = [], []
+def serving_leg(args, D, w, mats, precision, label):
+    """One serving measurement: the resident matrices with the given
+    preconditioner precision, a saturation burst, then Poisson arrivals at
+    0.5x and 0.9x of the saturation request rate.  Returns the leg's figures."""
+    hs = []
     t0 = time.perf_counter()
+    for mt in mats:
+        cfg = mt["cfg"]
+        hs.append(D.ddlr_setup(cfg["A"], cfg["part"], cfg["p"], cfg["k"], 1, alpha=mt["alpha"], lanczos_steps=cfg["m"],
+                               lanczos_start=w.lanczos_start(cfg["A"].n, cfg["seed"]), precision=precision))
+    setup_s = time.perf_counter() - t0
+    srv = D.ddlr_server_create(0, 0, 16)
+    mids = [D.ddlr_server_add(srv, h) for h in hs]
+    rhs = [w.rhs_from_solution(mt["cfg"]["A"], 100 + j, 16)[0] for j, mt in enumerate(mats)]
+    rng = np.random.default_rng(1)  # the same request stream in every leg
+
+    def request():
+        j = int(rng.integers(0, len(mats)))
+        c = int(rng.integers(1, 17))
+        return j, rhs[j][:, :c]
+
+    worst = 0.0
+
+    def check(info):
+        nonlocal worst
+        worst = max([worst] + [i["relres_true"] for i in info])
+
+    # warm-up and saturation: a burst of requests submitted at once
+    for _ in range(args.warmup):
+        ts = [D.ddlr_server_submit(srv, mids[j], b)[0] for j, b in (request() for _ in range(8))]
+        for t in ts:
+            check(D.ddlr_server_wait(srv, t)[1])
+    burst = [request() for _ in range(args.burst)]
+    t0 = time.perf_counter()
+    ts = [D.ddlr_server_submit(srv, mids[j], b)[0] for j, b in burst]
+    for t in ts:
+        check(D.ddlr_server_wait(srv, t)[1])
+    sat_s = time.perf_counter() - t0
+    sat_cols = sum(b.shape[1] for _, b in burst)
+    sat_rps = len(burst) / sat_s
+    log(f"serving {label}: saturation", round(sat_cols / sat_s, 2), "solves/s", round(sat_rps, 2), "requests/s")
+    loads = {}
+    for frac in (0.5, 0.9):
+        qps = frac * sat_rps
+        reqs = [request() for _ in range(args.requests)]
+        D.ddlr_server_reset_stats(srv)
+        gaps = rng.exponential(1.0 / qps, size=len(reqs))
+        sub = []
+        t_start = time.perf_counter()
+        t_next = t_start
+        for (j, b), g in zip(reqs, gaps):
+            t_next += g
+            while time.perf_counter() < t_next:
+                time.sleep(min(1e-4, max(0.0, t_next - time.perf_counter())))
+            t, _ = D.ddlr_server_submit(srv, mids[j], b)
+            sub.append((t, b.shape[1]))
+        cols = 0
+        for t, c in sub:
+            check(D.ddlr_server_wait(srv, t)[1])
+            cols += c
+        elapsed = time.perf_counter() - t_start
+        st = D.ddlr_server_stats(srv)
+        loads[f"{frac:.1f}x"] = {"qps": round(qps, 2), "requests": len(reqs), "solves": cols,
+                                 "solves_per_s": round(cols / elapsed, 2),
+                                 "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3)}
+        log(f"serving {label}: load", frac, loads[f"{frac:.1f}x"])
+    hbm = D.ddlr_server_stats(srv)["hbm_used"]
+    del srv
+    return {"solves_per_s": round(sat_cols / sat_s, 3), "ms_per_request": round(1e3 * sat_s / args.burst, 3),
+            "requests_per_s": round(sat_rps, 3), "loads": loads, "max_relres_true": worst,
+            "setup_s": round(setup_s, 2), "hbm_used_bytes": hbm}
+
+
+def cpu_baseline_serving(mats, count, cols=4):
+    """The oracle on `cols` right-hand sides of each of the `count` smallest
+    serving matrices, one matrix after another with every OpenMP thread (setup
+    excluded), CG to 1e-6."""
+    oracle = oracle_native()
+    dt, its, ns = 0.0, [], []
+    for j, mt in enumerate(mats[:count]):
+        cfg = mt["cfg"]
+        o = oracle.Oracle(cfg["A"], cfg["part"], cfg["p"], alpha=mt["alpha"]).lowrank(
+            1, cfg["k"], cfg["m"], __import__("workloads").lanczos_start(cfg["A"].n, cfg["seed"]))
+        b = __import__("workloads").rhs_from_solution(cfg["A"], 100 + j, cols)[0]
+        (_, info), t = timed_oracle(oracle, oracle.threads(), lambda: o.pcg(b))
+        dt += t
+        its.extend(int(v) for v in info["its"])
+        ns.append(cfg["A"].n)
+    log("cpu baseline (serving):", count * cols, "solves", f"{dt:.1f}s")
+    return {"value": round(count * cols / dt, 3), "unit": "solves/s", "cores": oracle.threads(), "kind": "oracle",
+            "sample": f"{cols} right-hand sides on each of the {count} smallest of the {len(mats)} matrices "
+                      f"(n {min(ns)}..{max(ns)}; the stream mixes n up to {mats[-1]['cfg']['A'].n}), solved to 1e-6 "
+                      f"by the oracle in turn ({min(its)}..{max(its)} iterations, {dt:.1f} s, setup excluded)",
+            "host": host_info(oracle)}
+
+
+def run_serving(args, D, w, torch):
+    mats = []
     for j in range(len(w.SERVING_MATRICES)):
         cfg = w.serving_matrix(j)
         alpha = 1.0
-        while True:
+        while True:  # the paper's fallback: alpha = 2 when a local factor breaks down
             try:
-                h = D.ddlr_setup(cfg["A"], cfg["part"], cfg["p"], cfg["k"], 1, alpha=alpha, lanczos_steps=cfg["m"],
-                                 lanczos_start=w.lanczos_start(cfg["A"].n, cfg["seed"]), precision=D.FP32)
+                D.ddlr_setup(cfg["A"], cfg["part"], cfg["p"], cfg["k"], 0, alpha=alpha, device=-1)
                 break
             except D.DDLRError as e:
                 if e.status != D.E_BREAKDOWN or alpha > 1.0:
@@ -523,76 +617,26 @@ def run_serving(args, D, w, torch):
                 alpha = 2.0
         log("serving: matrix", j, "n", cfg["A"].n, "p", cfg["p"], "k", cfg["k"], "alpha", alpha)
         mats.append(dict(cfg=cfg, alpha=alpha))
-        hs.append(h)
-    setup_s = time.perf_counter() - t0
-    srv = D.ddlr_server_create(0, 0, 16)
-    mids = [D.ddlr_server_add(srv, h) for h in hs]
-    rhs = []
-    for j, mt in enumerate(mats):
-        b, _ = w.rhs_from_solution(mt["cfg"]["A"], 100 + j, 16)
-        rhs.append(b)
-    rng = np.random.default_rng(1)
-
-    def request():
-        j = int(rng.integers(0, len(mats)))
-        c = int(rng.integers(1, 17))
-        return j, rhs[j][:, :c]
-
-    # warm-up and saturation: a burst of requests submitted at once
-    for _ in range(args.warmup):
-        ts = [D.ddlr_server_submit(srv, mids[j], b)[0] for j, b in (request() for _ in range(8))]
-        for t in ts:
-            D.ddlr_server_wait(srv, t)
-    burst = [request() for _ in range(args.burst)]
-    t0 = time.perf_counter()
-    ts = [D.ddlr_server_submit(srv, mids[j], b)[0] for j, b in burst]
-    for t in ts:
-        D.ddlr_server_wait(srv, t)
-    sat_s = time.perf_counter() - t0
-    sat_cols = sum(b.shape[1] for _, b in burst)
-    sat_rps = len(burst) / sat_s
-    log("serving: saturation", round(sat_cols / sat_s, 2), "solves/s", round(sat_rps, 2), "requests/s")
-
-    loads = {}
-    for frac in (0.5, 0.9):
-        qps = frac * sat_rps
-        reqs = [request() for _ in range(args.requests)]
-        D.ddlr_server_reset_stats(srv)
-        gaps = rng.exponential(1.0 / qps, size=len(reqs))
-        sub, lat = [], []
-        t_start = time.perf_counter()
-        t_next = t_start
-        for (j, b), g in zip(reqs, gaps):
-            t_next += g
-            while time.perf_counter() < t_next:
-                time.sleep(min(1e-4, max(0.0, t_next - time.perf_counter())))
-            t_sub = time.perf_counter()
-            t, _ = D.ddlr_server_submit(srv, mids[j], b)
-            sub.append((t, t_sub, b.shape[1]))
-        cols = 0
-        for t, t_sub, c in sub:
-            st, info = D.ddlr_server_wait(srv, t)
-            cols += c
-        elapsed = time.perf_counter() - t_start
-        s = D.ddlr_server_stats(srv)
-        loads[f"{frac:.1f}x"] = {"qps": round(qps, 2), "requests": len(reqs), "solves": cols,
-                                 "solves_per_s": round(cols / elapsed, 2),
-                                 "p50_ms": round(s["p50_ms"], 3), "p99_ms": round(s["p99_ms"], 3)}
-        log("serving: load", frac, loads[f"{frac:.1f}x"])
-    stats = D.ddlr_server_stats(srv)
+    mixed = serving_leg(args, D, w, mats, D.FP32, "mixed")
+    f64 = serving_leg(args, D, w, mats, D.FP64, "fp64")
+    cpu = None if args.no_cpu else cpu_baseline_serving(mats, args.cpu_systems_serving)
     return {
-        "metric": METRIC, "value": round(sat_cols / sat_s, 3), "unit": "solves/s", "n_gpus": 1,
-        "steps": args.burst, "warmup": args.warmup, "ms_per_step": round(1e3 * sat_s / args.burst, 3),
+        "metric": METRIC, "value": mixed["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
+        "steps": args.burst, "warmup": args.warmup, "ms_per_step": mixed["ms_per_request"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32 preconditioner / f64 CG",
         "data": "synthetic",
         "config": {"workload": "c5: serving 8 resident 27-point random-coefficient matrices (n 50,653..10^6, "
                                "16..128 boxes, k 32..64), requests of 1..16 rhs, CG to 1e-6",
                    "matrices": [dict(n=mt["cfg"]["A"].n, p=mt["cfg"]["p"], k=mt["cfg"]["k"], alpha=mt["alpha"])
                                 for mt in mats]},
-        "latency_ms": {"p50": loads["0.9x"]["p50_ms"], "p99": loads["0.9x"]["p99_ms"],
+        "latency_ms": {"p50": mixed["loads"]["0.9x"]["p50_ms"], "p99": mixed["loads"]["0.9x"]["p99_ms"],
                        "note": "per request, arrival to completion, Poisson arrivals at 0.9x saturation"},
-        "loads": loads, "saturation_requests_per_s": round(sat_rps, 3), "setup_s": round(setup_s, 2),
-        "hbm_used_bytes": stats["hbm_used"], "roofline": None, "cpu_baseline": None,
+        "loads": mixed["loads"], "saturation_requests_per_s": mixed["requests_per_s"],
+        "max_relres_true": mixed["max_relres_true"], "setup_s": mixed["setup_s"],
+        "hbm_used_bytes": mixed["hbm_used_bytes"],
+        "fp64": {k: f64[k] for k in ("solves_per_s", "requests_per_s", "loads", "max_relres_true", "hbm_used_bytes")},
+        "mixed_over_fp64": round(mixed["solves_per_s"] / f64["solves_per_s"], 3),
+        "roofline": None, "cpu_baseline": cpu,
     }
 
 
@@ -668,6 +712,8 @@ def main():
                     help="launch a plain copy kernel of known size (for hardware-counter scaling)")
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--cpu-systems", type=int, default=24, help="c4: systems the oracle solves for the baseline")
+    ap.add_argument("--cpu-systems-serving", type=int, default=8,
+                    help="c5: smallest matrices the oracle solves four right-hand sides of for the baseline")
     ap.add_argument("--trace-summary", default=None,
                     help="summarise a rocprofv3 kernel_trace.csv (per kernel: dispatches, average duration over all "
                          "and over those of at least --min-us) and exit; needs no GPU")

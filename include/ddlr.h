@@ -524,9 +524,12 @@ void ddlr_batch_destroy(ddlr_batch *b);
  * factors and U_k on the device and owns `slots_per_matrix` CG lanes (columns).
  * A worker thread admits queued right-hand sides into free lanes of their
  * matrix, runs a few CG iterations on every matrix with lanes (one stream per
- * matrix, so matrices overlap on the device), and retires finished lanes,
- * copying x back.  Each lane's arithmetic is independent of the other lanes and
- * of its admission time, so a result is the same alone and in a mix.
+ * matrix, so matrices overlap on the device; only the lanes up to the highest
+ * occupied one are iterated), and retires finished lanes, computing the true
+ * residual ||b - A x|| and copying x back.  Each lane's arithmetic is
+ * independent of the other lanes and of its admission time, so a result is the
+ * same alone and in a mix.  The device lock is taken per matrix while its work
+ * is queued, so other calls on the device interleave with the worker.
  *
  * ddlr_server_create: device, HBM budget in bytes (0 = unlimited), lanes per
  *   matrix (1..16).
@@ -536,8 +539,8 @@ void ddlr_batch_destroy(ddlr_batch *b);
  * ddlr_server_submit: b_host / x_host are host arrays of nrhs columns (user
  *   order, ld = n) that must stay valid until the request is done; x_host is
  *   written when the request completes.  CG only (method 0).
- * ddlr_server_poll / ddlr_server_wait: info is a host array of nrhs entries;
- *   relres_true is not computed by the server (-1).
+ * ddlr_server_poll / ddlr_server_wait: info is a host array of nrhs entries
+ *   (relres_true = ||b - A x|| / ||b|| of the returned x).
  * ddlr_server_stats: counters, solves/s over the span from the first submit
  *   to the last completion, p50 / p99 request latency (submit to completion).
  * ddlr_server_reset_stats: starts a new measurement window: clears the

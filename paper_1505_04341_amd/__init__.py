@@ -579,7 +579,7 @@ def ddlr_server_wait(server: Server, ticket: int):
     st = load_library().ddlr_server_wait(server.handle, C.c_uint64(ticket), infos)
     if st not in (OK, E_NO_CONVERGENCE):
         _check(st, "ddlr_server_wait")
-    return st, [dict(iters=i.iters, status=i.status, relres=i.relres) for i in infos]
+    return st, [dict(iters=i.iters, status=i.status, relres=i.relres, relres_true=i.relres_true) for i in infos]
 
 
 def ddlr_server_stats(server: Server) -> dict:

@@ -1640,8 +1640,9 @@ void spmv_dev(ddlr_prec* h, int nrhs, const double* x, int64_t ldx, double* y, i
 }
 
 // y = A x with x interleaved (x[i * S + r], S = lane_stride(nrhs))
+// S: the interleave stride of x (0: lane_stride(nrhs))
 void spmv_il_dev(ddlr_prec* h, int nrhs, const double* x, double* y, int64_t ldy, double* part, hipStream_t st,
-                 const int* done) {
+                 const int* done, int S = 0) {
     const int64_t n = h->ndev;
     ProfScope ps(h, 2, st);
     const int64_t chunks = (n + 255) / 256;
@@ -1649,7 +1650,7 @@ void spmv_il_dev(ddlr_prec* h, int nrhs, const double* x, double* y, int64_t ldy
     with_sell(h, [&](auto col, auto val) {
         using IT = std::remove_const_t<std::remove_pointer_t<decltype(col)>>;
         using VT = std::remove_const_t<std::remove_pointer_t<decltype(val)>>;
-        switch (lane_stride(nrhs)) {
+        switch (S ? S : lane_stride(nrhs)) {
         case 1:
             hipLaunchKernelGGL((k_spmv_sell_il<1, VT, IT>), grid, blk, 0, st, n, nrhs, h->sell_ptr, col, val, x, y, ldy,
                                part, done);
@@ -1676,11 +1677,11 @@ void spmv_il_dev(ddlr_prec* h, int nrhs, const double* x, double* y, int64_t ldy
 }
 
 // x += alpha p ; r -= alpha q per lane (p interleaved)
-void cg_xr_dev(ddlr_prec* h, int nr, hipStream_t st) {
+void cg_xr_dev(ddlr_prec* h, int nr, int S, hipStream_t st) {
     Workspace& W = h->ws;
     const int64_t n = h->ndev;
     const dim3 grid(kRedBlocks), blk(256);
-    switch (lane_stride(nr)) {
+    switch (S) {
         case 1:
             hipLaunchKernelGGL(k_cg_xr<1>, grid, blk, 0, st, n, nr, W.lanes, W.p, W.q, W.x, W.r, n, W.part, W.done);
             break;
@@ -1728,11 +1729,11 @@ template <int S> void cg_split_launch(ddlr_prec* h, int nr, hipStream_t st) {
 }
 
 // r -= alpha q (with r.r partials and the step record xa) on st
-void cg_r_dev(ddlr_prec* h, int nr, hipStream_t st) {
+void cg_r_dev(ddlr_prec* h, int nr, int S, hipStream_t st) {
     Workspace& W = h->ws;
     const int64_t n = h->ndev;
     const dim3 g(kRedBlocks), b(256);
-    switch (lane_stride(nr)) {
+    switch (S) {
     case 1: hipLaunchKernelGGL(k_cg_r<1>, g, b, 0, st, n, nr, W.lanes, W.q, W.r, n, W.xa, W.part, W.done); break;
     case 2: hipLaunchKernelGGL(k_cg_r<2>, g, b, 0, st, n, nr, W.lanes, W.q, W.r, n, W.xa, W.part, W.done); break;
     case 4: hipLaunchKernelGGL(k_cg_r<4>, g, b, 0, st, n, nr, W.lanes, W.q, W.r, n, W.xa, W.part, W.done); break;
@@ -1744,8 +1745,8 @@ void cg_r_dev(ddlr_prec* h, int nr, hipStream_t st) {
 
 // r -= alpha q (with r.r partials) on st; x += alpha p forked to the x stream
 // (joined by cg_join before p changes)
-void cg_split_dev(ddlr_prec* h, int nr, hipStream_t st) {
-    switch (lane_stride(nr)) {
+void cg_split_dev(ddlr_prec* h, int nr, int S, hipStream_t st) {
+    switch (S) {
     case 1: cg_split_launch<1>(h, nr, st); break;
     case 2: cg_split_launch<2>(h, nr, st); break;
     case 4: cg_split_launch<4>(h, nr, st); break;
@@ -2970,12 +2971,15 @@ extern "C" {
 
 // One CG iteration of every lane (lane phases, see CgLane), nr columns of the
 // handle's workspace.  Kernels exit early once W.done is set.
-static void lane_iteration(ddlr_prec* h, int nr, hipStream_t st) {
+// S: the interleave stride of p, at least lane_stride(nr) (0: that stride);
+// a lane's arithmetic does not depend on it or on the other lanes.
+static void lane_iteration(ddlr_prec* h, int nr, hipStream_t st, int S = 0) {
     Workspace& W = h->ws;
     const int64_t n = h->ndev;
+    if (!S) S = lane_stride(nr);
     const int npart_spmv = (int)((n + 255) / 256);
     // each dot product: partials, then one launch reducing them and updating the lanes
-    spmv_il_dev(h, nr, W.p, W.q, n, W.part, st, W.done);
+    spmv_il_dev(h, nr, W.p, W.q, n, W.part, st, W.done, S);
     hipLaunchKernelGGL(k_reduce_lane, dim3(nr), dim3(256), 0, st, 2, npart_spmv, nr, W.part, W.sums, W.lanes, W.done,
                        W.ctr);
     LAUNCHCHK();
@@ -2983,9 +2987,9 @@ static void lane_iteration(ddlr_prec* h, int nr, hipStream_t st) {
     // preconditioner, or with the r update
     const bool xp = h->cg_xp;
     const bool split = !xp && h->x_st != nullptr;
-    if (xp) cg_r_dev(h, nr, st);
-    else if (split) cg_split_dev(h, nr, st);
-    else cg_xr_dev(h, nr, st);
+    if (xp) cg_r_dev(h, nr, S, st);
+    else if (split) cg_split_dev(h, nr, S, st);
+    else cg_xr_dev(h, nr, S, st);
     hipLaunchKernelGGL(k_reduce_lane, dim3(nr), dim3(256), 0, st, 3, kRedBlocks, nr, W.part, W.sums, W.lanes, W.done,
                        W.ctr);
     LAUNCHCHK();
@@ -2997,7 +3001,6 @@ static void lane_iteration(ddlr_prec* h, int nr, hipStream_t st) {
                        W.ctr);
     LAUNCHCHK();
     if (split) HIPCHK(hipStreamWaitEvent(st, h->ev_xj, 0));  // x used the old p
-    const int S = lane_stride(nr);
     const dim3 gp(grid_for(n)), bp(256);
     if (xp) {
         switch (S) {
@@ -4770,6 +4773,11 @@ struct SrvMatrix {
     ddlr_prec* h = nullptr;
     hipStream_t st = nullptr;
     double* stage = nullptr;  // user-order staging, n x slots
+    double* bdev = nullptr;   // each slot's right-hand side in device order (n x slots), for the true residual
+    double* tq = nullptr;     // n: b - A x of a retiring slot
+    double* rpart = nullptr;  // kRedBlocks partials of its squared norm
+    double* rtrue = nullptr;  // slots: ||b - A x||^2 per retired slot
+    std::vector<double> rtrue_h;
     DMem mem;
     size_t bytes = 0;
     std::vector<SrvRequest*> slot_req;
@@ -4802,15 +4810,21 @@ double now_s() {
 }
 
 // One pass of the engine: admit queued columns into free slots, run `tick`
-// iterations on every matrix that has lanes, retire finished lanes.
+// iterations on every matrix that has lanes, retire finished lanes.  A matrix
+// iterates only the slots up to its highest occupied one (p keeps the stride
+// of all slots, so running lanes are not moved); its launch shapes for that
+// width are tuned on first use.  The device lock is held per matrix while its
+// work is enqueued, not across the whole pass, so other calls on the device
+// interleave.  A retiring lane's true residual ||b - A x|| is computed before
+// its x leaves the device.
 bool server_step(ddlr_server* S) {
-    DevLock dl(S->device);  // before S->mu, as in ddlr_server_add
     struct Adm {
         int slot;
         SrvRequest* r;
         int col;
     };
     std::vector<std::vector<Adm>> adm(S->mats.size());
+    std::vector<int> width(S->mats.size(), 0);
     bool any = false;
     {
         std::lock_guard<std::mutex> lk(S->mu);
@@ -4827,15 +4841,19 @@ bool server_step(ddlr_server* S) {
             if (r->next_col == r->nrhs) it = S->queue.erase(it);
             else ++it;
         }
-        for (auto& M : S->mats)
-            for (SrvRequest* r : M->slot_req) any = any || r;
+        for (size_t mi = 0; mi < S->mats.size(); ++mi)
+            for (int sl = 0; sl < S->slots; ++sl)
+                if (S->mats[mi]->slot_req[sl]) width[mi] = sl + 1;
+        for (int wdt : width) any = any || wdt > 0;
     }
     if (!any) return false;
-    const int ns = S->slots;
+    const int ns = S->slots, stride = lane_stride(ns);
     for (size_t mi = 0; mi < S->mats.size(); ++mi) {
         SrvMatrix& M = *S->mats[mi];
         ddlr_prec* h = M.h;
         const int64_t n = h->ndev;
+        if (adm[mi].empty() && width[mi] == 0) continue;
+        DevLock dl(S->device);
         if (!adm[mi].empty()) {
             std::vector<int32_t> start(ns, 0), maxit(ns, 0);
             std::vector<double> tol2(ns, 0.0);
@@ -4845,16 +4863,18 @@ bool server_step(ddlr_server* S) {
                 hipLaunchKernelGGL((k_gather<double, double>), dim3(grid_for(n)), dim3(256), 0, M.st, n, 1, h->perm_dev,
                                    M.stage + (size_t)a.slot * n, n, h->ws.r + (size_t)a.slot * n, n);
                 LAUNCHCHK();
+                hipLaunchKernelGGL((k_gather<double, double>), dim3(grid_for(n)), dim3(256), 0, M.st, n, 1, h->perm_dev,
+                                   M.stage + (size_t)a.slot * n, n, M.bdev + (size_t)a.slot * n, n);
+                LAUNCHCHK();
                 start[a.slot] = 1;
                 tol2[a.slot] = a.r->tol2;
                 maxit[a.slot] = a.r->maxit;
             }
             lane_admit(h, ns, start, tol2, maxit, M.st);
         }
-        bool occupied = false;
-        for (SrvRequest* r : M.slot_req) occupied = occupied || r;
-        if (!occupied) continue;
-        for (int c = 0; c < S->tick; ++c) lane_iteration(h, ns, M.st);
+        if (width[mi] == 0) continue;
+        autotune(h, width[mi], M.st, false);
+        for (int c = 0; c < S->tick; ++c) lane_iteration(h, width[mi], M.st, stride);
         HIPCHK(hipMemcpyAsync(M.lanes_h.data(), h->ws.lanes, ns * sizeof(CgLane), hipMemcpyDeviceToHost, M.st));
     }
     for (auto& Mp : S->mats) HIPCHK(hipStreamSynchronize(Mp->st));
@@ -4864,16 +4884,31 @@ bool server_step(ddlr_server* S) {
         ddlr_prec* h = M.h;
         const int64_t n = h->ndev;
         std::vector<int> fin;
-        for (int sl = 0; sl < ns; ++sl)
+        for (int sl = 0; sl < width[mi]; ++sl)
             if (M.slot_req[sl] && M.lanes_h[sl].phase == 3) fin.push_back(sl);
         if (fin.empty()) continue;
-        for (int sl : fin) {
-            hipLaunchKernelGGL((k_scatter<double, double>), dim3(grid_for(n)), dim3(256), 0, M.st, n, 1, h->perm_dev,
-                               h->ws.x + (size_t)sl * n, n, M.stage + (size_t)sl * n, n);
-            LAUNCHCHK();
-            SrvRequest* r = M.slot_req[sl];
-            HIPCHK(hipMemcpyAsync(r->x + (size_t)M.slot_col[sl] * n, M.stage + (size_t)sl * n, n * sizeof(double),
-                                  hipMemcpyDeviceToHost, M.st));
+        {
+            DevLock dl(S->device);
+            for (int sl : fin) {
+                const double* xs = h->ws.x + (size_t)sl * n;
+                spmv_dev(h, 1, xs, n, M.tq, n, nullptr, M.st, nullptr);
+                hipLaunchKernelGGL(k_sub, dim3(grid_for(n)), dim3(256), 0, M.st, n, M.bdev + (size_t)sl * n, M.tq,
+                                   M.tq);
+                LAUNCHCHK();
+                hipLaunchKernelGGL((k_dot<double, double>), dim3(kRedBlocks), dim3(256), 0, M.st, n, 1, M.tq, n, M.tq,
+                                   n, M.rpart, nullptr);
+                LAUNCHCHK();
+                hipLaunchKernelGGL(k_reduce_cols, dim3(1), dim3(256), 0, M.st, kRedBlocks, 1, M.rpart, M.rtrue + sl,
+                                   nullptr);
+                LAUNCHCHK();
+                hipLaunchKernelGGL((k_scatter<double, double>), dim3(grid_for(n)), dim3(256), 0, M.st, n, 1,
+                                   h->perm_dev, xs, n, M.stage + (size_t)sl * n, n);
+                LAUNCHCHK();
+                SrvRequest* r = M.slot_req[sl];
+                HIPCHK(hipMemcpyAsync(r->x + (size_t)M.slot_col[sl] * n, M.stage + (size_t)sl * n, n * sizeof(double),
+                                      hipMemcpyDeviceToHost, M.st));
+            }
+            HIPCHK(hipMemcpyAsync(M.rtrue_h.data(), M.rtrue, ns * sizeof(double), hipMemcpyDeviceToHost, M.st));
         }
         HIPCHK(hipStreamSynchronize(M.st));
         const double t = now_s();
@@ -4886,7 +4921,7 @@ bool server_step(ddlr_server* S) {
             inf.iters = l.its;
             inf.status = conv ? DDLR_OK : DDLR_E_NO_CONVERGENCE;
             inf.relres = l.bb > 0 ? std::sqrt(l.rr / l.bb) : 0.0;
-            inf.relres_true = -1.0;  // not computed by the server
+            inf.relres_true = l.bb > 0 ? std::sqrt(M.rtrue_h[sl] / l.bb) : 0.0;
             r->done_cols++;
             S->solves_done++;
             M.slot_req[sl] = nullptr;
@@ -4966,7 +5001,8 @@ ddlr_status ddlr_server_add(ddlr_server* S, ddlr_prec* h, int32_t* matrix_id) {
         DevLock dl(S->device);
         std::lock_guard<std::mutex> lk(S->mu);
         const size_t before = prec_bytes(h);
-        const size_t stage = (size_t)h->ndev * S->slots * sizeof(double);
+        // staging, device-order right-hand sides, the residual vector and its partials and sums
+        const size_t stage = ((size_t)h->ndev * (2 * S->slots + 1) + kRedBlocks + S->slots) * sizeof(double);
         // workspace for the slots, then the budget check on everything resident
         ensure_ws(h, S->slots);
         ensure_cg_streams(h);
@@ -4978,6 +5014,11 @@ ddlr_status ddlr_server_add(ddlr_server* S, ddlr_prec* h, int32_t* matrix_id) {
             return DDLR_E_BUDGET;
         }
         M->stage = M->mem.alloc<double>((size_t)h->ndev * S->slots);
+        M->bdev = M->mem.alloc<double>((size_t)h->ndev * S->slots);
+        M->tq = M->mem.alloc<double>((size_t)h->ndev);
+        M->rpart = M->mem.alloc<double>(kRedBlocks);
+        M->rtrue = M->mem.alloc<double>(S->slots);
+        M->rtrue_h.assign(S->slots, 0.0);
         HIPCHK(hipStreamCreateWithFlags(&M->st, hipStreamNonBlocking));  // default priority
         M->bytes = need;
         M->slot_req.assign(S->slots, nullptr);

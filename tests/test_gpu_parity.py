@@ -474,7 +474,8 @@ def test_serving_same_alone_and_in_mix():
     """Continuous batching: a right-hand side solved alone, by the server with
     an otherwise empty queue, and by the server inside a stream of requests on
     three matrices (requests arriving while others run, more columns than
-    lanes) gives bitwise the same x."""
+    lanes, the iterated lane width changing with occupancy) gives bitwise the
+    same x, and the server reports each column's true residual (<= 1e-6)."""
     import time
     cfgs = [w.config("c1"), w.config("small3d"), irregular()]
     hs, refs, bsets = [], [], []
@@ -502,6 +503,7 @@ def test_serving_same_alone_and_in_mix():
     t, x = D.ddlr_server_submit(srv, mids[1], bsets[1][:, 2])
     st, info = D.ddlr_server_wait(srv, t)
     assert st == D.OK and np.array_equal(x[:, 0], refs[1][:, 2])
+    assert 0 < info[0]["relres_true"] <= 1e-6
     # in a mix: random matrices, 1..6 columns, staggered arrivals
     rng = np.random.default_rng(5)
     jobs = []
@@ -514,7 +516,7 @@ def test_serving_same_alone_and_in_mix():
     for t, x, q, cols in jobs:
         st, info = D.ddlr_server_wait(srv, t)
         assert st == D.OK
-        assert all(i["relres"] <= 1e-6 for i in info)
+        assert all(i["relres"] <= 1e-6 and 0 < i["relres_true"] <= 1e-6 for i in info)
         assert np.array_equal(x, refs[q][:, cols]), (q, cols)
     stats = D.ddlr_server_stats(srv)
     assert stats["requests_done"] == 25 and stats["queued"] == 0
