@@ -21,13 +21,18 @@ FACTOR_IC, FACTOR_ILDL, FACTOR_EXACT = 0, 1, 2
 CORDER_MULTICOLOR, CORDER_NATURAL = 0, 1
 
 
-def build(force: bool = True, out: str = _LIB, native: bool = False) -> str:
+def build(force: bool = True, out: str = _LIB, native: bool = False, sanitize: bool = False) -> str:
     """Compile the oracle with gcc (-O3, OpenMP).  native=True adds
     -march=native: only for a build made and run on the same machine (the
-    CPU-baseline timing builds its own copy that way)."""
+    CPU-baseline timing builds its own copy that way).  sanitize=True builds
+    with AddressSanitizer and UndefinedBehaviorSanitizer (-O1 -g, stop at the
+    first report); a process loading it needs libasan preloaded."""
     if force or not os.path.exists(out):
         tmp = out + ".tmp"
         flags = ["-O3"] + (["-march=native"] if native else [])
+        if sanitize:
+            flags = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                     "-fno-sanitize-recover=all"]
         subprocess.check_call(["gcc", *flags, "-fopenmp", "-fPIC", "-shared", "-Wall", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, out)
     return out
@@ -44,6 +49,16 @@ def use_native_build(directory: str) -> str:
     if _lib is not None:
         raise RuntimeError("the oracle library is already loaded")
     _lib_path = build(True, os.path.join(directory, "libddlr_oracle_native.so"), native=True)
+    return _lib_path
+
+
+def use_library(path: str) -> str:
+    """Makes the oracle library at `path` (a build() output) the one this
+    process loads (call before the first Oracle)."""
+    global _lib_path
+    if _lib is not None:
+        raise RuntimeError("the oracle library is already loaded")
+    _lib_path = path
     return _lib_path
 
 
