@@ -21,7 +21,13 @@
 // implementation of the same rule: each entry of a sparse product
 // sum_k a_ik b_kj is accumulated from 0.0 in ascending k; ||z_:j||^2 is
 // accumulated down column j; tr(R^T W) and ||W||_F^2 (W = C Z) and ||R||_F^2
-// are single running sums over stored entries in row-major order.
+// are single running sums over stored entries in row-major order; R keeps an
+// entry for every entry of C X and for the diagonal.
+//
+// This implementation works on coordinate lists: a product expands the
+// terms of each output row as (column, k, value) triples, orders them by
+// column (stably, so k stays ascending) and sums each run; symmetrisation and
+// the two-sided survivor test pair entries by sorting (row, column) keys.
 //
 // X is SPD when ||I - C X||_inf < 1 (largest absolute row sum): I - C X is
 // similar to I - C^{1/2} X C^{1/2}, whose spectral radius is at most any
@@ -39,183 +45,172 @@ namespace ddlr {
 
 namespace {
 
-// Square sparse matrix, rows with ascending columns (symmetric ones double as
-// their own column storage).
-struct Sp {
+// Square sparse matrix in compressed rows, columns ascending in each row.
+struct Rows {
     int64_t n = 0;
-    std::vector<int64_t> row;  // n + 1
+    std::vector<int64_t> start;  // n + 1
     std::vector<int32_t> col;
     std::vector<double> val;
-    explicit Sp(int64_t n_ = 0) : n(n_), row(n_ + 1, 0) {}
-    double at(int64_t i, int32_t j) const {
-        auto b = col.begin() + row[i], e = col.begin() + row[i + 1];
-        auto it = std::lower_bound(b, e, j);
-        return (it != e && *it == j) ? val[it - col.begin()] : 0.0;
+    explicit Rows(int64_t n_ = 0) : n(n_), start(1, 0) { start.reserve(n_ + 1); }
+    void close_row() { start.push_back((int64_t)col.size()); }
+    void put(int32_t j, double v) {
+        col.push_back(j);
+        val.push_back(v);
     }
 };
 
-// Row-by-row product a * b with a dense accumulator; every entry sums its
-// terms from 0.0 in ascending k (the order of a's row).
-Sp product(const Sp& a, const Sp& b) {
-    const int64_t n = a.n;
-    Sp c(n);
-    std::vector<double> acc(n, 0.0);
-    std::vector<int64_t> seen(n, -1);
-    std::vector<int32_t> cols;
-    for (int64_t i = 0; i < n; ++i) {
-        cols.clear();
-        for (int64_t t = a.row[i]; t < a.row[i + 1]; ++t) {
+struct Term {
+    int32_t j;
+    double v;
+};
+
+// a * b: row i gathers the terms a_ik b_kj for its k in ascending order,
+// orders them by j keeping that order, and sums each run from 0.0.
+Rows multiply(const Rows& a, const Rows& b) {
+    Rows c(a.n);
+    std::vector<Term> terms;
+    for (int64_t i = 0; i < a.n; ++i) {
+        terms.clear();
+        for (int64_t t = a.start[i]; t < a.start[i + 1]; ++t) {
             const int32_t k = a.col[t];
-            const double aik = a.val[t];
-            for (int64_t u = b.row[k]; u < b.row[k + 1]; ++u) {
-                const int32_t j = b.col[u];
-                if (seen[j] != i) {
-                    seen[j] = i;
-                    acc[j] = 0.0;
-                    cols.push_back(j);
-                }
-                acc[j] += aik * b.val[u];
-            }
+            for (int64_t u = b.start[k]; u < b.start[k + 1]; ++u) terms.push_back({b.col[u], a.val[t] * b.val[u]});
         }
-        std::sort(cols.begin(), cols.end());
-        for (int32_t j : cols) {
-            c.col.push_back(j);
-            c.val.push_back(acc[j]);
+        std::stable_sort(terms.begin(), terms.end(), [](const Term& x, const Term& y) { return x.j < y.j; });
+        for (size_t q = 0; q < terms.size();) {
+            const int32_t j = terms[q].j;
+            double sum = 0.0;
+            for (; q < terms.size() && terms[q].j == j; ++q) sum += terms[q].v;
+            c.put(j, sum);
         }
-        c.row[i + 1] = (int64_t)c.col.size();
+        c.close_row();
     }
     return c;
 }
 
-// I - w
-Sp identity_minus(const Sp& w) {
-    Sp r(w.n);
+// R = I - W on the pattern of W plus the diagonal: 1 - w_ii, -w_ij, or 1
+Rows residual(const Rows& w) {
+    Rows r(w.n);
     for (int64_t i = 0; i < w.n; ++i) {
-        bool diag = false;
-        for (int64_t t = w.row[i]; t < w.row[i + 1]; ++t) {
-            const int32_t j = w.col[t];
-            if (!diag && j > i) {
-                r.col.push_back((int32_t)i);
-                r.val.push_back(1.0);
-                diag = true;
-            }
-            if (j == i) {
-                r.col.push_back(j);
-                r.val.push_back(1.0 - w.val[t]);
-                diag = true;
-            } else {
-                r.col.push_back(j);
-                r.val.push_back(-w.val[t]);
-            }
-        }
-        if (!diag) {
-            r.col.push_back((int32_t)i);
-            r.val.push_back(1.0);
-        }
-        r.row[i + 1] = (int64_t)r.col.size();
+        const int32_t d = (int32_t)i;
+        int64_t t = w.start[i];
+        const int64_t te = w.start[i + 1];
+        for (; t < te && w.col[t] < d; ++t) r.put(w.col[t], -w.val[t]);
+        if (t < te && w.col[t] == d) r.put(d, 1.0 - w.val[t++]);
+        else r.put(d, 1.0);
+        for (; t < te; ++t) r.put(w.col[t], -w.val[t]);
+        r.close_row();
     }
     return r;
 }
 
-double frobenius(const Sp& a) {
-    double t = 0.0;
-    for (double x : a.val) t += x * x;
-    return std::sqrt(t);
-}
+struct Coo {
+    int32_t i, j;
+    double v;
+    bool operator<(const Coo& o) const { return i != o.i ? i < o.i : j < o.j; }
+};
 
-// (z + z^T) / 2 on the union pattern
-Sp symmetrised(const Sp& z) {
-    const int64_t n = z.n;
-    // transpose by counting
-    Sp zt(n);
-    zt.col.resize(z.col.size());
-    zt.val.resize(z.col.size());
-    for (int32_t j : z.col) zt.row[j + 1]++;
-    for (int64_t i = 0; i < n; ++i) zt.row[i + 1] += zt.row[i];
-    std::vector<int64_t> next(zt.row.begin(), zt.row.end() - 1);
-    for (int64_t i = 0; i < n; ++i)
-        for (int64_t t = z.row[i]; t < z.row[i + 1]; ++t) {
-            const int64_t q = next[z.col[t]]++;
-            zt.col[q] = (int32_t)i;
-            zt.val[q] = z.val[t];
+// (z + z^T) / 2 on the union pattern: every entry listed once as (i, j) and
+// once transposed; sorting pairs the two copies of an entry that has both.
+Rows symmetrise(const Rows& z) {
+    std::vector<Coo> e;
+    e.reserve(2 * z.col.size());
+    for (int64_t i = 0; i < z.n; ++i)
+        for (int64_t t = z.start[i]; t < z.start[i + 1]; ++t) {
+            e.push_back({(int32_t)i, z.col[t], z.val[t]});
+            e.push_back({z.col[t], (int32_t)i, z.val[t]});
         }
-    Sp s(n);
-    for (int64_t i = 0; i < n; ++i) {
-        int64_t a = z.row[i], b = zt.row[i];
-        const int64_t ae = z.row[i + 1], be = zt.row[i + 1];
-        while (a < ae || b < be) {
-            const int32_t ja = a < ae ? z.col[a] : INT32_MAX, jb = b < be ? zt.col[b] : INT32_MAX;
-            const int32_t j = std::min(ja, jb);
-            const double u = ja == j ? z.val[a++] : 0.0;
-            const double v = jb == j ? zt.val[b++] : 0.0;
-            s.col.push_back(j);
-            s.val.push_back(0.5 * (u + v));
+    std::sort(e.begin(), e.end());  // (i, j) and its transposed copy are adjacent
+    Rows s(z.n);
+    size_t q = 0;
+    for (int64_t i = 0; i < z.n; ++i) {
+        for (; q < e.size() && e[q].i == i; ++q) {
+            if (e[q].i == e[q].j) {  // the diagonal appears twice with one value
+                s.put(e[q].j, 0.5 * (e[q].v + e[q].v));
+                ++q;
+            } else if (q + 1 < e.size() && e[q + 1].i == e[q].i && e[q + 1].j == e[q].j) {
+                s.put(e[q].j, 0.5 * (e[q].v + e[q + 1].v));
+                ++q;
+            } else {
+                s.put(e[q].j, 0.5 * (e[q].v + 0.0));
+            }
         }
-        s.row[i + 1] = (int64_t)s.col.size();
+        s.close_row();
     }
     return s;
 }
 
-// dual-threshold dropping with a symmetric survivor pattern (z symmetric)
-Sp dropped(const Sp& z, double tol, int lfil) {
-    const int64_t n = z.n;
-    std::vector<char> keep(z.col.size(), 0);
+// The dropping rule on symmetric z (column j = row j): each column selects
+// its survivors; an entry is kept when both its column and its row selected it.
+Rows drop(const Rows& z, double tol, int lfil) {
+    std::vector<Coo> picks;  // (column, row) of every selection, listed as (min, max)
     std::vector<int64_t> cand;
-    for (int64_t j = 0; j < n; ++j) {
+    for (int64_t j = 0; j < z.n; ++j) {
+        const int64_t a = z.start[j], e = z.start[j + 1];
         double sq = 0.0;
-        for (int64_t t = z.row[j]; t < z.row[j + 1]; ++t) sq += z.val[t] * z.val[t];
+        for (int64_t t = a; t < e; ++t) sq += z.val[t] * z.val[t];
         const double thr = tol * std::sqrt(sq);
         cand.clear();
-        for (int64_t t = z.row[j]; t < z.row[j + 1]; ++t) {
-            if (z.col[t] == j) {
-                keep[t] = 1;
-            } else if (!(std::fabs(z.val[t]) < thr)) {
-                cand.push_back(t);
-            }
-        }
-        // larger magnitude first; equal magnitudes by position (= ascending row)
-        std::sort(cand.begin(), cand.end(), [&](int64_t x, int64_t y) {
+        for (int64_t t = a; t < e; ++t)
+            if (z.col[t] != j && !(std::fabs(z.val[t]) < thr)) cand.push_back(t);
+        const size_t keep = std::min<size_t>(cand.size(), (size_t)std::max(lfil, 0));
+        // the keep largest magnitudes, equal magnitudes by ascending row
+        std::partial_sort(cand.begin(), cand.begin() + keep, cand.end(), [&](int64_t x, int64_t y) {
             const double ax = std::fabs(z.val[x]), ay = std::fabs(z.val[y]);
-            return ax != ay ? ax > ay : x < y;
+            return ax != ay ? ax > ay : z.col[x] < z.col[y];
         });
-        for (size_t q = 0; q < cand.size() && (int64_t)q < lfil; ++q) keep[cand[q]] = 1;
-    }
-    Sp d(n);
-    for (int64_t i = 0; i < n; ++i) {
-        for (int64_t t = z.row[i]; t < z.row[i + 1]; ++t) {
-            if (!keep[t]) continue;
-            const int32_t j = z.col[t];
-            auto b = z.col.begin() + z.row[j], e = z.col.begin() + z.row[j + 1];
-            auto it = std::lower_bound(b, e, (int32_t)i);
-            if (it == e || *it != i || !keep[it - z.col.begin()]) continue;
-            d.col.push_back(j);
-            d.val.push_back(z.val[t]);
+        for (size_t q = 0; q < keep; ++q) {
+            const int32_t i = z.col[cand[q]];
+            picks.push_back({std::min((int32_t)j, i), std::max((int32_t)j, i), 0.0});
         }
-        d.row[i + 1] = (int64_t)d.col.size();
+    }
+    std::sort(picks.begin(), picks.end());
+    // an off-diagonal pair selected from both sides appears twice
+    std::vector<Coo> both;
+    for (size_t q = 0; q + 1 < picks.size(); ++q)
+        if (picks[q].i == picks[q + 1].i && picks[q].j == picks[q + 1].j) {
+            both.push_back(picks[q]);
+            both.push_back({picks[q].j, picks[q].i, 0.0});
+            ++q;
+        }
+    std::sort(both.begin(), both.end());
+    Rows d(z.n);
+    size_t q = 0;
+    for (int64_t i = 0; i < z.n; ++i) {
+        for (int64_t t = z.start[i]; t < z.start[i + 1]; ++t) {
+            const int32_t j = z.col[t];
+            if (j == i) {
+                d.put(j, z.val[t]);
+                continue;
+            }
+            while (q < both.size() && (both[q].i < i || (both[q].i == i && both[q].j < j))) ++q;
+            if (q < both.size() && both[q].i == i && both[q].j == j) d.put(j, z.val[t]);
+        }
+        d.close_row();
     }
     return d;
 }
 
 // x + beta d on the union pattern
-Sp plus_scaled(const Sp& x, double beta, const Sp& d) {
-    Sp r(x.n);
+Rows axpy(const Rows& x, double beta, const Rows& d) {
+    Rows r(x.n);
     for (int64_t i = 0; i < x.n; ++i) {
-        int64_t a = x.row[i], b = d.row[i];
-        const int64_t ae = x.row[i + 1], be = d.row[i + 1];
-        while (a < ae || b < be) {
-            const int32_t ja = a < ae ? x.col[a] : INT32_MAX, jb = b < be ? d.col[b] : INT32_MAX;
-            if (ja < jb) {
-                r.col.push_back(ja);
-                r.val.push_back(x.val[a++]);
-            } else if (jb < ja) {
-                r.col.push_back(jb);
-                r.val.push_back(beta * d.val[b++]);
+        int64_t a = x.start[i], b = d.start[i];
+        const int64_t ae = x.start[i + 1], be = d.start[i + 1];
+        while (a < ae && b < be) {
+            if (x.col[a] < d.col[b]) {
+                r.put(x.col[a], x.val[a]);
+                ++a;
+            } else if (d.col[b] < x.col[a]) {
+                r.put(d.col[b], beta * d.val[b]);
+                ++b;
             } else {
-                r.col.push_back(ja);
-                r.val.push_back(x.val[a++] + beta * d.val[b++]);
+                r.put(x.col[a], x.val[a] + beta * d.val[b]);
+                ++a, ++b;
             }
         }
-        r.row[i + 1] = (int64_t)r.col.size();
+        for (; a < ae; ++a) r.put(x.col[a], x.val[a]);
+        for (; b < be; ++b) r.put(d.col[b], beta * d.val[b]);
+        r.close_row();
     }
     return r;
 }
@@ -224,49 +219,57 @@ Sp plus_scaled(const Sp& x, double beta, const Sp& d) {
 
 void build_cinv(HostPlan& P, int nit, double tol, int lfil) {
     const int64_t s = P.s, m = P.m;
-    if (nit < 0 || !(tol >= 0.0) || lfil < 0) throw SetupError{DDLR_E_INVALID, "approximate inverse: bad iteration count, tolerance or fill"};
-    Sp C(s);
+    if (nit < 0 || !(tol >= 0.0) || lfil < 0)
+        throw SetupError{DDLR_E_INVALID, "approximate inverse: bad iteration count, tolerance or fill"};
+    Rows C(s), X(s);
     for (int64_t y = 0; y < s; ++y) {
+        double dg = 0.0;
         for (int64_t t = P.A0.rp[m + y]; t < P.A0.rp[m + y + 1]; ++t) {
-            C.col.push_back((int32_t)(P.A0.ci[t] - m));
-            C.val.push_back(P.A0.v[t]);
+            const int32_t j = (int32_t)(P.A0.ci[t] - m);
+            C.put(j, P.A0.v[t]);
+            if (j == y) dg = P.A0.v[t];
         }
-        C.row[y + 1] = (int64_t)C.col.size();
-    }
-    Sp X(s);
-    for (int64_t y = 0; y < s; ++y) {
-        const double d = C.at(y, (int32_t)y);
-        if (!(d > 0.0)) throw SetupError{DDLR_E_BREAKDOWN, "approximate inverse: C_alpha has a non-positive diagonal entry"};
-        X.col.push_back((int32_t)y);
-        X.val.push_back(1.0 / d);
-        X.row[y + 1] = y + 1;
+        C.close_row();
+        if (!(dg > 0.0))
+            throw SetupError{DDLR_E_BREAKDOWN, "approximate inverse: C_alpha has a non-positive diagonal entry"};
+        X.put((int32_t)y, 1.0 / dg);
+        X.close_row();
     }
     P.x_res.clear();
     P.x_iters = 0;
     for (int it = 0;; ++it) {
-        const Sp R = identity_minus(product(C, X));
-        P.x_res.push_back(frobenius(R));
+        const Rows R = residual(multiply(C, X));
+        double fro = 0.0;
+        for (double v : R.val) fro += v * v;
+        P.x_res.push_back(std::sqrt(fro));
         P.x_rinf = 0.0;
         for (int64_t i = 0; i < s; ++i) {
             double rowsum = 0.0;
-            for (int64_t t = R.row[i]; t < R.row[i + 1]; ++t) rowsum += std::fabs(R.val[t]);
+            for (int64_t t = R.start[i]; t < R.start[i + 1]; ++t) rowsum += std::fabs(R.val[t]);
             P.x_rinf = std::max(P.x_rinf, rowsum);
         }
         if (it == nit) break;
-        const Sp Z = dropped(symmetrised(product(X, R)), tol, lfil);
-        const Sp W = product(C, Z);
+        const Rows Z = drop(symmetrise(multiply(X, R)), tol, lfil);
+        const Rows W = multiply(C, Z);
+        // tr(R^T W) and ||W||_F^2 over W's entries in row-major order; R_ij by a
+        // merge of the two sorted rows
         double num = 0.0, den = 0.0;
-        for (int64_t i = 0; i < s; ++i)
-            for (int64_t t = W.row[i]; t < W.row[i + 1]; ++t) {
-                num += R.at(i, W.col[t]) * W.val[t];
+        for (int64_t i = 0; i < s; ++i) {
+            int64_t a = R.start[i];
+            const int64_t ae = R.start[i + 1];
+            for (int64_t t = W.start[i]; t < W.start[i + 1]; ++t) {
+                while (a < ae && R.col[a] < W.col[t]) ++a;
+                const double rij = (a < ae && R.col[a] == W.col[t]) ? R.val[a] : 0.0;
+                num += rij * W.val[t];
                 den += W.val[t] * W.val[t];
             }
+        }
         if (!(den > 0.0)) break;
-        X = plus_scaled(X, num / den, Z);
+        X = axpy(X, num / den, Z);
         P.x_iters = it + 1;
     }
     P.x_spd = P.x_rinf < 1.0;
-    P.X.rp.assign(X.row.begin(), X.row.end());
+    P.X.rp.assign(X.start.begin(), X.start.end());
     P.X.ci = std::move(X.col);
     P.X.v = std::move(X.val);
 }

@@ -211,6 +211,16 @@ def test_cheb_factor_and_interval_match_oracle(name, cfg, kw):
     assert 0 < q["cheb_lo"] <= q["cheb_ritz_lo"] <= q["cheb_ritz_hi"] <= q["cheb_hi"]
 
 
+def test_cheb_refuses_indefinite_block_jacobi():
+    """The Chebyshev solver needs D_alpha SPD: ILDL(0) of a matrix shifted to
+    negative diagonals gives negative pivots, and the setup is refused."""
+    A = w.laplacian_3d(8, 8, 8, shift=7.0)
+    part = w.box_partition((8, 8, 8), (2, 2, 1))
+    with pytest.raises(D.DDLRError) as e:
+        D.ddlr_setup(A, part, 4, 4, D.DDLR_1, device=-1, factor=D.FACTOR_ILDL0, csolve=D.CSOLVE_CHEB)
+    assert e.value.status == D.E_BREAKDOWN and "pivot" in str(e.value)
+
+
 @pytest.mark.parametrize("dims,parts", [((64, 64), (2, 2)), ((37, 29), (3, 2)), ((25, 25, 25), (4, 4, 8)),
                                         ((100, 100, 100), (4, 4, 8)), ((7, 5, 3), (7, 1, 3))])
 def test_partition_box_matches_generator(dims, parts):
