@@ -296,6 +296,7 @@ struct ddlr_prec {
     int16_t* sell_cold = nullptr;
     double* sell_val = nullptr;
     float* sell_valf = nullptr;
+    uint64_t* sell_pk = nullptr;  // (int32 column, FP32 value) pairs when both fit, for the CG's SpMV
     int64_t nslices = 0, sell_nnz = 0;
     int32_t *lrp = nullptr, *lci = nullptr, *urp = nullptr, *uci = nullptr, *lvl_ptr = nullptr;
     int32_t *erp = nullptr, *eci = nullptr, *etrp = nullptr, *etci = nullptr;
@@ -910,6 +911,15 @@ void upload_devhost(ddlr_prec* h, const DevHost& D) {
     if (f32ok) {
         std::vector<float> f(sval.begin(), sval.end());
         h->sell_valf = M.upload(f);
+        if (!i16ok) {  // one 8-byte load per entry in the interleaved SpMV
+            std::vector<uint64_t> pk(scol.size());
+            for (size_t q = 0; q < pk.size(); ++q) {
+                uint32_t bits;
+                std::memcpy(&bits, &f[q], 4);
+                pk[q] = (uint64_t)(uint32_t)scol[q] | ((uint64_t)bits << 32);
+            }
+            h->sell_pk = M.upload(pk);
+        }
     } else {
         h->sell_val = M.upload(sval);
     }
@@ -1647,29 +1657,50 @@ void spmv_il_dev(ddlr_prec* h, int nrhs, const double* x, double* y, int64_t ldy
     ProfScope ps(h, 2, st);
     const int64_t chunks = (n + 255) / 256;
     const dim3 grid((chunks + 7) / 8 * 8), blk(256);
+    if (!S) S = lane_stride(nrhs);
+    if (h->sell_pk) {
+        const int32_t* nc = nullptr;
+        const float* nv = nullptr;
+        switch (S) {
+#define DDLR_SPMV_PK(SS)                                                                                             \
+    case SS:                                                                                                         \
+        hipLaunchKernelGGL((k_spmv_sell_il<SS, float, int32_t, true>), grid, blk, 0, st, n, nrhs, h->sell_ptr, nc, nv, \
+                           x, y, ldy, part, done, h->sell_pk);                                                       \
+        break;
+            DDLR_SPMV_PK(1)
+            DDLR_SPMV_PK(2)
+            DDLR_SPMV_PK(4)
+            DDLR_SPMV_PK(8)
+            DDLR_SPMV_PK(16)
+#undef DDLR_SPMV_PK
+        default: throw SetupError{DDLR_E_INVALID, "CG runs at most 16 lanes per launch"};
+        }
+        LAUNCHCHK();
+        return;
+    }
     with_sell(h, [&](auto col, auto val) {
         using IT = std::remove_const_t<std::remove_pointer_t<decltype(col)>>;
         using VT = std::remove_const_t<std::remove_pointer_t<decltype(val)>>;
-        switch (S ? S : lane_stride(nrhs)) {
+        switch (S) {
         case 1:
             hipLaunchKernelGGL((k_spmv_sell_il<1, VT, IT>), grid, blk, 0, st, n, nrhs, h->sell_ptr, col, val, x, y, ldy,
-                               part, done);
+                               part, done, nullptr);
             break;
         case 2:
             hipLaunchKernelGGL((k_spmv_sell_il<2, VT, IT>), grid, blk, 0, st, n, nrhs, h->sell_ptr, col, val, x, y, ldy,
-                               part, done);
+                               part, done, nullptr);
             break;
         case 4:
             hipLaunchKernelGGL((k_spmv_sell_il<4, VT, IT>), grid, blk, 0, st, n, nrhs, h->sell_ptr, col, val, x, y, ldy,
-                               part, done);
+                               part, done, nullptr);
             break;
         case 8:
             hipLaunchKernelGGL((k_spmv_sell_il<8, VT, IT>), grid, blk, 0, st, n, nrhs, h->sell_ptr, col, val, x, y, ldy,
-                               part, done);
+                               part, done, nullptr);
             break;
         default:
             hipLaunchKernelGGL((k_spmv_sell_il<16, VT, IT>), grid, blk, 0, st, n, nrhs, h->sell_ptr, col, val, x, y,
-                               ldy, part, done);
+                               ldy, part, done, nullptr);
             break;
         }
     });

@@ -871,12 +871,15 @@ __global__ __launch_bounds__(256) void k_spmv_sell(int64_t n, int nrhs, const in
 // several times.  Per-row sums run over the slice entries in the same order
 // as k_spmv_sell, so both give the same y (k_spmv_sell's weight-0 group
 // padding can turn a -0 row sum into +0).
-template <int S, typename VT, typename IT>
+// kPk: the entries come as packed (int32 column, FP32 value) pairs from pk
+// (one load per entry instead of two; col and val unused).
+template <int S, typename VT, typename IT, bool kPk = false>
 __global__ __launch_bounds__(256) void k_spmv_sell_il(int64_t n, int nrhs, const int32_t* __restrict__ sptr,
                                                       const IT* __restrict__ col,
                                                       const VT* __restrict__ val, const double* __restrict__ x,
                                                       double* __restrict__ y, int64_t ldy, double* __restrict__ part,
-                                                      const int* __restrict__ done) {
+                                                      const int* __restrict__ done,
+                                                      const uint64_t* __restrict__ pk = nullptr) {
     __shared__ double sh[4 * S];
     if (done && *done) return;
     const int64_t per = gridDim.x >> 3;
@@ -900,8 +903,14 @@ __global__ __launch_bounds__(256) void k_spmv_sell_il(int64_t n, int nrhs, const
                 if (j0 + u < width) {
                     const int q = base + (j0 + u) * kSell + lane;
                     // A streams through once: non-temporal loads keep the gathered x lines in L2
-                    cg[u] = sell_col<IT>(__builtin_nontemporal_load(col + q), row);
-                    ag[u] = (double)__builtin_nontemporal_load(val + q);
+                    if constexpr (kPk) {
+                        const uint64_t e = __builtin_nontemporal_load(pk + q);
+                        cg[u] = (int64_t)(int32_t)(uint32_t)(e & 0xffffffffu);
+                        ag[u] = (double)__uint_as_float((uint32_t)(e >> 32));
+                    } else {
+                        cg[u] = sell_col<IT>(__builtin_nontemporal_load(col + q), row);
+                        ag[u] = (double)__builtin_nontemporal_load(val + q);
+                    }
                 }
             }
 #pragma unroll
