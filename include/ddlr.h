@@ -510,6 +510,18 @@ ddlr_status ddlr_batch_offsets(const ddlr_batch *b, int64_t *offsets);
  * us_per_iter[5] = its tuning: microseconds per iteration of the launch with
  * 64, 128, 256, 512 and 1024 threads. */
 ddlr_status ddlr_batch_tuning(const ddlr_batch *b, int32_t *persistent, int32_t *threads, float *us_per_iter);
+/* Workgroups per system of the persistent form (members: host array of nsys
+ * entries; 0 for every system when the batch replays chunks).  A batch whose
+ * systems differ in size runs as long as its slowest system, so
+ * ddlr_batch_create gives the systems estimated to be slowest several
+ * workgroups (a group) when the lanes fit the resident workgroups of the
+ * device: each member sweeps the merged levels of its own subdomain blocks
+ * (the blocks of A0 are independent, Sec. 3.1), the last one also the interface
+ * block and the interface step of the correction; members meet at workgroup
+ * barriers in device memory for the dot products and to exchange p and the
+ * first solve's result.  DDLR_BATCH_GROUP=0 keeps one workgroup per system,
+ * =N asks for N.  Errors: DDLR_E_INVALID (null argument). */
+ddlr_status ddlr_batch_members(const ddlr_batch *b, int32_t *members);
 ddlr_status ddlr_batch_apply(ddlr_batch *b, const double *x, double *y, void *stream);
 /* PCG on every system (x0 = 0, stopping rule of Sec. 5); info: host array of
  * nsys entries.  Synchronises the stream.  DDLR_E_NO_CONVERGENCE if any system

@@ -143,6 +143,7 @@ def load_library(path: str = LIB_PATH):
         "ddlr_batch_offsets": (I32, [P, P]),
         "ddlr_batch_apply": (I32, [P, P, P, P]),
         "ddlr_batch_tuning": (I32, [P, P, P, P]),
+        "ddlr_batch_members": (I32, [P, P]),
         "ddlr_batch_solve": (I32, [P, P, P, P, P, P]),
         "ddlr_batch_destroy": (None, [P]),
         "ddlr_server_create": (I32, [I32, C.c_size_t, I32, P]),
@@ -500,6 +501,13 @@ def ddlr_batch_tuning(batch: Batch) -> dict:
     return dict(persistent=pers.value, threads=nt.value, us_per_iter=list(us))
 
 
+def ddlr_batch_members(batch: Batch) -> list:
+    """Workgroups that solve each system in the persistent form (0: chunked form)."""
+    arr = (C.c_int32 * batch.nsys)()
+    _check(load_library().ddlr_batch_members(batch.handle, arr), "ddlr_batch_members")
+    return list(arr)
+
+
 def ddlr_batch_solve(batch: Batch, b, x, *, maxit: int = 500, rtol: float = 1e-6, stream=None):
     """PCG on every system; returns (status, list of per-system info dicts)."""
     lib = load_library()
@@ -641,7 +649,7 @@ def ddlr_version() -> int:
 
 EXPORTED = ["ddlr_version", "ddlr_options_default", "ddlr_solve_options_default", "ddlr_setup", "ddlr_apply",
             "ddlr_apply_noalloc", "ddlr_ctx_create", "ddlr_ctx_usage", "ddlr_ctx_destroy", "ddlr_export_setup",
-            "ddlr_import_setup", "ddlr_partition_box", "ddlr_batch_tuning",
+            "ddlr_import_setup", "ddlr_partition_box", "ddlr_batch_tuning", "ddlr_batch_members",
             "ddlr_a0_solve", "ddlr_spmv", "ddlr_solve", "ddlr_query", "ddlr_get_ordering", "ddlr_get_factor",
             "ddlr_get_cinv",
             "ddlr_get_levels", "ddlr_get_lanczos", "ddlr_get_lanczos_reorth", "ddlr_get_lowrank", "ddlr_set_lowrank", "ddlr_profile",

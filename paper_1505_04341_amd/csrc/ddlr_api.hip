@@ -8,6 +8,7 @@
 #include <deque>
 #include <map>
 #include <mutex>
+#include <queue>
 #include <thread>
 #include <unordered_map>
 #include <cmath>
@@ -262,6 +263,15 @@ struct PersistData {
     int meta_off = 0;                   // level metadata of the lane, staged at this byte offset
     int nt = 0;                         // threads per workgroup (256, 512, 1024); 0: not tuned
     float nt_us[5] = {0, 0, 0, 0, 0};   // tuning: microseconds per iteration, 64 .. 1024 threads
+    // groups: several workgroups on one system (batches only)
+    int ngroups = 0;
+    unsigned* gctr = nullptr;    // per group 64 counters: the slow barrier's at 0, the fast one's at 32
+    double* gpart = nullptr;     // per group 4 x kGroupMax partial sums
+    int* gxcc = nullptr;         // per group kGroupMax XCD ids
+    int grid = 0;                // lanes of a launch, idle slots included (0: one lane per table entry)
+    int gslow = 0;               // 1: group barriers always take the slow form
+    std::vector<int> sys_lane;   // per system: the lane of its first member (its result)
+    std::vector<int> members;    // per system: workgroups on it
 };
 
 // A device and a device-memory budget shared by the handles created in it
@@ -3228,29 +3238,42 @@ struct MergedLevels {
     std::vector<double> fval, bval, dq;
 };
 
-void persist_levels(const HostPlan& P, int64_t r0, MergedLevels& M, int32_t& l0, int32_t& l1) {
+// L^T of a plan by device rows (each row's entries in ascending internal row order)
+struct PlanTranspose {
+    std::vector<int32_t> tcnt, tcol;
+    std::vector<double> tval;
+};
+
+void plan_transpose(const HostPlan& P, PlanTranspose& X) {
     const int64_t n = P.n;
-    // L^T rows of every device row, in ascending internal row order
-    std::vector<int32_t> tcnt(n + 1, 0);
+    X.tcnt.assign(n + 1, 0);
     for (int64_t i = 0; i < n; ++i)
-        for (int64_t t = P.L.rp[i]; t < P.L.rp[i + 1]; ++t) tcnt[P.int2dev[P.L.ci[t]] + 1]++;
-    for (int64_t d = 0; d < n; ++d) tcnt[d + 1] += tcnt[d];
-    std::vector<int32_t> tcol(tcnt[n]);
-    std::vector<double> tval(tcnt[n]);
-    std::vector<int32_t> fill(tcnt.begin(), tcnt.end() - 1);
+        for (int64_t t = P.L.rp[i]; t < P.L.rp[i + 1]; ++t) X.tcnt[P.int2dev[P.L.ci[t]] + 1]++;
+    for (int64_t d = 0; d < n; ++d) X.tcnt[d + 1] += X.tcnt[d];
+    X.tcol.assign(X.tcnt[n], 0);
+    X.tval.assign(X.tcnt[n], 0.0);
+    std::vector<int32_t> fill(X.tcnt.begin(), X.tcnt.end() - 1);
     for (int64_t i = 0; i < n; ++i)
         for (int64_t t = P.L.rp[i]; t < P.L.rp[i + 1]; ++t) {
             const int32_t q = fill[P.int2dev[P.L.ci[t]]]++;
-            tcol[q] = P.int2dev[i];
-            tval[q] = P.L.v[t];
+            X.tcol[q] = P.int2dev[i];
+            X.tval[q] = P.L.v[t];
         }
+}
+
+// Merged levels of blocks b0..b1-1 of a plan (block P.p is the interface block).
+void persist_levels(const HostPlan& P, const PlanTranspose& X, int64_t r0, int32_t b0, int32_t b1, MergedLevels& M,
+                    int32_t& l0, int32_t& l1) {
+    const std::vector<int32_t>& tcnt = X.tcnt;
+    const std::vector<int32_t>& tcol = X.tcol;
+    const std::vector<double>& tval = X.tval;
     int depth = 0;
-    for (int32_t b = 0; b <= P.p; ++b) depth = std::max(depth, P.blk_lvl[b + 1] - P.blk_lvl[b]);
+    for (int32_t b = b0; b < b1; ++b) depth = std::max(depth, P.blk_lvl[b + 1] - P.blk_lvl[b]);
     l0 = (int32_t)M.meta.size();
     std::vector<int32_t> rows;
     for (int j = 0; j < depth; ++j) {
         rows.clear();
-        for (int32_t b = 0; b <= P.p; ++b) {
+        for (int32_t b = b0; b < b1; ++b) {
             const int32_t l = P.blk_lvl[b] + j;
             if (l >= P.blk_lvl[b + 1]) continue;
             for (int32_t d = P.lvl_ptr[l]; d < P.lvl_ptr[l + 1]; ++d) rows.push_back(d);
@@ -3314,16 +3337,34 @@ size_t persist_lds_budget(int dev) {
     return cap > 8192 ? cap - 8192 : 0;  // the static reduction arrays and a margin
 }
 
+// First block of each of G members of a plan (G + 1 entries, the last P.p + 1):
+// contiguous ranges of the subdomain blocks balanced by rows, at least one per
+// member; the last member also takes the interface block (its rows count).
+std::vector<int32_t> member_blocks(const HostPlan& P, int G) {
+    std::vector<int32_t> cut(G + 1, 0);
+    cut[G] = P.p + 1;
+    const double target = (double)P.n / G;
+    for (int g = 1; g < G; ++g) {
+        int32_t b = cut[g - 1] + 1;
+        while (b < P.p - (G - g) && (double)P.boff[b] < g * target) ++b;
+        cut[g] = b;
+    }
+    return cut;
+}
+
 // Tables for the systems of `plans` (one per system; offsets r0 / s0 / d0, c0
-// per system, rank k), tsz = bytes of the preconditioner's type.
+// per system, rank k), tsz = bytes of the preconditioner's type.  groups: the
+// workgroups per system (empty: one each); lds_cap: largest dynamic LDS of a
+// launch (0: the device's).
 void persist_build(PersistData& PD, const std::vector<const HostPlan*>& plans, const std::vector<int64_t>& roff,
                    const std::vector<int64_t>& soff, const std::vector<int>& ks, const std::vector<double>& c0s,
-                   int kstride, size_t tsz, int dev) {
+                   int kstride, size_t tsz, int dev, const std::vector<int>& groups = {}, size_t lds_cap = 0) {
     MergedLevels M;
     std::vector<int64_t> arp(1, 0);
     std::vector<int32_t> aci;
     std::vector<double> av;
     size_t budget = persist_lds_budget(dev);
+    if (lds_cap) budget = std::min(budget, lds_cap);
     PD.hsys.clear();
     PD.lds_bytes = 0;
     // the level metadata of the deepest system takes (levels + 1) x 16 bytes of LDS
@@ -3337,23 +3378,38 @@ void persist_build(PersistData& PD, const std::vector<const HostPlan*>& plans, c
     if (meta_bytes + 16 > persist_lds_budget(dev) + 8192 - 4096)
         throw SetupError{DDLR_E_INVALID, "too many levels for the persistent form"};
     budget = budget > meta_bytes ? budget - meta_bytes : 0;
+    PD.ngroups = 0;
+    PD.members.assign(plans.size(), 1);
+    PlanTranspose X;
     for (size_t q = 0; q < plans.size(); ++q) {
         const HostPlan& P = *plans[q];
-        PSys S{};
-        S.r0 = roff[q];
-        S.s0 = soff[q];
-        S.d0 = (int64_t)q * kstride;
-        S.n = (int32_t)P.n;
-        S.m = (int32_t)P.m;
-        S.s = (int32_t)P.s;
-        S.k = ks[q];
-        S.c0 = c0s[q];
-        persist_levels(P, roff[q], M, S.l0, S.l1);
+        const int G = groups.empty() ? 1 : std::max(1, std::min({groups[q], (int)P.p, kGroupMax}));
+        PD.members[q] = G;
+        const std::vector<int32_t> cut = member_blocks(P, G);
+        plan_transpose(P, X);
+        const int grp = G > 1 ? PD.ngroups++ : -1;
+        for (int g = 0; g < G; ++g) {
+            PSys S{};
+            S.r0 = roff[q];
+            S.s0 = soff[q];
+            S.d0 = (int64_t)q * kstride;
+            S.n = (int32_t)P.n;
+            S.m = (int32_t)P.m;
+            S.s = (int32_t)P.s;
+            S.k = ks[q];
+            S.c0 = c0s[q];
+            S.o0 = (int32_t)P.boff[cut[g]];
+            S.o1 = (int32_t)P.boff[cut[g + 1]];
+            S.G = G;
+            S.g = g;
+            S.grp = grp;
+            persist_levels(P, X, roff[q], cut[g], cut[g + 1], M, S.l0, S.l1);
+            const size_t need = (size_t)(S.o1 - S.o0) * tsz;
+            S.lds = need <= budget;
+            if (S.lds) PD.lds_bytes = std::max(PD.lds_bytes, need);
+            PD.hsys.push_back(S);
+        }
         persist_csr(P, roff[q], arp, aci, av);
-        const size_t need = (size_t)P.n * tsz;
-        S.lds = need <= budget;
-        if (S.lds) PD.lds_bytes = std::max(PD.lds_bytes, need);
-        PD.hsys.push_back(S);
     }
     PD.meta_off = (int)((PD.lds_bytes + 15) & ~(size_t)15);
     PD.lds_bytes = PD.meta_off + meta_bytes;
@@ -3382,6 +3438,58 @@ void persist_build(PersistData& PD, const std::vector<const HostPlan*>& plans, c
     PD.arp = PD.mem.upload(arp);
     PD.aci = PD.mem.upload(aci);
     PD.av = PD.mem.upload(av);
+    if (PD.ngroups > 0) {
+        PD.gctr = PD.mem.alloc<unsigned>((size_t)PD.ngroups * 64);
+        PD.gpart = PD.mem.alloc<double>((size_t)PD.ngroups * 4 * kGroupMax);
+        PD.gxcc = PD.mem.alloc<int>((size_t)PD.ngroups * kGroupMax);
+    }
+}
+
+void persist_lanes(PersistData& PD, const std::vector<PLane>& lanes, int cols, int64_t n);
+
+// Lane table of a batch whose systems have PD.members workgroups each (table
+// entries in system order).  Ungrouped: lane q is system q.  Grouped: lanes
+// are dealt to the XCDs (lane l runs on XCD l mod nxcd, the dispatch order of
+// the device), every group on one XCD so that its barriers take the fast form,
+// the groups first, largest first, each on the XCD with the fewest lanes;
+// idle lanes fill the grid to a multiple of nxcd.
+void persist_batch_lanes(PersistData& PD, int64_t n, int nxcd) {
+    const int ns = (int)PD.members.size();
+    std::vector<int> first(ns + 1, 0);
+    for (int q = 0; q < ns; ++q) first[q + 1] = first[q] + PD.members[q];
+    PD.sys_lane.assign(ns, 0);
+    std::vector<PLane> lanes;
+    if (PD.ngroups == 0) {
+        for (int q = 0; q < ns; ++q) {
+            lanes.push_back(PLane{first[q], 0});
+            PD.sys_lane[q] = q;
+        }
+        PD.grid = ns;
+    } else {
+        std::vector<int> ord(ns);
+        for (int q = 0; q < ns; ++q) ord[q] = q;
+        std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return PD.members[a] > PD.members[b]; });
+        std::vector<std::vector<int>> slot(nxcd);  // table entries per XCD, in slot order
+        for (int q : ord) {
+            int x = 0;
+            for (int y = 1; y < nxcd; ++y)
+                if (slot[y].size() < slot[x].size()) x = y;
+            for (int g = 0; g < PD.members[q]; ++g) slot[x].push_back(first[q] + g);
+        }
+        size_t depth = 0;
+        for (const auto& v : slot) depth = std::max(depth, v.size());
+        lanes.assign(depth * nxcd, PLane{-1, 0});
+        for (int x = 0; x < nxcd; ++x)
+            for (size_t t = 0; t < slot[x].size(); ++t) lanes[t * nxcd + x] = PLane{slot[x][t], 0};
+        for (size_t l = 0; l < lanes.size(); ++l)
+            if (lanes[l].sys >= 0 && PD.hsys[lanes[l].sys].g == 0) {
+                int q = 0;
+                while (first[q + 1] <= lanes[l].sys) ++q;
+                PD.sys_lane[q] = (int)l;
+            }
+        PD.grid = (int)lanes.size();
+    }
+    persist_lanes(PD, lanes, 1, n);
 }
 
 // Lane table and per-lane results / vectors for `nl` lanes (columns `cols`).
@@ -3399,6 +3507,15 @@ void persist_lanes(PersistData& PD, const std::vector<PLane>& lanes, int cols, i
     }
 }
 
+// Workgroups of k_pcg_persist<T, NT> with PD's dynamic LDS the device keeps
+// resident at once (the dynamic-LDS attribute must be set first).
+template <typename T, int NT> int persist_resident_nt(const ddlr_prec* h, const PersistData& PD) {
+    int occ = 0, cus = 0;
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)k_pcg_persist<T, NT>, NT, PD.lds_bytes));
+    HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device));
+    return occ * cus;
+}
+
 template <typename T, int NT>
 void persist_launch_nt(ddlr_prec* h, PersistData& PD, int nl, double tol2, int maxit, hipStream_t st) {
     const DevFactors<T>& F = factors<T>(h);
@@ -3407,12 +3524,22 @@ void persist_launch_nt(ddlr_prec* h, PersistData& PD, int nl, double tol2, int m
     const T* U = F.U;
     const int ustride = std::max(1, h->k);
     const double* dco = multi ? h->dvecs : h->dvec;
+    if (PD.ngroups > 0) {
+        // every member of a group must be resident together: the grid may not
+        // exceed what the device holds at once
+        if (nl > persist_resident_nt<T, NT>(h, PD))
+            throw SetupError{DDLR_E_INVALID, "grouped persistent launch larger than the resident workgroups"};
+        const int64_t nc = (int64_t)PD.ngroups * 64;
+        hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, st, nc, PD.gctr);
+        LAUNCHCHK();
+    }
     auto kern = k_pcg_persist<T, NT>;
     hipLaunchKernelGGL(kern, dim3(nl), dim3(NT), PD.lds_bytes, st, PD.sys, PD.lanes, PD.arp, PD.aci, PD.av, PD.meta,
                        PD.mrow, PD.fcol, (const T*)PD.fval, PD.bcol, (const T*)PD.bval, (const T*)PD.dq, h->erp,
                        h->eci, F.ev, h->etrp,
                        h->etci, F.etv, U, ustride, dco, PD.b, W.x, W.r, PD.p, W.q, W.z, (T*)W.a1, (T*)W.a2, (T*)W.ys,
-                       (T*)W.ws, h->ndev, h->sdev, PD.meta_off, tol2, maxit, PD.res);
+                       (T*)W.ws, h->ndev, h->sdev, PD.meta_off, tol2, maxit, PD.res, PD.gctr, PD.gpart, PD.gxcc,
+                       PD.gslow);
     LAUNCHCHK();
 }
 
@@ -3462,6 +3589,19 @@ template <typename T> void persist_launch_T(ddlr_prec* h, PersistData& PD, int n
     }
 }
 
+// persist_resident_nt for the preconditioner's type and nt threads
+int persist_resident(ddlr_prec* h, const PersistData& PD, int nt) {
+    persist_lds_attr(h, PD, nt);
+    const bool f64 = h->precision == DDLR_FP64;
+    switch (nt) {
+    case 64: return f64 ? persist_resident_nt<double, 64>(h, PD) : persist_resident_nt<float, 64>(h, PD);
+    case 128: return f64 ? persist_resident_nt<double, 128>(h, PD) : persist_resident_nt<float, 128>(h, PD);
+    case 256: return f64 ? persist_resident_nt<double, 256>(h, PD) : persist_resident_nt<float, 256>(h, PD);
+    case 512: return f64 ? persist_resident_nt<double, 512>(h, PD) : persist_resident_nt<float, 512>(h, PD);
+    default: return f64 ? persist_resident_nt<double, 1024>(h, PD) : persist_resident_nt<float, 1024>(h, PD);
+    }
+}
+
 void persist_launch(ddlr_prec* h, PersistData& PD, int nl, double tol2, int maxit, hipStream_t st, int nt) {
     if (!h->capturing) persist_lds_attr(h, PD, nt);
     if (h->precision == DDLR_FP64) persist_launch_T<double>(h, PD, nl, tol2, maxit, st, nt);
@@ -3488,6 +3628,8 @@ void persist_tune(ddlr_prec* h, PersistData& PD, int nl, double tol2, int maxit,
     float best = 1e30f;
     std::vector<PRes> r(nl);
     for (int c = 0; c < 5; ++c) {
+        PD.nt_us[c] = 0.f;
+        if (PD.ngroups > 0 && nl > persist_resident(h, PD, cand[c])) continue;  // groups would not be resident
         HIPCHK(hipEventRecord(e0, st));
         persist_launch(h, PD, nl, tol2, trial, st, cand[c]);
         HIPCHK(hipEventRecord(e1, st));
@@ -3496,7 +3638,10 @@ void persist_tune(ddlr_prec* h, PersistData& PD, int nl, double tol2, int maxit,
         HIPCHK(hipEventElapsedTime(&ms, e0, e1));
         HIPCHK(hipMemcpy(r.data(), PD.res, nl * sizeof(PRes), hipMemcpyDeviceToHost));
         int its = 1;
-        for (const PRes& x : r) its = std::max(its, x.its);
+        if (PD.sys_lane.empty())
+            for (const PRes& x : r) its = std::max(its, x.its);
+        else
+            for (int l : PD.sys_lane) its = std::max(its, r[l].its);
         PD.nt_us[c] = 1e3f * ms / (float)its;
         if (PD.nt_us[c] < best) {
             best = PD.nt_us[c];
@@ -3505,6 +3650,77 @@ void persist_tune(ddlr_prec* h, PersistData& PD, int nl, double tol2, int maxit,
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    if (PD.nt == 0) throw SetupError{DDLR_E_INVALID, "no workgroup size keeps the grouped launch resident"};
+}
+
+// Workgroups per system of a persistent batch.  The batch takes as long as its
+// slowest system, so the system with the largest estimated solve time gets
+// more members while that lowers its estimate and the lanes fit `slots`.
+// Estimate: iterations ~ sqrt(n) (these stencils' condition numbers grow with
+// the grid side); per iteration four sweeps over the deepest member's merged
+// levels (0.25 us a level with its solve vector in LDS, 2.5 us in global
+// memory, as measured with one workgroup per system), 15 ns per row of the
+// largest member, and six group barriers of 3 us when G > 1.  Only the ratios
+// matter.  Systems start at the fewest members whose solve vectors fit LDS.
+std::vector<int> choose_groups(const std::vector<const HostPlan*>& plans, size_t tsz, size_t lds_cap, int slots) {
+    const int ns = (int)plans.size();
+    std::vector<int> G(ns, 1);
+    auto est = [&](int q, int g) {
+        const HostPlan& P = *plans[q];
+        const std::vector<int32_t> cut = member_blocks(P, g);
+        double worst = 0.0;
+        for (int u = 0; u < g; ++u) {
+            const int64_t rows = P.boff[cut[u + 1]] - P.boff[cut[u]];
+            int depth = 0;
+            for (int32_t b = cut[u]; b < cut[u + 1]; ++b) depth = std::max(depth, P.blk_lvl[b + 1] - P.blk_lvl[b]);
+            const double lev = (size_t)rows * tsz <= lds_cap ? 0.25 : 2.5;
+            worst = std::max(worst, 4.0 * depth * lev + 0.015 * (double)rows);
+        }
+        if (g > 1) worst += 6 * 3.0;
+        return std::sqrt((double)P.n) * worst;
+    };
+    int total = ns;
+    if (total >= slots) return G;
+    // the fewest members that bring every member's solve vector into LDS
+    for (int q = 0; q < ns; ++q) {
+        const HostPlan& P = *plans[q];
+        const int gmax = std::min((int)P.p, kGroupMax);
+        for (int g = 1; g <= gmax; ++g) {
+            const std::vector<int32_t> cut = member_blocks(P, g);
+            int64_t big = 0;
+            for (int u = 0; u < g; ++u) big = std::max(big, P.boff[cut[u + 1]] - P.boff[cut[u]]);
+            if ((size_t)big * tsz <= lds_cap || g == gmax) {
+                if ((size_t)big * tsz <= lds_cap && est(q, g) < est(q, G[q])) {
+                    total += g - G[q];
+                    G[q] = g;
+                }
+                break;
+            }
+        }
+    }
+    if (total > slots) return std::vector<int>(ns, 1);
+    std::priority_queue<std::pair<double, int>> pq;
+    for (int q = 0; q < ns; ++q) pq.push({est(q, 1), q});
+    while (!pq.empty() && total < slots) {
+        const auto [e, q] = pq.top();
+        pq.pop();
+        const int gmax = std::min({(int)plans[q]->p, kGroupMax, G[q] + (slots - total)});
+        int best = 0;
+        double eb = e;
+        for (int g = G[q] + 1; g <= std::min(gmax, G[q] + 4); ++g) {
+            const double e2 = est(q, g);
+            if (e2 < 0.98 * eb) {
+                eb = e2;
+                best = g;
+                break;  // the smallest step that helps
+            }
+        }
+        if (!best) break;  // the slowest system cannot be made faster
+        total += best - G[q];
+        G[q] = best;
+        pq.push({eb, q});
+    }
+    return G;
 }
 
 // Whether a handle may solve with the persistent form: CG, DDLR-1 or A0 only,
@@ -4561,12 +4777,39 @@ ddlr_status ddlr_batch_create(int32_t nsys, ddlr_prec* const* members, ddlr_batc
                 ks[q] = h->variant == DDLR_1 ? members[q]->k : 0;
                 c0v[q] = members[q]->c0;
             }
+            // large systems get several workgroups (groups) when the lanes fit
+            // the device at two 512-thread workgroups per CU: the dynamic LDS is
+            // then capped at 76 KB; DDLR_BATCH_GROUP=0 keeps one workgroup per
+            // system, =N asks for N per system
+            const size_t tsz = h->precision == DDLR_FP64 ? sizeof(double) : sizeof(float);
+            const size_t cap2 = 76 * 1024;
+            int cus = 0, nxcd = 1;
+            HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device));
+            hipDeviceProp_t prop;
+            HIPCHK(hipGetDeviceProperties(&prop, h->device));
+            if (std::strstr(prop.gcnArchName, "gfx950") || std::strstr(prop.gcnArchName, "gfx942")) nxcd = 8;
+            std::vector<int> groups;
+            const char* ge = std::getenv("DDLR_BATCH_GROUP");
+            if (ge && std::atoi(ge) > 0) groups.assign(nsys, std::atoi(ge));
+            else if (!(ge && ge[0] == '0')) groups = choose_groups(plans, tsz, cap2, 2 * cus);
+            bool grouped = false;
+            for (int g : groups) grouped = grouped || g > 1;
             B->pers.reset(new PersistData());
-            persist_build(*B->pers, plans, B->roff, B->soff, ks, c0v, std::max(1, h->k),
-                          h->precision == DDLR_FP64 ? sizeof(double) : sizeof(float), h->device);
-            std::vector<PLane> lanes(nsys);
-            for (int q = 0; q < nsys; ++q) lanes[q] = PLane{q, 0};
-            persist_lanes(*B->pers, lanes, 1, h->ndev);
+            if (grouped) {
+                persist_build(*B->pers, plans, B->roff, B->soff, ks, c0v, std::max(1, h->k), tsz, h->device, groups,
+                              cap2);
+                persist_batch_lanes(*B->pers, h->ndev, nxcd);
+                PersistData& PD = *B->pers;
+                if (PD.grid > std::max(persist_resident(h, PD, 256), persist_resident(h, PD, 512))) {
+                    B->pers.reset(new PersistData());  // does not fit: one workgroup per system
+                    grouped = false;
+                }
+            }
+            if (!grouped) {
+                persist_build(*B->pers, plans, B->roff, B->soff, ks, c0v, std::max(1, h->k), tsz, h->device);
+                persist_batch_lanes(*B->pers, h->ndev, nxcd);
+            }
+            if (const char* gs = std::getenv("DDLR_GROUP_SLOW")) B->pers->gslow = gs[0] == '1';
         }
         HIPCHK(hipStreamCreateWithFlags(&B->own, hipStreamNonBlocking));  // default priority
         HIPCHK(hipEventCreateWithFlags(&B->ev_in, hipEventDisableTiming));
@@ -4602,6 +4845,15 @@ ddlr_status ddlr_batch_tuning(const ddlr_batch* B, int32_t* persistent, int32_t*
     *persistent = B->pers ? 1 : 0;
     *threads = B->pers ? B->pers->nt : 0;
     for (int c = 0; c < 5; ++c) us_per_iter[c] = B->pers ? B->pers->nt_us[c] : 0.f;
+    return DDLR_OK;
+}
+
+ddlr_status ddlr_batch_members(const ddlr_batch* B, int32_t* members) {
+    if (!B || !members) {
+        g_err = "null argument";
+        return DDLR_E_INVALID;
+    }
+    for (int q = 0; q < B->nsys; ++q) members[q] = B->pers ? B->pers->members[q] : 0;
     return DDLR_OK;
 }
 
@@ -4648,7 +4900,7 @@ ddlr_status ddlr_batch_solve(ddlr_batch* B, const double* b, double* x, const dd
             hipLaunchKernelGGL((k_gather<double, double>), dim3(grid_for(n)), dim3(256), 0, st, n, 1, h->perm_dev, b,
                                n, PD.b, n);
             LAUNCHCHK();
-            if (PD.nt == 0) persist_tune(h, PD, ns, tol2, o.maxit, st);
+            if (PD.nt == 0) persist_tune(h, PD, PD.grid, tol2, o.maxit, st);
             if (!B->pgexec || B->pg_tol2 != tol2 || B->pg_maxit != o.maxit || B->pg_nt != PD.nt) {
                 if (B->pgexec) (void)hipGraphExecDestroy(B->pgexec);
                 if (B->pgraph) (void)hipGraphDestroy(B->pgraph);
@@ -4657,7 +4909,7 @@ ddlr_status ddlr_batch_solve(ddlr_batch* B, const double* b, double* x, const dd
                 persist_lds_attr(h, PD, PD.nt);
                 h->capturing = true;
                 HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-                persist_launch(h, PD, ns, tol2, o.maxit, st, PD.nt);
+                persist_launch(h, PD, PD.grid, tol2, o.maxit, st, PD.nt);
                 hipGraph_t g = nullptr;
                 const hipError_t ec = hipStreamEndCapture(st, &g);
                 h->capturing = false;
@@ -4672,18 +4924,25 @@ ddlr_status ddlr_batch_solve(ddlr_batch* B, const double* b, double* x, const dd
             hipLaunchKernelGGL((k_scatter<double, double>), dim3(grid_for(n)), dim3(256), 0, st, n, 1, h->perm_dev,
                                h->ws.x, n, x, n);
             LAUNCHCHK();
-            std::vector<PRes> r(ns);
-            HIPCHK(hipMemcpyAsync(r.data(), PD.res, ns * sizeof(PRes), hipMemcpyDeviceToHost, st));
+            std::vector<PRes> rl(PD.grid);
+            HIPCHK(hipMemcpyAsync(rl.data(), PD.res, PD.grid * sizeof(PRes), hipMemcpyDeviceToHost, st));
             HIPCHK(hipStreamSynchronize(st));
             HIPCHK(hipEventRecord(B->ev_out, st));
             HIPCHK(hipStreamWaitEvent(ust, B->ev_out, 0));
+            bool gave_up = false;
             for (int q = 0; q < ns; ++q) {
+                const PRes& r = rl[PD.sys_lane[q]];
                 ddlr_solve_info& inf = info[q];
-                inf.iters = r[q].its;
-                inf.status = r[q].status == 0 ? DDLR_OK : DDLR_E_NO_CONVERGENCE;
-                inf.relres = r[q].bb > 0 ? std::sqrt(r[q].rr / r[q].bb) : 0.0;
-                inf.relres_true = r[q].bb > 0 ? std::sqrt(r[q].rtrue / r[q].bb) : 0.0;
-                if (r[q].status) result = DDLR_E_NO_CONVERGENCE;
+                inf.iters = r.its;
+                inf.status = r.status == 0 ? DDLR_OK : DDLR_E_NO_CONVERGENCE;
+                inf.relres = r.bb > 0 ? std::sqrt(r.rr / r.bb) : 0.0;
+                inf.relres_true = r.bb > 0 ? std::sqrt(r.rtrue / r.bb) : 0.0;
+                if (r.status) result = DDLR_E_NO_CONVERGENCE;
+                if (r.status == 2) gave_up = true;
+            }
+            if (gave_up) {
+                g_err = "a group barrier of the persistent batch gave up waiting";
+                return DDLR_E_DEVICE;
             }
         } catch (const SetupError& e) {
             h->capturing = false;

@@ -28,16 +28,24 @@
 
 namespace ddlr {
 
+// One workgroup's share of a system.  A system is solved by G >= 1 workgroups
+// (a group); member g owns a contiguous range of the system's blocks and
+// their rows r0 + o0 .. r0 + o1 - 1, the last member also the interface block
+// (whose rows come last).  G = 1: the whole system, o0 = 0, o1 = n.
 struct PSys {
     int64_t r0;      // first device row of the system
     int64_t s0;      // first interface position (rows of U_k, y, w)
     int64_t d0;      // offset of d_1..d_k in the coefficient array
     int32_t n, m;    // rows; interior rows (the interface rows follow)
     int32_t s, k;    // interface rows; rank of the correction (0: A0 alone)
-    int32_t l0, l1;  // merged levels l0..l1-1 (level metadata meta[j], row lists in mrow)
-    int32_t lds;     // 1: the solve vector fits the dynamic LDS
+    int32_t l0, l1;  // the member's merged levels l0..l1-1 (metadata meta[j], row lists in mrow)
+    int32_t lds;     // 1: the member's solve vector fits the dynamic LDS
     int32_t pad;
     double c0;       // eq. (gkt): G^{-1} = c0 I + U_k diag(d) U_k^T
+    int32_t o0, o1;  // the member's rows, as offsets from r0
+    int32_t G, g;    // members of the group; this member's index
+    int32_t grp;     // group index (barrier counters and partial sums; -1 when G = 1)
+    int32_t pad2;
 };
 
 struct PLane {
@@ -52,6 +60,7 @@ struct PRes {
 };
 
 constexpr int kPersistMaxK = 64;  // rank bound of the persistent form
+constexpr int kGroupMax = 32;     // members of a group at most
 
 // Sum over the workgroup, the same value in every thread.  `red` holds NT/64
 // doubles of LDS; the barriers at entry and exit let consecutive calls reuse it.
@@ -303,6 +312,329 @@ __device__ __forceinline__ void wg_apply(const PSys& S, const int4* __restrict__
     __syncthreads();
 }
 
+
+// ------------------------------------------------ groups of workgroups
+//
+// A large system is shared by the G workgroups of a group (its blocks are
+// independent in the A0 solve, so each member sweeps its own blocks' merged
+// levels); dot products, the interface step of the correction and the
+// exchange of p and z1 need the group to meet.  A launch holds at most as
+// many workgroups as the device keeps resident (the host checks), so every
+// member of a group runs at once.
+//
+// Barrier: every thread waits until its stores are acknowledged by the L2 of
+// its XCD; one wave announces the arrival and waits for the group, then
+// invalidates the CU's L1 (and non-coherent L2 lines) before the members read
+// each other's data.
+//   slow form (any placement): that wave first writes the XCD's L2 back to
+//     memory; arrival is a device-scope atomic, polled with device-scope loads;
+//   fast form (every member on one XCD, checked once at start): the L2 is
+//     shared, so no write-back; arrival and polling are L2 atomics.
+// A wait gives up after kSpinMax polls and the lane reports failure (status
+// 2): no member waits without bound.  Values other members wrote are read
+// with lane-dependent addresses (vector loads through the invalidated L1),
+// never through the scalar cache.
+
+constexpr unsigned kSpinMax = 1u << 22;
+
+__global__ void k_zero_u32(int64_t n, unsigned* __restrict__ p) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+__device__ __forceinline__ int xcc_id() {
+    unsigned v;
+    asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(v));
+    return (int)(v & 0xf);
+}
+
+// A group member's barrier state, in LDS (thread 0 updates it).
+struct GroupLds {
+    int flag;         // 1 once a wait of this workgroup gave up
+    int fast;         // 1: the fast form (decided once, the same in every member)
+    unsigned n_slow;  // arrivals counted by the last barrier of each form
+    unsigned n_fast;
+};
+
+// ctr: the group's 64 counters (slow form at 0, fast form at 32, zero at launch).
+__device__ __forceinline__ bool group_barrier(unsigned* ctr, int G, GroupLds* gl) {
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        const bool fast = gl->fast != 0;
+        if (!fast) asm volatile("buffer_wbl2 sc1\n\ts_waitcnt vmcnt(0)" ::: "memory");
+        if (threadIdx.x == 0) {
+            unsigned* c = fast ? ctr + 32 : ctr;
+            const unsigned target = fast ? (gl->n_fast += (unsigned)G) : (gl->n_slow += (unsigned)G);
+            if (fast) __hip_atomic_fetch_add(c, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            else asm volatile("global_atomic_add %0, %1, off sc1\n\ts_waitcnt vmcnt(0)" ::"v"(c), "v"(1u) : "memory");
+            unsigned spins = 0;
+            for (;;) {
+                unsigned v;
+                if (fast) {
+                    v = 0u;  // compare-and-swap 0 -> 0: an L2 read of the counter that changes nothing
+                    __hip_atomic_compare_exchange_strong(c, &v, 0u, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_WORKGROUP);
+                } else {
+                    v = __hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+                if (v >= target) break;
+                __builtin_amdgcn_s_sleep(2);
+                if (++spins > kSpinMax) {
+                    gl->flag = 1;
+                    break;
+                }
+            }
+        }
+        asm volatile("buffer_inv sc1" ::: "memory");
+    }
+    __syncthreads();
+    return gl->flag == 0;
+}
+
+// The G values slots[0..G) (written by the members before a barrier), added
+// in member order; the same total in every thread.
+__device__ __forceinline__ double group_add(const double* slots, int G) {
+    const int ln = (int)(threadIdx.x & 63);
+    const double mine = ln < G ? slots[ln] : 0.0;
+    double s = 0.0;
+    for (int u = 0; u < G; ++u) s += __shfl(mine, u);
+    return s;
+}
+
+// Sum over the group of every thread's v: the workgroup's sum into slot g,
+// a barrier, then the slots in member order (0 if the wait gave up: the
+// caller checks gl->flag).
+template <int NT>
+__device__ __forceinline__ double group_sum(double v, double* red, double* slots, unsigned* ctr, int G, int g,
+                                            GroupLds* gl) {
+    const double mine = wg_sum<NT>(v, red);
+    if (threadIdx.x == 0) slots[g] = mine;
+    if (!group_barrier(ctr, G, gl)) return 0.0;
+    return group_add(slots, G);
+}
+
+// z = M^{-1} r on the member's rows (see wg_apply; here the first solve's
+// result z1 is also written to tg for the interface member, which forms y,
+// the coefficients and w alone between two barriers).  R0: the member's
+// first row (the solve vector's offset in LDS).  Returns false if a wait gave
+// up.
+template <typename T, int NT, bool kLds>
+__device__ __forceinline__ bool member_apply(const PSys& S, int64_t R0, unsigned* ctr, GroupLds* gl,
+                                             const int4* __restrict__ meta,
+                             const int32_t* __restrict__ mrow, const int32_t* __restrict__ fcol,
+                             const T* __restrict__ fval, const int32_t* __restrict__ bcol, const T* __restrict__ bval,
+                             const T* __restrict__ dq, const int32_t* __restrict__ erp, const int32_t* __restrict__ eci,
+                             const T* __restrict__ ev, const int32_t* __restrict__ etrp,
+                             const int32_t* __restrict__ etci, const T* __restrict__ etv, const T* __restrict__ U,
+                             int ustride, const double* __restrict__ dcoef, const double* r, double* z, T* tg, T* tq,
+                             T* y, T* w, T* lvec, double* red, double* coef) {
+    T* vec = kLds ? lvec : tg;
+    const int64_t R1 = S.r0 + S.o1;
+    const int64_t off = kLds ? R0 : 0;
+    const int q0 = meta[S.l0].x, q1 = meta[S.l1].x;
+#pragma unroll 4
+    for (int q = q0 + (int)threadIdx.x; q < q1; q += NT) tq[q] = (T)r[mrow[q]];
+    __syncthreads();
+    plev_sweep<T, NT, false, kLds>(S.l0, S.l1, off, meta, mrow, fcol, fval, tq, vec);
+    plev_sweep<T, NT, true, kLds>(S.l0, S.l1, off, meta, mrow, bcol, bval, dq, vec);
+    if constexpr (kLds) __syncthreads();
+    if (S.k > 0) {
+        if constexpr (kLds) {
+#pragma unroll 4
+            for (int64_t i = R0 + threadIdx.x; i < R1; i += NT) tg[i] = vec[i - R0];
+        }
+        if (!group_barrier(ctr, S.G, gl)) return false;
+        if (S.g == S.G - 1) {
+            const int64_t s0 = S.s0, s1 = S.s0 + S.s;
+#pragma unroll 4
+            for (int64_t jg = s0 + threadIdx.x; jg < s1; jg += NT) {
+                T acc = T(0);
+                const int t1 = etrp[jg + 1];
+                for (int t = etrp[jg]; t < t1; ++t) acc = fnms(acc, -etv[t], tg[etci[t]]);
+                y[jg] = acc;
+            }
+            __syncthreads();
+            constexpr int NW = NT / 64;
+            for (int j0 = 0; j0 < S.k; j0 += 16) {
+                double acc[16];
+#pragma unroll
+                for (int u = 0; u < 16; ++u) acc[u] = 0.0;
+#pragma unroll 4
+                for (int64_t ig = s0 + threadIdx.x; ig < s1; ig += NT) {
+                    const double yi = (double)y[ig];
+                    const T* Ui = U + ig * ustride + j0;
+#pragma unroll
+                    for (int u = 0; u < 16; ++u)
+                        if (j0 + u < S.k) acc[u] += (double)Ui[u] * yi;
+                }
+#pragma unroll
+                for (int u = 0; u < 16; ++u) {
+                    const double v = wave_sum(acc[u]);
+                    if ((threadIdx.x & 63) == 0) red[(threadIdx.x >> 6) * 16 + u] = v;
+                }
+                __syncthreads();
+                if ((int)threadIdx.x < 16 && j0 + (int)threadIdx.x < S.k) {
+                    double sum = 0.0;
+                    for (int wv = 0; wv < NW; ++wv) sum += red[wv * 16 + threadIdx.x];
+                    coef[j0 + threadIdx.x] = dcoef[S.d0 + j0 + threadIdx.x] * sum;
+                }
+                __syncthreads();
+            }
+#pragma unroll 4
+            for (int64_t ig = s0 + threadIdx.x; ig < s1; ig += NT) {
+                double acc = S.c0 * (double)y[ig];
+                const T* Ui = U + ig * ustride;
+                for (int j = 0; j < S.k; ++j) acc += (double)Ui[j] * coef[j];
+                w[ig] = (T)acc;
+            }
+        }
+        if (!group_barrier(ctr, S.G, gl)) return false;
+#pragma unroll 4
+        for (int q = q0 + (int)threadIdx.x; q < q1; q += NT) {
+            const int i = mrow[q];
+            T acc = (T)r[i];
+            const int t1 = erp[i + 1];
+            for (int t = erp[i]; t < t1; ++t) acc = fnms(acc, -ev[t], w[eci[t]]);
+            tq[q] = acc;
+        }
+        __syncthreads();
+        plev_sweep<T, NT, false, kLds>(S.l0, S.l1, off, meta, mrow, fcol, fval, tq, vec);
+        plev_sweep<T, NT, true, kLds>(S.l0, S.l1, off, meta, mrow, bcol, bval, dq, vec);
+        if constexpr (kLds) __syncthreads();
+    }
+#pragma unroll 4
+    for (int64_t i = R0 + threadIdx.x; i < R1; i += NT) z[i] = (double)vec[i - off];
+    __syncthreads();
+    return true;
+}
+
+// The PCG of k_pcg_persist for one member of a group (S.G > 1): the same
+// steps on the member's rows, every scalar summed over the group.
+template <typename T, int NT>
+__device__ __forceinline__ void member_pcg(const PSys& S, const int64_t* __restrict__ arp, const int32_t* __restrict__ aci,
+                           const double* __restrict__ av, const int4* meta, const int32_t* __restrict__ mrow,
+                           const int32_t* __restrict__ fcol, const T* __restrict__ fval,
+                           const int32_t* __restrict__ bcol, const T* __restrict__ bval, const T* __restrict__ dq,
+                           const int32_t* __restrict__ erp, const int32_t* __restrict__ eci, const T* __restrict__ ev,
+                           const int32_t* __restrict__ etrp, const int32_t* __restrict__ etci,
+                           const T* __restrict__ etv, const T* __restrict__ U, int ustride,
+                           const double* __restrict__ dcoef, const double* b, double* x, double* r, double* p,
+                           double* q, double* z, T* tg, T* tq, T* yv, T* wv, T* lvec, double* red, double* coef,
+                           unsigned* gctr, double* gpart, int* gxcc, int gslow, double tol2, int maxit, PRes* res,
+                           GroupLds* gl) {
+    const int G = S.G, g = S.g;
+    unsigned* ctr = gctr + (size_t)S.grp * 64;
+    double* slots = gpart + (size_t)S.grp * 4 * kGroupMax;
+    int* xs = gxcc + (size_t)S.grp * kGroupMax;
+    const int64_t R0 = S.r0 + S.o0, R1 = S.r0 + S.o1;
+    if (threadIdx.x == 0) {
+        gl->flag = 0;
+        gl->fast = 0;
+        gl->n_slow = 0u;
+        gl->n_fast = 0u;
+        xs[g] = xcc_id();
+    }
+    __syncthreads();
+    int its = 0;
+    double rr = 0.0, bb = 0.0;
+    // placement: the fast barrier only when every member runs on one XCD
+    if (group_barrier(ctr, G, gl)) {
+        const int ln = (int)(threadIdx.x & 63);
+        const int mine = ln < G ? xs[ln] : -1;
+        const int x0 = __shfl(mine, 0);
+        bool same = true;
+        for (int u = 1; u < G; ++u) same = same && __shfl(mine, u) == x0;
+        __syncthreads();
+        if (threadIdx.x == 0) gl->fast = same && !gslow;
+        if (S.lds) {
+            for (int i = threadIdx.x; i < S.o1 - S.o0; i += NT) lvec[i] = T(0);
+        } else {
+#pragma unroll 4
+            for (int64_t i = R0 + threadIdx.x; i < R1; i += NT) tg[i] = T(0);
+        }
+        double acc = 0.0;
+#pragma unroll 4
+        for (int64_t i = R0 + threadIdx.x; i < R1; i += NT) {
+            const double bi = b[i];
+            x[i] = 0.0;
+            r[i] = bi;
+            acc += bi * bi;
+        }
+        bb = group_sum<NT>(acc, red, slots, ctr, G, g, gl);
+        rr = bb;
+    }
+    double rz = 0.0;
+    while (gl->flag == 0 && bb > 0.0) {
+        bool ok;
+        if (S.lds)
+            ok = member_apply<T, NT, true>(S, R0, ctr, gl, meta, mrow, fcol, fval, bcol, bval, dq, erp, eci, ev, etrp,
+                                           etci, etv, U, ustride, dcoef, r, z, tg, tq, yv, wv, lvec, red, coef);
+        else
+            ok = member_apply<T, NT, false>(S, R0, ctr, gl, meta, mrow, fcol, fval, bcol, bval, dq, erp, eci, ev,
+                                            etrp, etci, etv, U, ustride, dcoef, r, z, tg, tq, yv, wv, lvec, red, coef);
+        if (!ok) break;
+        double acc = 0.0;
+#pragma unroll 4
+        for (int64_t i = R0 + threadIdx.x; i < R1; i += NT) acc += r[i] * z[i];
+        const double rzn = group_sum<NT>(acc, red, slots + kGroupMax, ctr, G, g, gl);
+        if (gl->flag) break;
+        const double beta = its == 0 ? 0.0 : rzn / rz;
+        rz = rzn;
+#pragma unroll 4
+        for (int64_t i = R0 + threadIdx.x; i < R1; i += NT) p[i] = its == 0 ? z[i] : z[i] + beta * p[i];
+        if (!group_barrier(ctr, G, gl)) break;  // q = A p reads the other members' p
+        ++its;
+        acc = 0.0;
+#pragma unroll 4
+        for (int64_t i = R0 + threadIdx.x; i < R1; i += NT) {
+            double s = 0.0;
+            const int64_t t1 = arp[i + 1];
+            for (int64_t t = arp[i]; t < t1; ++t) s += av[t] * p[aci[t]];
+            q[i] = s;
+            acc += p[i] * s;
+        }
+        const double pq = group_sum<NT>(acc, red, slots + 2 * kGroupMax, ctr, G, g, gl);
+        if (gl->flag) break;
+        const double alpha = rz / pq;
+        acc = 0.0;
+#pragma unroll 4
+        for (int64_t i = R0 + threadIdx.x; i < R1; i += NT) {
+            x[i] += alpha * p[i];
+            const double ri = r[i] - alpha * q[i];
+            r[i] = ri;
+            acc += ri * ri;
+        }
+        rr = group_sum<NT>(acc, red, slots + 3 * kGroupMax, ctr, G, g, gl);
+        if (gl->flag) break;
+        if (rr <= tol2 * bb || its >= maxit) break;
+    }
+    // true residual ||b - A x|| (A x reads the other members' x)
+    double rt = 0.0;
+    if (gl->flag == 0 && group_barrier(ctr, G, gl)) {
+        double acc = 0.0;
+#pragma unroll 4
+        for (int64_t i = R0 + threadIdx.x; i < R1; i += NT) {
+            double s = 0.0;
+            const int64_t t1 = arp[i + 1];
+            for (int64_t t = arp[i]; t < t1; ++t) s += av[t] * x[aci[t]];
+            const double d = b[i] - s;
+            acc += d * d;
+        }
+        rt = group_sum<NT>(acc, red, slots, ctr, G, g, gl);
+    }
+    const bool ok = gl->flag == 0;
+    if (threadIdx.x == 0) {
+        PRes o;
+        o.its = its;
+        o.status = !ok ? 2 : (bb == 0.0 || rr <= tol2 * bb) ? 0 : 1;
+        o.rr = rr;
+        o.bb = bb;
+        o.rtrue = rt;
+        res[blockIdx.x] = o;
+    }
+}
+
 // One workgroup per lane.  Vectors are double, device order, lane column at
 // col * ld: b (right-hand side), x (written), r, p, q, z (work).  T buffers tg
 // (n per column, ld), y and w (interface, lds per column).  tol2 = rtol^2.
@@ -317,11 +649,14 @@ __global__ __launch_bounds__(NT) void k_pcg_persist(
     const int32_t* __restrict__ etci, const T* __restrict__ etv, const T* __restrict__ U, int ustride,
     const double* __restrict__ dcoef, const double* __restrict__ b, double* __restrict__ x, double* __restrict__ r,
     double* __restrict__ p, double* __restrict__ q, double* __restrict__ z, T* tg, T* tq,
-    T* yv, T* wv, int64_t ld, int64_t lds_s, int meta_off, double tol2, int maxit, PRes* __restrict__ res) {
+    T* yv, T* wv, int64_t ld, int64_t lds_s, int meta_off, double tol2, int maxit, PRes* __restrict__ res,
+    unsigned* gctr, double* gpart, int* gxcc, int gslow) {
     extern __shared__ __attribute__((aligned(16))) unsigned char persist_lds[];
     __shared__ double red[(NT / 64) * 16];
     __shared__ double coef[kPersistMaxK];
+    __shared__ GroupLds glds;
     const PLane L = lanes[blockIdx.x];
+    if (L.sys < 0) return;  // an idle slot of the launch grid
     PSys S = sys[L.sys];
     const int64_t c = L.col;
     b += c * ld, x += c * ld, r += c * ld, p += c * ld, q += c * ld, z += c * ld, tg += c * ld, tq += c * ld;
@@ -334,6 +669,12 @@ __global__ __launch_bounds__(NT) void k_pcg_persist(
     meta = smeta;
     S.l1 -= S.l0;
     S.l0 = 0;
+    if (S.G > 1) {
+        member_pcg<T, NT>(S, arp, aci, av, meta, mrow, fcol, fval, bcol, bval, dq, erp, eci, ev, etrp, etci, etv, U,
+                          ustride, dcoef, b, x, r, p, q, z, tg, tq, yv, wv, lvec, red, coef, gctr, gpart, gxcc, gslow,
+                          tol2, maxit, res, &glds);
+        return;
+    }
     const int64_t r0 = S.r0, r1 = S.r0 + S.n;
     // the solve vector starts at zero (padded ELL terms read it with weight 0)
     if (S.lds) {

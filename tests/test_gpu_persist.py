@@ -175,3 +175,70 @@ def test_persistent_batch_matches_oracle(prec):
     t = D.ddlr_batch_tuning(B)
     say("batch tuning", t)
     assert t["persistent"] == 1 and t["threads"] in (64, 128, 256, 512, 1024)
+
+
+@pytest.mark.parametrize("prec,variant,form", [(D.FP64, 1, "fast"), (D.FP64, 1, "slow"), (D.FP64, 1, "global"),
+                                               (D.FP64, 0, "fast"), (D.FP32, 1, "fast"), (D.FP32, 1, "global")])
+def test_grouped_batch_matches_oracle(prec, variant, form):
+    """Systems split over several workgroups (DDLR_BATCH_GROUP=3: min(3, p)
+    members each), with the fast barriers (members on one XCD), the slow ones
+    (forced), and the members' solve vectors in global memory: the 6-step
+    iterate matches the oracle's (FP64, 1e-10), full solves take the oracle's
+    iteration count (FP64 +-1; FP32 the mixed bar) with true residual <= 1e-6."""
+    mem = batch_members(7, prec, seed=5)
+    say("grouped batch", prec, variant, form)
+    k, m = 4, 10
+    hs = [D.ddlr_setup(A, part, p, k, variant, lanczos_steps=m, lanczos_start=w.lanczos_start(A.n, 5),
+                       precision=prec) for A, part, p in mem]
+    orcs = []
+    for (A, part, p) in mem:
+        o = Oracle(A, part, p)
+        if variant == 1:
+            o = o.lowrank(1, k, m, w.lanczos_start(A.n, 5))
+        orcs.append(o)
+    if prec == D.FP64 and variant == 1:
+        for h, o in zip(hs, orcs):
+            D.ddlr_set_lowrank(h, 1, *o.get_lowrank())
+    env = {"DDLR_BATCH_GROUP": "3"}
+    if form == "slow":
+        env["DDLR_GROUP_SLOW"] = "1"
+    if form == "global":
+        env["DDLR_PERSIST_NO_LDS"] = "1"
+    os.environ.update(env)
+    try:
+        B = D.ddlr_batch_create(hs)
+    finally:
+        for key in env:
+            os.environ.pop(key, None)
+    counts = D.ddlr_batch_members(B)
+    say("members", counts)
+    assert counts == [min(3, p) for _, _, p in mem]
+    bs = [w.rhs_from_solution(A, q, 1)[0][:, 0] for q, (A, _, _) in enumerate(mem)]
+    bt = torch.from_numpy(np.concatenate(bs)).to(DEV)
+    off = B.offsets
+    if prec == D.FP64:
+        x = torch.zeros_like(bt)
+        st, info = D.ddlr_batch_solve(B, bt, x, maxit=6)
+        assert st == D.E_NO_CONVERGENCE and all(i["iters"] == 6 for i in info)
+        xs = x.cpu().numpy()
+        for q, o in enumerate(orcs):
+            xo6, _ = o.pcg(bs[q], maxit=6)
+            assert_close(xs[off[q]:off[q + 1]], xo6, 1e-10, f"system {q} 6-step iterate")
+    x = torch.zeros_like(bt)
+    st, info = D.ddlr_batch_solve(B, bt, x)
+    assert st == D.OK
+    xs = x.cpu().numpy()
+    for q, o in enumerate(orcs):
+        xo, io = o.pcg(bs[q])
+        assert info[q]["relres_true"] <= 1e-6
+        it = int(io["its"][0])
+        if prec == D.FP64:  # the group's dot products add the members' sums: another rounding order
+            assert abs(info[q]["iters"] - it) <= max(1, int(0.02 * it))
+        else:
+            assert info[q]["iters"] <= int(1.1 * it) + 1
+        assert_converged_close(xs[off[q]:off[q + 1]], xo, 1e-4, f"system {q}")
+    # a second solve replays the captured launch and gives the same result
+    x2 = torch.zeros_like(bt)
+    st2, info2 = D.ddlr_batch_solve(B, bt, x2)
+    assert st2 == D.OK and [i["iters"] for i in info2] == [i["iters"] for i in info]
+    assert torch.equal(x, x2)
