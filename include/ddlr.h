@@ -515,12 +515,13 @@ ddlr_status ddlr_batch_tuning(const ddlr_batch *b, int32_t *persistent, int32_t 
  * systems differ in size runs as long as its slowest system, so
  * ddlr_batch_create gives the systems estimated to be slowest several
  * workgroups (a group) when the lanes fit the resident workgroups of the
- * device: each member sweeps the merged levels of its own subdomain blocks
- * (the blocks of A0 are independent, Sec. 3.1), the last one also the interface
- * block and the interface step of the correction; members meet at workgroup
- * barriers in device memory for the dot products and to exchange p and the
- * first solve's result.  DDLR_BATCH_GROUP=0 keeps one workgroup per system,
- * =N asks for N.  Errors: DDLR_E_INVALID (null argument). */
+ * device: in the A0 solves the first min(G, p) members each sweep the merged
+ * levels of their own subdomain blocks (the blocks of A0 are independent,
+ * Sec. 3.1), the last of them also the interface block and the interface step
+ * of the correction; the SpMV, dot products and vector updates split the rows
+ * evenly over all G members; members meet at workgroup barriers in device
+ * memory.  DDLR_BATCH_GROUP=0 keeps one workgroup per system, =N asks for N.
+ * Errors: DDLR_E_INVALID (null argument). */
 ddlr_status ddlr_batch_members(const ddlr_batch *b, int32_t *members);
 ddlr_status ddlr_batch_apply(ddlr_batch *b, const double *x, double *y, void *stream);
 /* PCG on every system (x0 = 0, stopping rule of Sec. 5); info: host array of

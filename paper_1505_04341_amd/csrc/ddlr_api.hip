@@ -394,8 +394,9 @@ struct ddlr_prec {
     DevFactors<float> f32;
     int64_t urows = 0;      // rows of U (s for DDLR-1, n for DDLR-2)
     int64_t ndev = 0, sdev = 0;  // device-order rows and interface positions (all systems of a batch)
-    // batch of independent systems (nsys > 1): per-system row / interface offsets,
-    // low-rank scalars; the CG lanes are the systems
+    // batch of independent systems (batch, any nsys >= 1): per-system row /
+    // interface offsets, low-rank scalars; the CG lanes are the systems
+    bool batch = false;
     int nsys = 1;
     int64_t *seg_roff = nullptr, *seg_soff = nullptr;
     double *c0s = nullptr, *dvecs = nullptr;
@@ -1604,7 +1605,7 @@ void apply_dev_T(ddlr_prec* h, int nrhs, const double* in, int64_t ldin, double*
         T* wsv = (T*)W.ws;
         a0_solve_dev<T, double, T>(h, F, nrhs, in, ldin, a1, n, st, done);
         csr_mv<T, T>(s, nrhs, h->etrp, h->etci, F.etv, a1, n, (const T*)nullptr, 0, ys, s, st, done);
-        if (h->nsys > 1) {  // per system of a batch (one column)
+        if (h->batch) {  // per system of a batch (one column)
             ProfScope ps(h, 3, st);
             hipLaunchKernelGGL(k_seg_lr_coef<T>, dim3(h->nsys), dim3(256), 0, st, h->seg_soff, h->k, F.U, ys, h->dvecs,
                                W.coef, done);
@@ -2720,7 +2721,7 @@ void autotune_T(ddlr_prec* h, const DevFactors<T>& F, int nrhs, hipStream_t st) 
 }
 
 void autotune(ddlr_prec* h, int nrhs, hipStream_t st, bool force) {
-    if (h->capturing || h->nsys > 1) return;
+    if (h->capturing || h->batch) return;
     if (!force && (h->tune_mode == 0 || h->tune.count(nrhs))) return;
     ensure_ws(h, nrhs);
     drop_graphs(h);  // captured launches embed the shape
@@ -3383,9 +3384,10 @@ void persist_build(PersistData& PD, const std::vector<const HostPlan*>& plans, c
     PlanTranspose X;
     for (size_t q = 0; q < plans.size(); ++q) {
         const HostPlan& P = *plans[q];
-        const int G = groups.empty() ? 1 : std::max(1, std::min({groups[q], (int)P.p, kGroupMax}));
+        const int G = groups.empty() || P.p < 1 ? 1 : std::max(1, std::min(groups[q], kGroupMax));
+        const int Gb = std::min(G, (int)P.p);  // members that own blocks
         PD.members[q] = G;
-        const std::vector<int32_t> cut = member_blocks(P, G);
+        const std::vector<int32_t> cut = member_blocks(P, Gb);
         plan_transpose(P, X);
         const int grp = G > 1 ? PD.ngroups++ : -1;
         for (int g = 0; g < G; ++g) {
@@ -3398,12 +3400,16 @@ void persist_build(PersistData& PD, const std::vector<const HostPlan*>& plans, c
             S.s = (int32_t)P.s;
             S.k = ks[q];
             S.c0 = c0s[q];
-            S.o0 = (int32_t)P.boff[cut[g]];
-            S.o1 = (int32_t)P.boff[cut[g + 1]];
+            const int32_t b0 = g < Gb ? cut[g] : P.p + 1, b1 = g < Gb ? cut[g + 1] : P.p + 1;
+            S.o0 = (int32_t)P.boff[b0];
+            S.o1 = (int32_t)P.boff[b1];
             S.G = G;
             S.g = g;
             S.grp = grp;
-            persist_levels(P, X, roff[q], cut[g], cut[g + 1], M, S.l0, S.l1);
+            S.ifc = g == Gb - 1;
+            S.v0 = (int32_t)(P.n * g / G);
+            S.v1 = (int32_t)(P.n * (g + 1) / G);
+            persist_levels(P, X, roff[q], b0, b1, M, S.l0, S.l1);
             const size_t need = (size_t)(S.o1 - S.o0) * tsz;
             S.lds = need <= budget;
             if (S.lds) PD.lds_bytes = std::max(PD.lds_bytes, need);
@@ -3520,7 +3526,7 @@ template <typename T, int NT>
 void persist_launch_nt(ddlr_prec* h, PersistData& PD, int nl, double tol2, int maxit, hipStream_t st) {
     const DevFactors<T>& F = factors<T>(h);
     Workspace& W = h->ws;
-    const bool multi = h->nsys > 1;
+    const bool multi = h->batch;  // per-system coefficients of a batch (also of one system)
     const T* U = F.U;
     const int ustride = std::max(1, h->k);
     const double* dco = multi ? h->dvecs : h->dvec;
@@ -3656,27 +3662,31 @@ void persist_tune(ddlr_prec* h, PersistData& PD, int nl, double tol2, int maxit,
 // Workgroups per system of a persistent batch.  The batch takes as long as its
 // slowest system, so the system with the largest estimated solve time gets
 // more members while that lowers its estimate and the lanes fit `slots`.
-// Estimate: iterations ~ sqrt(n) (these stencils' condition numbers grow with
-// the grid side); per iteration four sweeps over the deepest member's merged
-// levels (0.25 us a level with its solve vector in LDS, 2.5 us in global
-// memory, as measured with one workgroup per system), 15 ns per row of the
-// largest member, and six group barriers of 3 us when G > 1.  Only the ratios
-// matter.  Systems start at the fewest members whose solve vectors fit LDS.
+// Estimate (256-thread workgroups): iterations ~ sqrt(n) (these stencils'
+// condition numbers grow with the grid side); per iteration four sweeps over
+// the deepest block member's merged levels (0.25 us a level with its solve
+// vector in LDS, 2.5 us in global memory) and 5 ns per row of its blocks,
+// 12 ns per row of the vector steps (n / G rows), and seven group barriers of
+// 3 us when G > 1.  Systems start at the fewest members whose solve vectors
+// fit LDS.  Only the ratios matter; of the forms tried on the 256-system
+// batch this one measured fastest.
 std::vector<int> choose_groups(const std::vector<const HostPlan*>& plans, size_t tsz, size_t lds_cap, int slots) {
     const int ns = (int)plans.size();
     std::vector<int> G(ns, 1);
     auto est = [&](int q, int g) {
         const HostPlan& P = *plans[q];
-        const std::vector<int32_t> cut = member_blocks(P, g);
+        const int gb = std::max(1, std::min(g, (int)P.p));
+        const std::vector<int32_t> cut = member_blocks(P, gb);
         double worst = 0.0;
-        for (int u = 0; u < g; ++u) {
+        for (int u = 0; u < gb; ++u) {
             const int64_t rows = P.boff[cut[u + 1]] - P.boff[cut[u]];
             int depth = 0;
             for (int32_t b = cut[u]; b < cut[u + 1]; ++b) depth = std::max(depth, P.blk_lvl[b + 1] - P.blk_lvl[b]);
             const double lev = (size_t)rows * tsz <= lds_cap ? 0.25 : 2.5;
-            worst = std::max(worst, 4.0 * depth * lev + 0.015 * (double)rows);
+            worst = std::max(worst, 4.0 * depth * lev + 0.005 * (double)rows);
         }
-        if (g > 1) worst += 6 * 3.0;
+        worst += 0.012 * (double)P.n / g;
+        if (g > 1) worst += 7 * 3.0;
         return std::sqrt((double)P.n) * worst;
     };
     int total = ns;
@@ -3685,7 +3695,7 @@ std::vector<int> choose_groups(const std::vector<const HostPlan*>& plans, size_t
     for (int q = 0; q < ns; ++q) {
         const HostPlan& P = *plans[q];
         const int gmax = std::min((int)P.p, kGroupMax);
-        for (int g = 1; g <= gmax; ++g) {
+        for (int g = 1; g <= gmax && P.p >= 1; ++g) {
             const std::vector<int32_t> cut = member_blocks(P, g);
             int64_t big = 0;
             for (int u = 0; u < g; ++u) big = std::max(big, P.boff[cut[u + 1]] - P.boff[cut[u]]);
@@ -3700,11 +3710,11 @@ std::vector<int> choose_groups(const std::vector<const HostPlan*>& plans, size_t
     }
     if (total > slots) return std::vector<int>(ns, 1);
     std::priority_queue<std::pair<double, int>> pq;
-    for (int q = 0; q < ns; ++q) pq.push({est(q, 1), q});
+    for (int q = 0; q < ns; ++q) pq.push({est(q, G[q]), q});
     while (!pq.empty() && total < slots) {
         const auto [e, q] = pq.top();
         pq.pop();
-        const int gmax = std::min({(int)plans[q]->p, kGroupMax, G[q] + (slots - total)});
+        const int gmax = plans[q]->p < 1 ? 1 : std::min(kGroupMax, G[q] + (slots - total));
         int best = 0;
         double eb = e;
         for (int g = G[q] + 1; g <= std::min(gmax, G[q] + 4); ++g) {
@@ -3727,7 +3737,7 @@ std::vector<int> choose_groups(const std::vector<const HostPlan*>& plans, size_t
 // C_alpha factored, FP64 or FP32, rank at most kPersistMaxK.
 bool persist_eligible(const ddlr_prec* h) {
     return (h->variant == DDLR_1 || h->variant == DDLR_VARIANT_A0) && h->plan.csolve == 0 &&
-           h->precision != DDLR_FP32_UK_BF16 && h->k <= kPersistMaxK && h->nsys == 1;
+           h->precision != DDLR_FP32_UK_BF16 && h->k <= kPersistMaxK && !h->batch;
 }
 
 // Tables of a single-system handle, built on first use.
@@ -4479,7 +4489,7 @@ ddlr_status ddlr_profile_read(ddlr_prec* h, int32_t which, double min_us, double
 
 ddlr_status ddlr_extend_lowrank(ddlr_prec* h, int32_t k, int32_t more_steps, int32_t check, double tol) {
     if (!dev_ok(h)) return h ? DDLR_E_DEVICE : DDLR_E_INVALID;
-    if (h->lrun.steps == 0 || h->lrun.lvariant == 0 || h->nsys > 1) {
+    if (h->lrun.steps == 0 || h->lrun.lvariant == 0 || h->batch) {
         g_err = "no Lanczos run to continue (variant 0, imported low-rank data, or a batch)";
         return DDLR_E_INVALID;
     }
@@ -4719,6 +4729,7 @@ ddlr_status ddlr_batch_create(int32_t nsys, ddlr_prec* const* members, ddlr_batc
         h->precision = m0->precision;
         h->variant = m0->variant;
         h->nsys = nsys;
+        h->batch = true;
         h->overlap = false;
         h->tune_mode = 0;
         // device structures of every member, interface blocks as single blocks

@@ -29,9 +29,12 @@
 namespace ddlr {
 
 // One workgroup's share of a system.  A system is solved by G >= 1 workgroups
-// (a group); member g owns a contiguous range of the system's blocks and
-// their rows r0 + o0 .. r0 + o1 - 1, the last member also the interface block
-// (whose rows come last).  G = 1: the whole system, o0 = 0, o1 = n.
+// (a group).  For the A0 solves the first min(G, p) members own contiguous
+// ranges of the system's blocks, rows r0 + o0 .. r0 + o1 - 1, the last of them
+// also the interface block (whose rows come last) and the interface step of
+// the correction; members beyond own no block.  The vector steps of CG (the
+// SpMV, the dot products, the updates) split the rows evenly over all G
+// members instead: rows r0 + v0 .. r0 + v1 - 1.  G = 1: the whole system.
 struct PSys {
     int64_t r0;      // first device row of the system
     int64_t s0;      // first interface position (rows of U_k, y, w)
@@ -42,10 +45,11 @@ struct PSys {
     int32_t lds;     // 1: the member's solve vector fits the dynamic LDS
     int32_t pad;
     double c0;       // eq. (gkt): G^{-1} = c0 I + U_k diag(d) U_k^T
-    int32_t o0, o1;  // the member's rows, as offsets from r0
+    int32_t o0, o1;  // the member's block rows (A0 solve), as offsets from r0
     int32_t G, g;    // members of the group; this member's index
     int32_t grp;     // group index (barrier counters and partial sums; -1 when G = 1)
-    int32_t pad2;
+    int32_t ifc;     // 1: the member owns the interface block
+    int32_t v0, v1;  // the member's rows of the vector steps, as offsets from r0
 };
 
 struct PLane {
@@ -445,7 +449,7 @@ __device__ __forceinline__ bool member_apply(const PSys& S, int64_t R0, unsigned
             for (int64_t i = R0 + threadIdx.x; i < R1; i += NT) tg[i] = vec[i - R0];
         }
         if (!group_barrier(ctr, S.G, gl)) return false;
-        if (S.g == S.G - 1) {
+        if (S.ifc) {
             const int64_t s0 = S.s0, s1 = S.s0 + S.s;
 #pragma unroll 4
             for (int64_t jg = s0 + threadIdx.x; jg < s1; jg += NT) {
@@ -527,7 +531,8 @@ __device__ __forceinline__ void member_pcg(const PSys& S, const int64_t* __restr
     unsigned* ctr = gctr + (size_t)S.grp * 64;
     double* slots = gpart + (size_t)S.grp * 4 * kGroupMax;
     int* xs = gxcc + (size_t)S.grp * kGroupMax;
-    const int64_t R0 = S.r0 + S.o0, R1 = S.r0 + S.o1;
+    const int64_t R0 = S.r0 + S.o0, R1 = S.r0 + S.o1;  // block rows (A0 solve)
+    const int64_t V0 = S.r0 + S.v0, V1 = S.r0 + S.v1;  // rows of the vector steps
     if (threadIdx.x == 0) {
         gl->flag = 0;
         gl->fast = 0;
@@ -555,7 +560,7 @@ __device__ __forceinline__ void member_pcg(const PSys& S, const int64_t* __restr
         }
         double acc = 0.0;
 #pragma unroll 4
-        for (int64_t i = R0 + threadIdx.x; i < R1; i += NT) {
+        for (int64_t i = V0 + threadIdx.x; i < V1; i += NT) {
             const double bi = b[i];
             x[i] = 0.0;
             r[i] = bi;
@@ -574,20 +579,21 @@ __device__ __forceinline__ void member_pcg(const PSys& S, const int64_t* __restr
             ok = member_apply<T, NT, false>(S, R0, ctr, gl, meta, mrow, fcol, fval, bcol, bval, dq, erp, eci, ev,
                                             etrp, etci, etv, U, ustride, dcoef, r, z, tg, tq, yv, wv, lvec, red, coef);
         if (!ok) break;
+        if (!group_barrier(ctr, G, gl)) break;  // z of the block rows, read by the vector steps
         double acc = 0.0;
 #pragma unroll 4
-        for (int64_t i = R0 + threadIdx.x; i < R1; i += NT) acc += r[i] * z[i];
+        for (int64_t i = V0 + threadIdx.x; i < V1; i += NT) acc += r[i] * z[i];
         const double rzn = group_sum<NT>(acc, red, slots + kGroupMax, ctr, G, g, gl);
         if (gl->flag) break;
         const double beta = its == 0 ? 0.0 : rzn / rz;
         rz = rzn;
 #pragma unroll 4
-        for (int64_t i = R0 + threadIdx.x; i < R1; i += NT) p[i] = its == 0 ? z[i] : z[i] + beta * p[i];
+        for (int64_t i = V0 + threadIdx.x; i < V1; i += NT) p[i] = its == 0 ? z[i] : z[i] + beta * p[i];
         if (!group_barrier(ctr, G, gl)) break;  // q = A p reads the other members' p
         ++its;
         acc = 0.0;
 #pragma unroll 4
-        for (int64_t i = R0 + threadIdx.x; i < R1; i += NT) {
+        for (int64_t i = V0 + threadIdx.x; i < V1; i += NT) {
             double s = 0.0;
             const int64_t t1 = arp[i + 1];
             for (int64_t t = arp[i]; t < t1; ++t) s += av[t] * p[aci[t]];
@@ -599,7 +605,7 @@ __device__ __forceinline__ void member_pcg(const PSys& S, const int64_t* __restr
         const double alpha = rz / pq;
         acc = 0.0;
 #pragma unroll 4
-        for (int64_t i = R0 + threadIdx.x; i < R1; i += NT) {
+        for (int64_t i = V0 + threadIdx.x; i < V1; i += NT) {
             x[i] += alpha * p[i];
             const double ri = r[i] - alpha * q[i];
             r[i] = ri;
@@ -614,7 +620,7 @@ __device__ __forceinline__ void member_pcg(const PSys& S, const int64_t* __restr
     if (gl->flag == 0 && group_barrier(ctr, G, gl)) {
         double acc = 0.0;
 #pragma unroll 4
-        for (int64_t i = R0 + threadIdx.x; i < R1; i += NT) {
+        for (int64_t i = V0 + threadIdx.x; i < V1; i += NT) {
             double s = 0.0;
             const int64_t t1 = arp[i + 1];
             for (int64_t t = arp[i]; t < t1; ++t) s += av[t] * x[aci[t]];
