@@ -270,6 +270,7 @@ struct PersistData {
     int* gxcc = nullptr;         // per group kGroupMax XCD ids
     int grid = 0;                // lanes of a launch, idle slots included (0: one lane per table entry)
     int gslow = 0;               // 1: group barriers always take the slow form
+    unsigned gspin = 0;          // polls before a group wait gives up (0: the kernel's limit)
     std::vector<int> sys_lane;   // per system: the lane of its first member (its result)
     std::vector<int> members;    // per system: workgroups on it
 };
@@ -3545,7 +3546,7 @@ void persist_launch_nt(ddlr_prec* h, PersistData& PD, int nl, double tol2, int m
                        h->eci, F.ev, h->etrp,
                        h->etci, F.etv, U, ustride, dco, PD.b, W.x, W.r, PD.p, W.q, W.z, (T*)W.a1, (T*)W.a2, (T*)W.ys,
                        (T*)W.ws, h->ndev, h->sdev, PD.meta_off, tol2, maxit, PD.res, PD.gctr, PD.gpart, PD.gxcc,
-                       PD.gslow);
+                       PD.gslow, PD.gspin);
     LAUNCHCHK();
 }
 
@@ -4821,6 +4822,8 @@ ddlr_status ddlr_batch_create(int32_t nsys, ddlr_prec* const* members, ddlr_batc
                 persist_batch_lanes(*B->pers, h->ndev, nxcd);
             }
             if (const char* gs = std::getenv("DDLR_GROUP_SLOW")) B->pers->gslow = gs[0] == '1';
+            // a smaller limit on the group waits (the failure path can be forced)
+            if (const char* sp = std::getenv("DDLR_GROUP_SPIN")) B->pers->gspin = (unsigned)std::strtoul(sp, nullptr, 10);
         }
         HIPCHK(hipStreamCreateWithFlags(&B->own, hipStreamNonBlocking));  // default priority
         HIPCHK(hipEventCreateWithFlags(&B->ev_in, hipEventDisableTiming));

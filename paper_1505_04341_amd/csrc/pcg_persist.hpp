@@ -334,8 +334,8 @@ __device__ __forceinline__ void wg_apply(const PSys& S, const int4* __restrict__
 //     memory; arrival is a device-scope atomic, polled with device-scope loads;
 //   fast form (every member on one XCD, checked once at start): the L2 is
 //     shared, so no write-back; arrival and polling are L2 atomics.
-// A wait gives up after kSpinMax polls and the lane reports failure (status
-// 2): no member waits without bound.  Values other members wrote are read
+// A wait gives up after kSpinMax polls (or the launch's smaller limit) and the
+// lane reports failure (status 2): no member waits without bound.  Values other members wrote are read
 // with lane-dependent addresses (vector loads through the invalidated L1),
 // never through the scalar cache.
 
@@ -358,6 +358,7 @@ struct GroupLds {
     int fast;         // 1: the fast form (decided once, the same in every member)
     unsigned n_slow;  // arrivals counted by the last barrier of each form
     unsigned n_fast;
+    unsigned spin;    // polls before a wait gives up
 };
 
 // ctr: the group's 64 counters (slow form at 0, fast form at 32, zero at launch).
@@ -384,7 +385,7 @@ __device__ __forceinline__ bool group_barrier(unsigned* ctr, int G, GroupLds* gl
                 }
                 if (v >= target) break;
                 __builtin_amdgcn_s_sleep(2);
-                if (++spins > kSpinMax) {
+                if (++spins > gl->spin) {
                     gl->flag = 1;
                     break;
                 }
@@ -525,8 +526,8 @@ __device__ __forceinline__ void member_pcg(const PSys& S, const int64_t* __restr
                            const T* __restrict__ etv, const T* __restrict__ U, int ustride,
                            const double* __restrict__ dcoef, const double* b, double* x, double* r, double* p,
                            double* q, double* z, T* tg, T* tq, T* yv, T* wv, T* lvec, double* red, double* coef,
-                           unsigned* gctr, double* gpart, int* gxcc, int gslow, double tol2, int maxit, PRes* res,
-                           GroupLds* gl) {
+                           unsigned* gctr, double* gpart, int* gxcc, int gslow, unsigned gspin, double tol2,
+                           int maxit, PRes* res, GroupLds* gl) {
     const int G = S.G, g = S.g;
     unsigned* ctr = gctr + (size_t)S.grp * 64;
     double* slots = gpart + (size_t)S.grp * 4 * kGroupMax;
@@ -538,6 +539,7 @@ __device__ __forceinline__ void member_pcg(const PSys& S, const int64_t* __restr
         gl->fast = 0;
         gl->n_slow = 0u;
         gl->n_fast = 0u;
+        gl->spin = gspin ? min(gspin, kSpinMax) : kSpinMax;
         xs[g] = xcc_id();
     }
     __syncthreads();
@@ -656,7 +658,7 @@ __global__ __launch_bounds__(NT) void k_pcg_persist(
     const double* __restrict__ dcoef, const double* __restrict__ b, double* __restrict__ x, double* __restrict__ r,
     double* __restrict__ p, double* __restrict__ q, double* __restrict__ z, T* tg, T* tq,
     T* yv, T* wv, int64_t ld, int64_t lds_s, int meta_off, double tol2, int maxit, PRes* __restrict__ res,
-    unsigned* gctr, double* gpart, int* gxcc, int gslow) {
+    unsigned* gctr, double* gpart, int* gxcc, int gslow, unsigned gspin) {
     extern __shared__ __attribute__((aligned(16))) unsigned char persist_lds[];
     __shared__ double red[(NT / 64) * 16];
     __shared__ double coef[kPersistMaxK];
@@ -678,7 +680,7 @@ __global__ __launch_bounds__(NT) void k_pcg_persist(
     if (S.G > 1) {
         member_pcg<T, NT>(S, arp, aci, av, meta, mrow, fcol, fval, bcol, bval, dq, erp, eci, ev, etrp, etci, etv, U,
                           ustride, dcoef, b, x, r, p, q, z, tg, tq, yv, wv, lvec, red, coef, gctr, gpart, gxcc, gslow,
-                          tol2, maxit, res, &glds);
+                          gspin, tol2, maxit, res, &glds);
         return;
     }
     const int64_t r0 = S.r0, r1 = S.r0 + S.n;

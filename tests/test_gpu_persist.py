@@ -272,3 +272,35 @@ def test_batch_of_one_system(persist):
     st, info = D.ddlr_batch_solve(B, bt, x)
     xo, io = o.pcg(b)
     assert st == D.OK and abs(info[0]["iters"] - int(io["its"][0])) <= 1 and info[0]["relres_true"] <= 1e-6
+
+
+def test_grouped_batch_wait_gives_up():
+    """A group wait limited to one poll (DDLR_GROUP_SPIN=1, forced from the
+    host) gives up instead of waiting: the solve returns DDLR_E_DEVICE with a
+    message, every workgroup exits, and a batch built afterwards solves."""
+    mem = batch_members(4, D.FP64, seed=7)
+    say("grouped batch, wait limit 1")
+    hs = [D.ddlr_setup(A, part, p, 4, 1, lanczos_steps=10, lanczos_start=w.lanczos_start(A.n, 7),
+                       precision=D.FP64) for A, part, p in mem]
+    bs = [w.rhs_from_solution(A, q, 1)[0][:, 0] for q, (A, _, _) in enumerate(mem)]
+    bt = torch.from_numpy(np.concatenate(bs)).to(DEV)
+    env = {"DDLR_BATCH_GROUP": "3", "DDLR_GROUP_SPIN": "1", "DDLR_GROUP_SLOW": "1"}
+    os.environ.update(env)
+    try:
+        B = D.ddlr_batch_create(hs)
+    finally:
+        for key in env:
+            os.environ.pop(key, None)
+    x = torch.zeros_like(bt)
+    with pytest.raises(D.DDLRError) as e:
+        D.ddlr_batch_solve(B, bt, x)
+    assert e.value.status == D.E_DEVICE and "gave up" in str(e.value)
+    torch.cuda.synchronize()
+    os.environ["DDLR_BATCH_GROUP"] = "3"
+    try:
+        B2 = D.ddlr_batch_create(hs)
+    finally:
+        os.environ.pop("DDLR_BATCH_GROUP")
+    x = torch.zeros_like(bt)
+    st, info = D.ddlr_batch_solve(B2, bt, x)
+    assert st == D.OK and all(i["relres_true"] <= 1e-6 for i in info)
