@@ -304,3 +304,39 @@ def test_grouped_batch_wait_gives_up():
     x = torch.zeros_like(bt)
     st, info = D.ddlr_batch_solve(B2, bt, x)
     assert st == D.OK and all(i["relres_true"] <= 1e-6 for i in info)
+
+
+def test_headline_batch_grouped():
+    """The full 256-system batch of the benchmark (sides 32..256, FP32
+    preconditioner, the library's own grouping and tuned workgroup size):
+    every system converges with true residual <= 1e-6; the largest split
+    system and an unsplit one match the oracle's converged solution and
+    iteration count (the mixed bar)."""
+    systems = w.batch_systems(256)
+    say("headline batch", len(systems))
+    hs, bs = [], []
+    for s in systems:
+        hs.append(D.ddlr_setup(s["A"], s["part"], s["p"], s["k"], 1, lanczos_steps=s["m"],
+                               lanczos_start=w.lanczos_start(s["A"].n, s["seed"]), precision=D.FP32))
+        bs.append(w.rhs_from_solution(s["A"], s["seed"], 1)[0][:, 0])
+    B = D.ddlr_batch_create(hs)
+    counts = D.ddlr_batch_members(B)
+    say("split systems", sum(1 for c in counts if c > 1), "max members", max(counts))
+    assert max(counts) > 1
+    bt = torch.from_numpy(np.concatenate(bs)).to(DEV)
+    x = torch.zeros_like(bt)
+    st, info = D.ddlr_batch_solve(B, bt, x, maxit=2000)
+    assert st == D.OK and all(i["relres_true"] <= 1e-6 for i in info)
+    xs = x.cpu().numpy()
+    off = B.offsets
+    split = [q for q in range(len(systems)) if counts[q] > 1]
+    whole = [q for q in range(len(systems)) if counts[q] == 1]
+    picks = [max(split, key=lambda q: systems[q]["A"].n), max(whole, key=lambda q: systems[q]["A"].n)]
+    for q in picks:
+        s = systems[q]
+        say("oracle on system", q, "n", s["A"].n, "members", counts[q])
+        o = Oracle(s["A"], s["part"], s["p"]).lowrank(1, s["k"], s["m"], w.lanczos_start(s["A"].n, s["seed"]))
+        xo, io = o.pcg(bs[q], maxit=2000)
+        it = int(io["its"][0])
+        assert info[q]["iters"] <= int(1.1 * it) + 1
+        assert_converged_close(xs[off[q]:off[q + 1]], xo, 1e-4, f"system {q}")
