@@ -874,8 +874,10 @@ def test_spmv_compact_storage_bitwise(name):
     values); irregular: random coefficients (FP64 values, 16-bit columns)."""
     cfg = CASES[name]()
     say("spmv compact", name)
-    h1, o = setup_pair(cfg, variant=D.VARIANT_A0)
-    h2, _ = setup_pair(cfg, variant=D.VARIANT_A0, env={"DDLR_SELL_WIDE": "1"})
+    # both handles take the chunked CG form: the persistent form, which a small system may
+    # choose by timing, sums its dot products in an order set by its tuned workgroup size
+    h1, o = setup_pair(cfg, variant=D.VARIANT_A0, env={"DDLR_CG_PERSIST": "0"})
+    h2, _ = setup_pair(cfg, variant=D.VARIANT_A0, env={"DDLR_SELL_WIDE": "1", "DDLR_CG_PERSIST": "0"})
     n = cfg["A"].n
     x = np.random.default_rng(2).standard_normal((n, 3))
     y1 = torch.empty((3, n), dtype=torch.float64, device=DEV)

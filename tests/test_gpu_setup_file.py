@@ -10,6 +10,7 @@ with the FP32 preconditioner the apply to 1e-4.  Export followed by import
 gives a handle whose apply and CG are bitwise those of the exported one.
 """
 import gc
+import os
 import sys
 
 import numpy as np
@@ -101,11 +102,17 @@ def test_export_import_same_operator(prec, variant, tmp_path):
     cfg = w.config("small3d")
     A, n = cfg["A"], cfg["A"].n
     say("export/import", prec, variant)
-    h = D.ddlr_setup(A, cfg["part"], cfg["p"], cfg["k"], variant, lanczos_steps=cfg["m"],
-                     lanczos_start=w.lanczos_start(n, 0), precision=prec)
-    f = str(tmp_path / "own.ddlr")
-    D.ddlr_export_setup(h, f)
-    h2 = D.ddlr_import_setup(A, f)
+    # both handles take the chunked CG form: the persistent form, which a small system may
+    # choose by timing, sums its dot products in an order set by its tuned workgroup size
+    os.environ["DDLR_CG_PERSIST"] = "0"
+    try:
+        h = D.ddlr_setup(A, cfg["part"], cfg["p"], cfg["k"], variant, lanczos_steps=cfg["m"],
+                         lanczos_start=w.lanczos_start(n, 0), precision=prec)
+        f = str(tmp_path / "own.ddlr")
+        D.ddlr_export_setup(h, f)
+        h2 = D.ddlr_import_setup(A, f)
+    finally:
+        os.environ.pop("DDLR_CG_PERSIST")
     x = to_dev(np.random.default_rng(10).standard_normal((n, 6)))
     y1, y2 = torch.empty_like(x), torch.empty_like(x)
     D.ddlr_apply(h, x, y1)
