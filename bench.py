@@ -648,17 +648,29 @@ def run_serving(args, D, w, torch):
     }
 
 
-def trace_summary(path, min_us):
+def trace_summary(path, min_us, kernel_re=None, tail=0):
     """Markdown table of a rocprofv3 kernel trace: per kernel name, dispatches,
     average duration over all of them and over those of at least min_us
-    (launches after every column converged return at once), total time."""
+    (launches after every column converged return at once), total time.
+    kernel_re / tail: only kernels whose name matches, and of those only the
+    last `tail` dispatches of the run in start order (the profiled solves,
+    which come last, are what the benchmark line averages)."""
     import csv
-    per = {}
+    import re
+    rows = []
     with open(path, newline="") as f:
         for row in csv.DictReader(f):
             name = row.get("Kernel_Name") or row.get("Kernel-Name") or row.get("KernelName")
-            t = (float(row["End_Timestamp"]) - float(row["Start_Timestamp"])) / 1e3  # ns -> us
-            per.setdefault(name, []).append(t)
+            if kernel_re and not re.search(kernel_re, name):
+                continue
+            rows.append((int(row["Start_Timestamp"]), name,
+                         (float(row["End_Timestamp"]) - float(row["Start_Timestamp"])) / 1e3))  # ns -> us
+    rows.sort()
+    if tail:
+        rows = rows[-tail:]
+    per = {}
+    for _, name, t in rows:
+        per.setdefault(name, []).append(t)
     rows = sorted(per.items(), key=lambda kv: -sum(kv[1]))
     print(f"| kernel | dispatches | avg us (all) | dispatches >= {min_us:g} us | avg us (>= {min_us:g} us) | total ms |")
     print("|---|---|---|---|---|---|")
@@ -728,11 +740,14 @@ def main():
     ap.add_argument("--pmc-summary", default=None,
                     help="summarise a rocprofv3 --pmc counter_collection.csv per kernel and exit; needs no GPU")
     ap.add_argument("--min-us", type=float, default=EARLY_EXIT_US)
+    ap.add_argument("--trace-kernel", default=None, help="--trace-summary: only kernels matching this regex")
+    ap.add_argument("--trace-tail", type=int, default=0,
+                    help="--trace-summary: only the last N matching dispatches of the run")
     ap.add_argument("--burst", type=int, default=64, help="c5: requests in the saturation burst")
     ap.add_argument("--requests", type=int, default=200, help="c5: requests per Poisson load level")
     args = ap.parse_args()
     if args.trace_summary:
-        trace_summary(args.trace_summary, args.min_us)
+        trace_summary(args.trace_summary, args.min_us, args.trace_kernel, args.trace_tail)
         return
     if args.pmc_summary:
         pmc_summary(args.pmc_summary, args.min_us)
