@@ -457,6 +457,10 @@ def run_batch(args, D, w, torch):
     total = time.perf_counter() - t0
     its = np.array([i["iters"] for i in info])
     rtrue = max(i["relres_true"] for i in info)
+    times = np.array(D.ddlr_batch_times(batch))
+    slow = [{"system": int(q), "n": int(systems[q]["A"].n), "boxes": int(systems[q]["p"]), "members": int(grp[q]),
+             "iters": int(its[q]), "ms": round(float(times[q]) / 1e3, 2)} for q in np.argsort(-times)[:6]]
+    log("batch: slowest systems", slow)
     log("batch: status", st, "iters min/median/max", its.min(), int(np.median(its)), its.max(), "max true relres",
         rtrue)
     solves = args.steps * len(systems)
@@ -486,7 +490,8 @@ def run_batch(args, D, w, torch):
                    "maxit": BATCH_MAXIT},
         "latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99), "note": "per batch solve (all systems)"},
         "batch": {"status": st, "iters_min": int(its.min()), "iters_median": float(np.median(its)),
-                  "iters_max": int(its.max()), "max_relres_true": rtrue, "setup_s": round(setup_s, 2)},
+                  "iters_max": int(its.max()), "max_relres_true": rtrue, "setup_s": round(setup_s, 2),
+                  "slowest_systems": slow},
         "tuning": tun,
         "roofline": roof,
         "cpu_baseline": None if args.no_cpu else cpu_baseline_batch(systems, bs, args.cpu_systems),

@@ -523,6 +523,12 @@ ddlr_status ddlr_batch_tuning(const ddlr_batch *b, int32_t *persistent, int32_t 
  * memory.  DDLR_BATCH_GROUP=0 keeps one workgroup per system, =N asks for N.
  * Errors: DDLR_E_INVALID (null argument). */
 ddlr_status ddlr_batch_members(const ddlr_batch *b, int32_t *members);
+/* Device time of each system in the last persistent ddlr_batch_solve (us: host
+ * array of nsys entries, microseconds from the launch start of the system's
+ * workgroups to the end of its slowest one, by the device wall clock; 0 for
+ * every system before such a solve or with the chunked form).  The batch
+ * takes as long as its largest entry.  Errors: DDLR_E_INVALID (null argument). */
+ddlr_status ddlr_batch_times(const ddlr_batch *b, double *us);
 ddlr_status ddlr_batch_apply(ddlr_batch *b, const double *x, double *y, void *stream);
 /* PCG on every system (x0 = 0, stopping rule of Sec. 5); info: host array of
  * nsys entries.  Synchronises the stream.  DDLR_E_NO_CONVERGENCE if any system

@@ -144,6 +144,7 @@ def load_library(path: str = LIB_PATH):
         "ddlr_batch_apply": (I32, [P, P, P, P]),
         "ddlr_batch_tuning": (I32, [P, P, P, P]),
         "ddlr_batch_members": (I32, [P, P]),
+        "ddlr_batch_times": (I32, [P, P]),
         "ddlr_batch_solve": (I32, [P, P, P, P, P, P]),
         "ddlr_batch_destroy": (None, [P]),
         "ddlr_server_create": (I32, [I32, C.c_size_t, I32, P]),
@@ -508,6 +509,13 @@ def ddlr_batch_members(batch: Batch) -> list:
     return list(arr)
 
 
+def ddlr_batch_times(batch: Batch) -> list:
+    """Device time (microseconds) of each system in the last persistent batch solve."""
+    arr = (C.c_double * batch.nsys)()
+    _check(load_library().ddlr_batch_times(batch.handle, arr), "ddlr_batch_times")
+    return list(arr)
+
+
 def ddlr_batch_solve(batch: Batch, b, x, *, maxit: int = 500, rtol: float = 1e-6, stream=None):
     """PCG on every system; returns (status, list of per-system info dicts)."""
     lib = load_library()
@@ -649,7 +657,7 @@ def ddlr_version() -> int:
 
 EXPORTED = ["ddlr_version", "ddlr_options_default", "ddlr_solve_options_default", "ddlr_setup", "ddlr_apply",
             "ddlr_apply_noalloc", "ddlr_ctx_create", "ddlr_ctx_usage", "ddlr_ctx_destroy", "ddlr_export_setup",
-            "ddlr_import_setup", "ddlr_partition_box", "ddlr_batch_tuning", "ddlr_batch_members",
+            "ddlr_import_setup", "ddlr_partition_box", "ddlr_batch_tuning", "ddlr_batch_members", "ddlr_batch_times",
             "ddlr_a0_solve", "ddlr_spmv", "ddlr_solve", "ddlr_query", "ddlr_get_ordering", "ddlr_get_factor",
             "ddlr_get_cinv",
             "ddlr_get_levels", "ddlr_get_lanczos", "ddlr_get_lanczos_reorth", "ddlr_get_lowrank", "ddlr_set_lowrank", "ddlr_profile",

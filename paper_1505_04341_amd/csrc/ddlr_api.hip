@@ -273,6 +273,9 @@ struct PersistData {
     unsigned gspin = 0;          // polls before a group wait gives up (0: the kernel's limit)
     std::vector<int> sys_lane;   // per system: the lane of its first member (its result)
     std::vector<int> members;    // per system: workgroups on it
+    std::vector<int> entry_sys;  // per table entry: its system
+    std::vector<PLane> hlanes;   // the lane table (host copy)
+    std::vector<double> sys_us;  // per system: device time of its slowest lane in the last solve
 };
 
 // A device and a device-memory budget shared by the handles created in it
@@ -3382,6 +3385,7 @@ void persist_build(PersistData& PD, const std::vector<const HostPlan*>& plans, c
     budget = budget > meta_bytes ? budget - meta_bytes : 0;
     PD.ngroups = 0;
     PD.members.assign(plans.size(), 1);
+    PD.entry_sys.clear();
     PlanTranspose X;
     for (size_t q = 0; q < plans.size(); ++q) {
         const HostPlan& P = *plans[q];
@@ -3415,6 +3419,7 @@ void persist_build(PersistData& PD, const std::vector<const HostPlan*>& plans, c
             S.lds = need <= budget;
             if (S.lds) PD.lds_bytes = std::max(PD.lds_bytes, need);
             PD.hsys.push_back(S);
+            PD.entry_sys.push_back((int)q);
         }
         persist_csr(P, roff[q], arp, aci, av);
     }
@@ -3507,6 +3512,7 @@ void persist_lanes(PersistData& PD, const std::vector<PLane>& lanes, int cols, i
         PD.nlanes = (int)lanes.size();
     }
     HIPCHK(hipMemcpy(PD.lanes, lanes.data(), lanes.size() * sizeof(PLane), hipMemcpyHostToDevice));
+    PD.hlanes = lanes;
     if (cols > PD.cols) {
         PD.b = PD.mem.alloc<double>((size_t)n * cols);
         PD.p = PD.mem.alloc<double>((size_t)n * cols);
@@ -3671,25 +3677,31 @@ void persist_tune(ddlr_prec* h, PersistData& PD, int nl, double tol2, int maxit,
 // 3 us when G > 1.  Systems start at the fewest members whose solve vectors
 // fit LDS.  Only the ratios matter; of the forms tried on the 256-system
 // batch this one measured fastest.
-std::vector<int> choose_groups(const std::vector<const HostPlan*>& plans, size_t tsz, size_t lds_cap, int slots) {
+//
+// scale (optional, per system): measured time over the estimate at the
+// grouping measured, so that the estimates of other groupings follow the
+// measurement (the first solve's regrouping).
+double group_est(const HostPlan& P, int g, size_t tsz, size_t lds_cap) {
+    const int gb = std::max(1, std::min(g, (int)P.p));
+    const std::vector<int32_t> cut = member_blocks(P, gb);
+    double worst = 0.0;
+    for (int u = 0; u < gb; ++u) {
+        const int64_t rows = P.boff[cut[u + 1]] - P.boff[cut[u]];
+        int depth = 0;
+        for (int32_t b = cut[u]; b < cut[u + 1]; ++b) depth = std::max(depth, P.blk_lvl[b + 1] - P.blk_lvl[b]);
+        const double lev = (size_t)rows * tsz <= lds_cap ? 0.25 : 2.5;
+        worst = std::max(worst, 4.0 * depth * lev + 0.005 * (double)rows);
+    }
+    worst += 0.012 * (double)P.n / g;
+    if (g > 1) worst += 7 * 3.0;
+    return std::sqrt((double)P.n) * worst;
+}
+
+std::vector<int> choose_groups(const std::vector<const HostPlan*>& plans, size_t tsz, size_t lds_cap, int slots,
+                               const std::vector<double>* scale = nullptr) {
     const int ns = (int)plans.size();
     std::vector<int> G(ns, 1);
-    auto est = [&](int q, int g) {
-        const HostPlan& P = *plans[q];
-        const int gb = std::max(1, std::min(g, (int)P.p));
-        const std::vector<int32_t> cut = member_blocks(P, gb);
-        double worst = 0.0;
-        for (int u = 0; u < gb; ++u) {
-            const int64_t rows = P.boff[cut[u + 1]] - P.boff[cut[u]];
-            int depth = 0;
-            for (int32_t b = cut[u]; b < cut[u + 1]; ++b) depth = std::max(depth, P.blk_lvl[b + 1] - P.blk_lvl[b]);
-            const double lev = (size_t)rows * tsz <= lds_cap ? 0.25 : 2.5;
-            worst = std::max(worst, 4.0 * depth * lev + 0.005 * (double)rows);
-        }
-        worst += 0.012 * (double)P.n / g;
-        if (g > 1) worst += 7 * 3.0;
-        return std::sqrt((double)P.n) * worst;
-    };
+    auto est = [&](int q, int g) { return group_est(*plans[q], g, tsz, lds_cap) * (scale ? (*scale)[q] : 1.0); };
     int total = ns;
     if (total >= slots) return G;
     // the fewest members that bring every member's solve vector into LDS
@@ -4643,6 +4655,14 @@ struct ddlr_batch {
     hipGraphExec_t pgexec = nullptr;
     int pg_maxit = -1, pg_nt = 0;
     double pg_tol2 = -1.0;
+    // measured regrouping (groups chosen by the library): what a rebuild of the
+    // persistent tables needs, kept until the first persistent solve has run
+    bool regroup = false;
+    std::vector<HostPlan> plans;
+    std::vector<int> ks;
+    std::vector<double> c0v;
+    size_t tsz = 0, cap = 0;
+    int nxcd = 1, slots = 0;
 };
 
 namespace {
@@ -4813,7 +4833,8 @@ ddlr_status ddlr_batch_create(int32_t nsys, ddlr_prec* const* members, ddlr_batc
                 persist_batch_lanes(*B->pers, h->ndev, nxcd);
                 PersistData& PD = *B->pers;
                 if (PD.grid > std::max(persist_resident(h, PD, 256), persist_resident(h, PD, 512))) {
-                    B->pers.reset(new PersistData());  // does not fit: one workgroup per system
+                    PD.mem.release();  // does not fit: one workgroup per system
+                    B->pers.reset(new PersistData());
                     grouped = false;
                 }
             }
@@ -4824,6 +4845,20 @@ ddlr_status ddlr_batch_create(int32_t nsys, ddlr_prec* const* members, ddlr_batc
             if (const char* gs = std::getenv("DDLR_GROUP_SLOW")) B->pers->gslow = gs[0] == '1';
             // a smaller limit on the group waits (the failure path can be forced)
             if (const char* sp = std::getenv("DDLR_GROUP_SPIN")) B->pers->gspin = (unsigned)std::strtoul(sp, nullptr, 10);
+            // groups the library chose are chosen again from the first solve's
+            // measured times (DDLR_BATCH_REGROUP=0: not)
+            const char* rg = std::getenv("DDLR_BATCH_REGROUP");
+            if (grouped && !ge && !(rg && rg[0] == '0')) {
+                B->regroup = true;
+                B->plans.reserve(nsys);
+                for (int q = 0; q < nsys; ++q) B->plans.push_back(members[q]->plan);
+                B->ks = ks;
+                B->c0v = c0v;
+                B->tsz = tsz;
+                B->cap = cap2;
+                B->nxcd = nxcd;
+                B->slots = 2 * cus;
+            }
         }
         HIPCHK(hipStreamCreateWithFlags(&B->own, hipStreamNonBlocking));  // default priority
         HIPCHK(hipEventCreateWithFlags(&B->ev_in, hipEventDisableTiming));
@@ -4862,6 +4897,16 @@ ddlr_status ddlr_batch_tuning(const ddlr_batch* B, int32_t* persistent, int32_t*
     return DDLR_OK;
 }
 
+ddlr_status ddlr_batch_times(const ddlr_batch* B, double* us) {
+    if (!B || !us) {
+        g_err = "null argument";
+        return DDLR_E_INVALID;
+    }
+    for (int q = 0; q < B->nsys; ++q)
+        us[q] = B->pers && (int)B->pers->sys_us.size() == B->nsys ? B->pers->sys_us[q] : 0.0;
+    return DDLR_OK;
+}
+
 ddlr_status ddlr_batch_members(const ddlr_batch* B, int32_t* members) {
     if (!B || !members) {
         g_err = "null argument";
@@ -4880,6 +4925,61 @@ ddlr_status ddlr_batch_apply(ddlr_batch* B, const double* x, double* y, void* st
     return run_chunked(h, 1, x, h->ndev, y, h->ndev, stream, [&](int nr, double* in, double* out, hipStream_t s) {
         apply_dev(h, nr, in, h->ndev, out, h->ndev, s, nullptr);
     });
+}
+
+// After the first persistent solve of a batch whose groups the library chose:
+// the measured per-system times calibrate the estimate (per system, its time
+// over the estimate at the groups it ran with), the groups are chosen again,
+// and when that lowers the slowest calibrated time by a tenth the tables are
+// rebuilt (the next solve tunes and captures anew).  Runs once; the kept
+// plans are released afterwards.
+static void batch_regroup(ddlr_batch* B) {
+    B->regroup = false;
+    PersistData& PD = *B->pers;
+    ddlr_prec* h = B->h;
+    const int ns = B->nsys;
+    std::vector<const HostPlan*> plans(ns);
+    for (int q = 0; q < ns; ++q) plans[q] = &B->plans[q];
+    std::vector<double> scale(ns, 1.0);
+    double tmax = 0.0;
+    bool timed = (int)PD.sys_us.size() == ns;
+    for (int q = 0; q < ns && timed; ++q) {
+        const double e = group_est(*plans[q], PD.members[q], B->tsz, B->cap);
+        timed = PD.sys_us[q] > 0.0 && e > 0.0;
+        if (timed) scale[q] = PD.sys_us[q] / e;
+        tmax = std::max(tmax, PD.sys_us[q]);
+    }
+    if (timed) {
+        const std::vector<int> G = choose_groups(plans, B->tsz, B->cap, B->slots, &scale);
+        double pmax = 0.0;
+        for (int q = 0; q < ns; ++q) pmax = std::max(pmax, group_est(*plans[q], G[q], B->tsz, B->cap) * scale[q]);
+        if (G != PD.members && pmax < 0.9 * tmax) {
+            std::unique_ptr<PersistData> N(new PersistData());
+            bool fits = false;
+            try {  // a regrouping that cannot be built leaves the batch as it was
+                persist_build(*N, plans, B->roff, B->soff, B->ks, B->c0v, std::max(1, h->k), B->tsz, h->device, G,
+                              B->cap);
+                persist_batch_lanes(*N, h->ndev, B->nxcd);
+                fits = N->grid <= std::max(persist_resident(h, *N, 256), persist_resident(h, *N, 512));
+            } catch (const SetupError&) {
+                (void)hipGetLastError();
+            }
+            if (fits) {
+                N->gslow = PD.gslow;
+                N->gspin = PD.gspin;
+                N->sys_us = PD.sys_us;  // the times measured, until the next solve
+                if (B->pgexec) (void)hipGraphExecDestroy(B->pgexec);
+                if (B->pgraph) (void)hipGraphDestroy(B->pgraph);
+                B->pgexec = nullptr;
+                B->pgraph = nullptr;
+                PD.mem.release();  // device memory is freed explicitly (DMem has no destructor)
+                B->pers = std::move(N);
+            } else {
+                N->mem.release();
+            }
+        }
+    }
+    std::vector<HostPlan>().swap(B->plans);
 }
 
 ddlr_status ddlr_batch_solve(ddlr_batch* B, const double* b, double* x, const ddlr_solve_options* opt_in,
@@ -4944,6 +5044,17 @@ ddlr_status ddlr_batch_solve(ddlr_batch* B, const double* b, double* x, const dd
             HIPCHK(hipEventRecord(B->ev_out, st));
             HIPCHK(hipStreamWaitEvent(ust, B->ev_out, 0));
             bool gave_up = false;
+            int khz = 0;  // the wall clock the lanes' ticks count
+            if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, h->device) != hipSuccess || khz <= 0) {
+                (void)hipGetLastError();
+                khz = 100000;
+            }
+            PD.sys_us.assign(ns, 0.0);
+            for (int l = 0; l < PD.grid; ++l)
+                if (PD.hlanes[l].sys >= 0) {
+                    double& u = PD.sys_us[PD.entry_sys[PD.hlanes[l].sys]];
+                    u = std::max(u, 1e3 * (double)rl[l].ticks / khz);
+                }
             for (int q = 0; q < ns; ++q) {
                 const PRes& r = rl[PD.sys_lane[q]];
                 ddlr_solve_info& inf = info[q];
@@ -4958,6 +5069,9 @@ ddlr_status ddlr_batch_solve(ddlr_batch* B, const double* b, double* x, const dd
                 g_err = "a group barrier of the persistent batch gave up waiting";
                 return DDLR_E_DEVICE;
             }
+            int itmax = 0;
+            for (int q = 0; q < ns; ++q) itmax = std::max(itmax, info[q].iters);
+            if (B->regroup && itmax >= 20) batch_regroup(B);
         } catch (const SetupError& e) {
             h->capturing = false;
             return fail_status(e);

@@ -61,6 +61,7 @@ struct PRes {
     int32_t its, status;  // iterations; 0 converged, 1 maxit reached
     double rr, bb;        // ||r||^2 (recursive) and ||b||^2
     double rtrue;         // ||b - A x||^2 after the solve
+    int64_t ticks;        // the lane's time in the launch, device wall-clock ticks
 };
 
 constexpr int kPersistMaxK = 64;  // rank bound of the persistent form
@@ -527,7 +528,7 @@ __device__ __forceinline__ void member_pcg(const PSys& S, const int64_t* __restr
                            const double* __restrict__ dcoef, const double* b, double* x, double* r, double* p,
                            double* q, double* z, T* tg, T* tq, T* yv, T* wv, T* lvec, double* red, double* coef,
                            unsigned* gctr, double* gpart, int* gxcc, int gslow, unsigned gspin, double tol2,
-                           int maxit, PRes* res, GroupLds* gl) {
+                           int maxit, PRes* res, GroupLds* gl, int64_t t0) {
     const int G = S.G, g = S.g;
     unsigned* ctr = gctr + (size_t)S.grp * 64;
     double* slots = gpart + (size_t)S.grp * 4 * kGroupMax;
@@ -639,6 +640,7 @@ __device__ __forceinline__ void member_pcg(const PSys& S, const int64_t* __restr
         o.rr = rr;
         o.bb = bb;
         o.rtrue = rt;
+        o.ticks = wall_clock64() - t0;
         res[blockIdx.x] = o;
     }
 }
@@ -665,6 +667,7 @@ __global__ __launch_bounds__(NT) void k_pcg_persist(
     __shared__ GroupLds glds;
     const PLane L = lanes[blockIdx.x];
     if (L.sys < 0) return;  // an idle slot of the launch grid
+    const int64_t t0 = wall_clock64();
     PSys S = sys[L.sys];
     const int64_t c = L.col;
     b += c * ld, x += c * ld, r += c * ld, p += c * ld, q += c * ld, z += c * ld, tg += c * ld, tq += c * ld;
@@ -680,7 +683,7 @@ __global__ __launch_bounds__(NT) void k_pcg_persist(
     if (S.G > 1) {
         member_pcg<T, NT>(S, arp, aci, av, meta, mrow, fcol, fval, bcol, bval, dq, erp, eci, ev, etrp, etci, etv, U,
                           ustride, dcoef, b, x, r, p, q, z, tg, tq, yv, wv, lvec, red, coef, gctr, gpart, gxcc, gslow,
-                          gspin, tol2, maxit, res, &glds);
+                          gspin, tol2, maxit, res, &glds, t0);
         return;
     }
     const int64_t r0 = S.r0, r1 = S.r0 + S.n;
@@ -764,6 +767,7 @@ __global__ __launch_bounds__(NT) void k_pcg_persist(
         o.rr = rr;
         o.bb = bb;
         o.rtrue = rt;
+        o.ticks = wall_clock64() - t0;
         res[blockIdx.x] = o;
     }
 }
