@@ -169,6 +169,12 @@ char* scratch_ptr(int dev) {
     return static_cast<char*>(p);
 }
 
+// An integer from the environment, else `dflt`.
+int env_int(const char* name, int dflt) {
+    const char* v = std::getenv(name);
+    return v && *v ? std::atoi(v) : dflt;
+}
+
 int grid_for(int64_t work, int block = 256, int cap = 8192) {
     int64_t g = (work + block - 1) / block;
     if (g < 1) g = 1;
@@ -4814,7 +4820,8 @@ ddlr_status ddlr_batch_create(int32_t nsys, ddlr_prec* const* members, ddlr_batc
             // then capped at 76 KB; DDLR_BATCH_GROUP=0 keeps one workgroup per
             // system, =N asks for N per system
             const size_t tsz = h->precision == DDLR_FP64 ? sizeof(double) : sizeof(float);
-            const size_t cap2 = 76 * 1024;
+            const size_t cap2 = (size_t)env_int("DDLR_GROUP_LDS_KB", 76) * 1024;
+            const int per_cu = env_int("DDLR_GROUP_PER_CU", 2);
             int cus = 0, nxcd = 1;
             HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device));
             hipDeviceProp_t prop;
@@ -4823,7 +4830,7 @@ ddlr_status ddlr_batch_create(int32_t nsys, ddlr_prec* const* members, ddlr_batc
             std::vector<int> groups;
             const char* ge = std::getenv("DDLR_BATCH_GROUP");
             if (ge && std::atoi(ge) > 0) groups.assign(nsys, std::atoi(ge));
-            else if (!(ge && ge[0] == '0')) groups = choose_groups(plans, tsz, cap2, 2 * cus);
+            else if (!(ge && ge[0] == '0')) groups = choose_groups(plans, tsz, cap2, per_cu * cus);
             bool grouped = false;
             for (int g : groups) grouped = grouped || g > 1;
             B->pers.reset(new PersistData());
@@ -4857,7 +4864,7 @@ ddlr_status ddlr_batch_create(int32_t nsys, ddlr_prec* const* members, ddlr_batc
                 B->tsz = tsz;
                 B->cap = cap2;
                 B->nxcd = nxcd;
-                B->slots = 2 * cus;
+                B->slots = per_cu * cus;
             }
         }
         HIPCHK(hipStreamCreateWithFlags(&B->own, hipStreamNonBlocking));  // default priority
