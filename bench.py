@@ -442,11 +442,6 @@ def run_batch(args, D, w, torch):
     for _ in range(args.warmup):
         D.ddlr_batch_solve(batch, bt, xt, maxit=BATCH_MAXIT)
     torch.cuda.synchronize()
-    tun = D.ddlr_batch_tuning(batch)
-    grp = D.ddlr_batch_members(batch)
-    tun["groups"] = {"systems_split": int(sum(1 for g in grp if g > 1)), "workgroups": int(sum(grp)),
-                     "max_members": int(max(grp))}
-    log("batch: tuning", tun)
     lat = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -455,6 +450,12 @@ def run_batch(args, D, w, torch):
         lat.append(1e3 * (time.perf_counter() - ts))
     torch.cuda.synchronize()
     total = time.perf_counter() - t0
+    # the batch's shapes after the solves (the first solve may regroup it and the next one tune it)
+    tun = D.ddlr_batch_tuning(batch)
+    grp = D.ddlr_batch_members(batch)
+    tun["groups"] = {"systems_split": int(sum(1 for g in grp if g > 1)), "workgroups": int(sum(grp)),
+                     "max_members": int(max(grp))}
+    log("batch: tuning", tun)
     its = np.array([i["iters"] for i in info])
     rtrue = max(i["relres_true"] for i in info)
     times = np.array(D.ddlr_batch_times(batch))
