@@ -4663,7 +4663,7 @@ struct ddlr_batch {
     double pg_tol2 = -1.0;
     // measured regrouping (groups chosen by the library): what a rebuild of the
     // persistent tables needs, kept until the first persistent solve has run
-    bool regroup = false;
+    int regroup = 0;  // regrouping passes left
     std::vector<HostPlan> plans;
     std::vector<int> ks;
     std::vector<double> c0v;
@@ -4856,7 +4856,7 @@ ddlr_status ddlr_batch_create(int32_t nsys, ddlr_prec* const* members, ddlr_batc
             // measured times (DDLR_BATCH_REGROUP=0: not)
             const char* rg = std::getenv("DDLR_BATCH_REGROUP");
             if (grouped && !ge && !(rg && rg[0] == '0')) {
-                B->regroup = true;
+                B->regroup = env_int("DDLR_BATCH_REGROUP", 2);
                 B->plans.reserve(nsys);
                 for (int q = 0; q < nsys; ++q) B->plans.push_back(members[q]->plan);
                 B->ks = ks;
@@ -4938,10 +4938,12 @@ ddlr_status ddlr_batch_apply(ddlr_batch* B, const double* x, double* y, void* st
 // the measured per-system times calibrate the estimate (per system, its time
 // over the estimate at the groups it ran with), the groups are chosen again,
 // and when that lowers the slowest calibrated time by a tenth the tables are
-// rebuilt (the next solve tunes and captures anew).  Runs once; the kept
-// plans are released afterwards.
+// rebuilt (the next solve tunes and captures anew).  Up to two passes (after
+// the first solves with at least 20 iterations; a pass that changes nothing
+// ends them); the kept plans are released afterwards.
 static void batch_regroup(ddlr_batch* B) {
-    B->regroup = false;
+    --B->regroup;
+    bool rebuilt = false;
     PersistData& PD = *B->pers;
     ddlr_prec* h = B->h;
     const int ns = B->nsys;
@@ -4981,12 +4983,14 @@ static void batch_regroup(ddlr_batch* B) {
                 B->pgraph = nullptr;
                 PD.mem.release();  // device memory is freed explicitly (DMem has no destructor)
                 B->pers = std::move(N);
+                rebuilt = true;
             } else {
                 N->mem.release();
             }
         }
     }
-    std::vector<HostPlan>().swap(B->plans);
+    if (!rebuilt) B->regroup = 0;
+    if (B->regroup <= 0) std::vector<HostPlan>().swap(B->plans);
 }
 
 ddlr_status ddlr_batch_solve(ddlr_batch* B, const double* b, double* x, const ddlr_solve_options* opt_in,
@@ -5078,7 +5082,7 @@ ddlr_status ddlr_batch_solve(ddlr_batch* B, const double* b, double* x, const dd
             }
             int itmax = 0;
             for (int q = 0; q < ns; ++q) itmax = std::max(itmax, info[q].iters);
-            if (B->regroup && itmax >= 20) batch_regroup(B);
+            if (B->regroup > 0 && itmax >= 20) batch_regroup(B);
         } catch (const SetupError& e) {
             h->capturing = false;
             return fail_status(e);
