@@ -520,7 +520,13 @@ ddlr_status ddlr_batch_tuning(const ddlr_batch *b, int32_t *persistent, int32_t 
  * Sec. 3.1), the last of them also the interface block and the interface step
  * of the correction; the SpMV, dot products and vector updates split the rows
  * evenly over all G members; members meet at workgroup barriers in device
- * memory.  DDLR_BATCH_GROUP=0 keeps one workgroup per system, =N asks for N.
+ * memory.  When the library chose the groups, its first persistent solves
+ * (up to two, each of at least 20 iterations) measure every system's time
+ * (ddlr_batch_times) and choose the groups again from those times; the tables
+ * are rebuilt when that lowers the slowest system's time by a tenth, so a
+ * later solve may differ from the first at rounding level.
+ * DDLR_BATCH_GROUP=0 keeps one workgroup per system, =N asks for N (no
+ * regrouping); DDLR_BATCH_REGROUP=0 keeps the first choice.
  * Errors: DDLR_E_INVALID (null argument). */
 ddlr_status ddlr_batch_members(const ddlr_batch *b, int32_t *members);
 /* Device time of each system in the last persistent ddlr_batch_solve (us: host
