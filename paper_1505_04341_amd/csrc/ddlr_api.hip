@@ -5082,7 +5082,15 @@ ddlr_status ddlr_batch_solve(ddlr_batch* B, const double* b, double* x, const dd
             }
             int itmax = 0;
             for (int q = 0; q < ns; ++q) itmax = std::max(itmax, info[q].iters);
-            if (B->regroup > 0 && itmax >= 20) batch_regroup(B);
+            if (B->regroup > 0 && itmax >= 20) {
+                try {  // optional: any failure keeps the batch as it is
+                    batch_regroup(B);
+                } catch (...) {
+                    (void)hipGetLastError();
+                    B->regroup = 0;
+                    std::vector<HostPlan>().swap(B->plans);
+                }
+            }
         } catch (const SetupError& e) {
             h->capturing = false;
             return fail_status(e);
