@@ -87,6 +87,31 @@ struct BlockDesc {
     int32_t lvl0, lvl1;  // levels [lvl0, lvl1) in lvl_ptr
 };
 
+// s - sum_t v[t] y[c[t]] over t in [t0, t1), the terms applied in order of t.
+// The entries go in groups of four so that a group's column, value and
+// gather loads go out together; an index past the row's end repeats its last
+// entry and is not applied.
+template <typename T, typename TY>
+__device__ __forceinline__ T row_terms(T s, int t0, int t1, const int32_t* __restrict__ col,
+                                       const T* __restrict__ val, const TY* y) {
+    for (int t = t0; t < t1; t += 4) {
+        int c[4];
+        T v[4], g[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int q = min(t + u, t1 - 1);
+            c[u] = col[q];
+            v[u] = val[q];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) g[u] = (T)y[c[u]];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (t + u < t1) s = fnms(s, v[u], g[u]);
+    }
+    return s;
+}
+
 template <typename T, typename TIn, typename TOut>
 __global__ __launch_bounds__(256) void k_trsv_narrow(
     const BlockDesc* __restrict__ blk, int nblk, int nblk_pad, int nrhs, const int32_t* __restrict__ lvl_ptr,
@@ -103,8 +128,7 @@ __global__ __launch_bounds__(256) void k_trsv_narrow(
         const int a = lvl_ptr[l], e = lvl_ptr[l + 1];
         for (int i = a + threadIdx.x; i < e; i += blockDim.x) {
             T s = (T)xr[i];
-            const int t1 = lrp[i + 1];
-            for (int t = lrp[i]; t < t1; ++t) s = fnms(s, lv[t], (T)zr[lci[t]]);
+            s = row_terms<T>(s, lrp[i], lrp[i + 1], lci, lv, zr);
             zr[i] = (TOut)s;
         }
         __syncthreads();
@@ -113,8 +137,7 @@ __global__ __launch_bounds__(256) void k_trsv_narrow(
         const int a = lvl_ptr[l], e = lvl_ptr[l + 1];
         for (int i = a + threadIdx.x; i < e; i += blockDim.x) {
             T s = (T)zr[i] * dinv[i];
-            const int t1 = urp[i + 1];
-            for (int t = urp[i]; t < t1; ++t) s = fnms(s, uv[t], (T)zr[uci[t]]);
+            s = row_terms<T>(s, urp[i], urp[i + 1], uci, uv, zr);
             zr[i] = (TOut)s;
         }
         __syncthreads();
@@ -758,12 +781,20 @@ __global__ __launch_bounds__(256) void k_iface_cols(int a, int e, int m, int nrh
     T s;
     if constexpr (kKind == 1) s = Y[(size_t)j * NR + r] * dinv[i];
     else s = (T)x[i + (int64_t)min(r, nrhs - 1) * ldx];
+    // entries in groups of four: a group's entry and gather loads go out
+    // together (an index past the row's end repeats its last entry and is
+    // not applied), then the terms are applied in their order
     const int t1 = prp[j + 1];
-    for (int t = prp[j]; t < t1; ++t) {
-        int c;
-        T v;
-        pk_unpack(pk[t], c, v);
-        s = fnms(s, v, Y[(size_t)(c - m) * NR + r]);
+    for (int t = prp[j]; t < t1; t += 4) {
+        int c[4];
+        T v[4], g[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) pk_unpack(pk[min(t + u, t1 - 1)], c[u], v[u]);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) g[u] = Y[(size_t)(c[u] - m) * NR + r];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (t + u < t1) s = fnms(s, v[u], g[u]);
     }
     if constexpr (kKind == 2) s *= dinv[i];
     Y[(size_t)j * NR + r] = s;
