@@ -87,26 +87,29 @@ struct BlockDesc {
     int32_t lvl0, lvl1;  // levels [lvl0, lvl1) in lvl_ptr
 };
 
-// s - sum_t v[t] y[c[t]] over t in [t0, t1), the terms applied in order of t.
-// The entries go in groups of four so that a group's column, value and
-// gather loads go out together; an index past the row's end repeats its last
-// entry and is not applied.
+// Entries per group in the row loops of the plain level kernels: a group's
+// column, value and gather loads go out together.
+constexpr int kTermGroup = 8;
+
+// s - sum_t v[t] y[c[t]] over t in [t0, t1), the terms applied in order of t,
+// the entries in groups of kTermGroup; an index past the row's end repeats
+// its last entry and is not applied.
 template <typename T, typename TY>
 __device__ __forceinline__ T row_terms(T s, int t0, int t1, const int32_t* __restrict__ col,
                                        const T* __restrict__ val, const TY* y) {
-    for (int t = t0; t < t1; t += 4) {
-        int c[4];
-        T v[4], g[4];
+    for (int t = t0; t < t1; t += kTermGroup) {
+        int c[kTermGroup];
+        T v[kTermGroup], g[kTermGroup];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < kTermGroup; ++u) {
             const int q = min(t + u, t1 - 1);
             c[u] = col[q];
             v[u] = val[q];
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) g[u] = (T)y[c[u]];
+        for (int u = 0; u < kTermGroup; ++u) g[u] = (T)y[c[u]];
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < kTermGroup; ++u)
             if (t + u < t1) s = fnms(s, v[u], g[u]);
     }
     return s;
@@ -781,19 +784,19 @@ __global__ __launch_bounds__(256) void k_iface_cols(int a, int e, int m, int nrh
     T s;
     if constexpr (kKind == 1) s = Y[(size_t)j * NR + r] * dinv[i];
     else s = (T)x[i + (int64_t)min(r, nrhs - 1) * ldx];
-    // entries in groups of four: a group's entry and gather loads go out
-    // together (an index past the row's end repeats its last entry and is
+    // entries in groups of kTermGroup: a group's entry and gather loads go
+    // out together (an index past the row's end repeats its last entry and is
     // not applied), then the terms are applied in their order
     const int t1 = prp[j + 1];
-    for (int t = prp[j]; t < t1; t += 4) {
-        int c[4];
-        T v[4], g[4];
+    for (int t = prp[j]; t < t1; t += kTermGroup) {
+        int c[kTermGroup];
+        T v[kTermGroup], g[kTermGroup];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) pk_unpack(pk[min(t + u, t1 - 1)], c[u], v[u]);
+        for (int u = 0; u < kTermGroup; ++u) pk_unpack(pk[min(t + u, t1 - 1)], c[u], v[u]);
 #pragma unroll
-        for (int u = 0; u < 4; ++u) g[u] = Y[(size_t)(c[u] - m) * NR + r];
+        for (int u = 0; u < kTermGroup; ++u) g[u] = Y[(size_t)(c[u] - m) * NR + r];
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < kTermGroup; ++u)
             if (t + u < t1) s = fnms(s, v[u], g[u]);
     }
     if constexpr (kKind == 2) s *= dinv[i];
